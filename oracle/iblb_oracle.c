@@ -39,8 +39,9 @@
  *    shape = the unperturbed mesh;
  *  - volume: V_j is the signed tetrahedron volume of face j with apex at the
  *    centroid o of the reference vertices; V0 = volume of the reference mesh;
- *    V - V0 is accumulated as sum_j (V_j - V0_j), an exact identity that keeps
- *    the small difference out of the large-sum rounding;
+ *    V - V0 is accumulated as sum_j (V_j - V0_j), each difference expanded
+ *    exactly in the vertex displacements from the reference shape, which keeps
+ *    the small volume change out of the rounding of O(1) tetrahedron volumes;
  *  - wall force: d = distance of the face centroid to the wall plane along its
  *    normal, cut off at r_cut, d clamped to >= xi/2, one third per vertex.
  */
@@ -183,6 +184,34 @@ static double tet_volume(const double *a, const double *b, const double *c, cons
     return (A[0] * x[0] + A[1] * x[1] + A[2] * x[2]) / 6.0;
 }
 
+/* T(a, b, c) = a . (b x c) */
+static double triple(const double *a, const double *b, const double *c)
+{
+    return a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) + a[2] * (b[0] * c[1] - b[1] * c[0]);
+}
+
+/* V(a,b,c) - V(A,B,C) for the tetrahedra with apex o, expanded exactly in the
+ * displacements da = a - A, db = b - B, dc = c - C: with T trilinear,
+ * T(A+da, B+db, C+dc) - T(A, B, C) is the sum of the seven terms that contain
+ * at least one displacement.  Every term is as small as the volume change
+ * itself, so the difference is not lost to the rounding of O(1) volumes. */
+static double tet_volume_change(const double *A, const double *B, const double *C, const double *a,
+                                const double *b, const double *c, const double *o)
+{
+    double Ar[3], Br[3], Cr[3], da[3], db[3], dc[3];
+    for (int k = 0; k < 3; ++k) {
+        Ar[k] = A[k] - o[k];
+        Br[k] = B[k] - o[k];
+        Cr[k] = C[k] - o[k];
+        da[k] = a[k] - A[k];
+        db[k] = b[k] - B[k];
+        dc[k] = c[k] - C[k];
+    }
+    const double t = triple(da, Br, Cr) + triple(Ar, db, Cr) + triple(Ar, Br, dc) + triple(da, db, Cr) +
+                     triple(da, Br, dc) + triple(Ar, db, dc) + triple(da, db, dc);
+    return t / 6.0;
+}
+
 /* (u - o) x (v - o) / 6 */
 static void cross6(const double *u, const double *v, const double *o, double *out)
 {
@@ -273,7 +302,7 @@ void oracle_mesh_forces(int nv, int nf, const double *q, const double *X, const 
         const double V0j = tet_volume(X + 3 * f[0], X + 3 * f[1], X + 3 * f[2], o);
         V += Vj;
         V0 += V0j;
-        dV += Vj - V0j;
+        dV += tet_volume_change(X + 3 * f[0], X + 3 * f[1], X + 3 * f[2], a, b, c, o);
         double da[3], db[3], dc[3];
         cross6(b, c, o, da);
         cross6(c, a, o, db);
