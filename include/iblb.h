@@ -1,0 +1,194 @@
+/*
+ * iblb.h -- C ABI of libiblb, one immersed-boundary / lattice-Boltzmann
+ * (IB-LB) time step on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: Pelusi, Guglietta, Sega, Aouane, Harting, "A sharp interface
+ * approach for wetting dynamics of hydrophobic coated droplets and soft
+ * particles", arXiv:2305.18919.  One call of iblb_step advances the coupled
+ * system by one lattice time step in the order of the algorithm listed at the
+ * end of the "Numerical implementation" section:
+ *   1. nodal forces phi_i = phi^S + phi^V + phi^W       (Eq. total_nodal_force)
+ *        phi^S = -dW/dq, W = sum_faces A0 w_S(I1, I2)    (Eqs. generalised_energy1,
+ *                                                         nodal_force_S)
+ *        phi^V = -d/dq [k_V (V - V0)^2 / (2 V0)]         (Eq. nodal_force_V)
+ *        phi^W = face-centroid Lennard-Jones wall force   (Eq. LJ_interaction)
+ *   2. spreading F(x) = sum_i phi_i delta_D(x - q_i)     (Eq. ibm-governing_eq2)
+ *   3. D3Q19 BGK collision with Guo forcing, streaming   (Eqs. LBeq, feq)
+ *   4. fluid velocity u = (sum c f + F/2)/rho            (Guo velocity)
+ *   5. interpolation qdot_i = sum_x u(x) delta_D(x - q_i) (Eq. ibm-governing_eq1)
+ *   6. q_i <- q_i + qdot_i                               (Eq. ibm_update_pos)
+ * with delta_D the product of three 4-point stencils phi4
+ * (Eq. ibm-interpolation_stencil), periodic x and y, and half-way bounce-back
+ * walls in z (the paragraph after the algorithm).
+ *
+ * Conventions shared by every call
+ *  - Lattice units: dx = dt = 1, c_s^2 = 1/3.  Node (x, y, z) sits at integer
+ *    coordinates.  With IBLB_WALLS_Z the layers z = 0 and z = nz-1 are solid,
+ *    the fluid is z = 1 .. nz-2 and the wall planes are z = 0.5 and z = nz-1.5.
+ *  - Field arrays on the host are [component][z_fluid][y][x], x fastest,
+ *    z_fluid = z - 1 with walls (z with IBLB_PERIODIC_ALL).  N = nx*ny*nz_fluid.
+ *  - Populations are exchanged as deviations f_i - w_i rho0 in the canonical
+ *    D3Q19 order: i = 0 rest; 1,2 = (+-1,0,0); 3,4 = (0,+-1,0); 5,6 = (0,0,+-1);
+ *    7,8 = +-(1,1,0); 9,10 = +-(1,-1,0); 11,12 = +-(1,0,1); 13,14 = +-(1,0,-1);
+ *    15,16 = +-(0,1,1); 17,18 = +-(0,1,-1); weights 1/3, 1/18 (1..6), 1/36.
+ *  - Vertex arrays on the host are [vertex][xyz] doubles, unwrapped
+ *    coordinates (x and y are not folded back into the box).
+ *  - Every function returns IBLB_OK (0) or a negative IBLB_E_* code and never
+ *    aborts or throws; iblb_last_error() then holds a message.  Errors raised
+ *    inside kernels (non-finite state, list overflow) are reported by the next
+ *    call that synchronises (iblb_sync and every getter).
+ *  - Host pointers passed in are read during the call only (inputs are
+ *    copied).  Output buffers belong to the caller.
+ *  - One context per host thread; calls on one context are not thread-safe.
+ */
+#ifndef IBLB_H
+#define IBLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    IBLB_OK = 0,
+    IBLB_E_INVAL = -1,    /* bad argument or size */
+    IBLB_E_DEVICE = -2,   /* HIP runtime error */
+    IBLB_E_MESH = -3,     /* mesh not closed / not consistently oriented / degenerate */
+    IBLB_E_UNSTABLE = -4, /* non-finite or runaway state found on the device */
+    IBLB_E_STATE = -5     /* call not valid in the current state */
+};
+
+enum { IBLB_FP64 = 0, IBLB_FP32_DEV = 1 };          /* population storage and LB arithmetic */
+enum { IBLB_WALLS_Z = 0, IBLB_PERIODIC_ALL = 1 };   /* z boundary */
+
+typedef struct iblb_ctx iblb_ctx;
+
+typedef struct {
+    int32_t nx, ny, nz;        /* lattice size incl. the two solid layers when IBLB_WALLS_Z; each >= 8 */
+    int32_t wall_mode;         /* IBLB_WALLS_Z or IBLB_PERIODIC_ALL */
+    int32_t precision;         /* IBLB_FP64: FP64 populations and LB arithmetic;
+                                  IBLB_FP32_DEV: FP32 deviations f - w rho0, FP32 LB and
+                                  interface arithmetic; positions, volume and area stay FP64 */
+    int32_t init_couette;      /* 0: fluid at rest; 1: f = f^eq(rho0, u linear between the walls) */
+    double tau;                /* BGK relaxation time (> 1/2); viscosity (tau - 1/2)/3 */
+    double rho0;               /* initial and reference density */
+    double u_wall_lo[3];       /* velocity of the wall at z = 0.5 (tangential) */
+    double u_wall_hi[3];       /* velocity of the wall at z = nz - 1.5 */
+    double body_force[3];      /* uniform force density added to F on every node */
+} iblb_domain_desc;
+
+typedef struct {
+    int32_t n_vertices, n_faces;
+    const double *vertices;     /* host [n_vertices][3]: initial positions q(0) */
+    const double *ref_vertices; /* host [n_vertices][3]: stress-free shape; NULL => vertices */
+    const int32_t *faces;       /* host [n_faces][3]: closed surface, outward counter-clockwise */
+    double alpha[3];            /* (alpha1, alpha2, alpha3) of Eq. generalised_energy1 */
+    double k_v;                 /* volume stiffness k_V of Eq. nodal_force_V (paper: 1) */
+    double eps_wall_lo;         /* LJ strength of the wall at z = 0.5 (0: off) */
+    double eps_wall_hi;         /* LJ strength of the wall at z = nz - 1.5 (0: off) */
+    double xi_wall;             /* LJ length xi (paper: 0.5) */
+    double r_cut_wall;          /* LJ cut-off distance from the wall plane */
+} iblb_mesh_desc;
+
+/* Device bytes needed by a context for this domain and (optional, may be NULL)
+ * mesh, for callers that pass their own workspace to iblb_create. */
+int iblb_workspace_bytes(const iblb_domain_desc *dom, const iblb_mesh_desc *mesh, size_t *bytes);
+
+/* Create a context on the current HIP device.
+ * dev_workspace: device buffer of >= iblb_workspace_bytes(dom, NULL) bytes that
+ *   the caller owns and keeps alive until iblb_destroy (e.g. a torch uint8
+ *   tensor); NULL => the library allocates and frees its own memory.  A
+ *   workspace of iblb_workspace_bytes(dom, mesh) bytes also holds the mesh
+ *   arrays of iblb_add_mesh; a smaller one makes iblb_add_mesh allocate them.
+ * hip_stream: hipStream_t all work is enqueued on; NULL => a private stream.
+ * Initialises the populations (rest, or Couette when init_couette = 1). */
+int iblb_create(const iblb_domain_desc *dom, void *dev_workspace, size_t workspace_bytes,
+                void *hip_stream, iblb_ctx **out);
+
+/* Attach the (single) mesh.  Validates that the surface is closed and
+ * consistently oriented, copies the inputs, precomputes per-face reference
+ * data (metric inverse, area) and the reference volume V0 (volume of
+ * ref_vertices), and bins the vertices for the first step.  V - V0 is later
+ * evaluated face by face, expanded exactly in the displacements from
+ * ref_vertices.  *mesh_id = 0.  Fails with IBLB_E_STATE if a mesh exists or a
+ * debug force field is set. */
+int iblb_add_mesh(iblb_ctx *ctx, const iblb_mesh_desc *mesh, int32_t *mesh_id);
+
+/* Enqueue n_steps full IB-LB steps on the context stream; returns without
+ * waiting.  In graph mode (default) one captured step is replayed. */
+int iblb_step(iblb_ctx *ctx, int32_t n_steps);
+
+/* Wait for the context stream and report device-side errors. */
+int iblb_sync(iblb_ctx *ctx);
+
+/* Number of completed steps (host count of enqueued steps). */
+int iblb_step_count(const iblb_ctx *ctx, int64_t *t);
+
+/* Vertex positions q(t) -> host [n_vertices][3] (synchronises). */
+int iblb_get_vertices(iblb_ctx *ctx, int32_t mesh_id, double *host_out);
+
+/* Device pointer to the FP64 positions, structure-of-arrays [3][n_vertices]
+ * (all x, then all y, then all z).  Valid until the next step is enqueued;
+ * the caller must order its reads after the context stream. */
+int iblb_vertices_device(iblb_ctx *ctx, int32_t mesh_id, const double **dev_ptr);
+
+/* Enclosed volume V and surface area A of the current mesh, FP64 reductions
+ * (V from signed tetrahedra, Eq. nodal_force_V's V = sum_j V_j). */
+int iblb_volume(iblb_ctx *ctx, int32_t mesh_id, double *V, double *A);
+
+/* Shape in the x-z shear plane: Taylor deformation D = (r1 - r3)/(r1 + r3)
+ * (Eq. taylor_deform) and inclination Theta of r1 from +x in (-pi/2, pi/2],
+ * with r1, r3 from the central second-moment tensor of the enclosed volume read
+ * as an ellipsoid (M = V/5 diag(r^2)); centroid = volume centroid. */
+int iblb_shape(iblb_ctx *ctx, int32_t mesh_id, double *D, double *Theta, double centroid[3]);
+
+/* Contact angle against a wall (0: lower, 1: upper), the paper's circle-cut-
+ * by-a-chord fit (appendix on the resolution test) done as an algebraic least-
+ * squares sphere fit in FP64 of the vertices at least 2 lattice units away from
+ * that wall plane (method 0, the only one supported).  Returns the angle in
+ * degrees measured inside the liquid, the contact radius and the height of the
+ * fitted cap above the wall plane. */
+int iblb_contact_angle(iblb_ctx *ctx, int32_t mesh_id, int32_t wall, int32_t method,
+                       double *theta_deg, double *contact_radius, double *height);
+
+/* rho [N] and u [3][N] on the fluid nodes at the current time, with the force
+ * density of the last step in the Guo velocity (zero before the first step). */
+int iblb_get_fields(iblb_ctx *ctx, double *rho, double *u);
+
+/* Debug / validation calls. */
+/* Fixed external force density [3][N] added every step; only without a mesh. */
+int iblb_debug_set_force(iblb_ctx *ctx, const double *F);
+/* Force density of the last step [3][N] (IB + body + external; zero before the first step). */
+int iblb_debug_get_force(iblb_ctx *ctx, double *F);
+/* Population deviations f_i - w_i rho0 at the current time, [19][N] canonical order. */
+int iblb_debug_get_populations(iblb_ctx *ctx, double *f);
+int iblb_debug_set_populations(iblb_ctx *ctx, const double *f);
+/* Nodal forces phi_i of the last step, host [n_vertices][3]. */
+int iblb_debug_get_nodal_forces(iblb_ctx *ctx, int32_t mesh_id, double *phi);
+
+/* Checkpoint: host_buf == NULL => *bytes receives the size; else the complete
+ * state (populations, positions, last force field, step count) is written.
+ * iblb_load_state accepts only a buffer from a context of identical shape,
+ * precision and mesh size. */
+int iblb_save_state(iblb_ctx *ctx, void *host_buf, size_t *bytes);
+int iblb_load_state(iblb_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Execution controls.  graph != 0: iblb_step replays a captured hipGraph
+ * (default); 0: plain launches.  timing != 0: plain launches bracketed by
+ * hipEvents per kernel on the context stream, accumulated until read. */
+int iblb_set_graph(iblb_ctx *ctx, int32_t graph);
+int iblb_set_timing(iblb_ctx *ctx, int32_t timing);
+/* Per-kernel accumulated event time.  names: "forces", "spread", "lb",
+ * "move", "tick".  Returns total milliseconds and launch count; resets nothing. */
+int iblb_kernel_time(iblb_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
+int iblb_reset_timing(iblb_ctx *ctx);
+
+const char *iblb_last_error(const iblb_ctx *ctx);
+int iblb_destroy(iblb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBLB_H */

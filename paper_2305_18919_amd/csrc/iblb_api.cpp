@@ -1,0 +1,939 @@
+// Host side of libiblb: the C ABI declared in include/iblb.h.
+//
+// Responsibilities: argument and mesh validation, device memory layout
+// (one workspace carved into 256-byte aligned arrays), per-face reference data
+// and the vertex -> (face, corner) table, step scheduling (plain launches,
+// a captured hipGraph of one step, or launches bracketed by hipEvents), the
+// FP64 solves behind the shape and contact-angle queries, and checkpoints.
+// All arithmetic of the step itself runs in the kernels of iblb_kernels.hip.
+#include "iblb.h"
+#include "iblb_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+using namespace iblb;
+
+namespace {
+
+constexpr char kMagic[8] = {'I', 'B', 'L', 'B', 'S', 'T', '0', '1'};
+constexpr int kNumKernels = 5;
+const char *const kKernelNames[kNumKernels] = {"forces", "spread", "lb", "move", "tick"};
+enum { K_FORCES = 0, K_SPREAD = 1, K_LB = 2, K_MOVE = 3, K_TICK = 4 };
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Layout {
+    // byte offsets into the workspace; domain part then mesh part
+    size_t f, F, stamp, t, done, err, scratch, dom_end;
+    size_t q, Xref, faces, fref, inc_off, inc, phiSW, gV, base, wts, partials, cnt, list, acnt, alist, mesh_end;
+};
+
+Grid make_grid(const iblb_domain_desc &d)
+{
+    Grid g;
+    g.nx = d.nx;
+    g.ny = d.ny;
+    g.nz = d.nz;
+    g.walls = d.wall_mode == IBLB_WALLS_Z ? 1 : 0;
+    g.zoff = g.walls;
+    g.nzf = g.walls ? d.nz - 2 : d.nz;
+    g.n = (long long)g.nx * g.ny * g.nzf;
+    g.ntx = (g.nx + 3) / 4;
+    g.nty = (g.ny + 3) / 4;
+    g.ntz = (g.nzf + 3) / 4;
+    g.nt = g.ntx * g.nty * g.ntz;
+    return g;
+}
+
+Layout make_layout(const Grid &g, size_t ts, int nv, int nf)
+{
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    L.f = take(19 * (size_t)g.n * ts);
+    L.F = take(3 * (size_t)g.n * ts);
+    L.stamp = take((size_t)g.nt * 4);
+    L.t = take(4);
+    L.done = take(4);
+    L.err = take(4);
+    L.scratch = take(64 * 8);
+    L.dom_end = o;
+    const int nparts = (nv + 255) / 256;
+    L.q = take((size_t)3 * nv * 8);
+    L.Xref = take((size_t)3 * nv * 8);
+    L.faces = take((size_t)3 * nf * 4);
+    L.fref = take((size_t)5 * nf * 8);
+    L.inc_off = take((size_t)(nv + 1) * 4);
+    L.inc = take((size_t)3 * nf * 4);
+    L.phiSW = take((size_t)3 * nv * ts);
+    L.gV = take((size_t)3 * nv * ts);
+    L.base = take((size_t)nv * sizeof(Base));
+    L.wts = take((size_t)12 * nv * ts);
+    L.partials = take((size_t)2 * nparts * 8);
+    L.cnt = take((size_t)2 * g.nt * 4);
+    L.list = take((size_t)2 * g.nt * kTileCap * 4);
+    L.acnt = take(2 * 4);
+    L.alist = take((size_t)2 * g.nt * 4);
+    L.mesh_end = o;
+    return L;
+}
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+}  // namespace
+
+struct iblb_ctx {
+    iblb_domain_desc dom;
+    int prec = 0;
+    size_t ts = 8;
+    Grid g;
+    LBArgs lb;
+    MeshArgs m;
+    Dev d;
+    Layout L;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    bool has_mesh = false;
+    int nv = 0, nf = 0;
+    double V0 = 0.0;
+    long long t = 0;
+    bool use_graph = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool timing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> pool;
+    double ktime[kNumKernels] = {0, 0, 0, 0, 0};
+    long long kcount[kNumKernels] = {0, 0, 0, 0, 0};
+    void *fext_alloc = nullptr;
+    void *mesh_alloc = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int fail(iblb_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(iblb_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, IBLB_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, expr)                                   \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_fail(c, e_, #expr); \
+    } while (0)
+
+int check_domain(const iblb_domain_desc *d, std::string &why)
+{
+    if (!d) { why = "null domain"; return IBLB_E_INVAL; }
+    if (d->nx < 8 || d->ny < 8 || d->nz < 8) { why = "nx, ny, nz must be >= 8"; return IBLB_E_INVAL; }
+    if ((long long)d->nx * d->ny * d->nz > (1ll << 31)) { why = "lattice too large"; return IBLB_E_INVAL; }
+    if (d->wall_mode != IBLB_WALLS_Z && d->wall_mode != IBLB_PERIODIC_ALL) { why = "bad wall_mode"; return IBLB_E_INVAL; }
+    if (d->precision != IBLB_FP64 && d->precision != IBLB_FP32_DEV) { why = "bad precision"; return IBLB_E_INVAL; }
+    if (!(d->tau > 0.5) || !std::isfinite(d->tau)) { why = "tau must be > 1/2"; return IBLB_E_INVAL; }
+    if (!(d->rho0 > 0.0) || !std::isfinite(d->rho0)) { why = "rho0 must be > 0"; return IBLB_E_INVAL; }
+    if (!finite3(d->u_wall_lo) || !finite3(d->u_wall_hi) || !finite3(d->body_force)) {
+        why = "non-finite wall velocity or body force";
+        return IBLB_E_INVAL;
+    }
+    if (d->u_wall_lo[2] != 0.0 || d->u_wall_hi[2] != 0.0) { why = "wall velocities must be tangential"; return IBLB_E_INVAL; }
+    return IBLB_OK;
+}
+
+int check_mesh(const iblb_mesh_desc *m, std::string &why)
+{
+    if (!m || !m->vertices || !m->faces) { why = "null mesh arrays"; return IBLB_E_INVAL; }
+    if (m->n_vertices < 4 || m->n_faces < 4) { why = "mesh too small"; return IBLB_E_MESH; }
+    if (m->n_vertices > (1 << 28) || m->n_faces > (1 << 28)) { why = "mesh too large"; return IBLB_E_INVAL; }
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(m->alpha[k])) { why = "non-finite alpha"; return IBLB_E_INVAL; }
+    if (!std::isfinite(m->k_v) || !std::isfinite(m->eps_wall_lo) || !std::isfinite(m->eps_wall_hi) ||
+        !(m->xi_wall > 0.0) || !std::isfinite(m->r_cut_wall)) {
+        why = "bad volume or wall parameters";
+        return IBLB_E_INVAL;
+    }
+    const int nv = m->n_vertices, nf = m->n_faces;
+    for (int i = 0; i < nv; ++i) {
+        if (!finite3(m->vertices + 3 * i) || std::fabs(m->vertices[3 * i]) > 1e6 ||
+            std::fabs(m->vertices[3 * i + 1]) > 1e6 || std::fabs(m->vertices[3 * i + 2]) > 1e6) {
+            why = "vertex " + std::to_string(i) + " not finite or beyond 1e6";
+            return IBLB_E_INVAL;
+        }
+        if (m->ref_vertices && !finite3(m->ref_vertices + 3 * i)) { why = "non-finite reference vertex"; return IBLB_E_INVAL; }
+    }
+    // closed, consistently oriented 2-manifold: each directed edge once, with its reverse
+    std::unordered_map<unsigned long long, int> edges;
+    edges.reserve((size_t)nf * 4);
+    for (int j = 0; j < nf; ++j) {
+        const int *f = m->faces + 3 * j;
+        for (int c = 0; c < 3; ++c)
+            if (f[c] < 0 || f[c] >= nv) { why = "face " + std::to_string(j) + " index out of range"; return IBLB_E_MESH; }
+        if (f[0] == f[1] || f[1] == f[2] || f[0] == f[2]) { why = "degenerate face " + std::to_string(j); return IBLB_E_MESH; }
+        for (int c = 0; c < 3; ++c) {
+            const unsigned long long key = ((unsigned long long)f[c] << 32) | (unsigned)f[(c + 1) % 3];
+            if (++edges[key] > 1) { why = "edge used twice in the same direction (orientation)"; return IBLB_E_MESH; }
+        }
+    }
+    for (const auto &kv : edges) {
+        const unsigned long long rev = ((kv.first & 0xffffffffull) << 32) | (kv.first >> 32);
+        if (edges.find(rev) == edges.end()) { why = "mesh is not closed"; return IBLB_E_MESH; }
+    }
+    return IBLB_OK;
+}
+
+void lb_args(iblb_ctx *c)
+{
+    LBArgs &a = c->lb;
+    a.g = c->g;
+    a.tau_inv = 1.0 / c->dom.tau;
+    a.guo = 1.0 - 1.0 / (2.0 * c->dom.tau);
+    a.rho0 = c->dom.rho0;
+    for (int k = 0; k < 3; ++k) {
+        a.body[k] = c->dom.body_force[k];
+        a.ulo[k] = c->dom.u_wall_lo[k];
+        a.uhi[k] = c->dom.u_wall_hi[k];
+    }
+    a.has_fext = c->d.Fext != nullptr;
+}
+
+void drop_graph(iblb_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
+
+hipEvent_t get_event(iblb_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+hipError_t launch_kernel(iblb_ctx *c, int which)
+{
+    const Dev &d = c->d;
+    switch (which) {
+    case K_FORCES: return launch_forces(c->prec, d, c->g, c->m, c->stream);
+    case K_SPREAD: return launch_spread(c->prec, d, c->g, c->m, c->stream);
+    case K_LB: return launch_lb(c->prec, d, c->lb, c->stream);
+    case K_MOVE: return launch_move(c->prec, d, c->lb, c->m, c->stream);
+    default: return launch_tick(d, c->stream);
+    }
+}
+
+// one step: forces -> spread -> lb -> move (mesh) or lb -> tick (no mesh)
+hipError_t enqueue_step(iblb_ctx *c, bool timed)
+{
+    int seq[4], ns = 0;
+    if (c->has_mesh) {
+        seq[ns++] = K_FORCES;
+        seq[ns++] = K_SPREAD;
+        seq[ns++] = K_LB;
+        seq[ns++] = K_MOVE;
+    } else {
+        seq[ns++] = K_LB;
+        seq[ns++] = K_TICK;
+    }
+    for (int k = 0; k < ns; ++k) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) {
+            e0 = get_event(c);
+            e1 = get_event(c);
+            (void)hipEventRecord(e0, c->stream);
+        }
+        hipError_t e = launch_kernel(c, seq[k]);
+        if (e != hipSuccess) return e;
+        if (timed) {
+            (void)hipEventRecord(e1, c->stream);
+            c->pending.push_back({seq[k], {e0, e1}});
+        }
+    }
+    return hipSuccess;
+}
+
+int collect_timing(iblb_ctx *c)
+{
+    if (c->pending.empty()) return IBLB_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, p.second.first, p.second.second);
+        c->ktime[p.first] += ms;
+        c->kcount[p.first] += 1;
+        c->pool.push_back(p.second.first);
+        c->pool.push_back(p.second.second);
+    }
+    c->pending.clear();
+    return IBLB_OK;
+}
+
+int read_err(iblb_ctx *c)
+{
+    int e = 0;
+    HIP_TRY(c, hipMemcpy(&e, c->d.err, sizeof(int), hipMemcpyDeviceToHost));
+    if (e) {
+        std::string why = "device reported:";
+        if (e & kErrNonFinite) why += " non-finite vertex position;";
+        if (e & kErrOverflow) why += " tile list overflow (vertex pile-up);";
+        if (e & kErrDensity) why += " density out of range or non-finite;";
+        if (e & kErrMach) why += " |u| above 0.3;";
+        return fail(c, IBLB_E_UNSTABLE, why);
+    }
+    return IBLB_OK;
+}
+
+int sync_ctx(iblb_ctx *c)
+{
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return read_err(c);
+}
+
+// temporary device buffer for debug / query copies
+struct TmpDev {
+    void *p = nullptr;
+    ~TmpDev() { if (p) (void)hipFree(p); }
+};
+
+int rebuild_lists(iblb_ctx *c)
+{
+    HIP_TRY(c, hipMemsetAsync(c->d.cnt, 0, (size_t)2 * c->g.nt * 4, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d.acnt, 0, 2 * 4, c->stream));
+    HIP_TRY(c, launch_bin(c->d, c->g, c->m, c->stream));
+    return IBLB_OK;
+}
+
+int mesh_ok(iblb_ctx *c, int32_t mesh_id)
+{
+    if (!c) return IBLB_E_INVAL;
+    if (!c->has_mesh) return fail(c, IBLB_E_STATE, "no mesh attached");
+    if (mesh_id != 0) return fail(c, IBLB_E_INVAL, "mesh_id must be 0");
+    return IBLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int iblb_workspace_bytes(const iblb_domain_desc *dom, const iblb_mesh_desc *mesh, size_t *bytes)
+{
+    std::string why;
+    if (!bytes) return IBLB_E_INVAL;
+    int rc = check_domain(dom, why);
+    if (rc) return rc;
+    const Grid g = make_grid(*dom);
+    const size_t ts = dom->precision == IBLB_FP64 ? 8 : 4;
+    const Layout L = make_layout(g, ts, mesh ? mesh->n_vertices : 0, mesh ? mesh->n_faces : 0);
+    *bytes = mesh ? L.mesh_end : L.dom_end;
+    return IBLB_OK;
+}
+
+int iblb_create(const iblb_domain_desc *dom, void *dev_workspace, size_t workspace_bytes, void *hip_stream,
+                iblb_ctx **out)
+{
+    if (!out) return IBLB_E_INVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = check_domain(dom, why);
+    if (rc) return rc;
+    iblb_ctx *c = new iblb_ctx();
+    c->dom = *dom;
+    c->prec = dom->precision;
+    c->ts = c->prec == IBLB_FP64 ? 8 : 4;
+    c->g = make_grid(*dom);
+    c->L = make_layout(c->g, c->ts, 0, 0);
+    auto bail = [&](int code) {
+        iblb_destroy(c);
+        return code;
+    };
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(IBLB_E_DEVICE);
+        c->own_stream = true;
+    }
+    if (dev_workspace) {
+        if (workspace_bytes < c->L.dom_end) return bail(IBLB_E_INVAL);
+        c->ws = (char *)dev_workspace;
+        c->ws_bytes = workspace_bytes;
+    } else {
+        void *p = nullptr;
+        if (hipMalloc(&p, c->L.dom_end) != hipSuccess) return bail(IBLB_E_DEVICE);
+        c->ws = (char *)p;
+        c->ws_bytes = c->L.dom_end;
+        c->own_ws = true;
+    }
+    Dev &d = c->d;
+    std::memset(&d, 0, sizeof(d));
+    d.f = c->ws + c->L.f;
+    d.F = c->ws + c->L.F;
+    d.stamp = (uint32_t *)(c->ws + c->L.stamp);
+    d.t = (uint32_t *)(c->ws + c->L.t);
+    d.done = (uint32_t *)(c->ws + c->L.done);
+    d.err = (int *)(c->ws + c->L.err);
+    d.scratch = (double *)(c->ws + c->L.scratch);
+    lb_args(c);
+    if (hipMemsetAsync(c->ws + c->L.stamp, 0, c->L.dom_end - c->L.stamp, c->stream) != hipSuccess ||
+        hipMemsetAsync(d.F, 0, 3 * (size_t)c->g.n * c->ts, c->stream) != hipSuccess ||
+        launch_init(c->prec, d, c->lb, dom->init_couette, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return bail(IBLB_E_DEVICE);
+    *out = c;
+    return IBLB_OK;
+}
+
+int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
+{
+    if (!c) return IBLB_E_INVAL;
+    if (c->has_mesh) return fail(c, IBLB_E_STATE, "a mesh is already attached (one per context)");
+    if (c->d.Fext) return fail(c, IBLB_E_STATE, "debug force field set: no mesh allowed");
+    std::string why;
+    int rc = check_mesh(mesh, why);
+    if (rc) return fail(c, rc, why);
+    const int nv = mesh->n_vertices, nf = mesh->n_faces;
+    const double *X = mesh->ref_vertices ? mesh->ref_vertices : mesh->vertices;
+
+    // reference geometry in FP64
+    double o[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < nv; ++i)
+        for (int k = 0; k < 3; ++k) o[k] += X[3 * i + k];
+    for (int k = 0; k < 3; ++k) o[k] /= nv;
+    std::vector<double> fref((size_t)5 * nf);
+    double V0 = 0.0;
+    for (int j = 0; j < nf; ++j) {
+        const int *f = mesh->faces + 3 * j;
+        const double *a = X + 3 * f[0], *b = X + 3 * f[1], *cc = X + 3 * f[2];
+        double E1[3], E2[3];
+        for (int k = 0; k < 3; ++k) {
+            E1[k] = b[k] - a[k];
+            E2[k] = cc[k] - a[k];
+        }
+        const double G11 = E1[0] * E1[0] + E1[1] * E1[1] + E1[2] * E1[2];
+        const double G12 = E1[0] * E2[0] + E1[1] * E2[1] + E1[2] * E2[2];
+        const double G22 = E2[0] * E2[0] + E2[1] * E2[1] + E2[2] * E2[2];
+        const double det = G11 * G22 - G12 * G12;
+        if (!(det > 0.0) || !std::isfinite(det)) return fail(c, IBLB_E_MESH, "degenerate reference face " + std::to_string(j));
+        fref[j] = G22 / det;
+        fref[(size_t)nf + j] = -G12 / det;
+        fref[(size_t)2 * nf + j] = G11 / det;
+        fref[(size_t)3 * nf + j] = 0.5 * std::sqrt(det);
+        fref[(size_t)4 * nf + j] = det;
+        const double A[3] = {a[0] - o[0], a[1] - o[1], a[2] - o[2]};
+        const double B[3] = {b[0] - o[0], b[1] - o[1], b[2] - o[2]};
+        const double C[3] = {cc[0] - o[0], cc[1] - o[1], cc[2] - o[2]};
+        const double Vj = (A[0] * (B[1] * C[2] - B[2] * C[1]) + A[1] * (B[2] * C[0] - B[0] * C[2]) +
+                           A[2] * (B[0] * C[1] - B[1] * C[0])) / 6.0;
+        V0 += Vj;
+    }
+    if (!(V0 > 0.0)) return fail(c, IBLB_E_MESH, "reference volume not positive (faces must point outward)");
+
+    // vertex -> (face, corner), faces ascending
+    std::vector<int> off(nv + 1, 0), inc((size_t)3 * nf);
+    for (int j = 0; j < nf; ++j)
+        for (int k = 0; k < 3; ++k) off[mesh->faces[3 * j + k] + 1]++;
+    for (int i = 0; i < nv; ++i) off[i + 1] += off[i];
+    {
+        std::vector<int> fill(off.begin(), off.end() - 1);
+        for (int j = 0; j < nf; ++j)
+            for (int k = 0; k < 3; ++k) inc[fill[mesh->faces[3 * j + k]]++] = (j << 2) | k;
+    }
+    // structure-of-arrays copies
+    std::vector<double> qs((size_t)3 * nv), Xs((size_t)3 * nv);
+    for (int i = 0; i < nv; ++i)
+        for (int k = 0; k < 3; ++k) {
+            qs[(size_t)k * nv + i] = mesh->vertices[3 * i + k];
+            Xs[(size_t)k * nv + i] = X[3 * i + k];
+        }
+    std::vector<int> fs((size_t)3 * nf);
+    for (int j = 0; j < nf; ++j)
+        for (int k = 0; k < 3; ++k) fs[(size_t)k * nf + j] = mesh->faces[3 * j + k];
+
+    // device memory for the mesh part
+    const Layout L = make_layout(c->g, c->ts, nv, nf);
+    char *mb = nullptr;
+    if (c->own_ws || c->ws_bytes < L.mesh_end) {
+        // the mesh block is not covered by a caller's workspace: allocate it here
+        void *p = nullptr;
+        HIP_TRY(c, hipMalloc(&p, L.mesh_end - L.dom_end));
+        c->mesh_alloc = p;
+        mb = (char *)p - L.dom_end;  // the offsets below are workspace-relative
+    } else {
+        mb = c->ws;
+    }
+    c->L = L;
+    Dev &d = c->d;
+    d.q = (double *)(mb + L.q);
+    d.Xref = (double *)(mb + L.Xref);
+    d.faces = (int *)(mb + L.faces);
+    d.fref = (double *)(mb + L.fref);
+    d.inc_off = (int *)(mb + L.inc_off);
+    d.inc = (int *)(mb + L.inc);
+    d.phiSW = mb + L.phiSW;
+    d.gV = mb + L.gV;
+    d.base = (Base *)(mb + L.base);
+    d.wts = mb + L.wts;
+    d.partials = (double *)(mb + L.partials);
+    d.cnt = (uint32_t *)(mb + L.cnt);
+    d.list = (int *)(mb + L.list);
+    d.acnt = (uint32_t *)(mb + L.acnt);
+    d.alist = (int *)(mb + L.alist);
+    HIP_TRY(c, hipMemcpyAsync(d.q, qs.data(), qs.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d.Xref, Xs.data(), Xs.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d.faces, fs.data(), fs.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d.fref, fref.data(), fref.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d.inc_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d.inc, inc.data(), inc.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(d.partials, 0, (size_t)2 * ((nv + 255) / 256) * 8, c->stream));
+
+    MeshArgs &m = c->m;
+    m.nv = nv;
+    m.nf = nf;
+    for (int k = 0; k < 3; ++k) {
+        m.alpha[k] = mesh->alpha[k];
+        m.origin[k] = o[k];
+    }
+    m.eps_lo = mesh->eps_wall_lo;
+    m.eps_hi = mesh->eps_wall_hi;
+    m.xi = mesh->xi_wall;
+    m.rc = mesh->r_cut_wall;
+    m.z_lo = 0.5;
+    m.z_hi = c->dom.nz - 1.5;
+    m.kv_over_V0 = mesh->k_v / V0;
+    m.nparts = (nv + 255) / 256;
+    c->V0 = V0;
+    c->nv = nv;
+    c->nf = nf;
+    c->has_mesh = true;
+    drop_graph(c);
+    rc = rebuild_lists(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (mesh_id) *mesh_id = 0;
+    return IBLB_OK;
+}
+
+int iblb_step(iblb_ctx *c, int32_t n_steps)
+{
+    if (!c || n_steps < 0) return IBLB_E_INVAL;
+    for (int s = 0; s < n_steps; ++s) {
+        if (c->timing) {
+            hipError_t e = enqueue_step(c, true);
+            if (e != hipSuccess) return hip_fail(c, e, "step launch");
+        } else if (c->use_graph) {
+            if (!c->gexec) {
+                HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                hipError_t e = enqueue_step(c, false);
+                hipGraph_t gr = nullptr;
+                hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
+                if (e != hipSuccess) return hip_fail(c, e, "step capture");
+                if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+                c->graph = gr;
+                HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+            }
+            HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+        } else {
+            hipError_t e = enqueue_step(c, false);
+            if (e != hipSuccess) return hip_fail(c, e, "step launch");
+        }
+        c->t++;
+    }
+    if (c->timing) return collect_timing(c);
+    return IBLB_OK;
+}
+
+int iblb_sync(iblb_ctx *c)
+{
+    if (!c) return IBLB_E_INVAL;
+    return sync_ctx(c);
+}
+
+int iblb_step_count(const iblb_ctx *c, int64_t *t)
+{
+    if (!c || !t) return IBLB_E_INVAL;
+    *t = c->t;
+    return IBLB_OK;
+}
+
+int iblb_get_vertices(iblb_ctx *c, int32_t mesh_id, double *host_out)
+{
+    int rc = mesh_ok(c, mesh_id);
+    if (rc) return rc;
+    if (!host_out) return IBLB_E_INVAL;
+    rc = sync_ctx(c);
+    std::vector<double> qs((size_t)3 * c->nv);
+    HIP_TRY(c, hipMemcpy(qs.data(), c->d.q, qs.size() * 8, hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->nv; ++i)
+        for (int k = 0; k < 3; ++k) host_out[3 * i + k] = qs[(size_t)k * c->nv + i];
+    return rc;
+}
+
+int iblb_vertices_device(iblb_ctx *c, int32_t mesh_id, const double **dev_ptr)
+{
+    int rc = mesh_ok(c, mesh_id);
+    if (rc) return rc;
+    if (!dev_ptr) return IBLB_E_INVAL;
+    *dev_ptr = c->d.q;
+    return IBLB_OK;
+}
+
+static int mesh_moments(iblb_ctx *c, double *mom)
+{
+    int rc = sync_ctx(c);
+    HIP_TRY(c, launch_mesh_moments(c->d, c->m, c->d.scratch, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(mom, c->d.scratch, 11 * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return rc;
+}
+
+int iblb_volume(iblb_ctx *c, int32_t mesh_id, double *V, double *A)
+{
+    int rc = mesh_ok(c, mesh_id);
+    if (rc) return rc;
+    double mom[11];
+    rc = mesh_moments(c, mom);
+    if (rc == IBLB_E_DEVICE) return rc;
+    if (V) *V = mom[0];
+    if (A) *A = mom[1];
+    return rc;
+}
+
+int iblb_shape(iblb_ctx *c, int32_t mesh_id, double *D, double *Theta, double centroid[3])
+{
+    int rc = mesh_ok(c, mesh_id);
+    if (rc) return rc;
+    double mom[11];
+    rc = mesh_moments(c, mom);
+    if (rc == IBLB_E_DEVICE) return rc;
+    const double V = mom[0];
+    if (!(V > 0.0)) return fail(c, IBLB_E_UNSTABLE, "non-positive enclosed volume");
+    const double xc[3] = {mom[2] / V, mom[3] / V, mom[4] / V};
+    // central second moments, x-z block
+    const double a = mom[5] - V * xc[0] * xc[0];  // xx
+    const double cz = mom[7] - V * xc[2] * xc[2]; // zz
+    const double b = mom[9] - V * xc[0] * xc[2];  // xz
+    const double mean = 0.5 * (a + cz), hd = 0.5 * (a - cz);
+    const double rad = std::sqrt(hd * hd + b * b);
+    const double l1 = mean + rad, l3 = mean - rad;
+    const double r1 = std::sqrt(5.0 * std::max(l1, 0.0) / V), r3 = std::sqrt(5.0 * std::max(l3, 0.0) / V);
+    double th = 0.5 * std::atan2(2.0 * b, a - cz);
+    if (th > M_PI / 2) th -= M_PI;
+    if (th <= -M_PI / 2) th += M_PI;
+    if (D) *D = (r1 - r3) / (r1 + r3);
+    if (Theta) *Theta = th;
+    if (centroid)
+        for (int k = 0; k < 3; ++k) centroid[k] = c->m.origin[k] + xc[k];
+    return rc;
+}
+
+int iblb_contact_angle(iblb_ctx *c, int32_t mesh_id, int32_t wall, int32_t method, double *theta_deg,
+                       double *contact_radius, double *height)
+{
+    int rc = mesh_ok(c, mesh_id);
+    if (rc) return rc;
+    if (wall != 0 && wall != 1) return fail(c, IBLB_E_INVAL, "wall must be 0 (lower) or 1 (upper)");
+    if (method != 0) return fail(c, IBLB_E_INVAL, "only method 0 (sphere fit) is supported");
+    if (!c->g.walls) return fail(c, IBLB_E_STATE, "no walls in a periodic domain");
+    rc = sync_ctx(c);
+    const double zw = wall ? c->dom.nz - 1.5 : 0.5;
+    const double shift[3] = {c->m.origin[0], c->m.origin[1], zw};
+    double mom[15];
+    HIP_TRY(c, launch_sphere_moments(c->d, c->m, wall, zw, 2.0, shift, c->d.scratch, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(mom, c->d.scratch, 15 * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (mom[14] < 4.0) return fail(c, IBLB_E_STATE, "fewer than 4 vertices away from the wall");
+    // normal equations N s = r, N symmetric 4x4 from the packed upper triangle
+    double N[4][5];
+    int k = 0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = i; j < 4; ++j) {
+            N[i][j] = mom[k];
+            N[j][i] = mom[k];
+            ++k;
+        }
+    for (int i = 0; i < 4; ++i) N[i][4] = mom[10 + i];
+    for (int col = 0; col < 4; ++col) {  // Gaussian elimination, partial pivoting
+        int piv = col;
+        for (int r = col + 1; r < 4; ++r)
+            if (std::fabs(N[r][col]) > std::fabs(N[piv][col])) piv = r;
+        if (!(std::fabs(N[piv][col]) > 0.0)) return fail(c, IBLB_E_STATE, "singular sphere fit");
+        for (int cc = 0; cc < 5; ++cc) std::swap(N[col][cc], N[piv][cc]);
+        for (int r = col + 1; r < 4; ++r) {
+            const double fct = N[r][col] / N[col][col];
+            for (int cc = col; cc < 5; ++cc) N[r][cc] -= fct * N[col][cc];
+        }
+    }
+    double s[4];
+    for (int i = 3; i >= 0; --i) {
+        double acc = N[i][4];
+        for (int j = i + 1; j < 4; ++j) acc -= N[i][j] * s[j];
+        s[i] = acc / N[i][i];
+    }
+    const double R = std::sqrt(s[3] + s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    const double hc = wall ? -s[2] : s[2];  // centre height above the wall plane (into the fluid)
+    const double cth = std::max(-1.0, std::min(1.0, -hc / R));
+    if (theta_deg) *theta_deg = std::acos(cth) * 180.0 / M_PI;
+    if (contact_radius) *contact_radius = std::sqrt(std::max(0.0, R * R - hc * hc));
+    if (height) *height = hc + R;
+    return rc;
+}
+
+int iblb_get_fields(iblb_ctx *c, double *rho, double *u)
+{
+    if (!c || !rho || !u) return IBLB_E_INVAL;
+    int rc = sync_ctx(c);
+    const size_t n = (size_t)c->g.n;
+    TmpDev tmp;
+    HIP_TRY(c, hipMalloc(&tmp.p, 4 * n * 8));
+    double *dr = (double *)tmp.p, *du = dr + n;
+    HIP_TRY(c, launch_get_fields(c->prec, c->d, c->lb, dr, du, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(rho, dr, n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(u, du, 3 * n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return rc;
+}
+
+int iblb_debug_set_force(iblb_ctx *c, const double *F)
+{
+    if (!c || !F) return IBLB_E_INVAL;
+    if (c->has_mesh) return fail(c, IBLB_E_STATE, "debug force field only without a mesh");
+    const size_t n = (size_t)c->g.n;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!c->d.Fext) {
+        HIP_TRY(c, hipMalloc(&c->fext_alloc, 3 * n * c->ts));
+        c->d.Fext = c->fext_alloc;
+    }
+    if (c->prec == IBLB_FP64) {
+        HIP_TRY(c, hipMemcpy(c->d.Fext, F, 3 * n * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> tmp(3 * n);
+        for (size_t i = 0; i < 3 * n; ++i) tmp[i] = (float)F[i];
+        HIP_TRY(c, hipMemcpy(c->d.Fext, tmp.data(), 3 * n * 4, hipMemcpyHostToDevice));
+    }
+    lb_args(c);
+    drop_graph(c);
+    return IBLB_OK;
+}
+
+int iblb_debug_get_force(iblb_ctx *c, double *F)
+{
+    if (!c || !F) return IBLB_E_INVAL;
+    int rc = sync_ctx(c);
+    const size_t n = (size_t)c->g.n;
+    TmpDev tmp;
+    HIP_TRY(c, hipMalloc(&tmp.p, 3 * n * 8));
+    HIP_TRY(c, launch_get_force(c->prec, c->d, c->lb, (double *)tmp.p, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(F, tmp.p, 3 * n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return rc;
+}
+
+int iblb_debug_get_populations(iblb_ctx *c, double *f)
+{
+    if (!c || !f) return IBLB_E_INVAL;
+    int rc = sync_ctx(c);
+    const size_t n = (size_t)c->g.n;
+    TmpDev tmp;
+    HIP_TRY(c, hipMalloc(&tmp.p, 19 * n * 8));
+    HIP_TRY(c, launch_get_pops(c->prec, c->d, c->g, (double *)tmp.p, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(f, tmp.p, 19 * n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return rc;
+}
+
+int iblb_debug_set_populations(iblb_ctx *c, const double *f)
+{
+    if (!c || !f) return IBLB_E_INVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const size_t n = (size_t)c->g.n;
+    TmpDev tmp;
+    HIP_TRY(c, hipMalloc(&tmp.p, 19 * n * 8));
+    HIP_TRY(c, hipMemcpyAsync(tmp.p, f, 19 * n * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, launch_set_pops(c->prec, c->d, c->g, (const double *)tmp.p, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return IBLB_OK;
+}
+
+int iblb_debug_get_nodal_forces(iblb_ctx *c, int32_t mesh_id, double *phi)
+{
+    int rc = mesh_ok(c, mesh_id);
+    if (rc) return rc;
+    if (!phi) return IBLB_E_INVAL;
+    rc = sync_ctx(c);
+    TmpDev tmp;
+    HIP_TRY(c, hipMalloc(&tmp.p, (size_t)3 * c->nv * 8));
+    HIP_TRY(c, launch_nodal_forces(c->prec, c->d, c->m, (double *)tmp.p, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(phi, tmp.p, (size_t)3 * c->nv * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return rc;
+}
+
+namespace {
+struct StateHeader {
+    char magic[8];
+    int32_t precision, nx, ny, nz, wall_mode, nv;
+    int64_t t;
+    int32_t err, pad;
+};
+}  // namespace
+
+int iblb_save_state(iblb_ctx *c, void *host_buf, size_t *bytes)
+{
+    if (!c || !bytes) return IBLB_E_INVAL;
+    const size_t n = (size_t)c->g.n;
+    const size_t need = sizeof(StateHeader) + 19 * n * c->ts + 3 * n * c->ts + (size_t)c->g.nt * 4 +
+                        (size_t)3 * c->nv * 8;
+    if (!host_buf) {
+        *bytes = need;
+        return IBLB_OK;
+    }
+    if (*bytes < need) return fail(c, IBLB_E_INVAL, "state buffer too small");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    StateHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, kMagic, 8);
+    h.precision = c->prec;
+    h.nx = c->g.nx;
+    h.ny = c->g.ny;
+    h.nz = c->g.nz;
+    h.wall_mode = c->dom.wall_mode;
+    h.nv = c->nv;
+    h.t = c->t;
+    HIP_TRY(c, hipMemcpy(&h.err, c->d.err, 4, hipMemcpyDeviceToHost));
+    char *p = (char *)host_buf;
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    HIP_TRY(c, hipMemcpy(p, c->d.f, 19 * n * c->ts, hipMemcpyDeviceToHost));
+    p += 19 * n * c->ts;
+    HIP_TRY(c, hipMemcpy(p, c->d.F, 3 * n * c->ts, hipMemcpyDeviceToHost));
+    p += 3 * n * c->ts;
+    HIP_TRY(c, hipMemcpy(p, c->d.stamp, (size_t)c->g.nt * 4, hipMemcpyDeviceToHost));
+    p += (size_t)c->g.nt * 4;
+    if (c->nv) HIP_TRY(c, hipMemcpy(p, c->d.q, (size_t)3 * c->nv * 8, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return IBLB_OK;
+}
+
+int iblb_load_state(iblb_ctx *c, const void *host_buf, size_t bytes)
+{
+    if (!c || !host_buf) return IBLB_E_INVAL;
+    const size_t n = (size_t)c->g.n;
+    const size_t need = sizeof(StateHeader) + 19 * n * c->ts + 3 * n * c->ts + (size_t)c->g.nt * 4 +
+                        (size_t)3 * c->nv * 8;
+    if (bytes < need) return fail(c, IBLB_E_INVAL, "state buffer too small");
+    StateHeader h;
+    std::memcpy(&h, host_buf, sizeof(h));
+    if (std::memcmp(h.magic, kMagic, 8) != 0) return fail(c, IBLB_E_INVAL, "not an iblb state buffer");
+    if (h.precision != c->prec || h.nx != c->g.nx || h.ny != c->g.ny || h.nz != c->g.nz ||
+        h.wall_mode != c->dom.wall_mode || h.nv != c->nv || h.t < 0 || h.t > 0xffffffffll)
+        return fail(c, IBLB_E_INVAL, "state buffer does not match this context");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const char *p = (const char *)host_buf + sizeof(h);
+    HIP_TRY(c, hipMemcpy(c->d.f, p, 19 * n * c->ts, hipMemcpyHostToDevice));
+    p += 19 * n * c->ts;
+    HIP_TRY(c, hipMemcpy(c->d.F, p, 3 * n * c->ts, hipMemcpyHostToDevice));
+    p += 3 * n * c->ts;
+    HIP_TRY(c, hipMemcpy(c->d.stamp, p, (size_t)c->g.nt * 4, hipMemcpyHostToDevice));
+    p += (size_t)c->g.nt * 4;
+    if (c->nv) HIP_TRY(c, hipMemcpy(c->d.q, p, (size_t)3 * c->nv * 8, hipMemcpyHostToDevice));
+    const uint32_t t32 = (uint32_t)h.t;
+    HIP_TRY(c, hipMemcpy(c->d.t, &t32, 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d.err, &h.err, 4, hipMemcpyHostToDevice));
+    c->t = h.t;
+    if (c->has_mesh) {
+        int rc = rebuild_lists(c);
+        if (rc) return rc;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return IBLB_OK;
+}
+
+int iblb_set_graph(iblb_ctx *c, int32_t graph)
+{
+    if (!c) return IBLB_E_INVAL;
+    c->use_graph = graph != 0;
+    if (!c->use_graph) drop_graph(c);
+    return IBLB_OK;
+}
+
+int iblb_set_timing(iblb_ctx *c, int32_t timing)
+{
+    if (!c) return IBLB_E_INVAL;
+    c->timing = timing != 0;
+    return IBLB_OK;
+}
+
+int iblb_kernel_time(iblb_ctx *c, const char *name, double *total_ms, int64_t *launches)
+{
+    if (!c || !name) return IBLB_E_INVAL;
+    int rc = collect_timing(c);
+    if (rc) return rc;
+    for (int k = 0; k < kNumKernels; ++k)
+        if (std::strcmp(name, kKernelNames[k]) == 0) {
+            if (total_ms) *total_ms = c->ktime[k];
+            if (launches) *launches = c->kcount[k];
+            return IBLB_OK;
+        }
+    return fail(c, IBLB_E_INVAL, std::string("unknown kernel name ") + name);
+}
+
+int iblb_reset_timing(iblb_ctx *c)
+{
+    if (!c) return IBLB_E_INVAL;
+    int rc = collect_timing(c);
+    for (int k = 0; k < kNumKernels; ++k) {
+        c->ktime[k] = 0.0;
+        c->kcount[k] = 0;
+    }
+    return rc;
+}
+
+const char *iblb_last_error(const iblb_ctx *c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+int iblb_destroy(iblb_ctx *c)
+{
+    if (!c) return IBLB_E_INVAL;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto &p : c->pending) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    drop_graph(c);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->mesh_alloc) (void)hipFree(c->mesh_alloc);
+    if (c->fext_alloc) (void)hipFree(c->fext_alloc);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return IBLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal interface between the host side of libiblb (iblb_api.cpp) and its
+// HIP kernels (iblb_kernels.hip).  Not installed, not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace iblb {
+
+// Force-density tiles: 4x4x4 fluid nodes, one wavefront each when spreading.
+constexpr int kTile = 4;
+// Maximum vertices whose stencil reaches one tile.
+constexpr int kTileCap = 512;
+// Device error bits.
+constexpr int kErrNonFinite = 1;   // a vertex position left the finite range
+constexpr int kErrOverflow = 2;    // a tile list overflowed kTileCap
+constexpr int kErrDensity = 4;     // a node density became non-finite or left (0.5, 2)
+constexpr int kErrMach = 8;        // |u| above 0.3 somewhere
+
+struct alignas(16) Base {
+    int x, y, z, ok;  // stencil corner floor(q)-1 (x, y wrapped; z absolute, wrapped if periodic); ok = 1 if finite
+};
+
+struct Grid {
+    int nx, ny, nz;       // lattice
+    int nzf, zoff;        // fluid layers, first fluid z
+    int walls;            // 1: solid z layers, 0: periodic z
+    long long n;          // fluid nodes
+    int ntx, nty, ntz;    // tiles over fluid nodes
+    int nt;
+};
+
+struct LBArgs {
+    Grid g;
+    double tau_inv;       // 1/tau
+    double guo;           // 1 - 1/(2 tau)
+    double rho0;
+    double body[3];
+    double ulo[3], uhi[3];
+    int has_fext;
+};
+
+struct MeshArgs {
+    int nv, nf;
+    double alpha[3];
+    double eps_lo, eps_hi, xi, rc;
+    double z_lo, z_hi;
+    double origin[3];
+    double kv_over_V0;    // k_V / V0
+    int nparts;           // force-kernel blocks = number of volume partials
+};
+
+// Device buffers of one context (typed as void* where the precision varies).
+struct Dev {
+    void *f;              // [19][n] populations (deviation), AA layout
+    void *F;              // [3][n] IB force density of the step stamped in `stamp`
+    void *Fext;           // [3][n] or null
+    uint32_t *stamp;      // [nt] step+1 for which F of the tile is valid
+    uint32_t *t;          // device step counter
+    uint32_t *done;       // last-block counter
+    int *err;             // error bits
+    // mesh
+    double *q;            // [3][nv] FP64 positions
+    double *Xref;         // [3][nv] FP64 reference (stress-free) positions
+    int *faces;           // [3][nf]
+    double *fref;         // [5][nf]: Ginv11, Ginv12, Ginv22, A0, detG
+    int *inc_off;         // [nv+1]
+    int *inc;             // [3 nf]: face*4 + corner, vertex-major, faces ascending
+    void *phiSW;          // [3][nv] elastic + wall force
+    void *gV;             // [3][nv] dV/dq
+    Base *base;           // [nv]
+    void *wts;            // [nv][12] phi4 weights (x 0..3, y 0..3, z 0..3)
+    double *partials;     // [2][nparts]: sum (V_j - V0_j), sum A_j per force block
+    uint32_t *cnt;        // [2][nt]
+    int *list;            // [2][nt][kTileCap]
+    uint32_t *acnt;       // [2]
+    int *alist;           // [2][nt]
+    double *scratch;      // small FP64 scratch for queries (64 doubles)
+};
+
+// launchers (iblb_kernels.hip); precision 0 = FP64, 1 = FP32
+hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hipStream_t s);
+hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, hipStream_t s);
+hipError_t launch_tick(const Dev &d, hipStream_t s);
+hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s);
+hipError_t launch_spread(int prec, const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s);
+hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s);
+hipError_t launch_bin(const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s);
+// debug / query kernels
+hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, double *out, hipStream_t s);
+hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, const double *in, hipStream_t s);
+hipError_t launch_get_fields(int prec, const Dev &d, const LBArgs &a, double *rho, double *u, hipStream_t s);
+hipError_t launch_get_force(int prec, const Dev &d, const LBArgs &a, double *F, hipStream_t s);
+hipError_t launch_nodal_forces(int prec, const Dev &d, const MeshArgs &m, double *phi, hipStream_t s);
+hipError_t launch_mesh_moments(const Dev &d, const MeshArgs &m, double *out, hipStream_t s);
+hipError_t launch_sphere_moments(const Dev &d, const MeshArgs &m, int wall_hi, double z_wall, double excl,
+                                 const double *shift, double *out, hipStream_t s);
+
+}  // namespace iblb

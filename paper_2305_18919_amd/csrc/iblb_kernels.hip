@@ -1,0 +1,1089 @@
+// HIP kernels of libiblb for gfx950 (MI355X): one IB-LB time step of
+// arXiv:2305.18919 (the enumerated algorithm of the "Numerical
+// implementation" section), plus the debug and query reductions.
+//
+// Per step, in stream order:
+//   k_forces  one thread per vertex: elastic force -dW/dq of the incident faces
+//             (Eqs. generalised_energy1, nodal_force_S), dV/dq (Eq.
+//             nodal_force_V), wall force (Eq. LJ_interaction), FP64 block
+//             partials of V - V0 and A, and the vertex's phi4 stencil weights
+//   k_spread  one wavefront per active 4x4x4 tile: gathers phi_i w_i(x) of the
+//             vertices whose stencil reaches the tile, in ascending vertex order
+//             (Eq. ibm-governing_eq2); no floating-point atomics
+//   k_lb      one thread per fluid node: AA-pattern in-place stream + BGK
+//             collision with Guo forcing and half-way moving-wall bounce-back
+//             (Eqs. LBeq, feq)
+//   k_move    one wavefront per vertex, one lane per stencil node: u(t+1) from
+//             the streamed populations and F(t)/2, interpolation (Eq.
+//             ibm-governing_eq1), Euler update (Eq. ibm_update_pos), and the
+//             tile lists of the next step; the last block advances the device
+//             step counter.
+//
+// Data layout (all structure-of-arrays, x fastest):
+//   populations f[19][N] (N fluid nodes), deviations f_i - w_i rho0, in place
+//   with the AA pattern: at even times slot (i, x) holds f_i(x); at odd times
+//   slot (opp(i), x - c_i) holds f_i(x) (slot (i, x) when x - c_i is solid).
+//   force density F[3][N], valid on a tile when stamp[tile] == step + 1.
+#include "iblb_internal.h"
+
+#include <math.h>
+
+namespace iblb {
+namespace {
+
+// D3Q19 velocities in the canonical order of the ABI: rest, +-x, +-y, +-z,
+// +-(1,1,0), +-(1,-1,0), +-(1,0,1), +-(1,0,-1), +-(0,1,1), +-(0,1,-1).
+__device__ __forceinline__ constexpr int cx(int i)
+{
+    constexpr int t[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return t[i];
+}
+__device__ __forceinline__ constexpr int cy(int i)
+{
+    constexpr int t[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return t[i];
+}
+__device__ __forceinline__ constexpr int cz(int i)
+{
+    constexpr int t[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return t[i];
+}
+__device__ __forceinline__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+template <typename T>
+__device__ __forceinline__ constexpr T wgt(int i)
+{
+    return i == 0 ? T(1.0 / 3.0) : (i <= 6 ? T(1.0 / 18.0) : T(1.0 / 36.0));
+}
+
+__device__ __forceinline__ int wrapi(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ long long nidx(const Grid &g, int x, int y, int zf)
+{
+    return ((long long)zf * g.ny + y) * g.nx + x;
+}
+
+__device__ __forceinline__ int tile_of(const Grid &g, int x, int y, int zf)
+{
+    return ((zf >> 2) * g.nty + (y >> 2)) * g.ntx + (x >> 2);
+}
+
+// 4-point stencil phi4, Eq. ibm-interpolation_stencil.
+template <typename T>
+__device__ __forceinline__ T phi4(T r)
+{
+    const T a = fabs(r);
+    if (a <= T(1))
+        return T(0.125) * (T(3) - T(2) * a + sqrt(T(1) + T(4) * a - T(4) * a * a));
+    if (a <= T(2))
+        return T(0.125) * (T(5) - T(2) * a - sqrt(T(-7) + T(12) * a - T(4) * a * a));
+    return T(0);
+}
+
+// Wall force magnitude along the wall normal at centroid distance d,
+// Eq. LJ_interaction: 48 eps [(xi/d)^12 - (xi/d)^6/2] / d, cut at rc, d >= xi/2.
+template <typename T>
+__device__ __forceinline__ T lj(T eps, T xi, T rc, T d)
+{
+    if (eps == T(0) || !(d < rc))
+        return T(0);
+    if (d < T(0.5) * xi)
+        d = T(0.5) * xi;
+    const T s = xi / d;
+    const T s2 = s * s;
+    const T s6 = s2 * s2 * s2;
+    return T(48) * eps * (s6 * s6 - T(0.5) * s6) / d;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Populations at time t in canonical order, for either AA layout.
+// swapped = (t odd): f_i(x) is at slot (opp(i), x - c_i), or at (i, x) when
+// x - c_i is not a fluid node.
+// ---------------------------------------------------------------------------
+struct Nbr {
+    int xp, xm, yp, ym, zp, zm;
+    bool zp_ok, zm_ok;
+};
+
+__device__ __forceinline__ Nbr neighbours(const Grid &g, int x, int y, int zf)
+{
+    Nbr b;
+    b.xp = (x + 1 == g.nx) ? 0 : x + 1;
+    b.xm = (x == 0) ? g.nx - 1 : x - 1;
+    b.yp = (y + 1 == g.ny) ? 0 : y + 1;
+    b.ym = (y == 0) ? g.ny - 1 : y - 1;
+    b.zp = zf + 1;
+    b.zm = zf - 1;
+    if (g.walls) {
+        b.zp_ok = b.zp < g.nzf;
+        b.zm_ok = b.zm >= 0;
+    } else {
+        b.zp_ok = b.zm_ok = true;
+        if (b.zp == g.nzf) b.zp = 0;
+        if (b.zm < 0) b.zm = g.nzf - 1;
+    }
+    return b;
+}
+
+// node x + s*c_i (s = +1 destination, -1 source); returns false if not fluid
+__device__ __forceinline__ bool shifted(const Grid &g, const Nbr &b, int x, int y, int zf, int i, int s,
+                                        long long &out)
+{
+    const int ddx = s * cx(i), ddy = s * cy(i), ddz = s * cz(i);
+    const int xx = ddx == 0 ? x : (ddx > 0 ? b.xp : b.xm);
+    const int yy = ddy == 0 ? y : (ddy > 0 ? b.yp : b.ym);
+    bool ok = true;
+    int zz = zf;
+    if (ddz > 0) { zz = b.zp; ok = b.zp_ok; }
+    if (ddz < 0) { zz = b.zm; ok = b.zm_ok; }
+    out = nidx(g, xx, yy, zz);
+    return ok;
+}
+
+template <typename T, bool SWAPPED>
+__device__ __forceinline__ void load_pops(const T *__restrict__ f, const Grid &g, int x, int y, int zf, T *d)
+{
+    const long long me = nidx(g, x, y, zf);
+    const long long n = g.n;
+    if (!SWAPPED) {
+#pragma unroll
+        for (int i = 0; i < 19; ++i)
+            d[i] = f[i * n + me];
+    } else {
+        const Nbr b = neighbours(g, x, y, zf);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            long long src;
+            const bool ok = shifted(g, b, x, y, zf, i, -1, src);
+            d[i] = ok ? f[opp(i) * n + src] : f[i * n + me];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LB: AA-pattern stream + collide
+// ---------------------------------------------------------------------------
+template <typename T, bool ODD>
+__device__ __forceinline__ void lb_node(T *__restrict__ f, const T *__restrict__ Fib, const T *__restrict__ Fext,
+                                        const uint32_t *__restrict__ stamp, uint32_t t, int *err, const LBArgs &a,
+                                        int x, int y, int zf)
+{
+    const Grid &g = a.g;
+    const long long n = g.n;
+    const long long me = nidx(g, x, y, zf);
+    const Nbr b = neighbours(g, x, y, zf);
+
+    T d[19];
+    if (!ODD) {
+#pragma unroll
+        for (int i = 0; i < 19; ++i)
+            d[i] = f[i * n + me];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            long long src;
+            const bool ok = shifted(g, b, x, y, zf, i, -1, src);
+            d[i] = ok ? f[opp(i) * n + src] : f[i * n + me];
+        }
+    }
+
+    // force density: body force + IB force (tile stamped for this step) + external
+    T Fx = T(a.body[0]), Fy = T(a.body[1]), Fz = T(a.body[2]);
+    if (stamp != nullptr && stamp[tile_of(g, x, y, zf)] == t + 1u) {
+        Fx += Fib[me];
+        Fy += Fib[n + me];
+        Fz += Fib[2 * n + me];
+    }
+    if (a.has_fext) {
+        Fx += Fext[me];
+        Fy += Fext[n + me];
+        Fz += Fext[2 * n + me];
+    }
+
+    T drho = T(0), mx = T(0), my = T(0), mz = T(0);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        drho += d[i];
+        if (cx(i) != 0) mx += T(cx(i)) * d[i];
+        if (cy(i) != 0) my += T(cy(i)) * d[i];
+        if (cz(i) != 0) mz += T(cz(i)) * d[i];
+    }
+    const T rho = T(a.rho0) + drho;
+    const T ux = (mx + T(0.5) * Fx) / rho;
+    const T uy = (my + T(0.5) * Fy) / rho;
+    const T uz = (mz + T(0.5) * Fz) / rho;
+    const T uu = ux * ux + uy * uy + uz * uz;
+    if (!(fabs(drho) < T(0.5)))
+        atomicOr(err, kErrDensity);
+    if (uu > T(0.09))
+        atomicOr(err, kErrMach);
+
+    const T tinv = T(a.tau_inv), guo = T(a.guo);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const T w = wgt<T>(i);
+        const T cu = T(cx(i)) * ux + T(cy(i)) * uy + T(cz(i)) * uz;
+        const T deq = w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
+        const T cmuF = (T(cx(i)) - ux) * Fx + (T(cy(i)) - uy) * Fy + (T(cz(i)) - uz) * Fz;
+        const T cF = T(cx(i)) * Fx + T(cy(i)) * Fy + T(cz(i)) * Fz;
+        const T S = w * guo * (T(3) * cmuF + T(9) * cF * cu);
+        T post = d[i] - (d[i] - deq) * tinv + S;
+        long long dst;
+        const bool fluid = shifted(g, b, x, y, zf, i, +1, dst);
+        if (!fluid) {
+            // half-way bounce-back off a (moving) wall: -2 w rho (c.u_w)/c_s^2
+            const double *uw = cz(i) < 0 ? a.ulo : a.uhi;
+            const T cuw = T(cx(i)) * T(uw[0]) + T(cy(i)) * T(uw[1]) + T(cz(i)) * T(uw[2]);
+            post -= T(6) * w * rho * cuw;
+        }
+        if (!ODD || !fluid)
+            f[opp(i) * n + me] = post;
+        else
+            f[i * n + dst] = post;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_lb(T *__restrict__ f, const T *__restrict__ Fib,
+                                            const T *__restrict__ Fext, const uint32_t *__restrict__ stamp,
+                                            const uint32_t *__restrict__ dt, uint32_t *acnt, int *err, LBArgs a)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int zf = blockIdx.z;
+    const uint32_t t = *dt;
+    if (acnt != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 &&
+        threadIdx.y == 0)
+        acnt[t & 1u] = 0u;  // the spread of this step has consumed its tile list
+    if (x >= a.g.nx || y >= a.g.ny)
+        return;
+    if (t & 1u)
+        lb_node<T, true>(f, Fib, Fext, stamp, t, err, a, x, y, zf);
+    else
+        lb_node<T, false>(f, Fib, Fext, stamp, t, err, a, x, y, zf);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init(T *__restrict__ f, LBArgs a, int couette)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int zf = blockIdx.z;
+    if (x >= a.g.nx || y >= a.g.ny)
+        return;
+    const Grid &g = a.g;
+    const long long me = nidx(g, x, y, zf);
+    double u[3] = {0.0, 0.0, 0.0};
+    if (couette && g.walls) {
+        const double z = zf + g.zoff, zlo = 0.5, zhi = g.nz - 1.5;
+        for (int k = 0; k < 3; ++k)
+            u[k] = a.ulo[k] + (a.uhi[k] - a.ulo[k]) * (z - zlo) / (zhi - zlo);
+    }
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
+        const double w = wgt<double>(i);
+        f[i * g.n + me] = T(w * a.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    }
+}
+
+__global__ void k_tick(uint32_t *dt)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *dt = *dt + 1u;
+}
+
+// ---------------------------------------------------------------------------
+// Interface forces, one thread per vertex
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cross6(double ux, double uy, double uz, double vx, double vy, double vz, double *o)
+{
+    o[0] = (uy * vz - uz * vy) / 6.0;
+    o[1] = (uz * vx - ux * vz) / 6.0;
+    o[2] = (ux * vy - uy * vx) / 6.0;
+}
+
+__device__ __forceinline__ double triple(double ax, double ay, double az, double bx, double by, double bz, double cx_,
+                                         double cy_, double cz_)
+{
+    return ax * (by * cz_ - bz * cy_) + ay * (bz * cx_ - bx * cz_) + az * (bx * cy_ - by * cx_);
+}
+
+// V_j(q) - V_j(X) of the tetrahedron (o, a, b, c), expanded exactly in the
+// displacements from the reference vertices X: the seven triple products that
+// contain at least one displacement (the triple product is trilinear).  Each
+// term is as small as the change itself, so it survives FP64 rounding.
+__device__ __forceinline__ double volume_change(const double *__restrict__ X, int nv, int ia, int ib, int ic,
+                                                double ax, double ay, double az, double bx, double by,
+                                                double bz, double cxv, double cyv, double czv, const double *o)
+{
+    const double Ax = X[ia] - o[0], Ay = X[nv + ia] - o[1], Az = X[2 * nv + ia] - o[2];
+    const double Bx = X[ib] - o[0], By = X[nv + ib] - o[1], Bz = X[2 * nv + ib] - o[2];
+    const double Cx = X[ic] - o[0], Cy = X[nv + ic] - o[1], Cz = X[2 * nv + ic] - o[2];
+    const double dax = ax - X[ia], day = ay - X[nv + ia], daz = az - X[2 * nv + ia];
+    const double dbx = bx - X[ib], dby = by - X[nv + ib], dbz = bz - X[2 * nv + ib];
+    const double dcx = cxv - X[ic], dcy = cyv - X[nv + ic], dcz = czv - X[2 * nv + ic];
+    const double t = triple(dax, day, daz, Bx, By, Bz, Cx, Cy, Cz) + triple(Ax, Ay, Az, dbx, dby, dbz, Cx, Cy, Cz) +
+                     triple(Ax, Ay, Az, Bx, By, Bz, dcx, dcy, dcz) + triple(dax, day, daz, dbx, dby, dbz, Cx, Cy, Cz) +
+                     triple(dax, day, daz, Bx, By, Bz, dcx, dcy, dcz) + triple(Ax, Ay, Az, dbx, dby, dbz, dcx, dcy, dcz) +
+                     triple(dax, day, daz, dbx, dby, dbz, dcx, dcy, dcz);
+    return t / 6.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, const double *__restrict__ Xref,
+                                                const int *__restrict__ faces,
+                                                const double *__restrict__ fref, const int *__restrict__ inc_off,
+                                                const int *__restrict__ inc, T *__restrict__ phiSW,
+                                                T *__restrict__ gVout, Base *__restrict__ base,
+                                                T *__restrict__ wts, double *__restrict__ partials, int *err,
+                                                Grid g, MeshArgs m)
+{
+    __shared__ double red[2][256];
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nv = m.nv, nf = m.nf;
+    double dvol = 0.0, darea = 0.0;
+    if (v < nv) {
+        T fs[3] = {T(0), T(0), T(0)};
+        T gv[3] = {T(0), T(0), T(0)};
+        const T a1 = T(m.alpha[0]), a2 = T(m.alpha[1]), a3 = T(m.alpha[2]);
+        const int k1 = inc_off[v + 1];
+        for (int k = inc_off[v]; k < k1; ++k) {
+            const int code = inc[k];
+            const int j = code >> 2, corner = code & 3;
+            const int ia = faces[j], ib = faces[nf + j], ic = faces[2 * nf + j];
+            const double ax = q[ia], ay = q[nv + ia], az = q[2 * nv + ia];
+            const double bx = q[ib], by = q[nv + ib], bz = q[2 * nv + ib];
+            const double cxv = q[ic], cyv = q[nv + ic], czv = q[2 * nv + ic];
+            // elastic corner forces of the face: dW/de1 = 2(S11 e1 + S12 e2), dW/de2 = 2(S12 e1 + S22 e2)
+            const T e1x = T(bx - ax), e1y = T(by - ay), e1z = T(bz - az);
+            const T e2x = T(cxv - ax), e2y = T(cyv - ay), e2z = T(czv - az);
+            const T g11 = e1x * e1x + e1y * e1y + e1z * e1z;
+            const T g12 = e1x * e2x + e1y * e2y + e1z * e2z;
+            const T g22 = e2x * e2x + e2y * e2y + e2z * e2z;
+            const T detg = g11 * g22 - g12 * g12;
+            const T Gi11 = T(fref[j]), Gi12 = T(fref[nf + j]), Gi22 = T(fref[2 * nf + j]);
+            const T A0 = T(fref[3 * nf + j]), detG = T(fref[4 * nf + j]);
+            const T J = detg / detG;
+            const T lnJ = log(J);
+            const T w1 = T(0.5) * a3;
+            const T w2 = (T(0.5) * (a1 - a3) + T(0.25) * (a1 + a2) * lnJ) / J;
+            const T S11 = A0 * (w1 * Gi11 + w2 * g22 / detG);
+            const T S12 = A0 * (w1 * Gi12 - w2 * g12 / detG);
+            const T S22 = A0 * (w1 * Gi22 + w2 * g11 / detG);
+            const T Fb[3] = {T(-2) * (S11 * e1x + S12 * e2x), T(-2) * (S11 * e1y + S12 * e2y),
+                             T(-2) * (S11 * e1z + S12 * e2z)};
+            const T Fc[3] = {T(-2) * (S12 * e1x + S22 * e2x), T(-2) * (S12 * e1y + S22 * e2y),
+                             T(-2) * (S12 * e1z + S22 * e2z)};
+            // volume gradient of this face at this corner, relative to the origin
+            const double Ax = ax - m.origin[0], Ay = ay - m.origin[1], Az = az - m.origin[2];
+            const double Bx = bx - m.origin[0], By = by - m.origin[1], Bz = bz - m.origin[2];
+            const double Cx = cxv - m.origin[0], Cy = cyv - m.origin[1], Cz = czv - m.origin[2];
+            double dv[3];
+            if (corner == 0) {
+                fs[0] += -Fb[0] - Fc[0];
+                fs[1] += -Fb[1] - Fc[1];
+                fs[2] += -Fb[2] - Fc[2];
+                cross6(Bx, By, Bz, Cx, Cy, Cz, dv);
+                // owner of the face: accumulate V_j - V0_j and A_j in FP64
+                dvol += volume_change(Xref, nv, ia, ib, ic, ax, ay, az, bx, by, bz, cxv, cyv, czv, m.origin);
+                const double ex = bx - ax, ey = by - ay, ez = bz - az;
+                const double fx = cxv - ax, fy = cyv - ay, fz = czv - az;
+                const double nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
+                darea += 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
+            } else if (corner == 1) {
+                fs[0] += Fb[0];
+                fs[1] += Fb[1];
+                fs[2] += Fb[2];
+                cross6(Cx, Cy, Cz, Ax, Ay, Az, dv);
+            } else {
+                fs[0] += Fc[0];
+                fs[1] += Fc[1];
+                fs[2] += Fc[2];
+                cross6(Ax, Ay, Az, Bx, By, Bz, dv);
+            }
+            gv[0] += T(dv[0]);
+            gv[1] += T(dv[1]);
+            gv[2] += T(dv[2]);
+            if (g.walls) {
+                const double cz3 = (az + bz + czv) / 3.0;
+                const T fzw = lj<T>(T(m.eps_lo), T(m.xi), T(m.rc), T(cz3 - m.z_lo)) -
+                              lj<T>(T(m.eps_hi), T(m.xi), T(m.rc), T(m.z_hi - cz3));
+                fs[2] += fzw / T(3);
+            }
+        }
+        phiSW[v] = fs[0];
+        phiSW[nv + v] = fs[1];
+        phiSW[2 * nv + v] = fs[2];
+        gVout[v] = gv[0];
+        gVout[nv + v] = gv[1];
+        gVout[2 * nv + v] = gv[2];
+
+        // stencil corner and phi4 weights of this vertex for the spreading
+        const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+        Base bs;
+        if (fabs(qx) < 1e6 && fabs(qy) < 1e6 && fabs(qz) < 1e6) {
+            const int fx = (int)floor(qx) - 1, fy = (int)floor(qy) - 1, fz = (int)floor(qz) - 1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                wts[v * 12 + k] = phi4<T>(T((double)(fx + k) - qx));
+                wts[v * 12 + 4 + k] = phi4<T>(T((double)(fy + k) - qy));
+                wts[v * 12 + 8 + k] = phi4<T>(T((double)(fz + k) - qz));
+            }
+            bs.x = wrapi(fx, g.nx);
+            bs.y = wrapi(fy, g.ny);
+            bs.z = g.walls ? fz : wrapi(fz, g.nz);
+            bs.ok = 1;
+        } else {
+            bs.x = bs.y = bs.z = 0;
+            bs.ok = 0;
+            atomicOr(err, kErrNonFinite);
+        }
+        base[v] = bs;
+    }
+    // FP64 block partials of V - V0 and A (fixed tree order)
+    red[0][threadIdx.x] = dvol;
+    red[1][threadIdx.x] = darea;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = red[0][0];
+        partials[m.nparts + blockIdx.x] = red[1][0];
+    }
+}
+
+// k_V (V - V0)/V0 from the force-kernel partials, summed by one wavefront in a
+// fixed order (lane-strided, then a butterfly).
+__device__ __forceinline__ double volume_factor(const double *__restrict__ partials, const MeshArgs &m, int lane)
+{
+    double s = 0.0;
+    for (int k = lane; k < m.nparts; k += 64)
+        s += partials[k];
+    s = wave_sum<double>(s);
+    return m.kv_over_V0 * s;
+}
+
+// ---------------------------------------------------------------------------
+// Spreading, one wavefront per active tile (gather form, no FP atomics)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
+                                               const T *__restrict__ phiSW, const T *__restrict__ gV,
+                                               const double *__restrict__ partials, const uint32_t *__restrict__ dt,
+                                               uint32_t *cnt, const int *__restrict__ list,
+                                               const uint32_t *__restrict__ acnt, const int *__restrict__ alist,
+                                               T *__restrict__ F, uint32_t *__restrict__ stamp, Grid g, MeshArgs m)
+{
+    __shared__ int ids[kTileCap];
+    const int lane = threadIdx.x;
+    const uint32_t t = *dt;
+    const int buf = t & 1;
+    const uint32_t na = acnt[buf];
+    if (blockIdx.x >= na)
+        return;
+    const T kfac = T(volume_factor(partials, m, lane));
+    const int nv = m.nv;
+    for (uint32_t a = blockIdx.x; a < na; a += gridDim.x) {
+        const int tile = alist[buf * g.nt + a];
+        const uint32_t c = cnt[buf * g.nt + tile];
+        const int nent = c < (uint32_t)kTileCap ? (int)c : kTileCap;
+        int P = 1;
+        while (P < nent)
+            P <<= 1;
+        const int *src = list + ((long long)buf * g.nt + tile) * kTileCap;
+        for (int e = lane; e < P; e += 64)
+            ids[e] = e < nent ? src[e] : 0x7fffffff;
+        __syncthreads();
+        if (lane == 0)
+            cnt[buf * g.nt + tile] = 0u;
+        // bitonic sort: ascending vertex index makes the sums order-deterministic
+        for (int k = 2; k <= P; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = lane; i < P; i += 64) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const int va = ids[i], vb = ids[ixj];
+                        if ((va > vb) == ((i & k) == 0)) {
+                            ids[i] = vb;
+                            ids[ixj] = va;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        // this lane's node
+        const int tz = tile / (g.ntx * g.nty);
+        const int rem = tile - tz * g.ntx * g.nty;
+        const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
+        const int x = tx * 4 + (lane & 3), y = ty * 4 + ((lane >> 2) & 3), zf = tz * 4 + (lane >> 4);
+        const int z = zf + g.zoff;
+        T Fx = T(0), Fy = T(0), Fz = T(0);
+        for (int e = 0; e < nent; ++e) {
+            const int v = ids[e];
+            const Base bs = base[v];
+            int dx = x - bs.x;
+            if (dx < 0) dx += g.nx;
+            int dy = y - bs.y;
+            if (dy < 0) dy += g.ny;
+            int dz = z - bs.z;
+            if (!g.walls && dz < 0) dz += g.nz;
+            if ((unsigned)dx < 4u && (unsigned)dy < 4u && (unsigned)dz < 4u) {
+                const T w = wts[v * 12 + dx] * wts[v * 12 + 4 + dy] * wts[v * 12 + 8 + dz];
+                Fx += (phiSW[v] - kfac * gV[v]) * w;
+                Fy += (phiSW[nv + v] - kfac * gV[nv + v]) * w;
+                Fz += (phiSW[2 * nv + v] - kfac * gV[2 * nv + v]) * w;
+            }
+        }
+        if (x < g.nx && y < g.ny && zf < g.nzf) {
+            const long long me = nidx(g, x, y, zf);
+            F[me] = Fx;
+            F[g.n + me] = Fy;
+            F[2 * g.n + me] = Fz;
+        }
+        if (lane == 0)
+            stamp[tile] = t + 1u;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile lists: a vertex is listed on every tile holding a fluid node of its 4^3
+// stencil (x, y wrapped; z wrapped if periodic, clipped to the fluid if walls).
+// Called by all 64 lanes of the vertex's wavefront, lane = stencil offset.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void list_vertex(int v, double qx, double qy, double qz, int lane, const Grid &g,
+                                            uint32_t *cnt, int *list, uint32_t *acnt, int *alist, int buf, int *err)
+{
+    if (!(fabs(qx) < 1e6 && fabs(qy) < 1e6 && fabs(qz) < 1e6)) {
+        if (lane == 0)
+            atomicOr(err, kErrNonFinite);
+        return;
+    }
+    const int ix = lane & 3, iy = (lane >> 2) & 3, iz = lane >> 4;
+    const int bx = (int)floor(qx) - 1, by = (int)floor(qy) - 1, bz = (int)floor(qz) - 1;
+    const int x0 = wrapi(bx + ix, g.nx), xm = wrapi(bx + ix - 1, g.nx);
+    const int y0 = wrapi(by + iy, g.ny), ym = wrapi(by + iy - 1, g.ny);
+    const bool lx = ix == 0 || (x0 >> 2) != (xm >> 2);
+    const bool ly = iy == 0 || (y0 >> 2) != (ym >> 2);
+    int zf, zfm;
+    bool ok, okm;
+    if (g.walls) {
+        zf = bz + iz - g.zoff;
+        zfm = zf - 1;
+        ok = zf >= 0 && zf < g.nzf;
+        okm = iz > 0 && zfm >= 0 && zfm < g.nzf;
+    } else {
+        zf = wrapi(bz + iz, g.nz);
+        zfm = wrapi(bz + iz - 1, g.nz);
+        ok = true;
+        okm = iz > 0;
+    }
+    const bool lz = ok && (!okm || (zf >> 2) != (zfm >> 2));
+    if (lx && ly && lz) {
+        const int tile = tile_of(g, x0, y0, zf);
+        const uint32_t slot = atomicAdd(&cnt[buf * g.nt + tile], 1u);
+        if (slot == 0u) {
+            const uint32_t a = atomicAdd(&acnt[buf], 1u);
+            alist[buf * g.nt + a] = tile;
+        }
+        if (slot < (uint32_t)kTileCap)
+            list[((long long)buf * g.nt + tile) * kTileCap + slot] = v;
+        else
+            atomicOr(err, kErrOverflow);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *__restrict__ f,
+                                              const T *__restrict__ Fib, const T *__restrict__ Fext,
+                                              const uint32_t *__restrict__ stamp, uint32_t *dt, uint32_t *done,
+                                              uint32_t *cnt, int *list, uint32_t *acnt, int *alist, int *err,
+                                              LBArgs a, MeshArgs m)
+{
+    const Grid &g = a.g;
+    const int lane = threadIdx.x & 63;
+    const int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t t = __atomic_load_n(dt, __ATOMIC_RELAXED);
+    if (v < m.nv) {
+        const int nv = m.nv;
+        const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+        if (fabs(qx) < 1e6 && fabs(qy) < 1e6 && fabs(qz) < 1e6) {
+            const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
+            const int bx = (int)floor(qx) - 1, by = (int)floor(qy) - 1, bz = (int)floor(qz) - 1;
+            const T w = phi4<T>(T((double)(bx + kx) - qx)) * phi4<T>(T((double)(by + ky) - qy)) *
+                        phi4<T>(T((double)(bz + kz) - qz));
+            const int x = wrapi(bx + kx, g.nx), y = wrapi(by + ky, g.ny);
+            int z = bz + kz;
+            T ux, uy, uz;
+            if (g.walls && z < 1) {
+                ux = T(a.ulo[0]); uy = T(a.ulo[1]); uz = T(a.ulo[2]);
+            } else if (g.walls && z > g.nz - 2) {
+                ux = T(a.uhi[0]); uy = T(a.uhi[1]); uz = T(a.uhi[2]);
+            } else {
+                if (!g.walls)
+                    z = wrapi(z, g.nz);
+                const int zf = z - g.zoff;
+                T d[19];
+                // populations at t+1 (after this step's LB): swapped layout when t+1 is odd
+                if ((t + 1u) & 1u)
+                    load_pops<T, true>(f, g, x, y, zf, d);
+                else
+                    load_pops<T, false>(f, g, x, y, zf, d);
+                T drho = T(0), mx = T(0), my = T(0), mz = T(0);
+#pragma unroll
+                for (int i = 0; i < 19; ++i) {
+                    drho += d[i];
+                    if (cx(i) != 0) mx += T(cx(i)) * d[i];
+                    if (cy(i) != 0) my += T(cy(i)) * d[i];
+                    if (cz(i) != 0) mz += T(cz(i)) * d[i];
+                }
+                const long long me = nidx(g, x, y, zf);
+                T Fx = T(a.body[0]), Fy = T(a.body[1]), Fz = T(a.body[2]);
+                if (stamp[tile_of(g, x, y, zf)] == t + 1u) {
+                    Fx += Fib[me];
+                    Fy += Fib[g.n + me];
+                    Fz += Fib[2 * g.n + me];
+                }
+                if (a.has_fext) {
+                    Fx += Fext[me];
+                    Fy += Fext[g.n + me];
+                    Fz += Fext[2 * g.n + me];
+                }
+                const T rho = T(a.rho0) + drho;
+                ux = (mx + T(0.5) * Fx) / rho;
+                uy = (my + T(0.5) * Fy) / rho;
+                uz = (mz + T(0.5) * Fz) / rho;
+            }
+            const T sx = wave_sum<T>(ux * w), sy = wave_sum<T>(uy * w), sz = wave_sum<T>(uz * w);
+            const double nqx = qx + double(sx), nqy = qy + double(sy), nqz = qz + double(sz);
+            if (lane == 0) {
+                q[v] = nqx;
+                q[nv + v] = nqy;
+                q[2 * nv + v] = nqz;
+            }
+            list_vertex(v, nqx, nqy, nqz, lane, g, cnt, list, acnt, alist, (t + 1u) & 1u, err);
+        } else if (lane == 0) {
+            atomicOr(err, kErrNonFinite);
+        }
+    }
+    // the last block to finish advances the step counter
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(done, 1u);
+        if (prev == gridDim.x - 1u) {
+            *done = 0u;
+            __atomic_store_n(dt, t + 1u, __ATOMIC_RELAXED);
+            __threadfence();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bin(const double *__restrict__ q, const uint32_t *__restrict__ dt,
+                                             uint32_t *cnt, int *list, uint32_t *acnt, int *alist, int *err, Grid g,
+                                             MeshArgs m)
+{
+    const int lane = threadIdx.x & 63;
+    const int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (v >= m.nv)
+        return;
+    const uint32_t t = *dt;
+    list_vertex(v, q[v], q[m.nv + v], q[2 * m.nv + v], lane, g, cnt, list, acnt, alist, t & 1u, err);
+}
+
+// ---------------------------------------------------------------------------
+// Debug and query kernels (not on the per-step path)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_get_pops(const T *__restrict__ f, const uint32_t *__restrict__ dt,
+                                                  double *__restrict__ out, Grid g)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int zf = blockIdx.z;
+    if (x >= g.nx || y >= g.ny)
+        return;
+    T d[19];
+    if (*dt & 1u)
+        load_pops<T, true>(f, g, x, y, zf, d);
+    else
+        load_pops<T, false>(f, g, x, y, zf, d);
+    const long long me = nidx(g, x, y, zf);
+    for (int i = 0; i < 19; ++i)
+        out[i * g.n + me] = double(d[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_set_pops(T *__restrict__ f, const uint32_t *__restrict__ dt,
+                                                  const double *__restrict__ in, Grid g)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int zf = blockIdx.z;
+    if (x >= g.nx || y >= g.ny)
+        return;
+    const long long me = nidx(g, x, y, zf);
+    const long long n = g.n;
+    if (*dt & 1u) {
+        const Nbr b = neighbours(g, x, y, zf);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            long long src;
+            const bool ok = shifted(g, b, x, y, zf, i, -1, src);
+            if (ok)
+                f[opp(i) * n + src] = T(in[i * n + me]);
+            else
+                f[i * n + me] = T(in[i * n + me]);
+        }
+    } else {
+        for (int i = 0; i < 19; ++i)
+            f[i * n + me] = T(in[i * n + me]);
+    }
+}
+
+// force density of the last step (t-1) at node me, zero before the first step
+template <typename T>
+__device__ __forceinline__ void last_force(const T *Fib, const T *Fext, const uint32_t *stamp, uint32_t t,
+                                           const LBArgs &a, int x, int y, int zf, long long me, double *F)
+{
+    F[0] = F[1] = F[2] = 0.0;
+    if (t == 0u)
+        return;
+    F[0] = a.body[0];
+    F[1] = a.body[1];
+    F[2] = a.body[2];
+    if (stamp != nullptr && stamp[tile_of(a.g, x, y, zf)] == t) {
+        F[0] += double(Fib[me]);
+        F[1] += double(Fib[a.g.n + me]);
+        F[2] += double(Fib[2 * a.g.n + me]);
+    }
+    if (a.has_fext) {
+        F[0] += double(Fext[me]);
+        F[1] += double(Fext[a.g.n + me]);
+        F[2] += double(Fext[2 * a.g.n + me]);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_get_fields(const T *__restrict__ f, const T *__restrict__ Fib,
+                                                    const T *__restrict__ Fext, const uint32_t *__restrict__ stamp,
+                                                    const uint32_t *__restrict__ dt, double *__restrict__ rho_out,
+                                                    double *__restrict__ u_out, double *__restrict__ F_out, LBArgs a)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int zf = blockIdx.z;
+    const Grid &g = a.g;
+    if (x >= g.nx || y >= g.ny)
+        return;
+    const uint32_t t = *dt;
+    const long long me = nidx(g, x, y, zf);
+    double F[3];
+    last_force<T>(Fib, Fext, stamp, t, a, x, y, zf, me, F);
+    if (F_out != nullptr) {
+        F_out[me] = F[0];
+        F_out[g.n + me] = F[1];
+        F_out[2 * g.n + me] = F[2];
+    }
+    if (rho_out == nullptr)
+        return;
+    T d[19];
+    if (t & 1u)
+        load_pops<T, true>(f, g, x, y, zf, d);
+    else
+        load_pops<T, false>(f, g, x, y, zf, d);
+    double drho = 0.0, m[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 19; ++i) {
+        const double di = double(d[i]);
+        drho += di;
+        m[0] += cx(i) * di;
+        m[1] += cy(i) * di;
+        m[2] += cz(i) * di;
+    }
+    const double rho = a.rho0 + drho;
+    rho_out[me] = rho;
+    for (int k = 0; k < 3; ++k)
+        u_out[k * g.n + me] = (m[k] + 0.5 * F[k]) / rho;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nodal_forces(const T *__restrict__ phiSW, const T *__restrict__ gV,
+                                                      const double *__restrict__ partials, double *__restrict__ out,
+                                                      MeshArgs m)
+{
+    __shared__ double kf;
+    if (threadIdx.x < 64) {
+        const double s = volume_factor(partials, m, threadIdx.x);
+        if (threadIdx.x == 0)
+            kf = s;
+    }
+    __syncthreads();
+    const T kfac = T(kf);
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= m.nv)
+        return;
+    for (int c = 0; c < 3; ++c)
+        out[3 * v + c] = double(phiSW[c * m.nv + v] - kfac * gV[c * m.nv + v]);
+}
+
+// FP64 block reduction of K values per thread, fixed tree order, 1024 threads
+template <int K>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[K], double *out)
+{
+    __shared__ double sh[1024];
+    for (int k = 0; k < K; ++k) {
+        sh[threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int s = 512; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s)
+                sh[threadIdx.x] += sh[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            out[k] = sh[0];
+        __syncthreads();
+    }
+}
+
+// V, A, volume first moments, volume second moments (about the origin)
+__global__ __launch_bounds__(1024) void k_mesh_moments(const double *__restrict__ q, const int *__restrict__ faces,
+                                                       double *__restrict__ out, MeshArgs m)
+{
+    double acc[11];
+    for (int k = 0; k < 11; ++k)
+        acc[k] = 0.0;
+    const int nv = m.nv, nf = m.nf;
+    for (int j = threadIdx.x; j < nf; j += blockDim.x) {
+        const int ia = faces[j], ib = faces[nf + j], ic = faces[2 * nf + j];
+        double A[3], B[3], C[3], S[3];
+        for (int k = 0; k < 3; ++k) {
+            A[k] = q[k * nv + ia] - m.origin[k];
+            B[k] = q[k * nv + ib] - m.origin[k];
+            C[k] = q[k * nv + ic] - m.origin[k];
+            S[k] = A[k] + B[k] + C[k];
+        }
+        const double vt = (A[0] * (B[1] * C[2] - B[2] * C[1]) + A[1] * (B[2] * C[0] - B[0] * C[2]) +
+                           A[2] * (B[0] * C[1] - B[1] * C[0])) / 6.0;
+        const double e[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+        const double f2[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+        const double n[3] = {e[1] * f2[2] - e[2] * f2[1], e[2] * f2[0] - e[0] * f2[2], e[0] * f2[1] - e[1] * f2[0]};
+        acc[0] += vt;
+        acc[1] += 0.5 * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int k = 0; k < 3; ++k)
+            acc[2 + k] += vt * S[k] / 4.0;
+        const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+        for (int p = 0; p < 6; ++p) {
+            const int r = ii[p], c = jj[p];
+            acc[5 + p] += vt / 20.0 * (A[r] * A[c] + B[r] * B[c] + C[r] * C[c] + S[r] * S[c]);
+        }
+    }
+    block_reduce_store<11>(acc, out);
+}
+
+// normal equations of the algebraic sphere fit |p|^2 = 2 c.p + k over vertices
+// at least excl away from the chosen wall plane; p shifted by `shift`
+__global__ __launch_bounds__(1024) void k_sphere_moments(const double *__restrict__ q, double *__restrict__ out,
+                                                         MeshArgs m, int wall_hi, double z_wall, double excl,
+                                                         double sx, double sy, double sz)
+{
+    double acc[15];
+    for (int k = 0; k < 15; ++k)
+        acc[k] = 0.0;
+    const int nv = m.nv;
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        const double zq = q[2 * nv + v];
+        const double dist = wall_hi ? z_wall - zq : zq - z_wall;
+        if (!(dist >= excl))
+            continue;
+        const double p[3] = {q[v] - sx, q[nv + v] - sy, zq - sz};
+        const double r[4] = {2.0 * p[0], 2.0 * p[1], 2.0 * p[2], 1.0};
+        const double b = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+        int k = 0;
+        for (int i = 0; i < 4; ++i)
+            for (int j = i; j < 4; ++j)
+                acc[k++] += r[i] * r[j];
+        for (int i = 0; i < 4; ++i)
+            acc[10 + i] += r[i] * b;
+        acc[14] += 1.0;
+    }
+    block_reduce_store<15>(acc, out);
+}
+
+dim3 lb_block(const Grid &g)
+{
+    const int bx = g.nx >= 64 ? 64 : (g.nx >= 32 ? 32 : 16);
+    return dim3(bx, 256 / bx, 1);
+}
+dim3 lb_grid(const Grid &g)
+{
+    const dim3 b = lb_block(g);
+    return dim3((g.nx + b.x - 1) / b.x, (g.ny + b.y - 1) / b.y, g.nzf);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hipStream_t s)
+{
+    if (prec == 0)
+        k_init<double><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((double *)d.f, a, couette);
+    else
+        k_init<float><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((float *)d.f, a, couette);
+    return hipGetLastError();
+}
+
+hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, hipStream_t s)
+{
+    const uint32_t *stamp = d.q ? d.stamp : nullptr;
+    if (prec == 0)
+        k_lb<double><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((double *)d.f, (const double *)d.F,
+                                                              (const double *)d.Fext, stamp, d.t, d.acnt, d.err, a);
+    else
+        k_lb<float><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((float *)d.f, (const float *)d.F,
+                                                             (const float *)d.Fext, stamp, d.t, d.acnt, d.err, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tick(const Dev &d, hipStream_t s)
+{
+    k_tick<<<1, 64, 0, s>>>(d.t);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s)
+{
+    const int blocks = m.nparts;
+    if (prec == 0)
+        k_forces<double><<<blocks, 256, 0, s>>>(d.q, d.Xref, d.faces, d.fref, d.inc_off, d.inc, (double *)d.phiSW,
+                                                (double *)d.gV, d.base, (double *)d.wts, d.partials, d.err, g, m);
+    else
+        k_forces<float><<<blocks, 256, 0, s>>>(d.q, d.Xref, d.faces, d.fref, d.inc_off, d.inc, (float *)d.phiSW,
+                                               (float *)d.gV, d.base, (float *)d.wts, d.partials, d.err, g, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_spread(int prec, const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s)
+{
+    const int blocks = g.nt < 2048 ? g.nt : 2048;
+    if (prec == 0)
+        k_spread<double><<<blocks, 64, 0, s>>>(d.base, (const double *)d.wts, (const double *)d.phiSW,
+                                               (const double *)d.gV, d.partials, d.t, d.cnt, d.list, d.acnt,
+                                               d.alist, (double *)d.F, d.stamp, g, m);
+    else
+        k_spread<float><<<blocks, 64, 0, s>>>(d.base, (const float *)d.wts, (const float *)d.phiSW,
+                                              (const float *)d.gV, d.partials, d.t, d.cnt, d.list, d.acnt,
+                                              d.alist, (float *)d.F, d.stamp, g, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s)
+{
+    const int blocks = (m.nv + 3) / 4;
+    if (prec == 0)
+        k_move<double><<<blocks, 256, 0, s>>>(d.q, (const double *)d.f, (const double *)d.F, (const double *)d.Fext,
+                                              d.stamp, d.t, d.done, d.cnt, d.list, d.acnt, d.alist, d.err, a, m);
+    else
+        k_move<float><<<blocks, 256, 0, s>>>(d.q, (const float *)d.f, (const float *)d.F, (const float *)d.Fext,
+                                             d.stamp, d.t, d.done, d.cnt, d.list, d.acnt, d.alist, d.err, a, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin(const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s)
+{
+    k_bin<<<(m.nv + 3) / 4, 256, 0, s>>>(d.q, d.t, d.cnt, d.list, d.acnt, d.alist, d.err, g, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, double *out, hipStream_t s)
+{
+    if (prec == 0)
+        k_get_pops<double><<<lb_grid(g), lb_block(g), 0, s>>>((const double *)d.f, d.t, out, g);
+    else
+        k_get_pops<float><<<lb_grid(g), lb_block(g), 0, s>>>((const float *)d.f, d.t, out, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, const double *in, hipStream_t s)
+{
+    if (prec == 0)
+        k_set_pops<double><<<lb_grid(g), lb_block(g), 0, s>>>((double *)d.f, d.t, in, g);
+    else
+        k_set_pops<float><<<lb_grid(g), lb_block(g), 0, s>>>((float *)d.f, d.t, in, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_fields(int prec, const Dev &d, const LBArgs &a, double *rho, double *u, hipStream_t s)
+{
+    const uint32_t *stamp = d.q ? d.stamp : nullptr;
+    if (prec == 0)
+        k_get_fields<double><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const double *)d.f, (const double *)d.F,
+                                                                    (const double *)d.Fext, stamp, d.t, rho, u,
+                                                                    nullptr, a);
+    else
+        k_get_fields<float><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const float *)d.f, (const float *)d.F,
+                                                                   (const float *)d.Fext, stamp, d.t, rho, u,
+                                                                   nullptr, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_force(int prec, const Dev &d, const LBArgs &a, double *F, hipStream_t s)
+{
+    const uint32_t *stamp = d.q ? d.stamp : nullptr;
+    if (prec == 0)
+        k_get_fields<double><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const double *)d.f, (const double *)d.F,
+                                                                    (const double *)d.Fext, stamp, d.t, nullptr,
+                                                                    nullptr, F, a);
+    else
+        k_get_fields<float><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const float *)d.f, (const float *)d.F,
+                                                                   (const float *)d.Fext, stamp, d.t, nullptr,
+                                                                   nullptr, F, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nodal_forces(int prec, const Dev &d, const MeshArgs &m, double *phi, hipStream_t s)
+{
+    const int blocks = (m.nv + 255) / 256;
+    if (prec == 0)
+        k_nodal_forces<double><<<blocks, 256, 0, s>>>((const double *)d.phiSW, (const double *)d.gV, d.partials,
+                                                      phi, m);
+    else
+        k_nodal_forces<float><<<blocks, 256, 0, s>>>((const float *)d.phiSW, (const float *)d.gV, d.partials,
+                                                     phi, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_mesh_moments(const Dev &d, const MeshArgs &m, double *out, hipStream_t s)
+{
+    k_mesh_moments<<<1, 1024, 0, s>>>(d.q, d.faces, out, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_sphere_moments(const Dev &d, const MeshArgs &m, int wall_hi, double z_wall, double excl,
+                                 const double *shift, double *out, hipStream_t s)
+{
+    k_sphere_moments<<<1, 1024, 0, s>>>(d.q, out, m, wall_hi, z_wall, excl, shift[0], shift[1], shift[2]);
+    return hipGetLastError();
+}
+
+}  // namespace iblb

@@ -1,0 +1,334 @@
+"""ctypes binding of libiblb (include/iblb.h): argument marshalling only.
+
+Every step of the IB-LB path runs in the library's HIP kernels; this module
+only converts numpy arrays and the workload descriptions of ``inputs`` into
+the C structs, allocates the device workspace and stream through PyTorch when
+it is available, and turns status codes into exceptions.  If the compiled
+library is missing the import of :class:`Simulation` fails loudly: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiblb.so")
+
+IBLB_OK, IBLB_E_INVAL, IBLB_E_DEVICE, IBLB_E_MESH, IBLB_E_UNSTABLE, IBLB_E_STATE = 0, -1, -2, -3, -4, -5
+FP64, FP32_DEV = 0, 1
+WALLS_Z, PERIODIC_ALL = 0, 1
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_vp = C.c_void_p
+
+
+class DomainDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("wall_mode", C.c_int32),
+                ("precision", C.c_int32), ("init_couette", C.c_int32), ("tau", C.c_double),
+                ("rho0", C.c_double), ("u_wall_lo", C.c_double * 3), ("u_wall_hi", C.c_double * 3),
+                ("body_force", C.c_double * 3)]
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_faces", C.c_int32), ("vertices", _dp),
+                ("ref_vertices", _dp), ("faces", _ip), ("alpha", C.c_double * 3), ("k_v", C.c_double),
+                ("eps_wall_lo", C.c_double), ("eps_wall_hi", C.c_double), ("xi_wall", C.c_double),
+                ("r_cut_wall", C.c_double)]
+
+
+class IBLBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"iblb error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def _hip_runtimes() -> set:
+    """Paths of HIP runtime libraries mapped into this process."""
+    found = set()
+    try:
+        with open("/proc/self/maps") as fh:
+            for line in fh:
+                path = line.split()[-1] if line.strip() else ""
+                if "libamdhip64.so" in path:
+                    found.add(path)
+    except OSError:
+        pass
+    return found
+
+
+def lib():
+    """Load libiblb.so (raises if it has not been built).
+
+    PyTorch ships its own HIP runtime and its libraries name it in a way that
+    does not match an already loaded system runtime, so loading libiblb first
+    would put two HIP runtimes in the process.  PyTorch is therefore imported
+    first (when installed) and libiblb binds to the runtime it brought; the
+    load is refused if two runtimes are mapped anyway.
+    """
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_18919_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        runtimes = _hip_runtimes()
+        if len(runtimes) > 1:
+            raise RuntimeError(f"two HIP runtimes are loaded in this process: {sorted(runtimes)}; import torch "
+                               f"before anything that loads /opt/rocm's libamdhip64")
+        pp = C.POINTER(_vp)
+        sig = {
+            "iblb_workspace_bytes": [C.POINTER(DomainDesc), C.POINTER(MeshDesc), C.POINTER(C.c_size_t)],
+            "iblb_create": [C.POINTER(DomainDesc), _vp, C.c_size_t, _vp, pp],
+            "iblb_add_mesh": [_vp, C.POINTER(MeshDesc), _ip],
+            "iblb_step": [_vp, C.c_int32],
+            "iblb_sync": [_vp],
+            "iblb_step_count": [_vp, C.POINTER(C.c_int64)],
+            "iblb_get_vertices": [_vp, C.c_int32, _dp],
+            "iblb_vertices_device": [_vp, C.c_int32, C.POINTER(_dp)],
+            "iblb_volume": [_vp, C.c_int32, _dp, _dp],
+            "iblb_shape": [_vp, C.c_int32, _dp, _dp, _dp],
+            "iblb_contact_angle": [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp, _dp],
+            "iblb_get_fields": [_vp, _dp, _dp],
+            "iblb_debug_set_force": [_vp, _dp],
+            "iblb_debug_get_force": [_vp, _dp],
+            "iblb_debug_get_populations": [_vp, _dp],
+            "iblb_debug_set_populations": [_vp, _dp],
+            "iblb_debug_get_nodal_forces": [_vp, C.c_int32, _dp],
+            "iblb_save_state": [_vp, _vp, C.POINTER(C.c_size_t)],
+            "iblb_load_state": [_vp, _vp, C.c_size_t],
+            "iblb_set_graph": [_vp, C.c_int32],
+            "iblb_set_timing": [_vp, C.c_int32],
+            "iblb_kernel_time": [_vp, C.c_char_p, _dp, C.POINTER(C.c_int64)],
+            "iblb_reset_timing": [_vp],
+            "iblb_destroy": [_vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.iblb_last_error.argtypes = [_vp]
+        L.iblb_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def domain_desc(dom, precision: int) -> DomainDesc:
+    d = DomainDesc()
+    d.nx, d.ny, d.nz = int(dom.nx), int(dom.ny), int(dom.nz)
+    d.wall_mode = int(dom.wall_mode)
+    d.precision = int(precision)
+    d.init_couette = int(dom.init_couette)
+    d.tau, d.rho0 = float(dom.tau), float(dom.rho0)
+    for k in range(3):
+        d.u_wall_lo[k] = float(dom.u_wall_lo[k])
+        d.u_wall_hi[k] = float(dom.u_wall_hi[k])
+        d.body_force[k] = float(dom.body_force[k])
+    return d
+
+
+def mesh_desc(mesh, keep: list) -> MeshDesc:
+    """MeshDesc over contiguous copies; `keep` holds them alive for the call."""
+    q = _f64(mesh.vertices)
+    X = _f64(mesh.ref_vertices)
+    F = np.ascontiguousarray(mesh.faces, dtype=np.int32)
+    keep += [q, X, F]
+    m = MeshDesc()
+    m.n_vertices, m.n_faces = q.shape[0], F.shape[0]
+    m.vertices, m.ref_vertices = _p(q), _p(X)
+    m.faces = F.ctypes.data_as(_ip)
+    for k in range(3):
+        m.alpha[k] = float(mesh.alpha[k])
+    m.k_v = float(mesh.k_v)
+    m.eps_wall_lo, m.eps_wall_hi = float(mesh.eps_wall_lo), float(mesh.eps_wall_hi)
+    m.xi_wall, m.r_cut_wall = float(mesh.xi_wall), float(mesh.r_cut_wall)
+    return m
+
+
+def workspace_bytes(dom, precision: int, mesh=None) -> int:
+    keep: list = []
+    n = C.c_size_t()
+    md = C.byref(mesh_desc(mesh, keep)) if mesh is not None else None
+    rc = lib().iblb_workspace_bytes(C.byref(domain_desc(dom, precision)), md, C.byref(n))
+    if rc != IBLB_OK:
+        raise IBLBError(rc, "iblb_workspace_bytes rejected the domain")
+    return n.value
+
+
+class Simulation:
+    """One IB-LB context on the current GPU.
+
+    use_torch: take the device workspace (a uint8 tensor) and the stream (a
+    torch.cuda.Stream at default priority) from PyTorch; otherwise the library
+    allocates both itself.
+    """
+
+    def __init__(self, domain, mesh=None, precision: int = FP64, graph: bool = True, use_torch: bool = True):
+        L = lib()
+        self.dom = domain
+        self.precision = precision
+        self.shape = (domain.nz_fluid, domain.ny, domain.nx)
+        self.n = int(np.prod(self.shape))
+        self._ws = None
+        self._stream = None
+        ws_ptr, ws_bytes, stream = None, 0, None
+        if use_torch:
+            import torch
+            ws_bytes = workspace_bytes(domain, precision, mesh)
+            self._ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+            self._stream = torch.cuda.Stream()
+            torch.cuda.synchronize()
+            ws_ptr, stream = self._ws.data_ptr(), self._stream.cuda_stream
+        h = _vp()
+        rc = L.iblb_create(C.byref(domain_desc(domain, precision)), ws_ptr, ws_bytes, stream, C.byref(h))
+        if rc != IBLB_OK:
+            raise IBLBError(rc, "iblb_create failed")
+        self.h = h
+        self.nv = 0
+        if mesh is not None:
+            self.add_mesh(mesh)
+        self.set_graph(graph)
+
+    # -- plumbing
+    def _check(self, rc: int):
+        if rc != IBLB_OK:
+            msg = lib().iblb_last_error(self.h)
+            raise IBLBError(rc, msg.decode() if msg else "")
+
+    def add_mesh(self, mesh):
+        keep: list = []
+        mid = C.c_int32()
+        self._check(lib().iblb_add_mesh(self.h, C.byref(mesh_desc(mesh, keep)), C.byref(mid)))
+        self.nv = mesh.n_vertices
+        self.mesh = mesh
+        return mid.value
+
+    def set_graph(self, on: bool):
+        self._check(lib().iblb_set_graph(self.h, int(bool(on))))
+
+    def set_timing(self, on: bool):
+        self._check(lib().iblb_set_timing(self.h, int(bool(on))))
+
+    def reset_timing(self):
+        self._check(lib().iblb_reset_timing(self.h))
+
+    def kernel_time(self, name: str):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(lib().iblb_kernel_time(self.h, name.encode(), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    # -- stepping
+    def step(self, n: int = 1):
+        self._check(lib().iblb_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(lib().iblb_sync(self.h))
+
+    @property
+    def t(self) -> int:
+        v = C.c_int64()
+        self._check(lib().iblb_step_count(self.h, C.byref(v)))
+        return v.value
+
+    # -- state access
+    def vertices(self) -> np.ndarray:
+        out = np.zeros((self.nv, 3))
+        self._check(lib().iblb_get_vertices(self.h, 0, _p(out)))
+        return out
+
+    def vertices_device_ptr(self) -> int:
+        p = _dp()
+        self._check(lib().iblb_vertices_device(self.h, 0, C.byref(p)))
+        return C.cast(p, C.c_void_p).value
+
+    def populations(self) -> np.ndarray:
+        out = np.zeros((19,) + self.shape)
+        self._check(lib().iblb_debug_get_populations(self.h, _p(out)))
+        return out
+
+    def set_populations(self, d: np.ndarray):
+        self._check(lib().iblb_debug_set_populations(self.h, _p(_f64(d).reshape(-1))))
+
+    def fields(self):
+        rho = np.zeros(self.shape)
+        u = np.zeros((3,) + self.shape)
+        self._check(lib().iblb_get_fields(self.h, _p(rho), _p(u)))
+        return rho, u
+
+    def force(self) -> np.ndarray:
+        out = np.zeros((3,) + self.shape)
+        self._check(lib().iblb_debug_get_force(self.h, _p(out)))
+        return out
+
+    def set_force(self, F: np.ndarray):
+        self._check(lib().iblb_debug_set_force(self.h, _p(_f64(F).reshape(-1))))
+
+    def nodal_forces(self) -> np.ndarray:
+        out = np.zeros((self.nv, 3))
+        self._check(lib().iblb_debug_get_nodal_forces(self.h, 0, _p(out)))
+        return out
+
+    # -- queries
+    def volume(self):
+        V, A = C.c_double(), C.c_double()
+        self._check(lib().iblb_volume(self.h, 0, C.byref(V), C.byref(A)))
+        return V.value, A.value
+
+    def shape_dtheta(self):
+        D, th = C.c_double(), C.c_double()
+        cen = np.zeros(3)
+        self._check(lib().iblb_shape(self.h, 0, C.byref(D), C.byref(th), _p(cen)))
+        return D.value, th.value, cen
+
+    def contact_angle(self, wall: int = 0):
+        th, r, h = C.c_double(), C.c_double(), C.c_double()
+        self._check(lib().iblb_contact_angle(self.h, 0, wall, 0, C.byref(th), C.byref(r), C.byref(h)))
+        return th.value, r.value, h.value
+
+    # -- checkpoints
+    def save_state(self) -> bytes:
+        n = C.c_size_t()
+        self._check(lib().iblb_save_state(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(lib().iblb_save_state(self.h, C.cast(buf, _vp), C.byref(n)))
+        return buf.raw
+
+    def load_state(self, state: bytes):
+        buf = C.create_string_buffer(state, len(state))
+        self._check(lib().iblb_load_state(self.h, C.cast(buf, _vp), len(state)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().iblb_destroy(self.h)
+            self.h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

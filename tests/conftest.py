@@ -18,3 +18,12 @@ def O():
     from oracle import oracle
     oracle.lib()
     return oracle
+
+
+def pytest_runtest_logreport(report):
+    """Print a failure as soon as it happens, so that a later crash of the
+    process cannot hide it."""
+    if report.failed:
+        import sys as _sys
+        _sys.stderr.write(f"\n[failed] {report.nodeid} ({report.when})\n{report.longreprtext}\n")
+        _sys.stderr.flush()

@@ -1,0 +1,116 @@
+"""Execution modes, determinism, checkpoints, queries and error paths of the
+C ABI on the GPU."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2305_18919_amd import iblb
+from paper_2305_18919_amd.inputs import Domain, c1_droplet, c3_wetting, sphere_mesh
+from tests.gpu_util import announce, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(w, prec, n, graph=True, timing=False):
+    with iblb.Simulation(w.domain, w.mesh, precision=prec, graph=graph) as g:
+        g.set_timing(timing)
+        g.step(n)
+        return g.vertices(), g.populations()
+
+
+@pytest.mark.parametrize("prec", [iblb.FP64, iblb.FP32_DEV])
+def test_graph_eager_timed_bitwise_equal_and_deterministic(prec):
+    w = c1_droplet(eps_over_abar=1.0)
+    announce(f"modes prec={prec}")
+    a = _run(w, prec, 37, graph=True)
+    b = _run(w, prec, 37, graph=False)
+    c = _run(w, prec, 37, graph=False, timing=True)
+    d = _run(w, prec, 37, graph=True)
+    for x in (b, c, d):
+        assert np.array_equal(a[0], x[0]) and np.array_equal(a[1], x[1])
+
+
+def test_checkpoint_resume_bitwise():
+    w = c1_droplet(eps_over_abar=1.0)
+    with iblb.Simulation(w.domain, w.mesh, precision=iblb.FP64) as g:
+        g.step(25)
+        st = g.save_state()
+        g.step(26)
+        q1, f1 = g.vertices(), g.populations()
+    with iblb.Simulation(w.domain, w.mesh, precision=iblb.FP64) as h:
+        h.load_state(st)
+        assert h.t == 25
+        h.step(26)
+        assert np.array_equal(h.vertices(), q1) and np.array_equal(h.populations(), f1)
+
+
+def test_queries_match_oracle():
+    w = c3_wetting(1.0)
+    with iblb.Simulation(w.domain, w.mesh, precision=iblb.FP32_DEV) as g:
+        g.step(3)
+        q = g.vertices()
+        V, A = g.volume()
+        D, th, cen = g.shape_dtheta()
+        ang, r, h = g.contact_angle(0)
+    Vo, Ao, xco = O.volume_area_centroid(q, w.mesh.faces)
+    Do, tho = O.shape_dtheta(q, w.mesh.faces)
+    ango, ro, ho, _, _ = O.contact_angle_sphere(q, 0.5, 2.0)
+    assert V == pytest.approx(Vo, rel=1e-12) and A == pytest.approx(Ao, rel=1e-12)
+    assert np.allclose(cen, xco, rtol=0, atol=1e-10)
+    assert abs(D - Do) < 1e-10 and abs(th - tho) < 1e-8
+    assert abs(ang - ango) < 1e-3 and r == pytest.approx(ro, rel=1e-8) and h == pytest.approx(ho, rel=1e-8)
+
+
+def test_mesh_validation_errors():
+    d = Domain(16, 16, 16)
+    m = sphere_mesh(1, 3.0, (8.0, 8.0, 8.0), (1e-3, 0, 0))
+    with iblb.Simulation(d, precision=iblb.FP64) as g:
+        open_mesh = sphere_mesh(1, 3.0, (8.0, 8.0, 8.0), (1e-3, 0, 0))
+        open_mesh.faces = open_mesh.faces[1:]
+        with pytest.raises(iblb.IBLBError) as e:
+            g.add_mesh(open_mesh)
+        assert e.value.code == iblb.IBLB_E_MESH
+        flipped = sphere_mesh(1, 3.0, (8.0, 8.0, 8.0), (1e-3, 0, 0))
+        flipped.faces = flipped.faces[:, [0, 2, 1]].copy()
+        with pytest.raises(iblb.IBLBError) as e:
+            g.add_mesh(flipped)
+        assert e.value.code == iblb.IBLB_E_MESH
+        bad = sphere_mesh(1, 3.0, (8.0, 8.0, 8.0), (1e-3, 0, 0))
+        bad.vertices = bad.vertices.copy()
+        bad.vertices[3, 1] = np.nan
+        with pytest.raises(iblb.IBLBError) as e:
+            g.add_mesh(bad)
+        assert e.value.code == iblb.IBLB_E_INVAL
+        g.add_mesh(m)
+        with pytest.raises(iblb.IBLBError) as e:
+            g.add_mesh(m)
+        assert e.value.code == iblb.IBLB_E_STATE
+        with pytest.raises(iblb.IBLBError) as e:
+            g.set_force(np.zeros((3, 14, 16, 16)))
+        assert e.value.code == iblb.IBLB_E_STATE
+        with pytest.raises(iblb.IBLBError):
+            g.contact_angle(wall=2)
+
+
+def test_unstable_state_reported():
+    """A non-finite population planted from the host is reported, not hidden."""
+    d = Domain(16, 16, 16)
+    with iblb.Simulation(d, precision=iblb.FP64) as g:
+        f = np.zeros((19, 14, 16, 16))
+        f[0, 3, 4, 5] = np.nan
+        g.set_populations(f)
+        g.step(2)
+        with pytest.raises(iblb.IBLBError) as e:
+            g.sync()
+        assert e.value.code == iblb.IBLB_E_UNSTABLE
+
+
+def test_load_state_rejects_mismatch():
+    w = c1_droplet()
+    with iblb.Simulation(w.domain, w.mesh, precision=iblb.FP64) as g:
+        st = g.save_state()
+    with iblb.Simulation(w.domain, w.mesh, precision=iblb.FP32_DEV) as h:
+        with pytest.raises(iblb.IBLBError):
+            h.load_state(st)
+        with pytest.raises(iblb.IBLBError):
+            h.load_state(b"garbage" * 10)
