@@ -106,7 +106,7 @@ def main():
     sim.step(args.timed_steps)
     sim.sync()
     kernels = {}
-    for name in ("forces", "spread", "lb", "move", "tick"):
+    for name in ("forces", "spread", "lb", "move"):
         ms, n = sim.kernel_time(name)
         if n:
             kernels[name] = {"avg_us": round(ms * 1e3 / n, 3), "launches": n}
@@ -125,7 +125,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == 1 else "f64", "data": "synthetic",
         "config": {"workload": w.name, "grid": [dom.nx, dom.ny, dom.nz], "fluid_nodes": dom.n_fluid,
                    "vertices": mesh.n_vertices, "faces": mesh.n_faces, "tau": dom.tau,
-                   "alpha": list(mesh.alpha), "positions": "f64", "launch": "hipGraph, 1 step per replay"},
+                   "alpha": list(mesh.alpha), "positions": "f64", "launch": "hipGraph, 16 steps per replay"},
         "roofline": roof,
         "kernels": kernels,
     }

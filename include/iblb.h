@@ -117,7 +117,9 @@ int iblb_create(const iblb_domain_desc *dom, void *dev_workspace, size_t workspa
 int iblb_add_mesh(iblb_ctx *ctx, const iblb_mesh_desc *mesh, int32_t *mesh_id);
 
 /* Enqueue n_steps full IB-LB steps on the context stream; returns without
- * waiting.  In graph mode (default) one captured step is replayed. */
+ * waiting.  In graph mode (default) a captured hipGraph of 16 steps that
+ * starts at an even time is replayed; the remaining steps are launched
+ * directly. */
 int iblb_step(iblb_ctx *ctx, int32_t n_steps);
 
 /* Wait for the context stream and report device-side errors. */
@@ -181,7 +183,7 @@ int iblb_load_state(iblb_ctx *ctx, const void *host_buf, size_t bytes);
 int iblb_set_graph(iblb_ctx *ctx, int32_t graph);
 int iblb_set_timing(iblb_ctx *ctx, int32_t timing);
 /* Per-kernel accumulated event time.  names: "forces", "spread", "lb",
- * "move", "tick".  Returns total milliseconds and launch count; resets nothing. */
+ * "move".  Returns total milliseconds and launch count; resets nothing. */
 int iblb_kernel_time(iblb_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 int iblb_reset_timing(iblb_ctx *ctx);
 

@@ -22,16 +22,17 @@ using namespace iblb;
 namespace {
 
 constexpr char kMagic[8] = {'I', 'B', 'L', 'B', 'S', 'T', '0', '1'};
-constexpr int kNumKernels = 5;
-const char *const kKernelNames[kNumKernels] = {"forces", "spread", "lb", "move", "tick"};
-enum { K_FORCES = 0, K_SPREAD = 1, K_LB = 2, K_MOVE = 3, K_TICK = 4 };
+constexpr int kNumKernels = 4;
+constexpr int kGraphSteps = 16;  // steps per captured graph (even)
+const char *const kKernelNames[kNumKernels] = {"forces", "spread", "lb", "move"};
+enum { K_FORCES = 0, K_SPREAD = 1, K_LB = 2, K_MOVE = 3 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
     // byte offsets into the workspace; domain part then mesh part
-    size_t f, F, stamp, t, done, err, scratch, dom_end;
-    size_t q, Xref, faces, fref, inc_off, inc, phiSW, gV, base, wts, partials, cnt, list, acnt, alist, mesh_end;
+    size_t f, F, stamp, ctr, err, scratch, dom_end;
+    size_t q, Xref, faces, fref, inc_off, inc4, phiSW, gV, base, wts, partials, cnt, list, acnt, alist, mesh_end;
 };
 
 Grid make_grid(const iblb_domain_desc &d)
@@ -63,18 +64,17 @@ Layout make_layout(const Grid &g, size_t ts, int nv, int nf)
     L.f = take(19 * (size_t)g.n * ts);
     L.F = take(3 * (size_t)g.n * ts);
     L.stamp = take((size_t)g.nt * 4);
-    L.t = take(4);
-    L.done = take(4);
+    L.ctr = take(2 * 4);
     L.err = take(4);
     L.scratch = take(64 * 8);
     L.dom_end = o;
-    const int nparts = (nv + 255) / 256;
+    const int nparts = (nv + 31) / 32;
     L.q = take((size_t)3 * nv * 8);
     L.Xref = take((size_t)3 * nv * 8);
     L.faces = take((size_t)3 * nf * 4);
     L.fref = take((size_t)5 * nf * 8);
     L.inc_off = take((size_t)(nv + 1) * 4);
-    L.inc = take((size_t)3 * nf * 4);
+    L.inc4 = take((size_t)3 * nf * 16);
     L.phiSW = take((size_t)3 * nv * ts);
     L.gV = take((size_t)3 * nv * ts);
     L.base = take((size_t)nv * sizeof(Base));
@@ -116,8 +116,8 @@ struct iblb_ctx {
     bool timing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<hipEvent_t> pool;
-    double ktime[kNumKernels] = {0, 0, 0, 0, 0};
-    long long kcount[kNumKernels] = {0, 0, 0, 0, 0};
+    double ktime[kNumKernels] = {0, 0, 0, 0};
+    long long kcount[kNumKernels] = {0, 0, 0, 0};
     void *fext_alloc = nullptr;
     void *mesh_alloc = nullptr;
     std::string err;
@@ -235,20 +235,19 @@ hipEvent_t get_event(iblb_ctx *c)
     return e;
 }
 
-hipError_t launch_kernel(iblb_ctx *c, int which)
+hipError_t launch_kernel(iblb_ctx *c, int which, int p)
 {
     const Dev &d = c->d;
     switch (which) {
     case K_FORCES: return launch_forces(c->prec, d, c->g, c->m, c->stream);
-    case K_SPREAD: return launch_spread(c->prec, d, c->g, c->m, c->stream);
-    case K_LB: return launch_lb(c->prec, d, c->lb, c->stream);
-    case K_MOVE: return launch_move(c->prec, d, c->lb, c->m, c->stream);
-    default: return launch_tick(d, c->stream);
+    case K_SPREAD: return launch_spread(c->prec, d, c->g, c->m, p, c->stream);
+    case K_LB: return launch_lb(c->prec, d, c->lb, p, c->has_mesh ? 0 : 1, c->stream);
+    default: return launch_move(c->prec, d, c->lb, c->m, p, c->stream);
     }
 }
 
-// one step: forces -> spread -> lb -> move (mesh) or lb -> tick (no mesh)
-hipError_t enqueue_step(iblb_ctx *c, bool timed)
+// one step of parity p: forces -> spread -> lb -> move (mesh) or lb alone
+hipError_t enqueue_step(iblb_ctx *c, int p, bool timed)
 {
     int seq[4], ns = 0;
     if (c->has_mesh) {
@@ -258,7 +257,6 @@ hipError_t enqueue_step(iblb_ctx *c, bool timed)
         seq[ns++] = K_MOVE;
     } else {
         seq[ns++] = K_LB;
-        seq[ns++] = K_TICK;
     }
     for (int k = 0; k < ns; ++k) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -267,7 +265,7 @@ hipError_t enqueue_step(iblb_ctx *c, bool timed)
             e1 = get_event(c);
             (void)hipEventRecord(e0, c->stream);
         }
-        hipError_t e = launch_kernel(c, seq[k]);
+        hipError_t e = launch_kernel(c, seq[k], p);
         if (e != hipSuccess) return e;
         if (timed) {
             (void)hipEventRecord(e1, c->stream);
@@ -324,7 +322,7 @@ int rebuild_lists(iblb_ctx *c)
 {
     HIP_TRY(c, hipMemsetAsync(c->d.cnt, 0, (size_t)2 * c->g.nt * 4, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d.acnt, 0, 2 * 4, c->stream));
-    HIP_TRY(c, launch_bin(c->d, c->g, c->m, c->stream));
+    HIP_TRY(c, launch_bin(c->d, c->g, c->m, (int)(c->t & 1), c->stream));
     return IBLB_OK;
 }
 
@@ -393,10 +391,16 @@ int iblb_create(const iblb_domain_desc *dom, void *dev_workspace, size_t workspa
     d.f = c->ws + c->L.f;
     d.F = c->ws + c->L.F;
     d.stamp = (uint32_t *)(c->ws + c->L.stamp);
-    d.t = (uint32_t *)(c->ws + c->L.t);
-    d.done = (uint32_t *)(c->ws + c->L.done);
+    d.ctr = (uint32_t *)(c->ws + c->L.ctr);
     d.err = (int *)(c->ws + c->L.err);
     d.scratch = (double *)(c->ws + c->L.scratch);
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            return bail(IBLB_E_DEVICE);
+        d.num_cus = cus;
+    }
     lb_args(c);
     if (hipMemsetAsync(c->ws + c->L.stamp, 0, c->L.dom_end - c->L.stamp, c->stream) != hipSuccess ||
         hipMemsetAsync(d.F, 0, 3 * (size_t)c->g.n * c->ts, c->stream) != hipSuccess ||
@@ -453,14 +457,18 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     if (!(V0 > 0.0)) return fail(c, IBLB_E_MESH, "reference volume not positive (faces must point outward)");
 
     // vertex -> (face, corner), faces ascending
-    std::vector<int> off(nv + 1, 0), inc((size_t)3 * nf);
+    std::vector<int> off(nv + 1, 0);
+    std::vector<int4> inc((size_t)3 * nf);
     for (int j = 0; j < nf; ++j)
         for (int k = 0; k < 3; ++k) off[mesh->faces[3 * j + k] + 1]++;
     for (int i = 0; i < nv; ++i) off[i + 1] += off[i];
     {
         std::vector<int> fill(off.begin(), off.end() - 1);
         for (int j = 0; j < nf; ++j)
-            for (int k = 0; k < 3; ++k) inc[fill[mesh->faces[3 * j + k]]++] = (j << 2) | k;
+            for (int k = 0; k < 3; ++k) {
+                const int *f = mesh->faces + 3 * j;
+                inc[fill[f[k]]++] = make_int4(f[0], f[1], f[2], (j << 2) | k);
+            }
     }
     // structure-of-arrays copies
     std::vector<double> qs((size_t)3 * nv), Xs((size_t)3 * nv);
@@ -492,7 +500,7 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     d.faces = (int *)(mb + L.faces);
     d.fref = (double *)(mb + L.fref);
     d.inc_off = (int *)(mb + L.inc_off);
-    d.inc = (int *)(mb + L.inc);
+    d.inc4 = (int4 *)(mb + L.inc4);
     d.phiSW = mb + L.phiSW;
     d.gV = mb + L.gV;
     d.base = (Base *)(mb + L.base);
@@ -507,8 +515,8 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     HIP_TRY(c, hipMemcpyAsync(d.faces, fs.data(), fs.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d.fref, fref.data(), fref.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d.inc_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(d.inc, inc.data(), inc.size() * 4, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemsetAsync(d.partials, 0, (size_t)2 * ((nv + 255) / 256) * 8, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d.inc4, inc.data(), inc.size() * 16, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(d.partials, 0, (size_t)2 * ((nv + 31) / 32) * 8, c->stream));
 
     MeshArgs &m = c->m;
     m.nv = nv;
@@ -524,7 +532,7 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     m.z_lo = 0.5;
     m.z_hi = c->dom.nz - 1.5;
     m.kv_over_V0 = mesh->k_v / V0;
-    m.nparts = (nv + 255) / 256;
+    m.nparts = (nv + 31) / 32;
     c->V0 = V0;
     c->nv = nv;
     c->nf = nf;
@@ -540,27 +548,36 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
 int iblb_step(iblb_ctx *c, int32_t n_steps)
 {
     if (!c || n_steps < 0) return IBLB_E_INVAL;
-    for (int s = 0; s < n_steps; ++s) {
-        if (c->timing) {
-            hipError_t e = enqueue_step(c, true);
-            if (e != hipSuccess) return hip_fail(c, e, "step launch");
-        } else if (c->use_graph) {
+    // A captured graph holds kGraphSteps steps starting at an even time;
+    // the rest (short counts, odd start, timing) is launched directly.
+    int left = n_steps;
+    while (left > 0) {
+        const int p = (int)(c->t & 1);
+        if (!c->timing && c->use_graph && p == 0 && left >= kGraphSteps) {
             if (!c->gexec) {
                 HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                hipError_t e = enqueue_step(c, false);
+                hipError_t e = hipSuccess;
+                for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
+                    e = enqueue_step(c, k & 1, false);
                 hipGraph_t gr = nullptr;
                 hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
-                if (e != hipSuccess) return hip_fail(c, e, "step capture");
+                if (e != hipSuccess) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    return hip_fail(c, e, "step capture");
+                }
                 if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
                 c->graph = gr;
                 HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
             }
             HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+            c->t += kGraphSteps;
+            left -= kGraphSteps;
         } else {
-            hipError_t e = enqueue_step(c, false);
+            hipError_t e = enqueue_step(c, p, c->timing);
             if (e != hipSuccess) return hip_fail(c, e, "step launch");
+            c->t += 1;
+            left -= 1;
         }
-        c->t++;
     }
     if (c->timing) return collect_timing(c);
     return IBLB_OK;
@@ -710,7 +727,7 @@ int iblb_get_fields(iblb_ctx *c, double *rho, double *u)
     TmpDev tmp;
     HIP_TRY(c, hipMalloc(&tmp.p, 4 * n * 8));
     double *dr = (double *)tmp.p, *du = dr + n;
-    HIP_TRY(c, launch_get_fields(c->prec, c->d, c->lb, dr, du, c->stream));
+    HIP_TRY(c, launch_get_fields(c->prec, c->d, c->lb, (int)(c->t & 1), dr, du, c->stream));
     HIP_TRY(c, hipMemcpyAsync(rho, dr, n * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(u, du, 3 * n * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -746,7 +763,7 @@ int iblb_debug_get_force(iblb_ctx *c, double *F)
     const size_t n = (size_t)c->g.n;
     TmpDev tmp;
     HIP_TRY(c, hipMalloc(&tmp.p, 3 * n * 8));
-    HIP_TRY(c, launch_get_force(c->prec, c->d, c->lb, (double *)tmp.p, c->stream));
+    HIP_TRY(c, launch_get_force(c->prec, c->d, c->lb, (int)(c->t & 1), (double *)tmp.p, c->stream));
     HIP_TRY(c, hipMemcpyAsync(F, tmp.p, 3 * n * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return rc;
@@ -759,7 +776,7 @@ int iblb_debug_get_populations(iblb_ctx *c, double *f)
     const size_t n = (size_t)c->g.n;
     TmpDev tmp;
     HIP_TRY(c, hipMalloc(&tmp.p, 19 * n * 8));
-    HIP_TRY(c, launch_get_pops(c->prec, c->d, c->g, (double *)tmp.p, c->stream));
+    HIP_TRY(c, launch_get_pops(c->prec, c->d, c->g, (int)(c->t & 1), (double *)tmp.p, c->stream));
     HIP_TRY(c, hipMemcpyAsync(f, tmp.p, 19 * n * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return rc;
@@ -773,7 +790,7 @@ int iblb_debug_set_populations(iblb_ctx *c, const double *f)
     TmpDev tmp;
     HIP_TRY(c, hipMalloc(&tmp.p, 19 * n * 8));
     HIP_TRY(c, hipMemcpyAsync(tmp.p, f, 19 * n * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, launch_set_pops(c->prec, c->d, c->g, (const double *)tmp.p, c->stream));
+    HIP_TRY(c, launch_set_pops(c->prec, c->d, c->g, (int)(c->t & 1), (const double *)tmp.p, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return IBLB_OK;
 }
@@ -860,8 +877,10 @@ int iblb_load_state(iblb_ctx *c, const void *host_buf, size_t bytes)
     HIP_TRY(c, hipMemcpy(c->d.stamp, p, (size_t)c->g.nt * 4, hipMemcpyHostToDevice));
     p += (size_t)c->g.nt * 4;
     if (c->nv) HIP_TRY(c, hipMemcpy(c->d.q, p, (size_t)3 * c->nv * 8, hipMemcpyHostToDevice));
-    const uint32_t t32 = (uint32_t)h.t;
-    HIP_TRY(c, hipMemcpy(c->d.t, &t32, 4, hipMemcpyHostToDevice));
+    uint32_t ctr[2];
+    ctr[h.t & 1] = (uint32_t)h.t;
+    ctr[1 - (h.t & 1)] = (uint32_t)h.t;  // not read before it is written
+    HIP_TRY(c, hipMemcpy(c->d.ctr, ctr, 8, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->d.err, &h.err, 4, hipMemcpyHostToDevice));
     c->t = h.t;
     if (c->has_mesh) {

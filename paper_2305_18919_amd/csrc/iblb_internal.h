@@ -47,7 +47,7 @@ struct MeshArgs {
     double z_lo, z_hi;
     double origin[3];
     double kv_over_V0;    // k_V / V0
-    int nparts;           // force-kernel blocks = number of volume partials
+    int nparts;           // force-kernel blocks (32 vertices each) = number of volume partials
 };
 
 // Device buffers of one context (typed as void* where the precision varies).
@@ -56,8 +56,7 @@ struct Dev {
     void *F;              // [3][n] IB force density of the step stamped in `stamp`
     void *Fext;           // [3][n] or null
     uint32_t *stamp;      // [nt] step+1 for which F of the tile is valid
-    uint32_t *t;          // device step counter
-    uint32_t *done;       // last-block counter
+    uint32_t *ctr;        // [2] step counter, ctr[t & 1] = t
     int *err;             // error bits
     // mesh
     double *q;            // [3][nv] FP64 positions
@@ -65,7 +64,7 @@ struct Dev {
     int *faces;           // [3][nf]
     double *fref;         // [5][nf]: Ginv11, Ginv12, Ginv22, A0, detG
     int *inc_off;         // [nv+1]
-    int *inc;             // [3 nf]: face*4 + corner, vertex-major, faces ascending
+    int4 *inc4;           // [3 nf]: (a, b, c, face*4 + corner), vertex-major, faces ascending
     void *phiSW;          // [3][nv] elastic + wall force
     void *gV;             // [3][nv] dV/dq
     Base *base;           // [nv]
@@ -76,21 +75,22 @@ struct Dev {
     uint32_t *acnt;       // [2]
     int *alist;           // [2][nt]
     double *scratch;      // small FP64 scratch for queries (64 doubles)
+    int num_cus;          // compute units of the device (launch sizing)
 };
 
 // launchers (iblb_kernels.hip); precision 0 = FP64, 1 = FP32
 hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hipStream_t s);
-hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, hipStream_t s);
-hipError_t launch_tick(const Dev &d, hipStream_t s);
+// p = t & 1 of the step (or of the current time for the debug kernels)
+hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int advance, hipStream_t s);
 hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s);
-hipError_t launch_spread(int prec, const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s);
-hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s);
-hipError_t launch_bin(const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s);
+hipError_t launch_spread(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s);
+hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);
+hipError_t launch_bin(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s);
 // debug / query kernels
-hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, double *out, hipStream_t s);
-hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, const double *in, hipStream_t s);
-hipError_t launch_get_fields(int prec, const Dev &d, const LBArgs &a, double *rho, double *u, hipStream_t s);
-hipError_t launch_get_force(int prec, const Dev &d, const LBArgs &a, double *F, hipStream_t s);
+hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double *out, hipStream_t s);
+hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, int p, const double *in, hipStream_t s);
+hipError_t launch_get_fields(int prec, const Dev &d, const LBArgs &a, int p, double *rho, double *u, hipStream_t s);
+hipError_t launch_get_force(int prec, const Dev &d, const LBArgs &a, int p, double *F, hipStream_t s);
 hipError_t launch_nodal_forces(int prec, const Dev &d, const MeshArgs &m, double *phi, hipStream_t s);
 hipError_t launch_mesh_moments(const Dev &d, const MeshArgs &m, double *out, hipStream_t s);
 hipError_t launch_sphere_moments(const Dev &d, const MeshArgs &m, int wall_hi, double z_wall, double excl,

@@ -6,7 +6,8 @@
 //   k_forces  one thread per vertex: elastic force -dW/dq of the incident faces
 //             (Eqs. generalised_energy1, nodal_force_S), dV/dq (Eq.
 //             nodal_force_V), wall force (Eq. LJ_interaction), FP64 block
-//             partials of V - V0 and A, and the vertex's phi4 stencil weights
+//             partials of V - V0 and A, and the vertex's phi4 stencil weights;
+//             eight lanes per vertex, one incident face each
 //   k_spread  one wavefront per active 4x4x4 tile: gathers phi_i w_i(x) of the
 //             vertices whose stencil reaches the tile, in ascending vertex order
 //             (Eq. ibm-governing_eq2); no floating-point atomics
@@ -16,8 +17,15 @@
 //   k_move    one wavefront per vertex, one lane per stencil node: u(t+1) from
 //             the streamed populations and F(t)/2, interpolation (Eq.
 //             ibm-governing_eq1), Euler update (Eq. ibm_update_pos), and the
-//             tile lists of the next step; the last block advances the device
-//             step counter.
+//             tile lists of the next step; it also advances the device step
+//             counter.
+//
+// Step counter: ctr[2] in device memory, ctr[t & 1] = t.  Every kernel of
+// step t is launched with p = t & 1 and reads t from ctr[p]; the last kernel
+// of the step writes t + 1 into ctr[1 - p], which no kernel of step t reads.
+// So a captured graph of two steps (p = 0, then p = 1) replays correctly
+// without atomics, and the AA parity is a compile-time property of each
+// launch.
 //
 // Data layout (all structure-of-arrays, x fastest):
 //   populations f[19][N] (N fluid nodes), deviations f_i - w_i rho0, in place
@@ -255,24 +263,24 @@ __device__ __forceinline__ void lb_node(T *__restrict__ f, const T *__restrict__
     }
 }
 
-template <typename T>
+template <typename T, bool ODD>
 __global__ __launch_bounds__(256) void k_lb(T *__restrict__ f, const T *__restrict__ Fib,
                                             const T *__restrict__ Fext, const uint32_t *__restrict__ stamp,
-                                            const uint32_t *__restrict__ dt, uint32_t *acnt, int *err, LBArgs a)
+                                            uint32_t *ctr, uint32_t *acnt, int *err, LBArgs a, int advance)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int zf = blockIdx.z;
-    const uint32_t t = *dt;
-    if (acnt != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 &&
-        threadIdx.y == 0)
-        acnt[t & 1u] = 0u;  // the spread of this step has consumed its tile list
+    const uint32_t t = ctr[ODD ? 1 : 0];
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+        if (acnt != nullptr)
+            acnt[ODD ? 1 : 0] = 0u;  // the spread of this step has consumed its tile list
+        if (advance)
+            ctr[ODD ? 0 : 1] = t + 1u;
+    }
     if (x >= a.g.nx || y >= a.g.ny)
         return;
-    if (t & 1u)
-        lb_node<T, true>(f, Fib, Fext, stamp, t, err, a, x, y, zf);
-    else
-        lb_node<T, false>(f, Fib, Fext, stamp, t, err, a, x, y, zf);
+    lb_node<T, ODD>(f, Fib, Fext, stamp, t, err, a, x, y, zf);
 }
 
 template <typename T>
@@ -298,12 +306,6 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ f, LBArgs a, int c
         const double w = wgt<double>(i);
         f[i * g.n + me] = T(w * a.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
     }
-}
-
-__global__ void k_tick(uint32_t *dt)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        *dt = *dt + 1u;
 }
 
 // ---------------------------------------------------------------------------
@@ -343,28 +345,29 @@ __device__ __forceinline__ double volume_change(const double *__restrict__ X, in
     return t / 6.0;
 }
 
+// Eight lanes per vertex (32 vertices per 256-thread block); lane k of a
+// vertex handles its incident faces k, k + 8, ...; the group sums by butterfly.
 template <typename T>
 __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, const double *__restrict__ Xref,
-                                                const int *__restrict__ faces,
-                                                const double *__restrict__ fref, const int *__restrict__ inc_off,
-                                                const int *__restrict__ inc, T *__restrict__ phiSW,
+                                                const int4 *__restrict__ inc4, const int *__restrict__ inc_off,
+                                                const double *__restrict__ fref, T *__restrict__ phiSW,
                                                 T *__restrict__ gVout, Base *__restrict__ base,
                                                 T *__restrict__ wts, double *__restrict__ partials, int *err,
                                                 Grid g, MeshArgs m)
 {
     __shared__ double red[2][256];
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sub = threadIdx.x & 7;
+    const int v = blockIdx.x * 32 + (threadIdx.x >> 3);
     const int nv = m.nv, nf = m.nf;
     double dvol = 0.0, darea = 0.0;
+    T fs[3] = {T(0), T(0), T(0)};
+    T gv[3] = {T(0), T(0), T(0)};
     if (v < nv) {
-        T fs[3] = {T(0), T(0), T(0)};
-        T gv[3] = {T(0), T(0), T(0)};
         const T a1 = T(m.alpha[0]), a2 = T(m.alpha[1]), a3 = T(m.alpha[2]);
         const int k1 = inc_off[v + 1];
-        for (int k = inc_off[v]; k < k1; ++k) {
-            const int code = inc[k];
-            const int j = code >> 2, corner = code & 3;
-            const int ia = faces[j], ib = faces[nf + j], ic = faces[2 * nf + j];
+        for (int k = inc_off[v] + sub; k < k1; k += 8) {
+            const int4 e = inc4[k];
+            const int ia = e.x, ib = e.y, ic = e.z, j = e.w >> 2, corner = e.w & 3;
             const double ax = q[ia], ay = q[nv + ia], az = q[2 * nv + ia];
             const double bx = q[ib], by = q[nv + ib], bz = q[2 * nv + ib];
             const double cxv = q[ic], cyv = q[nv + ic], czv = q[2 * nv + ic];
@@ -425,43 +428,55 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, co
                 fs[2] += fzw / T(3);
             }
         }
+    }
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1)
+        for (int c = 0; c < 3; ++c) {
+            fs[c] += __shfl_xor(fs[c], off, 64);
+            gv[c] += __shfl_xor(gv[c], off, 64);
+        }
+    if (v < nv && sub == 0) {
         phiSW[v] = fs[0];
         phiSW[nv + v] = fs[1];
         phiSW[2 * nv + v] = fs[2];
         gVout[v] = gv[0];
         gVout[nv + v] = gv[1];
         gVout[2 * nv + v] = gv[2];
-
-        // stencil corner and phi4 weights of this vertex for the spreading
+    }
+    // stencil corner and phi4 weights of this vertex for the spreading:
+    // sub-lanes 0..3 compute the x, y, z weights of offset `sub`, sub-lane 4 the corner
+    if (v < nv && sub < 5) {
         const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
-        Base bs;
         if (fabs(qx) < 1e6 && fabs(qy) < 1e6 && fabs(qz) < 1e6) {
             const int fx = (int)floor(qx) - 1, fy = (int)floor(qy) - 1, fz = (int)floor(qz) - 1;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                wts[v * 12 + k] = phi4<T>(T((double)(fx + k) - qx));
-                wts[v * 12 + 4 + k] = phi4<T>(T((double)(fy + k) - qy));
-                wts[v * 12 + 8 + k] = phi4<T>(T((double)(fz + k) - qz));
+            if (sub < 4) {
+                wts[v * 12 + sub] = phi4<T>(T((double)(fx + sub) - qx));
+                wts[v * 12 + 4 + sub] = phi4<T>(T((double)(fy + sub) - qy));
+                wts[v * 12 + 8 + sub] = phi4<T>(T((double)(fz + sub) - qz));
+            } else {
+                Base bs;
+                bs.x = wrapi(fx, g.nx);
+                bs.y = wrapi(fy, g.ny);
+                bs.z = g.walls ? fz : wrapi(fz, g.nz);
+                bs.ok = 1;
+                base[v] = bs;
             }
-            bs.x = wrapi(fx, g.nx);
-            bs.y = wrapi(fy, g.ny);
-            bs.z = g.walls ? fz : wrapi(fz, g.nz);
-            bs.ok = 1;
-        } else {
+        } else if (sub == 4) {
+            Base bs;
             bs.x = bs.y = bs.z = 0;
             bs.ok = 0;
+            base[v] = bs;
             atomicOr(err, kErrNonFinite);
         }
-        base[v] = bs;
     }
     // FP64 block partials of V - V0 and A (fixed tree order)
     red[0][threadIdx.x] = dvol;
     red[1][threadIdx.x] = darea;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + s];
-            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + st];
+            red[1][threadIdx.x] += red[1][threadIdx.x + st];
         }
         __syncthreads();
     }
@@ -485,82 +500,175 @@ __device__ __forceinline__ double volume_factor(const double *__restrict__ parti
 // ---------------------------------------------------------------------------
 // Spreading, one wavefront per active tile (gather form, no FP atomics)
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(64) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
-                                               const T *__restrict__ phiSW, const T *__restrict__ gV,
-                                               const double *__restrict__ partials, const uint32_t *__restrict__ dt,
-                                               uint32_t *cnt, const int *__restrict__ list,
-                                               const uint32_t *__restrict__ acnt, const int *__restrict__ alist,
-                                               T *__restrict__ F, uint32_t *__restrict__ stamp, Grid g, MeshArgs m)
+// Ascending bitonic sort of K * 64 keys (K = 1, 2, 4 or 8) held in registers:
+// element i = k * 64 + lane is v[k] of that lane.  Strides below 64 pair lanes
+// (butterfly shuffles), strides of 64 and more pair registers of one lane.
+__device__ __forceinline__ void cswap_regs(int &a, int &b, bool up)
 {
-    __shared__ int ids[kTileCap];
-    const int lane = threadIdx.x;
-    const uint32_t t = *dt;
-    const int buf = t & 1;
+    if ((a > b) == up) {
+        const int t = a;
+        a = b;
+        b = t;
+    }
+}
+
+__device__ __forceinline__ void bitonic_sort_regs(int (&v)[8], int K, int lane)
+{
+    const int P = K * 64;
+    for (int s = 2; s <= P; s <<= 1) {
+        for (int j = s >> 1; j > 0; j >>= 1) {
+            if (j < 64) {
+                const bool lower = (lane & j) == 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (k < K) {
+                        const int w = __shfl_xor(v[k], j, 64);
+                        const bool up = ((k * 64 + lane) & s) == 0;
+                        v[k] = (lower == up) ? min(v[k], w) : max(v[k], w);
+                    }
+                }
+            } else if (j == 64) {
+#pragma unroll
+                for (int k = 0; k < 8; k += 2)
+                    if (k < K) cswap_regs(v[k], v[k + 1], ((k * 64 + lane) & s) == 0);
+            } else if (j == 128) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if ((k & 2) == 0 && k < K) cswap_regs(v[k], v[k + 2], ((k * 64 + lane) & s) == 0);
+            } else {  // j == 256
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k + 4 < K) cswap_regs(v[k], v[k + 4], ((k * 64 + lane) & s) == 0);
+            }
+        }
+    }
+}
+
+// One 256-thread block (four wavefronts) per active tile.  Wavefront 0 sorts
+// the tile's vertex list; all four stage the listed vertices; wavefront w
+// then sums the w-th contiguous quarter of the sorted list for the 64 nodes
+// (one per lane), and the four partial sums are added in wavefront order, so
+// every node's sum has a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
+                                                const T *__restrict__ phiSW, const T *__restrict__ gV,
+                                                const double *__restrict__ partials, const uint32_t *__restrict__ ctr,
+                                                uint32_t *cnt, const int *__restrict__ list,
+                                                const uint32_t *__restrict__ acnt, const int *__restrict__ alist,
+                                                T *__restrict__ F, uint32_t *__restrict__ stamp, Grid g, MeshArgs m,
+                                                int p)
+{
+    __shared__ int sid[kTileCap];
+    __shared__ int sbx[kTileCap], sby[kTileCap], sbz[kTileCap];
+    __shared__ T sw[kTileCap * 12];
+    __shared__ T sph[kTileCap * 3];
+    __shared__ T part[3][3][64];
+    __shared__ int snent;
+    __shared__ T skfac;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t t = ctr[p];
+    const int buf = p;
     const uint32_t na = acnt[buf];
     if (blockIdx.x >= na)
         return;
-    const T kfac = T(volume_factor(partials, m, lane));
+    if (wave == 0) {
+        const T kfac = T(volume_factor(partials, m, lane));
+        if (lane == 0)
+            skfac = kfac;
+    }
     const int nv = m.nv;
     for (uint32_t a = blockIdx.x; a < na; a += gridDim.x) {
         const int tile = alist[buf * g.nt + a];
-        const uint32_t c = cnt[buf * g.nt + tile];
-        const int nent = c < (uint32_t)kTileCap ? (int)c : kTileCap;
-        int P = 1;
-        while (P < nent)
-            P <<= 1;
-        const int *src = list + ((long long)buf * g.nt + tile) * kTileCap;
-        for (int e = lane; e < P; e += 64)
-            ids[e] = e < nent ? src[e] : 0x7fffffff;
-        __syncthreads();
-        if (lane == 0)
-            cnt[buf * g.nt + tile] = 0u;
-        // bitonic sort: ascending vertex index makes the sums order-deterministic
-        for (int k = 2; k <= P; k <<= 1)
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int i = lane; i < P; i += 64) {
-                    const int ixj = i ^ j;
-                    if (ixj > i) {
-                        const int va = ids[i], vb = ids[ixj];
-                        if ((va > vb) == ((i & k) == 0)) {
-                            ids[i] = vb;
-                            ids[ixj] = va;
-                        }
-                    }
-                }
-                __syncthreads();
+        if (wave == 0) {
+            // the whole list slot range is read at once, next to its count, and masked after
+            const int *src = list + ((long long)buf * g.nt + tile) * kTileCap;
+            int key[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                key[k] = src[k * 64 + lane];
+            const uint32_t c = cnt[buf * g.nt + tile];
+            const int nent = c < (uint32_t)kTileCap ? (int)c : kTileCap;
+            int K = 1;
+            while (K * 64 < nent)
+                K <<= 1;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k * 64 + lane >= nent) key[k] = 0x7fffffff;
+            if (lane == 0) {
+                cnt[buf * g.nt + tile] = 0u;
+                snent = nent;
             }
-        // this lane's node
+            // ascending vertex index makes the sums order-deterministic
+            bitonic_sort_regs(key, K, lane);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k < K) sid[k * 64 + lane] = key[k];
+        }
+        __syncthreads();
+        const int nent = snent;
+        // stage each listed vertex's stencil corner, weights and total force in LDS
+        for (int e = threadIdx.x; e < nent; e += 256) {
+            const int v = sid[e];
+            const Base bs = base[v];
+            sbx[e] = bs.x;
+            sby[e] = bs.y;
+            sbz[e] = bs.z;
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                sw[e * 12 + k] = wts[v * 12 + k];
+        }
+        const T kf = skfac;
+        for (int e = threadIdx.x; e < nent; e += 256) {
+            const int v = sid[e];
+            sph[e * 3 + 0] = phiSW[v] - kf * gV[v];
+            sph[e * 3 + 1] = phiSW[nv + v] - kf * gV[nv + v];
+            sph[e * 3 + 2] = phiSW[2 * nv + v] - kf * gV[2 * nv + v];
+        }
+        __syncthreads();
+        // this lane's node, and this wavefront's quarter of the list
         const int tz = tile / (g.ntx * g.nty);
         const int rem = tile - tz * g.ntx * g.nty;
         const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
         const int x = tx * 4 + (lane & 3), y = ty * 4 + ((lane >> 2) & 3), zf = tz * 4 + (lane >> 4);
         const int z = zf + g.zoff;
+        const int chunk = (nent + 3) >> 2;
+        const int e0 = wave * chunk, e1 = min(nent, e0 + chunk);
         T Fx = T(0), Fy = T(0), Fz = T(0);
-        for (int e = 0; e < nent; ++e) {
-            const int v = ids[e];
-            const Base bs = base[v];
-            int dx = x - bs.x;
+        for (int e = e0; e < e1; ++e) {
+            int dx = x - sbx[e];
             if (dx < 0) dx += g.nx;
-            int dy = y - bs.y;
+            int dy = y - sby[e];
             if (dy < 0) dy += g.ny;
-            int dz = z - bs.z;
+            int dz = z - sbz[e];
             if (!g.walls && dz < 0) dz += g.nz;
             if ((unsigned)dx < 4u && (unsigned)dy < 4u && (unsigned)dz < 4u) {
-                const T w = wts[v * 12 + dx] * wts[v * 12 + 4 + dy] * wts[v * 12 + 8 + dz];
-                Fx += (phiSW[v] - kfac * gV[v]) * w;
-                Fy += (phiSW[nv + v] - kfac * gV[nv + v]) * w;
-                Fz += (phiSW[2 * nv + v] - kfac * gV[2 * nv + v]) * w;
+                const T w = sw[e * 12 + dx] * sw[e * 12 + 4 + dy] * sw[e * 12 + 8 + dz];
+                Fx += sph[e * 3 + 0] * w;
+                Fy += sph[e * 3 + 1] * w;
+                Fz += sph[e * 3 + 2] * w;
             }
         }
-        if (x < g.nx && y < g.ny && zf < g.nzf) {
-            const long long me = nidx(g, x, y, zf);
-            F[me] = Fx;
-            F[g.n + me] = Fy;
-            F[2 * g.n + me] = Fz;
+        if (wave > 0) {
+            part[wave - 1][0][lane] = Fx;
+            part[wave - 1][1][lane] = Fy;
+            part[wave - 1][2][lane] = Fz;
         }
-        if (lane == 0)
-            stamp[tile] = t + 1u;
+        __syncthreads();
+        if (wave == 0) {
+            for (int w = 0; w < 3; ++w) {
+                Fx += part[w][0][lane];
+                Fy += part[w][1][lane];
+                Fz += part[w][2][lane];
+            }
+            if (x < g.nx && y < g.ny && zf < g.nzf) {
+                const long long me = nidx(g, x, y, zf);
+                F[me] = Fx;
+                F[g.n + me] = Fy;
+                F[2 * g.n + me] = Fz;
+            }
+            if (lane == 0)
+                stamp[tile] = t + 1u;
+        }
         __syncthreads();
     }
 }
@@ -612,17 +720,21 @@ __device__ __forceinline__ void list_vertex(int v, double qx, double qy, double 
     }
 }
 
-template <typename T>
+// P = t & 1: after this step's LB the populations of time t + 1 sit in the
+// swapped layout exactly when P == 0.
+template <typename T, int P>
 __global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *__restrict__ f,
                                               const T *__restrict__ Fib, const T *__restrict__ Fext,
-                                              const uint32_t *__restrict__ stamp, uint32_t *dt, uint32_t *done,
-                                              uint32_t *cnt, int *list, uint32_t *acnt, int *alist, int *err,
-                                              LBArgs a, MeshArgs m)
+                                              const uint32_t *__restrict__ stamp, uint32_t *ctr, uint32_t *cnt,
+                                              int *list, uint32_t *acnt, int *alist, int *err, LBArgs a,
+                                              MeshArgs m)
 {
     const Grid &g = a.g;
     const int lane = threadIdx.x & 63;
     const int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t t = __atomic_load_n(dt, __ATOMIC_RELAXED);
+    const uint32_t t = ctr[P];
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        ctr[1 - P] = t + 1u;
     if (v < m.nv) {
         const int nv = m.nv;
         const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
@@ -644,10 +756,7 @@ __global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *_
                 const int zf = z - g.zoff;
                 T d[19];
                 // populations at t+1 (after this step's LB): swapped layout when t+1 is odd
-                if ((t + 1u) & 1u)
-                    load_pops<T, true>(f, g, x, y, zf, d);
-                else
-                    load_pops<T, false>(f, g, x, y, zf, d);
+                load_pops<T, P == 0>(f, g, x, y, zf, d);
                 T drho = T(0), mx = T(0), my = T(0), mz = T(0);
 #pragma unroll
                 for (int i = 0; i < 19; ++i) {
@@ -680,42 +789,28 @@ __global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *_
                 q[nv + v] = nqy;
                 q[2 * nv + v] = nqz;
             }
-            list_vertex(v, nqx, nqy, nqz, lane, g, cnt, list, acnt, alist, (t + 1u) & 1u, err);
+            list_vertex(v, nqx, nqy, nqz, lane, g, cnt, list, acnt, alist, 1 - P, err);
         } else if (lane == 0) {
             atomicOr(err, kErrNonFinite);
         }
     }
-    // the last block to finish advances the step counter
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(done, 1u);
-        if (prev == gridDim.x - 1u) {
-            *done = 0u;
-            __atomic_store_n(dt, t + 1u, __ATOMIC_RELAXED);
-            __threadfence();
-        }
-    }
 }
 
-__global__ __launch_bounds__(256) void k_bin(const double *__restrict__ q, const uint32_t *__restrict__ dt,
-                                             uint32_t *cnt, int *list, uint32_t *acnt, int *alist, int *err, Grid g,
-                                             MeshArgs m)
+__global__ __launch_bounds__(256) void k_bin(const double *__restrict__ q, uint32_t *cnt, int *list,
+                                             uint32_t *acnt, int *alist, int *err, Grid g, MeshArgs m, int p)
 {
     const int lane = threadIdx.x & 63;
     const int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (v >= m.nv)
         return;
-    const uint32_t t = *dt;
-    list_vertex(v, q[v], q[m.nv + v], q[2 * m.nv + v], lane, g, cnt, list, acnt, alist, t & 1u, err);
+    list_vertex(v, q[v], q[m.nv + v], q[2 * m.nv + v], lane, g, cnt, list, acnt, alist, p, err);
 }
 
 // ---------------------------------------------------------------------------
 // Debug and query kernels (not on the per-step path)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_get_pops(const T *__restrict__ f, const uint32_t *__restrict__ dt,
-                                                  double *__restrict__ out, Grid g)
+__global__ __launch_bounds__(256) void k_get_pops(const T *__restrict__ f, int p, double *__restrict__ out, Grid g)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -723,7 +818,7 @@ __global__ __launch_bounds__(256) void k_get_pops(const T *__restrict__ f, const
     if (x >= g.nx || y >= g.ny)
         return;
     T d[19];
-    if (*dt & 1u)
+    if (p)
         load_pops<T, true>(f, g, x, y, zf, d);
     else
         load_pops<T, false>(f, g, x, y, zf, d);
@@ -733,8 +828,7 @@ __global__ __launch_bounds__(256) void k_get_pops(const T *__restrict__ f, const
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_set_pops(T *__restrict__ f, const uint32_t *__restrict__ dt,
-                                                  const double *__restrict__ in, Grid g)
+__global__ __launch_bounds__(256) void k_set_pops(T *__restrict__ f, int p, const double *__restrict__ in, Grid g)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -743,7 +837,7 @@ __global__ __launch_bounds__(256) void k_set_pops(T *__restrict__ f, const uint3
         return;
     const long long me = nidx(g, x, y, zf);
     const long long n = g.n;
-    if (*dt & 1u) {
+    if (p) {
         const Nbr b = neighbours(g, x, y, zf);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
@@ -786,7 +880,7 @@ __device__ __forceinline__ void last_force(const T *Fib, const T *Fext, const ui
 template <typename T>
 __global__ __launch_bounds__(256) void k_get_fields(const T *__restrict__ f, const T *__restrict__ Fib,
                                                     const T *__restrict__ Fext, const uint32_t *__restrict__ stamp,
-                                                    const uint32_t *__restrict__ dt, double *__restrict__ rho_out,
+                                                    const uint32_t *__restrict__ ctr, int p, double *__restrict__ rho_out,
                                                     double *__restrict__ u_out, double *__restrict__ F_out, LBArgs a)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -795,7 +889,7 @@ __global__ __launch_bounds__(256) void k_get_fields(const T *__restrict__ f, con
     const Grid &g = a.g;
     if (x >= g.nx || y >= g.ny)
         return;
-    const uint32_t t = *dt;
+    const uint32_t t = ctr[p];
     const long long me = nidx(g, x, y, zf);
     double F[3];
     last_force<T>(Fib, Fext, stamp, t, a, x, y, zf, me, F);
@@ -807,7 +901,7 @@ __global__ __launch_bounds__(256) void k_get_fields(const T *__restrict__ f, con
     if (rho_out == nullptr)
         return;
     T d[19];
-    if (t & 1u)
+    if (p)
         load_pops<T, true>(f, g, x, y, zf, d);
     else
         load_pops<T, false>(f, g, x, y, zf, d);
@@ -953,21 +1047,25 @@ hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hip
     return hipGetLastError();
 }
 
-hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, hipStream_t s)
+hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int advance, hipStream_t s)
 {
     const uint32_t *stamp = d.q ? d.stamp : nullptr;
-    if (prec == 0)
-        k_lb<double><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((double *)d.f, (const double *)d.F,
-                                                              (const double *)d.Fext, stamp, d.t, d.acnt, d.err, a);
-    else
-        k_lb<float><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((float *)d.f, (const float *)d.F,
-                                                             (const float *)d.Fext, stamp, d.t, d.acnt, d.err, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_tick(const Dev &d, hipStream_t s)
-{
-    k_tick<<<1, 64, 0, s>>>(d.t);
+    const dim3 gr = lb_grid(a.g), bl = lb_block(a.g);
+    if (prec == 0) {
+        if (p)
+            k_lb<double, true><<<gr, bl, 0, s>>>((double *)d.f, (const double *)d.F, (const double *)d.Fext, stamp,
+                                                  d.ctr, d.acnt, d.err, a, advance);
+        else
+            k_lb<double, false><<<gr, bl, 0, s>>>((double *)d.f, (const double *)d.F, (const double *)d.Fext, stamp,
+                                                   d.ctr, d.acnt, d.err, a, advance);
+    } else {
+        if (p)
+            k_lb<float, true><<<gr, bl, 0, s>>>((float *)d.f, (const float *)d.F, (const float *)d.Fext, stamp,
+                                                 d.ctr, d.acnt, d.err, a, advance);
+        else
+            k_lb<float, false><<<gr, bl, 0, s>>>((float *)d.f, (const float *)d.F, (const float *)d.Fext, stamp,
+                                                  d.ctr, d.acnt, d.err, a, advance);
+    }
     return hipGetLastError();
 }
 
@@ -975,88 +1073,96 @@ hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &
 {
     const int blocks = m.nparts;
     if (prec == 0)
-        k_forces<double><<<blocks, 256, 0, s>>>(d.q, d.Xref, d.faces, d.fref, d.inc_off, d.inc, (double *)d.phiSW,
+        k_forces<double><<<blocks, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.inc_off, d.fref, (double *)d.phiSW,
                                                 (double *)d.gV, d.base, (double *)d.wts, d.partials, d.err, g, m);
     else
-        k_forces<float><<<blocks, 256, 0, s>>>(d.q, d.Xref, d.faces, d.fref, d.inc_off, d.inc, (float *)d.phiSW,
+        k_forces<float><<<blocks, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.inc_off, d.fref, (float *)d.phiSW,
                                                (float *)d.gV, d.base, (float *)d.wts, d.partials, d.err, g, m);
     return hipGetLastError();
 }
 
-hipError_t launch_spread(int prec, const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s)
+hipError_t launch_spread(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)
 {
-    const int blocks = g.nt < 2048 ? g.nt : 2048;
+    // one dispatch round: as many blocks as the CUs hold at once (LDS-limited:
+    // 3 per CU in FP32, 2 in FP64); the blocks stride over the active tiles
+    const int fit = d.num_cus * (prec == 0 ? 2 : 3);
+    const int blocks = g.nt < fit ? g.nt : fit;
     if (prec == 0)
-        k_spread<double><<<blocks, 64, 0, s>>>(d.base, (const double *)d.wts, (const double *)d.phiSW,
-                                               (const double *)d.gV, d.partials, d.t, d.cnt, d.list, d.acnt,
-                                               d.alist, (double *)d.F, d.stamp, g, m);
+        k_spread<double><<<blocks, 256, 0, s>>>(d.base, (const double *)d.wts, (const double *)d.phiSW,
+                                               (const double *)d.gV, d.partials, d.ctr, d.cnt, d.list, d.acnt,
+                                               d.alist, (double *)d.F, d.stamp, g, m, p);
     else
-        k_spread<float><<<blocks, 64, 0, s>>>(d.base, (const float *)d.wts, (const float *)d.phiSW,
-                                              (const float *)d.gV, d.partials, d.t, d.cnt, d.list, d.acnt,
-                                              d.alist, (float *)d.F, d.stamp, g, m);
+        k_spread<float><<<blocks, 256, 0, s>>>(d.base, (const float *)d.wts, (const float *)d.phiSW,
+                                              (const float *)d.gV, d.partials, d.ctr, d.cnt, d.list, d.acnt,
+                                              d.alist, (float *)d.F, d.stamp, g, m, p);
     return hipGetLastError();
 }
 
-hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s)
+template <typename T, int P>
+static void move_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s)
 {
     const int blocks = (m.nv + 3) / 4;
-    if (prec == 0)
-        k_move<double><<<blocks, 256, 0, s>>>(d.q, (const double *)d.f, (const double *)d.F, (const double *)d.Fext,
-                                              d.stamp, d.t, d.done, d.cnt, d.list, d.acnt, d.alist, d.err, a, m);
-    else
-        k_move<float><<<blocks, 256, 0, s>>>(d.q, (const float *)d.f, (const float *)d.F, (const float *)d.Fext,
-                                             d.stamp, d.t, d.done, d.cnt, d.list, d.acnt, d.alist, d.err, a, m);
-    return hipGetLastError();
+    k_move<T, P><<<blocks, 256, 0, s>>>(d.q, (const T *)d.f, (const T *)d.F, (const T *)d.Fext, d.stamp, d.ctr,
+                                        d.cnt, d.list, d.acnt, d.alist, d.err, a, m);
 }
 
-hipError_t launch_bin(const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s)
-{
-    k_bin<<<(m.nv + 3) / 4, 256, 0, s>>>(d.q, d.t, d.cnt, d.list, d.acnt, d.alist, d.err, g, m);
-    return hipGetLastError();
-}
-
-hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, double *out, hipStream_t s)
+hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
 {
     if (prec == 0)
-        k_get_pops<double><<<lb_grid(g), lb_block(g), 0, s>>>((const double *)d.f, d.t, out, g);
+        p ? move_launch<double, 1>(d, a, m, s) : move_launch<double, 0>(d, a, m, s);
     else
-        k_get_pops<float><<<lb_grid(g), lb_block(g), 0, s>>>((const float *)d.f, d.t, out, g);
+        p ? move_launch<float, 1>(d, a, m, s) : move_launch<float, 0>(d, a, m, s);
     return hipGetLastError();
 }
 
-hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, const double *in, hipStream_t s)
+hipError_t launch_bin(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)
+{
+    k_bin<<<(m.nv + 3) / 4, 256, 0, s>>>(d.q, d.cnt, d.list, d.acnt, d.alist, d.err, g, m, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double *out, hipStream_t s)
 {
     if (prec == 0)
-        k_set_pops<double><<<lb_grid(g), lb_block(g), 0, s>>>((double *)d.f, d.t, in, g);
+        k_get_pops<double><<<lb_grid(g), lb_block(g), 0, s>>>((const double *)d.f, p, out, g);
     else
-        k_set_pops<float><<<lb_grid(g), lb_block(g), 0, s>>>((float *)d.f, d.t, in, g);
+        k_get_pops<float><<<lb_grid(g), lb_block(g), 0, s>>>((const float *)d.f, p, out, g);
     return hipGetLastError();
 }
 
-hipError_t launch_get_fields(int prec, const Dev &d, const LBArgs &a, double *rho, double *u, hipStream_t s)
+hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, int p, const double *in, hipStream_t s)
+{
+    if (prec == 0)
+        k_set_pops<double><<<lb_grid(g), lb_block(g), 0, s>>>((double *)d.f, p, in, g);
+    else
+        k_set_pops<float><<<lb_grid(g), lb_block(g), 0, s>>>((float *)d.f, p, in, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_fields(int prec, const Dev &d, const LBArgs &a, int p, double *rho, double *u, hipStream_t s)
 {
     const uint32_t *stamp = d.q ? d.stamp : nullptr;
     if (prec == 0)
         k_get_fields<double><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const double *)d.f, (const double *)d.F,
-                                                                    (const double *)d.Fext, stamp, d.t, rho, u,
+                                                                    (const double *)d.Fext, stamp, d.ctr, p, rho, u,
                                                                     nullptr, a);
     else
         k_get_fields<float><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const float *)d.f, (const float *)d.F,
-                                                                   (const float *)d.Fext, stamp, d.t, rho, u,
+                                                                   (const float *)d.Fext, stamp, d.ctr, p, rho, u,
                                                                    nullptr, a);
     return hipGetLastError();
 }
 
-hipError_t launch_get_force(int prec, const Dev &d, const LBArgs &a, double *F, hipStream_t s)
+hipError_t launch_get_force(int prec, const Dev &d, const LBArgs &a, int p, double *F, hipStream_t s)
 {
     const uint32_t *stamp = d.q ? d.stamp : nullptr;
     if (prec == 0)
         k_get_fields<double><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const double *)d.f, (const double *)d.F,
-                                                                    (const double *)d.Fext, stamp, d.t, nullptr,
+                                                                    (const double *)d.Fext, stamp, d.ctr, p, nullptr,
                                                                     nullptr, F, a);
     else
         k_get_fields<float><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const float *)d.f, (const float *)d.F,
-                                                                   (const float *)d.Fext, stamp, d.t, nullptr,
+                                                                   (const float *)d.Fext, stamp, d.ctr, p, nullptr,
                                                                    nullptr, F, a);
     return hipGetLastError();
 }

@@ -114,3 +114,18 @@ def test_load_state_rejects_mismatch():
             h.load_state(st)
         with pytest.raises(iblb.IBLBError):
             h.load_state(b"garbage" * 10)
+
+
+@pytest.mark.parametrize("prec", [iblb.FP64, iblb.FP32_DEV])
+def test_graph_with_odd_starts_and_counts(prec):
+    """The two-step graph is only replayed from even times; odd starts and odd
+    counts fall back to single launches.  Any split gives the same state."""
+    w = c1_droplet(eps_over_abar=1.0)
+    with iblb.Simulation(w.domain, w.mesh, precision=prec, graph=True) as g:
+        for n in (1, 4, 3, 2, 1, 5):
+            g.step(n)
+        assert g.t == 16
+        qa, fa = g.vertices(), g.populations()
+    with iblb.Simulation(w.domain, w.mesh, precision=prec, graph=False) as h:
+        h.step(16)
+        assert np.array_equal(h.vertices(), qa) and np.array_equal(h.populations(), fa)
