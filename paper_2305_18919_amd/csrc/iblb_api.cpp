@@ -301,6 +301,7 @@ int read_err(iblb_ctx *c)
         if (e & kErrOverflow) why += " tile list overflow (vertex pile-up);";
         if (e & kErrDensity) why += " density out of range or non-finite;";
         if (e & kErrMach) why += " |u| above 0.3;";
+        if (e & kErrList) why += " invalid vertex index in a tile list;";
         return fail(c, IBLB_E_UNSTABLE, why);
     }
     return IBLB_OK;

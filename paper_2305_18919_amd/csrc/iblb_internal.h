@@ -16,6 +16,7 @@ constexpr int kErrNonFinite = 1;   // a vertex position left the finite range
 constexpr int kErrOverflow = 2;    // a tile list overflowed kTileCap
 constexpr int kErrDensity = 4;     // a node density became non-finite or left (0.5, 2)
 constexpr int kErrMach = 8;        // |u| above 0.3 somewhere
+constexpr int kErrList = 16;       // a tile list held an invalid vertex index
 
 struct alignas(16) Base {
     int x, y, z, ok;  // stencil corner floor(q)-1 (x, y wrapped; z absolute, wrapped if periodic); ok = 1 if finite

@@ -500,78 +500,37 @@ __device__ __forceinline__ double volume_factor(const double *__restrict__ parti
 // ---------------------------------------------------------------------------
 // Spreading, one wavefront per active tile (gather form, no FP atomics)
 // ---------------------------------------------------------------------------
-// Ascending bitonic sort of K * 64 keys (K = 1, 2, 4 or 8) held in registers:
-// element i = k * 64 + lane is v[k] of that lane.  Strides below 64 pair lanes
-// (butterfly shuffles), strides of 64 and more pair registers of one lane.
-__device__ __forceinline__ void cswap_regs(int &a, int &b, bool up)
-{
-    if ((a > b) == up) {
-        const int t = a;
-        a = b;
-        b = t;
-    }
-}
-
-__device__ __forceinline__ void bitonic_sort_regs(int (&v)[8], int K, int lane)
-{
-    const int P = K * 64;
-    for (int s = 2; s <= P; s <<= 1) {
-        for (int j = s >> 1; j > 0; j >>= 1) {
-            if (j < 64) {
-                const bool lower = (lane & j) == 0;
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    if (k < K) {
-                        const int w = __shfl_xor(v[k], j, 64);
-                        const bool up = ((k * 64 + lane) & s) == 0;
-                        v[k] = (lower == up) ? min(v[k], w) : max(v[k], w);
-                    }
-                }
-            } else if (j == 64) {
-#pragma unroll
-                for (int k = 0; k < 8; k += 2)
-                    if (k < K) cswap_regs(v[k], v[k + 1], ((k * 64 + lane) & s) == 0);
-            } else if (j == 128) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    if ((k & 2) == 0 && k < K) cswap_regs(v[k], v[k + 2], ((k * 64 + lane) & s) == 0);
-            } else {  // j == 256
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (k + 4 < K) cswap_regs(v[k], v[k + 4], ((k * 64 + lane) & s) == 0);
-            }
-        }
-    }
-}
-
-// One 256-thread block (four wavefronts) per active tile.  Wavefront 0 sorts
-// the tile's vertex list; all four stage the listed vertices; wavefront w
-// then sums the w-th contiguous quarter of the sorted list for the 64 nodes
-// (one per lane), and the four partial sums are added in wavefront order, so
-// every node's sum has a fixed order.
+// One 256-thread block (four wavefronts) per active tile.  The tile's vertex
+// list is ordered by vertex index (each key's rank is the number of smaller
+// keys: the keys are distinct, so ranks are a permutation); all four
+// wavefronts stage the listed vertices; wavefront w then sums the w-th
+// contiguous quarter of the ordered list for the 64 nodes (one per lane), and
+// the four partial sums are added in wavefront order, so every node's sum has
+// a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
                                                 const double *__restrict__ partials, const uint32_t *__restrict__ ctr,
                                                 uint32_t *cnt, const int *__restrict__ list,
                                                 const uint32_t *__restrict__ acnt, const int *__restrict__ alist,
-                                                T *__restrict__ F, uint32_t *__restrict__ stamp, Grid g, MeshArgs m,
-                                                int p)
+                                                T *__restrict__ F, uint32_t *__restrict__ stamp, int *err, Grid g,
+                                                MeshArgs m, int p)
 {
+    __shared__ int skey[kTileCap];
     __shared__ int sid[kTileCap];
-    __shared__ int sbx[kTileCap], sby[kTileCap], sbz[kTileCap];
+    __shared__ int4 sbase[kTileCap];
     __shared__ T sw[kTileCap * 12];
-    __shared__ T sph[kTileCap * 3];
+    __shared__ T sph[kTileCap * 4];
     __shared__ T part[3][3][64];
     __shared__ int snent;
     __shared__ T skfac;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t t = ctr[p];
     const int buf = p;
     const uint32_t na = acnt[buf];
     if (blockIdx.x >= na)
         return;
-    if (wave == 0) {
+    if (wave == 1) {
         const T kfac = T(volume_factor(partials, m, lane));
         if (lane == 0)
             skfac = kfac;
@@ -579,50 +538,54 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
     const int nv = m.nv;
     for (uint32_t a = blockIdx.x; a < na; a += gridDim.x) {
         const int tile = alist[buf * g.nt + a];
-        if (wave == 0) {
-            // the whole list slot range is read at once, next to its count, and masked after
-            const int *src = list + ((long long)buf * g.nt + tile) * kTileCap;
-            int key[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                key[k] = src[k * 64 + lane];
+        // the whole list slot range is read at once, next to its count; only
+        // thread 0 reads the count, hands it over through LDS and, once every
+        // thread has it, resets it for the buffer's next use
+        const int *src = list + ((long long)buf * g.nt + tile) * kTileCap;
+        const int k0 = src[tid], k1 = src[tid + 256];
+        if (tid == 0) {
             const uint32_t c = cnt[buf * g.nt + tile];
-            const int nent = c < (uint32_t)kTileCap ? (int)c : kTileCap;
-            int K = 1;
-            while (K * 64 < nent)
-                K <<= 1;
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (k * 64 + lane >= nent) key[k] = 0x7fffffff;
-            if (lane == 0) {
-                cnt[buf * g.nt + tile] = 0u;
-                snent = nent;
-            }
-            // ascending vertex index makes the sums order-deterministic
-            bitonic_sort_regs(key, K, lane);
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (k < K) sid[k * 64 + lane] = key[k];
+            snent = c < (uint32_t)kTileCap ? (int)c : kTileCap;
         }
         __syncthreads();
         const int nent = snent;
+        if (tid < nent) skey[tid] = k0;
+        if (tid + 256 < nent) skey[tid + 256] = k1;
+        if (tid == 0)
+            cnt[buf * g.nt + tile] = 0u;
+        __syncthreads();
+        // ascending vertex index makes the sums order-deterministic
+        for (int i = tid; i < nent; i += 256) {
+            const int key = skey[i];
+            int rank = 0;
+#pragma unroll 8
+            for (int j = 0; j < nent; ++j)
+                rank += skey[j] < key ? 1 : 0;
+            sid[rank] = key;
+        }
+        __syncthreads();
         // stage each listed vertex's stencil corner, weights and total force in LDS
-        for (int e = threadIdx.x; e < nent; e += 256) {
+        const T kf = skfac;
+        for (int e = tid; e < nent; e += 256) {
             const int v = sid[e];
+            if ((unsigned)v >= (unsigned)nv) {
+                // never index with a corrupt list entry: contribute nothing, report
+                atomicOr(err, kErrList);
+                sbase[e] = make_int4(-1000000, -1000000, -1000000, 0);
+                for (int k = 0; k < 12; ++k)
+                    sw[e * 12 + k] = T(0);
+                sph[e * 4 + 0] = sph[e * 4 + 1] = sph[e * 4 + 2] = sph[e * 4 + 3] = T(0);
+                continue;
+            }
             const Base bs = base[v];
-            sbx[e] = bs.x;
-            sby[e] = bs.y;
-            sbz[e] = bs.z;
+            sbase[e] = make_int4(bs.x, bs.y, bs.z, 0);
 #pragma unroll
             for (int k = 0; k < 12; ++k)
                 sw[e * 12 + k] = wts[v * 12 + k];
-        }
-        const T kf = skfac;
-        for (int e = threadIdx.x; e < nent; e += 256) {
-            const int v = sid[e];
-            sph[e * 3 + 0] = phiSW[v] - kf * gV[v];
-            sph[e * 3 + 1] = phiSW[nv + v] - kf * gV[nv + v];
-            sph[e * 3 + 2] = phiSW[2 * nv + v] - kf * gV[2 * nv + v];
+            sph[e * 4 + 0] = phiSW[v] - kf * gV[v];
+            sph[e * 4 + 1] = phiSW[nv + v] - kf * gV[nv + v];
+            sph[e * 4 + 2] = phiSW[2 * nv + v] - kf * gV[2 * nv + v];
+            sph[e * 4 + 3] = T(0);
         }
         __syncthreads();
         // this lane's node, and this wavefront's quarter of the list
@@ -634,19 +597,22 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
         const int chunk = (nent + 3) >> 2;
         const int e0 = wave * chunk, e1 = min(nent, e0 + chunk);
         T Fx = T(0), Fy = T(0), Fz = T(0);
+#pragma unroll 4
         for (int e = e0; e < e1; ++e) {
-            int dx = x - sbx[e];
-            if (dx < 0) dx += g.nx;
-            int dy = y - sby[e];
-            if (dy < 0) dy += g.ny;
-            int dz = z - sbz[e];
-            if (!g.walls && dz < 0) dz += g.nz;
-            if ((unsigned)dx < 4u && (unsigned)dy < 4u && (unsigned)dz < 4u) {
-                const T w = sw[e * 12 + dx] * sw[e * 12 + 4 + dy] * sw[e * 12 + 8 + dz];
-                Fx += sph[e * 3 + 0] * w;
-                Fy += sph[e * 3 + 1] * w;
-                Fz += sph[e * 3 + 2] * w;
-            }
+            const int4 b = sbase[e];
+            int dx = x - b.x;
+            dx += dx < 0 ? g.nx : 0;
+            int dy = y - b.y;
+            dy += dy < 0 ? g.ny : 0;
+            int dz = z - b.z;
+            dz += (!g.walls && dz < 0) ? g.nz : 0;
+            const bool in = (unsigned)dx < 4u && (unsigned)dy < 4u && (unsigned)dz < 4u;
+            // outside the stencil: clamp the index and weigh by zero
+            const T w = sw[e * 12 + (dx & 3)] * sw[e * 12 + 4 + (dy & 3)] * sw[e * 12 + 8 + (dz & 3)];
+            const T wi = in ? w : T(0);
+            Fx += sph[e * 4 + 0] * wi;
+            Fy += sph[e * 4 + 1] * wi;
+            Fz += sph[e * 4 + 2] * wi;
         }
         if (wave > 0) {
             part[wave - 1][0][lane] = Fx;
@@ -1084,17 +1050,17 @@ hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &
 hipError_t launch_spread(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)
 {
     // one dispatch round: as many blocks as the CUs hold at once (LDS-limited:
-    // 3 per CU in FP32, 2 in FP64); the blocks stride over the active tiles
-    const int fit = d.num_cus * (prec == 0 ? 2 : 3);
+    // 3 per CU in FP32, 1 in FP64); the blocks stride over the active tiles
+    const int fit = d.num_cus * (prec == 0 ? 1 : 3);
     const int blocks = g.nt < fit ? g.nt : fit;
     if (prec == 0)
         k_spread<double><<<blocks, 256, 0, s>>>(d.base, (const double *)d.wts, (const double *)d.phiSW,
                                                (const double *)d.gV, d.partials, d.ctr, d.cnt, d.list, d.acnt,
-                                               d.alist, (double *)d.F, d.stamp, g, m, p);
+                                               d.alist, (double *)d.F, d.stamp, d.err, g, m, p);
     else
         k_spread<float><<<blocks, 256, 0, s>>>(d.base, (const float *)d.wts, (const float *)d.phiSW,
                                               (const float *)d.gV, d.partials, d.ctr, d.cnt, d.list, d.acnt,
-                                              d.alist, (float *)d.F, d.stamp, g, m, p);
+                                              d.alist, (float *)d.F, d.stamp, d.err, g, m, p);
     return hipGetLastError();
 }
 
