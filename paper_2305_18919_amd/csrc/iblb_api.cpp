@@ -32,7 +32,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 struct Layout {
     // byte offsets into the workspace; domain part then mesh part
     size_t f, F, stamp, ctr, err, scratch, dom_end;
-    size_t q, Xref, faces, fref, inc_off, inc4, phiSW, gV, base, wts, partials, cnt, list, acnt, alist, mesh_end;
+    size_t q, Xref, faces, fref, inc_off, inc4, phiSW, gV, base, wts, partials, cnt, list, acnt, alist, act, mesh_end;
 };
 
 Grid make_grid(const iblb_domain_desc &d)
@@ -84,6 +84,7 @@ Layout make_layout(const Grid &g, size_t ts, int nv, int nf)
     L.list = take((size_t)2 * g.nt * kTileCap * 4);
     L.acnt = take(2 * 4);
     L.alist = take((size_t)2 * g.nt * 4);
+    L.act = take((size_t)g.nt * 4);
     L.mesh_end = o;
     return L;
 }
@@ -235,20 +236,30 @@ hipEvent_t get_event(iblb_ctx *c)
     return e;
 }
 
-hipError_t launch_kernel(iblb_ctx *c, int which, int p)
+hipError_t launch_kernel(iblb_ctx *c, int which, int p, hipStream_t st)
 {
     const Dev &d = c->d;
     switch (which) {
-    case K_FORCES: return launch_forces(c->prec, d, c->g, c->m, c->stream);
-    case K_SPREAD: return launch_spread(c->prec, d, c->g, c->m, p, c->stream);
-    case K_LB: return launch_lb(c->prec, d, c->lb, p, c->has_mesh ? 0 : 1, c->stream);
-    default: return launch_move(c->prec, d, c->lb, c->m, p, c->stream);
+    case K_FORCES: return launch_forces(c->prec, d, c->g, c->m, st);
+    case K_SPREAD: return launch_spread(c->prec, d, c->lb, c->m, p, st);
+    case K_LB: return launch_lb(c->prec, d, c->lb, p, c->has_mesh ? 1 : 0, st);
+    default: return launch_move(c->prec, d, c->lb, c->m, p, st);
     }
 }
 
-// one step of parity p: forces -> spread -> lb -> move (mesh) or lb alone
+// One step of parity p.  With a mesh: one dispatch computes the interface
+// forces and the bulk LB (nodes outside the active tiles) side by side, then
+// the spread updates the active tiles (force + LB), then the move.  Timed
+// steps launch forces and bulk LB as separate kernels so that each one's
+// duration can be read.
 hipError_t enqueue_step(iblb_ctx *c, int p, bool timed)
 {
+    if (c->has_mesh && !timed) {
+        hipError_t e = launch_bulk_forces(c->prec, c->d, c->lb, c->m, p, c->stream);
+        if (e == hipSuccess) e = launch_kernel(c, K_SPREAD, p, c->stream);
+        if (e == hipSuccess) e = launch_kernel(c, K_MOVE, p, c->stream);
+        return e;
+    }
     int seq[4], ns = 0;
     if (c->has_mesh) {
         seq[ns++] = K_FORCES;
@@ -265,7 +276,7 @@ hipError_t enqueue_step(iblb_ctx *c, int p, bool timed)
             e1 = get_event(c);
             (void)hipEventRecord(e0, c->stream);
         }
-        hipError_t e = launch_kernel(c, seq[k], p);
+        hipError_t e = launch_kernel(c, seq[k], p, c->stream);
         if (e != hipSuccess) return e;
         if (timed) {
             (void)hipEventRecord(e1, c->stream);
@@ -323,6 +334,7 @@ int rebuild_lists(iblb_ctx *c)
 {
     HIP_TRY(c, hipMemsetAsync(c->d.cnt, 0, (size_t)2 * c->g.nt * 4, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d.acnt, 0, 2 * 4, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d.act, 0, (size_t)c->g.nt * 4, c->stream));
     HIP_TRY(c, launch_bin(c->d, c->g, c->m, (int)(c->t & 1), c->stream));
     return IBLB_OK;
 }
@@ -376,6 +388,7 @@ int iblb_create(const iblb_domain_desc *dom, void *dev_workspace, size_t workspa
         if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(IBLB_E_DEVICE);
         c->own_stream = true;
     }
+
     if (dev_workspace) {
         if (workspace_bytes < c->L.dom_end) return bail(IBLB_E_INVAL);
         c->ws = (char *)dev_workspace;
@@ -511,6 +524,7 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     d.list = (int *)(mb + L.list);
     d.acnt = (uint32_t *)(mb + L.acnt);
     d.alist = (int *)(mb + L.alist);
+    d.act = (uint32_t *)(mb + L.act);
     HIP_TRY(c, hipMemcpyAsync(d.q, qs.data(), qs.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d.Xref, Xs.data(), Xs.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d.faces, fs.data(), fs.size() * 4, hipMemcpyHostToDevice, c->stream));

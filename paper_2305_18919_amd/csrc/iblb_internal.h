@@ -75,6 +75,7 @@ struct Dev {
     int *list;            // [2][nt][kTileCap]
     uint32_t *acnt;       // [2]
     int *alist;           // [2][nt]
+    uint32_t *act;        // [nt] step+1 for which the tile is active (listed)
     double *scratch;      // small FP64 scratch for queries (64 doubles)
     int num_cus;          // compute units of the device (launch sizing)
 };
@@ -82,9 +83,14 @@ struct Dev {
 // launchers (iblb_kernels.hip); precision 0 = FP64, 1 = FP32
 hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hipStream_t s);
 // p = t & 1 of the step (or of the current time for the debug kernels)
-hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int advance, hipStream_t s);
+// bulk != 0: only the nodes outside this step's active tiles (mesh present);
+// bulk == 0: every node, and the kernel advances the step counter (no mesh)
+hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, hipStream_t s);
 hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s);
-hipError_t launch_spread(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s);
+// forces and bulk LB in one dispatch (the two are independent within a step)
+hipError_t launch_bulk_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);
+// spreading of the active tiles followed by their LB update
+hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);
 hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);
 hipError_t launch_bin(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s);
 // debug / query kernels

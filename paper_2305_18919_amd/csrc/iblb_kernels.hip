@@ -183,10 +183,11 @@ __device__ __forceinline__ void load_pops(const T *__restrict__ f, const Grid &g
 // ---------------------------------------------------------------------------
 // LB: AA-pattern stream + collide
 // ---------------------------------------------------------------------------
+// LB update of node (x, y, zf) with the immersed-boundary force density
+// (fx, fy, fz) of this step; body force and external field are added here.
 template <typename T, bool ODD>
-__device__ __forceinline__ void lb_node(T *__restrict__ f, const T *__restrict__ Fib, const T *__restrict__ Fext,
-                                        const uint32_t *__restrict__ stamp, uint32_t t, int *err, const LBArgs &a,
-                                        int x, int y, int zf)
+__device__ __forceinline__ void lb_node(T *__restrict__ f, const T *__restrict__ Fext, int *err, const LBArgs &a,
+                                        int x, int y, int zf, T fx, T fy, T fz)
 {
     const Grid &g = a.g;
     const long long n = g.n;
@@ -207,13 +208,8 @@ __device__ __forceinline__ void lb_node(T *__restrict__ f, const T *__restrict__
         }
     }
 
-    // force density: body force + IB force (tile stamped for this step) + external
-    T Fx = T(a.body[0]), Fy = T(a.body[1]), Fz = T(a.body[2]);
-    if (stamp != nullptr && stamp[tile_of(g, x, y, zf)] == t + 1u) {
-        Fx += Fib[me];
-        Fy += Fib[n + me];
-        Fz += Fib[2 * n + me];
-    }
+    // force density: body force + IB force + external
+    T Fx = T(a.body[0]) + fx, Fy = T(a.body[1]) + fy, Fz = T(a.body[2]) + fz;
     if (a.has_fext) {
         Fx += Fext[me];
         Fy += Fext[n + me];
@@ -263,24 +259,28 @@ __device__ __forceinline__ void lb_node(T *__restrict__ f, const T *__restrict__
     }
 }
 
+// LB over the fluid nodes.  Without a mesh (act == null) every node, and the
+// kernel advances the step counter.  With a mesh only the nodes outside this
+// step's active tiles (act[tile] != t + 1): it runs concurrently with the
+// force and spreading kernels, which update the active tiles themselves.
+// In the AA pattern each node reads and writes only its own 19 slots, so the
+// two node sets never touch the same memory.
 template <typename T, bool ODD>
-__global__ __launch_bounds__(256) void k_lb(T *__restrict__ f, const T *__restrict__ Fib,
-                                            const T *__restrict__ Fext, const uint32_t *__restrict__ stamp,
-                                            uint32_t *ctr, uint32_t *acnt, int *err, LBArgs a, int advance)
+__global__ __launch_bounds__(256) void k_lb(T *__restrict__ f, const T *__restrict__ Fext,
+                                            const uint32_t *__restrict__ act, uint32_t *ctr, int *err, LBArgs a)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int zf = blockIdx.z;
     const uint32_t t = ctr[ODD ? 1 : 0];
-    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-        if (acnt != nullptr)
-            acnt[ODD ? 1 : 0] = 0u;  // the spread of this step has consumed its tile list
-        if (advance)
-            ctr[ODD ? 0 : 1] = t + 1u;
-    }
+    if (act == nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 &&
+        threadIdx.y == 0)
+        ctr[ODD ? 0 : 1] = t + 1u;
     if (x >= a.g.nx || y >= a.g.ny)
         return;
-    lb_node<T, ODD>(f, Fib, Fext, stamp, t, err, a, x, y, zf);
+    if (act != nullptr && act[tile_of(a.g, x, y, zf)] == t + 1u)
+        return;
+    lb_node<T, ODD>(f, Fext, err, a, x, y, zf, T(0), T(0), T(0));
 }
 
 template <typename T>
@@ -348,16 +348,16 @@ __device__ __forceinline__ double volume_change(const double *__restrict__ X, in
 // Eight lanes per vertex (32 vertices per 256-thread block); lane k of a
 // vertex handles its incident faces k, k + 8, ...; the group sums by butterfly.
 template <typename T>
-__global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, const double *__restrict__ Xref,
-                                                const int4 *__restrict__ inc4, const int *__restrict__ inc_off,
-                                                const double *__restrict__ fref, T *__restrict__ phiSW,
-                                                T *__restrict__ gVout, Base *__restrict__ base,
-                                                T *__restrict__ wts, double *__restrict__ partials, int *err,
-                                                Grid g, MeshArgs m)
+__device__ __forceinline__ void forces_block(int blk, const double *__restrict__ q, const double *__restrict__ Xref,
+                                             const int4 *__restrict__ inc4, const int *__restrict__ inc_off,
+                                             const double *__restrict__ fref, T *__restrict__ phiSW,
+                                             T *__restrict__ gVout, Base *__restrict__ base, T *__restrict__ wts,
+                                             double *__restrict__ partials, int *err, const Grid &g,
+                                             const MeshArgs &m)
 {
     __shared__ double red[2][256];
     const int sub = threadIdx.x & 7;
-    const int v = blockIdx.x * 32 + (threadIdx.x >> 3);
+    const int v = blk * 32 + (threadIdx.x >> 3);
     const int nv = m.nv, nf = m.nf;
     double dvol = 0.0, darea = 0.0;
     T fs[3] = {T(0), T(0), T(0)};
@@ -481,9 +481,52 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, co
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        partials[blockIdx.x] = red[0][0];
-        partials[m.nparts + blockIdx.x] = red[1][0];
+        partials[blk] = red[0][0];
+        partials[m.nparts + blk] = red[1][0];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, const double *__restrict__ Xref,
+                                                const int4 *__restrict__ inc4, const int *__restrict__ inc_off,
+                                                const double *__restrict__ fref, T *__restrict__ phiSW,
+                                                T *__restrict__ gVout, Base *__restrict__ base,
+                                                T *__restrict__ wts, double *__restrict__ partials, int *err,
+                                                Grid g, MeshArgs m)
+{
+    forces_block<T>(blockIdx.x, q, Xref, inc4, inc_off, fref, phiSW, gVout, base, wts, partials, err, g, m);
+}
+
+// The first m.nparts blocks compute the interface forces (latency-bound), the
+// rest run the bulk LB (bandwidth-bound) in the same dispatch, so the two
+// overlap without a second queue.  The bulk blocks use the LB kernel's tiling
+// (lb_block_x wide, 256 / lb_block_x rows), numbered x fastest.
+template <typename T, bool ODD>
+__global__ __launch_bounds__(256) void k_bulk_forces(const double *__restrict__ q, const double *__restrict__ Xref,
+                                                     const int4 *__restrict__ inc4, const int *__restrict__ inc_off,
+                                                     const double *__restrict__ fref, T *__restrict__ phiSW,
+                                                     T *__restrict__ gVout, Base *__restrict__ base,
+                                                     T *__restrict__ wts, double *__restrict__ partials,
+                                                     T *__restrict__ f, const T *__restrict__ Fext,
+                                                     const uint32_t *__restrict__ act, const uint32_t *__restrict__ ctr,
+                                                     int *err, LBArgs a, MeshArgs m, int bxw, int nbx, int nby)
+{
+    if ((int)blockIdx.x < m.nparts) {
+        forces_block<T>(blockIdx.x, q, Xref, inc4, inc_off, fref, phiSW, gVout, base, wts, partials, err, a.g, m);
+        return;
+    }
+    const int b = blockIdx.x - m.nparts;
+    const int zf = b / (nbx * nby);
+    const int rem = b - zf * nbx * nby;
+    const int byi = rem / nbx, bxi = rem - byi * nbx;
+    const int x = bxi * bxw + (int)(threadIdx.x % (unsigned)bxw);
+    const int y = byi * (256 / bxw) + (int)(threadIdx.x / (unsigned)bxw);
+    const uint32_t t = ctr[ODD ? 1 : 0];
+    if (x >= a.g.nx || y >= a.g.ny)
+        return;
+    if (act[tile_of(a.g, x, y, zf)] == t + 1u)
+        return;
+    lb_node<T, ODD>(f, Fext, err, a, x, y, zf, T(0), T(0), T(0));
 }
 
 // k_V (V - V0)/V0 from the force-kernel partials, summed by one wavefront in a
@@ -507,15 +550,17 @@ __device__ __forceinline__ double volume_factor(const double *__restrict__ parti
 // contiguous quarter of the ordered list for the 64 nodes (one per lane), and
 // the four partial sums are added in wavefront order, so every node's sum has
 // a fixed order.
-template <typename T>
+template <typename T, int P>
 __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
                                                 const double *__restrict__ partials, const uint32_t *__restrict__ ctr,
                                                 uint32_t *cnt, const int *__restrict__ list,
                                                 const uint32_t *__restrict__ acnt, const int *__restrict__ alist,
-                                                T *__restrict__ F, uint32_t *__restrict__ stamp, int *err, Grid g,
-                                                MeshArgs m, int p)
+                                                T *__restrict__ F, uint32_t *__restrict__ stamp, T *__restrict__ f,
+                                                const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m)
 {
+    const Grid &g = a.g;
+    const int p = P;
     __shared__ int skey[kTileCap];
     __shared__ int sid[kTileCap];
     __shared__ int4 sbase[kTileCap];
@@ -536,8 +581,8 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
             skfac = kfac;
     }
     const int nv = m.nv;
-    for (uint32_t a = blockIdx.x; a < na; a += gridDim.x) {
-        const int tile = alist[buf * g.nt + a];
+    for (uint32_t ai = blockIdx.x; ai < na; ai += gridDim.x) {
+        const int tile = alist[buf * g.nt + ai];
         // the whole list slot range is read at once, next to its count; only
         // thread 0 reads the count, hands it over through LDS and, once every
         // thread has it, resets it for the buffer's next use
@@ -631,6 +676,8 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
                 F[me] = Fx;
                 F[g.n + me] = Fy;
                 F[2 * g.n + me] = Fz;
+                // the LB update of this active node, with its force in hand
+                lb_node<T, P == 1>(f, Fext, err, a, x, y, zf, Fx, Fy, Fz);
             }
             if (lane == 0)
                 stamp[tile] = t + 1u;
@@ -645,7 +692,8 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
 // Called by all 64 lanes of the vertex's wavefront, lane = stencil offset.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void list_vertex(int v, double qx, double qy, double qz, int lane, const Grid &g,
-                                            uint32_t *cnt, int *list, uint32_t *acnt, int *alist, int buf, int *err)
+                                            uint32_t *cnt, int *list, uint32_t *acnt, int *alist, uint32_t *act,
+                                            uint32_t step, int buf, int *err)
 {
     if (!(fabs(qx) < 1e6 && fabs(qy) < 1e6 && fabs(qz) < 1e6)) {
         if (lane == 0)
@@ -678,6 +726,7 @@ __device__ __forceinline__ void list_vertex(int v, double qx, double qy, double 
         if (slot == 0u) {
             const uint32_t a = atomicAdd(&acnt[buf], 1u);
             alist[buf * g.nt + a] = tile;
+            act[tile] = step + 1u;
         }
         if (slot < (uint32_t)kTileCap)
             list[((long long)buf * g.nt + tile) * kTileCap + slot] = v;
@@ -692,15 +741,17 @@ template <typename T, int P>
 __global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *__restrict__ f,
                                               const T *__restrict__ Fib, const T *__restrict__ Fext,
                                               const uint32_t *__restrict__ stamp, uint32_t *ctr, uint32_t *cnt,
-                                              int *list, uint32_t *acnt, int *alist, int *err, LBArgs a,
-                                              MeshArgs m)
+                                              int *list, uint32_t *acnt, int *alist, uint32_t *act, int *err,
+                                              LBArgs a, MeshArgs m)
 {
     const Grid &g = a.g;
     const int lane = threadIdx.x & 63;
     const int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t t = ctr[P];
-    if (blockIdx.x == 0 && threadIdx.x == 0)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctr[1 - P] = t + 1u;
+        acnt[P] = 0u;  // this step's tile list has been consumed
+    }
     if (v < m.nv) {
         const int nv = m.nv;
         const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
@@ -732,11 +783,14 @@ __global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *_
                     if (cz(i) != 0) mz += T(cz(i)) * d[i];
                 }
                 const long long me = nidx(g, x, y, zf);
+                // F is read unconditionally and used if the tile carries this step's stamp
+                const T fibx = Fib[me], fiby = Fib[g.n + me], fibz = Fib[2 * g.n + me];
+                const bool fresh = stamp[tile_of(g, x, y, zf)] == t + 1u;
                 T Fx = T(a.body[0]), Fy = T(a.body[1]), Fz = T(a.body[2]);
-                if (stamp[tile_of(g, x, y, zf)] == t + 1u) {
-                    Fx += Fib[me];
-                    Fy += Fib[g.n + me];
-                    Fz += Fib[2 * g.n + me];
+                if (fresh) {
+                    Fx += fibx;
+                    Fy += fiby;
+                    Fz += fibz;
                 }
                 if (a.has_fext) {
                     Fx += Fext[me];
@@ -755,7 +809,7 @@ __global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *_
                 q[nv + v] = nqy;
                 q[2 * nv + v] = nqz;
             }
-            list_vertex(v, nqx, nqy, nqz, lane, g, cnt, list, acnt, alist, 1 - P, err);
+            list_vertex(v, nqx, nqy, nqz, lane, g, cnt, list, acnt, alist, act, t + 1u, 1 - P, err);
         } else if (lane == 0) {
             atomicOr(err, kErrNonFinite);
         }
@@ -763,13 +817,14 @@ __global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *_
 }
 
 __global__ __launch_bounds__(256) void k_bin(const double *__restrict__ q, uint32_t *cnt, int *list,
-                                             uint32_t *acnt, int *alist, int *err, Grid g, MeshArgs m, int p)
+                                             uint32_t *acnt, int *alist, uint32_t *act, const uint32_t *ctr,
+                                             int *err, Grid g, MeshArgs m, int p)
 {
     const int lane = threadIdx.x & 63;
     const int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (v >= m.nv)
         return;
-    list_vertex(v, q[v], q[m.nv + v], q[2 * m.nv + v], lane, g, cnt, list, acnt, alist, p, err);
+    list_vertex(v, q[v], q[m.nv + v], q[2 * m.nv + v], lane, g, cnt, list, acnt, alist, act, ctr[p], p, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -1013,25 +1068,19 @@ hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hip
     return hipGetLastError();
 }
 
-hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int advance, hipStream_t s)
+template <typename T, bool ODD>
+static void lb_launch(const Dev &d, const LBArgs &a, bool bulk, hipStream_t s)
 {
-    const uint32_t *stamp = d.q ? d.stamp : nullptr;
-    const dim3 gr = lb_grid(a.g), bl = lb_block(a.g);
-    if (prec == 0) {
-        if (p)
-            k_lb<double, true><<<gr, bl, 0, s>>>((double *)d.f, (const double *)d.F, (const double *)d.Fext, stamp,
-                                                  d.ctr, d.acnt, d.err, a, advance);
-        else
-            k_lb<double, false><<<gr, bl, 0, s>>>((double *)d.f, (const double *)d.F, (const double *)d.Fext, stamp,
-                                                   d.ctr, d.acnt, d.err, a, advance);
-    } else {
-        if (p)
-            k_lb<float, true><<<gr, bl, 0, s>>>((float *)d.f, (const float *)d.F, (const float *)d.Fext, stamp,
-                                                 d.ctr, d.acnt, d.err, a, advance);
-        else
-            k_lb<float, false><<<gr, bl, 0, s>>>((float *)d.f, (const float *)d.F, (const float *)d.Fext, stamp,
-                                                  d.ctr, d.acnt, d.err, a, advance);
-    }
+    k_lb<T, ODD><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((T *)d.f, (const T *)d.Fext, bulk ? d.act : nullptr, d.ctr,
+                                                          d.err, a);
+}
+
+hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, hipStream_t s)
+{
+    if (prec == 0)
+        p ? lb_launch<double, true>(d, a, bulk, s) : lb_launch<double, false>(d, a, bulk, s);
+    else
+        p ? lb_launch<float, true>(d, a, bulk, s) : lb_launch<float, false>(d, a, bulk, s);
     return hipGetLastError();
 }
 
@@ -1047,20 +1096,43 @@ hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &
     return hipGetLastError();
 }
 
-hipError_t launch_spread(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)
+template <typename T, bool ODD>
+static void bulk_forces_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s)
+{
+    const dim3 bl = lb_block(a.g), gr = lb_grid(a.g);
+    const int nblocks = m.nparts + (int)(gr.x * gr.y * gr.z);
+    k_bulk_forces<T, ODD><<<nblocks, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.inc_off, d.fref, (T *)d.phiSW, (T *)d.gV,
+                                                   d.base, (T *)d.wts, d.partials, (T *)d.f, (const T *)d.Fext,
+                                                   d.act, d.ctr, d.err, a, m, (int)bl.x, (int)gr.x, (int)gr.y);
+}
+
+hipError_t launch_bulk_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
+{
+    if (prec == 0)
+        p ? bulk_forces_launch<double, true>(d, a, m, s) : bulk_forces_launch<double, false>(d, a, m, s);
+    else
+        p ? bulk_forces_launch<float, true>(d, a, m, s) : bulk_forces_launch<float, false>(d, a, m, s);
+    return hipGetLastError();
+}
+
+template <typename T, int P>
+static void spread_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int blocks, hipStream_t s)
+{
+    k_spread<T, P><<<blocks, 256, 0, s>>>(d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV, d.partials,
+                                          d.ctr, d.cnt, d.list, d.acnt, d.alist, (T *)d.F, d.stamp, (T *)d.f,
+                                          (const T *)d.Fext, d.err, a, m);
+}
+
+hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
 {
     // one dispatch round: as many blocks as the CUs hold at once (LDS-limited:
     // 3 per CU in FP32, 1 in FP64); the blocks stride over the active tiles
     const int fit = d.num_cus * (prec == 0 ? 1 : 3);
-    const int blocks = g.nt < fit ? g.nt : fit;
+    const int blocks = a.g.nt < fit ? a.g.nt : fit;
     if (prec == 0)
-        k_spread<double><<<blocks, 256, 0, s>>>(d.base, (const double *)d.wts, (const double *)d.phiSW,
-                                               (const double *)d.gV, d.partials, d.ctr, d.cnt, d.list, d.acnt,
-                                               d.alist, (double *)d.F, d.stamp, d.err, g, m, p);
+        p ? spread_launch<double, 1>(d, a, m, blocks, s) : spread_launch<double, 0>(d, a, m, blocks, s);
     else
-        k_spread<float><<<blocks, 256, 0, s>>>(d.base, (const float *)d.wts, (const float *)d.phiSW,
-                                              (const float *)d.gV, d.partials, d.ctr, d.cnt, d.list, d.acnt,
-                                              d.alist, (float *)d.F, d.stamp, d.err, g, m, p);
+        p ? spread_launch<float, 1>(d, a, m, blocks, s) : spread_launch<float, 0>(d, a, m, blocks, s);
     return hipGetLastError();
 }
 
@@ -1069,7 +1141,7 @@ static void move_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, hipStr
 {
     const int blocks = (m.nv + 3) / 4;
     k_move<T, P><<<blocks, 256, 0, s>>>(d.q, (const T *)d.f, (const T *)d.F, (const T *)d.Fext, d.stamp, d.ctr,
-                                        d.cnt, d.list, d.acnt, d.alist, d.err, a, m);
+                                        d.cnt, d.list, d.acnt, d.alist, d.act, d.err, a, m);
 }
 
 hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
@@ -1083,7 +1155,7 @@ hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &
 
 hipError_t launch_bin(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)
 {
-    k_bin<<<(m.nv + 3) / 4, 256, 0, s>>>(d.q, d.cnt, d.list, d.acnt, d.alist, d.err, g, m, p);
+    k_bin<<<(m.nv + 3) / 4, 256, 0, s>>>(d.q, d.cnt, d.list, d.acnt, d.alist, d.act, d.ctr, d.err, g, m, p);
     return hipGetLastError();
 }
 
