@@ -6,13 +6,24 @@ coated capsule alpha = abar(1,1,1) at Ca = 0.05 meshed as a level-4 icosphere
 (2562 vertices, 5120 faces, R = 10), FP32 deviation populations with FP64
 positions and volume reductions.  Synthetic seeded inputs, no datasets.
 
-Timed region: K steps replayed from a captured hipGraph, inputs resident in
+Timed region: K steps replayed from captured hipGraphs, inputs resident in
 HBM, bracketed by torch.cuda.synchronize().  value = fluid nodes x steps /
-seconds / 1e6 (MLUPS) for the whole step (forces, spreading, LB, interpolation
-and move).  A second, instrumented pass times every kernel with hipEvents on
-the library's stream; the LB kernel's average duration gives the achieved
-algorithmic HBM bandwidth (38 population accesses of 4 bytes per fluid node).
-The FP64 CPU oracle is timed on a bounded sample of the same workload.
+seconds / 1e6 (MLUPS) for the whole step (forces, spreading, LB, moments,
+interpolation and move).
+
+roofline: the LB kernel k_lb, the step's bandwidth-bound work, timed in a
+pass of the same domain without a mesh (so that it updates every fluid node):
+hipEvents on the library's stream around a run of graph-replayed launches,
+achieved = fluid nodes x 38 population accesses x bytes per population /
+average launch time; traffic = HBM bytes per launch from the committed
+copy-calibrated FETCH_SIZE/WRITE_SIZE counter runs, while the kernel source is
+the one they were taken on (else null).  A further pass times every kernel of the coupled step
+with hipEvents around each launch ("kernels"; these include the per-launch
+event overhead).  The FP64 CPU oracle is timed on a bounded sample of the same
+workload.
+
+--pass lb / --pass copy run only the LB-only pass, or a plain device copy of
+--copy-mib MiB, for hardware-counter runs.
 """
 from __future__ import annotations
 
@@ -68,15 +79,73 @@ def cpu_baseline(w, budget_s: float):
             "sample": f"{w.name}: {steps} FP64 oracle steps after 2 warm-up steps ({dt:.1f} s)"}
 
 
+def lb_traffic(workload_name: str, prec: int):
+    """HBM bytes per k_lb launch from the committed FETCH_SIZE/WRITE_SIZE runs
+    (copy-calibrated), or None when they were taken on another kernel source
+    or another workload."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_lb_shear64_f32_counters.json")
+    if workload_name != "shear64_capsule_f32" or prec != 1 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
+def lb_roofline(dom, prec: int, launches: int, traffic=None):
+    """k_lb over every fluid node of the domain (no mesh), graph-replayed;
+    hipEvents on the library stream around `launches` consecutive launches."""
+    import torch
+    from paper_2305_18919_amd import iblb
+    launches = max(16, launches // 16 * 16)
+    with iblb.Simulation(dom, None, precision=prec, graph=True) as sim:
+        sim.step(64)
+        sim.sync()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.step(launches)
+        e1.record(sim.stream)
+        e1.synchronize()
+        sim.sync()
+        us = e0.elapsed_time(e1) * 1e3 / launches
+    alg = dom.n_fluid * lb_bytes_per_node(prec)
+    achieved = alg / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_lb (every fluid node, no mesh)", "alg_bytes_per_launch": alg,
+            "launches": launches, "avg_us": round(us, 3)}
+
+
+def copy_pass(mib: int, reps: int):
+    """A plain device-to-device copy of `mib` MiB, `reps` times (counter calibration)."""
+    import torch
+    n = mib * (1 << 20)
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"pass": "copy", "bytes_read_per_copy": n, "bytes_written_per_copy": n, "copies": reps}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="shear64")
-    ap.add_argument("--timed-steps", type=int, default=500, help="steps of the hipEvent-instrumented pass")
+    ap.add_argument("--timed-steps", type=int, default=500, help="steps of the per-kernel hipEvent pass")
+    ap.add_argument("--lb-launches", type=int, default=1600, help="launches of the LB-only roofline pass")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pass", dest="only", choices=["lb", "copy"], default=None)
+    ap.add_argument("--copy-mib", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
@@ -88,6 +157,14 @@ def main():
 
     w, prec = workload(args.workload)
     dom, mesh = w.domain, w.mesh
+    if args.only == "copy":
+        copy_pass(args.copy_mib, 10)
+        return
+    if args.only == "lb":
+        print(json.dumps({"pass": "lb", "workload": w.name, "roofline": lb_roofline(dom, prec, args.lb_launches)}),
+              flush=True)
+        return
+
     sim = iblb.Simulation(dom, mesh, precision=prec, graph=True)
     sim.step(args.warmup)
     sim.sync()
@@ -100,7 +177,7 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     mlups = dom.n_fluid * args.steps / dt / 1e6
 
-    # instrumented pass: per-kernel hipEvent durations on the library stream
+    # per-kernel hipEvent pass on the library stream
     sim.set_timing(True)
     sim.reset_timing()
     sim.step(args.timed_steps)
@@ -111,12 +188,7 @@ def main():
         if n:
             kernels[name] = {"avg_us": round(ms * 1e3 / n, 3), "launches": n}
     sim.set_timing(False)
-    lb_us = kernels["lb"]["avg_us"]
-    lb_alg = dom.n_fluid * lb_bytes_per_node(prec)
-    achieved = lb_alg / (lb_us * 1e-6) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_lb", "alg_bytes_per_launch": lb_alg, "avg_us": lb_us}
+    kernels["active_tile_nodes"] = sim.active_nodes()
     sim.close()
 
     out = {
@@ -126,7 +198,7 @@ def main():
         "config": {"workload": w.name, "grid": [dom.nx, dom.ny, dom.nz], "fluid_nodes": dom.n_fluid,
                    "vertices": mesh.n_vertices, "faces": mesh.n_faces, "tau": dom.tau,
                    "alpha": list(mesh.alpha), "positions": "f64", "launch": "hipGraph, 16 steps per replay"},
-        "roofline": roof,
+        "roofline": lb_roofline(dom, prec, args.lb_launches, lb_traffic(w.name, prec)),
         "kernels": kernels,
     }
     if not args.no_cpu:

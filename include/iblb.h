@@ -80,7 +80,7 @@ typedef struct {
 } iblb_domain_desc;
 
 typedef struct {
-    int32_t n_vertices, n_faces;
+    int32_t n_vertices, n_faces; /* 4 <= n_vertices <= 65536 */
     const double *vertices;     /* host [n_vertices][3]: initial positions q(0) */
     const double *ref_vertices; /* host [n_vertices][3]: stress-free shape; NULL => vertices */
     const int32_t *faces;       /* host [n_faces][3]: closed surface, outward counter-clockwise */
@@ -113,7 +113,9 @@ int iblb_create(const iblb_domain_desc *dom, void *dev_workspace, size_t workspa
  * ref_vertices), and bins the vertices for the first step.  V - V0 is later
  * evaluated face by face, expanded exactly in the displacements from
  * ref_vertices.  *mesh_id = 0.  Fails with IBLB_E_STATE if a mesh exists or a
- * debug force field is set. */
+ * debug force field is set, IBLB_E_INVAL above 65536 vertices (the spreading
+ * keeps one bit per vertex for every 4x4x4 tile of the lattice:
+ * tiles x ceil(n_vertices / 64) x 8 bytes of device memory). */
 int iblb_add_mesh(iblb_ctx *ctx, const iblb_mesh_desc *mesh, int32_t *mesh_id);
 
 /* Enqueue n_steps full IB-LB steps on the context stream; returns without
@@ -182,10 +184,19 @@ int iblb_load_state(iblb_ctx *ctx, const void *host_buf, size_t bytes);
  * hipEvents per kernel on the context stream, accumulated until read. */
 int iblb_set_graph(iblb_ctx *ctx, int32_t graph);
 int iblb_set_timing(iblb_ctx *ctx, int32_t timing);
-/* Per-kernel accumulated event time.  names: "forces", "spread", "lb",
- * "move".  Returns total milliseconds and launch count; resets nothing. */
+/* Per-kernel accumulated event time.  names: "forces" (interface forces and
+ * the list of active tiles), "spread" (spreading and the LB of the active
+ * tiles), "lb" (LB of the other nodes), "move" (u(t+1) on the active tiles,
+ * interpolation and move).  Returns total milliseconds and launch count;
+ * resets nothing. */
 int iblb_kernel_time(iblb_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 int iblb_reset_timing(iblb_ctx *ctx);
+
+/* Fluid nodes in the active tiles of the last completed step, the 4x4x4
+ * tiles reached by some vertex stencil (their LB runs with the spreading, the
+ * "lb" kernel updates the rest); 0 without a mesh or before the first step.
+ * Synchronises. */
+int iblb_active_nodes(iblb_ctx *ctx, int64_t *n);
 
 const char *iblb_last_error(const iblb_ctx *ctx);
 int iblb_destroy(iblb_ctx *ctx);

@@ -32,7 +32,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 struct Layout {
     // byte offsets into the workspace; domain part then mesh part
     size_t f, F, stamp, ctr, err, scratch, dom_end;
-    size_t q, Xref, faces, fref, inc_off, inc4, phiSW, gV, base, wts, partials, cnt, list, acnt, alist, act, mesh_end;
+    size_t q, Xref, faces, fref, inc_off, inc4, U, phiSW, gV, base, wts, partials, mask, act, acnt, alist, mesh_end;
 };
 
 Grid make_grid(const iblb_domain_desc &d)
@@ -75,16 +75,16 @@ Layout make_layout(const Grid &g, size_t ts, int nv, int nf)
     L.fref = take((size_t)5 * nf * 8);
     L.inc_off = take((size_t)(nv + 1) * 4);
     L.inc4 = take((size_t)3 * nf * 16);
+    L.U = take(nv ? (size_t)3 * g.n * ts : 0);
     L.phiSW = take((size_t)3 * nv * ts);
     L.gV = take((size_t)3 * nv * ts);
     L.base = take((size_t)nv * sizeof(Base));
     L.wts = take((size_t)12 * nv * ts);
     L.partials = take((size_t)2 * nparts * 8);
-    L.cnt = take((size_t)2 * g.nt * 4);
-    L.list = take((size_t)2 * g.nt * kTileCap * 4);
-    L.acnt = take(2 * 4);
-    L.alist = take((size_t)2 * g.nt * 4);
+    L.mask = take((size_t)g.nt * ((nv + 63) / 64) * 8);
     L.act = take((size_t)g.nt * 4);
+    L.acnt = take(4);
+    L.alist = take((size_t)g.nt * 4);
     L.mesh_end = o;
     return L;
 }
@@ -164,7 +164,7 @@ int check_mesh(const iblb_mesh_desc *m, std::string &why)
 {
     if (!m || !m->vertices || !m->faces) { why = "null mesh arrays"; return IBLB_E_INVAL; }
     if (m->n_vertices < 4 || m->n_faces < 4) { why = "mesh too small"; return IBLB_E_MESH; }
-    if (m->n_vertices > (1 << 28) || m->n_faces > (1 << 28)) { why = "mesh too large"; return IBLB_E_INVAL; }
+    if (m->n_vertices > kMaxVertices || m->n_faces > (1 << 28)) { why = "mesh too large (at most 65536 vertices)"; return IBLB_E_INVAL; }
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(m->alpha[k])) { why = "non-finite alpha"; return IBLB_E_INVAL; }
     if (!std::isfinite(m->k_v) || !std::isfinite(m->eps_wall_lo) || !std::isfinite(m->eps_wall_hi) ||
@@ -240,7 +240,7 @@ hipError_t launch_kernel(iblb_ctx *c, int which, int p, hipStream_t st)
 {
     const Dev &d = c->d;
     switch (which) {
-    case K_FORCES: return launch_forces(c->prec, d, c->g, c->m, st);
+    case K_FORCES: return launch_forces(c->prec, d, c->g, c->m, p, st);
     case K_SPREAD: return launch_spread(c->prec, d, c->lb, c->m, p, st);
     case K_LB: return launch_lb(c->prec, d, c->lb, p, c->has_mesh ? 1 : 0, st);
     default: return launch_move(c->prec, d, c->lb, c->m, p, st);
@@ -248,8 +248,9 @@ hipError_t launch_kernel(iblb_ctx *c, int which, int p, hipStream_t st)
 }
 
 // One step of parity p.  With a mesh: one dispatch computes the interface
-// forces and the bulk LB (nodes outside the active tiles) side by side, then
-// the spread updates the active tiles (force + LB), then the move.  Timed
+// forces, the list of active tiles and the bulk LB (nodes outside the active
+// tiles) side by side, then the spread updates the active tiles (force + LB), then the
+// moments of the active tiles and the move.  Timed
 // steps launch forces and bulk LB as separate kernels so that each one's
 // duration can be read.
 hipError_t enqueue_step(iblb_ctx *c, int p, bool timed)
@@ -330,12 +331,14 @@ struct TmpDev {
     ~TmpDev() { if (p) (void)hipFree(p); }
 };
 
+// Clears the vertex masks and activity stamps, then sets both for the current
+// step from the stored positions (each step sets them for the next one).
 int rebuild_lists(iblb_ctx *c)
 {
-    HIP_TRY(c, hipMemsetAsync(c->d.cnt, 0, (size_t)2 * c->g.nt * 4, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->d.acnt, 0, 2 * 4, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d.mask, 0, (size_t)c->g.nt * c->m.nwords * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d.act, 0, (size_t)c->g.nt * 4, c->stream));
-    HIP_TRY(c, launch_bin(c->d, c->g, c->m, (int)(c->t & 1), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d.acnt, 0, 4, c->stream));
+    HIP_TRY(c, launch_stamp(c->d, c->g, c->m, (int)(c->t & 1), c->stream));
     return IBLB_OK;
 }
 
@@ -515,16 +518,16 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     d.fref = (double *)(mb + L.fref);
     d.inc_off = (int *)(mb + L.inc_off);
     d.inc4 = (int4 *)(mb + L.inc4);
+    d.U = mb + L.U;
     d.phiSW = mb + L.phiSW;
     d.gV = mb + L.gV;
     d.base = (Base *)(mb + L.base);
     d.wts = mb + L.wts;
     d.partials = (double *)(mb + L.partials);
-    d.cnt = (uint32_t *)(mb + L.cnt);
-    d.list = (int *)(mb + L.list);
+    d.mask = (uint64_t *)(mb + L.mask);
+    d.act = (uint32_t *)(mb + L.act);
     d.acnt = (uint32_t *)(mb + L.acnt);
     d.alist = (int *)(mb + L.alist);
-    d.act = (uint32_t *)(mb + L.act);
     HIP_TRY(c, hipMemcpyAsync(d.q, qs.data(), qs.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d.Xref, Xs.data(), Xs.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d.faces, fs.data(), fs.size() * 4, hipMemcpyHostToDevice, c->stream));
@@ -548,6 +551,7 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     m.z_hi = c->dom.nz - 1.5;
     m.kv_over_V0 = mesh->k_v / V0;
     m.nparts = (nv + 31) / 32;
+    m.nwords = (nv + 63) / 64;
     c->V0 = V0;
     c->nv = nv;
     c->nf = nf;
@@ -933,6 +937,29 @@ int iblb_kernel_time(iblb_ctx *c, const char *name, double *total_ms, int64_t *l
             return IBLB_OK;
         }
     return fail(c, IBLB_E_INVAL, std::string("unknown kernel name ") + name);
+}
+
+int iblb_active_nodes(iblb_ctx *c, int64_t *n)
+{
+    if (!c || !n) return IBLB_E_INVAL;
+    *n = 0;
+    if (!c->has_mesh) return IBLB_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    uint32_t na = 0;
+    HIP_TRY(c, hipMemcpy(&na, c->d.acnt, 4, hipMemcpyDeviceToHost));
+    if (na > (uint32_t)c->g.nt) return fail(c, IBLB_E_STATE, "active tile count out of range");
+    std::vector<int> tiles(na);
+    if (na) HIP_TRY(c, hipMemcpy(tiles.data(), c->d.alist, (size_t)na * 4, hipMemcpyDeviceToHost));
+    const Grid &g = c->g;
+    int64_t total = 0;
+    for (int tile : tiles) {
+        if (tile < 0 || tile >= g.nt) return fail(c, IBLB_E_STATE, "active tile index out of range");
+        const int tz = tile / (g.ntx * g.nty), rem = tile % (g.ntx * g.nty);
+        const int ty = rem / g.ntx, tx = rem % g.ntx;
+        total += (int64_t)std::min(4, g.nx - 4 * tx) * std::min(4, g.ny - 4 * ty) * std::min(4, g.nzf - 4 * tz);
+    }
+    *n = total;
+    return IBLB_OK;
 }
 
 int iblb_reset_timing(iblb_ctx *c)

@@ -11,6 +11,9 @@ namespace iblb {
 constexpr int kTile = 4;
 // Maximum vertices whose stencil reaches one tile.
 constexpr int kTileCap = 512;
+// Maximum mesh vertices: the per-tile vertex masks hold nv bits in at most
+// 1024 64-bit words (four per thread of a 256-thread spreading block).
+constexpr int kMaxVertices = 65536;
 // Device error bits.
 constexpr int kErrNonFinite = 1;   // a vertex position left the finite range
 constexpr int kErrOverflow = 2;    // a tile list overflowed kTileCap
@@ -49,6 +52,7 @@ struct MeshArgs {
     double origin[3];
     double kv_over_V0;    // k_V / V0
     int nparts;           // force-kernel blocks (32 vertices each) = number of volume partials
+    int nwords;           // 64-bit words of one tile's vertex mask, ceil(nv / 64)
 };
 
 // Device buffers of one context (typed as void* where the precision varies).
@@ -66,16 +70,17 @@ struct Dev {
     double *fref;         // [5][nf]: Ginv11, Ginv12, Ginv22, A0, detG
     int *inc_off;         // [nv+1]
     int4 *inc4;           // [3 nf]: (a, b, c, face*4 + corner), vertex-major, faces ascending
+    void *U;              // [3][n] u(t+1) on the nodes of the active tiles
     void *phiSW;          // [3][nv] elastic + wall force
     void *gV;             // [3][nv] dV/dq
     Base *base;           // [nv]
     void *wts;            // [nv][12] phi4 weights (x 0..3, y 0..3, z 0..3)
     double *partials;     // [2][nparts]: sum (V_j - V0_j), sum A_j per force block
-    uint32_t *cnt;        // [2][nt]
-    int *list;            // [2][nt][kTileCap]
-    uint32_t *acnt;       // [2]
-    int *alist;           // [2][nt]
-    uint32_t *act;        // [nt] step+1 for which the tile is active (listed)
+    uint64_t *mask;       // [nt][nwords] bit v: vertex v's stencil reaches the tile (set by the
+                          // move, read and cleared by the next step's spreading)
+    uint32_t *act;        // [nt] step+1 for which the tile is active (stamped by the previous move)
+    uint32_t *acnt;       // [1] active tiles of the step
+    int *alist;           // [nt] active tile indices of the step (scan order)
     double *scratch;      // small FP64 scratch for queries (64 doubles)
     int num_cus;          // compute units of the device (launch sizing)
 };
@@ -86,13 +91,18 @@ hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hip
 // bulk != 0: only the nodes outside this step's active tiles (mesh present);
 // bulk == 0: every node, and the kernel advances the step counter (no mesh)
 hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, hipStream_t s);
-hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s);
-// forces and bulk LB in one dispatch (the two are independent within a step)
+// interface forces and the step's list of active tiles
+hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s);
+// forces, active-tile list and bulk LB in one dispatch (independent within a step)
 hipError_t launch_bulk_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);
 // spreading of the active tiles followed by their LB update
 hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);
+// moments of the active tiles, then interpolation, move, and the next step's
+// act stamps and vertex masks
 hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);
-hipError_t launch_bin(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s);
+// act stamps and vertex masks of the current step from the stored positions
+// (masks and stamps cleared beforehand)
+hipError_t launch_stamp(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s);
 // debug / query kernels
 hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double *out, hipStream_t s);
 hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, int p, const double *in, hipStream_t s);

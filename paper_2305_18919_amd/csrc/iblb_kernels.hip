@@ -183,30 +183,17 @@ __device__ __forceinline__ void load_pops(const T *__restrict__ f, const Grid &g
 // ---------------------------------------------------------------------------
 // LB: AA-pattern stream + collide
 // ---------------------------------------------------------------------------
-// LB update of node (x, y, zf) with the immersed-boundary force density
-// (fx, fy, fz) of this step; body force and external field are added here.
+// Collision of node (x, y, zf) whose populations d (canonical order, time t)
+// are in hand, with the immersed-boundary force density (fx, fy, fz) of this
+// step (body force and external field are added here), and the AA write-back.
 template <typename T, bool ODD>
-__device__ __forceinline__ void lb_node(T *__restrict__ f, const T *__restrict__ Fext, int *err, const LBArgs &a,
-                                        int x, int y, int zf, T fx, T fy, T fz)
+__device__ __forceinline__ void lb_collide(T *__restrict__ f, const T *__restrict__ Fext, int *err,
+                                           const LBArgs &a, int x, int y, int zf, const T *d, T fx, T fy, T fz)
 {
     const Grid &g = a.g;
     const long long n = g.n;
     const long long me = nidx(g, x, y, zf);
     const Nbr b = neighbours(g, x, y, zf);
-
-    T d[19];
-    if (!ODD) {
-#pragma unroll
-        for (int i = 0; i < 19; ++i)
-            d[i] = f[i * n + me];
-    } else {
-#pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            long long src;
-            const bool ok = shifted(g, b, x, y, zf, i, -1, src);
-            d[i] = ok ? f[opp(i) * n + src] : f[i * n + me];
-        }
-    }
 
     // force density: body force + IB force + external
     T Fx = T(a.body[0]) + fx, Fy = T(a.body[1]) + fy, Fz = T(a.body[2]) + fz;
@@ -259,6 +246,16 @@ __device__ __forceinline__ void lb_node(T *__restrict__ f, const T *__restrict__
     }
 }
 
+// LB update of node (x, y, zf): load its populations, collide, write back.
+template <typename T, bool ODD>
+__device__ __forceinline__ void lb_node(T *__restrict__ f, const T *__restrict__ Fext, int *err, const LBArgs &a,
+                                        int x, int y, int zf, T fx, T fy, T fz)
+{
+    T d[19];
+    load_pops<T, ODD>(f, a.g, x, y, zf, d);
+    lb_collide<T, ODD>(f, Fext, err, a, x, y, zf, d, fx, fy, fz);
+}
+
 // LB over the fluid nodes.  Without a mesh (act == null) every node, and the
 // kernel advances the step counter.  With a mesh only the nodes outside this
 // step's active tiles (act[tile] != t + 1): it runs concurrently with the
@@ -306,6 +303,127 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ f, LBArgs a, int c
         const double w = wgt<double>(i);
         f[i * g.n + me] = T(w * a.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
     }
+}
+
+// ---------------------------------------------------------------------------
+// Active tiles.  A vertex at q touches every tile that holds a fluid node of
+// its 4^3 stencil, floor(q) - 1 + {0..3} along each axis (x, y wrapped; z
+// wrapped if periodic, clipped to the fluid layers between walls).  Along an
+// axis the stencil's nodes form runs of consecutive nodes in one tile; a run
+// opens at offset k when node k is in the fluid and node k - 1 is not, or lies
+// in another tile.  With at least 8 nodes per axis a run never reopens a tile
+// already visited, so the run openings name each touched tile once: bit k of
+// the mask is set when offset k opens a run (at most three per axis).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned runs_wrapped(int b, int n)
+{
+    unsigned mask = 1u;
+    int prev = wrapi(b, n) >> 2;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        const int tl = wrapi(b + k, n) >> 2;
+        mask |= tl != prev ? 1u << k : 0u;
+        prev = tl;
+    }
+    return mask;
+}
+
+// b = first stencil layer counted in fluid layers (may be outside [0, nzf))
+__device__ __forceinline__ unsigned runs_clipped(int b, int nzf)
+{
+    unsigned mask = 0u;
+    int prev = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int zf = b + k;
+        const bool in = zf >= 0 && zf < nzf;
+        const int tl = in ? zf >> 2 : -1;
+        mask |= (in && tl != prev) ? 1u << k : 0u;
+        prev = tl;
+    }
+    return mask;
+}
+
+struct StencilRuns {
+    int bx, by, bz;          // stencil corner floor(q) - 1
+    unsigned mx, my, mz;     // run openings per axis
+};
+
+__device__ __forceinline__ StencilRuns stencil_runs(const Grid &g, double qx, double qy, double qz)
+{
+    StencilRuns r;
+    r.bx = (int)floor(qx) - 1;
+    r.by = (int)floor(qy) - 1;
+    r.bz = (int)floor(qz) - 1;
+    r.mx = runs_wrapped(r.bx, g.nx);
+    r.my = runs_wrapped(r.by, g.ny);
+    r.mz = g.walls ? runs_clipped(r.bz - g.zoff, g.nzf) : runs_wrapped(r.bz, g.nz);
+    return r;
+}
+
+// tile of the stencil node at offsets (kx, ky, kz)
+__device__ __forceinline__ int stencil_tile(const Grid &g, const StencilRuns &r, int kx, int ky, int kz)
+{
+    const int x = wrapi(r.bx + kx, g.nx), y = wrapi(r.by + ky, g.ny);
+    const int zf = g.walls ? r.bz + kz - g.zoff : wrapi(r.bz + kz, g.nz);
+    return tile_of(g, x, y, zf);
+}
+
+// Inclusive sum over the 64 lanes of a wavefront, in lane order.
+__device__ __forceinline__ int wave_incl_scan(int c, int lane)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(c, off, 64);
+        c += lane >= off ? y : 0;
+    }
+    return c;
+}
+
+// The step's active tiles, those stamped act[tile] == t + 1 by the previous
+// move, compacted into alist by one 256-thread block: thread k takes the k-th
+// contiguous range of tiles, so the list is in ascending tile order.  The
+// stamps are read in groups of 16 independent loads; a range of up to 64 tiles
+// is remembered as a bit mask, longer ones are read twice.
+__device__ __forceinline__ void scan_block(const uint32_t *__restrict__ act, uint32_t *acnt, int *alist, uint32_t t,
+                                           const Grid &g)
+{
+    __shared__ int swt[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per = (g.nt + 255) / 256;
+    const int k0 = min(g.nt, tid * per), k1 = min(g.nt, k0 + per);
+    uint64_t bits = 0ull;
+    int c = 0;
+    for (int kb = k0; kb < k1; kb += 16) {
+        uint32_t v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            v[j] = kb + j < k1 ? act[kb + j] : 0u;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const bool on = v[j] == t + 1u;
+            c += on ? 1 : 0;
+            if (on && kb + j - k0 < 64)
+                bits |= 1ull << (kb + j - k0);
+        }
+    }
+    const int incl = wave_incl_scan(c, lane);
+    if (lane == 63)
+        swt[wave] = incl;
+    __syncthreads();
+    int o = incl - c;
+    for (int w = 0; w < wave; ++w)
+        o += swt[w];
+    while (bits != 0ull) {
+        alist[o++] = k0 + __builtin_ctzll(bits);
+        bits &= bits - 1ull;
+    }
+    if (per > 64 && c > 0)
+        for (int k = k0 + 64; k < k1; ++k)
+            if (act[k] == t + 1u)
+                alist[o++] = k;
+    if (tid == 0)
+        *acnt = (uint32_t)(swt[0] + swt[1] + swt[2] + swt[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -486,42 +604,54 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
     }
 }
 
-template <typename T>
+// Blocks [0, nparts) compute the interface forces, block nparts lists the
+// step's active tiles.
+template <typename T, int P>
 __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, const double *__restrict__ Xref,
                                                 const int4 *__restrict__ inc4, const int *__restrict__ inc_off,
                                                 const double *__restrict__ fref, T *__restrict__ phiSW,
                                                 T *__restrict__ gVout, Base *__restrict__ base,
-                                                T *__restrict__ wts, double *__restrict__ partials, int *err,
-                                                Grid g, MeshArgs m)
+                                                T *__restrict__ wts, double *__restrict__ partials,
+                                                const uint32_t *__restrict__ act, uint32_t *acnt, int *alist,
+                                                const uint32_t *__restrict__ ctr, int *err, Grid g, MeshArgs m)
 {
-    forces_block<T>(blockIdx.x, q, Xref, inc4, inc_off, fref, phiSW, gVout, base, wts, partials, err, g, m);
+    if ((int)blockIdx.x < m.nparts)
+        forces_block<T>(blockIdx.x, q, Xref, inc4, inc_off, fref, phiSW, gVout, base, wts, partials, err, g, m);
+    else
+        scan_block(act, acnt, alist, ctr[P], g);
 }
 
-// The first m.nparts blocks compute the interface forces (latency-bound), the
-// rest run the bulk LB (bandwidth-bound) in the same dispatch, so the two
-// overlap without a second queue.  The bulk blocks use the LB kernel's tiling
-// (lb_block_x wide, 256 / lb_block_x rows), numbered x fastest.
+// The first nparts + 1 blocks are those of k_forces (latency-bound); the rest
+// run the bulk LB (bandwidth-bound) in the same dispatch, so the two overlap
+// without a second queue.  The bulk blocks use the LB kernel's tiling
+// (lb_block_x wide, 256 / lb_block_x rows), numbered x fastest.  The active
+// tiles of the step were stamped in `act` by the previous step's move.
 template <typename T, bool ODD>
 __global__ __launch_bounds__(256) void k_bulk_forces(const double *__restrict__ q, const double *__restrict__ Xref,
                                                      const int4 *__restrict__ inc4, const int *__restrict__ inc_off,
                                                      const double *__restrict__ fref, T *__restrict__ phiSW,
                                                      T *__restrict__ gVout, Base *__restrict__ base,
                                                      T *__restrict__ wts, double *__restrict__ partials,
-                                                     T *__restrict__ f, const T *__restrict__ Fext,
-                                                     const uint32_t *__restrict__ act, const uint32_t *__restrict__ ctr,
-                                                     int *err, LBArgs a, MeshArgs m, int bxw, int nbx, int nby)
+                                                     uint32_t *acnt, int *alist, T *__restrict__ f,
+                                                     const T *__restrict__ Fext, const uint32_t *__restrict__ act,
+                                                     const uint32_t *__restrict__ ctr, int *err, LBArgs a, MeshArgs m,
+                                                     int bxw, int nbx, int nby)
 {
+    const uint32_t t = ctr[ODD ? 1 : 0];
     if ((int)blockIdx.x < m.nparts) {
         forces_block<T>(blockIdx.x, q, Xref, inc4, inc_off, fref, phiSW, gVout, base, wts, partials, err, a.g, m);
         return;
     }
-    const int b = blockIdx.x - m.nparts;
+    if ((int)blockIdx.x == m.nparts) {
+        scan_block(act, acnt, alist, t, a.g);
+        return;
+    }
+    const int b = blockIdx.x - m.nparts - 1;
     const int zf = b / (nbx * nby);
     const int rem = b - zf * nbx * nby;
     const int byi = rem / nbx, bxi = rem - byi * nbx;
     const int x = bxi * bxw + (int)(threadIdx.x % (unsigned)bxw);
     const int y = byi * (256 / bxw) + (int)(threadIdx.x / (unsigned)bxw);
-    const uint32_t t = ctr[ODD ? 1 : 0];
     if (x >= a.g.nx || y >= a.g.ny)
         return;
     if (act[tile_of(a.g, x, y, zf)] == t + 1u)
@@ -530,115 +660,194 @@ __global__ __launch_bounds__(256) void k_bulk_forces(const double *__restrict__ 
 }
 
 // k_V (V - V0)/V0 from the force-kernel partials, summed by one wavefront in a
-// fixed order (lane-strided, then a butterfly).
+// fixed order (lane-strided, then a butterfly); the loads of a lane are issued
+// in groups of eight before any of them is added.
 __device__ __forceinline__ double volume_factor(const double *__restrict__ partials, const MeshArgs &m, int lane)
 {
     double s = 0.0;
-    for (int k = lane; k < m.nparts; k += 64)
-        s += partials[k];
+    for (int k0 = lane; k0 < m.nparts; k0 += 64 * 8) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            v[j] = k0 + 64 * j < m.nparts ? partials[k0 + 64 * j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            s += v[j];
+    }
     s = wave_sum<double>(s);
     return m.kv_over_V0 * s;
 }
 
 // ---------------------------------------------------------------------------
-// Spreading, one wavefront per active tile (gather form, no FP atomics)
+// Spreading, one 256-thread block per active tile (gather form, no FP atomics)
 // ---------------------------------------------------------------------------
+// A listed vertex as the gather needs it: stencil corner, phi4 weights,
+// phi_S + phi_W and dV/dq.
+template <typename T>
+struct Staged {
+    int4 b;
+    T w[12];
+    T ph[3], gv[3];
+};
+
+template <typename T>
+__device__ __forceinline__ Staged<T> stage_load(int v, const Base *__restrict__ base, const T *__restrict__ wts,
+                                                const T *__restrict__ phiSW, const T *__restrict__ gV, int nv,
+                                                int *err)
+{
+    Staged<T> s;
+    // a corrupt list entry is never used as an index: its corner is put far
+    // outside the grid, so it weighs zero everywhere
+    const bool ok = (unsigned)v < (unsigned)nv;
+    if (!ok)
+        atomicOr(err, kErrList);
+    const int u = ok ? v : 0;
+    const Base bs = base[u];
+    s.b = ok ? make_int4(bs.x, bs.y, bs.z, 0) : make_int4(-1000000, -1000000, -1000000, 0);
+    if constexpr (sizeof(T) == 4) {
+        const float4 *pw = reinterpret_cast<const float4 *>(wts) + 3 * u;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float4 w4 = pw[k];
+            s.w[4 * k] = w4.x;
+            s.w[4 * k + 1] = w4.y;
+            s.w[4 * k + 2] = w4.z;
+            s.w[4 * k + 3] = w4.w;
+        }
+    } else {
+        const double2 *pw = reinterpret_cast<const double2 *>(wts) + 6 * u;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double2 w2 = pw[k];
+            s.w[2 * k] = w2.x;
+            s.w[2 * k + 1] = w2.y;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        s.ph[c] = phiSW[c * nv + u];
+        s.gv[c] = gV[c * nv + u];
+    }
+    return s;
+}
+
 // One 256-thread block (four wavefronts) per active tile.  The tile's vertex
-// list is ordered by vertex index (each key's rank is the number of smaller
-// keys: the keys are distinct, so ranks are a permutation); all four
-// wavefronts stage the listed vertices; wavefront w then sums the w-th
-// contiguous quarter of the ordered list for the 64 nodes (one per lane), and
-// the four partial sums are added in wavefront order, so every node's sum has
-// a fixed order.
+// mask (bit v set when vertex v's stencil reaches the tile) is read whole,
+// thread k taking the k-th contiguous run of words; a block-wide prefix sum of
+// the words' bit counts places every set bit, so the listed vertices come out
+// in ascending index order, and the words are cleared for the next step.  All
+// four wavefronts then stage the listed vertices in LDS; wavefront w sums the
+// w-th contiguous quarter of the ordered list for the 64 nodes of the tile
+// (one per lane), and the four partial sums are added in wavefront order, so
+// every node's sum has a fixed order.  Wavefront 0 finishes with the LB update
+// of the tile's nodes, whose populations it fetched at the start.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
                                                 const double *__restrict__ partials, const uint32_t *__restrict__ ctr,
-                                                uint32_t *cnt, const int *__restrict__ list,
-                                                const uint32_t *__restrict__ acnt, const int *__restrict__ alist,
-                                                T *__restrict__ F, uint32_t *__restrict__ stamp, T *__restrict__ f,
+                                                uint64_t *__restrict__ mask, const uint32_t *__restrict__ acnt,
+                                                const int *__restrict__ alist, T *__restrict__ F,
+                                                uint32_t *__restrict__ stamp, T *__restrict__ f,
                                                 const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m)
 {
     const Grid &g = a.g;
-    const int p = P;
-    __shared__ int skey[kTileCap];
     __shared__ int sid[kTileCap];
     __shared__ int4 sbase[kTileCap];
-    __shared__ T sw[kTileCap * 12];
-    __shared__ T sph[kTileCap * 4];
+    __shared__ __align__(16) T sw[kTileCap * 12];
+    __shared__ __align__(16) T sph[kTileCap * 4];
     __shared__ T part[3][3][64];
-    __shared__ int snent;
+    __shared__ int swt[4];
     __shared__ T skfac;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t t = ctr[p];
-    const int buf = p;
-    const uint32_t na = acnt[buf];
-    if (blockIdx.x >= na)
-        return;
-    if (wave == 1) {
-        const T kfac = T(volume_factor(partials, m, lane));
-        if (lane == 0)
-            skfac = kfac;
-    }
-    const int nv = m.nv;
+    const int nv = m.nv, W = m.nwords;
+    const int J = (W + 255) >> 8;  // words per thread, at most 4
+    // the count of active tiles and the block's first tile are read together
+    // (block index < grid size <= tile count, so the slot exists); the volatile
+    // read keeps the compiler from deferring it past the test on the count
+    const uint32_t na = acnt[0];
+    int tile = ((const volatile int *)alist)[blockIdx.x];
+    const uint32_t t = ctr[P];
     for (uint32_t ai = blockIdx.x; ai < na; ai += gridDim.x) {
-        const int tile = alist[buf * g.nt + ai];
-        // the whole list slot range is read at once, next to its count; only
-        // thread 0 reads the count, hands it over through LDS and, once every
-        // thread has it, resets it for the buffer's next use
-        const int *src = list + ((long long)buf * g.nt + tile) * kTileCap;
-        const int k0 = src[tid], k1 = src[tid + 256];
-        if (tid == 0) {
-            const uint32_t c = cnt[buf * g.nt + tile];
-            snent = c < (uint32_t)kTileCap ? (int)c : kTileCap;
-        }
-        __syncthreads();
-        const int nent = snent;
-        if (tid < nent) skey[tid] = k0;
-        if (tid + 256 < nent) skey[tid + 256] = k1;
-        if (tid == 0)
-            cnt[buf * g.nt + tile] = 0u;
-        __syncthreads();
-        // ascending vertex index makes the sums order-deterministic
-        for (int i = tid; i < nent; i += 256) {
-            const int key = skey[i];
-            int rank = 0;
-#pragma unroll 8
-            for (int j = 0; j < nent; ++j)
-                rank += skey[j] < key ? 1 : 0;
-            sid[rank] = key;
-        }
-        __syncthreads();
-        // stage each listed vertex's stencil corner, weights and total force in LDS
-        const T kf = skfac;
-        for (int e = tid; e < nent; e += 256) {
-            const int v = sid[e];
-            if ((unsigned)v >= (unsigned)nv) {
-                // never index with a corrupt list entry: contribute nothing, report
-                atomicOr(err, kErrList);
-                sbase[e] = make_int4(-1000000, -1000000, -1000000, 0);
-                for (int k = 0; k < 12; ++k)
-                    sw[e * 12 + k] = T(0);
-                sph[e * 4 + 0] = sph[e * 4 + 1] = sph[e * 4 + 2] = sph[e * 4 + 3] = T(0);
-                continue;
-            }
-            const Base bs = base[v];
-            sbase[e] = make_int4(bs.x, bs.y, bs.z, 0);
-#pragma unroll
-            for (int k = 0; k < 12; ++k)
-                sw[e * 12 + k] = wts[v * 12 + k];
-            sph[e * 4 + 0] = phiSW[v] - kf * gV[v];
-            sph[e * 4 + 1] = phiSW[nv + v] - kf * gV[nv + v];
-            sph[e * 4 + 2] = phiSW[2 * nv + v] - kf * gV[2 * nv + v];
-            sph[e * 4 + 3] = T(0);
-        }
-        __syncthreads();
-        // this lane's node, and this wavefront's quarter of the list
+        const uint32_t an = ai + gridDim.x;
+        const int next = alist[an < na ? an : ai];
+        // this lane's node; wavefront 0 fetches its populations now, next to
+        // the tile's mask words
         const int tz = tile / (g.ntx * g.nty);
         const int rem = tile - tz * g.ntx * g.nty;
         const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
         const int x = tx * 4 + (lane & 3), y = ty * 4 + ((lane >> 2) & 3), zf = tz * 4 + (lane >> 4);
         const int z = zf + g.zoff;
+        const bool node = x < g.nx && y < g.ny && zf < g.nzf;
+        T d[19];
+        if (wave == 0 && node)
+            load_pops<T, P == 1>(f, g, x, y, zf, d);
+        uint64_t *mw = mask + (long long)tile * W;
+        const int w0 = tid * J;
+        uint64_t wv[4];
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            wv[j] = (j < J && w0 + j < W) ? mw[w0 + j] : 0ull;
+            c += __popcll(wv[j]);
+        }
+        if (wave == 1 && ai == blockIdx.x) {
+            const T kfac = T(volume_factor(partials, m, lane));
+            if (lane == 0)
+                skfac = kfac;
+        }
+        const int incl = wave_incl_scan(c, lane);
+        if (lane == 63)
+            swt[wave] = incl;
+        __syncthreads();
+        int nent = swt[0] + swt[1] + swt[2] + swt[3];
+        if (nent > kTileCap) {
+            if (tid == 0)
+                atomicOr(err, kErrOverflow);
+            nent = kTileCap;
+        }
+        int o = incl - c;
+        for (int w = 0; w < wave; ++w)
+            o += swt[w];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint64_t bits = wv[j];
+            while (bits != 0ull) {
+                if (o < kTileCap)
+                    sid[o] = (w0 + j) * 64 + __builtin_ctzll(bits);
+                ++o;
+                bits &= bits - 1ull;
+            }
+        }
+        __syncthreads();
+        // stage each listed vertex's stencil corner, weights and total force
+        {
+            const bool has0 = tid < nent, has1 = tid + 256 < nent;
+            const T kf = skfac;
+            Staged<T> s0, s1;
+            if (has0) s0 = stage_load<T>(sid[tid], base, wts, phiSW, gV, nv, err);
+            if (has1) s1 = stage_load<T>(sid[tid + 256], base, wts, phiSW, gV, nv, err);
+            if (has0) {
+                sbase[tid] = s0.b;
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    sw[tid * 12 + k] = s0.w[k];
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    sph[tid * 4 + cc] = s0.ph[cc] - kf * s0.gv[cc];
+            }
+            if (has1) {
+                const int e = tid + 256;
+                sbase[e] = s1.b;
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    sw[e * 12 + k] = s1.w[k];
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    sph[e * 4 + cc] = s1.ph[cc] - kf * s1.gv[cc];
+            }
+        }
+        __syncthreads();
+        // this wavefront's quarter of the ordered list
         const int chunk = (nent + 3) >> 2;
         const int e0 = wave * chunk, e1 = min(nent, e0 + chunk);
         T Fx = T(0), Fy = T(0), Fz = T(0);
@@ -665,166 +874,175 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
             part[wave - 1][2][lane] = Fz;
         }
         __syncthreads();
+        // the mask words are cleared for the next step only now: a barrier
+        // waits for a wavefront's outstanding stores
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (wv[j] != 0ull)
+                mw[w0 + j] = 0ull;
+        // LDS is not written again before every wavefront has passed the next
+        // iteration's first barrier, which wavefront 0 reaches only after this
         if (wave == 0) {
             for (int w = 0; w < 3; ++w) {
                 Fx += part[w][0][lane];
                 Fy += part[w][1][lane];
                 Fz += part[w][2][lane];
             }
-            if (x < g.nx && y < g.ny && zf < g.nzf) {
+            if (node) {
                 const long long me = nidx(g, x, y, zf);
                 F[me] = Fx;
                 F[g.n + me] = Fy;
                 F[2 * g.n + me] = Fz;
                 // the LB update of this active node, with its force in hand
-                lb_node<T, P == 1>(f, Fext, err, a, x, y, zf, Fx, Fy, Fz);
+                lb_collide<T, P == 1>(f, Fext, err, a, x, y, zf, d, Fx, Fy, Fz);
             }
             if (lane == 0)
                 stamp[tile] = t + 1u;
         }
-        __syncthreads();
+        tile = next;
     }
 }
 
-// ---------------------------------------------------------------------------
-// Tile lists: a vertex is listed on every tile holding a fluid node of its 4^3
-// stencil (x, y wrapped; z wrapped if periodic, clipped to the fluid if walls).
-// Called by all 64 lanes of the vertex's wavefront, lane = stencil offset.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void list_vertex(int v, double qx, double qy, double qz, int lane, const Grid &g,
-                                            uint32_t *cnt, int *list, uint32_t *acnt, int *alist, uint32_t *act,
-                                            uint32_t step, int buf, int *err)
-{
-    if (!(fabs(qx) < 1e6 && fabs(qy) < 1e6 && fabs(qz) < 1e6)) {
-        if (lane == 0)
-            atomicOr(err, kErrNonFinite);
-        return;
-    }
-    const int ix = lane & 3, iy = (lane >> 2) & 3, iz = lane >> 4;
-    const int bx = (int)floor(qx) - 1, by = (int)floor(qy) - 1, bz = (int)floor(qz) - 1;
-    const int x0 = wrapi(bx + ix, g.nx), xm = wrapi(bx + ix - 1, g.nx);
-    const int y0 = wrapi(by + iy, g.ny), ym = wrapi(by + iy - 1, g.ny);
-    const bool lx = ix == 0 || (x0 >> 2) != (xm >> 2);
-    const bool ly = iy == 0 || (y0 >> 2) != (ym >> 2);
-    int zf, zfm;
-    bool ok, okm;
-    if (g.walls) {
-        zf = bz + iz - g.zoff;
-        zfm = zf - 1;
-        ok = zf >= 0 && zf < g.nzf;
-        okm = iz > 0 && zfm >= 0 && zfm < g.nzf;
-    } else {
-        zf = wrapi(bz + iz, g.nz);
-        zfm = wrapi(bz + iz - 1, g.nz);
-        ok = true;
-        okm = iz > 0;
-    }
-    const bool lz = ok && (!okm || (zf >> 2) != (zfm >> 2));
-    if (lx && ly && lz) {
-        const int tile = tile_of(g, x0, y0, zf);
-        const uint32_t slot = atomicAdd(&cnt[buf * g.nt + tile], 1u);
-        if (slot == 0u) {
-            const uint32_t a = atomicAdd(&acnt[buf], 1u);
-            alist[buf * g.nt + a] = tile;
-            act[tile] = step + 1u;
-        }
-        if (slot < (uint32_t)kTileCap)
-            list[((long long)buf * g.nt + tile) * kTileCap + slot] = v;
-        else
-            atomicOr(err, kErrOverflow);
-    }
-}
-
+// u(t+1) = (sum c f(t+1) + F(t)/2) / rho(t+1) once per node of the active
+// tiles (one wavefront per tile, one lane per node), for the interpolation.
 // P = t & 1: after this step's LB the populations of time t + 1 sit in the
 // swapped layout exactly when P == 0.
 template <typename T, int P>
-__global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *__restrict__ f,
-                                              const T *__restrict__ Fib, const T *__restrict__ Fext,
-                                              const uint32_t *__restrict__ stamp, uint32_t *ctr, uint32_t *cnt,
-                                              int *list, uint32_t *acnt, int *alist, uint32_t *act, int *err,
-                                              LBArgs a, MeshArgs m)
+__global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const T *__restrict__ Fib,
+                                                 const T *__restrict__ Fext, const uint32_t *__restrict__ acnt,
+                                                 const int *__restrict__ alist, T *__restrict__ U, LBArgs a)
+{
+    const Grid &g = a.g;
+    const int lane = threadIdx.x & 63;
+    const uint32_t na = acnt[0];
+    const uint32_t first = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the first tile is read together with the count (clamped into the list;
+    // volatile, so that it is not deferred past the test on the count)
+    int tile = ((const volatile int *)alist)[first < (uint32_t)g.nt ? first : 0u];
+    for (uint32_t ai = first; ai < na; ai += gridDim.x * 4) {
+        const uint32_t an = ai + gridDim.x * 4;
+        const int next = alist[an < na ? an : ai];
+        const int tz = tile / (g.ntx * g.nty);
+        const int rem = tile - tz * g.ntx * g.nty;
+        const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
+        const int x = tx * 4 + (lane & 3), y = ty * 4 + ((lane >> 2) & 3), zf = tz * 4 + (lane >> 4);
+        tile = next;
+        if (x >= g.nx || y >= g.ny || zf >= g.nzf)
+            continue;
+        T d[19];
+        load_pops<T, P == 0>(f, g, x, y, zf, d);
+        const long long me = nidx(g, x, y, zf);
+        T Fx = T(a.body[0]) + Fib[me], Fy = T(a.body[1]) + Fib[g.n + me], Fz = T(a.body[2]) + Fib[2 * g.n + me];
+        if (a.has_fext) {
+            Fx += Fext[me];
+            Fy += Fext[g.n + me];
+            Fz += Fext[2 * g.n + me];
+        }
+        T drho = T(0), mx = T(0), my = T(0), mz = T(0);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            drho += d[i];
+            if (cx(i) != 0) mx += T(cx(i)) * d[i];
+            if (cy(i) != 0) my += T(cy(i)) * d[i];
+            if (cz(i) != 0) mz += T(cz(i)) * d[i];
+        }
+        const T rho = T(a.rho0) + drho;
+        U[me] = (mx + T(0.5) * Fx) / rho;
+        U[g.n + me] = (my + T(0.5) * Fy) / rho;
+        U[2 * g.n + me] = (mz + T(0.5) * Fz) / rho;
+    }
+}
+
+// Marks the tiles of vertex v's stencil for the step `step`: act[tile] =
+// step + 1 and bit v of the tile's vertex mask (all 64 lanes of the vertex's
+// wavefront, lane = stencil offset; each tile is marked by the lane at the
+// opening of its runs).  The mask update is an atomic OR whose result is not
+// waited for.
+__device__ __forceinline__ void mark_vertex(int v, const StencilRuns &r, int lane, const Grid &g, uint32_t *act,
+                                            uint64_t *mask, int nwords, uint32_t step)
+{
+    const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
+    if ((r.mx >> kx) & (r.my >> ky) & (r.mz >> kz) & 1u) {
+        const int tile = stencil_tile(g, r, kx, ky, kz);
+        act[tile] = step + 1u;
+        atomicOr((unsigned long long *)&mask[(long long)tile * nwords + (v >> 6)], 1ull << (v & 63));
+    }
+}
+
+// One wavefront per vertex, one lane per stencil node: interpolation of
+// u(t+1) (from k_moments on fluid nodes, the wall velocity beyond the walls),
+// Euler update, and the marks of the tiles the vertex reaches at t + 1.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *__restrict__ U,
+                                              const uint32_t *__restrict__ stamp, uint32_t *ctr, uint32_t *act,
+                                              uint64_t *mask, int *err, LBArgs a, MeshArgs m)
 {
     const Grid &g = a.g;
     const int lane = threadIdx.x & 63;
     const int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t t = ctr[P];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0)
         ctr[1 - P] = t + 1u;
-        acnt[P] = 0u;  // this step's tile list has been consumed
-    }
-    if (v < m.nv) {
-        const int nv = m.nv;
-        const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
-        if (fabs(qx) < 1e6 && fabs(qy) < 1e6 && fabs(qz) < 1e6) {
-            const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
-            const int bx = (int)floor(qx) - 1, by = (int)floor(qy) - 1, bz = (int)floor(qz) - 1;
-            const T w = phi4<T>(T((double)(bx + kx) - qx)) * phi4<T>(T((double)(by + ky) - qy)) *
-                        phi4<T>(T((double)(bz + kz) - qz));
-            const int x = wrapi(bx + kx, g.nx), y = wrapi(by + ky, g.ny);
-            int z = bz + kz;
-            T ux, uy, uz;
-            if (g.walls && z < 1) {
-                ux = T(a.ulo[0]); uy = T(a.ulo[1]); uz = T(a.ulo[2]);
-            } else if (g.walls && z > g.nz - 2) {
-                ux = T(a.uhi[0]); uy = T(a.uhi[1]); uz = T(a.uhi[2]);
-            } else {
-                if (!g.walls)
-                    z = wrapi(z, g.nz);
-                const int zf = z - g.zoff;
-                T d[19];
-                // populations at t+1 (after this step's LB): swapped layout when t+1 is odd
-                load_pops<T, P == 0>(f, g, x, y, zf, d);
-                T drho = T(0), mx = T(0), my = T(0), mz = T(0);
-#pragma unroll
-                for (int i = 0; i < 19; ++i) {
-                    drho += d[i];
-                    if (cx(i) != 0) mx += T(cx(i)) * d[i];
-                    if (cy(i) != 0) my += T(cy(i)) * d[i];
-                    if (cz(i) != 0) mz += T(cz(i)) * d[i];
-                }
-                const long long me = nidx(g, x, y, zf);
-                // F is read unconditionally and used if the tile carries this step's stamp
-                const T fibx = Fib[me], fiby = Fib[g.n + me], fibz = Fib[2 * g.n + me];
-                const bool fresh = stamp[tile_of(g, x, y, zf)] == t + 1u;
-                T Fx = T(a.body[0]), Fy = T(a.body[1]), Fz = T(a.body[2]);
-                if (fresh) {
-                    Fx += fibx;
-                    Fy += fiby;
-                    Fz += fibz;
-                }
-                if (a.has_fext) {
-                    Fx += Fext[me];
-                    Fy += Fext[g.n + me];
-                    Fz += Fext[2 * g.n + me];
-                }
-                const T rho = T(a.rho0) + drho;
-                ux = (mx + T(0.5) * Fx) / rho;
-                uy = (my + T(0.5) * Fy) / rho;
-                uz = (mz + T(0.5) * Fz) / rho;
-            }
-            const T sx = wave_sum<T>(ux * w), sy = wave_sum<T>(uy * w), sz = wave_sum<T>(uz * w);
-            const double nqx = qx + double(sx), nqy = qy + double(sy), nqz = qz + double(sz);
-            if (lane == 0) {
-                q[v] = nqx;
-                q[nv + v] = nqy;
-                q[2 * nv + v] = nqz;
-            }
-            list_vertex(v, nqx, nqy, nqz, lane, g, cnt, list, acnt, alist, act, t + 1u, 1 - P, err);
-        } else if (lane == 0) {
+    if (v >= m.nv)
+        return;
+    const int nv = m.nv;
+    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+    if (!(fabs(qx) < 1e6 && fabs(qy) < 1e6 && fabs(qz) < 1e6)) {
+        if (lane == 0)
             atomicOr(err, kErrNonFinite);
-        }
+        return;
     }
+    const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
+    const int bx = (int)floor(qx) - 1, by = (int)floor(qy) - 1, bz = (int)floor(qz) - 1;
+    const T w = phi4<T>(T((double)(bx + kx) - qx)) * phi4<T>(T((double)(by + ky) - qy)) *
+                phi4<T>(T((double)(bz + kz) - qz));
+    const int x = wrapi(bx + kx, g.nx), y = wrapi(by + ky, g.ny);
+    int z = bz + kz;
+    T ux, uy, uz;
+    if (g.walls && z < 1) {
+        ux = T(a.ulo[0]); uy = T(a.ulo[1]); uz = T(a.ulo[2]);
+    } else if (g.walls && z > g.nz - 2) {
+        ux = T(a.uhi[0]); uy = T(a.uhi[1]); uz = T(a.uhi[2]);
+    } else {
+        if (!g.walls)
+            z = wrapi(z, g.nz);
+        const int zf = z - g.zoff;
+        const long long me = nidx(g, x, y, zf);
+        // every fluid stencil node lies in an active tile of this step; U is
+        // read unconditionally and used if the tile carries this step's stamp
+        const T u0 = U[me], u1 = U[g.n + me], u2 = U[2 * g.n + me];
+        const bool fresh = stamp[tile_of(g, x, y, zf)] == t + 1u;
+        ux = fresh ? u0 : T(0);
+        uy = fresh ? u1 : T(0);
+        uz = fresh ? u2 : T(0);
+    }
+    const T sx = wave_sum<T>(ux * w), sy = wave_sum<T>(uy * w), sz = wave_sum<T>(uz * w);
+    const double nqx = qx + double(sx), nqy = qy + double(sy), nqz = qz + double(sz);
+    if (lane == 0) {
+        q[v] = nqx;
+        q[nv + v] = nqy;
+        q[2 * nv + v] = nqz;
+    }
+    if (fabs(nqx) < 1e6 && fabs(nqy) < 1e6 && fabs(nqz) < 1e6)
+        mark_vertex(v, stencil_runs(g, nqx, nqy, nqz), lane, g, act, mask, m.nwords, t + 1u);
+    else if (lane == 0)
+        atomicOr(err, kErrNonFinite);
 }
 
-__global__ __launch_bounds__(256) void k_bin(const double *__restrict__ q, uint32_t *cnt, int *list,
-                                             uint32_t *acnt, int *alist, uint32_t *act, const uint32_t *ctr,
-                                             int *err, Grid g, MeshArgs m, int p)
+// marks of the current step t = ctr[p] from the stored positions (after a
+// reset of the positions or the state; masks cleared beforehand)
+__global__ __launch_bounds__(256) void k_stamp(const double *__restrict__ q, uint32_t *act, uint64_t *mask,
+                                               const uint32_t *__restrict__ ctr, int *err, Grid g, MeshArgs m, int p)
 {
     const int lane = threadIdx.x & 63;
     const int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (v >= m.nv)
         return;
-    list_vertex(v, q[v], q[m.nv + v], q[2 * m.nv + v], lane, g, cnt, list, acnt, alist, act, ctr[p], p, err);
+    const double qx = q[v], qy = q[m.nv + v], qz = q[2 * m.nv + v];
+    if (fabs(qx) < 1e6 && fabs(qy) < 1e6 && fabs(qz) < 1e6)
+        mark_vertex(v, stencil_runs(g, qx, qy, qz), lane, g, act, mask, m.nwords, ctr[p]);
+    else if (lane == 0)
+        atomicOr(err, kErrNonFinite);
 }
 
 // ---------------------------------------------------------------------------
@@ -1084,15 +1302,20 @@ hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, h
     return hipGetLastError();
 }
 
-hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s)
+template <typename T, int P>
+static void forces_launch(const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s)
 {
-    const int blocks = m.nparts;
+    k_forces<T, P><<<m.nparts + 1, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.inc_off, d.fref, (T *)d.phiSW, (T *)d.gV,
+                                                 d.base, (T *)d.wts, d.partials, d.act, d.acnt, d.alist, d.ctr, d.err,
+                                                 g, m);
+}
+
+hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)
+{
     if (prec == 0)
-        k_forces<double><<<blocks, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.inc_off, d.fref, (double *)d.phiSW,
-                                                (double *)d.gV, d.base, (double *)d.wts, d.partials, d.err, g, m);
+        p ? forces_launch<double, 1>(d, g, m, s) : forces_launch<double, 0>(d, g, m, s);
     else
-        k_forces<float><<<blocks, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.inc_off, d.fref, (float *)d.phiSW,
-                                               (float *)d.gV, d.base, (float *)d.wts, d.partials, d.err, g, m);
+        p ? forces_launch<float, 1>(d, g, m, s) : forces_launch<float, 0>(d, g, m, s);
     return hipGetLastError();
 }
 
@@ -1100,10 +1323,11 @@ template <typename T, bool ODD>
 static void bulk_forces_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s)
 {
     const dim3 bl = lb_block(a.g), gr = lb_grid(a.g);
-    const int nblocks = m.nparts + (int)(gr.x * gr.y * gr.z);
+    const int nblocks = m.nparts + 1 + (int)(gr.x * gr.y * gr.z);
     k_bulk_forces<T, ODD><<<nblocks, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.inc_off, d.fref, (T *)d.phiSW, (T *)d.gV,
-                                                   d.base, (T *)d.wts, d.partials, (T *)d.f, (const T *)d.Fext,
-                                                   d.act, d.ctr, d.err, a, m, (int)bl.x, (int)gr.x, (int)gr.y);
+                                                   d.base, (T *)d.wts, d.partials, d.acnt, d.alist, (T *)d.f,
+                                                   (const T *)d.Fext, d.act, d.ctr, d.err, a, m, (int)bl.x, (int)gr.x,
+                                                   (int)gr.y);
 }
 
 hipError_t launch_bulk_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
@@ -1119,15 +1343,15 @@ template <typename T, int P>
 static void spread_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int blocks, hipStream_t s)
 {
     k_spread<T, P><<<blocks, 256, 0, s>>>(d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV, d.partials,
-                                          d.ctr, d.cnt, d.list, d.acnt, d.alist, (T *)d.F, d.stamp, (T *)d.f,
+                                          d.ctr, d.mask, d.acnt, d.alist, (T *)d.F, d.stamp, (T *)d.f,
                                           (const T *)d.Fext, d.err, a, m);
 }
 
 hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
 {
-    // one dispatch round: as many blocks as the CUs hold at once (LDS-limited:
-    // 3 per CU in FP32, 1 in FP64); the blocks stride over the active tiles
-    const int fit = d.num_cus * (prec == 0 ? 1 : 3);
+    // one dispatch round: as many blocks as the CUs hold at once (register-
+    // limited: 2 per CU in FP32, 1 in FP64); the blocks stride over the active tiles
+    const int fit = d.num_cus * (prec == 0 ? 1 : 2);
     const int blocks = a.g.nt < fit ? a.g.nt : fit;
     if (prec == 0)
         p ? spread_launch<double, 1>(d, a, m, blocks, s) : spread_launch<double, 0>(d, a, m, blocks, s);
@@ -1139,9 +1363,12 @@ hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs
 template <typename T, int P>
 static void move_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s)
 {
+    const int tiles = a.g.nt;
+    const int mblocks = (tiles + 3) / 4 < d.num_cus ? (tiles + 3) / 4 : d.num_cus;
+    k_moments<T, P><<<mblocks, 256, 0, s>>>((const T *)d.f, (const T *)d.F, (const T *)d.Fext, d.acnt, d.alist,
+                                            (T *)d.U, a);
     const int blocks = (m.nv + 3) / 4;
-    k_move<T, P><<<blocks, 256, 0, s>>>(d.q, (const T *)d.f, (const T *)d.F, (const T *)d.Fext, d.stamp, d.ctr,
-                                        d.cnt, d.list, d.acnt, d.alist, d.act, d.err, a, m);
+    k_move<T, P><<<blocks, 256, 0, s>>>(d.q, (const T *)d.U, d.stamp, d.ctr, d.act, d.mask, d.err, a, m);
 }
 
 hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
@@ -1153,9 +1380,9 @@ hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &
     return hipGetLastError();
 }
 
-hipError_t launch_bin(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)
+hipError_t launch_stamp(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)
 {
-    k_bin<<<(m.nv + 3) / 4, 256, 0, s>>>(d.q, d.cnt, d.list, d.acnt, d.alist, d.act, d.ctr, d.err, g, m, p);
+    k_stamp<<<(m.nv + 3) / 4, 256, 0, s>>>(d.q, d.act, d.mask, d.ctr, d.err, g, m, p);
     return hipGetLastError();
 }
 

@@ -110,6 +110,7 @@ def lib():
             "iblb_set_timing": [_vp, C.c_int32],
             "iblb_kernel_time": [_vp, C.c_char_p, _dp, C.POINTER(C.c_int64)],
             "iblb_reset_timing": [_vp],
+            "iblb_active_nodes": [_vp, C.POINTER(C.c_int64)],
             "iblb_destroy": [_vp],
         }
         for name, args in sig.items():
@@ -206,6 +207,12 @@ class Simulation:
             self.add_mesh(mesh)
         self.set_graph(graph)
 
+    @property
+    def stream(self):
+        """The torch.cuda.Stream all of this context's work runs on (None when
+        the library owns its stream)."""
+        return self._stream
+
     # -- plumbing
     def _check(self, rc: int):
         if rc != IBLB_OK:
@@ -234,6 +241,12 @@ class Simulation:
         n = C.c_int64()
         self._check(lib().iblb_kernel_time(self.h, name.encode(), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def active_nodes(self) -> int:
+        """Fluid nodes in the active tiles of the last completed step."""
+        n = C.c_int64()
+        self._check(lib().iblb_active_nodes(self.h, C.byref(n)))
+        return n.value
 
     # -- stepping
     def step(self, n: int = 1):

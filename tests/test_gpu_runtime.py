@@ -129,3 +129,43 @@ def test_graph_with_odd_starts_and_counts(prec):
     with iblb.Simulation(w.domain, w.mesh, precision=prec, graph=False) as h:
         h.step(16)
         assert np.array_equal(h.vertices(), qa) and np.array_equal(h.populations(), fa)
+
+
+def _stencil_tile_nodes(q, dom):
+    """Fluid nodes of the 4x4x4 tiles reached by the 4^3 stencils of the
+    vertices at q (x, y periodic; z periodic or clipped to the fluid layers)."""
+    walls = dom.wall_mode == iblb.WALLS_Z
+    zoff, nzf = (1, dom.nz - 2) if walls else (0, dom.nz)
+    tiles = set()
+    for p in q:
+        b = np.floor(p).astype(np.int64) - 1
+        for k in range(64):
+            x = (b[0] + (k & 3)) % dom.nx
+            y = (b[1] + ((k >> 2) & 3)) % dom.ny
+            z = b[2] + (k >> 4)
+            zf = z - zoff if walls else z % dom.nz
+            if 0 <= zf < nzf:
+                tiles.add((x // 4, y // 4, zf // 4))
+    return sum(min(4, dom.nx - 4 * tx) * min(4, dom.ny - 4 * ty) * min(4, nzf - 4 * tz) for tx, ty, tz in tiles)
+
+
+@pytest.mark.parametrize("case", ["walls_ragged", "periodic_ragged"])
+def test_active_nodes_are_the_stencil_tiles(case):
+    """The tiles the step treats as active (their LB runs with the spreading)
+    are exactly those reached by a vertex stencil at the step's positions."""
+    if case == "walls_ragged":
+        dom = Domain(26, 21, 18, tau=0.9, u_wall_lo=(0.002, 0, 0))
+        mesh = sphere_mesh(2, 4.5, (1.3, 10.2, 0.5 + 4.5 + 0.6), (2e-3, 1e-3, 1e-3), amplitude=0.02, seed=5,
+                           eps_lo=2e-3, r_cut=2.0)
+    else:
+        dom = Domain(21, 19, 17, wall_mode=iblb.PERIODIC_ALL)
+        mesh = sphere_mesh(2, 4.0, (19.6, 0.7, 16.2), (1e-3, 0.0, 1e-3), amplitude=0.05, seed=3)
+    announce(f"active nodes {case}")
+    with iblb.Simulation(dom, mesh, precision=iblb.FP64) as g:
+        assert g.active_nodes() == 0
+        for before in (0, 5):
+            g.step(before)
+            q = g.vertices()
+            g.step(1)
+            n = g.active_nodes()
+            assert 0 < n < dom.n_fluid and n == _stencil_tile_nodes(q, dom)
