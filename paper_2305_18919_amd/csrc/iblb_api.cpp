@@ -32,7 +32,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 struct Layout {
     // byte offsets into the workspace; domain part then mesh part
     size_t f, F, stamp, ctr, err, scratch, dom_end;
-    size_t q, Xref, faces, fref, inc_off, inc4, U, phiSW, gV, base, wts, partials, mask, act, acnt, alist, mesh_end;
+    size_t q, Xref, faces, fref, inc4, U, phiSW, gV, base, wts, partials, mask, act, acnt, alist, mesh_end;
 };
 
 Grid make_grid(const iblb_domain_desc &d)
@@ -52,7 +52,21 @@ Grid make_grid(const iblb_domain_desc &d)
     return g;
 }
 
-Layout make_layout(const Grid &g, size_t ts, int nv, int nf)
+// Incidence slots per vertex: 8 x ceil(max valence / 8), so that the eight
+// lanes of a vertex in the force kernel find its entries at fixed positions.
+int incidence_slots(const iblb_mesh_desc *m)
+{
+    if (!m || !m->faces || m->n_vertices <= 0 || m->n_faces <= 0) return 8;
+    std::vector<int> val((size_t)m->n_vertices, 0);
+    int mx = 0;
+    for (int j = 0; j < 3 * m->n_faces; ++j) {
+        const int v = m->faces[j];
+        if (v >= 0 && v < m->n_vertices) mx = std::max(mx, ++val[v]);
+    }
+    return 8 * std::max(1, (mx + 7) / 8);
+}
+
+Layout make_layout(const Grid &g, size_t ts, int nv, int nf, int slots)
 {
     Layout L;
     size_t o = 0;
@@ -73,8 +87,7 @@ Layout make_layout(const Grid &g, size_t ts, int nv, int nf)
     L.Xref = take((size_t)3 * nv * 8);
     L.faces = take((size_t)3 * nf * 4);
     L.fref = take((size_t)5 * nf * 8);
-    L.inc_off = take((size_t)(nv + 1) * 4);
-    L.inc4 = take((size_t)3 * nf * 16);
+    L.inc4 = take((size_t)nv * slots * 16);
     L.U = take(nv ? (size_t)3 * g.n * ts : 0);
     L.phiSW = take((size_t)3 * nv * ts);
     L.gV = take((size_t)3 * nv * ts);
@@ -362,7 +375,8 @@ int iblb_workspace_bytes(const iblb_domain_desc *dom, const iblb_mesh_desc *mesh
     if (rc) return rc;
     const Grid g = make_grid(*dom);
     const size_t ts = dom->precision == IBLB_FP64 ? 8 : 4;
-    const Layout L = make_layout(g, ts, mesh ? mesh->n_vertices : 0, mesh ? mesh->n_faces : 0);
+    if (mesh && (mesh->n_vertices < 0 || mesh->n_faces < 0 || (mesh->n_faces > 0 && !mesh->faces))) return IBLB_E_INVAL;
+    const Layout L = make_layout(g, ts, mesh ? mesh->n_vertices : 0, mesh ? mesh->n_faces : 0, incidence_slots(mesh));
     *bytes = mesh ? L.mesh_end : L.dom_end;
     return IBLB_OK;
 }
@@ -380,7 +394,7 @@ int iblb_create(const iblb_domain_desc *dom, void *dev_workspace, size_t workspa
     c->prec = dom->precision;
     c->ts = c->prec == IBLB_FP64 ? 8 : 4;
     c->g = make_grid(*dom);
-    c->L = make_layout(c->g, c->ts, 0, 0);
+    c->L = make_layout(c->g, c->ts, 0, 0, 8);
     auto bail = [&](int code) {
         iblb_destroy(c);
         return code;
@@ -473,18 +487,16 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     }
     if (!(V0 > 0.0)) return fail(c, IBLB_E_MESH, "reference volume not positive (faces must point outward)");
 
-    // vertex -> (face, corner), faces ascending
-    std::vector<int> off(nv + 1, 0);
-    std::vector<int4> inc((size_t)3 * nf);
-    for (int j = 0; j < nf; ++j)
-        for (int k = 0; k < 3; ++k) off[mesh->faces[3 * j + k] + 1]++;
-    for (int i = 0; i < nv; ++i) off[i + 1] += off[i];
+    // vertex -> (face, corner), faces ascending, in `slots` fixed slots per
+    // vertex; unused slots carry w = -1
+    const int slots = incidence_slots(mesh);
+    std::vector<int4> inc((size_t)nv * slots, make_int4(0, 0, 0, -1));
     {
-        std::vector<int> fill(off.begin(), off.end() - 1);
+        std::vector<int> fill((size_t)nv, 0);
         for (int j = 0; j < nf; ++j)
             for (int k = 0; k < 3; ++k) {
                 const int *f = mesh->faces + 3 * j;
-                inc[fill[f[k]]++] = make_int4(f[0], f[1], f[2], (j << 2) | k);
+                inc[(size_t)f[k] * slots + fill[f[k]]++] = make_int4(f[0], f[1], f[2], (j << 2) | k);
             }
     }
     // structure-of-arrays copies
@@ -499,7 +511,7 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
         for (int k = 0; k < 3; ++k) fs[(size_t)k * nf + j] = mesh->faces[3 * j + k];
 
     // device memory for the mesh part
-    const Layout L = make_layout(c->g, c->ts, nv, nf);
+    const Layout L = make_layout(c->g, c->ts, nv, nf, slots);
     char *mb = nullptr;
     if (c->own_ws || c->ws_bytes < L.mesh_end) {
         // the mesh block is not covered by a caller's workspace: allocate it here
@@ -516,7 +528,6 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     d.Xref = (double *)(mb + L.Xref);
     d.faces = (int *)(mb + L.faces);
     d.fref = (double *)(mb + L.fref);
-    d.inc_off = (int *)(mb + L.inc_off);
     d.inc4 = (int4 *)(mb + L.inc4);
     d.U = mb + L.U;
     d.phiSW = mb + L.phiSW;
@@ -532,7 +543,6 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     HIP_TRY(c, hipMemcpyAsync(d.Xref, Xs.data(), Xs.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d.faces, fs.data(), fs.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d.fref, fref.data(), fref.size() * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(d.inc_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d.inc4, inc.data(), inc.size() * 16, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemsetAsync(d.partials, 0, (size_t)2 * ((nv + 31) / 32) * 8, c->stream));
 
@@ -552,6 +562,7 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     m.kv_over_V0 = mesh->k_v / V0;
     m.nparts = (nv + 31) / 32;
     m.nwords = (nv + 63) / 64;
+    m.slots = slots;
     c->V0 = V0;
     c->nv = nv;
     c->nf = nf;

@@ -53,6 +53,7 @@ struct MeshArgs {
     double kv_over_V0;    // k_V / V0
     int nparts;           // force-kernel blocks (32 vertices each) = number of volume partials
     int nwords;           // 64-bit words of one tile's vertex mask, ceil(nv / 64)
+    int slots;            // incidence slots per vertex (a multiple of 8)
 };
 
 // Device buffers of one context (typed as void* where the precision varies).
@@ -68,8 +69,7 @@ struct Dev {
     double *Xref;         // [3][nv] FP64 reference (stress-free) positions
     int *faces;           // [3][nf]
     double *fref;         // [5][nf]: Ginv11, Ginv12, Ginv22, A0, detG
-    int *inc_off;         // [nv+1]
-    int4 *inc4;           // [3 nf]: (a, b, c, face*4 + corner), vertex-major, faces ascending
+    int4 *inc4;           // [nv][slots]: (a, b, c, face*4 + corner), faces ascending; unused slots w = -1
     void *U;              // [3][n] u(t+1) on the nodes of the active tiles
     void *phiSW;          // [3][nv] elastic + wall force
     void *gV;             // [3][nv] dV/dq

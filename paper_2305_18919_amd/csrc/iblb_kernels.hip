@@ -464,10 +464,11 @@ __device__ __forceinline__ double volume_change(const double *__restrict__ X, in
 }
 
 // Eight lanes per vertex (32 vertices per 256-thread block); lane k of a
-// vertex handles its incident faces k, k + 8, ...; the group sums by butterfly.
+// vertex handles its incident faces k, k + 8, ... (fixed incidence slots, so
+// the first entry is read without a lookup); the group sums by butterfly.
 template <typename T>
 __device__ __forceinline__ void forces_block(int blk, const double *__restrict__ q, const double *__restrict__ Xref,
-                                             const int4 *__restrict__ inc4, const int *__restrict__ inc_off,
+                                             const int4 *__restrict__ inc4,
                                              const double *__restrict__ fref, T *__restrict__ phiSW,
                                              T *__restrict__ gVout, Base *__restrict__ base, T *__restrict__ wts,
                                              double *__restrict__ partials, int *err, const Grid &g,
@@ -482,9 +483,11 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
     T gv[3] = {T(0), T(0), T(0)};
     if (v < nv) {
         const T a1 = T(m.alpha[0]), a2 = T(m.alpha[1]), a3 = T(m.alpha[2]);
-        const int k1 = inc_off[v + 1];
-        for (int k = inc_off[v] + sub; k < k1; k += 8) {
-            const int4 e = inc4[k];
+        const int4 *ev = inc4 + (long long)v * m.slots;
+        for (int k = sub; k < m.slots; k += 8) {
+            const int4 e = ev[k];
+            if (e.w < 0)
+                break;  // the vertex's entries come first, unused slots last
             const int ia = e.x, ib = e.y, ic = e.z, j = e.w >> 2, corner = e.w & 3;
             const double ax = q[ia], ay = q[nv + ia], az = q[2 * nv + ia];
             const double bx = q[ib], by = q[nv + ib], bz = q[2 * nv + ib];
@@ -608,7 +611,7 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
 // step's active tiles.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, const double *__restrict__ Xref,
-                                                const int4 *__restrict__ inc4, const int *__restrict__ inc_off,
+                                                const int4 *__restrict__ inc4,
                                                 const double *__restrict__ fref, T *__restrict__ phiSW,
                                                 T *__restrict__ gVout, Base *__restrict__ base,
                                                 T *__restrict__ wts, double *__restrict__ partials,
@@ -616,7 +619,7 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, co
                                                 const uint32_t *__restrict__ ctr, int *err, Grid g, MeshArgs m)
 {
     if ((int)blockIdx.x < m.nparts)
-        forces_block<T>(blockIdx.x, q, Xref, inc4, inc_off, fref, phiSW, gVout, base, wts, partials, err, g, m);
+        forces_block<T>(blockIdx.x, q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, err, g, m);
     else
         scan_block(act, acnt, alist, ctr[P], g);
 }
@@ -628,7 +631,7 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, co
 // tiles of the step were stamped in `act` by the previous step's move.
 template <typename T, bool ODD>
 __global__ __launch_bounds__(256) void k_bulk_forces(const double *__restrict__ q, const double *__restrict__ Xref,
-                                                     const int4 *__restrict__ inc4, const int *__restrict__ inc_off,
+                                                     const int4 *__restrict__ inc4,
                                                      const double *__restrict__ fref, T *__restrict__ phiSW,
                                                      T *__restrict__ gVout, Base *__restrict__ base,
                                                      T *__restrict__ wts, double *__restrict__ partials,
@@ -639,7 +642,7 @@ __global__ __launch_bounds__(256) void k_bulk_forces(const double *__restrict__ 
 {
     const uint32_t t = ctr[ODD ? 1 : 0];
     if ((int)blockIdx.x < m.nparts) {
-        forces_block<T>(blockIdx.x, q, Xref, inc4, inc_off, fref, phiSW, gVout, base, wts, partials, err, a.g, m);
+        forces_block<T>(blockIdx.x, q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, err, a.g, m);
         return;
     }
     if ((int)blockIdx.x == m.nparts) {
@@ -681,46 +684,60 @@ __device__ __forceinline__ double volume_factor(const double *__restrict__ parti
 // ---------------------------------------------------------------------------
 // Spreading, one 256-thread block per active tile (gather form, no FP atomics)
 // ---------------------------------------------------------------------------
-// A listed vertex as the gather needs it: stencil corner, phi4 weights,
-// phi_S + phi_W and dV/dq.
+// A listed vertex as the gather needs it: its phi4 weight at each of the
+// tile's four local coordinates per axis (zero where the stencil misses that
+// coordinate), and phi_S + phi_W and dV/dq.
 template <typename T>
 struct Staged {
-    int4 b;
     T w[12];
     T ph[3], gv[3];
 };
 
+// Weights of one axis at the tile's local coordinates origin + 0..3: the
+// stencil of corner b covers node b + k, k = 0..3 (wrapped with period n when
+// n > 0).
+template <typename T>
+__device__ __forceinline__ void local_weights(const T *sw, int b, int origin, int n, T *out)
+{
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        int k = origin + l - b;
+        if (n > 0 && k < 0)
+            k += n;
+        out[l] = (unsigned)k < 4u ? sw[k & 3] : T(0);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ Staged<T> stage_load(int v, const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV, int nv,
-                                                int *err)
+                                                int *err, const Grid &g, int x0, int y0, int z0)
 {
     Staged<T> s;
-    // a corrupt list entry is never used as an index: its corner is put far
-    // outside the grid, so it weighs zero everywhere
+    // a corrupt list entry is never used as an index: it weighs zero everywhere
     const bool ok = (unsigned)v < (unsigned)nv;
     if (!ok)
         atomicOr(err, kErrList);
     const int u = ok ? v : 0;
     const Base bs = base[u];
-    s.b = ok ? make_int4(bs.x, bs.y, bs.z, 0) : make_int4(-1000000, -1000000, -1000000, 0);
+    T w[12];
     if constexpr (sizeof(T) == 4) {
         const float4 *pw = reinterpret_cast<const float4 *>(wts) + 3 * u;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const float4 w4 = pw[k];
-            s.w[4 * k] = w4.x;
-            s.w[4 * k + 1] = w4.y;
-            s.w[4 * k + 2] = w4.z;
-            s.w[4 * k + 3] = w4.w;
+            w[4 * k] = w4.x;
+            w[4 * k + 1] = w4.y;
+            w[4 * k + 2] = w4.z;
+            w[4 * k + 3] = w4.w;
         }
     } else {
         const double2 *pw = reinterpret_cast<const double2 *>(wts) + 6 * u;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const double2 w2 = pw[k];
-            s.w[2 * k] = w2.x;
-            s.w[2 * k + 1] = w2.y;
+            w[2 * k] = w2.x;
+            w[2 * k + 1] = w2.y;
         }
     }
 #pragma unroll
@@ -728,19 +745,39 @@ __device__ __forceinline__ Staged<T> stage_load(int v, const Base *__restrict__ 
         s.ph[c] = phiSW[c * nv + u];
         s.gv[c] = gV[c * nv + u];
     }
+    local_weights<T>(w, bs.x, x0, g.nx, s.w);
+    local_weights<T>(w + 4, bs.y, y0, g.ny, s.w + 4);
+    local_weights<T>(w + 8, bs.z, z0, g.walls ? 0 : g.nz, s.w + 8);
+    if (!ok || !bs.ok) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            s.w[k] = T(0);
+    }
     return s;
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_store(const Staged<T> &s, int e, T kf, T *sw, T *sph)
+{
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        sw[e * 12 + k] = s.w[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        sph[e * 4 + c] = s.ph[c] - kf * s.gv[c];
 }
 
 // One 256-thread block (four wavefronts) per active tile.  The tile's vertex
 // mask (bit v set when vertex v's stencil reaches the tile) is read whole,
 // thread k taking the k-th contiguous run of words; a block-wide prefix sum of
-// the words' bit counts places every set bit, so the listed vertices come out
-// in ascending index order, and the words are cleared for the next step.  All
-// four wavefronts then stage the listed vertices in LDS; wavefront w sums the
-// w-th contiguous quarter of the ordered list for the 64 nodes of the tile
-// (one per lane), and the four partial sums are added in wavefront order, so
-// every node's sum has a fixed order.  Wavefront 0 finishes with the LB update
-// of the tile's nodes, whose populations it fetched at the start.
+// the words' bit counts gives every word the list position of its first set
+// bit, and the wavefronts then expand the words, one lane per bit, so the
+// listed vertices come out in ascending index order.  All four wavefronts
+// stage the listed vertices in LDS; wavefront w sums the w-th contiguous
+// quarter of the ordered list for the 64 nodes of the tile (one per lane), and
+// the four partial sums are added in wavefront order, so every node's sum has
+// a fixed order.  Wavefront 0 finishes with the LB update of the tile's nodes,
+// whose populations it fetched at the start.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
@@ -751,16 +788,19 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
                                                 const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m)
 {
     const Grid &g = a.g;
+    constexpr int kMaxWords = kMaxVertices / 64;
     __shared__ int sid[kTileCap];
-    __shared__ int4 sbase[kTileCap];
     __shared__ __align__(16) T sw[kTileCap * 12];
     __shared__ __align__(16) T sph[kTileCap * 4];
     __shared__ T part[3][3][64];
+    __shared__ uint64_t swd[kMaxWords];
+    __shared__ int swo[kMaxWords];
     __shared__ int swt[4];
     __shared__ T skfac;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nv = m.nv, W = m.nwords;
     const int J = (W + 255) >> 8;  // words per thread, at most 4
+    const uint64_t below = (1ull << lane) - 1ull;
     // the count of active tiles and the block's first tile are read together
     // (block index < grid size <= tile count, so the slot exists); the volatile
     // read keeps the compiler from deferring it past the test on the count
@@ -775,8 +815,8 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
         const int tz = tile / (g.ntx * g.nty);
         const int rem = tile - tz * g.ntx * g.nty;
         const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
-        const int x = tx * 4 + (lane & 3), y = ty * 4 + ((lane >> 2) & 3), zf = tz * 4 + (lane >> 4);
-        const int z = zf + g.zoff;
+        const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+        const int x = tx * 4 + lx, y = ty * 4 + ly, zf = tz * 4 + lz;
         const bool node = x < g.nx && y < g.ny && zf < g.nzf;
         T d[19];
         if (wave == 0 && node)
@@ -805,68 +845,52 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
                 atomicOr(err, kErrOverflow);
             nent = kTileCap;
         }
-        int o = incl - c;
-        for (int w = 0; w < wave; ++w)
-            o += swt[w];
+        {
+            int o = incl - c;
+            for (int w = 0; w < wave; ++w)
+                o += swt[w];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            uint64_t bits = wv[j];
-            while (bits != 0ull) {
-                if (o < kTileCap)
-                    sid[o] = (w0 + j) * 64 + __builtin_ctzll(bits);
-                ++o;
-                bits &= bits - 1ull;
+            for (int j = 0; j < 4; ++j)
+                if (j < J && w0 + j < W) {
+                    swd[w0 + j] = wv[j];
+                    swo[w0 + j] = o;
+                    o += __popcll(wv[j]);
+                }
+        }
+        __syncthreads();
+        // expand the words, one lane per bit
+#pragma unroll 4
+        for (int w = wave; w < W; w += 4) {
+            const uint64_t word = swd[w];
+            if (word != 0ull && ((word >> lane) & 1ull)) {
+                const int pos = swo[w] + __popcll(word & below);
+                if (pos < kTileCap)
+                    sid[pos] = w * 64 + lane;
             }
         }
         __syncthreads();
-        // stage each listed vertex's stencil corner, weights and total force
+        // stage each listed vertex's local weights and total force
         {
+            const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 4 + g.zoff;
             const bool has0 = tid < nent, has1 = tid + 256 < nent;
             const T kf = skfac;
             Staged<T> s0, s1;
-            if (has0) s0 = stage_load<T>(sid[tid], base, wts, phiSW, gV, nv, err);
-            if (has1) s1 = stage_load<T>(sid[tid + 256], base, wts, phiSW, gV, nv, err);
-            if (has0) {
-                sbase[tid] = s0.b;
-#pragma unroll
-                for (int k = 0; k < 12; ++k)
-                    sw[tid * 12 + k] = s0.w[k];
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    sph[tid * 4 + cc] = s0.ph[cc] - kf * s0.gv[cc];
-            }
-            if (has1) {
-                const int e = tid + 256;
-                sbase[e] = s1.b;
-#pragma unroll
-                for (int k = 0; k < 12; ++k)
-                    sw[e * 12 + k] = s1.w[k];
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    sph[e * 4 + cc] = s1.ph[cc] - kf * s1.gv[cc];
-            }
+            if (has0) s0 = stage_load<T>(sid[tid], base, wts, phiSW, gV, nv, err, g, x0, y0, z0);
+            if (has1) s1 = stage_load<T>(sid[tid + 256], base, wts, phiSW, gV, nv, err, g, x0, y0, z0);
+            if (has0) stage_store<T>(s0, tid, kf, sw, sph);
+            if (has1) stage_store<T>(s1, tid + 256, kf, sw, sph);
         }
         __syncthreads();
         // this wavefront's quarter of the ordered list
         const int chunk = (nent + 3) >> 2;
         const int e0 = wave * chunk, e1 = min(nent, e0 + chunk);
         T Fx = T(0), Fy = T(0), Fz = T(0);
-#pragma unroll 4
+#pragma unroll 8
         for (int e = e0; e < e1; ++e) {
-            const int4 b = sbase[e];
-            int dx = x - b.x;
-            dx += dx < 0 ? g.nx : 0;
-            int dy = y - b.y;
-            dy += dy < 0 ? g.ny : 0;
-            int dz = z - b.z;
-            dz += (!g.walls && dz < 0) ? g.nz : 0;
-            const bool in = (unsigned)dx < 4u && (unsigned)dy < 4u && (unsigned)dz < 4u;
-            // outside the stencil: clamp the index and weigh by zero
-            const T w = sw[e * 12 + (dx & 3)] * sw[e * 12 + 4 + (dy & 3)] * sw[e * 12 + 8 + (dz & 3)];
-            const T wi = in ? w : T(0);
-            Fx += sph[e * 4 + 0] * wi;
-            Fy += sph[e * 4 + 1] * wi;
-            Fz += sph[e * 4 + 2] * wi;
+            const T w = sw[e * 12 + lx] * sw[e * 12 + 4 + ly] * sw[e * 12 + 8 + lz];
+            Fx += sph[e * 4 + 0] * w;
+            Fy += sph[e * 4 + 1] * w;
+            Fz += sph[e * 4 + 2] * w;
         }
         if (wave > 0) {
             part[wave - 1][0][lane] = Fx;
@@ -874,8 +898,8 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
             part[wave - 1][2][lane] = Fz;
         }
         __syncthreads();
-        // the mask words are cleared for the next step only now: a barrier
-        // waits for a wavefront's outstanding stores
+        // the mask words are cleared for the next step (stores are not waited
+        // for by the barriers)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if (wv[j] != 0ull)
@@ -1305,7 +1329,7 @@ hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, h
 template <typename T, int P>
 static void forces_launch(const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s)
 {
-    k_forces<T, P><<<m.nparts + 1, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.inc_off, d.fref, (T *)d.phiSW, (T *)d.gV,
+    k_forces<T, P><<<m.nparts + 1, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.fref, (T *)d.phiSW, (T *)d.gV,
                                                  d.base, (T *)d.wts, d.partials, d.act, d.acnt, d.alist, d.ctr, d.err,
                                                  g, m);
 }
@@ -1324,7 +1348,7 @@ static void bulk_forces_launch(const Dev &d, const LBArgs &a, const MeshArgs &m,
 {
     const dim3 bl = lb_block(a.g), gr = lb_grid(a.g);
     const int nblocks = m.nparts + 1 + (int)(gr.x * gr.y * gr.z);
-    k_bulk_forces<T, ODD><<<nblocks, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.inc_off, d.fref, (T *)d.phiSW, (T *)d.gV,
+    k_bulk_forces<T, ODD><<<nblocks, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.fref, (T *)d.phiSW, (T *)d.gV,
                                                    d.base, (T *)d.wts, d.partials, d.acnt, d.alist, (T *)d.f,
                                                    (const T *)d.Fext, d.act, d.ctr, d.err, a, m, (int)bl.x, (int)gr.x,
                                                    (int)gr.y);
