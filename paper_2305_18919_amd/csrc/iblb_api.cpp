@@ -93,7 +93,7 @@ Layout make_layout(const Grid &g, size_t ts, int nv, int nf, int slots)
     L.gV = take((size_t)3 * nv * ts);
     L.base = take((size_t)nv * sizeof(Base));
     L.wts = take((size_t)12 * nv * ts);
-    L.partials = take((size_t)2 * nparts * 8);
+    L.partials = take((size_t)nparts * 8);
     L.mask = take((size_t)g.nt * ((nv + 63) / 64) * 8);
     L.act = take((size_t)g.nt * 4);
     L.acnt = take(4);
@@ -254,23 +254,22 @@ hipError_t launch_kernel(iblb_ctx *c, int which, int p, hipStream_t st)
     const Dev &d = c->d;
     switch (which) {
     case K_FORCES: return launch_forces(c->prec, d, c->g, c->m, p, st);
-    case K_SPREAD: return launch_spread(c->prec, d, c->lb, c->m, p, st);
+    case K_SPREAD: return launch_spread(c->prec, d, c->lb, c->m, p, 0, st);
     case K_LB: return launch_lb(c->prec, d, c->lb, p, c->has_mesh ? 1 : 0, st);
     default: return launch_move(c->prec, d, c->lb, c->m, p, st);
     }
 }
 
-// One step of parity p.  With a mesh: one dispatch computes the interface
-// forces, the list of active tiles and the bulk LB (nodes outside the active
-// tiles) side by side, then the spread updates the active tiles (force + LB), then the
-// moments of the active tiles and the move.  Timed
-// steps launch forces and bulk LB as separate kernels so that each one's
-// duration can be read.
+// One step of parity p.  With a mesh: the interface forces and the list of
+// active tiles, then one dispatch that spreads onto the active tiles (force +
+// their LB) and runs the LB of all other nodes, then the moments of the
+// active tiles and the move.  Timed steps launch the bulk LB as a kernel of
+// its own so that each duration can be read.
 hipError_t enqueue_step(iblb_ctx *c, int p, bool timed)
 {
     if (c->has_mesh && !timed) {
-        hipError_t e = launch_bulk_forces(c->prec, c->d, c->lb, c->m, p, c->stream);
-        if (e == hipSuccess) e = launch_kernel(c, K_SPREAD, p, c->stream);
+        hipError_t e = launch_kernel(c, K_FORCES, p, c->stream);
+        if (e == hipSuccess) e = launch_spread(c->prec, c->d, c->lb, c->m, p, 1, c->stream);
         if (e == hipSuccess) e = launch_kernel(c, K_MOVE, p, c->stream);
         return e;
     }
@@ -477,7 +476,7 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
         fref[(size_t)nf + j] = -G12 / det;
         fref[(size_t)2 * nf + j] = G11 / det;
         fref[(size_t)3 * nf + j] = 0.5 * std::sqrt(det);
-        fref[(size_t)4 * nf + j] = det;
+        fref[(size_t)4 * nf + j] = 1.0 / det;
         const double A[3] = {a[0] - o[0], a[1] - o[1], a[2] - o[2]};
         const double B[3] = {b[0] - o[0], b[1] - o[1], b[2] - o[2]};
         const double C[3] = {cc[0] - o[0], cc[1] - o[1], cc[2] - o[2]};
@@ -544,7 +543,7 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     HIP_TRY(c, hipMemcpyAsync(d.faces, fs.data(), fs.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d.fref, fref.data(), fref.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d.inc4, inc.data(), inc.size() * 16, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemsetAsync(d.partials, 0, (size_t)2 * ((nv + 31) / 32) * 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(d.partials, 0, (size_t)((nv + 31) / 32) * 8, c->stream));
 
     MeshArgs &m = c->m;
     m.nv = nv;

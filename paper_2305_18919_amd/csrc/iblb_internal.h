@@ -68,14 +68,14 @@ struct Dev {
     double *q;            // [3][nv] FP64 positions
     double *Xref;         // [3][nv] FP64 reference (stress-free) positions
     int *faces;           // [3][nf]
-    double *fref;         // [5][nf]: Ginv11, Ginv12, Ginv22, A0, detG
+    double *fref;         // [5][nf]: Ginv11, Ginv12, Ginv22, A0, 1/detG
     int4 *inc4;           // [nv][slots]: (a, b, c, face*4 + corner), faces ascending; unused slots w = -1
     void *U;              // [3][n] u(t+1) on the nodes of the active tiles
     void *phiSW;          // [3][nv] elastic + wall force
     void *gV;             // [3][nv] dV/dq
     Base *base;           // [nv]
     void *wts;            // [nv][12] phi4 weights (x 0..3, y 0..3, z 0..3)
-    double *partials;     // [2][nparts]: sum (V_j - V0_j), sum A_j per force block
+    double *partials;     // [nparts]: sum (V_j - V0_j) per force block
     uint64_t *mask;       // [nt][nwords] bit v: vertex v's stencil reaches the tile (set by the
                           // move, read and cleared by the next step's spreading)
     uint32_t *act;        // [nt] step+1 for which the tile is active (stamped by the previous move)
@@ -93,10 +93,10 @@ hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hip
 hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, hipStream_t s);
 // interface forces and the step's list of active tiles
 hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s);
-// forces, active-tile list and bulk LB in one dispatch (independent within a step)
-hipError_t launch_bulk_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);
-// spreading of the active tiles followed by their LB update
-hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);
+// spreading of the active tiles followed by their LB update; with_lb != 0:
+// the same dispatch also runs the LB of the nodes outside the active tiles
+hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, int with_lb,
+                         hipStream_t s);
 // moments of the active tiles, then interpolation, move, and the next step's
 // act stamps and vertex masks
 hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);

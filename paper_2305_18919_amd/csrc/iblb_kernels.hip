@@ -3,22 +3,22 @@
 // implementation" section), plus the debug and query reductions.
 //
 // Per step, in stream order:
-//   k_forces  one thread per vertex: elastic force -dW/dq of the incident faces
-//             (Eqs. generalised_energy1, nodal_force_S), dV/dq (Eq.
+//   k_forces  eight lanes per vertex, one incident face each: elastic force
+//             -dW/dq (Eqs. generalised_energy1, nodal_force_S), dV/dq (Eq.
 //             nodal_force_V), wall force (Eq. LJ_interaction), FP64 block
-//             partials of V - V0 and A, and the vertex's phi4 stencil weights;
-//             eight lanes per vertex, one incident face each
-//   k_spread  one wavefront per active 4x4x4 tile: gathers phi_i w_i(x) of the
+//             partials of V - V0, and the vertex's phi4 stencil weights; one
+//             more block compacts the step's active tiles
+//   k_spread  one block per active 4x4x4 tile: gathers phi_i w_i(x) of the
 //             vertices whose stencil reaches the tile, in ascending vertex order
-//             (Eq. ibm-governing_eq2); no floating-point atomics
-//   k_lb      one thread per fluid node: AA-pattern in-place stream + BGK
-//             collision with Guo forcing and half-way moving-wall bounce-back
-//             (Eqs. LBeq, feq)
-//   k_move    one wavefront per vertex, one lane per stencil node: u(t+1) from
-//             the streamed populations and F(t)/2, interpolation (Eq.
-//             ibm-governing_eq1), Euler update (Eq. ibm_update_pos), and the
-//             tile lists of the next step; it also advances the device step
-//             counter.
+//             (Eq. ibm-governing_eq2), no floating-point atomics, then the LB
+//             update of the tile's nodes with that force; further blocks of the
+//             same dispatch run the LB of every other fluid node (Eqs. LBeq, feq)
+//   k_moments u(t+1) on the nodes of the active tiles, with F(t)/2
+//   k_move    one wavefront per vertex, one lane per stencil node:
+//             interpolation (Eq. ibm-governing_eq1), Euler update (Eq.
+//             ibm_update_pos), the stamps and vertex masks of the tiles the
+//             vertex reaches at t + 1, and the device step counter.
+// Without a mesh the step is k_lb alone, over every fluid node.
 //
 // Step counter: ctr[2] in device memory, ctr[t & 1] = t.  Every kernel of
 // step t is launched with p = t & 1 and reads t from ctr[p]; the last kernel
@@ -100,10 +100,22 @@ __device__ __forceinline__ T lj(T eps, T xi, T rc, T d)
         return T(0);
     if (d < T(0.5) * xi)
         d = T(0.5) * xi;
-    const T s = xi / d;
+    const T rd = T(1) / d;
+    const T s = xi * rd;
     const T s2 = s * s;
     const T s6 = s2 * s2 * s2;
-    return T(48) * eps * (s6 * s6 - T(0.5) * s6) / d;
+    return T(48) * eps * (s6 * s6 - T(0.5) * s6) * rd;
+}
+
+// Store that writes through the L2 of the issuing XCD to memory (system-scope
+// coherence bits on a plain vector store).  Used for the populations: every
+// kernel boundary writes back and invalidates the per-XCD L2s, and data
+// written through leaves nothing dirty there, which shortens the boundary;
+// the LB streams its output anyway.
+template <typename T>
+__device__ __forceinline__ void store_through(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 template <typename T>
@@ -240,9 +252,9 @@ __device__ __forceinline__ void lb_collide(T *__restrict__ f, const T *__restric
             post -= T(6) * w * rho * cuw;
         }
         if (!ODD || !fluid)
-            f[opp(i) * n + me] = post;
+            store_through(&f[opp(i) * n + me], post);
         else
-            f[i * n + dst] = post;
+            store_through(&f[i * n + dst], post);
     }
 }
 
@@ -254,6 +266,26 @@ __device__ __forceinline__ void lb_node(T *__restrict__ f, const T *__restrict__
     T d[19];
     load_pops<T, ODD>(f, a.g, x, y, zf, d);
     lb_collide<T, ODD>(f, Fext, err, a, x, y, zf, d, fx, fy, fz);
+}
+
+// LB of one node of the LB tiling (blocks of bxw x (256 / bxw) nodes in one
+// z layer, numbered x fastest), unless its tile is active at step t (those
+// nodes are updated by the spreading, with their force).
+template <typename T, bool ODD>
+__device__ __forceinline__ void bulk_lb_block(int b, T *__restrict__ f, const T *__restrict__ Fext,
+                                              const uint32_t *__restrict__ act, uint32_t t, int *err, const LBArgs &a,
+                                              int bxw, int nbx, int nby)
+{
+    const int zf = b / (nbx * nby);
+    const int rem = b - zf * nbx * nby;
+    const int byi = rem / nbx, bxi = rem - byi * nbx;
+    const int x = bxi * bxw + (int)(threadIdx.x % (unsigned)bxw);
+    const int y = byi * (256 / bxw) + (int)(threadIdx.x / (unsigned)bxw);
+    if (x >= a.g.nx || y >= a.g.ny)
+        return;
+    if (act[tile_of(a.g, x, y, zf)] == t + 1u)
+        return;
+    lb_node<T, ODD>(f, Fext, err, a, x, y, zf, T(0), T(0), T(0));
 }
 
 // LB over the fluid nodes.  Without a mesh (act == null) every node, and the
@@ -429,11 +461,13 @@ __device__ __forceinline__ void scan_block(const uint32_t *__restrict__ act, uin
 // ---------------------------------------------------------------------------
 // Interface forces, one thread per vertex
 // ---------------------------------------------------------------------------
+constexpr double kSixth = 1.0 / 6.0;
+
 __device__ __forceinline__ void cross6(double ux, double uy, double uz, double vx, double vy, double vz, double *o)
 {
-    o[0] = (uy * vz - uz * vy) / 6.0;
-    o[1] = (uz * vx - ux * vz) / 6.0;
-    o[2] = (ux * vy - uy * vx) / 6.0;
+    o[0] = (uy * vz - uz * vy) * kSixth;
+    o[1] = (uz * vx - ux * vz) * kSixth;
+    o[2] = (ux * vy - uy * vx) * kSixth;
 }
 
 __device__ __forceinline__ double triple(double ax, double ay, double az, double bx, double by, double bz, double cx_,
@@ -460,7 +494,7 @@ __device__ __forceinline__ double volume_change(const double *__restrict__ X, in
                      triple(Ax, Ay, Az, Bx, By, Bz, dcx, dcy, dcz) + triple(dax, day, daz, dbx, dby, dbz, Cx, Cy, Cz) +
                      triple(dax, day, daz, Bx, By, Bz, dcx, dcy, dcz) + triple(Ax, Ay, Az, dbx, dby, dbz, dcx, dcy, dcz) +
                      triple(dax, day, daz, dbx, dby, dbz, dcx, dcy, dcz);
-    return t / 6.0;
+    return t * kSixth;
 }
 
 // Eight lanes per vertex (32 vertices per 256-thread block); lane k of a
@@ -474,11 +508,11 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
                                              double *__restrict__ partials, int *err, const Grid &g,
                                              const MeshArgs &m)
 {
-    __shared__ double red[2][256];
+    __shared__ double red[4];
     const int sub = threadIdx.x & 7;
     const int v = blk * 32 + (threadIdx.x >> 3);
     const int nv = m.nv, nf = m.nf;
-    double dvol = 0.0, darea = 0.0;
+    double dvol = 0.0;
     T fs[3] = {T(0), T(0), T(0)};
     T gv[3] = {T(0), T(0), T(0)};
     if (v < nv) {
@@ -500,14 +534,15 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
             const T g22 = e2x * e2x + e2y * e2y + e2z * e2z;
             const T detg = g11 * g22 - g12 * g12;
             const T Gi11 = T(fref[j]), Gi12 = T(fref[nf + j]), Gi22 = T(fref[2 * nf + j]);
-            const T A0 = T(fref[3 * nf + j]), detG = T(fref[4 * nf + j]);
-            const T J = detg / detG;
+            const T A0 = T(fref[3 * nf + j]), idetG = T(fref[4 * nf + j]);
+            const T J = detg * idetG;
             const T lnJ = log(J);
             const T w1 = T(0.5) * a3;
-            const T w2 = (T(0.5) * (a1 - a3) + T(0.25) * (a1 + a2) * lnJ) / J;
-            const T S11 = A0 * (w1 * Gi11 + w2 * g22 / detG);
-            const T S12 = A0 * (w1 * Gi12 - w2 * g12 / detG);
-            const T S22 = A0 * (w1 * Gi22 + w2 * g11 / detG);
+            // w2 adj(g) / det G, with w2 = [(a1 - a3)/2 + (a1 + a2)/4 ln J] / J
+            const T w2g = (T(0.5) * (a1 - a3) + T(0.25) * (a1 + a2) * lnJ) / J * idetG;
+            const T S11 = A0 * (w1 * Gi11 + w2g * g22);
+            const T S12 = A0 * (w1 * Gi12 - w2g * g12);
+            const T S22 = A0 * (w1 * Gi22 + w2g * g11);
             const T Fb[3] = {T(-2) * (S11 * e1x + S12 * e2x), T(-2) * (S11 * e1y + S12 * e2y),
                              T(-2) * (S11 * e1z + S12 * e2z)};
             const T Fc[3] = {T(-2) * (S12 * e1x + S22 * e2x), T(-2) * (S12 * e1y + S22 * e2y),
@@ -522,12 +557,8 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
                 fs[1] += -Fb[1] - Fc[1];
                 fs[2] += -Fb[2] - Fc[2];
                 cross6(Bx, By, Bz, Cx, Cy, Cz, dv);
-                // owner of the face: accumulate V_j - V0_j and A_j in FP64
+                // owner of the face: accumulate V_j - V0_j in FP64
                 dvol += volume_change(Xref, nv, ia, ib, ic, ax, ay, az, bx, by, bz, cxv, cyv, czv, m.origin);
-                const double ex = bx - ax, ey = by - ay, ez = bz - az;
-                const double fx = cxv - ax, fy = cyv - ay, fz = czv - az;
-                const double nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
-                darea += 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
             } else if (corner == 1) {
                 fs[0] += Fb[0];
                 fs[1] += Fb[1];
@@ -590,21 +621,14 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
             atomicOr(err, kErrNonFinite);
         }
     }
-    // FP64 block partials of V - V0 and A (fixed tree order)
-    red[0][threadIdx.x] = dvol;
-    red[1][threadIdx.x] = darea;
+    // FP64 block partial of V - V0: a butterfly in each wavefront, then the
+    // four wavefront sums in order (a fixed order)
+    dvol = wave_sum<double>(dvol);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = dvol;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + st];
-            red[1][threadIdx.x] += red[1][threadIdx.x + st];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        partials[blk] = red[0][0];
-        partials[m.nparts + blk] = red[1][0];
-    }
+    if (threadIdx.x == 0)
+        partials[blk] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // Blocks [0, nparts) compute the interface forces, block nparts lists the
@@ -622,44 +646,6 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, co
         forces_block<T>(blockIdx.x, q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, err, g, m);
     else
         scan_block(act, acnt, alist, ctr[P], g);
-}
-
-// The first nparts + 1 blocks are those of k_forces (latency-bound); the rest
-// run the bulk LB (bandwidth-bound) in the same dispatch, so the two overlap
-// without a second queue.  The bulk blocks use the LB kernel's tiling
-// (lb_block_x wide, 256 / lb_block_x rows), numbered x fastest.  The active
-// tiles of the step were stamped in `act` by the previous step's move.
-template <typename T, bool ODD>
-__global__ __launch_bounds__(256) void k_bulk_forces(const double *__restrict__ q, const double *__restrict__ Xref,
-                                                     const int4 *__restrict__ inc4,
-                                                     const double *__restrict__ fref, T *__restrict__ phiSW,
-                                                     T *__restrict__ gVout, Base *__restrict__ base,
-                                                     T *__restrict__ wts, double *__restrict__ partials,
-                                                     uint32_t *acnt, int *alist, T *__restrict__ f,
-                                                     const T *__restrict__ Fext, const uint32_t *__restrict__ act,
-                                                     const uint32_t *__restrict__ ctr, int *err, LBArgs a, MeshArgs m,
-                                                     int bxw, int nbx, int nby)
-{
-    const uint32_t t = ctr[ODD ? 1 : 0];
-    if ((int)blockIdx.x < m.nparts) {
-        forces_block<T>(blockIdx.x, q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, err, a.g, m);
-        return;
-    }
-    if ((int)blockIdx.x == m.nparts) {
-        scan_block(act, acnt, alist, t, a.g);
-        return;
-    }
-    const int b = blockIdx.x - m.nparts - 1;
-    const int zf = b / (nbx * nby);
-    const int rem = b - zf * nbx * nby;
-    const int byi = rem / nbx, bxi = rem - byi * nbx;
-    const int x = bxi * bxw + (int)(threadIdx.x % (unsigned)bxw);
-    const int y = byi * (256 / bxw) + (int)(threadIdx.x / (unsigned)bxw);
-    if (x >= a.g.nx || y >= a.g.ny)
-        return;
-    if (act[tile_of(a.g, x, y, zf)] == t + 1u)
-        return;
-    lb_node<T, ODD>(f, Fext, err, a, x, y, zf, T(0), T(0), T(0));
 }
 
 // k_V (V - V0)/V0 from the force-kernel partials, summed by one wavefront in a
@@ -767,7 +753,13 @@ __device__ __forceinline__ void stage_store(const Staged<T> &s, int e, T kf, T *
         sph[e * 4 + c] = s.ph[c] - kf * s.gv[c];
 }
 
-// One 256-thread block (four wavefronts) per active tile.  The tile's vertex
+// Blocks [0, nsp) spread: one 256-thread block (four wavefronts) per active
+// tile, striding over the list.  Blocks from nsp on (if any) run the LB of the
+// nodes outside the active tiles: it is bandwidth-bound, the spreading is
+// latency-bound, and the two touch disjoint nodes (in the AA pattern each node
+// reads and writes only its own 19 slots), so they share the dispatch.
+//
+// Spreading: the tile's vertex
 // mask (bit v set when vertex v's stencil reaches the tile) is read whole,
 // thread k taking the k-th contiguous run of words; a block-wide prefix sum of
 // the words' bit counts gives every word the list position of its first set
@@ -785,9 +777,14 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
                                                 uint64_t *__restrict__ mask, const uint32_t *__restrict__ acnt,
                                                 const int *__restrict__ alist, T *__restrict__ F,
                                                 uint32_t *__restrict__ stamp, T *__restrict__ f,
-                                                const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m)
+                                                const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m,
+                                                const uint32_t *__restrict__ act, int nsp, int bxw, int nbx, int nby)
 {
     const Grid &g = a.g;
+    if ((int)blockIdx.x >= nsp) {
+        bulk_lb_block<T, P == 1>(blockIdx.x - nsp, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
+        return;
+    }
     constexpr int kMaxWords = kMaxVertices / 64;
     __shared__ int sid[kTileCap];
     __shared__ __align__(16) T sw[kTileCap * 12];
@@ -802,13 +799,13 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
     const int J = (W + 255) >> 8;  // words per thread, at most 4
     const uint64_t below = (1ull << lane) - 1ull;
     // the count of active tiles and the block's first tile are read together
-    // (block index < grid size <= tile count, so the slot exists); the volatile
+    // (block index < nsp <= tile count, so the slot exists); the volatile
     // read keeps the compiler from deferring it past the test on the count
     const uint32_t na = acnt[0];
     int tile = ((const volatile int *)alist)[blockIdx.x];
     const uint32_t t = ctr[P];
-    for (uint32_t ai = blockIdx.x; ai < na; ai += gridDim.x) {
-        const uint32_t an = ai + gridDim.x;
+    for (uint32_t ai = blockIdx.x; ai < na; ai += nsp) {
+        const uint32_t an = ai + nsp;
         const int next = alist[an < na ? an : ai];
         // this lane's node; wavefront 0 fetches its populations now, next to
         // the tile's mask words
@@ -1343,44 +1340,28 @@ hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &
     return hipGetLastError();
 }
 
-template <typename T, bool ODD>
-static void bulk_forces_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s)
+template <typename T, int P>
+static void spread_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int nsp, int with_lb, hipStream_t s)
 {
     const dim3 bl = lb_block(a.g), gr = lb_grid(a.g);
-    const int nblocks = m.nparts + 1 + (int)(gr.x * gr.y * gr.z);
-    k_bulk_forces<T, ODD><<<nblocks, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.fref, (T *)d.phiSW, (T *)d.gV,
-                                                   d.base, (T *)d.wts, d.partials, d.acnt, d.alist, (T *)d.f,
-                                                   (const T *)d.Fext, d.act, d.ctr, d.err, a, m, (int)bl.x, (int)gr.x,
-                                                   (int)gr.y);
+    const int nlb = with_lb ? (int)(gr.x * gr.y * gr.z) : 0;
+    k_spread<T, P><<<nsp + nlb, 256, 0, s>>>(d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV,
+                                             d.partials, d.ctr, d.mask, d.acnt, d.alist, (T *)d.F, d.stamp,
+                                             (T *)d.f, (const T *)d.Fext, d.err, a, m, d.act, nsp, (int)bl.x,
+                                             (int)gr.x, (int)gr.y);
 }
 
-hipError_t launch_bulk_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
+hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, int with_lb,
+                         hipStream_t s)
 {
-    if (prec == 0)
-        p ? bulk_forces_launch<double, true>(d, a, m, s) : bulk_forces_launch<double, false>(d, a, m, s);
-    else
-        p ? bulk_forces_launch<float, true>(d, a, m, s) : bulk_forces_launch<float, false>(d, a, m, s);
-    return hipGetLastError();
-}
-
-template <typename T, int P>
-static void spread_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int blocks, hipStream_t s)
-{
-    k_spread<T, P><<<blocks, 256, 0, s>>>(d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV, d.partials,
-                                          d.ctr, d.mask, d.acnt, d.alist, (T *)d.F, d.stamp, (T *)d.f,
-                                          (const T *)d.Fext, d.err, a, m);
-}
-
-hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
-{
-    // one dispatch round: as many blocks as the CUs hold at once (register-
-    // limited: 2 per CU in FP32, 1 in FP64); the blocks stride over the active tiles
+    // spreading blocks: as many as the CUs hold at once (register-limited: 2
+    // per CU in FP32, 1 in FP64), striding over the active tiles
     const int fit = d.num_cus * (prec == 0 ? 1 : 2);
-    const int blocks = a.g.nt < fit ? a.g.nt : fit;
+    const int nsp = a.g.nt < fit ? a.g.nt : fit;
     if (prec == 0)
-        p ? spread_launch<double, 1>(d, a, m, blocks, s) : spread_launch<double, 0>(d, a, m, blocks, s);
+        p ? spread_launch<double, 1>(d, a, m, nsp, with_lb, s) : spread_launch<double, 0>(d, a, m, nsp, with_lb, s);
     else
-        p ? spread_launch<float, 1>(d, a, m, blocks, s) : spread_launch<float, 0>(d, a, m, blocks, s);
+        p ? spread_launch<float, 1>(d, a, m, nsp, with_lb, s) : spread_launch<float, 0>(d, a, m, nsp, with_lb, s);
     return hipGetLastError();
 }
 
