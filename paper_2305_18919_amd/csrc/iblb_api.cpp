@@ -253,7 +253,7 @@ hipError_t launch_kernel(iblb_ctx *c, int which, int p, hipStream_t st)
 {
     const Dev &d = c->d;
     switch (which) {
-    case K_FORCES: return launch_forces(c->prec, d, c->g, c->m, p, st);
+    case K_FORCES: return launch_forces(c->prec, d, c->lb, c->m, p, 0, st);
     case K_SPREAD: return launch_spread(c->prec, d, c->lb, c->m, p, 0, st);
     case K_LB: return launch_lb(c->prec, d, c->lb, p, c->has_mesh ? 1 : 0, st);
     default: return launch_move(c->prec, d, c->lb, c->m, p, st);
@@ -262,13 +262,13 @@ hipError_t launch_kernel(iblb_ctx *c, int which, int p, hipStream_t st)
 
 // One step of parity p.  With a mesh: the interface forces and the list of
 // active tiles, then one dispatch that spreads onto the active tiles (force +
-// their LB) and runs the LB of all other nodes, then the moments of the
-// active tiles and the move.  Timed steps launch the bulk LB as a kernel of
+// their LB), then the moments of the active tiles and the move.  The LB of
+// all other nodes runs in the first two dispatches, split between them.  Timed steps launch the bulk LB as a kernel of
 // its own so that each duration can be read.
 hipError_t enqueue_step(iblb_ctx *c, int p, bool timed)
 {
     if (c->has_mesh && !timed) {
-        hipError_t e = launch_kernel(c, K_FORCES, p, c->stream);
+        hipError_t e = launch_forces(c->prec, c->d, c->lb, c->m, p, 1, c->stream);
         if (e == hipSuccess) e = launch_spread(c->prec, c->d, c->lb, c->m, p, 1, c->stream);
         if (e == hipSuccess) e = launch_kernel(c, K_MOVE, p, c->stream);
         return e;

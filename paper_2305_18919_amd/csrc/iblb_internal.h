@@ -91,10 +91,13 @@ hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hip
 // bulk != 0: only the nodes outside this step's active tiles (mesh present);
 // bulk == 0: every node, and the kernel advances the step counter (no mesh)
 hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, hipStream_t s);
-// interface forces and the step's list of active tiles
-hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s);
+// interface forces and the step's list of active tiles; with_lb != 0: the same
+// dispatch also runs its share of the LB of the nodes outside the active tiles
+hipError_t launch_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, int with_lb,
+                         hipStream_t s);
 // spreading of the active tiles followed by their LB update; with_lb != 0:
-// the same dispatch also runs the LB of the nodes outside the active tiles
+// the same dispatch also runs its share of the LB of the nodes outside the
+// active tiles
 hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, int with_lb,
                          hipStream_t s);
 // moments of the active tiles, then interpolation, move, and the next step's

@@ -632,7 +632,9 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
 }
 
 // Blocks [0, nparts) compute the interface forces, block nparts lists the
-// step's active tiles.
+// step's active tiles, and the blocks after it (if any) run the first LB
+// blocks of the nodes outside the active tiles (the spreading dispatch runs
+// the rest).
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, const double *__restrict__ Xref,
                                                 const int4 *__restrict__ inc4,
@@ -640,12 +642,16 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, co
                                                 T *__restrict__ gVout, Base *__restrict__ base,
                                                 T *__restrict__ wts, double *__restrict__ partials,
                                                 const uint32_t *__restrict__ act, uint32_t *acnt, int *alist,
-                                                const uint32_t *__restrict__ ctr, int *err, Grid g, MeshArgs m)
+                                                const uint32_t *__restrict__ ctr, T *__restrict__ f,
+                                                const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m, int bxw,
+                                                int nbx, int nby)
 {
     if ((int)blockIdx.x < m.nparts)
-        forces_block<T>(blockIdx.x, q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, err, g, m);
+        forces_block<T>(blockIdx.x, q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, err, a.g, m);
+    else if ((int)blockIdx.x == m.nparts)
+        scan_block(act, acnt, alist, ctr[P], a.g);
     else
-        scan_block(act, acnt, alist, ctr[P], g);
+        bulk_lb_block<T, P == 1>(blockIdx.x - m.nparts - 1, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
 }
 
 // k_V (V - V0)/V0 from the force-kernel partials, summed by one wavefront in a
@@ -778,11 +784,12 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
                                                 const int *__restrict__ alist, T *__restrict__ F,
                                                 uint32_t *__restrict__ stamp, T *__restrict__ f,
                                                 const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m,
-                                                const uint32_t *__restrict__ act, int nsp, int bxw, int nbx, int nby)
+                                                const uint32_t *__restrict__ act, int nsp, int lb0, int bxw, int nbx,
+                                                int nby)
 {
     const Grid &g = a.g;
     if ((int)blockIdx.x >= nsp) {
-        bulk_lb_block<T, P == 1>(blockIdx.x - nsp, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
+        bulk_lb_block<T, P == 1>(lb0 + (int)blockIdx.x - nsp, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
         return;
     }
     constexpr int kMaxWords = kMaxVertices / 64;
@@ -1323,20 +1330,38 @@ hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, h
     return hipGetLastError();
 }
 
-template <typename T, int P>
-static void forces_launch(const Dev &d, const Grid &g, const MeshArgs &m, hipStream_t s)
+// Share of the LB blocks of the nodes outside the active tiles that runs in
+// the forces dispatch (the rest runs in the spreading dispatch), balancing the
+// two latency-bound kernels.  Measured on the 64^3 sheared capsule (FP32):
+// shares 0 / 0.2 / 0.35 / 0.5 / 0.6 / 0.7 / 0.8 gave 29.1 / 28.6 / 28.6 / 28.5 /
+// 28.7 / 29.8 / 29.8 us per step.
+constexpr double kLbShareWithForces = 0.45;
+
+int lb_blocks_with_forces(const Grid &g)
 {
-    k_forces<T, P><<<m.nparts + 1, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.fref, (T *)d.phiSW, (T *)d.gV,
-                                                 d.base, (T *)d.wts, d.partials, d.act, d.acnt, d.alist, d.ctr, d.err,
-                                                 g, m);
+    const dim3 gr = lb_grid(g);
+    const int nlb = (int)(gr.x * gr.y * gr.z);
+    return (int)(kLbShareWithForces * nlb + 0.5);
 }
 
-hipError_t launch_forces(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)
+template <typename T, int P>
+static void forces_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int nlb, hipStream_t s)
 {
+    const dim3 bl = lb_block(a.g), gr = lb_grid(a.g);
+    k_forces<T, P><<<m.nparts + 1 + nlb, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.fref, (T *)d.phiSW, (T *)d.gV, d.base,
+                                                       (T *)d.wts, d.partials, d.act, d.acnt, d.alist, d.ctr,
+                                                       (T *)d.f, (const T *)d.Fext, d.err, a, m, (int)bl.x,
+                                                       (int)gr.x, (int)gr.y);
+}
+
+hipError_t launch_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, int with_lb,
+                         hipStream_t s)
+{
+    const int nlb = with_lb ? lb_blocks_with_forces(a.g) : 0;
     if (prec == 0)
-        p ? forces_launch<double, 1>(d, g, m, s) : forces_launch<double, 0>(d, g, m, s);
+        p ? forces_launch<double, 1>(d, a, m, nlb, s) : forces_launch<double, 0>(d, a, m, nlb, s);
     else
-        p ? forces_launch<float, 1>(d, g, m, s) : forces_launch<float, 0>(d, g, m, s);
+        p ? forces_launch<float, 1>(d, a, m, nlb, s) : forces_launch<float, 0>(d, a, m, nlb, s);
     return hipGetLastError();
 }
 
@@ -1344,10 +1369,11 @@ template <typename T, int P>
 static void spread_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int nsp, int with_lb, hipStream_t s)
 {
     const dim3 bl = lb_block(a.g), gr = lb_grid(a.g);
-    const int nlb = with_lb ? (int)(gr.x * gr.y * gr.z) : 0;
+    const int lb0 = lb_blocks_with_forces(a.g);
+    const int nlb = with_lb ? (int)(gr.x * gr.y * gr.z) - lb0 : 0;
     k_spread<T, P><<<nsp + nlb, 256, 0, s>>>(d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV,
                                              d.partials, d.ctr, d.mask, d.acnt, d.alist, (T *)d.F, d.stamp,
-                                             (T *)d.f, (const T *)d.Fext, d.err, a, m, d.act, nsp, (int)bl.x,
+                                             (T *)d.f, (const T *)d.Fext, d.err, a, m, d.act, nsp, lb0, (int)bl.x,
                                              (int)gr.x, (int)gr.y);
 }
 
