@@ -58,8 +58,13 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+POP_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+DTYPE = {0: "f64", 1: "f32", 2: "f16 storage, f32 arithmetic", 3: "bf16 storage, f32 arithmetic"}
+
+
 def lb_bytes_per_node(precision: int) -> int:
-    return 38 * (8 if precision == 0 else 4)
+    return 38 * POP_BYTES[precision]
 
 
 def cpu_baseline(w, budget_s: float):
@@ -146,6 +151,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pass", dest="only", choices=["lb", "copy"], default=None)
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--precision", choices=sorted(PRECISIONS), default=None,
+                    help="population storage (default: the workload's, FP32 for shear64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
@@ -156,6 +163,10 @@ def main():
     from paper_2305_18919_amd import iblb
 
     w, prec = workload(args.workload)
+    if args.precision is not None:
+        prec = PRECISIONS[args.precision]
+        if prec != 1:
+            w.name = w.name.replace("_f32", "") + f"_{args.precision}"
     dom, mesh = w.domain, w.mesh
     if args.only == "copy":
         copy_pass(args.copy_mib, 10)
@@ -194,7 +205,7 @@ def main():
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == 1 else "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
         "config": {"workload": w.name, "grid": [dom.nx, dom.ny, dom.nz], "fluid_nodes": dom.n_fluid,
                    "vertices": mesh.n_vertices, "faces": mesh.n_faces, "tau": dom.tau,
                    "alpha": list(mesh.alpha), "positions": "f64", "launch": "hipGraph, 16 steps per replay"},

@@ -60,7 +60,12 @@ enum {
     IBLB_E_STATE = -5     /* call not valid in the current state */
 };
 
-enum { IBLB_FP64 = 0, IBLB_FP32_DEV = 1 };          /* population storage and LB arithmetic */
+enum {                                            /* population storage and LB arithmetic */
+    IBLB_FP64 = 0,
+    IBLB_FP32_DEV = 1,
+    IBLB_FP16_DEV = 2,
+    IBLB_BF16_DEV = 3
+};
 enum { IBLB_WALLS_Z = 0, IBLB_PERIODIC_ALL = 1 };   /* z boundary */
 
 typedef struct iblb_ctx iblb_ctx;
@@ -70,7 +75,11 @@ typedef struct {
     int32_t wall_mode;         /* IBLB_WALLS_Z or IBLB_PERIODIC_ALL */
     int32_t precision;         /* IBLB_FP64: FP64 populations and LB arithmetic;
                                   IBLB_FP32_DEV: FP32 deviations f - w rho0, FP32 LB and
-                                  interface arithmetic; positions, volume and area stay FP64 */
+                                  interface arithmetic; positions, volume and area stay FP64;
+                                  IBLB_FP16_DEV / IBLB_BF16_DEV: as FP32_DEV, but each
+                                  population is stored in 16 bits as (f - w rho0) / w,
+                                  times 2^12 for FP16 (|(f - w rho0) / w| < 16), rounded to
+                                  nearest even; the arithmetic stays FP32 */
     int32_t init_couette;      /* 0: fluid at rest; 1: f = f^eq(rho0, u linear between the walls) */
     double tau;                /* BGK relaxation time (> 1/2); viscosity (tau - 1/2)/3 */
     double rho0;               /* initial and reference density */

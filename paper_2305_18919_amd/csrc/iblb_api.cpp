@@ -66,7 +66,9 @@ int incidence_slots(const iblb_mesh_desc *m)
     return 8 * std::max(1, (mx + 7) / 8);
 }
 
-Layout make_layout(const Grid &g, size_t ts, int nv, int nf, int slots)
+// ps: bytes per stored population; ts: bytes per value of the other
+// per-node and per-vertex fields (F, U, vertex forces and weights)
+Layout make_layout(const Grid &g, size_t ps, size_t ts, int nv, int nf, int slots)
 {
     Layout L;
     size_t o = 0;
@@ -75,7 +77,7 @@ Layout make_layout(const Grid &g, size_t ts, int nv, int nf, int slots)
         o += align256(bytes);
         return at;
     };
-    L.f = take(19 * (size_t)g.n * ts);
+    L.f = take(19 * (size_t)g.n * ps);
     L.F = take(3 * (size_t)g.n * ts);
     L.stamp = take((size_t)g.nt * 4);
     L.ctr = take(2 * 4);
@@ -104,12 +106,15 @@ Layout make_layout(const Grid &g, size_t ts, int nv, int nf, int slots)
 
 bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
+size_t pop_bytes(int precision) { return precision == IBLB_FP64 ? 8 : (precision == IBLB_FP32_DEV ? 4 : 2); }
+
 }  // namespace
 
 struct iblb_ctx {
     iblb_domain_desc dom;
     int prec = 0;
-    size_t ts = 8;
+    size_t ps = 8;  // bytes per stored population
+    size_t ts = 8;  // bytes per value of the other fields
     Grid g;
     LBArgs lb;
     MeshArgs m;
@@ -162,7 +167,7 @@ int check_domain(const iblb_domain_desc *d, std::string &why)
     if (d->nx < 8 || d->ny < 8 || d->nz < 8) { why = "nx, ny, nz must be >= 8"; return IBLB_E_INVAL; }
     if ((long long)d->nx * d->ny * d->nz > (1ll << 31)) { why = "lattice too large"; return IBLB_E_INVAL; }
     if (d->wall_mode != IBLB_WALLS_Z && d->wall_mode != IBLB_PERIODIC_ALL) { why = "bad wall_mode"; return IBLB_E_INVAL; }
-    if (d->precision != IBLB_FP64 && d->precision != IBLB_FP32_DEV) { why = "bad precision"; return IBLB_E_INVAL; }
+    if (d->precision < IBLB_FP64 || d->precision > IBLB_BF16_DEV) { why = "bad precision"; return IBLB_E_INVAL; }
     if (!(d->tau > 0.5) || !std::isfinite(d->tau)) { why = "tau must be > 1/2"; return IBLB_E_INVAL; }
     if (!(d->rho0 > 0.0) || !std::isfinite(d->rho0)) { why = "rho0 must be > 0"; return IBLB_E_INVAL; }
     if (!finite3(d->u_wall_lo) || !finite3(d->u_wall_hi) || !finite3(d->body_force)) {
@@ -374,8 +379,10 @@ int iblb_workspace_bytes(const iblb_domain_desc *dom, const iblb_mesh_desc *mesh
     if (rc) return rc;
     const Grid g = make_grid(*dom);
     const size_t ts = dom->precision == IBLB_FP64 ? 8 : 4;
+    const size_t ps = pop_bytes(dom->precision);
     if (mesh && (mesh->n_vertices < 0 || mesh->n_faces < 0 || (mesh->n_faces > 0 && !mesh->faces))) return IBLB_E_INVAL;
-    const Layout L = make_layout(g, ts, mesh ? mesh->n_vertices : 0, mesh ? mesh->n_faces : 0, incidence_slots(mesh));
+    const Layout L = make_layout(g, ps, ts, mesh ? mesh->n_vertices : 0, mesh ? mesh->n_faces : 0,
+                                 incidence_slots(mesh));
     *bytes = mesh ? L.mesh_end : L.dom_end;
     return IBLB_OK;
 }
@@ -392,8 +399,9 @@ int iblb_create(const iblb_domain_desc *dom, void *dev_workspace, size_t workspa
     c->dom = *dom;
     c->prec = dom->precision;
     c->ts = c->prec == IBLB_FP64 ? 8 : 4;
+    c->ps = pop_bytes(c->prec);
     c->g = make_grid(*dom);
-    c->L = make_layout(c->g, c->ts, 0, 0, 8);
+    c->L = make_layout(c->g, c->ps, c->ts, 0, 0, 8);
     auto bail = [&](int code) {
         iblb_destroy(c);
         return code;
@@ -510,7 +518,7 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
         for (int k = 0; k < 3; ++k) fs[(size_t)k * nf + j] = mesh->faces[3 * j + k];
 
     // device memory for the mesh part
-    const Layout L = make_layout(c->g, c->ts, nv, nf, slots);
+    const Layout L = make_layout(c->g, c->ps, c->ts, nv, nf, slots);
     char *mb = nullptr;
     if (c->own_ws || c->ws_bytes < L.mesh_end) {
         // the mesh block is not covered by a caller's workspace: allocate it here
@@ -851,7 +859,7 @@ int iblb_save_state(iblb_ctx *c, void *host_buf, size_t *bytes)
 {
     if (!c || !bytes) return IBLB_E_INVAL;
     const size_t n = (size_t)c->g.n;
-    const size_t need = sizeof(StateHeader) + 19 * n * c->ts + 3 * n * c->ts + (size_t)c->g.nt * 4 +
+    const size_t need = sizeof(StateHeader) + 19 * n * c->ps + 3 * n * c->ts + (size_t)c->g.nt * 4 +
                         (size_t)3 * c->nv * 8;
     if (!host_buf) {
         *bytes = need;
@@ -873,8 +881,8 @@ int iblb_save_state(iblb_ctx *c, void *host_buf, size_t *bytes)
     char *p = (char *)host_buf;
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
-    HIP_TRY(c, hipMemcpy(p, c->d.f, 19 * n * c->ts, hipMemcpyDeviceToHost));
-    p += 19 * n * c->ts;
+    HIP_TRY(c, hipMemcpy(p, c->d.f, 19 * n * c->ps, hipMemcpyDeviceToHost));
+    p += 19 * n * c->ps;
     HIP_TRY(c, hipMemcpy(p, c->d.F, 3 * n * c->ts, hipMemcpyDeviceToHost));
     p += 3 * n * c->ts;
     HIP_TRY(c, hipMemcpy(p, c->d.stamp, (size_t)c->g.nt * 4, hipMemcpyDeviceToHost));
@@ -888,7 +896,7 @@ int iblb_load_state(iblb_ctx *c, const void *host_buf, size_t bytes)
 {
     if (!c || !host_buf) return IBLB_E_INVAL;
     const size_t n = (size_t)c->g.n;
-    const size_t need = sizeof(StateHeader) + 19 * n * c->ts + 3 * n * c->ts + (size_t)c->g.nt * 4 +
+    const size_t need = sizeof(StateHeader) + 19 * n * c->ps + 3 * n * c->ts + (size_t)c->g.nt * 4 +
                         (size_t)3 * c->nv * 8;
     if (bytes < need) return fail(c, IBLB_E_INVAL, "state buffer too small");
     StateHeader h;
@@ -899,8 +907,8 @@ int iblb_load_state(iblb_ctx *c, const void *host_buf, size_t bytes)
         return fail(c, IBLB_E_INVAL, "state buffer does not match this context");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const char *p = (const char *)host_buf + sizeof(h);
-    HIP_TRY(c, hipMemcpy(c->d.f, p, 19 * n * c->ts, hipMemcpyHostToDevice));
-    p += 19 * n * c->ts;
+    HIP_TRY(c, hipMemcpy(c->d.f, p, 19 * n * c->ps, hipMemcpyHostToDevice));
+    p += 19 * n * c->ps;
     HIP_TRY(c, hipMemcpy(c->d.F, p, 3 * n * c->ts, hipMemcpyHostToDevice));
     p += 3 * n * c->ts;
     HIP_TRY(c, hipMemcpy(c->d.stamp, p, (size_t)c->g.nt * 4, hipMemcpyHostToDevice));

@@ -58,7 +58,7 @@ struct MeshArgs {
 
 // Device buffers of one context (typed as void* where the precision varies).
 struct Dev {
-    void *f;              // [19][n] populations (deviation), AA layout
+    void *f;              // [19][n] populations (deviation; FP16/BF16: deviation / w_i, scaled), AA layout
     void *F;              // [3][n] IB force density of the step stamped in `stamp`
     void *Fext;           // [3][n] or null
     uint32_t *stamp;      // [nt] step+1 for which F of the tile is valid
@@ -85,7 +85,8 @@ struct Dev {
     int num_cus;          // compute units of the device (launch sizing)
 };
 
-// launchers (iblb_kernels.hip); precision 0 = FP64, 1 = FP32
+// launchers (iblb_kernels.hip); precision 0 = FP64, 1 = FP32, 2 = FP16 and
+// 3 = BF16 population storage (the last three compute in FP32)
 hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hipStream_t s);
 // p = t & 1 of the step (or of the current time for the debug kernels)
 // bulk != 0: only the nodes outside this step's active tiles (mesh present);

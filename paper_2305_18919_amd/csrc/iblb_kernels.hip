@@ -63,6 +63,36 @@ __device__ __forceinline__ constexpr T wgt(int i)
     return i == 0 ? T(1.0 / 3.0) : (i <= 6 ? T(1.0 / 18.0) : T(1.0 / 36.0));
 }
 
+// Population storage.  FP64 and FP32 hold the deviation f_i - w_i rho0 as
+// it is.  FP16 and BF16 hold it relative to w_i (h_i = (f_i - w_i rho0) / w_i),
+// FP16 scaled by 2^12 so that the deviations of slow flows (~1e-6) stay in its
+// normal range (|h_i| up to 16 fits); the arithmetic on them is FP32 (C).  The
+// conversions round to nearest even.  w_i = w_opp(i), so a population keeps
+// its scale wherever the AA pattern stores it.
+__device__ __forceinline__ constexpr float inv_w(int i) { return i == 0 ? 3.0f : (i <= 6 ? 18.0f : 36.0f); }
+
+template <typename S>
+struct Pop {
+    using C = S;
+    static __device__ __forceinline__ C get(S v, int) { return v; }
+    static __device__ __forceinline__ S put(C v, int) { return v; }
+};
+template <>
+struct Pop<_Float16> {
+    using C = float;
+    static __device__ __forceinline__ C get(_Float16 v, int i)
+    {
+        return float(v) * (i == 0 ? float(1.0 / 12288.0) : (i <= 6 ? float(1.0 / 73728.0) : float(1.0 / 147456.0)));
+    }
+    static __device__ __forceinline__ _Float16 put(C v, int i) { return (_Float16)(v * (4096.0f * inv_w(i))); }
+};
+template <>
+struct Pop<__bf16> {
+    using C = float;
+    static __device__ __forceinline__ C get(__bf16 v, int i) { return float(v) * wgt<float>(i); }
+    static __device__ __forceinline__ __bf16 put(C v, int i) { return (__bf16)(v * inv_w(i)); }
+};
+
 __device__ __forceinline__ int wrapi(int a, int n)
 {
     int r = a % n;
@@ -115,7 +145,11 @@ __device__ __forceinline__ T lj(T eps, T xi, T rc, T d)
 template <typename T>
 __device__ __forceinline__ void store_through(T *p, T v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if constexpr (sizeof(T) == 2)
+        __hip_atomic_store(reinterpret_cast<unsigned short *>(p), __builtin_bit_cast(unsigned short, v),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    else
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 template <typename T>
@@ -172,22 +206,23 @@ __device__ __forceinline__ bool shifted(const Grid &g, const Nbr &b, int x, int 
     return ok;
 }
 
-template <typename T, bool SWAPPED>
-__device__ __forceinline__ void load_pops(const T *__restrict__ f, const Grid &g, int x, int y, int zf, T *d)
+template <typename S, bool SWAPPED>
+__device__ __forceinline__ void load_pops(const S *__restrict__ f, const Grid &g, int x, int y, int zf,
+                                          typename Pop<S>::C *d)
 {
     const long long me = nidx(g, x, y, zf);
     const long long n = g.n;
     if (!SWAPPED) {
 #pragma unroll
         for (int i = 0; i < 19; ++i)
-            d[i] = f[i * n + me];
+            d[i] = Pop<S>::get(f[i * n + me], i);
     } else {
         const Nbr b = neighbours(g, x, y, zf);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             long long src;
             const bool ok = shifted(g, b, x, y, zf, i, -1, src);
-            d[i] = ok ? f[opp(i) * n + src] : f[i * n + me];
+            d[i] = Pop<S>::get(ok ? f[opp(i) * n + src] : f[i * n + me], i);
         }
     }
 }
@@ -198,8 +233,8 @@ __device__ __forceinline__ void load_pops(const T *__restrict__ f, const Grid &g
 // Collision of node (x, y, zf) whose populations d (canonical order, time t)
 // are in hand, with the immersed-boundary force density (fx, fy, fz) of this
 // step (body force and external field are added here), and the AA write-back.
-template <typename T, bool ODD>
-__device__ __forceinline__ void lb_collide(T *__restrict__ f, const T *__restrict__ Fext, int *err,
+template <typename S, bool ODD, typename T = typename Pop<S>::C>
+__device__ __forceinline__ void lb_collide(S *__restrict__ f, const T *__restrict__ Fext, int *err,
                                            const LBArgs &a, int x, int y, int zf, const T *d, T fx, T fy, T fz)
 {
     const Grid &g = a.g;
@@ -241,8 +276,8 @@ __device__ __forceinline__ void lb_collide(T *__restrict__ f, const T *__restric
         const T deq = w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
         const T cmuF = (T(cx(i)) - ux) * Fx + (T(cy(i)) - uy) * Fy + (T(cz(i)) - uz) * Fz;
         const T cF = T(cx(i)) * Fx + T(cy(i)) * Fy + T(cz(i)) * Fz;
-        const T S = w * guo * (T(3) * cmuF + T(9) * cF * cu);
-        T post = d[i] - (d[i] - deq) * tinv + S;
+        const T guo_i = w * guo * (T(3) * cmuF + T(9) * cF * cu);
+        T post = d[i] - (d[i] - deq) * tinv + guo_i;
         long long dst;
         const bool fluid = shifted(g, b, x, y, zf, i, +1, dst);
         if (!fluid) {
@@ -252,27 +287,27 @@ __device__ __forceinline__ void lb_collide(T *__restrict__ f, const T *__restric
             post -= T(6) * w * rho * cuw;
         }
         if (!ODD || !fluid)
-            store_through(&f[opp(i) * n + me], post);
+            store_through(&f[opp(i) * n + me], Pop<S>::put(post, i));
         else
-            store_through(&f[i * n + dst], post);
+            store_through(&f[i * n + dst], Pop<S>::put(post, i));
     }
 }
 
 // LB update of node (x, y, zf): load its populations, collide, write back.
-template <typename T, bool ODD>
-__device__ __forceinline__ void lb_node(T *__restrict__ f, const T *__restrict__ Fext, int *err, const LBArgs &a,
+template <typename S, bool ODD, typename T = typename Pop<S>::C>
+__device__ __forceinline__ void lb_node(S *__restrict__ f, const T *__restrict__ Fext, int *err, const LBArgs &a,
                                         int x, int y, int zf, T fx, T fy, T fz)
 {
     T d[19];
-    load_pops<T, ODD>(f, a.g, x, y, zf, d);
-    lb_collide<T, ODD>(f, Fext, err, a, x, y, zf, d, fx, fy, fz);
+    load_pops<S, ODD>(f, a.g, x, y, zf, d);
+    lb_collide<S, ODD>(f, Fext, err, a, x, y, zf, d, fx, fy, fz);
 }
 
 // LB of one node of the LB tiling (blocks of bxw x (256 / bxw) nodes in one
 // z layer, numbered x fastest), unless its tile is active at step t (those
 // nodes are updated by the spreading, with their force).
-template <typename T, bool ODD>
-__device__ __forceinline__ void bulk_lb_block(int b, T *__restrict__ f, const T *__restrict__ Fext,
+template <typename S, bool ODD, typename T = typename Pop<S>::C>
+__device__ __forceinline__ void bulk_lb_block(int b, S *__restrict__ f, const T *__restrict__ Fext,
                                               const uint32_t *__restrict__ act, uint32_t t, int *err, const LBArgs &a,
                                               int bxw, int nbx, int nby)
 {
@@ -285,7 +320,7 @@ __device__ __forceinline__ void bulk_lb_block(int b, T *__restrict__ f, const T 
         return;
     if (act[tile_of(a.g, x, y, zf)] == t + 1u)
         return;
-    lb_node<T, ODD>(f, Fext, err, a, x, y, zf, T(0), T(0), T(0));
+    lb_node<S, ODD>(f, Fext, err, a, x, y, zf, T(0), T(0), T(0));
 }
 
 // LB over the fluid nodes.  Without a mesh (act == null) every node, and the
@@ -294,10 +329,11 @@ __device__ __forceinline__ void bulk_lb_block(int b, T *__restrict__ f, const T 
 // force and spreading kernels, which update the active tiles themselves.
 // In the AA pattern each node reads and writes only its own 19 slots, so the
 // two node sets never touch the same memory.
-template <typename T, bool ODD>
-__global__ __launch_bounds__(256) void k_lb(T *__restrict__ f, const T *__restrict__ Fext,
+template <typename S, bool ODD>
+__global__ __launch_bounds__(256) void k_lb(S *__restrict__ f, const typename Pop<S>::C *__restrict__ Fext,
                                             const uint32_t *__restrict__ act, uint32_t *ctr, int *err, LBArgs a)
 {
+    using T = typename Pop<S>::C;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int zf = blockIdx.z;
@@ -309,12 +345,13 @@ __global__ __launch_bounds__(256) void k_lb(T *__restrict__ f, const T *__restri
         return;
     if (act != nullptr && act[tile_of(a.g, x, y, zf)] == t + 1u)
         return;
-    lb_node<T, ODD>(f, Fext, err, a, x, y, zf, T(0), T(0), T(0));
+    lb_node<S, ODD>(f, Fext, err, a, x, y, zf, T(0), T(0), T(0));
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_init(T *__restrict__ f, LBArgs a, int couette)
+template <typename S>
+__global__ __launch_bounds__(256) void k_init(S *__restrict__ f, LBArgs a, int couette)
 {
+    using T = typename Pop<S>::C;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int zf = blockIdx.z;
@@ -333,7 +370,7 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ f, LBArgs a, int c
     for (int i = 0; i < 19; ++i) {
         const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
         const double w = wgt<double>(i);
-        f[i * g.n + me] = T(w * a.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+        f[i * g.n + me] = Pop<S>::put(T(w * a.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu)), i);
     }
 }
 
@@ -635,14 +672,14 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
 // step's active tiles, and the blocks after it (if any) run the first LB
 // blocks of the nodes outside the active tiles (the spreading dispatch runs
 // the rest).
-template <typename T, int P>
+template <typename S, int P, typename T = typename Pop<S>::C>
 __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, const double *__restrict__ Xref,
                                                 const int4 *__restrict__ inc4,
                                                 const double *__restrict__ fref, T *__restrict__ phiSW,
                                                 T *__restrict__ gVout, Base *__restrict__ base,
                                                 T *__restrict__ wts, double *__restrict__ partials,
                                                 const uint32_t *__restrict__ act, uint32_t *acnt, int *alist,
-                                                const uint32_t *__restrict__ ctr, T *__restrict__ f,
+                                                const uint32_t *__restrict__ ctr, S *__restrict__ f,
                                                 const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m, int bxw,
                                                 int nbx, int nby)
 {
@@ -651,7 +688,7 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, co
     else if ((int)blockIdx.x == m.nparts)
         scan_block(act, acnt, alist, ctr[P], a.g);
     else
-        bulk_lb_block<T, P == 1>(blockIdx.x - m.nparts - 1, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
+        bulk_lb_block<S, P == 1>(blockIdx.x - m.nparts - 1, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
 }
 
 // k_V (V - V0)/V0 from the force-kernel partials, summed by one wavefront in a
@@ -776,20 +813,20 @@ __device__ __forceinline__ void stage_store(const Staged<T> &s, int e, T kf, T *
 // the four partial sums are added in wavefront order, so every node's sum has
 // a fixed order.  Wavefront 0 finishes with the LB update of the tile's nodes,
 // whose populations it fetched at the start.
-template <typename T, int P>
+template <typename S, int P, typename T = typename Pop<S>::C>
 __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
                                                 const double *__restrict__ partials, const uint32_t *__restrict__ ctr,
                                                 uint64_t *__restrict__ mask, const uint32_t *__restrict__ acnt,
                                                 const int *__restrict__ alist, T *__restrict__ F,
-                                                uint32_t *__restrict__ stamp, T *__restrict__ f,
+                                                uint32_t *__restrict__ stamp, S *__restrict__ f,
                                                 const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m,
                                                 const uint32_t *__restrict__ act, int nsp, int lb0, int bxw, int nbx,
                                                 int nby)
 {
     const Grid &g = a.g;
     if ((int)blockIdx.x >= nsp) {
-        bulk_lb_block<T, P == 1>(lb0 + (int)blockIdx.x - nsp, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
+        bulk_lb_block<S, P == 1>(lb0 + (int)blockIdx.x - nsp, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
         return;
     }
     constexpr int kMaxWords = kMaxVertices / 64;
@@ -824,7 +861,7 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
         const bool node = x < g.nx && y < g.ny && zf < g.nzf;
         T d[19];
         if (wave == 0 && node)
-            load_pops<T, P == 1>(f, g, x, y, zf, d);
+            load_pops<S, P == 1>(f, g, x, y, zf, d);
         uint64_t *mw = mask + (long long)tile * W;
         const int w0 = tid * J;
         uint64_t wv[4];
@@ -922,7 +959,7 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
                 F[g.n + me] = Fy;
                 F[2 * g.n + me] = Fz;
                 // the LB update of this active node, with its force in hand
-                lb_collide<T, P == 1>(f, Fext, err, a, x, y, zf, d, Fx, Fy, Fz);
+                lb_collide<S, P == 1>(f, Fext, err, a, x, y, zf, d, Fx, Fy, Fz);
             }
             if (lane == 0)
                 stamp[tile] = t + 1u;
@@ -935,8 +972,8 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
 // tiles (one wavefront per tile, one lane per node), for the interpolation.
 // P = t & 1: after this step's LB the populations of time t + 1 sit in the
 // swapped layout exactly when P == 0.
-template <typename T, int P>
-__global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const T *__restrict__ Fib,
+template <typename S, int P, typename T = typename Pop<S>::C>
+__global__ __launch_bounds__(256) void k_moments(const S *__restrict__ f, const T *__restrict__ Fib,
                                                  const T *__restrict__ Fext, const uint32_t *__restrict__ acnt,
                                                  const int *__restrict__ alist, T *__restrict__ U, LBArgs a)
 {
@@ -958,7 +995,7 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f, const 
         if (x >= g.nx || y >= g.ny || zf >= g.nzf)
             continue;
         T d[19];
-        load_pops<T, P == 0>(f, g, x, y, zf, d);
+        load_pops<S, P == 0>(f, g, x, y, zf, d);
         const long long me = nidx(g, x, y, zf);
         T Fx = T(a.body[0]) + Fib[me], Fy = T(a.body[1]) + Fib[g.n + me], Fz = T(a.body[2]) + Fib[2 * g.n + me];
         if (a.has_fext) {
@@ -1076,9 +1113,10 @@ __global__ __launch_bounds__(256) void k_stamp(const double *__restrict__ q, uin
 // ---------------------------------------------------------------------------
 // Debug and query kernels (not on the per-step path)
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_get_pops(const T *__restrict__ f, int p, double *__restrict__ out, Grid g)
+template <typename S>
+__global__ __launch_bounds__(256) void k_get_pops(const S *__restrict__ f, int p, double *__restrict__ out, Grid g)
 {
+    using T = typename Pop<S>::C;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int zf = blockIdx.z;
@@ -1086,17 +1124,18 @@ __global__ __launch_bounds__(256) void k_get_pops(const T *__restrict__ f, int p
         return;
     T d[19];
     if (p)
-        load_pops<T, true>(f, g, x, y, zf, d);
+        load_pops<S, true>(f, g, x, y, zf, d);
     else
-        load_pops<T, false>(f, g, x, y, zf, d);
+        load_pops<S, false>(f, g, x, y, zf, d);
     const long long me = nidx(g, x, y, zf);
     for (int i = 0; i < 19; ++i)
         out[i * g.n + me] = double(d[i]);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_set_pops(T *__restrict__ f, int p, const double *__restrict__ in, Grid g)
+template <typename S>
+__global__ __launch_bounds__(256) void k_set_pops(S *__restrict__ f, int p, const double *__restrict__ in, Grid g)
 {
+    using T = typename Pop<S>::C;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int zf = blockIdx.z;
@@ -1111,13 +1150,13 @@ __global__ __launch_bounds__(256) void k_set_pops(T *__restrict__ f, int p, cons
             long long src;
             const bool ok = shifted(g, b, x, y, zf, i, -1, src);
             if (ok)
-                f[opp(i) * n + src] = T(in[i * n + me]);
+                f[opp(i) * n + src] = Pop<S>::put(T(in[i * n + me]), i);
             else
-                f[i * n + me] = T(in[i * n + me]);
+                f[i * n + me] = Pop<S>::put(T(in[i * n + me]), i);
         }
     } else {
         for (int i = 0; i < 19; ++i)
-            f[i * n + me] = T(in[i * n + me]);
+            f[i * n + me] = Pop<S>::put(T(in[i * n + me]), i);
     }
 }
 
@@ -1144,8 +1183,8 @@ __device__ __forceinline__ void last_force(const T *Fib, const T *Fext, const ui
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_get_fields(const T *__restrict__ f, const T *__restrict__ Fib,
+template <typename S, typename T = typename Pop<S>::C>
+__global__ __launch_bounds__(256) void k_get_fields(const S *__restrict__ f, const T *__restrict__ Fib,
                                                     const T *__restrict__ Fext, const uint32_t *__restrict__ stamp,
                                                     const uint32_t *__restrict__ ctr, int p, double *__restrict__ rho_out,
                                                     double *__restrict__ u_out, double *__restrict__ F_out, LBArgs a)
@@ -1169,9 +1208,9 @@ __global__ __launch_bounds__(256) void k_get_fields(const T *__restrict__ f, con
         return;
     T d[19];
     if (p)
-        load_pops<T, true>(f, g, x, y, zf, d);
+        load_pops<S, true>(f, g, x, y, zf, d);
     else
-        load_pops<T, false>(f, g, x, y, zf, d);
+        load_pops<S, false>(f, g, x, y, zf, d);
     double drho = 0.0, m[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < 19; ++i) {
         const double di = double(d[i]);
@@ -1305,29 +1344,42 @@ dim3 lb_grid(const Grid &g)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hipStream_t s)
+// Calls fn with a value of the population storage type of `prec` (0 FP64,
+// 1 FP32, 2 FP16, 3 BF16).
+template <typename Fn>
+static hipError_t with_pop_type(int prec, Fn &&fn)
 {
-    if (prec == 0)
-        k_init<double><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((double *)d.f, a, couette);
-    else
-        k_init<float><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((float *)d.f, a, couette);
+    switch (prec) {
+    case 0: fn(double{}); break;
+    case 1: fn(float{}); break;
+    case 2: fn(_Float16{}); break;
+    default: fn(__bf16{}); break;
+    }
     return hipGetLastError();
 }
 
-template <typename T, bool ODD>
+hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hipStream_t s)
+{
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        k_init<S><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((S *)d.f, a, couette);
+    });
+}
+
+template <typename S, bool ODD>
 static void lb_launch(const Dev &d, const LBArgs &a, bool bulk, hipStream_t s)
 {
-    k_lb<T, ODD><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((T *)d.f, (const T *)d.Fext, bulk ? d.act : nullptr, d.ctr,
+    using T = typename Pop<S>::C;
+    k_lb<S, ODD><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((S *)d.f, (const T *)d.Fext, bulk ? d.act : nullptr, d.ctr,
                                                           d.err, a);
 }
 
 hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, hipStream_t s)
 {
-    if (prec == 0)
-        p ? lb_launch<double, true>(d, a, bulk, s) : lb_launch<double, false>(d, a, bulk, s);
-    else
-        p ? lb_launch<float, true>(d, a, bulk, s) : lb_launch<float, false>(d, a, bulk, s);
-    return hipGetLastError();
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        p ? lb_launch<S, true>(d, a, bulk, s) : lb_launch<S, false>(d, a, bulk, s);
+    });
 }
 
 // Share of the LB blocks of the nodes outside the active tiles that runs in
@@ -1344,13 +1396,14 @@ int lb_blocks_with_forces(const Grid &g)
     return (int)(kLbShareWithForces * nlb + 0.5);
 }
 
-template <typename T, int P>
+template <typename S, int P>
 static void forces_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int nlb, hipStream_t s)
 {
+    using T = typename Pop<S>::C;
     const dim3 bl = lb_block(a.g), gr = lb_grid(a.g);
-    k_forces<T, P><<<m.nparts + 1 + nlb, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.fref, (T *)d.phiSW, (T *)d.gV, d.base,
+    k_forces<S, P><<<m.nparts + 1 + nlb, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.fref, (T *)d.phiSW, (T *)d.gV, d.base,
                                                        (T *)d.wts, d.partials, d.act, d.acnt, d.alist, d.ctr,
-                                                       (T *)d.f, (const T *)d.Fext, d.err, a, m, (int)bl.x,
+                                                       (S *)d.f, (const T *)d.Fext, d.err, a, m, (int)bl.x,
                                                        (int)gr.x, (int)gr.y);
 }
 
@@ -1358,22 +1411,22 @@ hipError_t launch_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs
                          hipStream_t s)
 {
     const int nlb = with_lb ? lb_blocks_with_forces(a.g) : 0;
-    if (prec == 0)
-        p ? forces_launch<double, 1>(d, a, m, nlb, s) : forces_launch<double, 0>(d, a, m, nlb, s);
-    else
-        p ? forces_launch<float, 1>(d, a, m, nlb, s) : forces_launch<float, 0>(d, a, m, nlb, s);
-    return hipGetLastError();
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        p ? forces_launch<S, 1>(d, a, m, nlb, s) : forces_launch<S, 0>(d, a, m, nlb, s);
+    });
 }
 
-template <typename T, int P>
+template <typename S, int P>
 static void spread_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int nsp, int with_lb, hipStream_t s)
 {
+    using T = typename Pop<S>::C;
     const dim3 bl = lb_block(a.g), gr = lb_grid(a.g);
     const int lb0 = lb_blocks_with_forces(a.g);
     const int nlb = with_lb ? (int)(gr.x * gr.y * gr.z) - lb0 : 0;
-    k_spread<T, P><<<nsp + nlb, 256, 0, s>>>(d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV,
+    k_spread<S, P><<<nsp + nlb, 256, 0, s>>>(d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV,
                                              d.partials, d.ctr, d.mask, d.acnt, d.alist, (T *)d.F, d.stamp,
-                                             (T *)d.f, (const T *)d.Fext, d.err, a, m, d.act, nsp, lb0, (int)bl.x,
+                                             (S *)d.f, (const T *)d.Fext, d.err, a, m, d.act, nsp, lb0, (int)bl.x,
                                              (int)gr.x, (int)gr.y);
 }
 
@@ -1381,22 +1434,22 @@ hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs
                          hipStream_t s)
 {
     // spreading blocks: as many as the CUs hold at once (register-limited: 2
-    // per CU in FP32, 1 in FP64), striding over the active tiles
+    // per CU with FP32 arithmetic, 1 with FP64), striding over the active tiles
     const int fit = d.num_cus * (prec == 0 ? 1 : 2);
     const int nsp = a.g.nt < fit ? a.g.nt : fit;
-    if (prec == 0)
-        p ? spread_launch<double, 1>(d, a, m, nsp, with_lb, s) : spread_launch<double, 0>(d, a, m, nsp, with_lb, s);
-    else
-        p ? spread_launch<float, 1>(d, a, m, nsp, with_lb, s) : spread_launch<float, 0>(d, a, m, nsp, with_lb, s);
-    return hipGetLastError();
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        p ? spread_launch<S, 1>(d, a, m, nsp, with_lb, s) : spread_launch<S, 0>(d, a, m, nsp, with_lb, s);
+    });
 }
 
-template <typename T, int P>
+template <typename S, int P>
 static void move_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s)
 {
+    using T = typename Pop<S>::C;
     const int tiles = a.g.nt;
     const int mblocks = (tiles + 3) / 4 < d.num_cus ? (tiles + 3) / 4 : d.num_cus;
-    k_moments<T, P><<<mblocks, 256, 0, s>>>((const T *)d.f, (const T *)d.F, (const T *)d.Fext, d.acnt, d.alist,
+    k_moments<S, P><<<mblocks, 256, 0, s>>>((const S *)d.f, (const T *)d.F, (const T *)d.Fext, d.acnt, d.alist,
                                             (T *)d.U, a);
     const int blocks = (m.nv + 3) / 4;
     k_move<T, P><<<blocks, 256, 0, s>>>(d.q, (const T *)d.U, d.stamp, d.ctr, d.act, d.mask, d.err, a, m);
@@ -1404,11 +1457,10 @@ static void move_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, hipStr
 
 hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
 {
-    if (prec == 0)
-        p ? move_launch<double, 1>(d, a, m, s) : move_launch<double, 0>(d, a, m, s);
-    else
-        p ? move_launch<float, 1>(d, a, m, s) : move_launch<float, 0>(d, a, m, s);
-    return hipGetLastError();
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        p ? move_launch<S, 1>(d, a, m, s) : move_launch<S, 0>(d, a, m, s);
+    });
 }
 
 hipError_t launch_stamp(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)
@@ -1419,48 +1471,40 @@ hipError_t launch_stamp(const Dev &d, const Grid &g, const MeshArgs &m, int p, h
 
 hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double *out, hipStream_t s)
 {
-    if (prec == 0)
-        k_get_pops<double><<<lb_grid(g), lb_block(g), 0, s>>>((const double *)d.f, p, out, g);
-    else
-        k_get_pops<float><<<lb_grid(g), lb_block(g), 0, s>>>((const float *)d.f, p, out, g);
-    return hipGetLastError();
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        k_get_pops<S><<<lb_grid(g), lb_block(g), 0, s>>>((const S *)d.f, p, out, g);
+    });
 }
 
 hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, int p, const double *in, hipStream_t s)
 {
-    if (prec == 0)
-        k_set_pops<double><<<lb_grid(g), lb_block(g), 0, s>>>((double *)d.f, p, in, g);
-    else
-        k_set_pops<float><<<lb_grid(g), lb_block(g), 0, s>>>((float *)d.f, p, in, g);
-    return hipGetLastError();
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        k_set_pops<S><<<lb_grid(g), lb_block(g), 0, s>>>((S *)d.f, p, in, g);
+    });
+}
+
+static hipError_t fields_launch(int prec, const Dev &d, const LBArgs &a, int p, double *rho, double *u, double *F,
+                                hipStream_t s)
+{
+    const uint32_t *stamp = d.q ? d.stamp : nullptr;
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        using T = typename Pop<S>::C;
+        k_get_fields<S><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const S *)d.f, (const T *)d.F, (const T *)d.Fext,
+                                                               stamp, d.ctr, p, rho, u, F, a);
+    });
 }
 
 hipError_t launch_get_fields(int prec, const Dev &d, const LBArgs &a, int p, double *rho, double *u, hipStream_t s)
 {
-    const uint32_t *stamp = d.q ? d.stamp : nullptr;
-    if (prec == 0)
-        k_get_fields<double><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const double *)d.f, (const double *)d.F,
-                                                                    (const double *)d.Fext, stamp, d.ctr, p, rho, u,
-                                                                    nullptr, a);
-    else
-        k_get_fields<float><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const float *)d.f, (const float *)d.F,
-                                                                   (const float *)d.Fext, stamp, d.ctr, p, rho, u,
-                                                                   nullptr, a);
-    return hipGetLastError();
+    return fields_launch(prec, d, a, p, rho, u, nullptr, s);
 }
 
 hipError_t launch_get_force(int prec, const Dev &d, const LBArgs &a, int p, double *F, hipStream_t s)
 {
-    const uint32_t *stamp = d.q ? d.stamp : nullptr;
-    if (prec == 0)
-        k_get_fields<double><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const double *)d.f, (const double *)d.F,
-                                                                    (const double *)d.Fext, stamp, d.ctr, p, nullptr,
-                                                                    nullptr, F, a);
-    else
-        k_get_fields<float><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((const float *)d.f, (const float *)d.F,
-                                                                   (const float *)d.Fext, stamp, d.ctr, p, nullptr,
-                                                                   nullptr, F, a);
-    return hipGetLastError();
+    return fields_launch(prec, d, a, p, nullptr, nullptr, F, s);
 }
 
 hipError_t launch_nodal_forces(int prec, const Dev &d, const MeshArgs &m, double *phi, hipStream_t s)

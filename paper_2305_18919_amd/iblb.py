@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libiblb.so")
 
 IBLB_OK, IBLB_E_INVAL, IBLB_E_DEVICE, IBLB_E_MESH, IBLB_E_UNSTABLE, IBLB_E_STATE = 0, -1, -2, -3, -4, -5
-FP64, FP32_DEV = 0, 1
+FP64, FP32_DEV, FP16_DEV, BF16_DEV = 0, 1, 2, 3
 WALLS_Z, PERIODIC_ALL = 0, 1
 
 _dp = C.POINTER(C.c_double)

@@ -86,20 +86,44 @@ def test_periodic_momentum_conserved_on_gpu():
     assert np.abs(p).max() < 1e-15 * d.n_fluid * np.abs(phi).max()
 
 
-def test_shear64_fp32_500_steps():
-    """The benchmark workload (64^3, sheared coated capsule, FP32 populations),
-    run in the benchmark's launch configuration (captured graph)."""
+@pytest.fixture(scope="module")
+def shear64_oracle_500():
+    """The benchmark workload (64^3, sheared coated capsule) after 500 steps
+    of the FP64 oracle, shared by the precision variants below."""
     w = c2_shear(0.05)
-    announce("shear64 fp32 500 steps (graph)")
+    announce("shear64 oracle 500 steps")
     o = O.OracleSim(w.domain, w.mesh)
     o.step(500)
-    with iblb.Simulation(w.domain, w.mesh, precision=iblb.FP32_DEV, graph=True) as g:
+    return w, o
+
+
+# Tolerances after 500 steps: FP32 as stated for the FP32 path; FP16 and BF16
+# are the stated errors of 16-bit storage (observed 4.5e-4 / 8.5e-3 in u,
+# 7.8e-6 / 8.2e-4 in q/R, 1.8e-4 / 1.9e-2 in D/D, 2.9e-6 / 1.1e-3 rad in
+# Theta, bounded here with a margin of about 4): rounding the stored
+# populations every step accumulates, and no closed form bounds that sum over
+# a coupled run.
+SHEAR_TOL = {
+    iblb.FP32_DEV: dict(q=1e-6, u=1e-5, D=1e-4, th=1e-4),
+    iblb.FP16_DEV: dict(q=5e-5, u=2e-3, D=1e-3, th=3e-5),
+    iblb.BF16_DEV: dict(q=4e-3, u=4e-2, D=8e-2, th=5e-3),
+}
+
+
+@pytest.mark.parametrize("prec", [iblb.FP32_DEV, iblb.FP16_DEV, iblb.BF16_DEV])
+def test_shear64_500_steps(shear64_oracle_500, prec):
+    """The benchmark workload in the benchmark's launch configuration
+    (captured graph), FP32 / FP16 / BF16 population storage."""
+    w, o = shear64_oracle_500
+    tol = SHEAR_TOL[prec]
+    with iblb.Simulation(w.domain, w.mesh, precision=prec, graph=True) as g:
         g.step(500)
-        compare(g, o, 10.0, 1e-6, 1e-5, "shear64 fp32")
+        compare(g, o, 10.0, tol["q"], tol["u"], f"shear64 prec={prec}")
         Dg, thg, _ = g.shape_dtheta()
     Do, tho = O.shape_dtheta(o.vertices(), w.mesh.faces)
-    assert abs(Dg - Do) <= 1e-4 * abs(Do) + 1e-7
-    assert abs(thg - tho) <= 1e-4
+    announce(f"  dD/D={abs(Dg - Do) / abs(Do):.3e} dTheta={abs(thg - tho):.3e}")
+    assert abs(Dg - Do) <= tol["D"] * abs(Do) + 1e-7
+    assert abs(thg - tho) <= tol["th"]
 
 
 def test_shear64_fp64_graph_vs_oracle():
