@@ -23,7 +23,8 @@ event overhead).  The FP64 CPU oracle is timed on a bounded sample of the same
 workload.
 
 --pass lb / --pass copy run only the LB-only pass, or a plain device copy of
---copy-mib MiB, for hardware-counter runs.
+--copy-mib MiB, for hardware-counter runs.  --study precision runs the
+contact-angle comparison of the population storage precisions instead.
 """
 from __future__ import annotations
 
@@ -124,6 +125,39 @@ def lb_roofline(dom, prec: int, launches: int, traffic=None):
             "launches": launches, "avg_us": round(us, 3)}
 
 
+def precision_study(steps: int):
+    """Equilibrium contact angle of the 128x128x96 wetting droplet with FP32,
+    FP16 and BF16 population storage against the FP64 path, at eps/abar =
+    0.05, 1 and 7: the same run of `steps` steps in each precision, then the
+    sphere fit of the lower contact angle."""
+    import torch
+    from paper_2305_18919_amd import iblb
+    from paper_2305_18919_amd import inputs as I
+    out = {"study": "contact angle vs population storage", "workload": "wetting128", "steps": steps,
+           "fit": "sphere fit (method 0) of the vertices >= 2 above the lower wall plane", "cases": []}
+    for eps in (0.05, 1.0, 7.0):
+        w = I.c3_wetting(eps)
+        case = {"eps_over_abar": eps}
+        for name in ("fp64", "fp32", "fp16", "bf16"):
+            prec = PRECISIONS[name]
+            with iblb.Simulation(w.domain, w.mesh, precision=prec, graph=True) as sim:
+                sim.step(16)
+                sim.sync()
+                t0 = time.perf_counter()
+                sim.step(steps - 16)
+                sim.sync()
+                dt = time.perf_counter() - t0
+                theta, r, h = sim.contact_angle(0)
+                V, _ = sim.volume()
+            case[name] = {"theta_deg": theta, "contact_radius": r, "height": h, "volume": V,
+                          "mlups": round(w.domain.n_fluid * (steps - 16) / dt / 1e6, 1)}
+        for name in ("fp32", "fp16", "bf16"):
+            case[name]["dtheta_deg"] = case[name]["theta_deg"] - case["fp64"]["theta_deg"]
+        out["cases"].append(case)
+        print(json.dumps(case), flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def copy_pass(mib: int, reps: int):
     """A plain device-to-device copy of `mib` MiB, `reps` times (counter calibration)."""
     import torch
@@ -151,6 +185,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pass", dest="only", choices=["lb", "copy"], default=None)
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--study", choices=["precision"], default=None,
+                    help="precision: contact angle of the wetting droplet per population storage")
+    ap.add_argument("--study-steps", type=int, default=50000)
     ap.add_argument("--precision", choices=sorted(PRECISIONS), default=None,
                     help="population storage (default: the workload's, FP32 for shear64)")
     args = ap.parse_args()
@@ -162,6 +199,9 @@ def main():
     import torch
     from paper_2305_18919_amd import iblb
 
+    if args.study == "precision":
+        precision_study(args.study_steps)
+        return
     w, prec = workload(args.workload)
     if args.precision is not None:
         prec = PRECISIONS[args.precision]
