@@ -97,7 +97,7 @@ Layout make_layout(const Grid &g, size_t ps, size_t ts, int nv, int nf, int slot
     L.wts = take((size_t)12 * nv * ts);
     L.partials = take((size_t)nparts * 8);
     L.mask = take((size_t)g.nt * ((nv + 63) / 64) * 8);
-    L.act = take((size_t)g.nt * 4);
+    L.act = take((size_t)(g.nt + 4095) / 4096 * 4096);
     L.acnt = take(4);
     L.alist = take((size_t)g.nt * 4);
     L.mesh_end = o;
@@ -348,12 +348,47 @@ struct TmpDev {
     ~TmpDev() { if (p) (void)hipFree(p); }
 };
 
+// Tiles holding a fluid node of some vertex's 4^3 stencil at the stored
+// positions: sizes the moments launch (the kernels do not depend on it).
+int count_active_tiles(iblb_ctx *c, int *out)
+{
+    std::vector<double> q((size_t)3 * c->nv);
+    HIP_TRY(c, hipMemcpyAsync(q.data(), c->d.q, q.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const Grid &g = c->g;
+    std::vector<char> on((size_t)g.nt, 0);
+    auto wrap = [](long long a, int n) { long long r = a % n; return (int)(r < 0 ? r + n : r); };
+    for (int v = 0; v < c->nv; ++v) {
+        const double p[3] = {q[v], q[(size_t)c->nv + v], q[(size_t)2 * c->nv + v]};
+        if (!(std::fabs(p[0]) < 1e6 && std::fabs(p[1]) < 1e6 && std::fabs(p[2]) < 1e6)) continue;
+        const long long b[3] = {(long long)std::floor(p[0]) - 1, (long long)std::floor(p[1]) - 1,
+                                (long long)std::floor(p[2]) - 1};
+        for (int k = 0; k < 64; ++k) {
+            const int x = wrap(b[0] + (k & 3), g.nx), y = wrap(b[1] + ((k >> 2) & 3), g.ny);
+            long long zf = b[2] + (k >> 4);
+            if (g.walls) {
+                zf -= g.zoff;
+                if (zf < 0 || zf >= g.nzf) continue;
+            } else {
+                zf = wrap(zf, g.nz);
+            }
+            on[((size_t)(zf >> 2) * g.nty + (y >> 2)) * g.ntx + (x >> 2)] = 1;
+        }
+    }
+    int n = 0;
+    for (char x : on) n += x;
+    *out = n;
+    return IBLB_OK;
+}
+
 // Clears the vertex masks and activity stamps, then sets both for the current
 // step from the stored positions (each step sets them for the next one).
 int rebuild_lists(iblb_ctx *c)
 {
+    int rc = count_active_tiles(c, &c->m.tiles_hint);
+    if (rc) return rc;
     HIP_TRY(c, hipMemsetAsync(c->d.mask, 0, (size_t)c->g.nt * c->m.nwords * 8, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->d.act, 0, (size_t)c->g.nt * 4, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d.act, 0, (size_t)(c->g.nt + 4095) / 4096 * 4096, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d.acnt, 0, 4, c->stream));
     HIP_TRY(c, launch_stamp(c->d, c->g, c->m, (int)(c->t & 1), c->stream));
     return IBLB_OK;
@@ -543,7 +578,7 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
     d.wts = mb + L.wts;
     d.partials = (double *)(mb + L.partials);
     d.mask = (uint64_t *)(mb + L.mask);
-    d.act = (uint32_t *)(mb + L.act);
+    d.act = (uint8_t *)(mb + L.act);
     d.acnt = (uint32_t *)(mb + L.acnt);
     d.alist = (int *)(mb + L.alist);
     HIP_TRY(c, hipMemcpyAsync(d.q, qs.data(), qs.size() * 8, hipMemcpyHostToDevice, c->stream));

@@ -54,6 +54,7 @@ struct MeshArgs {
     int nparts;           // force-kernel blocks (32 vertices each) = number of volume partials
     int nwords;           // 64-bit words of one tile's vertex mask, ceil(nv / 64)
     int slots;            // incidence slots per vertex (a multiple of 8)
+    int tiles_hint;       // active tiles counted at set-up (launch sizing only)
 };
 
 // Device buffers of one context (typed as void* where the precision varies).
@@ -78,7 +79,8 @@ struct Dev {
     double *partials;     // [nparts]: sum (V_j - V0_j) per force block
     uint64_t *mask;       // [nt][nwords] bit v: vertex v's stencil reaches the tile (set by the
                           // move, read and cleared by the next step's spreading)
-    uint32_t *act;        // [nt] step+1 for which the tile is active (stamped by the previous move)
+    uint8_t *act;         // [nt, padded to 4096] act_stamp(t) of the step t at which the tile is
+                          // active (written by the previous move; 0 = never)
     uint32_t *acnt;       // [1] active tiles of the step
     int *alist;           // [nt] active tile indices of the step (scan order)
     double *scratch;      // small FP64 scratch for queries (64 doubles)

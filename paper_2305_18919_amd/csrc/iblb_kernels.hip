@@ -93,6 +93,13 @@ struct Pop<__bf16> {
     static __device__ __forceinline__ __bf16 put(C v, int i) { return (__bf16)(v * inv_w(i)); }
 };
 
+// Activity stamp of step t: one byte, (t mod 255) + 1, never 0, so a tile
+// that was never marked (0) never matches.  A tile last marked a multiple of
+// 255 steps ago matches again; it is then treated as active with an empty
+// vertex mask, which gives the same LB update (zero interface force) at the
+// cost of a little extra work.
+__host__ __device__ __forceinline__ uint8_t act_stamp(uint32_t t) { return (uint8_t)(t % 255u + 1u); }
+
 __device__ __forceinline__ int wrapi(int a, int n)
 {
     int r = a % n;
@@ -308,7 +315,7 @@ __device__ __forceinline__ void lb_node(S *__restrict__ f, const T *__restrict__
 // nodes are updated by the spreading, with their force).
 template <typename S, bool ODD, typename T = typename Pop<S>::C>
 __device__ __forceinline__ void bulk_lb_block(int b, S *__restrict__ f, const T *__restrict__ Fext,
-                                              const uint32_t *__restrict__ act, uint32_t t, int *err, const LBArgs &a,
+                                              const uint8_t *__restrict__ act, uint32_t t, int *err, const LBArgs &a,
                                               int bxw, int nbx, int nby)
 {
     const int zf = b / (nbx * nby);
@@ -318,20 +325,20 @@ __device__ __forceinline__ void bulk_lb_block(int b, S *__restrict__ f, const T 
     const int y = byi * (256 / bxw) + (int)(threadIdx.x / (unsigned)bxw);
     if (x >= a.g.nx || y >= a.g.ny)
         return;
-    if (act[tile_of(a.g, x, y, zf)] == t + 1u)
+    if (act[tile_of(a.g, x, y, zf)] == act_stamp(t))
         return;
     lb_node<S, ODD>(f, Fext, err, a, x, y, zf, T(0), T(0), T(0));
 }
 
 // LB over the fluid nodes.  Without a mesh (act == null) every node, and the
 // kernel advances the step counter.  With a mesh only the nodes outside this
-// step's active tiles (act[tile] != t + 1): it runs concurrently with the
+// step's active tiles (act[tile] != act_stamp(t)): it runs concurrently with the
 // force and spreading kernels, which update the active tiles themselves.
 // In the AA pattern each node reads and writes only its own 19 slots, so the
 // two node sets never touch the same memory.
 template <typename S, bool ODD>
 __global__ __launch_bounds__(256) void k_lb(S *__restrict__ f, const typename Pop<S>::C *__restrict__ Fext,
-                                            const uint32_t *__restrict__ act, uint32_t *ctr, int *err, LBArgs a)
+                                            const uint8_t *__restrict__ act, uint32_t *ctr, int *err, LBArgs a)
 {
     using T = typename Pop<S>::C;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -343,7 +350,7 @@ __global__ __launch_bounds__(256) void k_lb(S *__restrict__ f, const typename Po
         ctr[ODD ? 0 : 1] = t + 1u;
     if (x >= a.g.nx || y >= a.g.ny)
         return;
-    if (act != nullptr && act[tile_of(a.g, x, y, zf)] == t + 1u)
+    if (act != nullptr && act[tile_of(a.g, x, y, zf)] == act_stamp(t))
         return;
     lb_node<S, ODD>(f, Fext, err, a, x, y, zf, T(0), T(0), T(0));
 }
@@ -449,50 +456,59 @@ __device__ __forceinline__ int wave_incl_scan(int c, int lane)
     return c;
 }
 
-// The step's active tiles, those stamped act[tile] == t + 1 by the previous
-// move, compacted into alist by one 256-thread block: thread k takes the k-th
-// contiguous range of tiles, so the list is in ascending tile order.  The
-// stamps are read in groups of 16 independent loads; a range of up to 64 tiles
-// is remembered as a bit mask, longer ones are read twice.
-__device__ __forceinline__ void scan_block(const uint32_t *__restrict__ act, uint32_t *acnt, int *alist, uint32_t t,
+// The step's active tiles, those stamped act[tile] == act_stamp(t) by the
+// previous move, compacted into alist in ascending tile order by one
+// 256-thread block.  The byte stamps are read in chunks of 4096 tiles, 16
+// per thread (one 16-byte load each; the array is padded to whole chunks),
+// the loads of up to eight chunks issued before any is used; each chunk is
+// then a block-wide prefix sum of the per-thread counts.
+constexpr int kScanChunk = 4096;
+
+__device__ __forceinline__ void scan_block(const uint8_t *__restrict__ act, uint32_t *acnt, int *alist, uint32_t t,
                                            const Grid &g)
 {
     __shared__ int swt[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int per = (g.nt + 255) / 256;
-    const int k0 = min(g.nt, tid * per), k1 = min(g.nt, k0 + per);
-    uint64_t bits = 0ull;
-    int c = 0;
-    for (int kb = k0; kb < k1; kb += 16) {
-        uint32_t v[16];
+    const int nch = (g.nt + kScanChunk - 1) / kScanChunk;
+    const uint32_t st = act_stamp(t);
+    const uint4 *a4 = reinterpret_cast<const uint4 *>(act);
+    int base = 0;
+    for (int c0 = 0; c0 < nch; c0 += 8) {
+        uint4 v[8];
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-            v[j] = kb + j < k1 ? act[kb + j] : 0u;
+        for (int j = 0; j < 8; ++j)
+            v[j] = c0 + j < nch ? a4[(c0 + j) * (kScanChunk / 16) + tid] : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const bool on = v[j] == t + 1u;
-            c += on ? 1 : 0;
-            if (on && kb + j - k0 < 64)
-                bits |= 1ull << (kb + j - k0);
+        for (int j = 0; j < 8; ++j) {
+            if (c0 + j >= nch)
+                break;
+            // bit b: the b-th of this thread's 16 tiles carries the stamp
+            uint32_t m = 0u;
+            const uint32_t w4[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    m |= ((w4[q] >> (8 * b)) & 0xffu) == st ? 1u << (4 * q + b) : 0u;
+            const int c = __popc(m);
+            const int incl = wave_incl_scan(c, lane);
+            if (lane == 63)
+                swt[wave] = incl;
+            __syncthreads();
+            int o = base + incl - c;
+            for (int w = 0; w < wave; ++w)
+                o += swt[w];
+            base += swt[0] + swt[1] + swt[2] + swt[3];
+            const int k0 = (c0 + j) * kScanChunk + tid * 16;
+            while (m != 0u) {
+                alist[o++] = k0 + __builtin_ctz(m);
+                m &= m - 1u;
+            }
+            __syncthreads();
         }
     }
-    const int incl = wave_incl_scan(c, lane);
-    if (lane == 63)
-        swt[wave] = incl;
-    __syncthreads();
-    int o = incl - c;
-    for (int w = 0; w < wave; ++w)
-        o += swt[w];
-    while (bits != 0ull) {
-        alist[o++] = k0 + __builtin_ctzll(bits);
-        bits &= bits - 1ull;
-    }
-    if (per > 64 && c > 0)
-        for (int k = k0 + 64; k < k1; ++k)
-            if (act[k] == t + 1u)
-                alist[o++] = k;
     if (tid == 0)
-        *acnt = (uint32_t)(swt[0] + swt[1] + swt[2] + swt[3]);
+        *acnt = (uint32_t)base;
 }
 
 // ---------------------------------------------------------------------------
@@ -678,7 +694,7 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, co
                                                 const double *__restrict__ fref, T *__restrict__ phiSW,
                                                 T *__restrict__ gVout, Base *__restrict__ base,
                                                 T *__restrict__ wts, double *__restrict__ partials,
-                                                const uint32_t *__restrict__ act, uint32_t *acnt, int *alist,
+                                                const uint8_t *__restrict__ act, uint32_t *acnt, int *alist,
                                                 const uint32_t *__restrict__ ctr, S *__restrict__ f,
                                                 const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m, int bxw,
                                                 int nbx, int nby)
@@ -806,8 +822,8 @@ __device__ __forceinline__ void stage_store(const Staged<T> &s, int e, T kf, T *
 // mask (bit v set when vertex v's stencil reaches the tile) is read whole,
 // thread k taking the k-th contiguous run of words; a block-wide prefix sum of
 // the words' bit counts gives every word the list position of its first set
-// bit, and the wavefronts then expand the words, one lane per bit, so the
-// listed vertices come out in ascending index order.  All four wavefronts
+// bit; the nonzero words go to LDS in order and the wavefronts expand them,
+// one lane per bit, so the listed vertices come out in ascending index order.  All four wavefronts
 // stage the listed vertices in LDS; wavefront w sums the w-th contiguous
 // quarter of the ordered list for the 64 nodes of the tile (one per lane), and
 // the four partial sums are added in wavefront order, so every node's sum has
@@ -821,7 +837,7 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
                                                 const int *__restrict__ alist, T *__restrict__ F,
                                                 uint32_t *__restrict__ stamp, S *__restrict__ f,
                                                 const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m,
-                                                const uint32_t *__restrict__ act, int nsp, int lb0, int bxw, int nbx,
+                                                const uint8_t *__restrict__ act, int nsp, int lb0, int bxw, int nbx,
                                                 int nby)
 {
     const Grid &g = a.g;
@@ -829,13 +845,14 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
         bulk_lb_block<S, P == 1>(lb0 + (int)blockIdx.x - nsp, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
         return;
     }
-    constexpr int kMaxWords = kMaxVertices / 64;
     __shared__ int sid[kTileCap];
     __shared__ __align__(16) T sw[kTileCap * 12];
     __shared__ __align__(16) T sph[kTileCap * 4];
     __shared__ T part[3][3][64];
-    __shared__ uint64_t swd[kMaxWords];
-    __shared__ int swo[kMaxWords];
+    __shared__ T spop[19][64];        // wavefront 0's prefetched populations
+    __shared__ uint64_t swd[kTileCap];  // the nonzero mask words, in order,
+    __shared__ int swo[kTileCap];       // the list position of each one's first bit,
+    __shared__ int swi[kTileCap];       // and its word index
     __shared__ int swt[4];
     __shared__ T skfac;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -848,6 +865,8 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
     const uint32_t na = acnt[0];
     int tile = ((const volatile int *)alist)[blockIdx.x];
     const uint32_t t = ctr[P];
+    const int w0 = tid * J;
+    uint64_t wv[4];  // this thread's mask words of the current tile
     for (uint32_t ai = blockIdx.x; ai < na; ai += nsp) {
         const uint32_t an = ai + nsp;
         const int next = alist[an < na ? an : ai];
@@ -859,18 +878,26 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
         const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
         const int x = tx * 4 + lx, y = ty * 4 + ly, zf = tz * 4 + lz;
         const bool node = x < g.nx && y < g.ny && zf < g.nzf;
-        T d[19];
-        if (wave == 0 && node)
-            load_pops<S, P == 1>(f, g, x, y, zf, d);
         uint64_t *mw = mask + (long long)tile * W;
-        const int w0 = tid * J;
-        uint64_t wv[4];
+        if (ai == blockIdx.x) {
+            // the first tile's words; later tiles' words were fetched during
+            // the previous tile
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                wv[j] = (j < J && w0 + j < W) ? mw[w0 + j] : 0ull;
+        }
+        if (wave == 0 && node) {
+            T d[19];
+            load_pops<S, P == 1>(f, g, x, y, zf, d);
+#pragma unroll
+            for (int i = 0; i < 19; ++i)
+                spop[i][lane] = d[i];
+        }
+        // set bits (low 20 bits) and nonzero words (above) of this thread's words
         int c = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            wv[j] = (j < J && w0 + j < W) ? mw[w0 + j] : 0ull;
-            c += __popcll(wv[j]);
-        }
+        for (int j = 0; j < 4; ++j)
+            c += __popcll(wv[j]) + (wv[j] != 0ull ? 1 << 20 : 0);
         if (wave == 1 && ai == blockIdx.x) {
             const T kfac = T(volume_factor(partials, m, lane));
             if (lane == 0)
@@ -880,46 +907,59 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
         if (lane == 63)
             swt[wave] = incl;
         __syncthreads();
-        int nent = swt[0] + swt[1] + swt[2] + swt[3];
+        // the next tile's words (its index has arrived by now)
+        uint64_t wn[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            wn[j] = (an < na && j < J && w0 + j < W) ? mask[(long long)next * W + w0 + j] : 0ull;
+        const int tot = swt[0] + swt[1] + swt[2] + swt[3];
+        int nent = tot & 0xfffff;
+        const int nnz = tot >> 20;
         if (nent > kTileCap) {
             if (tid == 0)
                 atomicOr(err, kErrOverflow);
             nent = kTileCap;
         }
+        // the nonzero words in order; a word at position >= kTileCap has all its
+        // bits at list positions >= kTileCap and is dropped with them
         {
-            int o = incl - c;
+            int pre = incl - c;
             for (int w = 0; w < wave; ++w)
-                o += swt[w];
+                pre += swt[w];
+            int o = pre & 0xfffff, k = pre >> 20;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (j < J && w0 + j < W) {
-                    swd[w0 + j] = wv[j];
-                    swo[w0 + j] = o;
+                if (wv[j] != 0ull) {
+                    if (k < kTileCap) {
+                        swd[k] = wv[j];
+                        swo[k] = o;
+                        swi[k] = w0 + j;
+                    }
+                    ++k;
                     o += __popcll(wv[j]);
                 }
         }
         __syncthreads();
-        // expand the words, one lane per bit
+        // expand the nonzero words, one lane per bit
+        const int nw = nnz < kTileCap ? nnz : kTileCap;
 #pragma unroll 4
-        for (int w = wave; w < W; w += 4) {
-            const uint64_t word = swd[w];
-            if (word != 0ull && ((word >> lane) & 1ull)) {
-                const int pos = swo[w] + __popcll(word & below);
+        for (int k = wave; k < nw; k += 4) {
+            const uint64_t word = swd[k];
+            if ((word >> lane) & 1ull) {
+                const int pos = swo[k] + __popcll(word & below);
                 if (pos < kTileCap)
-                    sid[pos] = w * 64 + lane;
+                    sid[pos] = swi[k] * 64 + lane;
             }
         }
         __syncthreads();
         // stage each listed vertex's local weights and total force
         {
             const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 4 + g.zoff;
-            const bool has0 = tid < nent, has1 = tid + 256 < nent;
             const T kf = skfac;
-            Staged<T> s0, s1;
-            if (has0) s0 = stage_load<T>(sid[tid], base, wts, phiSW, gV, nv, err, g, x0, y0, z0);
-            if (has1) s1 = stage_load<T>(sid[tid + 256], base, wts, phiSW, gV, nv, err, g, x0, y0, z0);
-            if (has0) stage_store<T>(s0, tid, kf, sw, sph);
-            if (has1) stage_store<T>(s1, tid + 256, kf, sw, sph);
+            for (int e = tid; e < nent; e += 256) {
+                const Staged<T> st = stage_load<T>(sid[e], base, wts, phiSW, gV, nv, err, g, x0, y0, z0);
+                stage_store<T>(st, e, kf, sw, sph);
+            }
         }
         __syncthreads();
         // this wavefront's quarter of the ordered list
@@ -959,12 +999,19 @@ __global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, c
                 F[g.n + me] = Fy;
                 F[2 * g.n + me] = Fz;
                 // the LB update of this active node, with its force in hand
+                T d[19];
+#pragma unroll
+                for (int i = 0; i < 19; ++i)
+                    d[i] = spop[i][lane];
                 lb_collide<S, P == 1>(f, Fext, err, a, x, y, zf, d, Fx, Fy, Fz);
             }
             if (lane == 0)
                 stamp[tile] = t + 1u;
         }
         tile = next;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            wv[j] = wn[j];
     }
 }
 
@@ -1019,46 +1066,33 @@ __global__ __launch_bounds__(256) void k_moments(const S *__restrict__ f, const 
 }
 
 // Marks the tiles of vertex v's stencil for the step `step`: act[tile] =
-// step + 1 and bit v of the tile's vertex mask (all 64 lanes of the vertex's
-// wavefront, lane = stencil offset; each tile is marked by the lane at the
-// opening of its runs).  The mask update is an atomic OR whose result is not
-// waited for.
-__device__ __forceinline__ void mark_vertex(int v, const StencilRuns &r, int lane, const Grid &g, uint32_t *act,
+// act_stamp(step) and bit v of the tile's vertex mask (called for each of the
+// 64 stencil offsets k; each tile is marked by the offset at the opening of
+// its runs).  The mask update is an atomic OR whose result is not waited for.
+__device__ __forceinline__ void mark_vertex(int v, const StencilRuns &r, int k, const Grid &g, uint8_t *act,
                                             uint64_t *mask, int nwords, uint32_t step)
 {
-    const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
+    const int kx = k & 3, ky = (k >> 2) & 3, kz = k >> 4;
     if ((r.mx >> kx) & (r.my >> ky) & (r.mz >> kz) & 1u) {
         const int tile = stencil_tile(g, r, kx, ky, kz);
-        act[tile] = step + 1u;
+        act[tile] = act_stamp(step);
         atomicOr((unsigned long long *)&mask[(long long)tile * nwords + (v >> 6)], 1ull << (v & 63));
     }
 }
 
-// One wavefront per vertex, one lane per stencil node: interpolation of
-// u(t+1) (from k_moments on fluid nodes, the wall velocity beyond the walls),
-// Euler update, and the marks of the tiles the vertex reaches at t + 1.
-template <typename T, int P>
-__global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *__restrict__ U,
-                                              const uint32_t *__restrict__ stamp, uint32_t *ctr, uint32_t *act,
-                                              uint64_t *mask, int *err, LBArgs a, MeshArgs m)
+// VPW vertices per wavefront (1: one lane per stencil node; 2: lanes 0-31
+// and 32-63, two stencil nodes per lane, offsets k and k + 32): interpolation
+// of u(t+1) (from k_moments on fluid nodes, the wall velocity beyond the
+// walls), Euler update, and the marks of the tiles the vertex reaches at
+// t + 1.  Two per wavefront halves the wavefronts when there are more than
+// the GPU holds at once.
+template <typename T>
+__device__ __forceinline__ void stencil_velocity(const T *__restrict__ U, const uint32_t *__restrict__ stamp,
+                                                 uint32_t t, const LBArgs &a, int bx, int by, int bz, double qx,
+                                                 double qy, double qz, int k, T &sx, T &sy, T &sz)
 {
     const Grid &g = a.g;
-    const int lane = threadIdx.x & 63;
-    const int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t t = ctr[P];
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        ctr[1 - P] = t + 1u;
-    if (v >= m.nv)
-        return;
-    const int nv = m.nv;
-    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
-    if (!(fabs(qx) < 1e6 && fabs(qy) < 1e6 && fabs(qz) < 1e6)) {
-        if (lane == 0)
-            atomicOr(err, kErrNonFinite);
-        return;
-    }
-    const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
-    const int bx = (int)floor(qx) - 1, by = (int)floor(qy) - 1, bz = (int)floor(qz) - 1;
+    const int kx = k & 3, ky = (k >> 2) & 3, kz = k >> 4;
     const T w = phi4<T>(T((double)(bx + kx) - qx)) * phi4<T>(T((double)(by + ky) - qy)) *
                 phi4<T>(T((double)(bz + kz) - qz));
     const int x = wrapi(bx + kx, g.nx), y = wrapi(by + ky, g.ny);
@@ -1081,22 +1115,69 @@ __global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *_
         uy = fresh ? u1 : T(0);
         uz = fresh ? u2 : T(0);
     }
-    const T sx = wave_sum<T>(ux * w), sy = wave_sum<T>(uy * w), sz = wave_sum<T>(uz * w);
+    sx += ux * w;
+    sy += uy * w;
+    sz += uz * w;
+}
+
+// sum over the 64 / VPW lanes of a vertex
+template <typename T, int VPW>
+__device__ __forceinline__ T group_sum(T v)
+{
+#pragma unroll
+    for (int off = 32 / VPW; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T, int P, int VPW>
+__global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *__restrict__ U,
+                                              const uint32_t *__restrict__ stamp, uint32_t *ctr, uint8_t *act,
+                                              uint64_t *mask, int *err, LBArgs a, MeshArgs m)
+{
+    const Grid &g = a.g;
+    constexpr int L = 64 / VPW;  // lanes per vertex
+    const int sl = threadIdx.x & (L - 1);
+    const int v = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    const uint32_t t = ctr[P];
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        ctr[1 - P] = t + 1u;
+    if (v >= m.nv)
+        return;
+    const int nv = m.nv;
+    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+    if (!(fabs(qx) < 1e6 && fabs(qy) < 1e6 && fabs(qz) < 1e6)) {
+        if (sl == 0)
+            atomicOr(err, kErrNonFinite);
+        return;
+    }
+    const int bx = (int)floor(qx) - 1, by = (int)floor(qy) - 1, bz = (int)floor(qz) - 1;
+    T sx = T(0), sy = T(0), sz = T(0);
+#pragma unroll
+    for (int r = 0; r < VPW; ++r)
+        stencil_velocity<T>(U, stamp, t, a, bx, by, bz, qx, qy, qz, sl + r * L, sx, sy, sz);
+    sx = group_sum<T, VPW>(sx);
+    sy = group_sum<T, VPW>(sy);
+    sz = group_sum<T, VPW>(sz);
     const double nqx = qx + double(sx), nqy = qy + double(sy), nqz = qz + double(sz);
-    if (lane == 0) {
+    if (sl == 0) {
         q[v] = nqx;
         q[nv + v] = nqy;
         q[2 * nv + v] = nqz;
     }
-    if (fabs(nqx) < 1e6 && fabs(nqy) < 1e6 && fabs(nqz) < 1e6)
-        mark_vertex(v, stencil_runs(g, nqx, nqy, nqz), lane, g, act, mask, m.nwords, t + 1u);
-    else if (lane == 0)
+    if (fabs(nqx) < 1e6 && fabs(nqy) < 1e6 && fabs(nqz) < 1e6) {
+        const StencilRuns rn = stencil_runs(g, nqx, nqy, nqz);
+#pragma unroll
+        for (int r = 0; r < VPW; ++r)
+            mark_vertex(v, rn, sl + r * L, g, act, mask, m.nwords, t + 1u);
+    } else if (sl == 0) {
         atomicOr(err, kErrNonFinite);
+    }
 }
 
 // marks of the current step t = ctr[p] from the stored positions (after a
 // reset of the positions or the state; masks cleared beforehand)
-__global__ __launch_bounds__(256) void k_stamp(const double *__restrict__ q, uint32_t *act, uint64_t *mask,
+__global__ __launch_bounds__(256) void k_stamp(const double *__restrict__ q, uint8_t *act, uint64_t *mask,
                                                const uint32_t *__restrict__ ctr, int *err, Grid g, MeshArgs m, int p)
 {
     const int lane = threadIdx.x & 63;
@@ -1384,10 +1465,12 @@ hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, h
 
 // Share of the LB blocks of the nodes outside the active tiles that runs in
 // the forces dispatch (the rest runs in the spreading dispatch), balancing the
-// two latency-bound kernels.  Measured on the 64^3 sheared capsule (FP32):
-// shares 0 / 0.2 / 0.35 / 0.5 / 0.6 / 0.7 / 0.8 gave 29.1 / 28.6 / 28.6 / 28.5 /
-// 28.7 / 29.8 / 29.8 us per step.
-constexpr double kLbShareWithForces = 0.45;
+// two latency-bound kernels.  Measured (FP32, us per step): on the 64^3
+// sheared capsule shares 0 / 0.2 / 0.35 / 0.5 / 0.6 / 0.7 / 0.8 gave 29.1 /
+// 28.6 / 28.6 / 28.5 / 28.7 / 29.8 / 29.8; shares 0.45 / 0.6 / 0.75 gave
+// 28.8 / 28.2 / 28.9 there and 82.4 / 81.5 / 83.8 on the 128x128x96 wetting
+// droplet.
+constexpr double kLbShareWithForces = 0.6;
 
 int lb_blocks_with_forces(const Grid &g)
 {
@@ -1447,12 +1530,22 @@ template <typename S, int P>
 static void move_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s)
 {
     using T = typename Pop<S>::C;
-    const int tiles = a.g.nt;
-    const int mblocks = (tiles + 3) / 4 < d.num_cus ? (tiles + 3) / 4 : d.num_cus;
+    // four active tiles per block (one per wavefront), for the active-tile
+    // count expected at set-up with a quarter in reserve; the blocks stride
+    // over the list if it grows beyond that
+    const int want = (m.tiles_hint + m.tiles_hint / 4 + 3) / 4 + 1;
+    const int cap = (a.g.nt + 3) / 4;
+    const int mblocks = want < cap ? want : cap;
     k_moments<S, P><<<mblocks, 256, 0, s>>>((const S *)d.f, (const T *)d.F, (const T *)d.Fext, d.acnt, d.alist,
                                             (T *)d.U, a);
-    const int blocks = (m.nv + 3) / 4;
-    k_move<T, P><<<blocks, 256, 0, s>>>(d.q, (const T *)d.U, d.stamp, d.ctr, d.act, d.mask, d.err, a, m);
+    // one vertex per wavefront while the GPU holds all of them at once (about
+    // 32 wavefronts per CU at this kernel's register count), else two
+    if (m.nv <= 32 * d.num_cus)
+        k_move<T, P, 1><<<(m.nv + 3) / 4, 256, 0, s>>>(d.q, (const T *)d.U, d.stamp, d.ctr, d.act, d.mask, d.err,
+                                                        a, m);
+    else
+        k_move<T, P, 2><<<(m.nv + 7) / 8, 256, 0, s>>>(d.q, (const T *)d.U, d.stamp, d.ctr, d.act, d.mask, d.err,
+                                                        a, m);
 }
 
 hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
