@@ -166,6 +166,10 @@ int check_domain(const iblb_domain_desc *d, std::string &why)
     if (!d) { why = "null domain"; return IBLB_E_INVAL; }
     if (d->nx < 8 || d->ny < 8 || d->nz < 8) { why = "nx, ny, nz must be >= 8"; return IBLB_E_INVAL; }
     if ((long long)d->nx * d->ny * d->nz > (1ll << 31)) { why = "lattice too large"; return IBLB_E_INVAL; }
+    if (19ll * d->nx * d->ny * d->nz * (long long)pop_bytes(d->precision) >= (1ll << 32)) {
+        why = "lattice too large: the populations must fit in 4 GiB (19 x nodes x bytes per population)";
+        return IBLB_E_INVAL;
+    }
     if (d->wall_mode != IBLB_WALLS_Z && d->wall_mode != IBLB_PERIODIC_ALL) { why = "bad wall_mode"; return IBLB_E_INVAL; }
     if (d->precision < IBLB_FP64 || d->precision > IBLB_BF16_DEV) { why = "bad precision"; return IBLB_E_INVAL; }
     if (!(d->tau > 0.5) || !std::isfinite(d->tau)) { why = "tau must be > 1/2"; return IBLB_E_INVAL; }

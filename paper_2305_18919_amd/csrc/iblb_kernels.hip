@@ -213,23 +213,37 @@ __device__ __forceinline__ bool shifted(const Grid &g, const Nbr &b, int x, int 
     return ok;
 }
 
+// Population slot `idx` (= i * n + node) of f.  The byte offset is formed in
+// 32 bits (the domain check keeps 19 n sizeof(S) below 2^32), which lets the
+// compiler address from a uniform base with one register per access.
+template <typename S>
+__device__ __forceinline__ const S *pop_at(const S *f, uint32_t idx)
+{
+    return reinterpret_cast<const S *>(reinterpret_cast<const char *>(f) + idx * (uint32_t)sizeof(S));
+}
+template <typename S>
+__device__ __forceinline__ S *pop_at(S *f, uint32_t idx)
+{
+    return reinterpret_cast<S *>(reinterpret_cast<char *>(f) + idx * (uint32_t)sizeof(S));
+}
+
 template <typename S, bool SWAPPED>
 __device__ __forceinline__ void load_pops(const S *__restrict__ f, const Grid &g, int x, int y, int zf,
                                           typename Pop<S>::C *d)
 {
-    const long long me = nidx(g, x, y, zf);
-    const long long n = g.n;
+    const uint32_t me = (uint32_t)nidx(g, x, y, zf);
+    const uint32_t n = (uint32_t)g.n;
     if (!SWAPPED) {
 #pragma unroll
         for (int i = 0; i < 19; ++i)
-            d[i] = Pop<S>::get(f[i * n + me], i);
+            d[i] = Pop<S>::get(*pop_at(f, i * n + me), i);
     } else {
         const Nbr b = neighbours(g, x, y, zf);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             long long src;
             const bool ok = shifted(g, b, x, y, zf, i, -1, src);
-            d[i] = Pop<S>::get(ok ? f[opp(i) * n + src] : f[i * n + me], i);
+            d[i] = Pop<S>::get(*pop_at(f, ok ? opp(i) * n + (uint32_t)src : i * n + me), i);
         }
     }
 }
@@ -293,10 +307,11 @@ __device__ __forceinline__ void lb_collide(S *__restrict__ f, const T *__restric
             const T cuw = T(cx(i)) * T(uw[0]) + T(cy(i)) * T(uw[1]) + T(cz(i)) * T(uw[2]);
             post -= T(6) * w * rho * cuw;
         }
+        const uint32_t n32 = (uint32_t)n, me32 = (uint32_t)me;
         if (!ODD || !fluid)
-            store_through(&f[opp(i) * n + me], Pop<S>::put(post, i));
+            store_through(pop_at(f, opp(i) * n32 + me32), Pop<S>::put(post, i));
         else
-            store_through(&f[i * n + dst], Pop<S>::put(post, i));
+            store_through(pop_at(f, i * n32 + (uint32_t)dst), Pop<S>::put(post, i));
     }
 }
 
@@ -830,7 +845,7 @@ __device__ __forceinline__ void stage_store(const Staged<T> &s, int e, T kf, T *
 // a fixed order.  Wavefront 0 finishes with the LB update of the tile's nodes,
 // whose populations it fetched at the start.
 template <typename S, int P, typename T = typename Pop<S>::C>
-__global__ __launch_bounds__(256) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
+__global__ __launch_bounds__(256, 3) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
                                                 const double *__restrict__ partials, const uint32_t *__restrict__ ctr,
                                                 uint64_t *__restrict__ mask, const uint32_t *__restrict__ acnt,
