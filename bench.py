@@ -24,8 +24,10 @@ workload.
 
 --pass lb / --pass copy run only the LB-only pass, or a plain device copy of
 --copy-mib MiB, for hardware-counter runs.  --study precision runs the
-contact-angle comparison of the population storage precisions instead, and
---study shear the capillary-number sweep of the sheared particles.
+contact-angle comparison of the population storage precisions instead,
+--study shear the capillary-number sweep of the sheared particles, and
+--study batch the 48-domain parameter sweep stepped as one batch against the
+same domains stepped one at a time.
 """
 from __future__ import annotations
 
@@ -222,6 +224,65 @@ def shear_study(steps: int):
     print(json.dumps(out), flush=True)
 
 
+def batch_study(steps: int, warmup: int):
+    """The 48-domain parameter sweep (cubic edges 32-80, one droplet each)
+    stepped as one batch -- each step kernel launched once for all domains,
+    launch shape from the library's autotuner -- against the same domains
+    stepped one context after another.  MLUPS count the fluid nodes of the
+    domains still stepped (members frozen by an instability before the timed
+    steps are left out of both rates).  step_roofline: LB bytes of those
+    domains per step (38 FP32 population accesses per node) over the batch's
+    time per step, against 8 TB/s."""
+    import torch
+    from paper_2305_18919_amd import iblb
+    from paper_2305_18919_amd import inputs as I
+    ws = I.batch_sweep()
+    sims = [iblb.Simulation(w.domain, w.mesh, precision=1, graph=True) for w in ws]
+    out = {"study": "batched sweep", "domains": len(ws), "steps": steps, "warmup": warmup}
+    with iblb.Batch(sims) as b:
+        t0 = time.perf_counter()
+        out["tune_ms_per_step"] = round(b.tune(32), 5)
+        out["tune_seconds"] = round(time.perf_counter() - t0, 2)
+        out["config"] = b.config
+        b.step(warmup)
+        status = b.check()
+        live = [k for k, st in enumerate(status) if st == iblb.IBLB_OK]
+        nodes = sum(ws[k].domain.n_fluid for k in live)
+        b.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        b.sync()
+        dt = time.perf_counter() - t0
+        after = b.check()
+    ms = dt * 1e3 / steps
+    out.update({
+        "frozen_before_timing": [ws[k].name for k, st in enumerate(status) if st != iblb.IBLB_OK],
+        "frozen_during_timing": [ws[k].name for k in live if after[k] != iblb.IBLB_OK],
+        "fluid_nodes": nodes, "vertices": sum(ws[k].mesh.n_vertices for k in live),
+        "batch": {"ms_per_step": round(ms, 5), "mlups": round(nodes * steps / dt / 1e6, 1)},
+    })
+    alg = nodes * lb_bytes_per_node(1)
+    out["step_roofline"] = {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "alg_bytes_per_step": alg}
+    # the same domains stepped one context at a time (each replaying its own graphs)
+    seq = 0.0
+    for k in live:
+        s = sims[k]
+        s.step(32)
+        s.sync()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        seq += time.perf_counter() - t0
+    out["one_at_a_time"] = {"ms_per_step": round(seq * 1e3 / steps, 5), "mlups": round(nodes * steps / seq / 1e6, 1)}
+    out["speedup"] = round(seq / dt, 2)
+    for s in sims:
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
 def copy_pass(mib: int, reps: int):
     """A plain device-to-device copy of `mib` MiB, `reps` times (counter calibration)."""
     import torch
@@ -249,7 +310,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pass", dest="only", choices=["lb", "copy"], default=None)
     ap.add_argument("--copy-mib", type=int, default=256)
-    ap.add_argument("--study", choices=["precision", "shear"], default=None,
+    ap.add_argument("--study", choices=["precision", "shear", "batch"], default=None,
                     help="precision: contact angle of the wetting droplet per population storage; "
                          "shear: steady D and Theta against the small-Ca theory")
     ap.add_argument("--study-steps", type=int, default=50000)
@@ -269,6 +330,9 @@ def main():
         return
     if args.study == "shear":
         shear_study(args.study_steps)
+        return
+    if args.study == "batch":
+        batch_study(args.study_steps, args.warmup)
         return
     w, prec = workload(args.workload)
     if args.precision is not None:

@@ -210,6 +210,78 @@ int iblb_active_nodes(iblb_ctx *ctx, int64_t *n);
 const char *iblb_last_error(const iblb_ctx *ctx);
 int iblb_destroy(iblb_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+ * Batches of independent domains
+ *
+ * Parameter sweeps (the contact-angle campaigns of the "Results" section, the
+ * capillary-number sweep of the shear benchmark) run many small, independent
+ * domains.  A batch advances several contexts together: each step launches
+ * each step kernel once for all members, every block working on one member's
+ * arrays, so the members share the per-kernel launch and cache-flush costs
+ * that dominate a small domain's step.  Each member computes what iblb_step
+ * computes for it, in the same operation order: the batched kernels are
+ * compiled from the same code, so a member agrees with the same context
+ * stepped alone to rounding (the compiler fuses a different set of
+ * multiply-adds).  Every launch shape of iblb_batch_config gives
+ * bit-identical results, except vertices_per_wave, which changes the order of
+ * the interpolation sums.
+ *
+ * Members are contexts created with iblb_create / iblb_add_mesh on the
+ * current device: each has a mesh, all have the same precision and step
+ * parity.  They stay owned by the caller, must outlive the batch and keep
+ * answering every query (vertices, volume, shape, contact angle, fields,
+ * checkpoints).  Work is ordered against each member's stream with events,
+ * so queries on a member see the batch's steps.  Stepping a member on its own
+ * while it is in a batch is allowed, but the next batch call then fails with
+ * IBLB_E_STATE if the members' step parities differ.
+ * ------------------------------------------------------------------------- */
+typedef struct iblb_batch iblb_batch;
+
+typedef struct {
+    int32_t lb_block_x;           /* LB blocks of lb_block_x x (256 / lb_block_x) nodes of one z
+                                     layer: 16, 32 or 64 (capped per member by its nx); 0 = the
+                                     single-context rule (64 if nx >= 64, 32 if nx >= 32, else 16) */
+    int32_t spread_blocks_per_cu; /* spreading blocks of the whole batch per compute unit, 1..8,
+                                     shared out in proportion to the members' active tiles;
+                                     0 = 2 (1 with FP64) */
+    int32_t vertices_per_wave;    /* interpolation and move: 1 or 2 vertices per 64-lane wavefront;
+                                     0 = 1 while the batch has at most 32 vertices per compute unit */
+    int32_t reserved;             /* 0 */
+    double lb_share_forces;       /* fraction of each member's LB blocks (nodes outside the active
+                                     tiles) run in the forces dispatch, [0, 1]; default 0.6 */
+} iblb_batch_config;
+
+/* Groups n (1..256) distinct contexts.  hip_stream: the stream the batch's
+ * launches go to (NULL => a stream of its own).  Errors: IBLB_E_INVAL (null or
+ * repeated member, n out of range), IBLB_E_STATE (a member without mesh, or
+ * precisions or step parities that differ), IBLB_E_DEVICE. */
+int iblb_batch_create(iblb_ctx *const *members, int32_t n, void *hip_stream, iblb_batch **out);
+/* n_steps steps of every member that is not frozen (asynchronous; replays a
+ * captured hipGraph of 16 steps from even times).  Each member's step count
+ * advances by n_steps. */
+int iblb_batch_step(iblb_batch *b, int32_t n_steps);
+int iblb_batch_sync(iblb_batch *b);
+/* Synchronises, reads every member's device error bits and freezes each
+ * member that reports one: later batch steps leave it where it is.
+ * status (NULL or n entries): IBLB_OK, or IBLB_E_UNSTABLE for a frozen member
+ * (iblb_batch_member_error gives the reason); *n_frozen: frozen members. */
+int iblb_batch_check(iblb_batch *b, int32_t *status, int32_t *n_frozen);
+const char *iblb_batch_member_error(const iblb_batch *b, int32_t member);
+/* Launch shape of the batch's dispatches; get returns the resolved values. */
+int iblb_batch_get_config(const iblb_batch *b, iblb_batch_config *cfg);
+int iblb_batch_set_config(iblb_batch *b, iblb_batch_config const *cfg);
+/* Autotuner: times trial_steps (rounded up to a multiple of 16) graph-replayed
+ * steps of the batch for each launch shape visited by two passes of
+ * coordinate descent over lb_block_x {16, 32, 64}, lb_share_forces {0.3,
+ * 0.45, 0.6, 0.75}, spread_blocks_per_cu {1, 2, 3} and vertices_per_wave
+ * {1, 2}, keeps the fastest and writes its time per step (ms).  The members'
+ * device state is copied aside first and restored afterwards (needs that much
+ * free device memory), so the trial steps leave no trace. */
+int iblb_batch_tune(iblb_batch *b, int32_t trial_steps, double *best_ms_per_step);
+const char *iblb_batch_last_error(const iblb_batch *b);
+/* Synchronises and frees the batch; the members are untouched. */
+int iblb_batch_destroy(iblb_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -324,19 +324,22 @@ int collect_timing(iblb_ctx *c)
     return IBLB_OK;
 }
 
+std::string err_text(int e)
+{
+    std::string why = "device reported:";
+    if (e & kErrNonFinite) why += " non-finite vertex position;";
+    if (e & kErrOverflow) why += " tile list overflow (vertex pile-up);";
+    if (e & kErrDensity) why += " density out of range or non-finite;";
+    if (e & kErrMach) why += " |u| above 0.3;";
+    if (e & kErrList) why += " invalid vertex index in a tile list;";
+    return why;
+}
+
 int read_err(iblb_ctx *c)
 {
     int e = 0;
     HIP_TRY(c, hipMemcpy(&e, c->d.err, sizeof(int), hipMemcpyDeviceToHost));
-    if (e) {
-        std::string why = "device reported:";
-        if (e & kErrNonFinite) why += " non-finite vertex position;";
-        if (e & kErrOverflow) why += " tile list overflow (vertex pile-up);";
-        if (e & kErrDensity) why += " density out of range or non-finite;";
-        if (e & kErrMach) why += " |u| above 0.3;";
-        if (e & kErrList) why += " invalid vertex index in a tile list;";
-        return fail(c, IBLB_E_UNSTABLE, why);
-    }
+    if (e) return fail(c, IBLB_E_UNSTABLE, err_text(e));
     return IBLB_OK;
 }
 
@@ -1051,6 +1054,519 @@ int iblb_destroy(iblb_ctx *c)
     if (c->fext_alloc) (void)hipFree(c->fext_alloc);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
+    return IBLB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: independent contexts advanced together, one launch of each step
+// kernel per step for all of them
+// ---------------------------------------------------------------------------
+namespace {
+
+// Share of each member's LB blocks in the forces dispatch before tuning (the
+// single-context value).
+constexpr double kBatchLbShare = 0.6;
+
+// Launch shape of a batch; zero fields take the defaults resolved by `resolved`.
+struct BatchCfg {
+    int lb_bx = 0;
+    int spread_per_cu = 0;
+    int vpw = 0;
+    double lb_share = kBatchLbShare;
+};
+
+}  // namespace
+
+struct iblb_batch {
+    std::vector<iblb_ctx *> mem;
+    std::vector<int> status;        // IBLB_OK while stepped; the code that froze the member otherwise
+    std::vector<std::string> why;
+    int prec = 0;
+    int num_cus = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t ev = nullptr;        // end of the batch's work, waited for by the members' streams
+    std::vector<hipEvent_t> mev;    // end of each member's own work, waited for by the batch stream
+    DomRec *recs = nullptr;         // device: one record per member
+    uint32_t *tabs = nullptr;       // device: the four dispatch tables, back to back
+    int *errs = nullptr;            // device: the members' error bits
+    size_t tab_cap = 0;             // entries allocated in tabs
+    int off[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
+    BatchCfg cfg;
+    int vpw_used = 1;
+    bool dirty = true;              // tables to rebuild before the next launch
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int bfail(iblb_batch *b, int code, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BHIP_TRY(b, expr)                                                                                  \
+    do {                                                                                                   \
+        hipError_t e_ = (expr);                                                                            \
+        if (e_ != hipSuccess) return bfail(b, IBLB_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void bdrop_graph(iblb_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+}
+
+// the single-context LB block width for a lattice of width nx
+int lb_width_rule(int nx) { return nx >= 64 ? 64 : (nx >= 32 ? 32 : 16); }
+
+BatchCfg resolved(const iblb_batch *b)
+{
+    BatchCfg c = b->cfg;
+    if (c.spread_per_cu == 0) c.spread_per_cu = b->prec == IBLB_FP64 ? 1 : 2;
+    if (c.vpw == 0) {
+        long long nv = 0;
+        for (size_t k = 0; k < b->mem.size(); ++k)
+            if (b->status[k] == IBLB_OK) nv += b->mem[k]->nv;
+        c.vpw = nv <= 32ll * b->num_cus ? 1 : 2;
+    }
+    return c;
+}
+
+// Per-member records and the four dispatch tables.  The latency-bound blocks
+// of every member (forces and list scan; spreading) come first in their
+// dispatch and the LB blocks of the nodes outside the active tiles after
+// them, so that the hardware starts the former first.
+int build_tables(iblb_batch *b)
+{
+    // launches already queued read the current records and tables
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    const BatchCfg cfg = resolved(b);
+    const int n = (int)b->mem.size();
+    std::vector<DomRec> recs((size_t)n);
+    std::vector<uint32_t> tab[4];
+    long long hint_sum = 0;
+    for (int k = 0; k < n; ++k)
+        if (b->status[(size_t)k] == IBLB_OK) hint_sum += std::max(1, b->mem[(size_t)k]->m.tiles_hint);
+    const double budget = (double)cfg.spread_per_cu * b->num_cus;
+    std::vector<int> nlb((size_t)n, 0);
+    for (int k = 0; k < n; ++k) {
+        const iblb_ctx *c = b->mem[(size_t)k];
+        DomRec &r = recs[(size_t)k];
+        std::memset(&r, 0, sizeof(r));
+        r.d = c->d;
+        r.a = c->lb;
+        r.m = c->m;
+        const int bx = cfg.lb_bx ? std::min(cfg.lb_bx, lb_width_rule(c->g.nx)) : lb_width_rule(c->g.nx);
+        r.bxw = bx;
+        r.nbx = (c->g.nx + bx - 1) / bx;
+        r.nby = (c->g.ny + 256 / bx - 1) / (256 / bx);
+        nlb[(size_t)k] = r.nbx * r.nby * c->g.nzf;
+        r.lb0 = (int)(cfg.lb_share * nlb[(size_t)k] + 0.5);
+        const int hint = std::max(1, c->m.tiles_hint);
+        const long long want = hint_sum > 0 ? std::llround(budget * hint / (double)hint_sum) : 1;
+        r.nsp = (int)std::max(1ll, std::min(want, (long long)c->g.nt));
+        const int mw = (hint + hint / 4 + 3) / 4 + 1, mcap = (c->g.nt + 3) / 4;
+        r.mblocks = std::max(1, std::min(mw, mcap));
+        if ((long long)c->m.nparts + 1 + nlb[(size_t)k] >= (1ll << 24) ||
+            (long long)r.nsp + nlb[(size_t)k] >= (1ll << 24))
+            return bfail(b, IBLB_E_INVAL, "member " + std::to_string(k) + " has too many blocks for a batch");
+    }
+    auto entry = [](int k, int blk) { return (uint32_t)k | ((uint32_t)blk << 8); };
+    auto on = [&](int k) { return b->status[(size_t)k] == IBLB_OK; };
+    for (int k = 0; k < n; ++k)
+        if (on(k))
+            for (int j = 0; j <= recs[(size_t)k].m.nparts; ++j) tab[B_FORCES].push_back(entry(k, j));
+    for (int k = 0; k < n; ++k)
+        if (on(k))
+            for (int j = 0; j < recs[(size_t)k].lb0; ++j)
+                tab[B_FORCES].push_back(entry(k, recs[(size_t)k].m.nparts + 1 + j));
+    for (int k = 0; k < n; ++k)
+        if (on(k))
+            for (int j = 0; j < recs[(size_t)k].nsp; ++j) tab[B_SPREAD].push_back(entry(k, j));
+    for (int k = 0; k < n; ++k)
+        if (on(k))
+            for (int j = 0; j < nlb[(size_t)k] - recs[(size_t)k].lb0; ++j)
+                tab[B_SPREAD].push_back(entry(k, recs[(size_t)k].nsp + j));
+    for (int k = 0; k < n; ++k)
+        if (on(k))
+            for (int j = 0; j < recs[(size_t)k].mblocks; ++j) tab[B_MOMENTS].push_back(entry(k, j));
+    for (int k = 0; k < n; ++k)
+        if (on(k)) {
+            const int nv = recs[(size_t)k].m.nv;
+            const int blocks = cfg.vpw == 2 ? (nv + 7) / 8 : (nv + 3) / 4;
+            for (int j = 0; j < blocks; ++j) tab[B_MOVE].push_back(entry(k, j));
+        }
+    size_t total = 0;
+    for (int w = 0; w < 4; ++w) {
+        b->off[w] = (int)total;
+        b->cnt[w] = (int)tab[w].size();
+        total += tab[w].size();
+    }
+    bdrop_graph(b);
+    if (total > b->tab_cap) {
+        if (b->tabs) (void)hipFree(b->tabs);
+        b->tabs = nullptr;
+        b->tab_cap = 0;
+        BHIP_TRY(b, hipMalloc(&b->tabs, total * 4));
+        b->tab_cap = total;
+    }
+    std::vector<uint32_t> all;
+    all.reserve(total);
+    for (int w = 0; w < 4; ++w) all.insert(all.end(), tab[w].begin(), tab[w].end());
+    BHIP_TRY(b, hipMemcpyAsync(b->recs, recs.data(), recs.size() * sizeof(DomRec), hipMemcpyHostToDevice, b->stream));
+    if (total) BHIP_TRY(b, hipMemcpyAsync(b->tabs, all.data(), total * 4, hipMemcpyHostToDevice, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    b->vpw_used = cfg.vpw;
+    b->dirty = false;
+    return IBLB_OK;
+}
+
+hipError_t batch_enqueue(iblb_batch *b, int p)
+{
+    for (int w = 0; w < 4; ++w) {
+        hipError_t e = launch_batch(b->prec, w, b->recs, b->tabs + b->off[w], b->cnt[w], p, b->vpw_used, b->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// n steps of every stepped member from a time of parity t0 & 1 (the members'
+// host step counters are the caller's): graphs of kGraphSteps steps from even
+// times, single launches otherwise.
+int batch_advance(iblb_batch *b, long long t0, int n)
+{
+    if (b->dirty) {
+        int rc = build_tables(b);
+        if (rc) return rc;
+    }
+    if (b->cnt[B_FORCES] == 0) return IBLB_OK;  // every member frozen
+    long long t = t0;
+    int left = n;
+    while (left > 0) {
+        const int p = (int)(t & 1);
+        if (p == 0 && left >= kGraphSteps) {
+            if (!b->gexec) {
+                BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                hipError_t e = hipSuccess;
+                for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = batch_enqueue(b, k & 1);
+                hipGraph_t gr = nullptr;
+                hipError_t e2 = hipStreamEndCapture(b->stream, &gr);
+                if (e != hipSuccess) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    return bfail(b, IBLB_E_DEVICE, std::string("batch step capture: ") + hipGetErrorString(e));
+                }
+                BHIP_TRY(b, e2);
+                b->graph = gr;
+                BHIP_TRY(b, hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+            }
+            BHIP_TRY(b, hipGraphLaunch(b->gexec, b->stream));
+            t += kGraphSteps;
+            left -= kGraphSteps;
+        } else {
+            BHIP_TRY(b, batch_enqueue(b, p));
+            t += 1;
+            left -= 1;
+        }
+    }
+    return IBLB_OK;
+}
+
+// the batch stream waits for the work already queued on each stepped member's stream
+int order_after_members(iblb_batch *b)
+{
+    for (size_t k = 0; k < b->mem.size(); ++k) {
+        if (b->status[k] != IBLB_OK) continue;
+        BHIP_TRY(b, hipEventRecord(b->mev[k], b->mem[k]->stream));
+        BHIP_TRY(b, hipStreamWaitEvent(b->stream, b->mev[k], 0));
+    }
+    return IBLB_OK;
+}
+
+// each member's stream waits for the batch's work queued so far
+int order_members_after(iblb_batch *b)
+{
+    BHIP_TRY(b, hipEventRecord(b->ev, b->stream));
+    for (size_t k = 0; k < b->mem.size(); ++k) BHIP_TRY(b, hipStreamWaitEvent(b->mem[k]->stream, b->ev, 0));
+    return IBLB_OK;
+}
+
+// a step counter of the stepped members (whose parities must agree)
+int batch_time(iblb_batch *b, long long *t0)
+{
+    bool have = false;
+    *t0 = 0;
+    for (size_t k = 0; k < b->mem.size(); ++k) {
+        if (b->status[k] != IBLB_OK) continue;
+        const long long t = b->mem[k]->t;
+        if (!have) {
+            *t0 = t;
+            have = true;
+        } else if ((t & 1) != (*t0 & 1)) {
+            return bfail(b, IBLB_E_STATE, "member " + std::to_string(k) +
+                                              " was stepped on its own: the members' step parities differ");
+        }
+    }
+    return IBLB_OK;
+}
+
+// device byte ranges holding a member's whole state (workspace and mesh block)
+void state_regions(const iblb_ctx *c, std::vector<std::pair<char *, size_t>> &out)
+{
+    if (c->mesh_alloc) {
+        out.push_back({c->ws, c->L.dom_end});
+        out.push_back({(char *)c->mesh_alloc, c->L.mesh_end - c->L.dom_end});
+    } else {
+        out.push_back({c->ws, c->L.mesh_end});
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int iblb_batch_create(iblb_ctx *const *members, int32_t n, void *hip_stream, iblb_batch **out)
+{
+    if (!out) return IBLB_E_INVAL;
+    *out = nullptr;
+    if (!members || n < 1 || n > kMaxBatch) return IBLB_E_INVAL;
+    for (int k = 0; k < n; ++k) {
+        const iblb_ctx *c = members[k];
+        if (!c) return IBLB_E_INVAL;
+        for (int j = 0; j < k; ++j)
+            if (members[j] == c) return IBLB_E_INVAL;
+        if (!c->has_mesh || c->prec != members[0]->prec || ((c->t ^ members[0]->t) & 1)) return IBLB_E_STATE;
+    }
+    iblb_batch *b = new iblb_batch();
+    b->mem.assign(members, members + n);
+    b->status.assign((size_t)n, IBLB_OK);
+    b->why.assign((size_t)n, std::string());
+    b->prec = members[0]->prec;
+    b->num_cus = members[0]->d.num_cus;
+    auto bail = [&](int code) {
+        iblb_batch_destroy(b);
+        return code;
+    };
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) return bail(IBLB_E_DEVICE);
+        b->own_stream = true;
+    }
+    if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) return bail(IBLB_E_DEVICE);
+    b->mev.assign((size_t)n, nullptr);
+    for (int k = 0; k < n; ++k)
+        if (hipEventCreateWithFlags(&b->mev[(size_t)k], hipEventDisableTiming) != hipSuccess) return bail(IBLB_E_DEVICE);
+    if (hipMalloc(&b->recs, (size_t)n * sizeof(DomRec)) != hipSuccess ||
+        hipMalloc(&b->errs, (size_t)n * sizeof(int)) != hipSuccess)
+        return bail(IBLB_E_DEVICE);
+    if (order_after_members(b) || build_tables(b)) return bail(IBLB_E_DEVICE);
+    *out = b;
+    return IBLB_OK;
+}
+
+int iblb_batch_step(iblb_batch *b, int32_t n_steps)
+{
+    if (!b || n_steps < 0) return IBLB_E_INVAL;
+    long long t0 = 0;
+    int rc = batch_time(b, &t0);
+    if (!rc) rc = order_after_members(b);
+    if (!rc) rc = batch_advance(b, t0, n_steps);
+    if (!rc) rc = order_members_after(b);
+    if (rc) return rc;
+    for (size_t k = 0; k < b->mem.size(); ++k)
+        if (b->status[k] == IBLB_OK) b->mem[k]->t += n_steps;
+    return IBLB_OK;
+}
+
+int iblb_batch_sync(iblb_batch *b)
+{
+    if (!b) return IBLB_E_INVAL;
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    return IBLB_OK;
+}
+
+int iblb_batch_check(iblb_batch *b, int32_t *status, int32_t *n_frozen)
+{
+    if (!b) return IBLB_E_INVAL;
+    const int n = (int)b->mem.size();
+    std::vector<int> e((size_t)n, 0);
+    BHIP_TRY(b, launch_batch_errors(b->recs, n, b->errs, b->stream));
+    BHIP_TRY(b, hipMemcpyAsync(e.data(), b->errs, (size_t)n * 4, hipMemcpyDeviceToHost, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    int frozen = 0;
+    for (int k = 0; k < n; ++k) {
+        if (b->status[(size_t)k] == IBLB_OK && e[(size_t)k] != 0) {
+            b->status[(size_t)k] = IBLB_E_UNSTABLE;
+            b->why[(size_t)k] = err_text(e[(size_t)k]);
+            b->dirty = true;
+        }
+        if (status) status[k] = b->status[(size_t)k];
+        frozen += b->status[(size_t)k] != IBLB_OK;
+    }
+    if (n_frozen) *n_frozen = frozen;
+    return IBLB_OK;
+}
+
+const char *iblb_batch_member_error(const iblb_batch *b, int32_t member)
+{
+    if (!b || member < 0 || member >= (int)b->mem.size()) return "bad batch or member index";
+    return b->why[(size_t)member].c_str();
+}
+
+int iblb_batch_get_config(const iblb_batch *b, iblb_batch_config *cfg)
+{
+    if (!b || !cfg) return IBLB_E_INVAL;
+    const BatchCfg c = resolved(b);
+    cfg->lb_block_x = c.lb_bx;
+    cfg->spread_blocks_per_cu = c.spread_per_cu;
+    cfg->vertices_per_wave = c.vpw;
+    cfg->reserved = 0;
+    cfg->lb_share_forces = c.lb_share;
+    return IBLB_OK;
+}
+
+int iblb_batch_set_config(iblb_batch *b, const iblb_batch_config *cfg)
+{
+    if (!b || !cfg) return IBLB_E_INVAL;
+    if ((cfg->lb_block_x != 0 && cfg->lb_block_x != 16 && cfg->lb_block_x != 32 && cfg->lb_block_x != 64) ||
+        cfg->spread_blocks_per_cu < 0 || cfg->spread_blocks_per_cu > 8 || cfg->vertices_per_wave < 0 ||
+        cfg->vertices_per_wave > 2 || !(cfg->lb_share_forces >= 0.0 && cfg->lb_share_forces <= 1.0))
+        return bfail(b, IBLB_E_INVAL, "bad batch configuration");
+    b->cfg.lb_bx = cfg->lb_block_x;
+    b->cfg.spread_per_cu = cfg->spread_blocks_per_cu;
+    b->cfg.vpw = cfg->vertices_per_wave;
+    b->cfg.lb_share = cfg->lb_share_forces;
+    b->dirty = true;
+    return IBLB_OK;
+}
+
+int iblb_batch_tune(iblb_batch *b, int32_t trial_steps, double *best_ms_per_step)
+{
+    if (!b || trial_steps < 1) return IBLB_E_INVAL;
+    const int trial = (trial_steps + kGraphSteps - 1) / kGraphSteps * kGraphSteps;
+    long long t0 = 0;
+    int rc = batch_time(b, &t0);
+    if (!rc) rc = order_after_members(b);
+    if (rc) return rc;
+    // a copy of every stepped member's device state, put back afterwards
+    std::vector<std::pair<char *, size_t>> regs;
+    for (size_t k = 0; k < b->mem.size(); ++k)
+        if (b->status[k] == IBLB_OK) state_regions(b->mem[k], regs);
+    size_t total = 0;
+    for (auto &r : regs) total += align256(r.second);
+    struct Owned {
+        char *p = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Owned()
+        {
+            if (p) (void)hipFree(p);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } own;
+    BHIP_TRY(b, hipMalloc(&own.p, std::max<size_t>(total, 256)));
+    BHIP_TRY(b, hipEventCreate(&own.e0));
+    BHIP_TRY(b, hipEventCreate(&own.e1));
+    size_t o = 0;
+    for (auto &r : regs) {
+        BHIP_TRY(b, hipMemcpyAsync(own.p + o, r.first, r.second, hipMemcpyDeviceToDevice, b->stream));
+        o += align256(r.second);
+    }
+    long long t = t0;
+    auto run = [&](const BatchCfg &cfg, double *ms) -> int {
+        b->cfg = cfg;
+        b->dirty = true;
+        const int warm = kGraphSteps + (int)(t & 1);  // graph capture included; ends at an even time
+        int r = batch_advance(b, t, warm);
+        if (r) return r;
+        t += warm;
+        BHIP_TRY(b, hipEventRecord(own.e0, b->stream));
+        r = batch_advance(b, t, trial);
+        if (r) return r;
+        t += trial;
+        BHIP_TRY(b, hipEventRecord(own.e1, b->stream));
+        BHIP_TRY(b, hipEventSynchronize(own.e1));
+        float f = 0.f;
+        BHIP_TRY(b, hipEventElapsedTime(&f, own.e0, own.e1));
+        *ms = (double)f / trial;
+        return IBLB_OK;
+    };
+    const BatchCfg start = b->cfg;
+    BatchCfg best = resolved(b);
+    if (best.lb_bx == 0) best.lb_bx = 64;
+    double best_ms = 0.0;
+    rc = run(best, &best_ms);
+    // coordinate descent: two passes over the four launch parameters
+    for (int pass = 0; pass < 2 && !rc; ++pass) {
+        for (int dim = 0; dim < 4 && !rc; ++dim) {
+            std::vector<BatchCfg> cands;
+            BatchCfg c = best;
+            if (dim == 0)
+                for (int v : {16, 32, 64}) { c.lb_bx = v; cands.push_back(c); }
+            if (dim == 1)
+                for (double v : {0.3, 0.45, 0.6, 0.75}) { c.lb_share = v; cands.push_back(c); }
+            if (dim == 2)
+                for (int v : {1, 2, 3}) { c.spread_per_cu = v; cands.push_back(c); }
+            if (dim == 3)
+                for (int v : {1, 2}) { c.vpw = v; cands.push_back(c); }
+            const BatchCfg cur = best;
+            for (const BatchCfg &cand : cands) {
+                if (cand.lb_bx == cur.lb_bx && cand.lb_share == cur.lb_share &&
+                    cand.spread_per_cu == cur.spread_per_cu && cand.vpw == cur.vpw)
+                    continue;
+                double ms = 0.0;
+                rc = run(cand, &ms);
+                if (rc) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = cand;
+                }
+            }
+        }
+    }
+    o = 0;
+    for (auto &r : regs) {
+        BHIP_TRY(b, hipMemcpyAsync(r.first, own.p + o, r.second, hipMemcpyDeviceToDevice, b->stream));
+        o += align256(r.second);
+    }
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    b->cfg = rc ? start : best;
+    b->dirty = true;
+    if (rc) return rc;
+    rc = build_tables(b);
+    if (!rc) rc = order_members_after(b);
+    if (rc) return rc;
+    if (best_ms_per_step) *best_ms_per_step = best_ms;
+    return IBLB_OK;
+}
+
+const char *iblb_batch_last_error(const iblb_batch *b)
+{
+    if (!b) return "null batch";
+    return b->err.c_str();
+}
+
+int iblb_batch_destroy(iblb_batch *b)
+{
+    if (!b) return IBLB_E_INVAL;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    bdrop_graph(b);
+    if (b->recs) (void)hipFree(b->recs);
+    if (b->tabs) (void)hipFree(b->tabs);
+    if (b->errs) (void)hipFree(b->errs);
+    if (b->ev) (void)hipEventDestroy(b->ev);
+    for (hipEvent_t e : b->mev)
+        if (e) (void)hipEventDestroy(e);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
     return IBLB_OK;
 }
 

@@ -87,6 +87,22 @@ struct Dev {
     int num_cus;          // compute units of the device (launch sizing)
 };
 
+// One domain of a batch: its arrays, arguments and launch shape, read by every
+// block of a batched dispatch that works on it.
+struct DomRec {
+    Dev d;
+    LBArgs a;
+    MeshArgs m;
+    int bxw, nbx, nby;    // LB blocks: bxw x (256 / bxw) nodes of one z layer, nbx x nby per layer
+    int nsp;              // spreading blocks
+    int lb0;              // LB blocks run by the forces dispatch (the spreading dispatch runs the rest)
+    int mblocks;          // moments blocks
+};
+// Domains per batch: a batched dispatch names a block's domain in 8 bits.
+constexpr int kMaxBatch = 256;
+// Batched dispatches of one step, in launch order.
+enum { B_FORCES = 0, B_SPREAD = 1, B_MOMENTS = 2, B_MOVE = 3 };
+
 // launchers (iblb_kernels.hip); precision 0 = FP64, 1 = FP32, 2 = FP16 and
 // 3 = BF16 population storage (the last three compute in FP32)
 hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hipStream_t s);
@@ -109,6 +125,14 @@ hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &
 // act stamps and vertex masks of the current step from the stored positions
 // (masks and stamps cleared beforehand)
 hipError_t launch_stamp(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s);
+// One batched dispatch `which` over `nblocks` blocks: entry k of `tab` is block
+// k's domain (low 8 bits) and its block index within the single-domain
+// dispatch of that domain (upper 24 bits).  vpw: vertices per wavefront of the
+// move (1 or 2).
+hipError_t launch_batch(int prec, int which, const DomRec *recs, const uint32_t *tab, int nblocks, int p, int vpw,
+                        hipStream_t s);
+// err[k] = *recs[k].d.err for k < n
+hipError_t launch_batch_errors(const DomRec *recs, int n, int *err, hipStream_t s);
 // debug / query kernels
 hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double *out, hipStream_t s);
 hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, int p, const double *in, hipStream_t s);

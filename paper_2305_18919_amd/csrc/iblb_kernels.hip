@@ -704,6 +704,25 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
 // blocks of the nodes outside the active tiles (the spreading dispatch runs
 // the rest).
 template <typename S, int P, typename T = typename Pop<S>::C>
+__device__ __forceinline__ void forces_dispatch(int blk, const double *__restrict__ q,
+                                                const double *__restrict__ Xref, const int4 *__restrict__ inc4,
+                                                const double *__restrict__ fref, T *__restrict__ phiSW,
+                                                T *__restrict__ gVout, Base *__restrict__ base,
+                                                T *__restrict__ wts, double *__restrict__ partials,
+                                                const uint8_t *__restrict__ act, uint32_t *acnt, int *alist,
+                                                const uint32_t *__restrict__ ctr, S *__restrict__ f,
+                                                const T *__restrict__ Fext, int *err, const LBArgs &a,
+                                                const MeshArgs &m, int bxw, int nbx, int nby)
+{
+    if (blk < m.nparts)
+        forces_block<T>(blk, q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, err, a.g, m);
+    else if (blk == m.nparts)
+        scan_block(act, acnt, alist, ctr[P], a.g);
+    else
+        bulk_lb_block<S, P == 1>(blk - m.nparts - 1, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
+}
+
+template <typename S, int P, typename T = typename Pop<S>::C>
 __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, const double *__restrict__ Xref,
                                                 const int4 *__restrict__ inc4,
                                                 const double *__restrict__ fref, T *__restrict__ phiSW,
@@ -714,12 +733,8 @@ __global__ __launch_bounds__(256) void k_forces(const double *__restrict__ q, co
                                                 const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m, int bxw,
                                                 int nbx, int nby)
 {
-    if ((int)blockIdx.x < m.nparts)
-        forces_block<T>(blockIdx.x, q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, err, a.g, m);
-    else if ((int)blockIdx.x == m.nparts)
-        scan_block(act, acnt, alist, ctr[P], a.g);
-    else
-        bulk_lb_block<S, P == 1>(blockIdx.x - m.nparts - 1, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
+    forces_dispatch<S, P, T>((int)blockIdx.x, q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, act, acnt,
+                             alist, ctr, f, Fext, err, a, m, bxw, nbx, nby);
 }
 
 // k_V (V - V0)/V0 from the force-kernel partials, summed by one wavefront in a
@@ -845,19 +860,19 @@ __device__ __forceinline__ void stage_store(const Staged<T> &s, int e, T kf, T *
 // a fixed order.  Wavefront 0 finishes with the LB update of the tile's nodes,
 // whose populations it fetched at the start.
 template <typename S, int P, typename T = typename Pop<S>::C>
-__global__ __launch_bounds__(256, 3) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
+__device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
                                                 const double *__restrict__ partials, const uint32_t *__restrict__ ctr,
                                                 uint64_t *__restrict__ mask, const uint32_t *__restrict__ acnt,
                                                 const int *__restrict__ alist, T *__restrict__ F,
                                                 uint32_t *__restrict__ stamp, S *__restrict__ f,
-                                                const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m,
+                                                const T *__restrict__ Fext, int *err, const LBArgs &a, const MeshArgs &m,
                                                 const uint8_t *__restrict__ act, int nsp, int lb0, int bxw, int nbx,
                                                 int nby)
 {
     const Grid &g = a.g;
-    if ((int)blockIdx.x >= nsp) {
-        bulk_lb_block<S, P == 1>(lb0 + (int)blockIdx.x - nsp, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
+    if (blk >= nsp) {
+        bulk_lb_block<S, P == 1>(lb0 + blk - nsp, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
         return;
     }
     __shared__ int sid[kTileCap];
@@ -878,11 +893,11 @@ __global__ __launch_bounds__(256, 3) void k_spread(const Base *__restrict__ base
     // (block index < nsp <= tile count, so the slot exists); the volatile
     // read keeps the compiler from deferring it past the test on the count
     const uint32_t na = acnt[0];
-    int tile = ((const volatile int *)alist)[blockIdx.x];
+    int tile = ((const volatile int *)alist)[(uint32_t)blk];
     const uint32_t t = ctr[P];
     const int w0 = tid * J;
     uint64_t wv[4];  // this thread's mask words of the current tile
-    for (uint32_t ai = blockIdx.x; ai < na; ai += nsp) {
+    for (uint32_t ai = (uint32_t)blk; ai < na; ai += nsp) {
         const uint32_t an = ai + nsp;
         const int next = alist[an < na ? an : ai];
         // this lane's node; wavefront 0 fetches its populations now, next to
@@ -894,7 +909,7 @@ __global__ __launch_bounds__(256, 3) void k_spread(const Base *__restrict__ base
         const int x = tx * 4 + lx, y = ty * 4 + ly, zf = tz * 4 + lz;
         const bool node = x < g.nx && y < g.ny && zf < g.nzf;
         uint64_t *mw = mask + (long long)tile * W;
-        if (ai == blockIdx.x) {
+        if (ai == (uint32_t)blk) {
             // the first tile's words; later tiles' words were fetched during
             // the previous tile
 #pragma unroll
@@ -913,7 +928,7 @@ __global__ __launch_bounds__(256, 3) void k_spread(const Base *__restrict__ base
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             c += __popcll(wv[j]) + (wv[j] != 0ull ? 1 << 20 : 0);
-        if (wave == 1 && ai == blockIdx.x) {
+        if (wave == 1 && ai == (uint32_t)blk) {
             const T kfac = T(volume_factor(partials, m, lane));
             if (lane == 0)
                 skfac = kfac;
@@ -1030,24 +1045,39 @@ __global__ __launch_bounds__(256, 3) void k_spread(const Base *__restrict__ base
     }
 }
 
+template <typename S, int P, typename T = typename Pop<S>::C>
+__global__ __launch_bounds__(256, 3) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
+                                                const T *__restrict__ phiSW, const T *__restrict__ gV,
+                                                const double *__restrict__ partials, const uint32_t *__restrict__ ctr,
+                                                uint64_t *__restrict__ mask, const uint32_t *__restrict__ acnt,
+                                                const int *__restrict__ alist, T *__restrict__ F,
+                                                uint32_t *__restrict__ stamp, S *__restrict__ f,
+                                                const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m,
+                                                const uint8_t *__restrict__ act, int nsp, int lb0, int bxw, int nbx,
+                                                int nby)
+{
+    spread_dispatch<S, P, T>((int)blockIdx.x, base, wts, phiSW, gV, partials, ctr, mask, acnt, alist, F, stamp, f,
+                             Fext, err, a, m, act, nsp, lb0, bxw, nbx, nby);
+}
+
 // u(t+1) = (sum c f(t+1) + F(t)/2) / rho(t+1) once per node of the active
 // tiles (one wavefront per tile, one lane per node), for the interpolation.
 // P = t & 1: after this step's LB the populations of time t + 1 sit in the
 // swapped layout exactly when P == 0.
 template <typename S, int P, typename T = typename Pop<S>::C>
-__global__ __launch_bounds__(256) void k_moments(const S *__restrict__ f, const T *__restrict__ Fib,
+__device__ __forceinline__ void moments_dispatch(int blk, int nblk, const S *__restrict__ f, const T *__restrict__ Fib,
                                                  const T *__restrict__ Fext, const uint32_t *__restrict__ acnt,
-                                                 const int *__restrict__ alist, T *__restrict__ U, LBArgs a)
+                                                 const int *__restrict__ alist, T *__restrict__ U, const LBArgs &a)
 {
     const Grid &g = a.g;
     const int lane = threadIdx.x & 63;
     const uint32_t na = acnt[0];
-    const uint32_t first = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t first = (uint32_t)blk * 4 + (threadIdx.x >> 6);
     // the first tile is read together with the count (clamped into the list;
     // volatile, so that it is not deferred past the test on the count)
     int tile = ((const volatile int *)alist)[first < (uint32_t)g.nt ? first : 0u];
-    for (uint32_t ai = first; ai < na; ai += gridDim.x * 4) {
-        const uint32_t an = ai + gridDim.x * 4;
+    for (uint32_t ai = first; ai < na; ai += (uint32_t)nblk * 4) {
+        const uint32_t an = ai + (uint32_t)nblk * 4;
         const int next = alist[an < na ? an : ai];
         const int tz = tile / (g.ntx * g.nty);
         const int rem = tile - tz * g.ntx * g.nty;
@@ -1078,6 +1108,14 @@ __global__ __launch_bounds__(256) void k_moments(const S *__restrict__ f, const 
         U[g.n + me] = (my + T(0.5) * Fy) / rho;
         U[2 * g.n + me] = (mz + T(0.5) * Fz) / rho;
     }
+}
+
+template <typename S, int P, typename T = typename Pop<S>::C>
+__global__ __launch_bounds__(256) void k_moments(const S *__restrict__ f, const T *__restrict__ Fib,
+                                                 const T *__restrict__ Fext, const uint32_t *__restrict__ acnt,
+                                                 const int *__restrict__ alist, T *__restrict__ U, LBArgs a)
+{
+    moments_dispatch<S, P, T>((int)blockIdx.x, (int)gridDim.x, f, Fib, Fext, acnt, alist, U, a);
 }
 
 // Marks the tiles of vertex v's stencil for the step `step`: act[tile] =
@@ -1146,16 +1184,16 @@ __device__ __forceinline__ T group_sum(T v)
 }
 
 template <typename T, int P, int VPW>
-__global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *__restrict__ U,
+__device__ __forceinline__ void move_dispatch(int blk, double *__restrict__ q, const T *__restrict__ U,
                                               const uint32_t *__restrict__ stamp, uint32_t *ctr, uint8_t *act,
-                                              uint64_t *mask, int *err, LBArgs a, MeshArgs m)
+                                              uint64_t *mask, int *err, const LBArgs &a, const MeshArgs &m)
 {
     const Grid &g = a.g;
     constexpr int L = 64 / VPW;  // lanes per vertex
     const int sl = threadIdx.x & (L - 1);
-    const int v = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    const int v = (blk * 256 + (int)threadIdx.x) / L;
     const uint32_t t = ctr[P];
-    if (blockIdx.x == 0 && threadIdx.x == 0)
+    if (blk == 0 && threadIdx.x == 0)
         ctr[1 - P] = t + 1u;
     if (v >= m.nv)
         return;
@@ -1190,6 +1228,14 @@ __global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *_
     }
 }
 
+template <typename T, int P, int VPW>
+__global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *__restrict__ U,
+                                              const uint32_t *__restrict__ stamp, uint32_t *ctr, uint8_t *act,
+                                              uint64_t *mask, int *err, LBArgs a, MeshArgs m)
+{
+    move_dispatch<T, P, VPW>((int)blockIdx.x, q, U, stamp, ctr, act, mask, err, a, m);
+}
+
 // marks of the current step t = ctr[p] from the stored positions (after a
 // reset of the positions or the state; masks cleared beforehand)
 __global__ __launch_bounds__(256) void k_stamp(const double *__restrict__ q, uint8_t *act, uint64_t *mask,
@@ -1204,6 +1250,61 @@ __global__ __launch_bounds__(256) void k_stamp(const double *__restrict__ q, uin
         mark_vertex(v, stencil_runs(g, qx, qy, qz), lane, g, act, mask, m.nwords, ctr[p]);
     else if (lane == 0)
         atomicOr(err, kErrNonFinite);
+}
+
+// ---------------------------------------------------------------------------
+// Batched dispatches: one launch of each step kernel advances every domain of
+// a batch.  Block k reads its domain and its block index within that domain's
+// dispatch from tab[k], then that domain's record, and runs exactly the code
+// of the single-domain dispatch; the ordering of the table (latency-bound
+// blocks of every domain first, LB blocks after) is the host's.
+// ---------------------------------------------------------------------------
+template <typename S, int P, typename T = typename Pop<S>::C>
+__global__ __launch_bounds__(256) void kb_forces(const DomRec *__restrict__ R, const uint32_t *__restrict__ tab)
+{
+    const uint32_t e = tab[blockIdx.x];
+    const DomRec &r = R[e & 0xffu];
+    const Dev &d = r.d;
+    forces_dispatch<S, P, T>((int)(e >> 8), d.q, d.Xref, d.inc4, d.fref, (T *)d.phiSW, (T *)d.gV, d.base,
+                             (T *)d.wts, d.partials, d.act, d.acnt, d.alist, d.ctr, (S *)d.f, (const T *)d.Fext,
+                             d.err, r.a, r.m, r.bxw, r.nbx, r.nby);
+}
+
+template <typename S, int P, typename T = typename Pop<S>::C>
+__global__ __launch_bounds__(256, 3) void kb_spread(const DomRec *__restrict__ R, const uint32_t *__restrict__ tab)
+{
+    const uint32_t e = tab[blockIdx.x];
+    const DomRec &r = R[e & 0xffu];
+    const Dev &d = r.d;
+    spread_dispatch<S, P, T>((int)(e >> 8), d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV,
+                             d.partials, d.ctr, d.mask, d.acnt, d.alist, (T *)d.F, d.stamp, (S *)d.f,
+                             (const T *)d.Fext, d.err, r.a, r.m, d.act, r.nsp, r.lb0, r.bxw, r.nbx, r.nby);
+}
+
+template <typename S, int P, typename T = typename Pop<S>::C>
+__global__ __launch_bounds__(256) void kb_moments(const DomRec *__restrict__ R, const uint32_t *__restrict__ tab)
+{
+    const uint32_t e = tab[blockIdx.x];
+    const DomRec &r = R[e & 0xffu];
+    const Dev &d = r.d;
+    moments_dispatch<S, P, T>((int)(e >> 8), r.mblocks, (const S *)d.f, (const T *)d.F, (const T *)d.Fext, d.acnt,
+                              d.alist, (T *)d.U, r.a);
+}
+
+template <typename T, int P, int VPW>
+__global__ __launch_bounds__(256) void kb_move(const DomRec *__restrict__ R, const uint32_t *__restrict__ tab)
+{
+    const uint32_t e = tab[blockIdx.x];
+    const DomRec &r = R[e & 0xffu];
+    const Dev &d = r.d;
+    move_dispatch<T, P, VPW>((int)(e >> 8), d.q, (const T *)d.U, d.stamp, d.ctr, d.act, d.mask, d.err, r.a, r.m);
+}
+
+__global__ __launch_bounds__(256) void kb_errors(const DomRec *__restrict__ R, int n, int *__restrict__ err)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n)
+        err[k] = *R[k].d.err;
 }
 
 // ---------------------------------------------------------------------------
@@ -1569,6 +1670,39 @@ hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &
         using S = decltype(tag);
         p ? move_launch<S, 1>(d, a, m, s) : move_launch<S, 0>(d, a, m, s);
     });
+}
+
+template <typename S, int P>
+static void batch_launch(int which, const DomRec *R, const uint32_t *tab, int nb, int vpw, hipStream_t s)
+{
+    using T = typename Pop<S>::C;
+    switch (which) {
+    case B_FORCES: kb_forces<S, P><<<nb, 256, 0, s>>>(R, tab); break;
+    case B_SPREAD: kb_spread<S, P><<<nb, 256, 0, s>>>(R, tab); break;
+    case B_MOMENTS: kb_moments<S, P><<<nb, 256, 0, s>>>(R, tab); break;
+    default:
+        if (vpw == 2)
+            kb_move<T, P, 2><<<nb, 256, 0, s>>>(R, tab);
+        else
+            kb_move<T, P, 1><<<nb, 256, 0, s>>>(R, tab);
+    }
+}
+
+hipError_t launch_batch(int prec, int which, const DomRec *recs, const uint32_t *tab, int nblocks, int p, int vpw,
+                        hipStream_t s)
+{
+    if (nblocks <= 0)
+        return hipSuccess;
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        p ? batch_launch<S, 1>(which, recs, tab, nblocks, vpw, s) : batch_launch<S, 0>(which, recs, tab, nblocks, vpw, s);
+    });
+}
+
+hipError_t launch_batch_errors(const DomRec *recs, int n, int *err, hipStream_t s)
+{
+    kb_errors<<<(n + 255) / 256, 256, 0, s>>>(recs, n, err);
+    return hipGetLastError();
 }
 
 hipError_t launch_stamp(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)

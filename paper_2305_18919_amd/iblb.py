@@ -40,6 +40,11 @@ class MeshDesc(C.Structure):
                 ("r_cut_wall", C.c_double)]
 
 
+class BatchConfig(C.Structure):
+    _fields_ = [("lb_block_x", C.c_int32), ("spread_blocks_per_cu", C.c_int32),
+                ("vertices_per_wave", C.c_int32), ("reserved", C.c_int32), ("lb_share_forces", C.c_double)]
+
+
 class IBLBError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"iblb error {code}: {msg}")
@@ -112,6 +117,14 @@ def lib():
             "iblb_reset_timing": [_vp],
             "iblb_active_nodes": [_vp, C.POINTER(C.c_int64)],
             "iblb_destroy": [_vp],
+            "iblb_batch_create": [C.POINTER(_vp), C.c_int32, _vp, pp],
+            "iblb_batch_step": [_vp, C.c_int32],
+            "iblb_batch_sync": [_vp],
+            "iblb_batch_check": [_vp, _ip, _ip],
+            "iblb_batch_get_config": [_vp, C.POINTER(BatchConfig)],
+            "iblb_batch_set_config": [_vp, C.POINTER(BatchConfig)],
+            "iblb_batch_tune": [_vp, C.c_int32, _dp],
+            "iblb_batch_destroy": [_vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -119,6 +132,10 @@ def lib():
             fn.restype = C.c_int
         L.iblb_last_error.argtypes = [_vp]
         L.iblb_last_error.restype = C.c_char_p
+        L.iblb_batch_last_error.argtypes = [_vp]
+        L.iblb_batch_last_error.restype = C.c_char_p
+        L.iblb_batch_member_error.argtypes = [_vp, C.c_int32]
+        L.iblb_batch_member_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -333,6 +350,100 @@ class Simulation:
             lib().iblb_destroy(self.h)
             self.h = None
         self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Batch:
+    """Several Simulations advanced together by one launch of each step
+    kernel per step (iblb_batch_*).  The members keep answering their own
+    queries; they must stay open while the batch exists.
+
+    use_torch: the batch's launches go to a torch.cuda.Stream at default
+    priority; otherwise the library creates the stream.
+    """
+
+    def __init__(self, sims, use_torch: bool = True):
+        L = lib()
+        self.sims = list(sims)
+        n = len(self.sims)
+        arr = (_vp * n)(*[s.h for s in self.sims])
+        self._stream = None
+        stream = None
+        if use_torch:
+            import torch
+            self._stream = torch.cuda.Stream()
+            stream = self._stream.cuda_stream
+        h = _vp()
+        rc = L.iblb_batch_create(arr, n, stream, C.byref(h))
+        if rc != IBLB_OK:
+            raise IBLBError(rc, "iblb_batch_create failed")
+        self.h = h
+
+    def _check(self, rc: int):
+        if rc != IBLB_OK:
+            msg = lib().iblb_batch_last_error(self.h)
+            raise IBLBError(rc, msg.decode() if msg else "")
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def step(self, n: int = 1):
+        self._check(lib().iblb_batch_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(lib().iblb_batch_sync(self.h))
+
+    def check(self):
+        """Per-member status after freezing the members whose device error
+        bits are set: IBLB_OK or IBLB_E_UNSTABLE."""
+        st = (C.c_int32 * len(self.sims))()
+        nf = C.c_int32()
+        self._check(lib().iblb_batch_check(self.h, st, C.byref(nf)))
+        return list(st)
+
+    def member_error(self, k: int) -> str:
+        return lib().iblb_batch_member_error(self.h, int(k)).decode()
+
+    @property
+    def config(self) -> dict:
+        c = BatchConfig()
+        self._check(lib().iblb_batch_get_config(self.h, C.byref(c)))
+        return {"lb_block_x": c.lb_block_x, "spread_blocks_per_cu": c.spread_blocks_per_cu,
+                "vertices_per_wave": c.vertices_per_wave, "lb_share_forces": c.lb_share_forces}
+
+    def set_config(self, **kw):
+        cur = self.config
+        cur.update(kw)
+        c = BatchConfig()
+        c.lb_block_x = int(cur["lb_block_x"])
+        c.spread_blocks_per_cu = int(cur["spread_blocks_per_cu"])
+        c.vertices_per_wave = int(cur["vertices_per_wave"])
+        c.reserved = 0
+        c.lb_share_forces = float(cur["lb_share_forces"])
+        self._check(lib().iblb_batch_set_config(self.h, C.byref(c)))
+
+    def tune(self, trial_steps: int = 64) -> float:
+        """Autotune the launch shape; returns the best time per step (ms)."""
+        ms = C.c_double()
+        self._check(lib().iblb_batch_tune(self.h, int(trial_steps), C.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().iblb_batch_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

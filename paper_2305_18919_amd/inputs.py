@@ -246,3 +246,35 @@ def c3_wetting(eps_over_abar: float = 1.0) -> Workload:
                        eps_lo=eps_over_abar * abar)
     return Workload("wetting128_f32", Domain(128, 128, 96), mesh, 1000, "f32",
                     {"eps_over_abar": eps_over_abar})
+
+
+# Batched parameter sweep: cubic edges, and the three pre-stressed particle
+# models of Table 1 (pure droplet, softly and rigidly coated droplet).
+BATCH_EDGES = (32, 48, 64, 80)
+BATCH_MODELS = ((1.0, 0.0, 0.0), (1.0, 0.0, 1.0), (1.0, 1.0, 1.0))
+
+
+def batch_sweep(n: int = 48, seed: int = SEED + 5) -> list[Workload]:
+    """n independent wetting domains of a parameter sweep, FP32 populations.
+
+    Per domain, drawn from splitmix64 in this order: the cubic edge uniform
+    over {32, 48, 64, 80} (walls at z = 0 and edge-1), the radius R uniform in
+    [6, 14], the particle model uniform over the three pre-stressed models of
+    Table 1, and abar log-uniform in [1e-3, 1e-1].  The droplet is an
+    icosphere of level 3 below R = 10 and level 4 from there on, centred in x
+    and y and lifted R + 2^(1/6) xi above the lower wall plane, with a wetting
+    lower wall of eps = abar.
+    """
+    rng = SplitMix64(seed)
+    out = []
+    for k in range(n):
+        edge = BATCH_EDGES[min(3, int(rng.uniform() * 4))]
+        R = 6.0 + 8.0 * rng.uniform()
+        model = BATCH_MODELS[min(2, int(rng.uniform() * 3))]
+        abar = 10.0 ** (-3.0 + 2.0 * rng.uniform())
+        level = 3 if R < 10.0 else 4
+        centre = (edge / 2.0 - 0.5, edge / 2.0 - 0.5, 0.5 + R + LJ_R0)
+        mesh = sphere_mesh(level, R, centre, tuple(abar * a for a in model), eps_lo=abar)
+        out.append(Workload(f"sweep{k:02d}_e{edge}", Domain(edge, edge, edge), mesh, 5000, "f32",
+                            {"edge": edge, "R": R, "model": model, "abar": abar, "level": level}))
+    return out

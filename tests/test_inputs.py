@@ -37,3 +37,24 @@ def test_workloads():
     assert (w2.mesh.n_vertices, w2.mesh.n_faces, w2.domain.n_fluid) == (2562, 5120, 64 * 64 * 62)
     assert (w3.mesh.n_vertices, w3.mesh.n_faces, w3.domain.n_fluid) == (10242, 20480, 128 * 128 * 94)
     assert w2.notes["abar"] == pytest.approx(1.0753e-2, rel=1e-3)
+
+
+def test_batch_sweep_recipe():
+    from paper_2305_18919_amd.inputs import BATCH_EDGES, BATCH_MODELS, LJ_R0, batch_sweep
+    ws, again = batch_sweep(), batch_sweep()
+    assert len(ws) == 48
+    for w, v in zip(ws, again):
+        assert np.array_equal(w.mesh.vertices, v.mesh.vertices) and w.notes == v.notes
+        e, R, abar = w.notes["edge"], w.notes["R"], w.notes["abar"]
+        assert e in BATCH_EDGES and (w.domain.nx, w.domain.ny, w.domain.nz) == (e, e, e)
+        assert 6.0 <= R < 14.0 and 1e-3 <= abar < 1e-1
+        assert w.notes["model"] in BATCH_MODELS
+        assert w.mesh.alpha == tuple(abar * a for a in w.notes["model"])
+        assert w.mesh.n_vertices == (642 if R < 10.0 else 2562)
+        assert w.mesh.eps_wall_lo == abar
+        # the droplet fits between the walls, its lowest point at the LJ zero-force distance
+        z = w.mesh.vertices[:, 2]
+        assert z.min() == pytest.approx(0.5 + LJ_R0) and z.max() < w.domain.z_hi
+    # every edge and every model is drawn
+    assert {w.notes["edge"] for w in ws} == set(BATCH_EDGES)
+    assert {w.notes["model"] for w in ws} == set(BATCH_MODELS)
