@@ -27,7 +27,9 @@ workload.
 contact-angle comparison of the population storage precisions instead,
 --study shear the capillary-number sweep of the sheared particles, and
 --study batch the 48-domain parameter sweep stepped as one batch against the
-same domains stepped one at a time.
+same domains stepped one at a time, and --study adjoint the gradient of the
+wetting observables by the adjoint, its cost relative to the forward run and
+its error against finite differences.
 """
 from __future__ import annotations
 
@@ -252,7 +254,7 @@ def batch_study(steps: int, warmup: int):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.step(steps)
-        b.sync()
+        torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         after = b.check()
     ms = dt * 1e3 / steps
@@ -266,20 +268,93 @@ def batch_study(steps: int, warmup: int):
     out["step_roofline"] = {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                             "alg_bytes_per_step": alg}
-    # the same domains stepped one context at a time (each replaying its own graphs)
+    # the same domains stepped one context at a time (each replaying its own
+    # graphs); a member that turns unstable still costs its launches in both
+    # legs, so the device is synchronised without reading its error word
     seq = 0.0
     for k in live:
         s = sims[k]
         s.step(32)
-        s.sync()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.step(steps)
-        s.sync()
+        torch.cuda.synchronize()
         seq += time.perf_counter() - t0
     out["one_at_a_time"] = {"ms_per_step": round(seq * 1e3 / steps, 5), "mlups": round(nodes * steps / seq / 1e6, 1)}
     out["speedup"] = round(seq / dt, 2)
     for s in sims:
         s.close()
+    print(json.dumps(out), flush=True)
+
+
+def adjoint_study(every: int):
+    """The differentiation workload (64x64x48, pure droplet R = 12, level 4,
+    abar = 1e-3, eps/abar = 1, 2000 steps, FP32 populations): gradients of
+    the final height h and signed squared contact radius r2 of the fit with
+    respect to (abar, k_V, eps, tau) by the hand-written adjoint, timed against
+    the forward run alone, and checked against central differences of the
+    FP64 path (relative steps 1e-4 for abar and k_V, 1e-5 for eps and tau: the
+    plainly cut-off wall force makes the observables only piecewise smooth,
+    and wider steps in the parameters the contact region is most sensitive to
+    straddle its switching)."""
+    import torch
+    from paper_2305_18919_amd import iblb
+    from paper_2305_18919_amd import inputs as I
+    w = I.differentiation_case()
+    model = w.notes["model"]
+    base = dict(abar=w.notes["abar"], kv=w.notes["kv"], eps=w.notes["eps"], tau=w.notes["tau"])
+    out = {"study": "adjoint", "workload": w.name, "steps": w.steps, "checkpoint_every": every,
+           "fluid_nodes": w.domain.n_fluid, "vertices": w.mesh.n_vertices}
+    # forward alone (graph-replayed steps)
+    with iblb.Simulation(w.domain, w.mesh, precision=1, graph=True) as s:
+        s.step(64)  # warm-up: code objects loaded, graph path exercised
+        torch.cuda.synchronize()
+    with iblb.Simulation(w.domain, w.mesh, precision=1, graph=True) as s:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(w.steps)
+        s.sync()
+        t_fwd = time.perf_counter() - t0
+    # recorded forward, then the reverse sweep (both observables from one sweep each)
+    with iblb.Simulation(w.domain, w.mesh, precision=1, graph=True) as s:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.adjoint_record(w.steps, every)
+        s.sync()
+        t_rec = time.perf_counter() - t0
+        h, r2, dh, dr2 = iblb.sphere_fit_grad(s.vertices(), 0, w.domain.z_lo, w.mesh.r_cut_wall)
+        t0 = time.perf_counter()
+        gh, _ = s.adjoint_backward(dh)
+        t_bwd = time.perf_counter() - t0
+        gr, _ = s.adjoint_backward(dr2)
+    ad = {"h": [sum(m * gh[k] for k, m in enumerate(model)), gh[3], gh[4], gh[5]],
+          "r2": [sum(m * gr[k] for k, m in enumerate(model)), gr[3], gr[4], gr[5]]}
+
+    def observe(pp):
+        wc = I.differentiation_case(pp["abar"], pp["kv"], pp["eps"] / pp["abar"], pp["tau"])
+        with iblb.Simulation(wc.domain, wc.mesh, precision=0, graph=True) as sm:
+            sm.step(wc.steps)
+            hh, rr, _, _ = iblb.sphere_fit_grad(sm.vertices(), 0, wc.domain.z_lo, wc.mesh.r_cut_wall)
+        return hh, rr
+
+    fd = {"h": [], "r2": []}
+    for name in ("abar", "kv", "eps", "tau"):
+        hstep = base[name] * (1e-5 if name in ("eps", "tau") else 1e-4)
+        pp, pm = dict(base), dict(base)
+        pp[name] += hstep
+        pm[name] -= hstep
+        a, b = observe(pp), observe(pm)
+        fd["h"].append((a[0] - b[0]) / (2 * hstep))
+        fd["r2"].append((a[1] - b[1]) / (2 * hstep))
+    rel = {k: [abs(ad[k][j] - fd[k][j]) / abs(fd[k][j]) for j in range(4)] for k in ad}
+    out.update({
+        "h": h, "r2": r2, "params": ["abar", "k_V", "eps", "tau"],
+        "adjoint": ad, "finite_difference_fp64": fd, "rel_error": rel,
+        "max_rel_error": max(max(v) for v in rel.values()),
+        "forward_s": round(t_fwd, 4), "record_s": round(t_rec, 4), "backward_s": round(t_bwd, 4),
+        "adjoint_over_forward": round((t_rec + t_bwd) / t_fwd, 3),
+        "backward_over_forward": round(t_bwd / t_fwd, 3),
+    })
     print(json.dumps(out), flush=True)
 
 
@@ -310,7 +385,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pass", dest="only", choices=["lb", "copy"], default=None)
     ap.add_argument("--copy-mib", type=int, default=256)
-    ap.add_argument("--study", choices=["precision", "shear", "batch"], default=None,
+    ap.add_argument("--study", choices=["precision", "shear", "batch", "adjoint"], default=None,
                     help="precision: contact angle of the wetting droplet per population storage; "
                          "shear: steady D and Theta against the small-Ca theory")
     ap.add_argument("--study-steps", type=int, default=50000)
@@ -333,6 +408,9 @@ def main():
         return
     if args.study == "batch":
         batch_study(args.study_steps, args.warmup)
+        return
+    if args.study == "adjoint":
+        adjoint_study(100)
         return
     w, prec = workload(args.workload)
     if args.precision is not None:

@@ -1,0 +1,658 @@
+// Discrete adjoint of one IB-LB step (reverse mode), FP64.
+//
+// The forward step maps (f(t), q(t)) to (f(t+1), q(t+1)):
+//   phi = Phi(q)                              nodal forces (Eqs. generalised_energy1,
+//                                             nodal_force_S, nodal_force_V, LJ_interaction)
+//   F   = sum_i phi_i delta(x - q_i)          spreading (Eq. ibm-governing_eq2)
+//   f*  = f - (f - f^eq(rho, u)) / tau + S(u, F),  rho u = sum c f + F/2   (Eqs. LBeq, feq)
+//   f(t+1) = propagation of f*, half-way bounce-back with the moving-wall term
+//   u'  = (sum c f(t+1) + F/2) / rho(t+1)
+//   q(t+1) = q + sum_x u'(x) delta(x - q)     interpolation (Eq. ibm-governing_eq1)
+// Given the adjoints lam(t+1) of f(t+1) and qb(t+1) of q(t+1), the kernels
+// below produce lam(t), qb(t) and add this step's share of the parameter
+// derivatives, in the reverse order of the forward operations:
+//   ka_spread (qb -> ub)       ub(x) = sum_i delta(x - q_i) qb_i, the adjoint of u'
+//   ka_moments_adj             lam(t+1) += d u'/d f(t+1)^T ub,  Fb += ub / (2 rho')
+//   ka_interp_adj              qb(t) = qb(t+1) + sum_x (u'(x) . qb) grad_q delta
+//   ka_lb_adj                  lam(t) from lam(t+1): propagation reversed (a pull),
+//                              then the transposed Jacobian of the collision;
+//                              Fb += d f*/d F^T Lam, tau derivative
+//   ka_interp_force            phib_i = sum_x Fb delta, qb += sum_x (Fb . phi_i) grad_q delta
+//   ka_volume (direction phib) Vdot = grad V . phib
+//   ka_force_jvp               qb += (d Phi / d q)^T phib and the alpha, k_V, eps derivatives.
+// Every nodal force is minus the gradient of an energy (W_S, k_V (V - V0)^2 /
+// (2 V0) and the LJ potential of each face centroid), so d Phi / d q is
+// symmetric and its transpose product is the directional derivative of Phi
+// along phib, computed with dual numbers.  The forward quantities (phi, F,
+// rho, u, u') are recomputed in FP64 from the stored populations and
+// positions of each time level.
+#include "iblb_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace iblb {
+namespace {
+
+constexpr int kCx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int kCy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int kCz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+__device__ __forceinline__ double wq(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+__device__ __forceinline__ int oppq(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+__device__ __forceinline__ int wrapn(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------- dual numbers
+struct Dual {
+    double v, d;
+};
+__device__ __forceinline__ Dual mk(double v, double d = 0.0) { return Dual{v, d}; }
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual{a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual{a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a) { return Dual{-a.v, -a.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual{a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dual operator*(double s, Dual a) { return Dual{s * a.v, s * a.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, double s) { return Dual{s * a.v, s * a.d}; }
+__device__ __forceinline__ Dual operator+(Dual a, double s) { return Dual{a.v + s, a.d}; }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) { return Dual{a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
+__device__ __forceinline__ Dual operator/(Dual a, double s) { return Dual{a.v / s, a.d / s}; }
+__device__ __forceinline__ Dual operator/(double s, Dual b) { return Dual{s / b.v, -s * b.d / (b.v * b.v)}; }
+__device__ __forceinline__ Dual dlog(Dual a) { return Dual{log(a.v), a.d / a.v}; }
+__device__ __forceinline__ double dlog(double a) { return log(a); }
+__device__ __forceinline__ double val(double a) { return a; }
+__device__ __forceinline__ double val(Dual a) { return a.v; }
+
+// ---------------------------------------------------------------- face mechanics
+// Corner `corner` of a face (a, b, c): the two parts of the elastic force,
+// F = w1 FG + w2 Fadj with w1 = alpha3/2 and w2 = dw_S/dI2, where FG comes
+// from the G^-1 term and Fadj from the adj(g)/det G term of
+// S = A0 [w1 G^-1 + w2 adj(g)/det G] (Fb = -2 (S11 e1 + S12 e2),
+// Fc = -2 (S12 e1 + S22 e2), Fa = -Fb - Fc), and J = det g / det G.
+template <typename T>
+struct FaceParts {
+    T FG[3], Fadj[3];
+    T J, lnJ;
+};
+
+template <typename T>
+__device__ __forceinline__ FaceParts<T> face_parts(const T *a, const T *b, const T *c, const double *fr, int corner)
+{
+    // fr: Ginv11, Ginv12, Ginv22, A0, 1/det G
+    T e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = b[k] - a[k];
+        e2[k] = c[k] - a[k];
+    }
+    const T g11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+    const T g12 = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+    const T g22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+    const T detg = g11 * g22 - g12 * g12;
+    FaceParts<T> p;
+    p.J = detg * fr[4];
+    p.lnJ = dlog(p.J);
+    const double A0 = fr[3];
+    // G^-1 part: S = A0 G^-1 (constant); adj part: S = A0 adj(g) / det G
+    const double G11 = A0 * fr[0], G12 = A0 * fr[1], G22 = A0 * fr[2];
+    const T H11 = g22 * (A0 * fr[4]), H12 = -(g12 * (A0 * fr[4])), H22 = g11 * (A0 * fr[4]);
+    T fbG[3], fcG[3], fbH[3], fcH[3];
+    for (int k = 0; k < 3; ++k) {
+        fbG[k] = -2.0 * (G11 * e1[k] + G12 * e2[k]);
+        fcG[k] = -2.0 * (G12 * e1[k] + G22 * e2[k]);
+        fbH[k] = -2.0 * (H11 * e1[k] + H12 * e2[k]);
+        fcH[k] = -2.0 * (H12 * e1[k] + H22 * e2[k]);
+    }
+    for (int k = 0; k < 3; ++k) {
+        if (corner == 0) {
+            p.FG[k] = -(fbG[k] + fcG[k]);
+            p.Fadj[k] = -(fbH[k] + fcH[k]);
+        } else if (corner == 1) {
+            p.FG[k] = fbG[k];
+            p.Fadj[k] = fbH[k];
+        } else {
+            p.FG[k] = fcG[k];
+            p.Fadj[k] = fcH[k];
+        }
+    }
+    return p;
+}
+
+// dV/d(corner) of the tetrahedron (o, a, b, c): (b-o)x(c-o)/6 for a, and cyclically
+template <typename T>
+__device__ __forceinline__ void volume_corner(const T *a, const T *b, const T *c, const double *o, int corner, T *g)
+{
+    const T *u = corner == 0 ? b : (corner == 1 ? c : a);
+    const T *w = corner == 0 ? c : (corner == 1 ? a : b);
+    T U[3], Wv[3];
+    for (int k = 0; k < 3; ++k) {
+        U[k] = u[k] + (-o[k]);
+        Wv[k] = w[k] + (-o[k]);
+    }
+    g[0] = (U[1] * Wv[2] - U[2] * Wv[1]) / 6.0;
+    g[1] = (U[2] * Wv[0] - U[0] * Wv[2]) / 6.0;
+    g[2] = (U[0] * Wv[1] - U[1] * Wv[0]) / 6.0;
+}
+
+// LJ force magnitude per unit eps along the wall normal at distance d
+// (Eq. LJ_interaction): 48 [(xi/d)^12 - (xi/d)^6 / 2] / d, 0 from rc on, d >= xi/2
+template <typename T>
+__device__ __forceinline__ T lj_unit(double xi, double rc, T d)
+{
+    if (!(val(d) < rc)) return T{} * 0.0;
+    T dd = d;
+    if (val(d) < 0.5 * xi) dd = T{} * 0.0 + 0.5 * xi;
+    const T r = xi / dd;
+    const T r2 = r * r;
+    const T r6 = r2 * r2 * r2;
+    return 48.0 * (r6 * r6 - 0.5 * r6) / dd;
+}
+
+__device__ __forceinline__ double lj_unit(double xi, double rc, double d)
+{
+    if (!(d < rc)) return 0.0;
+    const double dd = d < 0.5 * xi ? 0.5 * xi : d;
+    const double r = xi / dd, r2 = r * r, r6 = r2 * r2 * r2;
+    return 48.0 * (r6 * r6 - 0.5 * r6) / dd;
+}
+
+__device__ __forceinline__ Dual lj_unit(double xi, double rc, Dual d)
+{
+    if (!(d.v < rc)) return mk(0.0);
+    const Dual dd = d.v < 0.5 * xi ? mk(0.5 * xi) : d;
+    const Dual r = xi / dd;
+    const Dual r2 = r * r;
+    const Dual r6 = r2 * r2 * r2;
+    return 48.0 * (r6 * r6 - 0.5 * r6) / dd;
+}
+
+// ---------------------------------------------------------------- 4-point stencil
+__device__ __forceinline__ double phi4d(double r)
+{
+    const double a = fabs(r);
+    if (a <= 1.0) return 0.125 * (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a));
+    if (a <= 2.0) return 0.125 * (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a));
+    return 0.0;
+}
+
+// d phi4 / d r
+__device__ __forceinline__ double dphi4d(double r)
+{
+    const double a = fabs(r), s = r < 0.0 ? -1.0 : 1.0;
+    if (a <= 1.0) return s * 0.125 * (-2.0 + (2.0 - 4.0 * a) / sqrt(1.0 + 4.0 * a - 4.0 * a * a));
+    if (a <= 2.0) return s * 0.125 * (-2.0 - (6.0 - 4.0 * a) / sqrt(-7.0 + 12.0 * a - 4.0 * a * a));
+    return 0.0;
+}
+
+__device__ __forceinline__ bool finite_pos(double x, double y, double z)
+{
+    return fabs(x) < 1e6 && fabs(y) < 1e6 && fabs(z) < 1e6;
+}
+
+// Stencil node k (0..63, x fastest) of a vertex at (qx, qy, qz): its fluid
+// index (or -1 outside the fluid, then side = 0 below / 1 above), weight and
+// weight gradient with respect to the vertex position.
+struct Node {
+    long long id;
+    int side;
+    double w, gw[3];
+};
+
+__device__ __forceinline__ Node stencil_node(const AdjArgs &A, double qx, double qy, double qz, int k)
+{
+    const Grid &g = A.g;
+    const int bx = (int)floor(qx) - 1, by = (int)floor(qy) - 1, bz = (int)floor(qz) - 1;
+    const int nxk = bx + (k & 3), nyk = by + ((k >> 2) & 3), nzk = bz + (k >> 4);
+    const double rx = nxk - qx, ry = nyk - qy, rz = nzk - qz;
+    const double px = phi4d(rx), py = phi4d(ry), pz = phi4d(rz);
+    Node nd;
+    nd.w = px * py * pz;
+    // d/dq of phi4(node - q) = -phi4'(node - q)
+    nd.gw[0] = -dphi4d(rx) * py * pz;
+    nd.gw[1] = -px * dphi4d(ry) * pz;
+    nd.gw[2] = -px * py * dphi4d(rz);
+    nd.side = 0;
+    int zf;
+    if (g.walls) {
+        if (nzk < 1 || nzk > g.nz - 2) {
+            nd.id = -1;
+            nd.side = nzk < 1 ? 0 : 1;
+            return nd;
+        }
+        zf = nzk - 1;
+    } else {
+        zf = wrapn(nzk, g.nz);
+    }
+    nd.id = ((long long)zf * g.ny + wrapn(nyk, g.ny)) * g.nx + wrapn(nxk, g.nx);
+    return nd;
+}
+
+// u(t+1) = (sum c f + (F + body)/2) / rho at a fluid node, from canonical deviations
+__device__ __forceinline__ void velocity(const AdjArgs &A, const double *__restrict__ f, const double *__restrict__ F,
+                                         long long id, double *u, double *rho)
+{
+    const long long n = A.g.n;
+    double dr = 0.0, m[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const double d = f[i * n + id];
+        dr += d;
+        m[0] += kCx[i] * d;
+        m[1] += kCy[i] * d;
+        m[2] += kCz[i] * d;
+    }
+    *rho = A.rho0 + dr;
+    for (int k = 0; k < 3; ++k) u[k] = (m[k] + 0.5 * (F[k * n + id] + A.body[k])) / *rho;
+}
+
+__device__ __forceinline__ double wave_sum64(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int K>
+__device__ __forceinline__ void block_atomic_add(double (&v)[K], double *out)
+{
+    __shared__ double red[K][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double s = wave_sum64(v[k]);
+        if (lane == 0) red[k][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int k = threadIdx.x;
+        atomicAdd(out + k, red[k][0] + red[k][1] + red[k][2] + red[k][3]);
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+// acc[0] += sum_j (V_j - V0_j) (displacement expansion of the triple
+// product, as the forward computes it), acc[1] += sum_j grad V_j . dir
+__global__ __launch_bounds__(256) void ka_volume(AdjArgs A, const double *__restrict__ q, const double *__restrict__ X,
+                                                 const int *__restrict__ faces, const double *__restrict__ dir,
+                                                 double *acc)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (j < A.nf) {
+        const int nv = A.nv;
+        const int ia = faces[j], ib = faces[A.nf + j], ic = faces[2 * A.nf + j];
+        double Ar[3], Br[3], Cr[3], da[3], db[3], dc[3], a[3], b[3], c[3];
+        for (int k = 0; k < 3; ++k) {
+            Ar[k] = X[k * nv + ia] - A.origin[k];
+            Br[k] = X[k * nv + ib] - A.origin[k];
+            Cr[k] = X[k * nv + ic] - A.origin[k];
+            a[k] = q[k * nv + ia];
+            b[k] = q[k * nv + ib];
+            c[k] = q[k * nv + ic];
+            da[k] = a[k] - X[k * nv + ia];
+            db[k] = b[k] - X[k * nv + ib];
+            dc[k] = c[k] - X[k * nv + ic];
+        }
+        auto T3 = [](const double *x, const double *y, const double *z) {
+            return x[0] * (y[1] * z[2] - y[2] * z[1]) + x[1] * (y[2] * z[0] - y[0] * z[2]) +
+                   x[2] * (y[0] * z[1] - y[1] * z[0]);
+        };
+        v[0] = (T3(da, Br, Cr) + T3(Ar, db, Cr) + T3(Ar, Br, dc) + T3(da, db, Cr) + T3(da, Br, dc) + T3(Ar, db, dc) +
+                T3(da, db, dc)) / 6.0;
+        if (dir) {
+            const int idx[3] = {ia, ib, ic};
+            for (int corner = 0; corner < 3; ++corner) {
+                double gc[3];
+                volume_corner<double>(a, b, c, A.origin, corner, gc);
+                for (int k = 0; k < 3; ++k) v[1] += gc[k] * dir[k * nv + idx[corner]];
+            }
+        }
+    }
+    block_atomic_add<2>(v, acc);
+}
+
+// Nodal forces phi = phi^S + phi^V + phi^W and grad V per vertex, gathered
+// over the vertex's incident faces; acc[0] = V - V0.
+__global__ __launch_bounds__(256) void ka_vertex_forces(AdjArgs A, const double *__restrict__ q,
+                                                        const int4 *__restrict__ inc4, const double *__restrict__ fref,
+                                                        const double *__restrict__ acc, double *__restrict__ phi,
+                                                        double *__restrict__ gV)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= A.nv) return;
+    const int nv = A.nv, nf = A.nf;
+    const double dV = acc[0];
+    double fs[3] = {0, 0, 0}, gv[3] = {0, 0, 0}, fw = 0.0;
+    for (int s = 0; s < A.slots; ++s) {
+        const int4 e = inc4[(long long)v * A.slots + s];
+        if (e.w < 0) continue;
+        const int j = e.w >> 2, corner = e.w & 3;
+        double a[3], b[3], c[3], fr[5];
+        for (int k = 0; k < 3; ++k) {
+            a[k] = q[k * nv + e.x];
+            b[k] = q[k * nv + e.y];
+            c[k] = q[k * nv + e.z];
+        }
+        for (int k = 0; k < 5; ++k) fr[k] = fref[k * nf + j];
+        const FaceParts<double> p = face_parts<double>(a, b, c, fr, corner);
+        const double w1 = 0.5 * A.alpha[2];
+        const double w2 = (0.5 * (A.alpha[0] - A.alpha[2]) + 0.25 * (A.alpha[0] + A.alpha[1]) * p.lnJ) / p.J;
+        double gc[3];
+        volume_corner<double>(a, b, c, A.origin, corner, gc);
+        for (int k = 0; k < 3; ++k) {
+            fs[k] += w1 * p.FG[k] + w2 * p.Fadj[k];
+            gv[k] += gc[k];
+        }
+        if (A.g.walls) {
+            const double cz = (a[2] + b[2] + c[2]) / 3.0;
+            fw += (A.eps_lo * lj_unit(A.xi, A.rc, cz - A.z_lo) - A.eps_hi * lj_unit(A.xi, A.rc, A.z_hi - cz)) / 3.0;
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        phi[k * nv + v] = fs[k] - A.kv_over_V0 * dV * gv[k] + (k == 2 ? fw : 0.0);
+        gV[k * nv + v] = gv[k];
+    }
+}
+
+// out(x) += sum_i delta(x - q_i) val_i over the fluid nodes (one thread per
+// vertex and stencil node)
+__global__ __launch_bounds__(256) void ka_spread(AdjArgs A, const double *__restrict__ q, const double *__restrict__ val,
+                                                 double *out)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(t >> 6), k = (int)(t & 63);
+    if (v >= A.nv) return;
+    const int nv = A.nv;
+    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+    if (!finite_pos(qx, qy, qz)) return;
+    const Node nd = stencil_node(A, qx, qy, qz, k);
+    if (nd.id < 0 || nd.w == 0.0) return;
+    const long long n = A.g.n;
+    for (int c = 0; c < 3; ++c) atomicAdd(out + c * n + nd.id, val[c * nv + v] * nd.w);
+}
+
+// Adjoint of u' = (sum c f1 + (F + body)/2) / rho1 at every fluid node with ub != 0:
+// lam_j += (c_j - u') . ub / rho1,  Fb += ub / (2 rho1)
+__global__ __launch_bounds__(256) void ka_moments_adj(AdjArgs A, const double *__restrict__ f1,
+                                                      const double *__restrict__ F, const double *__restrict__ ub,
+                                                      double *__restrict__ lam, double *__restrict__ Fb)
+{
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = A.g.n;
+    if (id >= n) return;
+    const double b[3] = {ub[id], ub[n + id], ub[2 * n + id]};
+    if (b[0] == 0.0 && b[1] == 0.0 && b[2] == 0.0) return;
+    double u[3], rho;
+    velocity(A, f1, F, id, u, &rho);
+    const double ub_u = b[0] * u[0] + b[1] * u[1] + b[2] * u[2];
+#pragma unroll
+    for (int j = 0; j < 19; ++j)
+        lam[j * n + id] += (kCx[j] * b[0] + kCy[j] * b[1] + kCz[j] * b[2] - ub_u) / rho;
+    for (int k = 0; k < 3; ++k) Fb[k * n + id] += b[k] / (2.0 * rho);
+}
+
+// qb0_i = qb1_i + sum_x (u'(x) . qb1_i) grad_q delta(x - q_i), u' at the
+// fluid nodes from (f1, F), the wall velocity elsewhere (one wavefront per
+// vertex, one lane per stencil node)
+__global__ __launch_bounds__(256) void ka_interp_adj(AdjArgs A, const double *__restrict__ q,
+                                                     const double *__restrict__ qb1, const double *__restrict__ f1,
+                                                     const double *__restrict__ F, double *__restrict__ qb0)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(t >> 6), k = (int)(t & 63);
+    if (v >= A.nv) return;
+    const int nv = A.nv;
+    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+    const double b[3] = {qb1[v], qb1[nv + v], qb1[2 * nv + v]};
+    double s[3] = {0.0, 0.0, 0.0};
+    if (finite_pos(qx, qy, qz)) {
+        const Node nd = stencil_node(A, qx, qy, qz, k);
+        double u[3];
+        if (nd.id >= 0) {
+            double rho;
+            velocity(A, f1, F, nd.id, u, &rho);
+        } else {
+            for (int c = 0; c < 3; ++c) u[c] = nd.side ? A.uhi[c] : A.ulo[c];
+        }
+        const double ubq = u[0] * b[0] + u[1] * b[1] + u[2] * b[2];
+        for (int c = 0; c < 3; ++c) s[c] = ubq * nd.gw[c];
+    }
+    for (int c = 0; c < 3; ++c) s[c] = wave_sum64(s[c]);
+    if (k == 0)
+        for (int c = 0; c < 3; ++c) qb0[c * nv + v] = b[c] + s[c];
+}
+
+// Collision and propagation reversed at node x: Lam_i = lam1_i(x + c_i), or
+// lam1_opp(i)(x) for a link that bounces back at a wall (whose moving-wall
+// term -6 w_i rho (c_i . u_w) adds to the density adjoint); then
+//   lam0_j = (1 - 1/tau) Lam_j + a + b . (c_j - u) / rho,
+//   a = sum_i Lam_i d f*_i / d rho |u,   b = sum_i Lam_i d f*_i / d u,
+//   Fb += sum_i Lam_i d S_i / d F + b / (2 rho),
+//   d/dtau: sum_i Lam_i [(f_i - f^eq_i) + s_i / 2] / tau^2  with S_i = (1 - 1/(2 tau)) s_i.
+__global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const double *__restrict__ f0, const double *__restrict__ F,
+                                                 const double *__restrict__ lam1, double *__restrict__ lam0,
+                                                 double *__restrict__ Fb, double *grads)
+{
+    const Grid &g = A.g;
+    const long long n = g.n;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double tb[1] = {0.0};
+    if (id < n) {
+        const int x = (int)(id % g.nx), y = (int)((id / g.nx) % g.ny), zf = (int)(id / ((long long)g.nx * g.ny));
+        double d[19], dr = 0.0, m[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            d[i] = f0[i * n + id];
+            dr += d[i];
+            m[0] += kCx[i] * d[i];
+            m[1] += kCy[i] * d[i];
+            m[2] += kCz[i] * d[i];
+        }
+        const double rho = A.rho0 + dr;
+        const double Fx = F[id] + A.body[0], Fy = F[n + id] + A.body[1], Fz = F[2 * n + id] + A.body[2];
+        const double u[3] = {(m[0] + 0.5 * Fx) / rho, (m[1] + 0.5 * Fy) / rho, (m[2] + 0.5 * Fz) / rho};
+        const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const double uF = u[0] * Fx + u[1] * Fy + u[2] * Fz;
+        const double om = A.omega, guo = 1.0 - 0.5 * om;
+        double a = 0.0, b[3] = {0.0, 0.0, 0.0}, fb[3] = {0.0, 0.0, 0.0}, Lam[19];
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const int cx = kCx[i], cy = kCy[i], cz = kCz[i];
+            const int tz = zf + (g.walls ? 1 : 0) + cz;
+            double L;
+            if (g.walls && (tz < 1 || tz > g.nz - 2)) {
+                L = lam1[oppq(i) * n + id];
+                const double *uw = tz < 1 ? A.ulo : A.uhi;
+                a += -6.0 * wq(i) * (cx * uw[0] + cy * uw[1] + cz * uw[2]) * L;
+            } else {
+                const int tzf = g.walls ? tz - 1 : wrapn(tz, g.nz);
+                const long long to = ((long long)tzf * g.ny + wrapn(y + cy, g.ny)) * g.nx + wrapn(x + cx, g.nx);
+                L = lam1[i * n + to];
+            }
+            Lam[i] = L;
+            const double w = wq(i);
+            const double cu = cx * u[0] + cy * u[1] + cz * u[2];
+            const double cF = cx * Fx + cy * Fy + cz * Fz;
+            const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+            const double deq = w * dr + w * rho * poly;
+            const double si = w * (3.0 * (cF - uF) + 9.0 * cF * cu);
+            // f*_i = d_i - om (d_i - deq_i) + guo s_i
+            a += L * om * w * (1.0 + poly);
+            const double c3[3] = {(double)cx, (double)cy, (double)cz};
+            const double Fv[3] = {Fx, Fy, Fz};
+            for (int k = 0; k < 3; ++k) {
+                b[k] += L * (om * w * rho * (3.0 * c3[k] + 9.0 * cu * c3[k] - 3.0 * u[k]) +
+                             guo * w * (-3.0 * Fv[k] + 9.0 * cF * c3[k]));
+                fb[k] += L * guo * w * (3.0 * (c3[k] - u[k]) + 9.0 * cu * c3[k]);
+            }
+            tb[0] += L * om * om * ((d[i] - deq) + 0.5 * si);
+        }
+#pragma unroll
+        for (int j = 0; j < 19; ++j)
+            lam0[j * n + id] = (1.0 - om) * Lam[j] + a +
+                               (b[0] * (kCx[j] - u[0]) + b[1] * (kCy[j] - u[1]) + b[2] * (kCz[j] - u[2])) / rho;
+        for (int k = 0; k < 3; ++k) Fb[k * n + id] += fb[k] + b[k] / (2.0 * rho);
+    }
+    block_atomic_add<1>(tb, grads + 5);
+}
+
+// phib_i = sum_x Fb(x) delta(x - q_i) and qb0_i += sum_x (Fb(x) . phi_i)
+// grad_q delta over the fluid nodes (one wavefront per vertex)
+__global__ __launch_bounds__(256) void ka_interp_force(AdjArgs A, const double *__restrict__ q,
+                                                       const double *__restrict__ phi, const double *__restrict__ Fb,
+                                                       double *__restrict__ phib, double *__restrict__ qb0)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(t >> 6), k = (int)(t & 63);
+    if (v >= A.nv) return;
+    const int nv = A.nv;
+    const long long n = A.g.n;
+    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+    const double p[3] = {phi[v], phi[nv + v], phi[2 * nv + v]};
+    double pb[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
+    if (finite_pos(qx, qy, qz)) {
+        const Node nd = stencil_node(A, qx, qy, qz, k);
+        if (nd.id >= 0) {
+            const double fb[3] = {Fb[nd.id], Fb[n + nd.id], Fb[2 * n + nd.id]};
+            const double fp = fb[0] * p[0] + fb[1] * p[1] + fb[2] * p[2];
+            for (int c = 0; c < 3; ++c) {
+                pb[c] = fb[c] * nd.w;
+                s[c] = fp * nd.gw[c];
+            }
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        pb[c] = wave_sum64(pb[c]);
+        s[c] = wave_sum64(s[c]);
+    }
+    if (k == 0)
+        for (int c = 0; c < 3; ++c) {
+            phib[c * nv + v] = pb[c];
+            qb0[c * nv + v] += s[c];
+        }
+}
+
+// qb0_i += (d Phi / d q phib)_i (the directional derivative of the nodal
+// forces along phib, with acc[0] = V - V0 and acc[1] = grad V . phib), and the
+// parameter derivatives phib . dPhi/dalpha_m (m = 1..3), phib . dPhi/dk_V,
+// phib . dPhi/deps_lo into grads[0..4].
+__global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__restrict__ q,
+                                                    const int4 *__restrict__ inc4, const double *__restrict__ fref,
+                                                    const double *__restrict__ phib, const double *__restrict__ gV,
+                                                    const double *__restrict__ acc, double *__restrict__ qb0,
+                                                    double *grads)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    double pg[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (v < A.nv) {
+        const int nv = A.nv, nf = A.nf;
+        const double dV = acc[0], Vdot = acc[1];
+        const double w1 = 0.5 * A.alpha[2];
+        const double pbv[3] = {phib[v], phib[nv + v], phib[2 * nv + v]};
+        double jv[3] = {0.0, 0.0, 0.0}, dgv[3] = {0.0, 0.0, 0.0}, dS[3][3] = {{0}}, ljz = 0.0;
+        for (int s = 0; s < A.slots; ++s) {
+            const int4 e = inc4[(long long)v * A.slots + s];
+            if (e.w < 0) continue;
+            const int j = e.w >> 2, corner = e.w & 3;
+            Dual a[3], b[3], c[3];
+            double fr[5];
+            for (int k = 0; k < 3; ++k) {
+                a[k] = mk(q[k * nv + e.x], phib[k * nv + e.x]);
+                b[k] = mk(q[k * nv + e.y], phib[k * nv + e.y]);
+                c[k] = mk(q[k * nv + e.z], phib[k * nv + e.z]);
+            }
+            for (int k = 0; k < 5; ++k) fr[k] = fref[k * nf + j];
+            const FaceParts<Dual> p = face_parts<Dual>(a, b, c, fr, corner);
+            const Dual w2 = (mk(0.5 * (A.alpha[0] - A.alpha[2])) + 0.25 * (A.alpha[0] + A.alpha[1]) * p.lnJ) / p.J;
+            // derivatives of w2 with respect to alpha_1..3 (w1 = alpha3/2)
+            const double lnJ = p.lnJ.v, J = p.J.v;
+            const double dw2[3] = {(0.5 + 0.25 * lnJ) / J, 0.25 * lnJ / J, -0.5 / J};
+            Dual gc[3];
+            volume_corner<Dual>(a, b, c, A.origin, corner, gc);
+            for (int k = 0; k < 3; ++k) {
+                jv[k] += (w1 * p.FG[k] + w2 * p.Fadj[k]).d;
+                dgv[k] += gc[k].d;
+                for (int m = 0; m < 3; ++m) dS[m][k] += dw2[m] * p.Fadj[k].v + (m == 2 ? 0.5 * p.FG[k].v : 0.0);
+            }
+            if (A.g.walls) {
+                const Dual cz = (a[2] + b[2] + c[2]) / 3.0;
+                const Dual flo = lj_unit(A.xi, A.rc, cz + (-A.z_lo));
+                const Dual fhi = lj_unit(A.xi, A.rc, (-1.0) * cz + A.z_hi);
+                jv[2] += (A.eps_lo * flo.d - A.eps_hi * fhi.d) / 3.0;
+                ljz += flo.v / 3.0;
+            }
+        }
+        for (int k = 0; k < 3; ++k) {
+            const double gvk = gV[k * nv + v];
+            jv[k] += -A.kv_over_V0 * (Vdot * gvk + dV * dgv[k]);
+            qb0[k * nv + v] += jv[k];
+            for (int m = 0; m < 3; ++m) pg[m] += pbv[k] * dS[m][k];
+            pg[3] += pbv[k] * (-dV / A.V0) * gvk;
+        }
+        pg[4] = pbv[2] * ljz;
+    }
+    block_atomic_add<5>(pg, grads);
+}
+
+int blocks_for(long long threads) { return (int)((threads + 255) / 256); }
+
+}  // namespace
+
+hipError_t adj_volume(const AdjArgs &A, const double *q, const double *X, const int *faces, const double *dir,
+                      double *acc, hipStream_t s)
+{
+    ka_volume<<<blocks_for(A.nf), 256, 0, s>>>(A, q, X, faces, dir, acc);
+    return hipGetLastError();
+}
+
+hipError_t adj_vertex_forces(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref,
+                             const double *acc, double *phi, double *gV, hipStream_t s)
+{
+    ka_vertex_forces<<<blocks_for(A.nv), 256, 0, s>>>(A, q, inc4, fref, acc, phi, gV);
+    return hipGetLastError();
+}
+
+hipError_t adj_spread(const AdjArgs &A, const double *q, const double *val, double *out, hipStream_t s)
+{
+    ka_spread<<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, val, out);
+    return hipGetLastError();
+}
+
+hipError_t adj_moments(const AdjArgs &A, const double *f1, const double *F, const double *ub, double *lam,
+                       double *Fb, hipStream_t s)
+{
+    ka_moments_adj<<<blocks_for(A.g.n), 256, 0, s>>>(A, f1, F, ub, lam, Fb);
+    return hipGetLastError();
+}
+
+hipError_t adj_interp(const AdjArgs &A, const double *q, const double *qb1, const double *f1, const double *F,
+                      double *qb0, hipStream_t s)
+{
+    ka_interp_adj<<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, qb1, f1, F, qb0);
+    return hipGetLastError();
+}
+
+hipError_t adj_lb(const AdjArgs &A, const double *f0, const double *F, const double *lam1, double *lam0,
+                  double *Fb, double *grads, hipStream_t s)
+{
+    ka_lb_adj<<<blocks_for(A.g.n), 256, 0, s>>>(A, f0, F, lam1, lam0, Fb, grads);
+    return hipGetLastError();
+}
+
+hipError_t adj_interp_force(const AdjArgs &A, const double *q, const double *phi, const double *Fb, double *phib,
+                            double *qb0, hipStream_t s)
+{
+    ka_interp_force<<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, phi, Fb, phib, qb0);
+    return hipGetLastError();
+}
+
+hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref, const double *phib,
+                         const double *gV, const double *acc, double *qb0, double *grads, hipStream_t s)
+{
+    ka_force_jvp<<<blocks_for(A.nv), 256, 0, s>>>(A, q, inc4, fref, phib, gV, acc, qb0, grads);
+    return hipGetLastError();
+}
+
+}  // namespace iblb

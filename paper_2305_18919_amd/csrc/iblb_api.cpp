@@ -139,10 +139,12 @@ struct iblb_ctx {
     long long kcount[kNumKernels] = {0, 0, 0, 0};
     void *fext_alloc = nullptr;
     void *mesh_alloc = nullptr;
+    struct AdjState *adj = nullptr;  // recorded window of the adjoint, if any
     std::string err;
 };
 
 namespace {
+void free_adjoint(iblb_ctx *c);
 
 int fail(iblb_ctx *c, int code, const std::string &msg)
 {
@@ -1049,6 +1051,7 @@ int iblb_destroy(iblb_ctx *c)
     }
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     drop_graph(c);
+    free_adjoint(c);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->mesh_alloc) (void)hipFree(c->mesh_alloc);
     if (c->fext_alloc) (void)hipFree(c->fext_alloc);
@@ -1567,6 +1570,328 @@ int iblb_batch_destroy(iblb_batch *b)
         if (e) (void)hipEventDestroy(e);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
+    return IBLB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adjoint: a recorded window of steps and its reverse sweep
+// ---------------------------------------------------------------------------
+struct AdjState {
+    long long t0 = 0;                  // time at the start of the recorded window
+    int n = 0, every = 0;              // steps recorded, steps per checkpoint
+    std::vector<char *> ck;            // device checkpoints at t0, t0 + every, ..., and t0 + n
+    size_t snap = 0;                   // bytes of one checkpoint
+    // reverse-sweep buffers (allocated by the first backward call)
+    double *store = nullptr;           // [every + 1][19][n] populations of a segment's time levels
+    double *qs = nullptr;              // [every + 1][3][nv] positions of a segment's time levels
+    double *lam[2] = {nullptr, nullptr};
+    double *qb[2] = {nullptr, nullptr};
+    double *F = nullptr, *Fb = nullptr, *ub = nullptr;
+    double *phi = nullptr, *gV = nullptr, *phib = nullptr;
+    double *acc = nullptr;             // [4]: V - V0 and grad V . dir, twice
+    double *grads = nullptr;           // [6]
+};
+
+namespace {
+
+void free_adjoint(iblb_ctx *c)
+{
+    AdjState *a = c->adj;
+    if (!a) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (char *p : a->ck) (void)hipFree(p);
+    for (double *p : {a->store, a->qs, a->lam[0], a->lam[1], a->qb[0], a->qb[1], a->F, a->Fb, a->ub, a->phi,
+                      a->gV, a->phib, a->acc, a->grads})
+        if (p) (void)hipFree(p);
+    delete a;
+    c->adj = nullptr;
+}
+
+// device copy of the whole state of a context into / out of a checkpoint
+int checkpoint(iblb_ctx *c, char *dst, bool save)
+{
+    std::vector<std::pair<char *, size_t>> regs;
+    state_regions(c, regs);
+    size_t o = 0;
+    for (auto &r : regs) {
+        if (save)
+            HIP_TRY(c, hipMemcpyAsync(dst + o, r.first, r.second, hipMemcpyDeviceToDevice, c->stream));
+        else
+            HIP_TRY(c, hipMemcpyAsync(r.first, dst + o, r.second, hipMemcpyDeviceToDevice, c->stream));
+        o += align256(r.second);
+    }
+    return IBLB_OK;
+}
+
+size_t checkpoint_bytes(const iblb_ctx *c)
+{
+    std::vector<std::pair<char *, size_t>> regs;
+    state_regions(c, regs);
+    size_t o = 0;
+    for (auto &r : regs) o += align256(r.second);
+    return o;
+}
+
+AdjArgs adj_args(const iblb_ctx *c)
+{
+    AdjArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.g = c->g;
+    A.nv = c->nv;
+    A.nf = c->nf;
+    A.slots = c->m.slots;
+    A.rho0 = c->dom.rho0;
+    A.omega = 1.0 / c->dom.tau;
+    for (int k = 0; k < 3; ++k) {
+        A.body[k] = c->dom.body_force[k];
+        A.ulo[k] = c->dom.u_wall_lo[k];
+        A.uhi[k] = c->dom.u_wall_hi[k];
+        A.alpha[k] = c->m.alpha[k];
+        A.origin[k] = c->m.origin[k];
+    }
+    A.kv_over_V0 = c->m.kv_over_V0;
+    A.V0 = c->V0;
+    A.eps_lo = c->m.eps_lo;
+    A.eps_hi = c->m.eps_hi;
+    A.xi = c->m.xi;
+    A.rc = c->m.rc;
+    A.z_lo = c->m.z_lo;
+    A.z_hi = c->m.z_hi;
+    return A;
+}
+
+// One reverse step: (lam[1], qb[1]) at t+1 -> (lam[0], qb[0]) at t, from the
+// populations f0 = f(t), f1 = f(t+1) and positions q = q(t).
+hipError_t reverse_step(iblb_ctx *c, AdjState *a, const AdjArgs &A, const double *f0, const double *f1,
+                        const double *q)
+{
+    const hipStream_t s = c->stream;
+    const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
+    const Dev &d = c->d;
+    hipError_t e;
+#define ADJ_TRY(x)                    \
+    do {                              \
+        e = (x);                      \
+        if (e != hipSuccess) return e; \
+    } while (0)
+    ADJ_TRY(hipMemsetAsync(a->acc, 0, 4 * sizeof(double), s));
+    ADJ_TRY(adj_volume(A, q, d.Xref, d.faces, nullptr, a->acc, s));
+    ADJ_TRY(adj_vertex_forces(A, q, d.inc4, d.fref, a->acc, a->phi, a->gV, s));
+    ADJ_TRY(hipMemsetAsync(a->F, 0, 3 * n * sizeof(double), s));
+    ADJ_TRY(adj_spread(A, q, a->phi, a->F, s));
+    ADJ_TRY(hipMemsetAsync(a->ub, 0, 3 * n * sizeof(double), s));
+    ADJ_TRY(adj_spread(A, q, a->qb[1], a->ub, s));
+    ADJ_TRY(hipMemsetAsync(a->Fb, 0, 3 * n * sizeof(double), s));
+    ADJ_TRY(adj_moments(A, f1, a->F, a->ub, a->lam[1], a->Fb, s));
+    ADJ_TRY(adj_interp(A, q, a->qb[1], f1, a->F, a->qb[0], s));
+    ADJ_TRY(adj_lb(A, f0, a->F, a->lam[1], a->lam[0], a->Fb, a->grads, s));
+    ADJ_TRY(adj_interp_force(A, q, a->phi, a->Fb, a->phib, a->qb[0], s));
+    ADJ_TRY(adj_volume(A, q, d.Xref, d.faces, a->phib, a->acc + 2, s));
+    ADJ_TRY(adj_force_jvp(A, q, d.inc4, d.fref, a->phib, a->gV, a->acc + 2, a->qb[0], a->grads, s));
+#undef ADJ_TRY
+    (void)nv;
+    std::swap(a->lam[0], a->lam[1]);
+    std::swap(a->qb[0], a->qb[1]);
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int iblb_adjoint_record(iblb_ctx *c, int32_t n_steps, int32_t every)
+{
+    if (!c || n_steps < 1 || every < 1) return IBLB_E_INVAL;
+    if (!c->has_mesh) return fail(c, IBLB_E_STATE, "the adjoint needs a mesh");
+    free_adjoint(c);
+    AdjState *a = new AdjState();
+    c->adj = a;
+    a->t0 = c->t;
+    a->n = n_steps;
+    a->every = every;
+    a->snap = checkpoint_bytes(c);
+    const int nseg = (n_steps + every - 1) / every;
+    for (int k = 0; k <= nseg; ++k) {
+        char *p = nullptr;
+        if (hipMalloc(&p, a->snap) != hipSuccess) {
+            free_adjoint(c);
+            return fail(c, IBLB_E_DEVICE, "no device memory for the adjoint checkpoints");
+        }
+        a->ck.push_back(p);
+    }
+    for (int sgm = 0; sgm < nseg; ++sgm) {
+        int rc = checkpoint(c, a->ck[(size_t)sgm], true);
+        if (!rc) rc = iblb_step(c, std::min(every, n_steps - sgm * every));
+        if (rc) {
+            free_adjoint(c);
+            return rc;
+        }
+    }
+    int rc = checkpoint(c, a->ck[(size_t)nseg], true);
+    if (rc) {
+        free_adjoint(c);
+        return rc;
+    }
+    return IBLB_OK;
+}
+
+int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double *dJdq0)
+{
+    if (!c || !dJdq || !grads) return IBLB_E_INVAL;
+    AdjState *a = c->adj;
+    if (!a) return fail(c, IBLB_E_STATE, "no recorded window (iblb_adjoint_record)");
+    if (c->t != a->t0 + a->n) return fail(c, IBLB_E_STATE, "the context was stepped after the recorded window");
+    int rc = sync_ctx(c);
+    if (rc) return rc;
+    const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
+    const size_t lev = (size_t)a->every + 1;
+    if (!a->store) {
+        auto get = [&](double **p, size_t count) { return hipMalloc(p, std::max<size_t>(count, 1) * 8) == hipSuccess; };
+        if (!get(&a->store, lev * 19 * n) || !get(&a->qs, lev * 3 * nv) || !get(&a->lam[0], 19 * n) ||
+            !get(&a->lam[1], 19 * n) || !get(&a->qb[0], 3 * nv) || !get(&a->qb[1], 3 * nv) || !get(&a->F, 3 * n) ||
+            !get(&a->Fb, 3 * n) || !get(&a->ub, 3 * n) || !get(&a->phi, 3 * nv) || !get(&a->gV, 3 * nv) ||
+            !get(&a->phib, 3 * nv) || !get(&a->acc, 4) || !get(&a->grads, 6))
+            return fail(c, IBLB_E_DEVICE, "no device memory for the reverse sweep");
+    }
+    const AdjArgs A = adj_args(c);
+    std::vector<double> soa(3 * nv);
+    for (size_t i = 0; i < nv; ++i)
+        for (int k = 0; k < 3; ++k) soa[(size_t)k * nv + i] = dJdq[3 * i + k];
+    HIP_TRY(c, hipMemcpyAsync(a->qb[1], soa.data(), 3 * nv * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(a->lam[1], 0, 19 * n * 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(a->grads, 0, 6 * 8, c->stream));
+    const int nseg = (a->n + a->every - 1) / a->every;
+    drop_graph(c);
+    for (int sgm = nseg - 1; sgm >= 0; --sgm) {
+        rc = checkpoint(c, a->ck[(size_t)sgm], false);
+        if (rc) return rc;
+        const int len = std::min(a->every, a->n - sgm * a->every);
+        long long t = a->t0 + (long long)sgm * a->every;
+        for (int k = 0; k <= len; ++k) {
+            HIP_TRY(c, launch_get_pops(c->prec, c->d, c->g, (int)(t & 1), a->store + (size_t)k * 19 * n, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(a->qs + (size_t)k * 3 * nv, c->d.q, 3 * nv * 8, hipMemcpyDeviceToDevice,
+                                      c->stream));
+            if (k < len) {
+                HIP_TRY(c, enqueue_step(c, (int)(t & 1), false));
+                ++t;
+            }
+        }
+        for (int k = len - 1; k >= 0; --k)
+            HIP_TRY(c, reverse_step(c, a, A, a->store + (size_t)k * 19 * n, a->store + (size_t)(k + 1) * 19 * n,
+                                    a->qs + (size_t)k * 3 * nv));
+    }
+    // back to the end of the window
+    rc = checkpoint(c, a->ck[(size_t)nseg], false);
+    if (rc) return rc;
+    HIP_TRY(c, hipMemcpyAsync(grads, a->grads, 6 * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(soa.data(), a->qb[1], 3 * nv * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (dJdq0)
+        for (size_t i = 0; i < nv; ++i)
+            for (int k = 0; k < 3; ++k) dJdq0[3 * i + k] = soa[(size_t)k * nv + i];
+    return read_err(c);
+}
+
+int iblb_adjoint_release(iblb_ctx *c)
+{
+    if (!c) return IBLB_E_INVAL;
+    free_adjoint(c);
+    return IBLB_OK;
+}
+
+int iblb_sphere_fit_grad(int32_t nv, const double *q, int32_t wall, double z_wall, double exclude, double *h,
+                         double *r2, double *dh_dq, double *dr2_dq)
+{
+    if (nv < 4 || !q || (wall != 0 && wall != 1) || !std::isfinite(z_wall) || !std::isfinite(exclude))
+        return IBLB_E_INVAL;
+    // vertices at least `exclude` from the wall plane, coordinates relative to
+    // their centroid in x, y and to the wall plane in z
+    std::vector<int> sel;
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < nv; ++i) {
+        const double dz = wall ? z_wall - q[3 * i + 2] : q[3 * i + 2] - z_wall;
+        if (dz >= exclude) {
+            sel.push_back(i);
+            sx += q[3 * i];
+            sy += q[3 * i + 1];
+        }
+    }
+    const int m = (int)sel.size();
+    if (m < 4) return IBLB_E_STATE;
+    sx /= m;
+    sy /= m;
+    auto row = [&](int i, double *p, double *Arow, double *b) {
+        p[0] = q[3 * i] - sx;
+        p[1] = q[3 * i + 1] - sy;
+        p[2] = q[3 * i + 2] - z_wall;
+        Arow[0] = 2.0 * p[0];
+        Arow[1] = 2.0 * p[1];
+        Arow[2] = 2.0 * p[2];
+        Arow[3] = 1.0;
+        *b = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+    };
+    // normal equations M s = A^T b of |p|^2 = 2 c.p + k
+    double M[4][4] = {{0}}, r[4] = {0, 0, 0, 0};
+    for (int i : sel) {
+        double p[3], Ar[4], b;
+        row(i, p, Ar, &b);
+        for (int u = 0; u < 4; ++u) {
+            r[u] += Ar[u] * b;
+            for (int v = 0; v < 4; ++v) M[u][v] += Ar[u] * Ar[v];
+        }
+    }
+    // inverse of M (symmetric positive definite) by Gauss-Jordan with pivoting
+    double Mi[4][8];
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 8; ++v) Mi[u][v] = v < 4 ? M[u][v] : (v - 4 == u ? 1.0 : 0.0);
+    for (int col = 0; col < 4; ++col) {
+        int piv = col;
+        for (int u = col + 1; u < 4; ++u)
+            if (std::fabs(Mi[u][col]) > std::fabs(Mi[piv][col])) piv = u;
+        if (!(std::fabs(Mi[piv][col]) > 0.0)) return IBLB_E_STATE;
+        for (int v = 0; v < 8; ++v) std::swap(Mi[col][v], Mi[piv][v]);
+        const double dgn = Mi[col][col];
+        for (int v = 0; v < 8; ++v) Mi[col][v] /= dgn;
+        for (int u = 0; u < 4; ++u)
+            if (u != col) {
+                const double f = Mi[u][col];
+                for (int v = 0; v < 8; ++v) Mi[u][v] -= f * Mi[col][v];
+            }
+    }
+    double s[4];
+    for (int u = 0; u < 4; ++u) {
+        s[u] = 0.0;
+        for (int v = 0; v < 4; ++v) s[u] += Mi[u][4 + v] * r[v];
+    }
+    const double R = std::sqrt(s[3] + s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    const double hc = wall ? -s[2] : s[2];
+    if (h) *h = hc + R;
+    if (r2) *r2 = s[3] + s[0] * s[0] + s[1] * s[1];  // R^2 - hc^2
+    // d(observable)/ds, then through the least-squares solution: with
+    // w = M^-1 ds and e_i = b_i - A_i.s, dL/dA_i = e_i w - (A_i.w) s and
+    // dL/db_i = A_i.w; A_i = (2 p_i, 1), b_i = |p_i|^2
+    const double dh[4] = {s[0] / R, s[1] / R, (wall ? -1.0 : 1.0) + s[2] / R, 0.5 / R};
+    const double dr[4] = {2.0 * s[0], 2.0 * s[1], 0.0, 1.0};
+    for (int which = 0; which < 2; ++which) {
+        double *out = which == 0 ? dh_dq : dr2_dq;
+        if (!out) continue;
+        const double *ds = which == 0 ? dh : dr;
+        double w[4];
+        for (int u = 0; u < 4; ++u) {
+            w[u] = 0.0;
+            for (int v = 0; v < 4; ++v) w[u] += Mi[u][4 + v] * ds[v];
+        }
+        for (int i = 0; i < 3 * nv; ++i) out[i] = 0.0;
+        for (int i : sel) {
+            double p[3], Ar[4], b;
+            row(i, p, Ar, &b);
+            const double e = b - (Ar[0] * s[0] + Ar[1] * s[1] + Ar[2] * s[2] + Ar[3] * s[3]);
+            const double Aw = Ar[0] * w[0] + Ar[1] * w[1] + Ar[2] * w[2] + Ar[3] * w[3];
+            for (int k = 0; k < 3; ++k) out[3 * i + k] = 2.0 * (e * w[k] - Aw * s[k]) + 2.0 * p[k] * Aw;
+        }
+    }
     return IBLB_OK;
 }
 

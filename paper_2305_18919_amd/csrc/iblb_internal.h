@@ -133,6 +133,37 @@ hipError_t launch_batch(int prec, int which, const DomRec *recs, const uint32_t 
                         hipStream_t s);
 // err[k] = *recs[k].d.err for k < n
 hipError_t launch_batch_errors(const DomRec *recs, int n, int *err, hipStream_t s);
+// Discrete adjoint of the step (iblb_adjoint.hip), FP64 throughout: the
+// constants of one context's step.  Fields are canonical [19][n] / [3][n]
+// FP64 arrays (deviations f - w rho0), vertex arrays SoA [3][nv].
+struct AdjArgs {
+    Grid g;
+    int nv, nf, slots;
+    double rho0, omega;         // omega = 1/tau
+    double body[3], ulo[3], uhi[3];
+    double alpha[3], kv_over_V0, V0, eps_lo, eps_hi, xi, rc, z_lo, z_hi;
+    double origin[3];
+};
+// acc[0] += V - V0, acc[1] += grad V . dir (dir may be null)
+hipError_t adj_volume(const AdjArgs &A, const double *q, const double *X, const int *faces, const double *dir,
+                      double *acc, hipStream_t s);
+// nodal forces phi and grad V per vertex (acc[0] = V - V0)
+hipError_t adj_vertex_forces(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref,
+                             const double *acc, double *phi, double *gV, hipStream_t s);
+// out(x) += sum_i delta(x - q_i) val_i on the fluid nodes
+hipError_t adj_spread(const AdjArgs &A, const double *q, const double *val, double *out, hipStream_t s);
+hipError_t adj_moments(const AdjArgs &A, const double *f1, const double *F, const double *ub, double *lam,
+                       double *Fb, hipStream_t s);
+hipError_t adj_interp(const AdjArgs &A, const double *q, const double *qb1, const double *f1, const double *F,
+                      double *qb0, hipStream_t s);
+// grads[5] += the tau derivative of this step
+hipError_t adj_lb(const AdjArgs &A, const double *f0, const double *F, const double *lam1, double *lam0,
+                  double *Fb, double *grads, hipStream_t s);
+hipError_t adj_interp_force(const AdjArgs &A, const double *q, const double *phi, const double *Fb, double *phib,
+                            double *qb0, hipStream_t s);
+// grads[0..4] += the alpha_1..3, k_V and eps_lo derivatives of this step
+hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref, const double *phib,
+                         const double *gV, const double *acc, double *qb0, double *grads, hipStream_t s);
 // debug / query kernels
 hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double *out, hipStream_t s);
 hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, int p, const double *in, hipStream_t s);

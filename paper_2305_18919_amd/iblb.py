@@ -125,6 +125,10 @@ def lib():
             "iblb_batch_set_config": [_vp, C.POINTER(BatchConfig)],
             "iblb_batch_tune": [_vp, C.c_int32, _dp],
             "iblb_batch_destroy": [_vp],
+            "iblb_adjoint_record": [_vp, C.c_int32, C.c_int32],
+            "iblb_adjoint_backward": [_vp, _dp, _dp, _dp],
+            "iblb_adjoint_release": [_vp],
+            "iblb_sphere_fit_grad": [C.c_int32, _dp, C.c_int32, C.c_double, C.c_double, _dp, _dp, _dp, _dp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -188,6 +192,19 @@ def workspace_bytes(dom, precision: int, mesh=None) -> int:
     if rc != IBLB_OK:
         raise IBLBError(rc, "iblb_workspace_bytes rejected the domain")
     return n.value
+
+
+def sphere_fit_grad(q, wall: int = 0, z_wall: float = 0.5, exclude: float = 2.0):
+    """Height h and signed squared contact radius r2 of the contact-angle fit
+    (iblb_sphere_fit_grad) and their gradients [nv, 3] with respect to q."""
+    qa = _f64(q)
+    h, r2 = C.c_double(), C.c_double()
+    dh, dr2 = np.zeros_like(qa), np.zeros_like(qa)
+    rc = lib().iblb_sphere_fit_grad(qa.shape[0], _p(qa), int(wall), float(z_wall), float(exclude), C.byref(h),
+                                    C.byref(r2), _p(dh), _p(dr2))
+    if rc != IBLB_OK:
+        raise IBLBError(rc, "sphere fit failed (fewer than 4 vertices away from the wall, or singular)")
+    return h.value, r2.value, dh, dr2
 
 
 class Simulation:
@@ -332,6 +349,24 @@ class Simulation:
         th, r, h = C.c_double(), C.c_double(), C.c_double()
         self._check(lib().iblb_contact_angle(self.h, 0, wall, 0, C.byref(th), C.byref(r), C.byref(h)))
         return th.value, r.value, h.value
+
+    # -- adjoint
+    def adjoint_record(self, n: int, every: int = 100):
+        """Step n times keeping device checkpoints every `every` steps."""
+        self._check(lib().iblb_adjoint_record(self.h, int(n), int(every)))
+
+    def adjoint_backward(self, dJdq: np.ndarray):
+        """Reverse sweep over the recorded steps for an observable J of the
+        final positions with gradient dJdq [nv, 3].  Returns dJ/d(alpha_1,
+        alpha_2, alpha_3, k_V, eps_lo, tau) and dJ/dq at the window's start."""
+        src = _f64(dJdq).reshape(-1)
+        g = np.zeros(6)
+        dq0 = np.zeros((self.nv, 3))
+        self._check(lib().iblb_adjoint_backward(self.h, _p(src), _p(g), _p(dq0)))
+        return g, dq0
+
+    def adjoint_release(self):
+        self._check(lib().iblb_adjoint_release(self.h))
 
     # -- checkpoints
     def save_state(self) -> bytes:

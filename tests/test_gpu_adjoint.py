@@ -1,0 +1,126 @@
+"""The hand-written discrete adjoint (iblb_adjoint_*) on the GPU.
+
+Against the FP64 reference gradients of oracle/adjoint.py (autograd through
+a restatement of the step pinned to the C oracle) on a small case with every
+term of the step active, and at the size of the differentiation workload
+(64x64x48, R = 12, 2000 steps, FP32 forward) against central finite
+differences of the FP64 GPU path.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.adjoint import gradients
+from paper_2305_18919_amd import iblb
+from paper_2305_18919_amd.adjoint import contact_observables
+from paper_2305_18919_amd.inputs import Domain, differentiation_case, sphere_mesh
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+MODEL = (1.0, 0.5, 1.0)
+BASE = dict(abar=2e-3, kv=1.0, eps=2e-3, tau=0.9)
+STEPS = 20
+
+
+def make(abar, kv, eps, tau):
+    """Moving walls, a perturbed level-2 mesh across the x seam feeling the
+    wetting lower wall, every alpha term on (the case the reference gradients
+    are pinned on)."""
+    d = Domain(18, 16, 16, tau=tau, u_wall_lo=(0.002, 0, 0), u_wall_hi=(-0.003, 0.001, 0))
+    m = sphere_mesh(2, 4.5, (1.3, 8.2, 0.5 + 4.5 + 0.6), tuple(abar * k for k in MODEL), amplitude=0.02, seed=5,
+                    eps_lo=eps, k_v=kv)
+    return d, m
+
+
+def gpu_gradients(prec, which, every):
+    d, m = make(**BASE)
+    with iblb.Simulation(d, m, precision=prec) as s:
+        s.adjoint_record(STEPS, every)
+        h, r2, dh, dr2 = iblb.sphere_fit_grad(s.vertices(), 0, 0.5, 2.0)
+        g, dq0 = s.adjoint_backward(dh if which == "h" else dr2)
+        assert s.t == STEPS
+    dabar = sum(mk * g[k] for k, mk in enumerate(MODEL))
+    return (h if which == "h" else r2), np.array([dabar, g[3], g[4], g[5]]), dq0
+
+
+@pytest.mark.parametrize("which", ["h", "r2"])
+@pytest.mark.parametrize("every", [8, 20])
+def test_fp64_adjoint_matches_reference(which, every):
+    announce(f"adjoint fp64 {which} every={every}")
+    J, g, dq0 = gpu_gradients(iblb.FP64, which, every)
+    d, m = make(**BASE)
+    Jr, gr, dqr = gradients(d, m, MODEL, BASE["abar"], BASE["kv"], BASE["eps"], BASE["tau"], STEPS, which)
+    announce(f"  J {J:.12g} ref {Jr:.12g}; grads {g} ref {gr}")
+    assert J == pytest.approx(Jr, rel=1e-11)
+    for k in range(4):
+        assert abs(g[k] - gr[k]) <= 1e-9 * abs(gr[k]), (k, g[k], gr[k])
+    assert np.abs(dq0 - dqr).max() <= 1e-9 * np.abs(dqr).max()
+
+
+def test_fp32_forward_adjoint_matches_reference():
+    announce("adjoint fp32 h")
+    J, g, dq0 = gpu_gradients(iblb.FP32_DEV, "h", 8)
+    d, m = make(**BASE)
+    Jr, gr, dqr = gradients(d, m, MODEL, BASE["abar"], BASE["kv"], BASE["eps"], BASE["tau"], STEPS, "h")
+    rel = np.abs(g - gr) / np.abs(gr)
+    announce(f"  rel {rel}")
+    assert (rel <= 1e-4).all()
+    assert np.abs(dq0 - dqr).max() <= 1e-4 * np.abs(dqr).max()
+
+
+def test_autograd_function_combines_both_observables():
+    d, m = make(**BASE)
+    p = torch.tensor([BASE["abar"], BASE["kv"], BASE["eps"], BASE["tau"]], dtype=torch.float64, requires_grad=True)
+    out = contact_observables(p, d, m, MODEL, STEPS, every=8, precision=iblb.FP64)
+    (out[0] + 0.25 * out[1]).backward()
+    _, gh, _ = gradients(d, m, MODEL, BASE["abar"], BASE["kv"], BASE["eps"], BASE["tau"], STEPS, "h")
+    _, gr, _ = gradients(d, m, MODEL, BASE["abar"], BASE["kv"], BASE["eps"], BASE["tau"], STEPS, "r2")
+    ref = gh + 0.25 * gr
+    assert np.allclose(p.grad.numpy(), ref, rtol=1e-9, atol=0)
+
+
+# Relative steps of the central differences, per parameter.  The wall force
+# is cut off plainly at r_c (Eq. LJ_interaction as printed, no shift), so the
+# step at which a face centroid crosses r_c moves in jumps as a parameter
+# changes and the observables are only piecewise smooth: for eps and tau, to
+# which the contact region is most sensitive, an interval of 1e-4 straddles
+# such a jump and the differences are off by up to 1e-3, while 1e-5 agrees
+# with the adjoint to 1e-7.  k_V barely moves the observables (dr2/dk_V ~ 1e-2),
+# so at 1e-5 the rounding of the two runs dominates; 1e-4 is used for it and
+# for abar.
+FD_STEP = {"abar": 1e-4, "kv": 1e-4, "eps": 1e-5, "tau": 1e-5}
+
+
+def test_differentiation_workload_against_finite_differences():
+    """64x64x48, R = 12, 2000 steps: the FP32-forward adjoint against central
+    differences (FD_STEP of each parameter) of the FP64 GPU path."""
+    w = differentiation_case()
+    base = dict(abar=w.notes["abar"], kv=w.notes["kv"], eps=w.notes["eps"], tau=w.notes["tau"])
+    announce("adjoint 64x64x48, 2000 steps")
+    p = torch.tensor([base["abar"], base["kv"], base["eps"], base["tau"]], dtype=torch.float64, requires_grad=True)
+    out = contact_observables(p, w.domain, w.mesh, w.notes["model"], w.steps, every=100, precision=iblb.FP32_DEV)
+    grads = {}
+    for k, name in enumerate(("h", "r2")):
+        g, = torch.autograd.grad(out[k], p, retain_graph=(k == 0))
+        grads[name] = g.numpy()
+
+    def observe(pp):
+        wc = differentiation_case(pp["abar"], pp["kv"], pp["eps"] / pp["abar"], pp["tau"])
+        with iblb.Simulation(wc.domain, wc.mesh, precision=iblb.FP64) as s:
+            s.step(wc.steps)
+            h, r2, _, _ = iblb.sphere_fit_grad(s.vertices(), 0, 0.5, 2.0)
+        return np.array([h, r2])
+
+    for k, name in enumerate(("abar", "kv", "eps", "tau")):
+        hh = base[name] * FD_STEP[name]
+        pp, pm = dict(base), dict(base)
+        pp[name] += hh
+        pm[name] -= hh
+        fd = (observe(pp) - observe(pm)) / (2 * hh)
+        for j, obs in enumerate(("h", "r2")):
+            ad = grads[obs][k]
+            announce(f"  d{obs}/d{name}: adjoint {ad:.6e} fd {fd[j]:.6e} rel {abs(ad - fd[j]) / abs(fd[j]):.2e}")
+            assert abs(ad - fd[j]) <= 1e-4 * abs(fd[j])
