@@ -38,8 +38,10 @@ class _ContactRun(torch.autograd.Function):
         return torch.tensor([dabar, g[3], g[4], g[5]], dtype=torch.float64), None
 
 
-def contact_observables(params: torch.Tensor, domain, mesh, model, steps: int, every: int = 100,
+def contact_observables(params: torch.Tensor, domain, mesh, model, steps: int, every: int = 0,
                         precision: int = iblb.FP32_DEV) -> torch.Tensor:
     """(h, r2) after `steps` steps; differentiable with respect to params =
-    (abar, k_V, eps_lo, tau)."""
+    (abar, k_V, eps_lo, tau).  every = 0 keeps every time level in device
+    memory (no recompute); every > 0 keeps a checkpoint every `every` steps
+    and recomputes each segment in the backward pass."""
     return _ContactRun.apply(params, (domain, mesh, model, steps, every, precision))

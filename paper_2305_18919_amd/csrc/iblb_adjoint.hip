@@ -33,6 +33,12 @@
 namespace iblb {
 namespace {
 
+// the same tables in constant memory, for loops that index them with a
+// uniform counter
+__constant__ int cCx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__constant__ int cCy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__constant__ int cCz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
 constexpr int kCx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 constexpr int kCy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int kCz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
@@ -138,18 +144,6 @@ __device__ __forceinline__ void volume_corner(const T *a, const T *b, const T *c
 
 // LJ force magnitude per unit eps along the wall normal at distance d
 // (Eq. LJ_interaction): 48 [(xi/d)^12 - (xi/d)^6 / 2] / d, 0 from rc on, d >= xi/2
-template <typename T>
-__device__ __forceinline__ T lj_unit(double xi, double rc, T d)
-{
-    if (!(val(d) < rc)) return T{} * 0.0;
-    T dd = d;
-    if (val(d) < 0.5 * xi) dd = T{} * 0.0 + 0.5 * xi;
-    const T r = xi / dd;
-    const T r2 = r * r;
-    const T r6 = r2 * r2 * r2;
-    return 48.0 * (r6 * r6 - 0.5 * r6) / dd;
-}
-
 __device__ __forceinline__ double lj_unit(double xi, double rc, double d)
 {
     if (!(d < rc)) return 0.0;
@@ -229,15 +223,17 @@ __device__ __forceinline__ Node stencil_node(const AdjArgs &A, double qx, double
     return nd;
 }
 
-// u(t+1) = (sum c f + (F + body)/2) / rho at a fluid node, from canonical deviations
-__device__ __forceinline__ void velocity(const AdjArgs &A, const double *__restrict__ f, const double *__restrict__ F,
+// u = (sum c f + (F + body)/2) / rho at a fluid node, from canonical
+// deviations stored with element type P
+template <typename P>
+__device__ __forceinline__ void velocity(const AdjArgs &A, const P *__restrict__ f, const double *__restrict__ F,
                                          long long id, double *u, double *rho)
 {
     const long long n = A.g.n;
     double dr = 0.0, m[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-        const double d = f[i * n + id];
+        const double d = double(f[i * n + id]);
         dr += d;
         m[0] += kCx[i] * d;
         m[1] += kCy[i] * d;
@@ -251,6 +247,15 @@ __device__ __forceinline__ double wave_sum64(double v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// sum over the aligned group of 8 lanes
+__device__ __forceinline__ double group8_sum(double v)
+{
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 1, 64);
     return v;
 }
 
@@ -314,18 +319,19 @@ __global__ __launch_bounds__(256) void ka_volume(AdjArgs A, const double *__rest
 }
 
 // Nodal forces phi = phi^S + phi^V + phi^W and grad V per vertex, gathered
-// over the vertex's incident faces; acc[0] = V - V0.
+// over the vertex's incident faces by 8 lanes (one incident face each, slot
+// s = lane, lane + 8, ...); acc[0] = V - V0.
 __global__ __launch_bounds__(256) void ka_vertex_forces(AdjArgs A, const double *__restrict__ q,
                                                         const int4 *__restrict__ inc4, const double *__restrict__ fref,
                                                         const double *__restrict__ acc, double *__restrict__ phi,
                                                         double *__restrict__ gV)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= A.nv) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = t >> 3, lane = t & 7;
+    if (v >= A.nv) return;  // whole groups of 8 leave together
     const int nv = A.nv, nf = A.nf;
-    const double dV = acc[0];
     double fs[3] = {0, 0, 0}, gv[3] = {0, 0, 0}, fw = 0.0;
-    for (int s = 0; s < A.slots; ++s) {
+    for (int s = lane; s < A.slots; s += 8) {
         const int4 e = inc4[(long long)v * A.slots + s];
         if (e.w < 0) continue;
         const int j = e.w >> 2, corner = e.w & 3;
@@ -351,15 +357,24 @@ __global__ __launch_bounds__(256) void ka_vertex_forces(AdjArgs A, const double 
         }
     }
     for (int k = 0; k < 3; ++k) {
-        phi[k * nv + v] = fs[k] - A.kv_over_V0 * dV * gv[k] + (k == 2 ? fw : 0.0);
-        gV[k * nv + v] = gv[k];
+        fs[k] = group8_sum(fs[k]);
+        gv[k] = group8_sum(gv[k]);
+    }
+    fw = group8_sum(fw);
+    if (lane == 0) {
+        const double dV = acc[0];
+        for (int k = 0; k < 3; ++k) {
+            phi[k * nv + v] = fs[k] - A.kv_over_V0 * dV * gv[k] + (k == 2 ? fw : 0.0);
+            gV[k * nv + v] = gv[k];
+        }
     }
 }
 
-// out(x) += sum_i delta(x - q_i) val_i over the fluid nodes (one thread per
-// vertex and stencil node)
-__global__ __launch_bounds__(256) void ka_spread(AdjArgs A, const double *__restrict__ q, const double *__restrict__ val,
-                                                 double *out)
+// F(x) += sum_i delta(x - q_i) phi_i and ub(x) += sum_i delta(x - q_i) qb_i
+// over the fluid nodes (one thread per vertex and stencil node)
+__global__ __launch_bounds__(256) void ka_spread2(AdjArgs A, const double *__restrict__ q,
+                                                  const double *__restrict__ phi, const double *__restrict__ qb,
+                                                  double *F, double *ub)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = (int)(t >> 6), k = (int)(t & 63);
@@ -370,14 +385,19 @@ __global__ __launch_bounds__(256) void ka_spread(AdjArgs A, const double *__rest
     const Node nd = stencil_node(A, qx, qy, qz, k);
     if (nd.id < 0 || nd.w == 0.0) return;
     const long long n = A.g.n;
-    for (int c = 0; c < 3; ++c) atomicAdd(out + c * n + nd.id, val[c * nv + v] * nd.w);
+    for (int c = 0; c < 3; ++c) {
+        atomicAdd(F + c * n + nd.id, phi[c * nv + v] * nd.w);
+        atomicAdd(ub + c * n + nd.id, qb[c * nv + v] * nd.w);
+    }
 }
 
-// Adjoint of u' = (sum c f1 + (F + body)/2) / rho1 at every fluid node with ub != 0:
-// lam_j += (c_j - u') . ub / rho1,  Fb += ub / (2 rho1)
-__global__ __launch_bounds__(256) void ka_moments_adj(AdjArgs A, const double *__restrict__ f1,
+// Adjoint of u' = (sum c f1 + (F + body)/2) / rho1 with respect to f1 at every
+// fluid node with ub != 0: lam_j += (c_j - u') . ub / rho1 (its share of the
+// force adjoint, ub / (2 rho1), is added by ka_lb_adj)
+template <typename P>
+__global__ __launch_bounds__(256) void ka_moments_adj(AdjArgs A, const P *__restrict__ f1,
                                                       const double *__restrict__ F, const double *__restrict__ ub,
-                                                      double *__restrict__ lam, double *__restrict__ Fb)
+                                                      double *__restrict__ lam)
 {
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = A.g.n;
@@ -385,19 +405,19 @@ __global__ __launch_bounds__(256) void ka_moments_adj(AdjArgs A, const double *_
     const double b[3] = {ub[id], ub[n + id], ub[2 * n + id]};
     if (b[0] == 0.0 && b[1] == 0.0 && b[2] == 0.0) return;
     double u[3], rho;
-    velocity(A, f1, F, id, u, &rho);
+    velocity<P>(A, f1, F, id, u, &rho);
     const double ub_u = b[0] * u[0] + b[1] * u[1] + b[2] * u[2];
 #pragma unroll
     for (int j = 0; j < 19; ++j)
         lam[j * n + id] += (kCx[j] * b[0] + kCy[j] * b[1] + kCz[j] * b[2] - ub_u) / rho;
-    for (int k = 0; k < 3; ++k) Fb[k * n + id] += b[k] / (2.0 * rho);
 }
 
 // qb0_i = qb1_i + sum_x (u'(x) . qb1_i) grad_q delta(x - q_i), u' at the
 // fluid nodes from (f1, F), the wall velocity elsewhere (one wavefront per
 // vertex, one lane per stencil node)
+template <typename P>
 __global__ __launch_bounds__(256) void ka_interp_adj(AdjArgs A, const double *__restrict__ q,
-                                                     const double *__restrict__ qb1, const double *__restrict__ f1,
+                                                     const double *__restrict__ qb1, const P *__restrict__ f1,
                                                      const double *__restrict__ F, double *__restrict__ qb0)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -412,7 +432,7 @@ __global__ __launch_bounds__(256) void ka_interp_adj(AdjArgs A, const double *__
         double u[3];
         if (nd.id >= 0) {
             double rho;
-            velocity(A, f1, F, nd.id, u, &rho);
+            velocity<P>(A, f1, F, nd.id, u, &rho);
         } else {
             for (int c = 0; c < 3; ++c) u[c] = nd.side ? A.uhi[c] : A.ulo[c];
         }
@@ -429,9 +449,22 @@ __global__ __launch_bounds__(256) void ka_interp_adj(AdjArgs A, const double *__
 // term -6 w_i rho (c_i . u_w) adds to the density adjoint); then
 //   lam0_j = (1 - 1/tau) Lam_j + a + b . (c_j - u) / rho,
 //   a = sum_i Lam_i d f*_i / d rho |u,   b = sum_i Lam_i d f*_i / d u,
-//   Fb += sum_i Lam_i d S_i / d F + b / (2 rho),
+//   Fb = sum_i Lam_i d S_i / d F + b / (2 rho) + ub / (2 rho1)  (the last term
+//        the force share of the interpolated velocity's adjoint),
 //   d/dtau: sum_i Lam_i [(f_i - f^eq_i) + s_i / 2] / tau^2  with S_i = (1 - 1/(2 tau)) s_i.
-__global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const double *__restrict__ f0, const double *__restrict__ F,
+// Lam and the populations are each read twice (the second time from cache)
+// so that the kernel keeps few registers.
+// element at a 32-bit byte offset from a base pointer (a uniform base and
+// one address register per access)
+template <typename T>
+__device__ __forceinline__ T ld32(const T *base, uint32_t byte_off)
+{
+    return *(const T *)((const char *)base + byte_off);
+}
+
+template <typename P>
+__global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict__ f0, const P *__restrict__ f1,
+                                                 const double *__restrict__ F, const double *__restrict__ ub,
                                                  const double *__restrict__ lam1, double *__restrict__ lam0,
                                                  double *__restrict__ Fb, double *grads)
 {
@@ -441,59 +474,95 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const double *__rest
     double tb[1] = {0.0};
     if (id < n) {
         const int x = (int)(id % g.nx), y = (int)((id / g.nx) % g.ny), zf = (int)(id / ((long long)g.nx * g.ny));
-        double d[19], dr = 0.0, m[3] = {0.0, 0.0, 0.0};
+        // byte offsets of this node in a [19][n] array of P and of doubles
+        const uint32_t oP = (uint32_t)id * (uint32_t)sizeof(P), oD = (uint32_t)id * 8u;
+        double dr = 0.0, m[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            d[i] = f0[i * n + id];
-            dr += d[i];
-            m[0] += kCx[i] * d[i];
-            m[1] += kCy[i] * d[i];
-            m[2] += kCz[i] * d[i];
+            const double d = double(ld32(f0 + (size_t)i * n, oP));
+            dr += d;
+            m[0] += kCx[i] * d;
+            m[1] += kCy[i] * d;
+            m[2] += kCz[i] * d;
         }
         const double rho = A.rho0 + dr;
-        const double Fx = F[id] + A.body[0], Fy = F[n + id] + A.body[1], Fz = F[2 * n + id] + A.body[2];
-        const double u[3] = {(m[0] + 0.5 * Fx) / rho, (m[1] + 0.5 * Fy) / rho, (m[2] + 0.5 * Fz) / rho};
-        const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-        const double uF = u[0] * Fx + u[1] * Fy + u[2] * Fz;
+        const double Fx = ld32(F, oD) + A.body[0], Fy = ld32(F + n, oD) + A.body[1],
+                     Fz = ld32(F + 2 * n, oD) + A.body[2];
+        const double u0 = (m[0] + 0.5 * Fx) / rho, u1 = (m[1] + 0.5 * Fy) / rho, u2 = (m[2] + 0.5 * Fz) / rho;
+        const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+        const double uF = u0 * Fx + u1 * Fy + u2 * Fz;
         const double om = A.omega, guo = 1.0 - 0.5 * om;
-        double a = 0.0, b[3] = {0.0, 0.0, 0.0}, fb[3] = {0.0, 0.0, 0.0}, Lam[19];
-#pragma unroll
+        double a = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0, tt = 0.0;
+        const int zt = zf + (g.walls ? 1 : 0);
+        // Lam_i, the adjoint of post-collision population i at x; wall links
+        // also add their moving-wall term to the density adjoint
+        // (the accumulation unrolled by two only, to keep the registers of a
+        // few directions live at a time)
+#pragma unroll 2
         for (int i = 0; i < 19; ++i) {
-            const int cx = kCx[i], cy = kCy[i], cz = kCz[i];
-            const int tz = zf + (g.walls ? 1 : 0) + cz;
+            const int cx = cCx[i], cy = cCy[i], cz = cCz[i];
+            const int tz = zt + cz;
+            const double w = wq(i);
             double L;
             if (g.walls && (tz < 1 || tz > g.nz - 2)) {
-                L = lam1[oppq(i) * n + id];
-                const double *uw = tz < 1 ? A.ulo : A.uhi;
-                a += -6.0 * wq(i) * (cx * uw[0] + cy * uw[1] + cz * uw[2]) * L;
+                L = ld32(lam1 + (size_t)oppq(i) * n, oD);
+                const double uwx = tz < 1 ? A.ulo[0] : A.uhi[0], uwy = tz < 1 ? A.ulo[1] : A.uhi[1];
+                a += -6.0 * w * (cx * uwx + cy * uwy) * L;  // wall velocities are tangential
             } else {
                 const int tzf = g.walls ? tz - 1 : wrapn(tz, g.nz);
-                const long long to = ((long long)tzf * g.ny + wrapn(y + cy, g.ny)) * g.nx + wrapn(x + cx, g.nx);
-                L = lam1[i * n + to];
+                const uint32_t to = ((uint32_t)tzf * (uint32_t)g.ny + (uint32_t)wrapn(y + cy, g.ny)) * (uint32_t)g.nx +
+                                    (uint32_t)wrapn(x + cx, g.nx);
+                L = ld32(lam1 + (size_t)i * n, to * 8u);
             }
-            Lam[i] = L;
-            const double w = wq(i);
-            const double cu = cx * u[0] + cy * u[1] + cz * u[2];
+            const double cu = cx * u0 + cy * u1 + cz * u2;
             const double cF = cx * Fx + cy * Fy + cz * Fz;
             const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
             const double deq = w * dr + w * rho * poly;
             const double si = w * (3.0 * (cF - uF) + 9.0 * cF * cu);
             // f*_i = d_i - om (d_i - deq_i) + guo s_i
             a += L * om * w * (1.0 + poly);
-            const double c3[3] = {(double)cx, (double)cy, (double)cz};
-            const double Fv[3] = {Fx, Fy, Fz};
-            for (int k = 0; k < 3; ++k) {
-                b[k] += L * (om * w * rho * (3.0 * c3[k] + 9.0 * cu * c3[k] - 3.0 * u[k]) +
-                             guo * w * (-3.0 * Fv[k] + 9.0 * cF * c3[k]));
-                fb[k] += L * guo * w * (3.0 * (c3[k] - u[k]) + 9.0 * cu * c3[k]);
-            }
-            tb[0] += L * om * om * ((d[i] - deq) + 0.5 * si);
+            const double Lr = L * om * w * rho, Lg = L * guo * w;
+            b0 += Lr * (3.0 * cx + 9.0 * cu * cx - 3.0 * u0) + Lg * (-3.0 * Fx + 9.0 * cF * cx);
+            b1 += Lr * (3.0 * cy + 9.0 * cu * cy - 3.0 * u1) + Lg * (-3.0 * Fy + 9.0 * cF * cy);
+            b2 += Lr * (3.0 * cz + 9.0 * cu * cz - 3.0 * u2) + Lg * (-3.0 * Fz + 9.0 * cF * cz);
+            g0 += Lg * (3.0 * (cx - u0) + 9.0 * cu * cx);
+            g1 += Lg * (3.0 * (cy - u1) + 9.0 * cu * cy);
+            g2 += Lg * (3.0 * (cz - u2) + 9.0 * cu * cz);
+            tt += L * om * om * ((double(ld32(f0 + (size_t)i * n, oP)) - deq) + 0.5 * si);
         }
+        tb[0] = tt;
+        const double ir = 1.0 / rho;
+        // second pass: Lam gathered again (cache-resident) rather than held in registers
 #pragma unroll
-        for (int j = 0; j < 19; ++j)
-            lam0[j * n + id] = (1.0 - om) * Lam[j] + a +
-                               (b[0] * (kCx[j] - u[0]) + b[1] * (kCy[j] - u[1]) + b[2] * (kCz[j] - u[2])) / rho;
-        for (int k = 0; k < 3; ++k) Fb[k * n + id] += fb[k] + b[k] / (2.0 * rho);
+        for (int j = 0; j < 19; ++j) {
+            const int cx = cCx[j], cy = cCy[j], cz = cCz[j];
+            const int tz = zt + cz;
+            double L;
+            if (g.walls && (tz < 1 || tz > g.nz - 2)) {
+                L = ld32(lam1 + (size_t)oppq(j) * n, oD);
+            } else {
+                const int tzf = g.walls ? tz - 1 : wrapn(tz, g.nz);
+                const uint32_t to = ((uint32_t)tzf * (uint32_t)g.ny + (uint32_t)wrapn(y + cy, g.ny)) * (uint32_t)g.nx +
+                                    (uint32_t)wrapn(x + cx, g.nx);
+                L = ld32(lam1 + (size_t)j * n, to * 8u);
+            }
+            *(double *)((char *)(lam0 + (size_t)j * n) + oD) =
+                (1.0 - om) * L + a + (b0 * (cx - u0) + b1 * (cy - u1) + b2 * (cz - u2)) * ir;
+        }
+        double fb0 = g0 + 0.5 * b0 * ir, fb1 = g1 + 0.5 * b1 * ir, fb2 = g2 + 0.5 * b2 * ir;
+        const double ub0 = ub[id], ub1 = ub[n + id], ub2 = ub[2 * n + id];
+        if (ub0 != 0.0 || ub1 != 0.0 || ub2 != 0.0) {
+            double d1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < 19; ++i) d1 += double(ld32(f1 + (size_t)i * n, oP));
+            const double h = 0.5 / (A.rho0 + d1);
+            fb0 += ub0 * h;
+            fb1 += ub1 * h;
+            fb2 += ub2 * h;
+        }
+        Fb[id] = fb0;
+        Fb[n + id] = fb1;
+        Fb[2 * n + id] = fb2;
     }
     block_atomic_add<1>(tb, grads + 5);
 }
@@ -537,22 +606,22 @@ __global__ __launch_bounds__(256) void ka_interp_force(AdjArgs A, const double *
 // qb0_i += (d Phi / d q phib)_i (the directional derivative of the nodal
 // forces along phib, with acc[0] = V - V0 and acc[1] = grad V . phib), and the
 // parameter derivatives phib . dPhi/dalpha_m (m = 1..3), phib . dPhi/dk_V,
-// phib . dPhi/deps_lo into grads[0..4].
+// phib . dPhi/deps_lo into grads[0..4].  8 lanes per vertex, one incident
+// face each.
 __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__restrict__ q,
                                                     const int4 *__restrict__ inc4, const double *__restrict__ fref,
                                                     const double *__restrict__ phib, const double *__restrict__ gV,
                                                     const double *__restrict__ acc, double *__restrict__ qb0,
                                                     double *grads)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = t >> 3, lane = t & 7;
     double pg[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (v < A.nv) {
+    if (v < A.nv) {  // whole groups of 8 take the same branch
         const int nv = A.nv, nf = A.nf;
-        const double dV = acc[0], Vdot = acc[1];
         const double w1 = 0.5 * A.alpha[2];
-        const double pbv[3] = {phib[v], phib[nv + v], phib[2 * nv + v]};
         double jv[3] = {0.0, 0.0, 0.0}, dgv[3] = {0.0, 0.0, 0.0}, dS[3][3] = {{0}}, ljz = 0.0;
-        for (int s = 0; s < A.slots; ++s) {
+        for (int s = lane; s < A.slots; s += 8) {
             const int4 e = inc4[(long long)v * A.slots + s];
             if (e.w < 0) continue;
             const int j = e.w >> 2, corner = e.w & 3;
@@ -585,20 +654,79 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
             }
         }
         for (int k = 0; k < 3; ++k) {
-            const double gvk = gV[k * nv + v];
-            jv[k] += -A.kv_over_V0 * (Vdot * gvk + dV * dgv[k]);
-            qb0[k * nv + v] += jv[k];
-            for (int m = 0; m < 3; ++m) pg[m] += pbv[k] * dS[m][k];
-            pg[3] += pbv[k] * (-dV / A.V0) * gvk;
+            jv[k] = group8_sum(jv[k]);
+            dgv[k] = group8_sum(dgv[k]);
+            for (int m = 0; m < 3; ++m) dS[m][k] = group8_sum(dS[m][k]);
         }
-        pg[4] = pbv[2] * ljz;
+        ljz = group8_sum(ljz);
+        if (lane == 0) {
+            const double dV = acc[0], Vdot = acc[1];
+            const double pbv[3] = {phib[v], phib[nv + v], phib[2 * nv + v]};
+            for (int k = 0; k < 3; ++k) {
+                const double gvk = gV[k * nv + v];
+                qb0[k * nv + v] += jv[k] - A.kv_over_V0 * (Vdot * gvk + dV * dgv[k]);
+                for (int m = 0; m < 3; ++m) pg[m] += pbv[k] * dS[m][k];
+                pg[3] += pbv[k] * (-dV / A.V0) * gvk;
+            }
+            pg[4] = pbv[2] * ljz;
+        }
     }
     block_atomic_add<5>(pg, grads);
 }
 
+// F = ub = 0 over [3][n] each, acc[0..3] = 0, in one launch
+__global__ __launch_bounds__(256) void ka_zero_fields(double *__restrict__ F, double *__restrict__ ub, long long n3,
+                                                      double *__restrict__ acc)
+{
+    const long long s0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s0 < 4) acc[s0] = 0.0;
+    for (long long i = s0; i < n3; i += (long long)gridDim.x * blockDim.x) {
+        F[i] = 0.0;
+        ub[i] = 0.0;
+    }
+}
+
+// p[0..n) = 0 and dst[0..n) = src[0..n) as kernels, so that the reverse
+// sweep can be captured in a graph without memset or copy nodes
+__global__ __launch_bounds__(256) void ka_zero(double *__restrict__ p, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void ka_copy(double *__restrict__ dst, const double *__restrict__ src, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 int blocks_for(long long threads) { return (int)((threads + 255) / 256); }
 
+int grid_stride_blocks(long long n)
+{
+    const long long b = (n + 255) / 256;
+    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
 }  // namespace
+
+hipError_t adj_zero(double *p, long long n, hipStream_t s)
+{
+    ka_zero<<<grid_stride_blocks(n), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t adj_copy(double *dst, const double *src, long long n, hipStream_t s)
+{
+    ka_copy<<<grid_stride_blocks(n), 256, 0, s>>>(dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t adj_zero_fields(double *F, double *ub, long long n3, double *acc, hipStream_t s)
+{
+    ka_zero_fields<<<grid_stride_blocks(n3), 256, 0, s>>>(F, ub, n3, acc);
+    return hipGetLastError();
+}
 
 hipError_t adj_volume(const AdjArgs &A, const double *q, const double *X, const int *faces, const double *dir,
                       double *acc, hipStream_t s)
@@ -610,34 +738,46 @@ hipError_t adj_volume(const AdjArgs &A, const double *q, const double *X, const 
 hipError_t adj_vertex_forces(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref,
                              const double *acc, double *phi, double *gV, hipStream_t s)
 {
-    ka_vertex_forces<<<blocks_for(A.nv), 256, 0, s>>>(A, q, inc4, fref, acc, phi, gV);
+    ka_vertex_forces<<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, q, inc4, fref, acc, phi, gV);
     return hipGetLastError();
 }
 
-hipError_t adj_spread(const AdjArgs &A, const double *q, const double *val, double *out, hipStream_t s)
+hipError_t adj_spread2(const AdjArgs &A, const double *q, const double *phi, const double *qb, double *F, double *ub,
+                       hipStream_t s)
 {
-    ka_spread<<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, val, out);
+    ka_spread2<<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, phi, qb, F, ub);
     return hipGetLastError();
 }
 
-hipError_t adj_moments(const AdjArgs &A, const double *f1, const double *F, const double *ub, double *lam,
-                       double *Fb, hipStream_t s)
+hipError_t adj_moments(const AdjArgs &A, int fp64, const void *f1, const double *F, const double *ub, double *lam,
+                       hipStream_t s)
 {
-    ka_moments_adj<<<blocks_for(A.g.n), 256, 0, s>>>(A, f1, F, ub, lam, Fb);
+    if (fp64)
+        ka_moments_adj<double><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const double *)f1, F, ub, lam);
+    else
+        ka_moments_adj<float><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const float *)f1, F, ub, lam);
     return hipGetLastError();
 }
 
-hipError_t adj_interp(const AdjArgs &A, const double *q, const double *qb1, const double *f1, const double *F,
-                      double *qb0, hipStream_t s)
+hipError_t adj_interp(const AdjArgs &A, int fp64, const double *q, const double *qb1, const void *f1,
+                      const double *F, double *qb0, hipStream_t s)
 {
-    ka_interp_adj<<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, qb1, f1, F, qb0);
+    if (fp64)
+        ka_interp_adj<double><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, qb1, (const double *)f1, F, qb0);
+    else
+        ka_interp_adj<float><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, qb1, (const float *)f1, F, qb0);
     return hipGetLastError();
 }
 
-hipError_t adj_lb(const AdjArgs &A, const double *f0, const double *F, const double *lam1, double *lam0,
-                  double *Fb, double *grads, hipStream_t s)
+hipError_t adj_lb(const AdjArgs &A, int fp64, const void *f0, const void *f1, const double *F, const double *ub,
+                  const double *lam1, double *lam0, double *Fb, double *grads, hipStream_t s)
 {
-    ka_lb_adj<<<blocks_for(A.g.n), 256, 0, s>>>(A, f0, F, lam1, lam0, Fb, grads);
+    if (fp64)
+        ka_lb_adj<double><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const double *)f0, (const double *)f1, F, ub, lam1,
+                                                              lam0, Fb, grads);
+    else
+        ka_lb_adj<float><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const float *)f0, (const float *)f1, F, ub, lam1,
+                                                             lam0, Fb, grads);
     return hipGetLastError();
 }
 
@@ -651,7 +791,7 @@ hipError_t adj_interp_force(const AdjArgs &A, const double *q, const double *phi
 hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref, const double *phib,
                          const double *gV, const double *acc, double *qb0, double *grads, hipStream_t s)
 {
-    ka_force_jvp<<<blocks_for(A.nv), 256, 0, s>>>(A, q, inc4, fref, phib, gV, acc, qb0, grads);
+    ka_force_jvp<<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, q, inc4, fref, phib, gV, acc, qb0, grads);
     return hipGetLastError();
 }
 

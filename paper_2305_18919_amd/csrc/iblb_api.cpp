@@ -1580,18 +1580,21 @@ int iblb_batch_destroy(iblb_batch *b)
 // ---------------------------------------------------------------------------
 struct AdjState {
     long long t0 = 0;                  // time at the start of the recorded window
-    int n = 0, every = 0;              // steps recorded, steps per checkpoint
-    std::vector<char *> ck;            // device checkpoints at t0, t0 + every, ..., and t0 + n
+    int n = 0, every = 0;              // steps recorded; steps per checkpoint, 0 = every level kept
+    std::vector<char *> ck;            // checkpoint mode: device states at t0, t0 + every, ..., t0 + n
     size_t snap = 0;                   // bytes of one checkpoint
-    // reverse-sweep buffers (allocated by the first backward call)
-    double *store = nullptr;           // [every + 1][19][n] populations of a segment's time levels
-    double *qs = nullptr;              // [every + 1][3][nv] positions of a segment's time levels
-    double *lam[2] = {nullptr, nullptr};
-    double *qb[2] = {nullptr, nullptr};
+    size_t es = 8;                     // bytes per stored population: the step's arithmetic precision
+    void *store = nullptr;             // [levels][19][n] populations of the stored time levels
+    double *qs = nullptr;              // [levels][3][nv] positions of the stored time levels
+    double *lam[2] = {nullptr, nullptr};  // ping-pong adjoints of the populations: [1] is t+1
+    double *qb[2] = {nullptr, nullptr};   // and of the positions
+    double *lam_buf[2] = {nullptr, nullptr}, *qb_buf[2] = {nullptr, nullptr};  // their allocations
     double *F = nullptr, *Fb = nullptr, *ub = nullptr;
     double *phi = nullptr, *gV = nullptr, *phib = nullptr;
     double *acc = nullptr;             // [4]: V - V0 and grad V . dir, twice
     double *grads = nullptr;           // [6]
+    hipGraph_t graph = nullptr;        // checkpoint mode: recompute and reverse sweep of one full segment
+    hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -1601,8 +1604,11 @@ void free_adjoint(iblb_ctx *c)
     AdjState *a = c->adj;
     if (!a) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (a->gexec) (void)hipGraphExecDestroy(a->gexec);
+    if (a->graph) (void)hipGraphDestroy(a->graph);
     for (char *p : a->ck) (void)hipFree(p);
-    for (double *p : {a->store, a->qs, a->lam[0], a->lam[1], a->qb[0], a->qb[1], a->F, a->Fb, a->ub, a->phi,
+    if (a->store) (void)hipFree(a->store);
+    for (double *p : {a->qs, a->lam_buf[0], a->lam_buf[1], a->qb_buf[0], a->qb_buf[1], a->F, a->Fb, a->ub, a->phi,
                       a->gV, a->phib, a->acc, a->grads})
         if (p) (void)hipFree(p);
     delete a;
@@ -1662,39 +1668,88 @@ AdjArgs adj_args(const iblb_ctx *c)
     return A;
 }
 
+void *level(AdjState *a, size_t n, int k) { return (char *)a->store + (size_t)k * 19 * n * a->es; }
+
+// Stores the populations (in the step's arithmetic precision) and positions
+// of the current time t as level k.
+hipError_t store_level(iblb_ctx *c, AdjState *a, long long t, int k)
+{
+    const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
+    hipError_t e = c->prec == IBLB_FP64
+                       ? launch_get_pops(c->prec, c->d, c->g, (int)(t & 1), (double *)level(a, n, k), c->stream)
+                       : launch_get_pops_f32(c->prec, c->d, c->g, (int)(t & 1), (float *)level(a, n, k), c->stream);
+    if (e == hipSuccess) e = adj_copy(a->qs + (size_t)k * 3 * nv, c->d.q, 3 * (long long)nv, c->stream);
+    return e;
+}
+
 // One reverse step: (lam[1], qb[1]) at t+1 -> (lam[0], qb[0]) at t, from the
-// populations f0 = f(t), f1 = f(t+1) and positions q = q(t).
-hipError_t reverse_step(iblb_ctx *c, AdjState *a, const AdjArgs &A, const double *f0, const double *f1,
-                        const double *q)
+// stored levels k (time t) and k + 1.
+hipError_t reverse_step(iblb_ctx *c, AdjState *a, const AdjArgs &A, int k)
 {
     const hipStream_t s = c->stream;
-    const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
+    const size_t n = (size_t)c->g.n;
     const Dev &d = c->d;
+    const int fp64 = a->es == 8;
+    const void *f0 = level(a, n, k), *f1 = level(a, n, k + 1);
+    const double *q = a->qs + (size_t)k * 3 * c->nv;
     hipError_t e;
 #define ADJ_TRY(x)                    \
     do {                              \
         e = (x);                      \
         if (e != hipSuccess) return e; \
     } while (0)
-    ADJ_TRY(hipMemsetAsync(a->acc, 0, 4 * sizeof(double), s));
+    ADJ_TRY(adj_zero_fields(a->F, a->ub, 3 * (long long)n, a->acc, s));
     ADJ_TRY(adj_volume(A, q, d.Xref, d.faces, nullptr, a->acc, s));
     ADJ_TRY(adj_vertex_forces(A, q, d.inc4, d.fref, a->acc, a->phi, a->gV, s));
-    ADJ_TRY(hipMemsetAsync(a->F, 0, 3 * n * sizeof(double), s));
-    ADJ_TRY(adj_spread(A, q, a->phi, a->F, s));
-    ADJ_TRY(hipMemsetAsync(a->ub, 0, 3 * n * sizeof(double), s));
-    ADJ_TRY(adj_spread(A, q, a->qb[1], a->ub, s));
-    ADJ_TRY(hipMemsetAsync(a->Fb, 0, 3 * n * sizeof(double), s));
-    ADJ_TRY(adj_moments(A, f1, a->F, a->ub, a->lam[1], a->Fb, s));
-    ADJ_TRY(adj_interp(A, q, a->qb[1], f1, a->F, a->qb[0], s));
-    ADJ_TRY(adj_lb(A, f0, a->F, a->lam[1], a->lam[0], a->Fb, a->grads, s));
+    ADJ_TRY(adj_spread2(A, q, a->phi, a->qb[1], a->F, a->ub, s));
+    ADJ_TRY(adj_moments(A, fp64, f1, a->F, a->ub, a->lam[1], s));
+    ADJ_TRY(adj_interp(A, fp64, q, a->qb[1], f1, a->F, a->qb[0], s));
+    ADJ_TRY(adj_lb(A, fp64, f0, f1, a->F, a->ub, a->lam[1], a->lam[0], a->Fb, a->grads, s));
     ADJ_TRY(adj_interp_force(A, q, a->phi, a->Fb, a->phib, a->qb[0], s));
     ADJ_TRY(adj_volume(A, q, d.Xref, d.faces, a->phib, a->acc + 2, s));
     ADJ_TRY(adj_force_jvp(A, q, d.inc4, d.fref, a->phib, a->gV, a->acc + 2, a->qb[0], a->grads, s));
 #undef ADJ_TRY
-    (void)nv;
     std::swap(a->lam[0], a->lam[1]);
     std::swap(a->qb[0], a->qb[1]);
     return hipSuccess;
+}
+
+// Checkpoint mode: the recompute of one segment from its restored checkpoint
+// (time levels t .. t + len) and its reverse sweep, as launches on the
+// context stream (kernels only, so that it can be captured).
+hipError_t enqueue_segment(iblb_ctx *c, AdjState *a, const AdjArgs &A, long long t, int len)
+{
+    hipError_t e;
+    for (int k = 0; k <= len; ++k) {
+        e = store_level(c, a, t, k);
+        if (e == hipSuccess && k < len) {
+            e = enqueue_step(c, (int)(t & 1), false);
+            ++t;
+        }
+        if (e != hipSuccess) return e;
+    }
+    for (int k = len - 1; k >= 0; --k) {
+        e = reverse_step(c, a, A, k);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int alloc_sweep(iblb_ctx *c, AdjState *a, size_t levels)
+{
+    const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
+    auto get = [&](double **p, size_t count) { return hipMalloc(p, std::max<size_t>(count, 1) * 8) == hipSuccess; };
+    if (hipMalloc(&a->store, levels * 19 * n * a->es) != hipSuccess) {
+        a->store = nullptr;
+        return fail(c, IBLB_E_DEVICE, "no device memory for " + std::to_string(levels) +
+                                          " stored time levels (record with a checkpoint interval instead)");
+    }
+    if (!get(&a->qs, levels * 3 * nv) || !get(&a->lam_buf[0], 19 * n) || !get(&a->lam_buf[1], 19 * n) ||
+        !get(&a->qb_buf[0], 3 * nv) || !get(&a->qb_buf[1], 3 * nv) || !get(&a->F, 3 * n) || !get(&a->Fb, 3 * n) ||
+        !get(&a->ub, 3 * n) || !get(&a->phi, 3 * nv) || !get(&a->gV, 3 * nv) || !get(&a->phib, 3 * nv) ||
+        !get(&a->acc, 4) || !get(&a->grads, 6))
+        return fail(c, IBLB_E_DEVICE, "no device memory for the reverse sweep");
+    return IBLB_OK;
 }
 
 }  // namespace
@@ -1703,7 +1758,7 @@ extern "C" {
 
 int iblb_adjoint_record(iblb_ctx *c, int32_t n_steps, int32_t every)
 {
-    if (!c || n_steps < 1 || every < 1) return IBLB_E_INVAL;
+    if (!c || n_steps < 1 || every < 0) return IBLB_E_INVAL;
     if (!c->has_mesh) return fail(c, IBLB_E_STATE, "the adjoint needs a mesh");
     free_adjoint(c);
     AdjState *a = new AdjState();
@@ -1711,30 +1766,70 @@ int iblb_adjoint_record(iblb_ctx *c, int32_t n_steps, int32_t every)
     a->t0 = c->t;
     a->n = n_steps;
     a->every = every;
-    a->snap = checkpoint_bytes(c);
-    const int nseg = (n_steps + every - 1) / every;
-    for (int k = 0; k <= nseg; ++k) {
-        char *p = nullptr;
-        if (hipMalloc(&p, a->snap) != hipSuccess) {
-            free_adjoint(c);
-            return fail(c, IBLB_E_DEVICE, "no device memory for the adjoint checkpoints");
+    a->es = c->prec == IBLB_FP64 ? 8 : 4;
+    int rc = IBLB_OK;
+    if (every == 0) {
+        // every time level kept: the reverse sweep needs no recompute.  Each
+        // step stores the level of its start time (the level index comes
+        // from the device step counter), in replays of one captured graph of
+        // kGraphSteps steps from even times and single launches otherwise.
+        rc = alloc_sweep(c, a, (size_t)n_steps + 1);
+        const uint32_t t0 = (uint32_t)a->t0, maxl = (uint32_t)n_steps;
+        hipGraphExec_t gx = nullptr;
+        hipGraph_t gr = nullptr;
+        auto one = [&](int p) {
+            hipError_t e = launch_store_level(c->prec, c->d, c->g, c->nv, p, t0, maxl, a->store, a->qs, c->stream);
+            return e == hipSuccess ? enqueue_step(c, p, false) : e;
+        };
+        int left = n_steps;
+        while (!rc && left > 0) {
+            const int p = (int)(c->t & 1);
+            hipError_t e = hipSuccess;
+            if (p == 0 && left >= kGraphSteps && c->use_graph) {
+                if (!gx) {
+                    e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+                    hipError_t e1 = hipSuccess;
+                    for (int k = 0; k < kGraphSteps && e == hipSuccess && e1 == hipSuccess; ++k) e1 = one(k & 1);
+                    if (e == hipSuccess) e = hipStreamEndCapture(c->stream, &gr);
+                    if (e == hipSuccess) e = e1;
+                    if (e == hipSuccess) e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
+                }
+                if (e == hipSuccess) e = hipGraphLaunch(gx, c->stream);
+                c->t += kGraphSteps;
+                left -= kGraphSteps;
+            } else {
+                e = one(p);
+                c->t += 1;
+                left -= 1;
+            }
+            if (e != hipSuccess) rc = hip_fail(c, e, "recording the window");
         }
-        a->ck.push_back(p);
-    }
-    for (int sgm = 0; sgm < nseg; ++sgm) {
-        int rc = checkpoint(c, a->ck[(size_t)sgm], true);
-        if (!rc) rc = iblb_step(c, std::min(every, n_steps - sgm * every));
-        if (rc) {
-            free_adjoint(c);
-            return rc;
+        if (!rc) {
+            hipError_t e = launch_store_level(c->prec, c->d, c->g, c->nv, (int)(c->t & 1), t0, maxl, a->store, a->qs,
+                                              c->stream);
+            if (e != hipSuccess) rc = hip_fail(c, e, "storing the last level");
         }
+        if (c->stream) (void)hipStreamSynchronize(c->stream);
+        if (gx) (void)hipGraphExecDestroy(gx);
+        if (gr) (void)hipGraphDestroy(gr);
+    } else {
+        a->snap = checkpoint_bytes(c);
+        const int nseg = (n_steps + every - 1) / every;
+        for (int k = 0; !rc && k <= nseg; ++k) {
+            char *p = nullptr;
+            if (hipMalloc(&p, a->snap) != hipSuccess)
+                rc = fail(c, IBLB_E_DEVICE, "no device memory for the adjoint checkpoints");
+            else
+                a->ck.push_back(p);
+        }
+        for (int sgm = 0; !rc && sgm < nseg; ++sgm) {
+            rc = checkpoint(c, a->ck[(size_t)sgm], true);
+            if (!rc) rc = iblb_step(c, std::min(every, n_steps - sgm * every));
+        }
+        if (!rc) rc = checkpoint(c, a->ck[(size_t)nseg], true);
     }
-    int rc = checkpoint(c, a->ck[(size_t)nseg], true);
-    if (rc) {
-        free_adjoint(c);
-        return rc;
-    }
-    return IBLB_OK;
+    if (rc) free_adjoint(c);
+    return rc;
 }
 
 int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double *dJdq0)
@@ -1746,14 +1841,15 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     int rc = sync_ctx(c);
     if (rc) return rc;
     const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
-    const size_t lev = (size_t)a->every + 1;
-    if (!a->store) {
-        auto get = [&](double **p, size_t count) { return hipMalloc(p, std::max<size_t>(count, 1) * 8) == hipSuccess; };
-        if (!get(&a->store, lev * 19 * n) || !get(&a->qs, lev * 3 * nv) || !get(&a->lam[0], 19 * n) ||
-            !get(&a->lam[1], 19 * n) || !get(&a->qb[0], 3 * nv) || !get(&a->qb[1], 3 * nv) || !get(&a->F, 3 * n) ||
-            !get(&a->Fb, 3 * n) || !get(&a->ub, 3 * n) || !get(&a->phi, 3 * nv) || !get(&a->gV, 3 * nv) ||
-            !get(&a->phib, 3 * nv) || !get(&a->acc, 4) || !get(&a->grads, 6))
-            return fail(c, IBLB_E_DEVICE, "no device memory for the reverse sweep");
+    if (!a->lam_buf[0]) {
+        rc = alloc_sweep(c, a, (size_t)a->every + 1);
+        if (rc) return rc;
+    }
+    // the same buffer roles at the start of every call (a captured segment
+    // graph has them built in)
+    for (int k = 0; k < 2; ++k) {
+        a->lam[k] = a->lam_buf[k];
+        a->qb[k] = a->qb_buf[k];
     }
     const AdjArgs A = adj_args(c);
     std::vector<double> soa(3 * nv);
@@ -1762,29 +1858,44 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     HIP_TRY(c, hipMemcpyAsync(a->qb[1], soa.data(), 3 * nv * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemsetAsync(a->lam[1], 0, 19 * n * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(a->grads, 0, 6 * 8, c->stream));
-    const int nseg = (a->n + a->every - 1) / a->every;
-    drop_graph(c);
-    for (int sgm = nseg - 1; sgm >= 0; --sgm) {
-        rc = checkpoint(c, a->ck[(size_t)sgm], false);
-        if (rc) return rc;
-        const int len = std::min(a->every, a->n - sgm * a->every);
-        long long t = a->t0 + (long long)sgm * a->every;
-        for (int k = 0; k <= len; ++k) {
-            HIP_TRY(c, launch_get_pops(c->prec, c->d, c->g, (int)(t & 1), a->store + (size_t)k * 19 * n, c->stream));
-            HIP_TRY(c, hipMemcpyAsync(a->qs + (size_t)k * 3 * nv, c->d.q, 3 * nv * 8, hipMemcpyDeviceToDevice,
-                                      c->stream));
-            if (k < len) {
-                HIP_TRY(c, enqueue_step(c, (int)(t & 1), false));
-                ++t;
+    if (a->every == 0) {
+        for (int k = a->n - 1; k >= 0; --k) HIP_TRY(c, reverse_step(c, a, A, k));
+    } else {
+        // Full segments replay one captured graph: with an even checkpoint
+        // interval every full segment starts at the parity of t0, and the
+        // ping-pong buffers are back in their roles at its end.  A shorter
+        // last segment, or an odd interval, is launched directly.
+        const bool use_graph = (a->every % 2) == 0 && c->use_graph;
+        const int nseg = (a->n + a->every - 1) / a->every;
+        drop_graph(c);
+        for (int sgm = nseg - 1; sgm >= 0; --sgm) {
+            rc = checkpoint(c, a->ck[(size_t)sgm], false);
+            if (rc) return rc;
+            const int len = std::min(a->every, a->n - sgm * a->every);
+            const long long t = a->t0 + (long long)sgm * a->every;
+            if (use_graph && len == a->every) {
+                if (!a->gexec) {
+                    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                    hipError_t e = enqueue_segment(c, a, A, t, len);
+                    hipGraph_t gr = nullptr;
+                    hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
+                    if (e != hipSuccess) {
+                        if (gr) (void)hipGraphDestroy(gr);
+                        return hip_fail(c, e, "reverse sweep capture");
+                    }
+                    HIP_TRY(c, e2);
+                    a->graph = gr;
+                    HIP_TRY(c, hipGraphInstantiate(&a->gexec, a->graph, nullptr, nullptr, 0));
+                }
+                HIP_TRY(c, hipGraphLaunch(a->gexec, c->stream));
+            } else {
+                HIP_TRY(c, enqueue_segment(c, a, A, t, len));
             }
         }
-        for (int k = len - 1; k >= 0; --k)
-            HIP_TRY(c, reverse_step(c, a, A, a->store + (size_t)k * 19 * n, a->store + (size_t)(k + 1) * 19 * n,
-                                    a->qs + (size_t)k * 3 * nv));
+        // back to the end of the window
+        rc = checkpoint(c, a->ck[(size_t)nseg], false);
+        if (rc) return rc;
     }
-    // back to the end of the window
-    rc = checkpoint(c, a->ck[(size_t)nseg], false);
-    if (rc) return rc;
     HIP_TRY(c, hipMemcpyAsync(grads, a->grads, 6 * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(soa.data(), a->qb[1], 3 * nv * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -144,21 +144,27 @@ struct AdjArgs {
     double alpha[3], kv_over_V0, V0, eps_lo, eps_hi, xi, rc, z_lo, z_hi;
     double origin[3];
 };
+hipError_t adj_zero(double *p, long long n, hipStream_t s);
+hipError_t adj_copy(double *dst, const double *src, long long n, hipStream_t s);
+// F = ub = 0 ([3][n] each) and acc[0..3] = 0
+hipError_t adj_zero_fields(double *F, double *ub, long long n3, double *acc, hipStream_t s);
 // acc[0] += V - V0, acc[1] += grad V . dir (dir may be null)
 hipError_t adj_volume(const AdjArgs &A, const double *q, const double *X, const int *faces, const double *dir,
                       double *acc, hipStream_t s);
 // nodal forces phi and grad V per vertex (acc[0] = V - V0)
 hipError_t adj_vertex_forces(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref,
                              const double *acc, double *phi, double *gV, hipStream_t s);
-// out(x) += sum_i delta(x - q_i) val_i on the fluid nodes
-hipError_t adj_spread(const AdjArgs &A, const double *q, const double *val, double *out, hipStream_t s);
-hipError_t adj_moments(const AdjArgs &A, const double *f1, const double *F, const double *ub, double *lam,
-                       double *Fb, hipStream_t s);
-hipError_t adj_interp(const AdjArgs &A, const double *q, const double *qb1, const double *f1, const double *F,
-                      double *qb0, hipStream_t s);
-// grads[5] += the tau derivative of this step
-hipError_t adj_lb(const AdjArgs &A, const double *f0, const double *F, const double *lam1, double *lam0,
-                  double *Fb, double *grads, hipStream_t s);
+// F(x) += sum_i delta(x - q_i) phi_i, ub(x) += sum_i delta(x - q_i) qb_i on the fluid nodes
+hipError_t adj_spread2(const AdjArgs &A, const double *q, const double *phi, const double *qb, double *F, double *ub,
+                       hipStream_t s);
+// stored populations f0 = f(t), f1 = f(t+1): double (fp64 != 0) or float
+hipError_t adj_moments(const AdjArgs &A, int fp64, const void *f1, const double *F, const double *ub, double *lam,
+                       hipStream_t s);
+hipError_t adj_interp(const AdjArgs &A, int fp64, const double *q, const double *qb1, const void *f1,
+                      const double *F, double *qb0, hipStream_t s);
+// lam0 and Fb from lam1; grads[5] += the tau derivative of this step
+hipError_t adj_lb(const AdjArgs &A, int fp64, const void *f0, const void *f1, const double *F, const double *ub,
+                  const double *lam1, double *lam0, double *Fb, double *grads, hipStream_t s);
 hipError_t adj_interp_force(const AdjArgs &A, const double *q, const double *phi, const double *Fb, double *phib,
                             double *qb0, hipStream_t s);
 // grads[0..4] += the alpha_1..3, k_V and eps_lo derivatives of this step
@@ -166,6 +172,12 @@ hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, co
                          const double *gV, const double *acc, double *qb0, double *grads, hipStream_t s);
 // debug / query kernels
 hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double *out, hipStream_t s);
+hipError_t launch_get_pops_f32(int prec, const Dev &d, const Grid &g, int p, float *out, hipStream_t s);
+// populations (FP64 storage: double, else float) and positions of the current
+// time into level ctr[p] - t0 of [level][19][n] and [level][3][nv] stores
+// (nothing for a level above max_level)
+hipError_t launch_store_level(int prec, const Dev &d, const Grid &g, int nv, int p, uint32_t t0, uint32_t max_level,
+                              void *store, double *qs, hipStream_t s);
 hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, int p, const double *in, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Dev &d, const LBArgs &a, int p, double *rho, double *u, hipStream_t s);
 hipError_t launch_get_force(int prec, const Dev &d, const LBArgs &a, int p, double *F, hipStream_t s);

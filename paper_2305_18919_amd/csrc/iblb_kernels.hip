@@ -1310,8 +1310,8 @@ __global__ __launch_bounds__(256) void kb_errors(const DomRec *__restrict__ R, i
 // ---------------------------------------------------------------------------
 // Debug and query kernels (not on the per-step path)
 // ---------------------------------------------------------------------------
-template <typename S>
-__global__ __launch_bounds__(256) void k_get_pops(const S *__restrict__ f, int p, double *__restrict__ out, Grid g)
+template <typename S, typename O = double>
+__global__ __launch_bounds__(256) void k_get_pops(const S *__restrict__ f, int p, O *__restrict__ out, Grid g)
 {
     using T = typename Pop<S>::C;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1326,7 +1326,45 @@ __global__ __launch_bounds__(256) void k_get_pops(const S *__restrict__ f, int p
         load_pops<S, false>(f, g, x, y, zf, d);
     const long long me = nidx(g, x, y, zf);
     for (int i = 0; i < 19; ++i)
-        out[i * g.n + me] = double(d[i]);
+        out[i * g.n + me] = O(d[i]);
+}
+
+// Level ctr[p] - t0 (at most max_level) of a store of time levels
+// [level][19][n]: the populations of the current time in canonical order,
+// converted to O.  The level comes from the device step counter, so that a
+// captured graph of several steps writes a new level at every step.
+template <typename S, typename O>
+__global__ __launch_bounds__(256) void k_store_level(const S *__restrict__ f, const uint32_t *__restrict__ ctr, int p,
+                                                     uint32_t t0, uint32_t max_level, O *__restrict__ store, Grid g)
+{
+    using T = typename Pop<S>::C;
+    const uint32_t level = ctr[p] - t0;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int zf = blockIdx.z;
+    if (level > max_level || x >= g.nx || y >= g.ny)
+        return;
+    T d[19];
+    if (p)
+        load_pops<S, true>(f, g, x, y, zf, d);
+    else
+        load_pops<S, false>(f, g, x, y, zf, d);
+    O *out = store + (size_t)level * 19 * (size_t)g.n;
+    const long long me = nidx(g, x, y, zf);
+    for (int i = 0; i < 19; ++i)
+        out[i * g.n + me] = O(d[i]);
+}
+
+// positions [3][nv] of the current time into level ctr[p] - t0 of [level][3][nv]
+__global__ __launch_bounds__(256) void k_store_positions(const double *__restrict__ q, const uint32_t *__restrict__ ctr,
+                                                         int p, uint32_t t0, uint32_t max_level,
+                                                         double *__restrict__ qs, int nv)
+{
+    const uint32_t level = ctr[p] - t0;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (level > max_level || i >= 3 * nv)
+        return;
+    qs[(size_t)level * 3 * nv + i] = q[i];
 }
 
 template <typename S>
@@ -1708,6 +1746,36 @@ hipError_t launch_batch_errors(const DomRec *recs, int n, int *err, hipStream_t 
 hipError_t launch_stamp(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s)
 {
     k_stamp<<<(m.nv + 3) / 4, 256, 0, s>>>(d.q, d.act, d.mask, d.ctr, d.err, g, m, p);
+    return hipGetLastError();
+}
+
+// populations in the arithmetic precision of the step: exact for every
+// storage precision except FP64 (prec 0), which this launcher rejects
+hipError_t launch_get_pops_f32(int prec, const Dev &d, const Grid &g, int p, float *out, hipStream_t s)
+{
+    if (prec == 0)
+        return hipErrorInvalidValue;
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        k_get_pops<S, float><<<lb_grid(g), lb_block(g), 0, s>>>((const S *)d.f, p, out, g);
+    });
+}
+
+hipError_t launch_store_level(int prec, const Dev &d, const Grid &g, int nv, int p, uint32_t t0, uint32_t max_level,
+                              void *store, double *qs, hipStream_t s)
+{
+    hipError_t e = with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        if (prec == 0)
+            k_store_level<S, double><<<lb_grid(g), lb_block(g), 0, s>>>((const S *)d.f, d.ctr, p, t0, max_level,
+                                                                       (double *)store, g);
+        else
+            k_store_level<S, float><<<lb_grid(g), lb_block(g), 0, s>>>((const S *)d.f, d.ctr, p, t0, max_level,
+                                                                      (float *)store, g);
+    });
+    if (e != hipSuccess)
+        return e;
+    k_store_positions<<<(3 * nv + 255) / 256, 256, 0, s>>>(d.q, d.ctr, p, t0, max_level, qs, nv);
     return hipGetLastError();
 }
 
