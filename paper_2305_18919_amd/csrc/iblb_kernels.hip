@@ -352,7 +352,7 @@ __device__ __forceinline__ void bulk_lb_block(int b, S *__restrict__ f, const T 
 // In the AA pattern each node reads and writes only its own 19 slots, so the
 // two node sets never touch the same memory.
 template <typename S, bool ODD>
-__global__ __launch_bounds__(256) void k_lb(S *__restrict__ f, const typename Pop<S>::C *__restrict__ Fext,
+__global__ __launch_bounds__(1024) void k_lb(S *__restrict__ f, const typename Pop<S>::C *__restrict__ Fext,
                                             const uint8_t *__restrict__ act, uint32_t *ctr, int *err, LBArgs a)
 {
     using T = typename Pop<S>::C;
@@ -1601,12 +1601,17 @@ hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hip
     });
 }
 
+// The LB-only kernel runs 1024-thread blocks (the x-width of lb_block, 1024 /
+// width rows): on the 128x128x96 lattice 64x16 blocks took 33.2 us per
+// launch against 33.3 (64x8) and 34.0 (64x4); x-widths below a 64-node row
+// were 13 % slower (measured on MI355X, FP32).
 template <typename S, bool ODD>
 static void lb_launch(const Dev &d, const LBArgs &a, bool bulk, hipStream_t s)
 {
     using T = typename Pop<S>::C;
-    k_lb<S, ODD><<<lb_grid(a.g), lb_block(a.g), 0, s>>>((S *)d.f, (const T *)d.Fext, bulk ? d.act : nullptr, d.ctr,
-                                                          d.err, a);
+    const int bx = (int)lb_block(a.g).x, by = 1024 / bx;
+    const dim3 blk(bx, by, 1), grd((a.g.nx + bx - 1) / bx, (a.g.ny + by - 1) / by, a.g.nzf);
+    k_lb<S, ODD><<<grd, blk, 0, s>>>((S *)d.f, (const T *)d.Fext, bulk ? d.act : nullptr, d.ctr, d.err, a);
 }
 
 hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, hipStream_t s)

@@ -280,13 +280,19 @@ def batch_sweep(n: int = 48, seed: int = SEED + 5) -> list[Workload]:
     return out
 
 
-def differentiation_case(abar: float = 1e-3, kv: float = 1.0, eps_over_abar: float = 1.0,
-                         tau: float = 1.0) -> Workload:
-    """64x64x48 walls, pure droplet abar(1,0,0), level 4 (2562/5120), R = 12,
-    lifted R + 2^(1/6) xi above the wetting lower wall (eps = eps_over_abar *
-    abar), 2000 steps, FP32 populations: the run whose final contact radius and
-    height are differentiated."""
-    mesh = sphere_mesh(4, 12.0, (31.5, 31.5, 0.5 + 12.0 + LJ_R0), (abar, 0.0, 0.0), k_v=kv,
+def wetting_case(model=(1.0, 0.0, 0.0), eps_over_abar: float = 1.0, abar: float = 1e-3, kv: float = 1.0,
+                 tau: float = 1.0) -> Workload:
+    """64x64x48 walls, a droplet alpha = abar * model of radius R = 12 at
+    level 4 (2562/5120), lifted R + 2^(1/6) xi above the wetting lower wall
+    (eps = eps_over_abar * abar), FP32 populations."""
+    mesh = sphere_mesh(4, 12.0, (31.5, 31.5, 0.5 + 12.0 + LJ_R0), tuple(abar * m for m in model), k_v=kv,
                        eps_lo=eps_over_abar * abar)
     return Workload("wetting64x48_f32", Domain(64, 64, 48, tau=tau), mesh, 2000, "f32",
-                    {"model": (1.0, 0.0, 0.0), "abar": abar, "kv": kv, "eps": eps_over_abar * abar, "tau": tau})
+                    {"model": tuple(model), "abar": abar, "kv": kv, "eps": eps_over_abar * abar, "tau": tau})
+
+
+def differentiation_case(abar: float = 1e-3, kv: float = 1.0, eps_over_abar: float = 1.0,
+                         tau: float = 1.0) -> Workload:
+    """The run whose final contact radius and height are differentiated: the
+    pure droplet abar(1,0,0) of wetting_case, 2000 steps."""
+    return wetting_case((1.0, 0.0, 0.0), eps_over_abar, abar, kv, tau)
