@@ -364,7 +364,7 @@ def adjoint_study(every: int):
     # recorded forward, then the reverse sweep (one per observable): every
     # time level kept (every = 0), and checkpoints every `every` steps with
     # recompute
-    modes = {}
+    modes, grads = {}, {}
     for ev in (0, every):
         with iblb.Simulation(w.domain, w.mesh, precision=1, graph=True) as s:
             torch.cuda.synchronize()
@@ -379,7 +379,9 @@ def adjoint_study(every: int):
             gr, _ = s.adjoint_backward(dr2)
         modes[ev] = {"record_s": round(t_rec, 4), "backward_s": round(t_bwd, 4),
                      "adjoint_over_forward": round((t_rec + t_bwd) / t_fwd, 3)}
+        grads[ev] = (gh, gr)
     t_rec, t_bwd = modes[0]["record_s"], modes[0]["backward_s"]
+    gh, gr = grads[0]
     ad = {"h": [sum(m * gh[k] for k, m in enumerate(model)), gh[3], gh[4], gh[5]],
           "r2": [sum(m * gr[k] for k, m in enumerate(model)), gr[3], gr[4], gr[5]]}
 

@@ -23,9 +23,11 @@
 // Every nodal force is minus the gradient of an energy (W_S, k_V (V - V0)^2 /
 // (2 V0) and the LJ potential of each face centroid), so d Phi / d q is
 // symmetric and its transpose product is the directional derivative of Phi
-// along phib, computed with dual numbers.  The forward quantities (phi, F,
-// rho, u, u') are recomputed in FP64 from the stored populations and
-// positions of each time level.
+// along phib, computed with dual numbers.  With every time level kept, the
+// forward's own force density, u(t+1) and nodal force parts of each step are
+// read back (ka_*_u, ka_interp_force_s, reverse_kept); with checkpoints, the
+// forward quantities (phi, F, rho, u, u') are recomputed in FP64 from the
+// stored populations and positions of each time level.
 #include "iblb_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -462,9 +464,9 @@ __device__ __forceinline__ T ld32(const T *base, uint32_t byte_off)
     return *(const T *)((const char *)base + byte_off);
 }
 
-template <typename P>
+template <typename P, typename FT = double>
 __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict__ f0, const P *__restrict__ f1,
-                                                 const double *__restrict__ F, const double *__restrict__ ub,
+                                                 const FT *__restrict__ F, const double *__restrict__ ub,
                                                  const double *__restrict__ lam1, double *__restrict__ lam0,
                                                  double *__restrict__ Fb, double *grads)
 {
@@ -486,8 +488,9 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
             m[2] += kCz[i] * d;
         }
         const double rho = A.rho0 + dr;
-        const double Fx = ld32(F, oD) + A.body[0], Fy = ld32(F + n, oD) + A.body[1],
-                     Fz = ld32(F + 2 * n, oD) + A.body[2];
+        const uint32_t oF = (uint32_t)id * (uint32_t)sizeof(FT);
+        const double Fx = double(ld32(F, oF)) + A.body[0], Fy = double(ld32(F + n, oF)) + A.body[1],
+                     Fz = double(ld32(F + 2 * n, oF)) + A.body[2];
         const double u0 = (m[0] + 0.5 * Fx) / rho, u1 = (m[1] + 0.5 * Fy) / rho, u2 = (m[2] + 0.5 * Fz) / rho;
         const double uu = u0 * u0 + u1 * u1 + u2 * u2;
         const double uF = u0 * Fx + u1 * Fy + u2 * Fz;
@@ -608,9 +611,10 @@ __global__ __launch_bounds__(256) void ka_interp_force(AdjArgs A, const double *
 // parameter derivatives phib . dPhi/dalpha_m (m = 1..3), phib . dPhi/dk_V,
 // phib . dPhi/deps_lo into grads[0..4].  8 lanes per vertex, one incident
 // face each.
+template <typename G>
 __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__restrict__ q,
                                                     const int4 *__restrict__ inc4, const double *__restrict__ fref,
-                                                    const double *__restrict__ phib, const double *__restrict__ gV,
+                                                    const double *__restrict__ phib, const G *__restrict__ gV,
                                                     const double *__restrict__ acc, double *__restrict__ qb0,
                                                     double *grads)
 {
@@ -663,7 +667,7 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
             const double dV = acc[0], Vdot = acc[1];
             const double pbv[3] = {phib[v], phib[nv + v], phib[2 * nv + v]};
             for (int k = 0; k < 3; ++k) {
-                const double gvk = gV[k * nv + v];
+                const double gvk = double(gV[k * nv + v]);
                 qb0[k * nv + v] += jv[k] - A.kv_over_V0 * (Vdot * gvk + dV * dgv[k]);
                 for (int m = 0; m < 3; ++m) pg[m] += pbv[k] * dS[m][k];
                 pg[3] += pbv[k] * (-dV / A.V0) * gvk;
@@ -674,14 +678,124 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
     block_atomic_add<5>(pg, grads);
 }
 
-// F = ub = 0 over [3][n] each, acc[0..3] = 0, in one launch
+// ---- variants for a window whose every level was kept by the forward run:
+// the force density F, u(t+1) in U, the nodal force parts and V - V0 of each
+// step come from the forward itself (element type P), so nothing is recomputed
+
+// ub(x) += sum_i delta(x - q_i) qb_i over the fluid nodes
+__global__ __launch_bounds__(256) void ka_spread1(AdjArgs A, const double *__restrict__ q,
+                                                  const double *__restrict__ qb, double *ub)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(t >> 6), k = (int)(t & 63);
+    if (v >= A.nv) return;
+    const int nv = A.nv;
+    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+    if (!finite_pos(qx, qy, qz)) return;
+    const Node nd = stencil_node(A, qx, qy, qz, k);
+    if (nd.id < 0 || nd.w == 0.0) return;
+    const long long n = A.g.n;
+    for (int c = 0; c < 3; ++c) atomicAdd(ub + c * n + nd.id, qb[c * nv + v] * nd.w);
+}
+
+// lam_j += (c_j - u') . ub / rho1 where ub != 0, u' from U, rho1 from f1
+template <typename P>
+__global__ __launch_bounds__(256) void ka_moments_adj_u(AdjArgs A, const P *__restrict__ f1, const P *__restrict__ U,
+                                                        const double *__restrict__ ub, double *__restrict__ lam)
+{
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = A.g.n;
+    if (id >= n) return;
+    const double b[3] = {ub[id], ub[n + id], ub[2 * n + id]};
+    if (b[0] == 0.0 && b[1] == 0.0 && b[2] == 0.0) return;
+    double dr = 0.0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) dr += double(f1[i * n + id]);
+    const double rho = A.rho0 + dr;
+    const double ub_u = b[0] * double(U[id]) + b[1] * double(U[n + id]) + b[2] * double(U[2 * n + id]);
+#pragma unroll
+    for (int j = 0; j < 19; ++j)
+        lam[j * n + id] += (kCx[j] * b[0] + kCy[j] * b[1] + kCz[j] * b[2] - ub_u) / rho;
+}
+
+// qb0_i = qb1_i + sum_x (u'(x) . qb1_i) grad_q delta(x - q_i), u' from U
+template <typename P>
+__global__ __launch_bounds__(256) void ka_interp_adj_u(AdjArgs A, const double *__restrict__ q,
+                                                       const double *__restrict__ qb1, const P *__restrict__ U,
+                                                       double *__restrict__ qb0)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(t >> 6), k = (int)(t & 63);
+    if (v >= A.nv) return;
+    const int nv = A.nv;
+    const long long n = A.g.n;
+    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+    const double b[3] = {qb1[v], qb1[nv + v], qb1[2 * nv + v]};
+    double s[3] = {0.0, 0.0, 0.0};
+    if (finite_pos(qx, qy, qz)) {
+        const Node nd = stencil_node(A, qx, qy, qz, k);
+        double u[3];
+        if (nd.id >= 0) {
+            for (int c = 0; c < 3; ++c) u[c] = double(U[c * n + nd.id]);
+        } else {
+            for (int c = 0; c < 3; ++c) u[c] = nd.side ? A.uhi[c] : A.ulo[c];
+        }
+        const double ubq = u[0] * b[0] + u[1] * b[1] + u[2] * b[2];
+        for (int c = 0; c < 3; ++c) s[c] = ubq * nd.gw[c];
+    }
+    for (int c = 0; c < 3; ++c) s[c] = wave_sum64(s[c]);
+    if (k == 0)
+        for (int c = 0; c < 3; ++c) qb0[c * nv + v] = b[c] + s[c];
+}
+
+// phib_i = sum_x Fb delta and qb0_i += sum_x (Fb . phi_i) grad_q delta, with
+// phi_i = (phi_S + phi_W)_i - k_V (V - V0) / V0 (dV/dq)_i from the kept parts
+template <typename P>
+__global__ __launch_bounds__(256) void ka_interp_force_s(AdjArgs A, const double *__restrict__ q,
+                                                         const P *__restrict__ phs, const P *__restrict__ gvs,
+                                                         const double *__restrict__ dV, const double *__restrict__ Fb,
+                                                         double *__restrict__ phib, double *__restrict__ qb0)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(t >> 6), k = (int)(t & 63);
+    if (v >= A.nv) return;
+    const int nv = A.nv;
+    const long long n = A.g.n;
+    const double kf = A.kv_over_V0 * dV[0];
+    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+    double p[3];
+    for (int c = 0; c < 3; ++c) p[c] = double(phs[c * nv + v]) - kf * double(gvs[c * nv + v]);
+    double pb[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
+    if (finite_pos(qx, qy, qz)) {
+        const Node nd = stencil_node(A, qx, qy, qz, k);
+        if (nd.id >= 0) {
+            const double fb[3] = {Fb[nd.id], Fb[n + nd.id], Fb[2 * n + nd.id]};
+            const double fp = fb[0] * p[0] + fb[1] * p[1] + fb[2] * p[2];
+            for (int c = 0; c < 3; ++c) {
+                pb[c] = fb[c] * nd.w;
+                s[c] = fp * nd.gw[c];
+            }
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        pb[c] = wave_sum64(pb[c]);
+        s[c] = wave_sum64(s[c]);
+    }
+    if (k == 0)
+        for (int c = 0; c < 3; ++c) {
+            phib[c * nv + v] = pb[c];
+            qb0[c * nv + v] += s[c];
+        }
+}
+
+// F = ub = 0 over [3][n] each (F may be null), acc[0..3] = 0, in one launch
 __global__ __launch_bounds__(256) void ka_zero_fields(double *__restrict__ F, double *__restrict__ ub, long long n3,
                                                       double *__restrict__ acc)
 {
     const long long s0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s0 < 4) acc[s0] = 0.0;
     for (long long i = s0; i < n3; i += (long long)gridDim.x * blockDim.x) {
-        F[i] = 0.0;
+        if (F) F[i] = 0.0;
         ub[i] = 0.0;
     }
 }
@@ -791,8 +905,31 @@ hipError_t adj_interp_force(const AdjArgs &A, const double *q, const double *phi
 hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref, const double *phib,
                          const double *gV, const double *acc, double *qb0, double *grads, hipStream_t s)
 {
-    ka_force_jvp<<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, q, inc4, fref, phib, gV, acc, qb0, grads);
+    ka_force_jvp<double><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, q, inc4, fref, phib, gV, acc, qb0, grads);
     return hipGetLastError();
+}
+
+template <typename P>
+static hipError_t reverse_kept(const AdjArgs &A, const AdjLevel &L, const AdjWork &w, hipStream_t s)
+{
+    const long long n = A.g.n;
+    const P *f0 = (const P *)L.f0, *f1 = (const P *)L.f1, *F = (const P *)L.F, *U = (const P *)L.U;
+    const P *phs = (const P *)L.phs, *gvs = (const P *)L.gvs;
+    ka_zero_fields<<<grid_stride_blocks(3 * n), 256, 0, s>>>(nullptr, w.ub, 3 * n, w.acc);
+    ka_spread1<<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, w.ub);
+    ka_moments_adj_u<P><<<blocks_for(n), 256, 0, s>>>(A, f1, U, w.ub, w.lam1);
+    ka_interp_adj_u<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, U, w.qb0);
+    ka_lb_adj<P, P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, w.ub, w.lam1, w.lam0, w.Fb, w.grads);
+    ka_interp_force_s<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, phs, gvs, L.dV, w.Fb, w.phib, w.qb0);
+    ka_volume<<<blocks_for(A.nf), 256, 0, s>>>(A, L.q, L.Xref, L.faces, w.phib, w.acc + 2);
+    ka_force_jvp<P><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, L.q, L.inc4, L.fref, w.phib, gvs, w.acc + 2, w.qb0,
+                                                          w.grads);
+    return hipGetLastError();
+}
+
+hipError_t adj_reverse_kept(const AdjArgs &A, int fp64, const AdjLevel &L, const AdjWork &w, hipStream_t s)
+{
+    return fp64 ? reverse_kept<double>(A, L, w, s) : reverse_kept<float>(A, L, w, s);
 }
 
 }  // namespace iblb

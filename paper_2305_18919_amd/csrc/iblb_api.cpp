@@ -1595,6 +1595,10 @@ struct AdjState {
     double *grads = nullptr;           // [6]
     hipGraph_t graph = nullptr;        // checkpoint mode: recompute and reverse sweep of one full segment
     hipGraphExec_t gexec = nullptr;
+    // every level kept: the forward's own fields of each step (element size es)
+    void *Fs = nullptr, *Us = nullptr;    // [n][3][n_nodes] force density (active tiles), u(t+1)
+    void *phs = nullptr, *gvs = nullptr;  // [n][3][nv] phi_S + phi_W, dV/dq
+    double *dVs = nullptr;                // [n] V - V0
 };
 
 namespace {
@@ -1608,6 +1612,8 @@ void free_adjoint(iblb_ctx *c)
     if (a->graph) (void)hipGraphDestroy(a->graph);
     for (char *p : a->ck) (void)hipFree(p);
     if (a->store) (void)hipFree(a->store);
+    for (void *p : {a->Fs, a->Us, a->phs, a->gvs, (void *)a->dVs})
+        if (p) (void)hipFree(p);
     for (double *p : {a->qs, a->lam_buf[0], a->lam_buf[1], a->qb_buf[0], a->qb_buf[1], a->F, a->Fb, a->ub, a->phi,
                       a->gV, a->phib, a->acc, a->grads})
         if (p) (void)hipFree(p);
@@ -1774,11 +1780,22 @@ int iblb_adjoint_record(iblb_ctx *c, int32_t n_steps, int32_t every)
         // from the device step counter), in replays of one captured graph of
         // kGraphSteps steps from even times and single launches otherwise.
         rc = alloc_sweep(c, a, (size_t)n_steps + 1);
+        if (!rc) {
+            const size_t n = (size_t)c->g.n, nv = (size_t)c->nv, L = (size_t)n_steps;
+            if (hipMalloc(&a->Fs, L * 3 * n * a->es) != hipSuccess || hipMalloc(&a->Us, L * 3 * n * a->es) != hipSuccess ||
+                hipMalloc(&a->phs, L * 3 * nv * a->es) != hipSuccess ||
+                hipMalloc(&a->gvs, L * 3 * nv * a->es) != hipSuccess || hipMalloc(&a->dVs, L * 8) != hipSuccess)
+                rc = fail(c, IBLB_E_DEVICE, "no device memory for the kept fields (record with a checkpoint interval)");
+        }
         const uint32_t t0 = (uint32_t)a->t0, maxl = (uint32_t)n_steps;
+        const uint32_t maxf = (uint32_t)n_steps - 1u;  // field levels: the steps of the window
         hipGraphExec_t gx = nullptr;
         hipGraph_t gr = nullptr;
         auto one = [&](int p) {
             hipError_t e = launch_store_level(c->prec, c->d, c->g, c->nv, p, t0, maxl, a->store, a->qs, c->stream);
+            if (e == hipSuccess)
+                e = launch_store_fields(c->prec, c->d, c->g, c->m, p, t0, maxf, a->Fs, a->Us, a->phs, a->gvs, a->dVs,
+                                        c->stream);
             return e == hipSuccess ? enqueue_step(c, p, false) : e;
         };
         int left = n_steps;
@@ -1805,8 +1822,11 @@ int iblb_adjoint_record(iblb_ctx *c, int32_t n_steps, int32_t every)
             if (e != hipSuccess) rc = hip_fail(c, e, "recording the window");
         }
         if (!rc) {
-            hipError_t e = launch_store_level(c->prec, c->d, c->g, c->nv, (int)(c->t & 1), t0, maxl, a->store, a->qs,
-                                              c->stream);
+            const int p = (int)(c->t & 1);
+            hipError_t e = launch_store_level(c->prec, c->d, c->g, c->nv, p, t0, maxl, a->store, a->qs, c->stream);
+            if (e == hipSuccess)
+                e = launch_store_fields(c->prec, c->d, c->g, c->m, p, t0, maxf, a->Fs, a->Us, a->phs, a->gvs, a->dVs,
+                                        c->stream);
             if (e != hipSuccess) rc = hip_fail(c, e, "storing the last level");
         }
         if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -1859,7 +1879,26 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     HIP_TRY(c, hipMemsetAsync(a->lam[1], 0, 19 * n * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(a->grads, 0, 6 * 8, c->stream));
     if (a->every == 0) {
-        for (int k = a->n - 1; k >= 0; --k) HIP_TRY(c, reverse_step(c, a, A, k));
+        const size_t fl = 3 * n * a->es, vl = 3 * nv * a->es;
+        for (int k = a->n - 1; k >= 0; --k) {
+            AdjLevel L;
+            L.f0 = level(a, n, k);
+            L.f1 = level(a, n, k + 1);
+            L.F = (const char *)a->Fs + (size_t)k * fl;
+            L.U = (const char *)a->Us + (size_t)k * fl;
+            L.phs = (const char *)a->phs + (size_t)k * vl;
+            L.gvs = (const char *)a->gvs + (size_t)k * vl;
+            L.dV = a->dVs + k;
+            L.q = a->qs + (size_t)k * 3 * nv;
+            L.Xref = c->d.Xref;
+            L.faces = c->d.faces;
+            L.inc4 = c->d.inc4;
+            L.fref = c->d.fref;
+            const AdjWork W{a->ub, a->lam[1], a->lam[0], a->Fb, a->phib, a->qb[1], a->qb[0], a->acc, a->grads};
+            HIP_TRY(c, adj_reverse_kept(A, a->es == 8, L, W, c->stream));
+            std::swap(a->lam[0], a->lam[1]);
+            std::swap(a->qb[0], a->qb[1]);
+        }
     } else {
         // Full segments replay one captured graph: with an even checkpoint
         // interval every full segment starts at the parity of t0, and the

@@ -167,6 +167,24 @@ hipError_t adj_lb(const AdjArgs &A, int fp64, const void *f0, const void *f1, co
                   const double *lam1, double *lam0, double *Fb, double *grads, hipStream_t s);
 hipError_t adj_interp_force(const AdjArgs &A, const double *q, const double *phi, const double *Fb, double *phib,
                             double *qb0, hipStream_t s);
+// One reverse step of a window whose every level was kept with its fields
+// (launch_store_level / launch_store_fields): the level's arrays, element type
+// double (fp64 != 0) or float, and the working arrays of the sweep.
+struct AdjLevel {
+    const void *f0, *f1;          // populations of time t and t + 1
+    const void *F, *U;            // force density of step t (zero off its active tiles), u(t+1)
+    const void *phs, *gvs;        // phi_S + phi_W and dV/dq of step t
+    const double *dV;             // V - V0 of step t
+    const double *q;              // positions of time t
+    const double *Xref;
+    const int *faces;
+    const int4 *inc4;
+    const double *fref;
+};
+struct AdjWork {
+    double *ub, *lam1, *lam0, *Fb, *phib, *qb1, *qb0, *acc, *grads;
+};
+hipError_t adj_reverse_kept(const AdjArgs &A, int fp64, const AdjLevel &L, const AdjWork &w, hipStream_t s);
 // grads[0..4] += the alpha_1..3, k_V and eps_lo derivatives of this step
 hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref, const double *phib,
                          const double *gV, const double *acc, double *qb0, double *grads, hipStream_t s);
@@ -178,6 +196,13 @@ hipError_t launch_get_pops_f32(int prec, const Dev &d, const Grid &g, int p, flo
 // (nothing for a level above max_level)
 hipError_t launch_store_level(int prec, const Dev &d, const Grid &g, int nv, int p, uint32_t t0, uint32_t max_level,
                               void *store, double *qs, hipStream_t s);
+// fields of the step just taken (t = ctr[p] - 1) into level t - t0: force
+// density on the step's active tiles (zero elsewhere), u(t+1) there, nodal
+// force parts phi_S + phi_W and dV/dq, and V - V0; stored in the step's
+// arithmetic type (double for FP64 storage, else float)
+hipError_t launch_store_fields(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, uint32_t t0,
+                               uint32_t max_level, void *Fs, void *Us, void *phs, void *gvs, double *dVs,
+                               hipStream_t s);
 hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, int p, const double *in, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Dev &d, const LBArgs &a, int p, double *rho, double *u, hipStream_t s);
 hipError_t launch_get_force(int prec, const Dev &d, const LBArgs &a, int p, double *F, hipStream_t s);

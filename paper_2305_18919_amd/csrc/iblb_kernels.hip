@@ -1367,6 +1367,52 @@ __global__ __launch_bounds__(256) void k_store_positions(const double *__restric
     qs[(size_t)level * 3 * nv + i] = q[i];
 }
 
+// Fields of the step just taken, t = ctr[p] - 1, into level t - t0 of the
+// adjoint's stores (nothing for a level above max_level, which includes the
+// wrapped -1 before the window's first step): the force density on the
+// step's active tiles (stamp == t + 1) and zero elsewhere, u(t+1) as the step
+// left it in U (valid on the active tiles, the only nodes the adjoint reads),
+// the nodal force parts phi_S + phi_W and dV/dq, and V - V0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_store_fields(const T *__restrict__ F, const T *__restrict__ U,
+                                                      const uint32_t *__restrict__ stamp,
+                                                      const uint32_t *__restrict__ ctr, int p, uint32_t t0,
+                                                      uint32_t max_level, T *__restrict__ Fs, T *__restrict__ Us,
+                                                      const T *__restrict__ phiSW, const T *__restrict__ gV,
+                                                      const double *__restrict__ partials, int nparts, int nv,
+                                                      T *__restrict__ phs, T *__restrict__ gvs,
+                                                      double *__restrict__ dVs, Grid g)
+{
+    const uint32_t t1 = ctr[p];
+    const uint32_t level = t1 - 1u - t0;
+    if (level > max_level)
+        return;
+    const long long n = g.n;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), zf = (int)(i / ((long long)g.nx * g.ny));
+        const bool on = stamp[tile_of(g, x, y, zf)] == t1;
+        T *Fo = Fs + (size_t)level * 3 * (size_t)n;
+        T *Uo = Us + (size_t)level * 3 * (size_t)n;
+        for (int c = 0; c < 3; ++c) {
+            Fo[c * n + i] = on ? F[c * n + i] : T(0);
+            Uo[c * n + i] = U[c * n + i];
+        }
+    }
+    if (i < 3ll * nv) {
+        phs[(size_t)level * 3 * nv + i] = phiSW[i];
+        gvs[(size_t)level * 3 * nv + i] = gV[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        double sum = 0.0;
+        for (int k = threadIdx.x; k < nparts; k += 64)
+            sum += partials[k];
+        sum = wave_sum<double>(sum);
+        if (threadIdx.x == 0)
+            dVs[level] = sum;
+    }
+}
+
 template <typename S>
 __global__ __launch_bounds__(256) void k_set_pops(S *__restrict__ f, int p, const double *__restrict__ in, Grid g)
 {
@@ -1781,6 +1827,25 @@ hipError_t launch_store_level(int prec, const Dev &d, const Grid &g, int nv, int
     if (e != hipSuccess)
         return e;
     k_store_positions<<<(3 * nv + 255) / 256, 256, 0, s>>>(d.q, d.ctr, p, t0, max_level, qs, nv);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_fields(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, uint32_t t0,
+                               uint32_t max_level, void *Fs, void *Us, void *phs, void *gvs, double *dVs,
+                               hipStream_t s)
+{
+    const long long work = g.n > 3ll * m.nv ? g.n : 3ll * m.nv;
+    const int blocks = (int)((work + 255) / 256);
+    if (prec == 0)
+        k_store_fields<double><<<blocks, 256, 0, s>>>((const double *)d.F, (const double *)d.U, d.stamp, d.ctr, p, t0,
+                                                      max_level, (double *)Fs, (double *)Us,
+                                                      (const double *)d.phiSW, (const double *)d.gV, d.partials,
+                                                      m.nparts, m.nv, (double *)phs, (double *)gvs, dVs, g);
+    else
+        k_store_fields<float><<<blocks, 256, 0, s>>>((const float *)d.F, (const float *)d.U, d.stamp, d.ctr, p, t0,
+                                                     max_level, (float *)Fs, (float *)Us, (const float *)d.phiSW,
+                                                     (const float *)d.gV, d.partials, m.nparts, m.nv, (float *)phs,
+                                                     (float *)gvs, dVs, g);
     return hipGetLastError();
 }
 
