@@ -455,7 +455,9 @@ __global__ __launch_bounds__(256) void ka_interp_adj(AdjArgs A, const double *__
 //        the force share of the interpolated velocity's adjoint),
 //   d/dtau: sum_i Lam_i [(f_i - f^eq_i) + s_i / 2] / tau^2  with S_i = (1 - 1/(2 tau)) s_i.
 // Lam and the populations are each read twice (the second time from cache)
-// so that the kernel keeps few registers.
+// so that the kernel keeps few registers.  clear_ub != 0: ub is zeroed where
+// it was read (this kernel is its last reader in the step); acc_clear, when
+// given, is zeroed by one thread.
 // element at a 32-bit byte offset from a base pointer (a uniform base and
 // one address register per access)
 template <typename T>
@@ -466,7 +468,8 @@ __device__ __forceinline__ T ld32(const T *base, uint32_t byte_off)
 
 template <typename P, typename FT = double>
 __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict__ f0, const P *__restrict__ f1,
-                                                 const FT *__restrict__ F, const double *__restrict__ ub,
+                                                 const FT *__restrict__ F, double *__restrict__ ub, int clear_ub,
+                                                 double *__restrict__ acc_clear,
                                                  const double *__restrict__ lam1, double *__restrict__ lam0,
                                                  double *__restrict__ Fb, double *grads)
 {
@@ -562,7 +565,14 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
             fb0 += ub0 * h;
             fb1 += ub1 * h;
             fb2 += ub2 * h;
+            if (clear_ub) {  // this thread was its last reader: zero for the next step's spread
+                ub[id] = 0.0;
+                ub[n + id] = 0.0;
+                ub[2 * n + id] = 0.0;
+            }
         }
+        if (acc_clear && id == 0)
+            *acc_clear = 0.0;
         Fb[id] = fb0;
         Fb[n + id] = fb1;
         Fb[2 * n + id] = fb2;
@@ -607,7 +617,7 @@ __global__ __launch_bounds__(256) void ka_interp_force(AdjArgs A, const double *
 }
 
 // qb0_i += (d Phi / d q phib)_i (the directional derivative of the nodal
-// forces along phib, with acc[0] = V - V0 and acc[1] = grad V . phib), and the
+// forces along phib, with dVp[0] = V - V0 and Vdotp[0] = grad V . phib), and the
 // parameter derivatives phib . dPhi/dalpha_m (m = 1..3), phib . dPhi/dk_V,
 // phib . dPhi/deps_lo into grads[0..4].  8 lanes per vertex, one incident
 // face each.
@@ -615,8 +625,8 @@ template <typename G>
 __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__restrict__ q,
                                                     const int4 *__restrict__ inc4, const double *__restrict__ fref,
                                                     const double *__restrict__ phib, const G *__restrict__ gV,
-                                                    const double *__restrict__ acc, double *__restrict__ qb0,
-                                                    double *grads)
+                                                    const double *__restrict__ dVp, const double *__restrict__ Vdotp,
+                                                    double *__restrict__ qb0, double *grads)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int v = t >> 3, lane = t & 7;
@@ -664,7 +674,7 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
         }
         ljz = group8_sum(ljz);
         if (lane == 0) {
-            const double dV = acc[0], Vdot = acc[1];
+            const double dV = dVp[0], Vdot = Vdotp[0];
             const double pbv[3] = {phib[v], phib[nv + v], phib[2 * nv + v]};
             for (int k = 0; k < 3; ++k) {
                 const double gvk = double(gV[k * nv + v]);
@@ -749,43 +759,53 @@ __global__ __launch_bounds__(256) void ka_interp_adj_u(AdjArgs A, const double *
 }
 
 // phib_i = sum_x Fb delta and qb0_i += sum_x (Fb . phi_i) grad_q delta, with
-// phi_i = (phi_S + phi_W)_i - k_V (V - V0) / V0 (dV/dq)_i from the kept parts
+// phi_i = (phi_S + phi_W)_i - k_V (V - V0) / V0 (dV/dq)_i from the kept parts;
+// *vdot += grad V . phib
 template <typename P>
 __global__ __launch_bounds__(256) void ka_interp_force_s(AdjArgs A, const double *__restrict__ q,
                                                          const P *__restrict__ phs, const P *__restrict__ gvs,
                                                          const double *__restrict__ dV, const double *__restrict__ Fb,
-                                                         double *__restrict__ phib, double *__restrict__ qb0)
+                                                         double *__restrict__ phib, double *__restrict__ qb0,
+                                                         double *vdot)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = (int)(t >> 6), k = (int)(t & 63);
-    if (v >= A.nv) return;
     const int nv = A.nv;
     const long long n = A.g.n;
-    const double kf = A.kv_over_V0 * dV[0];
-    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
-    double p[3];
-    for (int c = 0; c < 3; ++c) p[c] = double(phs[c * nv + v]) - kf * double(gvs[c * nv + v]);
-    double pb[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
-    if (finite_pos(qx, qy, qz)) {
-        const Node nd = stencil_node(A, qx, qy, qz, k);
-        if (nd.id >= 0) {
-            const double fb[3] = {Fb[nd.id], Fb[n + nd.id], Fb[2 * n + nd.id]};
-            const double fp = fb[0] * p[0] + fb[1] * p[1] + fb[2] * p[2];
-            for (int c = 0; c < 3; ++c) {
-                pb[c] = fb[c] * nd.w;
-                s[c] = fp * nd.gw[c];
+    double vd[1] = {0.0};
+    if (v < nv) {  // whole wavefronts take the same branch
+        const double kf = A.kv_over_V0 * dV[0];
+        const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+        double p[3], gv[3];
+        for (int c = 0; c < 3; ++c) {
+            gv[c] = double(gvs[c * nv + v]);
+            p[c] = double(phs[c * nv + v]) - kf * gv[c];
+        }
+        double pb[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
+        if (finite_pos(qx, qy, qz)) {
+            const Node nd = stencil_node(A, qx, qy, qz, k);
+            if (nd.id >= 0) {
+                const double fb[3] = {Fb[nd.id], Fb[n + nd.id], Fb[2 * n + nd.id]};
+                const double fp = fb[0] * p[0] + fb[1] * p[1] + fb[2] * p[2];
+                for (int c = 0; c < 3; ++c) {
+                    pb[c] = fb[c] * nd.w;
+                    s[c] = fp * nd.gw[c];
+                }
             }
         }
-    }
-    for (int c = 0; c < 3; ++c) {
-        pb[c] = wave_sum64(pb[c]);
-        s[c] = wave_sum64(s[c]);
-    }
-    if (k == 0)
         for (int c = 0; c < 3; ++c) {
-            phib[c * nv + v] = pb[c];
-            qb0[c * nv + v] += s[c];
+            pb[c] = wave_sum64(pb[c]);
+            s[c] = wave_sum64(s[c]);
         }
+        if (k == 0) {
+            for (int c = 0; c < 3; ++c) {
+                phib[c * nv + v] = pb[c];
+                qb0[c * nv + v] += s[c];
+            }
+            vd[0] = gv[0] * pb[0] + gv[1] * pb[1] + gv[2] * pb[2];
+        }
+    }
+    block_atomic_add<1>(vd, vdot);  // grad V . phib = sum_i (dV/dq)_i . phib_i
 }
 
 // F = ub = 0 over [3][n] each (F may be null), acc[0..3] = 0, in one launch
@@ -883,14 +903,16 @@ hipError_t adj_interp(const AdjArgs &A, int fp64, const double *q, const double 
     return hipGetLastError();
 }
 
-hipError_t adj_lb(const AdjArgs &A, int fp64, const void *f0, const void *f1, const double *F, const double *ub,
+hipError_t adj_lb(const AdjArgs &A, int fp64, const void *f0, const void *f1, const double *F, double *ub,
                   const double *lam1, double *lam0, double *Fb, double *grads, hipStream_t s)
 {
     if (fp64)
-        ka_lb_adj<double><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const double *)f0, (const double *)f1, F, ub, lam1,
+        ka_lb_adj<double><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const double *)f0, (const double *)f1, F, ub, 0,
+                                                              nullptr, lam1,
                                                               lam0, Fb, grads);
     else
-        ka_lb_adj<float><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const float *)f0, (const float *)f1, F, ub, lam1,
+        ka_lb_adj<float><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const float *)f0, (const float *)f1, F, ub, 0,
+                                                             nullptr, lam1,
                                                              lam0, Fb, grads);
     return hipGetLastError();
 }
@@ -905,7 +927,7 @@ hipError_t adj_interp_force(const AdjArgs &A, const double *q, const double *phi
 hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref, const double *phib,
                          const double *gV, const double *acc, double *qb0, double *grads, hipStream_t s)
 {
-    ka_force_jvp<double><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, q, inc4, fref, phib, gV, acc, qb0, grads);
+    ka_force_jvp<double><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, q, inc4, fref, phib, gV, acc, acc + 1, qb0, grads);
     return hipGetLastError();
 }
 
@@ -915,15 +937,16 @@ static hipError_t reverse_kept(const AdjArgs &A, const AdjLevel &L, const AdjWor
     const long long n = A.g.n;
     const P *f0 = (const P *)L.f0, *f1 = (const P *)L.f1, *F = (const P *)L.F, *U = (const P *)L.U;
     const P *phs = (const P *)L.phs, *gvs = (const P *)L.gvs;
-    ka_zero_fields<<<grid_stride_blocks(3 * n), 256, 0, s>>>(nullptr, w.ub, 3 * n, w.acc);
+    // ub starts at zero (cleared by the sweep's caller, then by ka_lb_adj of
+    // every step); acc[3] collects grad V . phib (zeroed by ka_lb_adj)
     ka_spread1<<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, w.ub);
     ka_moments_adj_u<P><<<blocks_for(n), 256, 0, s>>>(A, f1, U, w.ub, w.lam1);
     ka_interp_adj_u<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, U, w.qb0);
-    ka_lb_adj<P, P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, w.ub, w.lam1, w.lam0, w.Fb, w.grads);
-    ka_interp_force_s<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, phs, gvs, L.dV, w.Fb, w.phib, w.qb0);
-    ka_volume<<<blocks_for(A.nf), 256, 0, s>>>(A, L.q, L.Xref, L.faces, w.phib, w.acc + 2);
-    ka_force_jvp<P><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, L.q, L.inc4, L.fref, w.phib, gvs, w.acc + 2, w.qb0,
-                                                          w.grads);
+    ka_lb_adj<P, P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, w.ub, 1, w.acc + 3, w.lam1, w.lam0, w.Fb, w.grads);
+    ka_interp_force_s<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, phs, gvs, L.dV, w.Fb, w.phib, w.qb0,
+                                                                 w.acc + 3);
+    ka_force_jvp<P><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, L.q, L.inc4, L.fref, w.phib, gvs, L.dV, w.acc + 3,
+                                                          w.qb0, w.grads);
     return hipGetLastError();
 }
 

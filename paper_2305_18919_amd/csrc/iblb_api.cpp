@@ -1791,11 +1791,12 @@ int iblb_adjoint_record(iblb_ctx *c, int32_t n_steps, int32_t every)
         const uint32_t maxf = (uint32_t)n_steps - 1u;  // field levels: the steps of the window
         hipGraphExec_t gx = nullptr;
         hipGraph_t gr = nullptr;
+        auto record = [&](int p) {
+            return launch_record(c->prec, c->d, c->g, c->m, p, t0, maxl, maxf, a->store, a->qs, a->Fs, a->Us, a->phs,
+                                 a->gvs, a->dVs, c->stream);
+        };
         auto one = [&](int p) {
-            hipError_t e = launch_store_level(c->prec, c->d, c->g, c->nv, p, t0, maxl, a->store, a->qs, c->stream);
-            if (e == hipSuccess)
-                e = launch_store_fields(c->prec, c->d, c->g, c->m, p, t0, maxf, a->Fs, a->Us, a->phs, a->gvs, a->dVs,
-                                        c->stream);
+            hipError_t e = record(p);
             return e == hipSuccess ? enqueue_step(c, p, false) : e;
         };
         int left = n_steps;
@@ -1822,11 +1823,7 @@ int iblb_adjoint_record(iblb_ctx *c, int32_t n_steps, int32_t every)
             if (e != hipSuccess) rc = hip_fail(c, e, "recording the window");
         }
         if (!rc) {
-            const int p = (int)(c->t & 1);
-            hipError_t e = launch_store_level(c->prec, c->d, c->g, c->nv, p, t0, maxl, a->store, a->qs, c->stream);
-            if (e == hipSuccess)
-                e = launch_store_fields(c->prec, c->d, c->g, c->m, p, t0, maxf, a->Fs, a->Us, a->phs, a->gvs, a->dVs,
-                                        c->stream);
+            hipError_t e = record((int)(c->t & 1));
             if (e != hipSuccess) rc = hip_fail(c, e, "storing the last level");
         }
         if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -1879,6 +1876,9 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     HIP_TRY(c, hipMemsetAsync(a->lam[1], 0, 19 * n * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(a->grads, 0, 6 * 8, c->stream));
     if (a->every == 0) {
+        // the kept-field sweep clears ub and acc itself after this first zeroing
+        HIP_TRY(c, hipMemsetAsync(a->ub, 0, 3 * n * 8, c->stream));
+        HIP_TRY(c, hipMemsetAsync(a->acc, 0, 4 * 8, c->stream));
         const size_t fl = 3 * n * a->es, vl = 3 * nv * a->es;
         for (int k = a->n - 1; k >= 0; --k) {
             AdjLevel L;

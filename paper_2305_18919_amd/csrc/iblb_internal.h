@@ -163,12 +163,12 @@ hipError_t adj_moments(const AdjArgs &A, int fp64, const void *f1, const double 
 hipError_t adj_interp(const AdjArgs &A, int fp64, const double *q, const double *qb1, const void *f1,
                       const double *F, double *qb0, hipStream_t s);
 // lam0 and Fb from lam1; grads[5] += the tau derivative of this step
-hipError_t adj_lb(const AdjArgs &A, int fp64, const void *f0, const void *f1, const double *F, const double *ub,
+hipError_t adj_lb(const AdjArgs &A, int fp64, const void *f0, const void *f1, const double *F, double *ub,
                   const double *lam1, double *lam0, double *Fb, double *grads, hipStream_t s);
 hipError_t adj_interp_force(const AdjArgs &A, const double *q, const double *phi, const double *Fb, double *phib,
                             double *qb0, hipStream_t s);
 // One reverse step of a window whose every level was kept with its fields
-// (launch_store_level / launch_store_fields): the level's arrays, element type
+// (launch_record): the level's arrays, element type
 // double (fp64 != 0) or float, and the working arrays of the sweep.
 struct AdjLevel {
     const void *f0, *f1;          // populations of time t and t + 1
@@ -191,18 +191,17 @@ hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, co
 // debug / query kernels
 hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double *out, hipStream_t s);
 hipError_t launch_get_pops_f32(int prec, const Dev &d, const Grid &g, int p, float *out, hipStream_t s);
-// populations (FP64 storage: double, else float) and positions of the current
-// time into level ctr[p] - t0 of [level][19][n] and [level][3][nv] stores
-// (nothing for a level above max_level)
-hipError_t launch_store_level(int prec, const Dev &d, const Grid &g, int nv, int p, uint32_t t0, uint32_t max_level,
-                              void *store, double *qs, hipStream_t s);
-// fields of the step just taken (t = ctr[p] - 1) into level t - t0: force
-// density on the step's active tiles (zero elsewhere), u(t+1) there, nodal
-// force parts phi_S + phi_W and dV/dq, and V - V0; stored in the step's
-// arithmetic type (double for FP64 storage, else float)
-hipError_t launch_store_fields(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, uint32_t t0,
-                               uint32_t max_level, void *Fs, void *Us, void *phs, void *gvs, double *dVs,
-                               hipStream_t s);
+// One step of an adjoint recording (device step counter t = ctr[p]): the
+// populations (double for FP64 storage, else float) and positions of time t
+// into level t - t0 (at most maxl) of [level][19][n] and [level][3][nv]; the
+// fields of the step just taken into level t - 1 - t0 (at most maxf): force
+// density on its active tiles (zero elsewhere) and u into [level][3][n], the
+// nodal force parts phi_S + phi_W and dV/dq into [level][3][nv], V - V0 into
+// [level].
+hipError_t launch_record(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, uint32_t t0, uint32_t maxl,
+                         uint32_t maxf, void *store, double *qs, void *Fs, void *Us, void *phs, void *gvs,
+                         double *dVs, hipStream_t s);
+
 hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, int p, const double *in, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Dev &d, const LBArgs &a, int p, double *rho, double *u, hipStream_t s);
 hipError_t launch_get_force(int prec, const Dev &d, const LBArgs &a, int p, double *F, hipStream_t s);

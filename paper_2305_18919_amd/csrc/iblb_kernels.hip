@@ -1329,87 +1329,71 @@ __global__ __launch_bounds__(256) void k_get_pops(const S *__restrict__ f, int p
         out[i * g.n + me] = O(d[i]);
 }
 
-// Level ctr[p] - t0 (at most max_level) of a store of time levels
-// [level][19][n]: the populations of the current time in canonical order,
-// converted to O.  The level comes from the device step counter, so that a
-// captured graph of several steps writes a new level at every step.
+// One step of an adjoint recording, from the device step counter t = ctr[p]
+// (so that a captured graph of several steps records a new level at every
+// step):
+//  - level t - t0 (at most maxl) of the time levels: the populations of time
+//    t in canonical order, converted to O, and the positions;
+//  - level t - 1 - t0 (at most maxf; the wrapped -1 before the window's
+//    first step is skipped) of the fields of the step just taken: its force
+//    density on its active tiles (stamp == t) and zero elsewhere, u(t) as it
+//    left it in U (valid on the active tiles, the only nodes the adjoint
+//    reads), the nodal force parts phi_S + phi_W and dV/dq, and V - V0.
+// O is the step's arithmetic type (double for FP64 storage, else float).
 template <typename S, typename O>
-__global__ __launch_bounds__(256) void k_store_level(const S *__restrict__ f, const uint32_t *__restrict__ ctr, int p,
-                                                     uint32_t t0, uint32_t max_level, O *__restrict__ store, Grid g)
+__global__ __launch_bounds__(256) void k_record(const S *__restrict__ f, const O *__restrict__ F,
+                                                const O *__restrict__ U, const uint32_t *__restrict__ stamp,
+                                                const uint32_t *__restrict__ ctr, int p, uint32_t t0, uint32_t maxl,
+                                                uint32_t maxf, O *__restrict__ store, double *__restrict__ qs,
+                                                O *__restrict__ Fs, O *__restrict__ Us, const double *__restrict__ q,
+                                                const O *__restrict__ phiSW, const O *__restrict__ gV,
+                                                const double *__restrict__ partials, int nparts, int nv,
+                                                O *__restrict__ phs, O *__restrict__ gvs, double *__restrict__ dVs,
+                                                Grid g)
 {
     using T = typename Pop<S>::C;
-    const uint32_t level = ctr[p] - t0;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int zf = blockIdx.z;
-    if (level > max_level || x >= g.nx || y >= g.ny)
-        return;
-    T d[19];
-    if (p)
-        load_pops<S, true>(f, g, x, y, zf, d);
-    else
-        load_pops<S, false>(f, g, x, y, zf, d);
-    O *out = store + (size_t)level * 19 * (size_t)g.n;
-    const long long me = nidx(g, x, y, zf);
-    for (int i = 0; i < 19; ++i)
-        out[i * g.n + me] = O(d[i]);
-}
-
-// positions [3][nv] of the current time into level ctr[p] - t0 of [level][3][nv]
-__global__ __launch_bounds__(256) void k_store_positions(const double *__restrict__ q, const uint32_t *__restrict__ ctr,
-                                                         int p, uint32_t t0, uint32_t max_level,
-                                                         double *__restrict__ qs, int nv)
-{
-    const uint32_t level = ctr[p] - t0;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (level > max_level || i >= 3 * nv)
-        return;
-    qs[(size_t)level * 3 * nv + i] = q[i];
-}
-
-// Fields of the step just taken, t = ctr[p] - 1, into level t - t0 of the
-// adjoint's stores (nothing for a level above max_level, which includes the
-// wrapped -1 before the window's first step): the force density on the
-// step's active tiles (stamp == t + 1) and zero elsewhere, u(t+1) as the step
-// left it in U (valid on the active tiles, the only nodes the adjoint reads),
-// the nodal force parts phi_S + phi_W and dV/dq, and V - V0.
-template <typename T>
-__global__ __launch_bounds__(256) void k_store_fields(const T *__restrict__ F, const T *__restrict__ U,
-                                                      const uint32_t *__restrict__ stamp,
-                                                      const uint32_t *__restrict__ ctr, int p, uint32_t t0,
-                                                      uint32_t max_level, T *__restrict__ Fs, T *__restrict__ Us,
-                                                      const T *__restrict__ phiSW, const T *__restrict__ gV,
-                                                      const double *__restrict__ partials, int nparts, int nv,
-                                                      T *__restrict__ phs, T *__restrict__ gvs,
-                                                      double *__restrict__ dVs, Grid g)
-{
-    const uint32_t t1 = ctr[p];
-    const uint32_t level = t1 - 1u - t0;
-    if (level > max_level)
-        return;
+    const uint32_t t = ctr[p];
+    const uint32_t lev = t - t0, levf = t - 1u - t0;
+    const bool rec = lev <= maxl, recf = levf <= maxf;
     const long long n = g.n;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), zf = (int)(i / ((long long)g.nx * g.ny));
-        const bool on = stamp[tile_of(g, x, y, zf)] == t1;
-        T *Fo = Fs + (size_t)level * 3 * (size_t)n;
-        T *Uo = Us + (size_t)level * 3 * (size_t)n;
-        for (int c = 0; c < 3; ++c) {
-            Fo[c * n + i] = on ? F[c * n + i] : T(0);
-            Uo[c * n + i] = U[c * n + i];
+        if (rec) {
+            T d[19];
+            if (p)
+                load_pops<S, true>(f, g, x, y, zf, d);
+            else
+                load_pops<S, false>(f, g, x, y, zf, d);
+            O *out = store + (size_t)lev * 19 * (size_t)n;
+            for (int k = 0; k < 19; ++k)
+                out[k * n + i] = O(d[k]);
+        }
+        if (recf) {
+            const bool on = stamp[tile_of(g, x, y, zf)] == t;
+            O *Fo = Fs + (size_t)levf * 3 * (size_t)n;
+            O *Uo = Us + (size_t)levf * 3 * (size_t)n;
+            for (int c = 0; c < 3; ++c) {
+                Fo[c * n + i] = on ? F[c * n + i] : O(0);
+                Uo[c * n + i] = U[c * n + i];
+            }
         }
     }
     if (i < 3ll * nv) {
-        phs[(size_t)level * 3 * nv + i] = phiSW[i];
-        gvs[(size_t)level * 3 * nv + i] = gV[i];
+        if (rec)
+            qs[(size_t)lev * 3 * nv + i] = q[i];
+        if (recf) {
+            phs[(size_t)levf * 3 * nv + i] = phiSW[i];
+            gvs[(size_t)levf * 3 * nv + i] = gV[i];
+        }
     }
-    if (blockIdx.x == 0 && threadIdx.x < 64) {
+    if (recf && blockIdx.x == 0 && threadIdx.x < 64) {
         double sum = 0.0;
         for (int k = threadIdx.x; k < nparts; k += 64)
             sum += partials[k];
         sum = wave_sum<double>(sum);
         if (threadIdx.x == 0)
-            dVs[level] = sum;
+            dVs[levf] = sum;
     }
 }
 
@@ -1812,41 +1796,19 @@ hipError_t launch_get_pops_f32(int prec, const Dev &d, const Grid &g, int p, flo
     });
 }
 
-hipError_t launch_store_level(int prec, const Dev &d, const Grid &g, int nv, int p, uint32_t t0, uint32_t max_level,
-                              void *store, double *qs, hipStream_t s)
-{
-    hipError_t e = with_pop_type(prec, [&](auto tag) {
-        using S = decltype(tag);
-        if (prec == 0)
-            k_store_level<S, double><<<lb_grid(g), lb_block(g), 0, s>>>((const S *)d.f, d.ctr, p, t0, max_level,
-                                                                       (double *)store, g);
-        else
-            k_store_level<S, float><<<lb_grid(g), lb_block(g), 0, s>>>((const S *)d.f, d.ctr, p, t0, max_level,
-                                                                      (float *)store, g);
-    });
-    if (e != hipSuccess)
-        return e;
-    k_store_positions<<<(3 * nv + 255) / 256, 256, 0, s>>>(d.q, d.ctr, p, t0, max_level, qs, nv);
-    return hipGetLastError();
-}
-
-hipError_t launch_store_fields(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, uint32_t t0,
-                               uint32_t max_level, void *Fs, void *Us, void *phs, void *gvs, double *dVs,
-                               hipStream_t s)
+hipError_t launch_record(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, uint32_t t0, uint32_t maxl,
+                         uint32_t maxf, void *store, double *qs, void *Fs, void *Us, void *phs, void *gvs,
+                         double *dVs, hipStream_t s)
 {
     const long long work = g.n > 3ll * m.nv ? g.n : 3ll * m.nv;
     const int blocks = (int)((work + 255) / 256);
-    if (prec == 0)
-        k_store_fields<double><<<blocks, 256, 0, s>>>((const double *)d.F, (const double *)d.U, d.stamp, d.ctr, p, t0,
-                                                      max_level, (double *)Fs, (double *)Us,
-                                                      (const double *)d.phiSW, (const double *)d.gV, d.partials,
-                                                      m.nparts, m.nv, (double *)phs, (double *)gvs, dVs, g);
-    else
-        k_store_fields<float><<<blocks, 256, 0, s>>>((const float *)d.F, (const float *)d.U, d.stamp, d.ctr, p, t0,
-                                                     max_level, (float *)Fs, (float *)Us, (const float *)d.phiSW,
-                                                     (const float *)d.gV, d.partials, m.nparts, m.nv, (float *)phs,
-                                                     (float *)gvs, dVs, g);
-    return hipGetLastError();
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        using O = typename Pop<S>::C;
+        k_record<S, O><<<blocks, 256, 0, s>>>((const S *)d.f, (const O *)d.F, (const O *)d.U, d.stamp, d.ctr, p, t0,
+                                             maxl, maxf, (O *)store, qs, (O *)Fs, (O *)Us, d.q, (const O *)d.phiSW,
+                                             (const O *)d.gV, d.partials, m.nparts, m.nv, (O *)phs, (O *)gvs, dVs, g);
+    });
 }
 
 hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double *out, hipStream_t s)
