@@ -282,6 +282,60 @@ const char *iblb_batch_last_error(const iblb_batch *b);
 /* Synchronises and frees the batch; the members are untouched. */
 int iblb_batch_destroy(iblb_batch *b);
 
+/* ---- Discrete adjoint of the step (reverse mode)
+ * Gradients of an observable J(q(t0 + n)) of the mesh's final vertex
+ * positions, after n steps from t0, with respect to the mesh parameters of
+ * the nodal forces (alpha_1, alpha_2, alpha_3 of Eq. generalised_energy1, k_V
+ * of Eq. nodal_force_V, eps of the lower wall in Eq. LJ_interaction), the
+ * relaxation time tau of Eq. LBeq and the positions q(t0).  The reverse sweep
+ * takes the transpose of every operation of the step (the algorithm at the end
+ * of the "Numerical implementation" section) in reverse order; the adjoint of
+ * the populations is kept in FP64 arithmetic.  J itself is the caller's: it
+ * passes dJ/dq(t0 + n).  Requires a mesh (IBLB_E_STATE otherwise).
+ *
+ * Steps the context n times (like iblb_step) and records what the reverse
+ * sweep needs:
+ *  every = 0: every time level and the forward's own fields of each step in
+ *    device memory, in the step's arithmetic precision (FP64 for FP64
+ *    storage, FP32 otherwise): per step 25 x N values (populations, force
+ *    density, velocity), 6 x n_vertices values (nodal force parts, dV/dq) and
+ *    3 x n_vertices + 1 doubles (positions, V - V0); the sweep then
+ *    recomputes nothing.  Its adjoint populations are stored in the same
+ *    precision.
+ *  every > 0: a device copy of the whole context state every `every` steps;
+ *    the sweep recomputes each segment of `every` steps (in FP64 from the
+ *    stored levels) before walking it backwards.
+ * Replaces any earlier recording.  The context is left at t0 + n.  Errors:
+ * IBLB_E_INVAL (null context, n < 1, every < 0), IBLB_E_STATE (no mesh),
+ * IBLB_E_DEVICE (the recording does not fit in device memory, or a HIP
+ * error). */
+int iblb_adjoint_record(iblb_ctx *ctx, int32_t n_steps, int32_t every);
+/* Reverse sweep over the recorded window.
+ * dJdq: [n_vertices][3] host doubles, dJ/dq at the window's end (read only).
+ * grads: 6 host doubles written with dJ/d(alpha_1, alpha_2, alpha_3, k_V,
+ *   eps_lo, tau).  dJdq0: NULL or [n_vertices][3] host doubles, written with
+ *   dJ/dq at the window's start.
+ * May be called again (another J over the same window).  The context must not
+ * have been stepped since iblb_adjoint_record (IBLB_E_STATE), and is left at
+ * the window's end.  IBLB_E_INVAL for a null pointer, IBLB_E_STATE with no
+ * recording, IBLB_E_UNSTABLE / IBLB_E_DEVICE from the device. */
+int iblb_adjoint_backward(iblb_ctx *ctx, const double *dJdq, double *grads, double *dJdq0);
+/* Frees the recording (also done by iblb_destroy). */
+int iblb_adjoint_release(iblb_ctx *ctx);
+/* Host-side, FP64: the sphere fit of the contact-angle measurement
+ * (iblb_contact_angle, method 0) and its gradient.  Least-squares sphere
+ * |p|^2 = 2 c.p + k through the vertices at least `exclude` from the wall
+ * plane z = z_wall (wall 0: lower, the droplet above; 1: upper), coordinates
+ * relative to the selected vertices' x-y centroid and to the plane.  Writes
+ * h = height of the fitted sphere's top above the plane (NULL to skip), r2 =
+ * R^2 - c_z^2 (the squared contact radius when positive; NULL to skip) and
+ * their gradients with respect to q (NULL to skip; [nv][3], zero for vertices
+ * left out), differentiating the normal equations.  q: [nv][3] host doubles.
+ * IBLB_E_INVAL for bad arguments, IBLB_E_STATE with fewer than 4 vertices
+ * selected or singular normal equations. */
+int iblb_sphere_fit_grad(int32_t nv, const double *q, int32_t wall, double z_wall, double exclude, double *h,
+                         double *r2, double *dh_dq, double *dr2_dq);
+
 #ifdef __cplusplus
 }
 #endif

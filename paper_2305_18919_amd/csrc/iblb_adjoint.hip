@@ -1,4 +1,4 @@
-// Discrete adjoint of one IB-LB step (reverse mode), FP64.
+// Discrete adjoint of one IB-LB step (reverse mode), in FP64 arithmetic.
 //
 // The forward step maps (f(t), q(t)) to (f(t+1), q(t+1)):
 //   phi = Phi(q)                              nodal forces (Eqs. generalised_energy1,
@@ -25,9 +25,10 @@
 // symmetric and its transpose product is the directional derivative of Phi
 // along phib, computed with dual numbers.  With every time level kept, the
 // forward's own force density, u(t+1) and nodal force parts of each step are
-// read back (ka_*_u, ka_interp_force_s, reverse_kept); with checkpoints, the
-// forward quantities (phi, F, rho, u, u') are recomputed in FP64 from the
-// stored populations and positions of each time level.
+// read back (ka_*_u, ka_interp_force_s, reverse_kept), and the adjoint lam
+// is stored in the step's own precision (FP32 for an FP32 step); with
+// checkpoints, the forward quantities (phi, F, rho, u, u') are recomputed in
+// FP64 from the stored populations and positions of each time level.
 #include "iblb_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -50,6 +51,8 @@ __device__ __forceinline__ int oppq(int i) { return i == 0 ? 0 : ((i & 1) ? i + 
 
 __device__ __forceinline__ int wrapn(int a, int n)
 {
+    if ((unsigned)a < (unsigned)n)  // the usual case: no division
+        return a;
     int r = a % n;
     return r < 0 ? r + n : r;
 }
@@ -196,19 +199,27 @@ struct Node {
     double w, gw[3];
 };
 
+// Called by all 64 lanes of a wavefront for one vertex, k = the lane: the 12
+// one-dimensional weights and derivatives (axis l / 4, offset l % 4) are
+// evaluated once, by lanes l < 12, and every lane takes its three by shuffle.
 __device__ __forceinline__ Node stencil_node(const AdjArgs &A, double qx, double qy, double qz, int k)
 {
     const Grid &g = A.g;
     const int bx = (int)floor(qx) - 1, by = (int)floor(qy) - 1, bz = (int)floor(qz) - 1;
     const int nxk = bx + (k & 3), nyk = by + ((k >> 2) & 3), nzk = bz + (k >> 4);
-    const double rx = nxk - qx, ry = nyk - qy, rz = nzk - qz;
-    const double px = phi4d(rx), py = phi4d(ry), pz = phi4d(rz);
+    const int ax = k >> 2, off = k & 3;
+    const double r = k < 12 ? double((ax == 0 ? bx : (ax == 1 ? by : bz)) + off) - (ax == 0 ? qx : (ax == 1 ? qy : qz))
+                            : 0.0;
+    const double w1 = phi4d(r), d1 = dphi4d(r);
+    const int lx = k & 3, ly = 4 + ((k >> 2) & 3), lz = 8 + (k >> 4);
+    const double px = __shfl(w1, lx, 64), py = __shfl(w1, ly, 64), pz = __shfl(w1, lz, 64);
+    const double dx = __shfl(d1, lx, 64), dy = __shfl(d1, ly, 64), dz = __shfl(d1, lz, 64);
     Node nd;
     nd.w = px * py * pz;
     // d/dq of phi4(node - q) = -phi4'(node - q)
-    nd.gw[0] = -dphi4d(rx) * py * pz;
-    nd.gw[1] = -px * dphi4d(ry) * pz;
-    nd.gw[2] = -px * py * dphi4d(rz);
+    nd.gw[0] = -dx * py * pz;
+    nd.gw[1] = -px * dy * pz;
+    nd.gw[2] = -px * py * dz;
     nd.side = 0;
     int zf;
     if (g.walls) {
@@ -466,30 +477,56 @@ __device__ __forceinline__ T ld32(const T *base, uint32_t byte_off)
     return *(const T *)((const char *)base + byte_off);
 }
 
-template <typename P, typename FT = double>
+template <typename P, typename FT = double, typename LT = double>
 __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict__ f0, const P *__restrict__ f1,
                                                  const FT *__restrict__ F, double *__restrict__ ub, int clear_ub,
                                                  double *__restrict__ acc_clear,
-                                                 const double *__restrict__ lam1, double *__restrict__ lam0,
+                                                 const LT *__restrict__ lam1, LT *__restrict__ lam0,
                                                  double *__restrict__ Fb, double *grads)
 {
     const Grid &g = A.g;
     const long long n = g.n;
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ LT Ls[19][256];
     double tb[1] = {0.0};
     if (id < n) {
-        const int x = (int)(id % g.nx), y = (int)((id / g.nx) % g.ny), zf = (int)(id / ((long long)g.nx * g.ny));
+        // node coordinates and the row/plane offsets of its neighbours (no
+        // division per link): index 0, 1, 2 for the offsets -1, 0, +1
+        const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny, nxy = nx * ny, uid = (uint32_t)id;
+        const uint32_t row = uid / nx, x = uid - row * nx, zf = row / ny, y = row - zf * ny;
+        const uint32_t xo[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+        const uint32_t yo[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y == ny - 1 ? 0 : y + 1) * nx};
+        const uint32_t nzf = (uint32_t)g.nzf;
+        const uint32_t zo[3] = {(zf == 0 ? nzf - 1 : zf - 1) * nxy, zf * nxy, (zf == nzf - 1 ? 0 : zf + 1) * nxy};
+        // a link whose source lies in a solid wall layer bounces back at x
+        const bool wlo = g.walls && zf == 0, whi = g.walls && zf == nzf - 1;
         // byte offsets of this node in a [19][n] array of P and of doubles
-        const uint32_t oP = (uint32_t)id * (uint32_t)sizeof(P), oD = (uint32_t)id * 8u;
+        const uint32_t oP = uid * (uint32_t)sizeof(P), oL = uid * (uint32_t)sizeof(LT);
+        // the node's populations and Lam_i, the adjoint of post-collision
+        // population i at x, gathered before any is used (all loads in
+        // flight together); the populations stay in registers, Lam goes to
+        // this thread's LDS slots, which the two passes below read
+        P fv[19];
+        LT lt[19];
+#pragma unroll
+        for (int i = 0; i < 19; ++i) fv[i] = ld32(f0 + (size_t)i * n, oP);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const bool wall = (kCz[i] < 0 && wlo) || (kCz[i] > 0 && whi);
+            const uint32_t to = zo[kCz[i] + 1] + yo[kCy[i] + 1] + xo[kCx[i] + 1];
+            lt[i] = wall ? ld32(lam1 + (size_t)oppq(i) * n, oL) : ld32(lam1 + (size_t)i * n, to * (uint32_t)sizeof(LT));
+        }
         double dr = 0.0, m[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            const double d = double(ld32(f0 + (size_t)i * n, oP));
+            const double d = double(fv[i]);
             dr += d;
             m[0] += kCx[i] * d;
             m[1] += kCy[i] * d;
             m[2] += kCz[i] * d;
         }
+#pragma unroll
+        for (int i = 0; i < 19; ++i) Ls[i][threadIdx.x] = lt[i];
         const double rho = A.rho0 + dr;
         const uint32_t oF = (uint32_t)id * (uint32_t)sizeof(FT);
         const double Fx = double(ld32(F, oF)) + A.body[0], Fy = double(ld32(F + n, oF)) + A.body[1],
@@ -499,26 +536,18 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
         const double uF = u0 * Fx + u1 * Fy + u2 * Fz;
         const double om = A.omega, guo = 1.0 - 0.5 * om;
         double a = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0, tt = 0.0;
-        const int zt = zf + (g.walls ? 1 : 0);
-        // Lam_i, the adjoint of post-collision population i at x; wall links
-        // also add their moving-wall term to the density adjoint
-        // (the accumulation unrolled by two only, to keep the registers of a
-        // few directions live at a time)
+        // first pass: the density, velocity and force adjoints (unrolled by
+        // two only, to keep the registers of a few directions live at a
+        // time); wall links also add their moving-wall term to the density
+        // adjoint
 #pragma unroll 2
         for (int i = 0; i < 19; ++i) {
             const int cx = cCx[i], cy = cCy[i], cz = cCz[i];
-            const int tz = zt + cz;
             const double w = wq(i);
-            double L;
-            if (g.walls && (tz < 1 || tz > g.nz - 2)) {
-                L = ld32(lam1 + (size_t)oppq(i) * n, oD);
-                const double uwx = tz < 1 ? A.ulo[0] : A.uhi[0], uwy = tz < 1 ? A.ulo[1] : A.uhi[1];
+            const double L = double(Ls[i][threadIdx.x]);
+            if ((cz < 0 && wlo) || (cz > 0 && whi)) {
+                const double uwx = cz < 0 ? A.ulo[0] : A.uhi[0], uwy = cz < 0 ? A.ulo[1] : A.uhi[1];
                 a += -6.0 * w * (cx * uwx + cy * uwy) * L;  // wall velocities are tangential
-            } else {
-                const int tzf = g.walls ? tz - 1 : wrapn(tz, g.nz);
-                const uint32_t to = ((uint32_t)tzf * (uint32_t)g.ny + (uint32_t)wrapn(y + cy, g.ny)) * (uint32_t)g.nx +
-                                    (uint32_t)wrapn(x + cx, g.nx);
-                L = ld32(lam1 + (size_t)i * n, to * 8u);
             }
             const double cu = cx * u0 + cy * u1 + cz * u2;
             const double cF = cx * Fx + cy * Fy + cz * Fz;
@@ -534,27 +563,23 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
             g0 += Lg * (3.0 * (cx - u0) + 9.0 * cu * cx);
             g1 += Lg * (3.0 * (cy - u1) + 9.0 * cu * cy);
             g2 += Lg * (3.0 * (cz - u2) + 9.0 * cu * cz);
-            tt += L * om * om * ((double(ld32(f0 + (size_t)i * n, oP)) - deq) + 0.5 * si);
         }
-        tb[0] = tt;
+        // second pass: lam(t) and the tau derivative
         const double ir = 1.0 / rho;
-        // second pass: Lam gathered again (cache-resident) rather than held in registers
 #pragma unroll
         for (int j = 0; j < 19; ++j) {
-            const int cx = cCx[j], cy = cCy[j], cz = cCz[j];
-            const int tz = zt + cz;
-            double L;
-            if (g.walls && (tz < 1 || tz > g.nz - 2)) {
-                L = ld32(lam1 + (size_t)oppq(j) * n, oD);
-            } else {
-                const int tzf = g.walls ? tz - 1 : wrapn(tz, g.nz);
-                const uint32_t to = ((uint32_t)tzf * (uint32_t)g.ny + (uint32_t)wrapn(y + cy, g.ny)) * (uint32_t)g.nx +
-                                    (uint32_t)wrapn(x + cx, g.nx);
-                L = ld32(lam1 + (size_t)j * n, to * 8u);
-            }
-            *(double *)((char *)(lam0 + (size_t)j * n) + oD) =
-                (1.0 - om) * L + a + (b0 * (cx - u0) + b1 * (cy - u1) + b2 * (cz - u2)) * ir;
+            const int cx = kCx[j], cy = kCy[j], cz = kCz[j];
+            const double w = wq(j);
+            const double L = double(Ls[j][threadIdx.x]);
+            *(LT *)((char *)(lam0 + (size_t)j * n) + oL) =
+                LT((1.0 - om) * L + a + (b0 * (cx - u0) + b1 * (cy - u1) + b2 * (cz - u2)) * ir);
+            const double cu = cx * u0 + cy * u1 + cz * u2;
+            const double cF = cx * Fx + cy * Fy + cz * Fz;
+            const double deq = w * dr + w * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+            const double si = w * (3.0 * (cF - uF) + 9.0 * cF * cu);
+            tt += L * om * om * ((double(fv[j]) - deq) + 0.5 * si);
         }
+        tb[0] = tt;
         double fb0 = g0 + 0.5 * b0 * ir, fb1 = g1 + 0.5 * b1 * ir, fb2 = g2 + 0.5 * b2 * ir;
         const double ub0 = ub[id], ub1 = ub[n + id], ub2 = ub[2 * n + id];
         if (ub0 != 0.0 || ub1 != 0.0 || ub2 != 0.0) {
@@ -692,26 +717,10 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
 // the force density F, u(t+1) in U, the nodal force parts and V - V0 of each
 // step come from the forward itself (element type P), so nothing is recomputed
 
-// ub(x) += sum_i delta(x - q_i) qb_i over the fluid nodes
-__global__ __launch_bounds__(256) void ka_spread1(AdjArgs A, const double *__restrict__ q,
-                                                  const double *__restrict__ qb, double *ub)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = (int)(t >> 6), k = (int)(t & 63);
-    if (v >= A.nv) return;
-    const int nv = A.nv;
-    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
-    if (!finite_pos(qx, qy, qz)) return;
-    const Node nd = stencil_node(A, qx, qy, qz, k);
-    if (nd.id < 0 || nd.w == 0.0) return;
-    const long long n = A.g.n;
-    for (int c = 0; c < 3; ++c) atomicAdd(ub + c * n + nd.id, qb[c * nv + v] * nd.w);
-}
-
 // lam_j += (c_j - u') . ub / rho1 where ub != 0, u' from U, rho1 from f1
 template <typename P>
 __global__ __launch_bounds__(256) void ka_moments_adj_u(AdjArgs A, const P *__restrict__ f1, const P *__restrict__ U,
-                                                        const double *__restrict__ ub, double *__restrict__ lam)
+                                                        const double *__restrict__ ub, P *__restrict__ lam)
 {
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = A.g.n;
@@ -721,22 +730,25 @@ __global__ __launch_bounds__(256) void ka_moments_adj_u(AdjArgs A, const P *__re
     double dr = 0.0;
 #pragma unroll
     for (int i = 0; i < 19; ++i) dr += double(f1[i * n + id]);
-    const double rho = A.rho0 + dr;
+    const double ir = 1.0 / (A.rho0 + dr);
     const double ub_u = b[0] * double(U[id]) + b[1] * double(U[n + id]) + b[2] * double(U[2 * n + id]);
 #pragma unroll
     for (int j = 0; j < 19; ++j)
-        lam[j * n + id] += (kCx[j] * b[0] + kCy[j] * b[1] + kCz[j] * b[2] - ub_u) / rho;
+        lam[j * n + id] = P(double(lam[j * n + id]) + (kCx[j] * b[0] + kCy[j] * b[1] + kCz[j] * b[2] - ub_u) * ir);
 }
 
-// qb0_i = qb1_i + sum_x (u'(x) . qb1_i) grad_q delta(x - q_i), u' from U
+// One lane per (vertex, stencil node), both adjoints that start from qb1:
+//   ub(x) += sum_i delta(x - q_i) qb1_i over the fluid nodes (the adjoint of u'),
+//   qb0_i = qb1_i + sum_x (u'(x) . qb1_i) grad_q delta(x - q_i), u' from U
+//   (the wall velocity at a wall node).
 template <typename P>
-__global__ __launch_bounds__(256) void ka_interp_adj_u(AdjArgs A, const double *__restrict__ q,
-                                                       const double *__restrict__ qb1, const P *__restrict__ U,
-                                                       double *__restrict__ qb0)
+__global__ __launch_bounds__(256) void ka_spread_interp_u(AdjArgs A, const double *__restrict__ q,
+                                                          const double *__restrict__ qb1, const P *__restrict__ U,
+                                                          double *ub, double *__restrict__ qb0)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = (int)(t >> 6), k = (int)(t & 63);
-    if (v >= A.nv) return;
+    if (v >= A.nv) return;  // whole wavefronts take the same branch
     const int nv = A.nv;
     const long long n = A.g.n;
     const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
@@ -747,6 +759,8 @@ __global__ __launch_bounds__(256) void ka_interp_adj_u(AdjArgs A, const double *
         double u[3];
         if (nd.id >= 0) {
             for (int c = 0; c < 3; ++c) u[c] = double(U[c * n + nd.id]);
+            if (nd.w != 0.0)
+                for (int c = 0; c < 3; ++c) atomicAdd(ub + c * n + nd.id, b[c] * nd.w);
         } else {
             for (int c = 0; c < 3; ++c) u[c] = nd.side ? A.uhi[c] : A.ulo[c];
         }
@@ -939,10 +953,10 @@ static hipError_t reverse_kept(const AdjArgs &A, const AdjLevel &L, const AdjWor
     const P *phs = (const P *)L.phs, *gvs = (const P *)L.gvs;
     // ub starts at zero (cleared by the sweep's caller, then by ka_lb_adj of
     // every step); acc[3] collects grad V . phib (zeroed by ka_lb_adj)
-    ka_spread1<<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, w.ub);
-    ka_moments_adj_u<P><<<blocks_for(n), 256, 0, s>>>(A, f1, U, w.ub, w.lam1);
-    ka_interp_adj_u<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, U, w.qb0);
-    ka_lb_adj<P, P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, w.ub, 1, w.acc + 3, w.lam1, w.lam0, w.Fb, w.grads);
+    ka_spread_interp_u<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, U, w.ub, w.qb0);
+    ka_moments_adj_u<P><<<blocks_for(n), 256, 0, s>>>(A, f1, U, w.ub, (P *)w.lam1);
+    ka_lb_adj<P, P, P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, w.ub, 1, w.acc + 3, (const P *)w.lam1, (P *)w.lam0,
+                                                     w.Fb, w.grads);
     ka_interp_force_s<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, phs, gvs, L.dV, w.Fb, w.phib, w.qb0,
                                                                  w.acc + 3);
     ka_force_jvp<P><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, L.q, L.inc4, L.fref, w.phib, gvs, L.dV, w.acc + 3,

@@ -133,9 +133,10 @@ hipError_t launch_batch(int prec, int which, const DomRec *recs, const uint32_t 
                         hipStream_t s);
 // err[k] = *recs[k].d.err for k < n
 hipError_t launch_batch_errors(const DomRec *recs, int n, int *err, hipStream_t s);
-// Discrete adjoint of the step (iblb_adjoint.hip), FP64 throughout: the
+// Discrete adjoint of the step (iblb_adjoint.hip), FP64 arithmetic: the
 // constants of one context's step.  Fields are canonical [19][n] / [3][n]
-// FP64 arrays (deviations f - w rho0), vertex arrays SoA [3][nv].
+// arrays (deviations f - w rho0; FP64, or the step's own precision where a
+// kernel says so), vertex arrays SoA [3][nv].
 struct AdjArgs {
     Grid g;
     int nv, nf, slots;

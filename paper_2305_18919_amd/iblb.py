@@ -352,7 +352,9 @@ class Simulation:
 
     # -- adjoint
     def adjoint_record(self, n: int, every: int = 100):
-        """Step n times keeping device checkpoints every `every` steps."""
+        """Step n times recording the window for adjoint_backward: every time
+        level and the step's own fields in device memory (every = 0), or a
+        device checkpoint every `every` steps that the sweep recomputes from."""
         self._check(lib().iblb_adjoint_record(self.h, int(n), int(every)))
 
     def adjoint_backward(self, dJdq: np.ndarray):
