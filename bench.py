@@ -289,22 +289,27 @@ def batch_study(steps: int, warmup: int):
 
 
 def wetting_study(steps: int):
-    """Equilibrium contact angle against eps/abar for the three pre-stressed
-    models of Table 1 (pure, softly and rigidly coated droplet): 64x64x48,
-    R = 12 at level 4, abar = 1e-3 (inertial-capillary time sqrt(R^3/abar) =
-    1314 steps), eps/abar in {0.05, 1, 3, 5, 7}, all 15 runs in one batch.
+    """Equilibrium contact angle against eps/abar for the five models of
+    Table 1: the pre-stressed pure, softly and rigidly coated droplets at
+    eps/abar in {0.05, 1, 3, 5, 7}, and the non-pre-stressed pure elastic and
+    non-pre-stressed capsules at eps/abar in {0.05, 0.5, 1, 1.5, 2} (they
+    stay stable over a narrower range); 64x64x48, R = 12 at level 4, abar =
+    1e-3 (inertial-capillary time sqrt(R^3/abar) = 1314 steps), all 25 runs
+    in one batch.
     theta from the sphere fit is sampled 10 times; the paper's fit of Eq.
     cos_theta_prediction with its Table 1 constants (other R and mesh) is
     listed beside it."""
     import math
     from paper_2305_18919_amd import iblb
     from paper_2305_18919_amd import inputs as I
-    fits = {"pure droplet": ((1.0, 0.0, 0.0), (0.78, 0.42, 0.0, 1.0)),
-            "softly coated": ((1.0, 0.0, 1.0), (0.87, 0.5, 0.0, 1.0)),
-            "rigidly coated": ((1.0, 1.0, 1.0), (0.91, 0.55, 0.0, 1.0))}
-    ratios = (0.05, 1.0, 3.0, 5.0, 7.0)
+    pre, non = (0.05, 1.0, 3.0, 5.0, 7.0), (0.05, 0.5, 1.0, 1.5, 2.0)
+    fits = {"pure droplet": ((1.0, 0.0, 0.0), (0.78, 0.42, 0.0, 1.0), pre),
+            "softly coated": ((1.0, 0.0, 1.0), (0.87, 0.5, 0.0, 1.0), pre),
+            "rigidly coated": ((1.0, 1.0, 1.0), (0.91, 0.55, 0.0, 1.0), pre),
+            "pure elastic capsule": ((0.0, 0.0, 1.0), (0.71, 2.0, 0.2, 0.75), non),
+            "non-pre-stressed capsule": ((0.0, 1.0, 1.0), (0.7, 1.6, 0.2, 0.75), non)}
     cases, sims = [], []
-    for name, (model, _) in fits.items():
+    for name, (model, _, ratios) in fits.items():
         for r in ratios:
             w = I.wetting_case(model, r)
             cases.append((name, r))
@@ -328,6 +333,90 @@ def wetting_study(steps: int):
         out["cases"].append({"model": name, "eps_over_abar": r, "status": status[k],
                              "theta_deg": trace[k][-1] if trace[k] else None, "theta_trace": trace[k],
                              "paper_fit_theta_deg": round(math.degrees(math.acos(cos_fit)), 1)})
+    for s in sims:
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
+def precision64_study(steps: int):
+    """Equilibrium contact angle per population storage near equilibrium: the
+    softly coated droplet abar(1,0,1) of the 64x64x48 wetting case (R = 12,
+    abar = 1e-3) at eps/abar = 0.05, 1 and 7, `steps` steps in FP64, FP32,
+    FP16 and BF16 storage (one batch of the three runs per storage), then the
+    sphere fit of the lower contact angle and its difference from FP64."""
+    from paper_2305_18919_amd import iblb
+    from paper_2305_18919_amd import inputs as I
+    ratios = (0.05, 1.0, 7.0)
+    out = {"study": "contact angle vs population storage", "workload": "wetting64x48", "steps": steps,
+           "model": "softly coated abar(1,0,1)", "abar": 1e-3, "R": 12.0,
+           "fit": "sphere fit (method 0) of the vertices >= 2 above the lower wall plane", "cases": []}
+    res = {}
+    ws = [I.wetting_case((1.0, 0.0, 1.0), r) for r in ratios]
+    for name in ("fp64", "fp32", "fp16", "bf16"):
+        sims = [iblb.Simulation(w.domain, w.mesh, precision=PRECISIONS[name], graph=True) for w in ws]
+        with iblb.Batch(sims) as b:
+            b.step(steps)
+            status = b.check()
+        for k, r in enumerate(ratios):
+            if status[k] == iblb.IBLB_OK:
+                th, cr, h = sims[k].contact_angle(0)
+                V, _ = sims[k].volume()
+                res[(name, r)] = {"theta_deg": th, "contact_radius": cr, "height": h, "volume": V}
+            else:
+                res[(name, r)] = {"status": int(status[k])}
+        for s in sims:
+            s.close()
+    for r in ratios:
+        case = {"eps_over_abar": r}
+        for name in ("fp64", "fp32", "fp16", "bf16"):
+            case[name] = res[(name, r)]
+            if name != "fp64" and "theta_deg" in case[name] and "theta_deg" in case["fp64"]:
+                case[name]["dtheta_deg"] = case[name]["theta_deg"] - case["fp64"]["theta_deg"]
+                case[name]["dheight"] = case[name]["height"] - case["fp64"]["height"]
+        out["cases"].append(case)
+    print(json.dumps(out), flush=True)
+
+
+def spreading_study(steps: int):
+    """Spreading of a pure droplet abar(1,0,0) on the wetting wall (Eq.
+    tanner_law): the 64x64x48 wetting case (R = 12, abar = 1e-3, t* =
+    sqrt(R^3/abar) = 1314 steps) at eps/abar = 1, 3, 5 and 7 in one FP32
+    batch.  The contact radius r (the equivalent radius of the faces within
+    one lattice unit of the wall plane) is sampled at log-spaced times up to
+    `steps`; delta and C of r/R = C (t/t*)^delta are fitted over t/t* >= 0.2
+    up to the time r first reaches 90 % of its largest value."""
+    import math
+    import numpy as np
+    from paper_2305_18919_amd import iblb
+    from paper_2305_18919_amd import inputs as I
+    from paper_2305_18919_amd.analysis import contact_patch_radius, power_law_fit
+    ratios = (1.0, 3.0, 5.0, 7.0)
+    abar, R = 1e-3, 12.0
+    t_star = math.sqrt(R ** 3 / abar)
+    ws = [I.wetting_case((1.0, 0.0, 0.0), r, abar=abar) for r in ratios]
+    sims = [iblb.Simulation(w.domain, w.mesh, precision=1, graph=True) for w in ws]
+    times = sorted({int(round(x / 16.0)) * 16 for x in np.geomspace(16, steps, 48)} - {0})
+    z_wall = ws[0].domain.z_lo
+    r_t = [[] for _ in ratios]
+    with iblb.Batch(sims) as b:
+        t = 0
+        for tn in times:
+            b.step(tn - t)
+            t = tn
+            status = b.check()
+            for k, s in enumerate(sims):
+                r_t[k].append(contact_patch_radius(s.vertices(), ws[k].mesh.faces, z_wall)
+                              if status[k] == iblb.IBLB_OK else float("nan"))
+        theta = [s.contact_angle(0)[0] if status[k] == iblb.IBLB_OK else None for k, s in enumerate(sims)]
+    out = {"study": "spreading law", "workload": "wetting64x48", "model": "pure droplet abar(1,0,0)",
+           "R": R, "abar": abar, "t_star": t_star, "steps": times[-1], "t": times, "cases": []}
+    for k, r in enumerate(ratios):
+        rr = np.array(r_t[k])
+        case = {"eps_over_abar": r, "status": int(status[k]), "theta_final_deg": theta[k],
+                "r_over_R": [round(v / R, 5) for v in rr]}
+        if status[k] == iblb.IBLB_OK:
+            case.update(power_law_fit(np.array(times, dtype=float), rr, R, t_star))
+        out["cases"].append(case)
     for s in sims:
         s.close()
     print(json.dumps(out), flush=True)
@@ -442,16 +531,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pass", dest="only", choices=["lb", "copy"], default=None)
     ap.add_argument("--copy-mib", type=int, default=256)
-    ap.add_argument("--study", choices=["precision", "shear", "batch", "adjoint", "wetting"], default=None,
-                    help="precision: contact angle of the wetting droplet per population storage; "
-                         "shear: steady D and Theta against the small-Ca theory")
+    ap.add_argument("--study", choices=["precision", "precision64", "shear", "batch", "adjoint", "wetting",
+                                        "spreading"], default=None,
+                    help="precision: contact angle of the 128x128x96 wetting droplet per population storage; "
+                         "precision64: the same on the 64x64x48 wetting case, near equilibrium; "
+                         "shear: steady D and Theta against the small-Ca theory; "
+                         "wetting: equilibrium contact angle against eps/abar for the five models; "
+                         "spreading: contact radius against time (Eq. tanner_law)")
     ap.add_argument("--study-steps", type=int, default=50000)
     ap.add_argument("--precision", choices=sorted(PRECISIONS), default=None,
                     help="population storage (default: the workload's, FP32 for shear64)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
-                                   "this build (see the sharding notes in the design document)"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the library has no multi-GPU path"}))
         raise SystemExit(2)
 
     import torch
@@ -471,6 +563,12 @@ def main():
         return
     if args.study == "wetting":
         wetting_study(args.study_steps)
+        return
+    if args.study == "precision64":
+        precision64_study(args.study_steps)
+        return
+    if args.study == "spreading":
+        spreading_study(args.study_steps)
         return
     w, prec = workload(args.workload)
     if args.precision is not None:
