@@ -552,8 +552,6 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
             const double cu = cx * u0 + cy * u1 + cz * u2;
             const double cF = cx * Fx + cy * Fy + cz * Fz;
             const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
-            const double deq = w * dr + w * rho * poly;
-            const double si = w * (3.0 * (cF - uF) + 9.0 * cF * cu);
             // f*_i = d_i - om (d_i - deq_i) + guo s_i
             a += L * om * w * (1.0 + poly);
             const double Lr = L * om * w * rho, Lg = L * guo * w;

@@ -1631,15 +1631,18 @@ hipError_t launch_init(int prec, const Dev &d, const LBArgs &a, int couette, hip
     });
 }
 
-// The LB-only kernel runs 1024-thread blocks (the x-width of lb_block, 1024 /
-// width rows): on the 128x128x96 lattice 64x16 blocks took 33.2 us per
-// launch against 33.3 (64x8) and 34.0 (64x4); x-widths below a 64-node row
-// were 13 % slower (measured on MI355X, FP32).
+// The LB-only kernel runs 1024-thread blocks, 128 nodes wide where the rows
+// are that long (else the x-width of lb_block), 1024 / width rows.  Measured
+// on MI355X, FP32, us per launch: on the 128x128x96 lattice 64x16 blocks took
+// 33.2 against 33.3 (64x8) and 34.0 (64x4), and 128x8 blocks 32.6; x-widths
+// below a 64-node row were 13 % slower.  128-wide blocks also gave 485 us
+// against 576 (64-wide) and 497 (256-wide) on 512x256x128, 507 against 530
+// on 250^3, and 647 against 640 on 256^3.
 template <typename S, bool ODD>
 static void lb_launch(const Dev &d, const LBArgs &a, bool bulk, hipStream_t s)
 {
     using T = typename Pop<S>::C;
-    const int bx = (int)lb_block(a.g).x, by = 1024 / bx;
+    const int bx = a.g.nx >= 128 ? 128 : (int)lb_block(a.g).x, by = 1024 / bx;
     const dim3 blk(bx, by, 1), grd((a.g.nx + bx - 1) / bx, (a.g.ny + by - 1) / by, a.g.nzf);
     k_lb<S, ODD><<<grd, blk, 0, s>>>((S *)d.f, (const T *)d.Fext, bulk ? d.act : nullptr, d.ctr, d.err, a);
 }
