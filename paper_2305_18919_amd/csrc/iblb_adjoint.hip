@@ -289,6 +289,23 @@ __device__ __forceinline__ void block_atomic_add(double (&v)[K], double *out)
     }
 }
 
+// Sums of the block (256 threads) into thread 0's v[]: for partial sums kept
+// per block, which avoid many blocks' atomics on one address
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K])
+{
+    __shared__ double red[K][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double s = wave_sum64(v[k]);
+        if (lane == 0) red[k][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < K; ++k) v[k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+}
+
 // ---------------------------------------------------------------- kernels
 // acc[0] += sum_j (V_j - V0_j) (displacement expansion of the triple
 // product, as the forward computes it), acc[1] += sum_j grad V_j . dir
@@ -467,8 +484,9 @@ __global__ __launch_bounds__(256) void ka_interp_adj(AdjArgs A, const double *__
 //   d/dtau: sum_i Lam_i [(f_i - f^eq_i) + s_i / 2] / tau^2  with S_i = (1 - 1/(2 tau)) s_i.
 // Lam and the populations are each read twice (the second time from cache)
 // so that the kernel keeps few registers.  clear_ub != 0: ub is zeroed where
-// it was read (this kernel is its last reader in the step); acc_clear, when
-// given, is zeroed by one thread.
+// it was read (this kernel is its last reader in the step).  The tau
+// derivative goes to grads[5], or with tslot to tslot[block] (a running sum
+// per block that the caller adds up at the end of the sweep).
 // element at a 32-bit byte offset from a base pointer (a uniform base and
 // one address register per access)
 template <typename T>
@@ -480,7 +498,7 @@ __device__ __forceinline__ T ld32(const T *base, uint32_t byte_off)
 template <typename P, typename FT = double, typename LT = double>
 __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict__ f0, const P *__restrict__ f1,
                                                  const FT *__restrict__ F, double *__restrict__ ub, int clear_ub,
-                                                 double *__restrict__ acc_clear,
+                                                 double *__restrict__ tslot,
                                                  const LT *__restrict__ lam1, LT *__restrict__ lam0,
                                                  double *__restrict__ Fb, double *grads)
 {
@@ -594,13 +612,17 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
                 ub[2 * n + id] = 0.0;
             }
         }
-        if (acc_clear && id == 0)
-            *acc_clear = 0.0;
         Fb[id] = fb0;
         Fb[n + id] = fb1;
         Fb[2 * n + id] = fb2;
     }
-    block_atomic_add<1>(tb, grads + 5);
+    if (tslot) {  // this block's running sum over the sweep, in its own slot
+        block_sum<1>(tb);
+        if (threadIdx.x == 0)
+            tslot[blockIdx.x] += tb[0];
+    } else {
+        block_atomic_add<1>(tb, grads + 5);
+    }
 }
 
 // phib_i = sum_x Fb(x) delta(x - q_i) and qb0_i += sum_x (Fb(x) . phi_i)
@@ -640,7 +662,8 @@ __global__ __launch_bounds__(256) void ka_interp_force(AdjArgs A, const double *
 }
 
 // qb0_i += (d Phi / d q phib)_i (the directional derivative of the nodal
-// forces along phib, with dVp[0] = V - V0 and Vdotp[0] = grad V . phib), and the
+// forces along phib, with dVp[0] = V - V0 and grad V . phib the sum of
+// vparts[0 .. nvp)), and the
 // parameter derivatives phib . dPhi/dalpha_m (m = 1..3), phib . dPhi/dk_V,
 // phib . dPhi/deps_lo into grads[0..4].  8 lanes per vertex, one incident
 // face each.
@@ -648,11 +671,20 @@ template <typename G>
 __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__restrict__ q,
                                                     const int4 *__restrict__ inc4, const double *__restrict__ fref,
                                                     const double *__restrict__ phib, const G *__restrict__ gV,
-                                                    const double *__restrict__ dVp, const double *__restrict__ Vdotp,
-                                                    double *__restrict__ qb0, double *grads)
+                                                    const double *__restrict__ dVp, const double *__restrict__ vparts,
+                                                    int nvp, double *__restrict__ qb0, double *grads)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int v = t >> 3, lane = t & 7;
+    // Vdot = grad V . phib, the sum of nvp partial sums
+    __shared__ double s_vdot;
+    {
+        double vs[1] = {0.0};
+        for (int k = threadIdx.x; k < nvp; k += 256) vs[0] += vparts[k];
+        block_sum<1>(vs);
+        if (threadIdx.x == 0) s_vdot = vs[0];
+        __syncthreads();
+    }
     double pg[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (v < A.nv) {  // whole groups of 8 take the same branch
         const int nv = A.nv, nf = A.nf;
@@ -697,7 +729,7 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
         }
         ljz = group8_sum(ljz);
         if (lane == 0) {
-            const double dV = dVp[0], Vdot = Vdotp[0];
+            const double dV = dVp[0], Vdot = s_vdot;
             const double pbv[3] = {phib[v], phib[nv + v], phib[2 * nv + v]};
             for (int k = 0; k < 3; ++k) {
                 const double gvk = double(gV[k * nv + v]);
@@ -772,13 +804,13 @@ __global__ __launch_bounds__(256) void ka_spread_interp_u(AdjArgs A, const doubl
 
 // phib_i = sum_x Fb delta and qb0_i += sum_x (Fb . phi_i) grad_q delta, with
 // phi_i = (phi_S + phi_W)_i - k_V (V - V0) / V0 (dV/dq)_i from the kept parts;
-// *vdot += grad V . phib
+// vpart[block] = this block's share of grad V . phib
 template <typename P>
 __global__ __launch_bounds__(256) void ka_interp_force_s(AdjArgs A, const double *__restrict__ q,
                                                          const P *__restrict__ phs, const P *__restrict__ gvs,
                                                          const double *__restrict__ dV, const double *__restrict__ Fb,
                                                          double *__restrict__ phib, double *__restrict__ qb0,
-                                                         double *vdot)
+                                                         double *__restrict__ vpart)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = (int)(t >> 6), k = (int)(t & 63);
@@ -817,7 +849,9 @@ __global__ __launch_bounds__(256) void ka_interp_force_s(AdjArgs A, const double
             vd[0] = gv[0] * pb[0] + gv[1] * pb[1] + gv[2] * pb[2];
         }
     }
-    block_atomic_add<1>(vd, vdot);  // grad V . phib = sum_i (dV/dq)_i . phib_i
+    block_sum<1>(vd);  // grad V . phib = sum_i (dV/dq)_i . phib_i, by blocks
+    if (threadIdx.x == 0)
+        vpart[blockIdx.x] = vd[0];
 }
 
 // F = ub = 0 over [3][n] each (F may be null), acc[0..3] = 0, in one launch
@@ -939,7 +973,8 @@ hipError_t adj_interp_force(const AdjArgs &A, const double *q, const double *phi
 hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref, const double *phib,
                          const double *gV, const double *acc, double *qb0, double *grads, hipStream_t s)
 {
-    ka_force_jvp<double><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, q, inc4, fref, phib, gV, acc, acc + 1, qb0, grads);
+    ka_force_jvp<double><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, q, inc4, fref, phib, gV, acc, acc + 1, 1, qb0,
+                                                                  grads);
     return hipGetLastError();
 }
 
@@ -950,14 +985,14 @@ static hipError_t reverse_kept(const AdjArgs &A, const AdjLevel &L, const AdjWor
     const P *f0 = (const P *)L.f0, *f1 = (const P *)L.f1, *F = (const P *)L.F, *U = (const P *)L.U;
     const P *phs = (const P *)L.phs, *gvs = (const P *)L.gvs;
     // ub starts at zero (cleared by the sweep's caller, then by ka_lb_adj of
-    // every step); acc[3] collects grad V . phib (zeroed by ka_lb_adj)
+    // every step); grad V . phib goes through per-block partial sums
     ka_spread_interp_u<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, U, w.ub, w.qb0);
     ka_moments_adj_u<P><<<blocks_for(n), 256, 0, s>>>(A, f1, U, w.ub, (P *)w.lam1);
-    ka_lb_adj<P, P, P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, w.ub, 1, w.acc + 3, (const P *)w.lam1, (P *)w.lam0,
+    ka_lb_adj<P, P, P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, w.ub, 1, w.tpart, (const P *)w.lam1, (P *)w.lam0,
                                                      w.Fb, w.grads);
-    ka_interp_force_s<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, phs, gvs, L.dV, w.Fb, w.phib, w.qb0,
-                                                                 w.acc + 3);
-    ka_force_jvp<P><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, L.q, L.inc4, L.fref, w.phib, gvs, L.dV, w.acc + 3,
+    const int nvp = blocks_for(64ll * A.nv);
+    ka_interp_force_s<P><<<nvp, 256, 0, s>>>(A, L.q, phs, gvs, L.dV, w.Fb, w.phib, w.qb0, w.vpart);
+    ka_force_jvp<P><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, L.q, L.inc4, L.fref, w.phib, gvs, L.dV, w.vpart, nvp,
                                                           w.qb0, w.grads);
     return hipGetLastError();
 }

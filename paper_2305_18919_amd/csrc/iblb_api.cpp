@@ -1593,6 +1593,8 @@ struct AdjState {
     double *phi = nullptr, *gV = nullptr, *phib = nullptr;
     double *acc = nullptr;             // [4]: V - V0 and grad V . dir, twice
     double *grads = nullptr;           // [6]
+    double *tpart = nullptr;           // every level kept: per-block sums of the tau derivative
+    double *vpart = nullptr;           // and per-block shares of grad V . phib
     hipGraph_t graph = nullptr;        // checkpoint mode: recompute and reverse sweep of one full segment
     hipGraphExec_t gexec = nullptr;
     // every level kept: the forward's own fields of each step (element size es)
@@ -1615,7 +1617,7 @@ void free_adjoint(iblb_ctx *c)
     for (void *p : {a->Fs, a->Us, a->phs, a->gvs, (void *)a->dVs})
         if (p) (void)hipFree(p);
     for (double *p : {a->qs, a->lam_buf[0], a->lam_buf[1], a->qb_buf[0], a->qb_buf[1], a->F, a->Fb, a->ub, a->phi,
-                      a->gV, a->phib, a->acc, a->grads})
+                      a->gV, a->phib, a->acc, a->grads, a->tpart, a->vpart})
         if (p) (void)hipFree(p);
     delete a;
     c->adj = nullptr;
@@ -1753,7 +1755,8 @@ int alloc_sweep(iblb_ctx *c, AdjState *a, size_t levels)
     if (!get(&a->qs, levels * 3 * nv) || !get(&a->lam_buf[0], 19 * n) || !get(&a->lam_buf[1], 19 * n) ||
         !get(&a->qb_buf[0], 3 * nv) || !get(&a->qb_buf[1], 3 * nv) || !get(&a->F, 3 * n) || !get(&a->Fb, 3 * n) ||
         !get(&a->ub, 3 * n) || !get(&a->phi, 3 * nv) || !get(&a->gV, 3 * nv) || !get(&a->phib, 3 * nv) ||
-        !get(&a->acc, 4) || !get(&a->grads, 6))
+        !get(&a->acc, 4) || !get(&a->grads, 6) || !get(&a->tpart, (size_t)adj_lb_blocks((long long)n)) ||
+        !get(&a->vpart, (size_t)adj_vertex_blocks((long long)nv)))
         return fail(c, IBLB_E_DEVICE, "no device memory for the reverse sweep");
     return IBLB_OK;
 }
@@ -1876,9 +1879,10 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     HIP_TRY(c, hipMemsetAsync(a->lam[1], 0, 19 * n * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(a->grads, 0, 6 * 8, c->stream));
     if (a->every == 0) {
-        // the kept-field sweep clears ub and acc itself after this first zeroing
+        // the kept-field sweep clears ub itself after this first zeroing; the
+        // tau derivative collects in per-block slots, added up below
         HIP_TRY(c, hipMemsetAsync(a->ub, 0, 3 * n * 8, c->stream));
-        HIP_TRY(c, hipMemsetAsync(a->acc, 0, 4 * 8, c->stream));
+        HIP_TRY(c, hipMemsetAsync(a->tpart, 0, (size_t)adj_lb_blocks((long long)n) * 8, c->stream));
         const size_t fl = 3 * n * a->es, vl = 3 * nv * a->es;
         for (int k = a->n - 1; k >= 0; --k) {
             AdjLevel L;
@@ -1894,7 +1898,8 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
             L.faces = c->d.faces;
             L.inc4 = c->d.inc4;
             L.fref = c->d.fref;
-            const AdjWork W{a->ub, a->lam[1], a->lam[0], a->Fb, a->phib, a->qb[1], a->qb[0], a->acc, a->grads};
+            const AdjWork W{a->ub,   a->lam[1], a->lam[0], a->Fb,    a->phib,
+                            a->qb[1], a->qb[0], a->acc,    a->grads, a->tpart, a->vpart};
             HIP_TRY(c, adj_reverse_kept(A, a->es == 8, L, W, c->stream));
             std::swap(a->lam[0], a->lam[1]);
             std::swap(a->qb[0], a->qb[1]);
@@ -1937,7 +1942,11 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     }
     HIP_TRY(c, hipMemcpyAsync(grads, a->grads, 6 * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(soa.data(), a->qb[1], 3 * nv * 8, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> tp(a->every == 0 ? (size_t)adj_lb_blocks((long long)n) : 0);
+    if (!tp.empty())
+        HIP_TRY(c, hipMemcpyAsync(tp.data(), a->tpart, tp.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (double v : tp) grads[5] += v;  // the kept-field sweep's tau derivative, by blocks
     if (dJdq0)
         for (size_t i = 0; i < nv; ++i)
             for (int k = 0; k < 3; ++k) dJdq0[3 * i + k] = soa[(size_t)k * nv + i];

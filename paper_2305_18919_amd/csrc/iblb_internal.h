@@ -184,7 +184,13 @@ struct AdjLevel {
 };
 struct AdjWork {
     double *ub, *lam1, *lam0, *Fb, *phib, *qb1, *qb0, *acc, *grads;
+    double *tpart;  // [adj_lb_blocks(n)] per-block running sums of the tau derivative
+    double *vpart;  // [adj_vertex_blocks(nv)] per-block shares of grad V . phib
 };
+// Blocks of the LB adjoint over n nodes and of the 64-lanes-per-vertex
+// kernels over nv vertices (256 threads per block): the sizes of tpart, vpart.
+inline int adj_lb_blocks(long long n) { return (int)((n + 255) / 256); }
+inline int adj_vertex_blocks(long long nv) { return (int)((64 * nv + 255) / 256); }
 hipError_t adj_reverse_kept(const AdjArgs &A, int fp64, const AdjLevel &L, const AdjWork &w, hipStream_t s);
 // grads[0..4] += the alpha_1..3, k_V and eps_lo derivatives of this step
 hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref, const double *phib,
