@@ -432,6 +432,7 @@ def adjoint_study(every: int):
     plainly cut-off wall force makes the observables only piecewise smooth,
     and wider steps in the parameters the contact region is most sensitive to
     straddle its switching)."""
+    import numpy as np
     import torch
     from paper_2305_18919_amd import iblb
     from paper_2305_18919_amd import inputs as I
@@ -499,7 +500,11 @@ def adjoint_study(every: int):
         "adjoint_over_forward": round((t_rec + t_bwd) / t_fwd, 3),
         "backward_over_forward": round(t_bwd / t_fwd, 3),
         "storage": "every time level in device memory (FP32 populations, 19 x nodes x 4 B per level)",
-        "checkpoint_mode": dict(modes[every], checkpoint_every=every),
+        "checkpoint_mode": dict(modes[every], checkpoint_every=every,
+                                max_rel_diff_from_every_level_kept=max(
+                                    float(np.max(np.abs(np.array(grads[every][j]) - np.array(grads[0][j])) /
+                                                 np.maximum(np.abs(np.array(grads[0][j])), 1e-300)))
+                                    for j in (0, 1))),
     })
     print(json.dumps(out), flush=True)
 

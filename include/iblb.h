@@ -303,8 +303,9 @@ int iblb_batch_destroy(iblb_batch *b);
  *    recomputes nothing.  Its adjoint populations are stored in the same
  *    precision.
  *  every > 0: a device copy of the whole context state every `every` steps;
- *    the sweep recomputes each segment of `every` steps (in FP64 from the
- *    stored levels) before walking it backwards.
+ *    the sweep restores each segment's checkpoint, records the segment again
+ *    as above (every + 1 levels and every steps of fields in device memory)
+ *    and walks it backwards.
  * Replaces any earlier recording.  The context is left at t0 + n.  Errors:
  * IBLB_E_INVAL (null context, n < 1, every < 0), IBLB_E_STATE (no mesh),
  * IBLB_E_DEVICE (the recording does not fit in device memory, or a HIP

@@ -11,24 +11,24 @@
 // Given the adjoints lam(t+1) of f(t+1) and qb(t+1) of q(t+1), the kernels
 // below produce lam(t), qb(t) and add this step's share of the parameter
 // derivatives, in the reverse order of the forward operations:
-//   ka_spread (qb -> ub)       ub(x) = sum_i delta(x - q_i) qb_i, the adjoint of u'
-//   ka_moments_adj             lam(t+1) += d u'/d f(t+1)^T ub,  Fb += ub / (2 rho')
-//   ka_interp_adj              qb(t) = qb(t+1) + sum_x (u'(x) . qb) grad_q delta
-//   ka_lb_adj                  lam(t) from lam(t+1): propagation reversed (a pull),
-//                              then the transposed Jacobian of the collision;
-//                              Fb += d f*/d F^T Lam, tau derivative
-//   ka_interp_force            phib_i = sum_x Fb delta, qb += sum_x (Fb . phi_i) grad_q delta
-//   ka_volume (direction phib) Vdot = grad V . phib
-//   ka_force_jvp               qb += (d Phi / d q)^T phib and the alpha, k_V, eps derivatives.
+//   ka_spread_interp_u   ub(x) = sum_i delta(x - q_i) qb_i (the adjoint of u'),
+//                        and qb(t) = qb(t+1) + sum_x (u'(x) . qb) grad_q delta
+//   ka_moments_adj_u     lam(t+1) += d u'/d f(t+1)^T ub
+//   ka_lb_adj            lam(t) from lam(t+1): propagation reversed (a pull),
+//                        then the transposed Jacobian of the collision;
+//                        Fb = d f*/d F^T Lam + ub / (2 rho'), tau derivative
+//   ka_interp_force_s    phib_i = sum_x Fb delta, qb += sum_x (Fb . phi_i) grad_q
+//                        delta, and the shares of Vdot = grad V . phib
+//   ka_force_jvp         qb += (d Phi / d q)^T phib and the alpha, k_V, eps
+//                        derivatives.
 // Every nodal force is minus the gradient of an energy (W_S, k_V (V - V0)^2 /
 // (2 V0) and the LJ potential of each face centroid), so d Phi / d q is
 // symmetric and its transpose product is the directional derivative of Phi
-// along phib, computed with dual numbers.  With every time level kept, the
-// forward's own force density, u(t+1) and nodal force parts of each step are
-// read back (ka_*_u, ka_interp_force_s, reverse_kept), and the adjoint lam
-// is stored in the step's own precision (FP32 for an FP32 step); with
-// checkpoints, the forward quantities (phi, F, rho, u, u') are recomputed in
-// FP64 from the stored populations and positions of each time level.
+// along phib, computed with dual numbers.  The forward's own force density,
+// u(t+1) and nodal force parts of each step are read back from the recording
+// (every level of the window, or of one checkpoint segment at a time), so
+// nothing of the forward is recomputed here, and the adjoint lam is stored in
+// the step's own precision (FP32 for an FP32 step).
 #include "iblb_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -236,26 +236,6 @@ __device__ __forceinline__ Node stencil_node(const AdjArgs &A, double qx, double
     return nd;
 }
 
-// u = (sum c f + (F + body)/2) / rho at a fluid node, from canonical
-// deviations stored with element type P
-template <typename P>
-__device__ __forceinline__ void velocity(const AdjArgs &A, const P *__restrict__ f, const double *__restrict__ F,
-                                         long long id, double *u, double *rho)
-{
-    const long long n = A.g.n;
-    double dr = 0.0, m[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const double d = double(f[i * n + id]);
-        dr += d;
-        m[0] += kCx[i] * d;
-        m[1] += kCy[i] * d;
-        m[2] += kCz[i] * d;
-    }
-    *rho = A.rho0 + dr;
-    for (int k = 0; k < 3; ++k) u[k] = (m[k] + 0.5 * (F[k * n + id] + A.body[k])) / *rho;
-}
-
 __device__ __forceinline__ double wave_sum64(double v)
 {
 #pragma unroll
@@ -307,173 +287,6 @@ __device__ __forceinline__ void block_sum(double (&v)[K])
 }
 
 // ---------------------------------------------------------------- kernels
-// acc[0] += sum_j (V_j - V0_j) (displacement expansion of the triple
-// product, as the forward computes it), acc[1] += sum_j grad V_j . dir
-__global__ __launch_bounds__(256) void ka_volume(AdjArgs A, const double *__restrict__ q, const double *__restrict__ X,
-                                                 const int *__restrict__ faces, const double *__restrict__ dir,
-                                                 double *acc)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    double v[2] = {0.0, 0.0};
-    if (j < A.nf) {
-        const int nv = A.nv;
-        const int ia = faces[j], ib = faces[A.nf + j], ic = faces[2 * A.nf + j];
-        double Ar[3], Br[3], Cr[3], da[3], db[3], dc[3], a[3], b[3], c[3];
-        for (int k = 0; k < 3; ++k) {
-            Ar[k] = X[k * nv + ia] - A.origin[k];
-            Br[k] = X[k * nv + ib] - A.origin[k];
-            Cr[k] = X[k * nv + ic] - A.origin[k];
-            a[k] = q[k * nv + ia];
-            b[k] = q[k * nv + ib];
-            c[k] = q[k * nv + ic];
-            da[k] = a[k] - X[k * nv + ia];
-            db[k] = b[k] - X[k * nv + ib];
-            dc[k] = c[k] - X[k * nv + ic];
-        }
-        auto T3 = [](const double *x, const double *y, const double *z) {
-            return x[0] * (y[1] * z[2] - y[2] * z[1]) + x[1] * (y[2] * z[0] - y[0] * z[2]) +
-                   x[2] * (y[0] * z[1] - y[1] * z[0]);
-        };
-        v[0] = (T3(da, Br, Cr) + T3(Ar, db, Cr) + T3(Ar, Br, dc) + T3(da, db, Cr) + T3(da, Br, dc) + T3(Ar, db, dc) +
-                T3(da, db, dc)) / 6.0;
-        if (dir) {
-            const int idx[3] = {ia, ib, ic};
-            for (int corner = 0; corner < 3; ++corner) {
-                double gc[3];
-                volume_corner<double>(a, b, c, A.origin, corner, gc);
-                for (int k = 0; k < 3; ++k) v[1] += gc[k] * dir[k * nv + idx[corner]];
-            }
-        }
-    }
-    block_atomic_add<2>(v, acc);
-}
-
-// Nodal forces phi = phi^S + phi^V + phi^W and grad V per vertex, gathered
-// over the vertex's incident faces by 8 lanes (one incident face each, slot
-// s = lane, lane + 8, ...); acc[0] = V - V0.
-__global__ __launch_bounds__(256) void ka_vertex_forces(AdjArgs A, const double *__restrict__ q,
-                                                        const int4 *__restrict__ inc4, const double *__restrict__ fref,
-                                                        const double *__restrict__ acc, double *__restrict__ phi,
-                                                        double *__restrict__ gV)
-{
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = t >> 3, lane = t & 7;
-    if (v >= A.nv) return;  // whole groups of 8 leave together
-    const int nv = A.nv, nf = A.nf;
-    double fs[3] = {0, 0, 0}, gv[3] = {0, 0, 0}, fw = 0.0;
-    for (int s = lane; s < A.slots; s += 8) {
-        const int4 e = inc4[(long long)v * A.slots + s];
-        if (e.w < 0) continue;
-        const int j = e.w >> 2, corner = e.w & 3;
-        double a[3], b[3], c[3], fr[5];
-        for (int k = 0; k < 3; ++k) {
-            a[k] = q[k * nv + e.x];
-            b[k] = q[k * nv + e.y];
-            c[k] = q[k * nv + e.z];
-        }
-        for (int k = 0; k < 5; ++k) fr[k] = fref[k * nf + j];
-        const FaceParts<double> p = face_parts<double>(a, b, c, fr, corner);
-        const double w1 = 0.5 * A.alpha[2];
-        const double w2 = (0.5 * (A.alpha[0] - A.alpha[2]) + 0.25 * (A.alpha[0] + A.alpha[1]) * p.lnJ) / p.J;
-        double gc[3];
-        volume_corner<double>(a, b, c, A.origin, corner, gc);
-        for (int k = 0; k < 3; ++k) {
-            fs[k] += w1 * p.FG[k] + w2 * p.Fadj[k];
-            gv[k] += gc[k];
-        }
-        if (A.g.walls) {
-            const double cz = (a[2] + b[2] + c[2]) / 3.0;
-            fw += (A.eps_lo * lj_unit(A.xi, A.rc, cz - A.z_lo) - A.eps_hi * lj_unit(A.xi, A.rc, A.z_hi - cz)) / 3.0;
-        }
-    }
-    for (int k = 0; k < 3; ++k) {
-        fs[k] = group8_sum(fs[k]);
-        gv[k] = group8_sum(gv[k]);
-    }
-    fw = group8_sum(fw);
-    if (lane == 0) {
-        const double dV = acc[0];
-        for (int k = 0; k < 3; ++k) {
-            phi[k * nv + v] = fs[k] - A.kv_over_V0 * dV * gv[k] + (k == 2 ? fw : 0.0);
-            gV[k * nv + v] = gv[k];
-        }
-    }
-}
-
-// F(x) += sum_i delta(x - q_i) phi_i and ub(x) += sum_i delta(x - q_i) qb_i
-// over the fluid nodes (one thread per vertex and stencil node)
-__global__ __launch_bounds__(256) void ka_spread2(AdjArgs A, const double *__restrict__ q,
-                                                  const double *__restrict__ phi, const double *__restrict__ qb,
-                                                  double *F, double *ub)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = (int)(t >> 6), k = (int)(t & 63);
-    if (v >= A.nv) return;
-    const int nv = A.nv;
-    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
-    if (!finite_pos(qx, qy, qz)) return;
-    const Node nd = stencil_node(A, qx, qy, qz, k);
-    if (nd.id < 0 || nd.w == 0.0) return;
-    const long long n = A.g.n;
-    for (int c = 0; c < 3; ++c) {
-        atomicAdd(F + c * n + nd.id, phi[c * nv + v] * nd.w);
-        atomicAdd(ub + c * n + nd.id, qb[c * nv + v] * nd.w);
-    }
-}
-
-// Adjoint of u' = (sum c f1 + (F + body)/2) / rho1 with respect to f1 at every
-// fluid node with ub != 0: lam_j += (c_j - u') . ub / rho1 (its share of the
-// force adjoint, ub / (2 rho1), is added by ka_lb_adj)
-template <typename P>
-__global__ __launch_bounds__(256) void ka_moments_adj(AdjArgs A, const P *__restrict__ f1,
-                                                      const double *__restrict__ F, const double *__restrict__ ub,
-                                                      double *__restrict__ lam)
-{
-    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long n = A.g.n;
-    if (id >= n) return;
-    const double b[3] = {ub[id], ub[n + id], ub[2 * n + id]};
-    if (b[0] == 0.0 && b[1] == 0.0 && b[2] == 0.0) return;
-    double u[3], rho;
-    velocity<P>(A, f1, F, id, u, &rho);
-    const double ub_u = b[0] * u[0] + b[1] * u[1] + b[2] * u[2];
-#pragma unroll
-    for (int j = 0; j < 19; ++j)
-        lam[j * n + id] += (kCx[j] * b[0] + kCy[j] * b[1] + kCz[j] * b[2] - ub_u) / rho;
-}
-
-// qb0_i = qb1_i + sum_x (u'(x) . qb1_i) grad_q delta(x - q_i), u' at the
-// fluid nodes from (f1, F), the wall velocity elsewhere (one wavefront per
-// vertex, one lane per stencil node)
-template <typename P>
-__global__ __launch_bounds__(256) void ka_interp_adj(AdjArgs A, const double *__restrict__ q,
-                                                     const double *__restrict__ qb1, const P *__restrict__ f1,
-                                                     const double *__restrict__ F, double *__restrict__ qb0)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = (int)(t >> 6), k = (int)(t & 63);
-    if (v >= A.nv) return;
-    const int nv = A.nv;
-    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
-    const double b[3] = {qb1[v], qb1[nv + v], qb1[2 * nv + v]};
-    double s[3] = {0.0, 0.0, 0.0};
-    if (finite_pos(qx, qy, qz)) {
-        const Node nd = stencil_node(A, qx, qy, qz, k);
-        double u[3];
-        if (nd.id >= 0) {
-            double rho;
-            velocity<P>(A, f1, F, nd.id, u, &rho);
-        } else {
-            for (int c = 0; c < 3; ++c) u[c] = nd.side ? A.uhi[c] : A.ulo[c];
-        }
-        const double ubq = u[0] * b[0] + u[1] * b[1] + u[2] * b[2];
-        for (int c = 0; c < 3; ++c) s[c] = ubq * nd.gw[c];
-    }
-    for (int c = 0; c < 3; ++c) s[c] = wave_sum64(s[c]);
-    if (k == 0)
-        for (int c = 0; c < 3; ++c) qb0[c * nv + v] = b[c] + s[c];
-}
-
 // Collision and propagation reversed at node x: Lam_i = lam1_i(x + c_i), or
 // lam1_opp(i)(x) for a link that bounces back at a wall (whose moving-wall
 // term -6 w_i rho (c_i . u_w) adds to the density adjoint); then
@@ -482,11 +295,11 @@ __global__ __launch_bounds__(256) void ka_interp_adj(AdjArgs A, const double *__
 //   Fb = sum_i Lam_i d S_i / d F + b / (2 rho) + ub / (2 rho1)  (the last term
 //        the force share of the interpolated velocity's adjoint),
 //   d/dtau: sum_i Lam_i [(f_i - f^eq_i) + s_i / 2] / tau^2  with S_i = (1 - 1/(2 tau)) s_i.
-// Lam and the populations are each read twice (the second time from cache)
-// so that the kernel keeps few registers.  clear_ub != 0: ub is zeroed where
-// it was read (this kernel is its last reader in the step).  The tau
-// derivative goes to grads[5], or with tslot to tslot[block] (a running sum
-// per block that the caller adds up at the end of the sweep).
+// Lam is gathered once into LDS and read by two passes; the populations stay
+// in registers.  ub is zeroed where it was read (this kernel is its last
+// reader in the step).  The tau derivative goes to tslot[block], a running
+// sum per block that the caller adds up at the end of the sweep.  P is the
+// element type of the kept populations, force density and of lam.
 // element at a 32-bit byte offset from a base pointer (a uniform base and
 // one address register per access)
 template <typename T>
@@ -495,17 +308,16 @@ __device__ __forceinline__ T ld32(const T *base, uint32_t byte_off)
     return *(const T *)((const char *)base + byte_off);
 }
 
-template <typename P, typename FT = double, typename LT = double>
+template <typename P>
 __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict__ f0, const P *__restrict__ f1,
-                                                 const FT *__restrict__ F, double *__restrict__ ub, int clear_ub,
-                                                 double *__restrict__ tslot,
-                                                 const LT *__restrict__ lam1, LT *__restrict__ lam0,
-                                                 double *__restrict__ Fb, double *grads)
+                                                 const P *__restrict__ F, double *__restrict__ ub,
+                                                 double *__restrict__ tslot, const P *__restrict__ lam1,
+                                                 P *__restrict__ lam0, double *__restrict__ Fb)
 {
     const Grid &g = A.g;
     const long long n = g.n;
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    __shared__ LT Ls[19][256];
+    __shared__ P Ls[19][256];
     double tb[1] = {0.0};
     if (id < n) {
         // node coordinates and the row/plane offsets of its neighbours (no
@@ -519,20 +331,20 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
         // a link whose source lies in a solid wall layer bounces back at x
         const bool wlo = g.walls && zf == 0, whi = g.walls && zf == nzf - 1;
         // byte offsets of this node in a [19][n] array of P and of doubles
-        const uint32_t oP = uid * (uint32_t)sizeof(P), oL = uid * (uint32_t)sizeof(LT);
+        const uint32_t oP = uid * (uint32_t)sizeof(P);
         // the node's populations and Lam_i, the adjoint of post-collision
         // population i at x, gathered before any is used (all loads in
         // flight together); the populations stay in registers, Lam goes to
         // this thread's LDS slots, which the two passes below read
         P fv[19];
-        LT lt[19];
+        P lt[19];
 #pragma unroll
         for (int i = 0; i < 19; ++i) fv[i] = ld32(f0 + (size_t)i * n, oP);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             const bool wall = (kCz[i] < 0 && wlo) || (kCz[i] > 0 && whi);
             const uint32_t to = zo[kCz[i] + 1] + yo[kCy[i] + 1] + xo[kCx[i] + 1];
-            lt[i] = wall ? ld32(lam1 + (size_t)oppq(i) * n, oL) : ld32(lam1 + (size_t)i * n, to * (uint32_t)sizeof(LT));
+            lt[i] = wall ? ld32(lam1 + (size_t)oppq(i) * n, oP) : ld32(lam1 + (size_t)i * n, to * (uint32_t)sizeof(P));
         }
         double dr = 0.0, m[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -546,9 +358,8 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
 #pragma unroll
         for (int i = 0; i < 19; ++i) Ls[i][threadIdx.x] = lt[i];
         const double rho = A.rho0 + dr;
-        const uint32_t oF = (uint32_t)id * (uint32_t)sizeof(FT);
-        const double Fx = double(ld32(F, oF)) + A.body[0], Fy = double(ld32(F + n, oF)) + A.body[1],
-                     Fz = double(ld32(F + 2 * n, oF)) + A.body[2];
+        const double Fx = double(ld32(F, oP)) + A.body[0], Fy = double(ld32(F + n, oP)) + A.body[1],
+                     Fz = double(ld32(F + 2 * n, oP)) + A.body[2];
         const double u0 = (m[0] + 0.5 * Fx) / rho, u1 = (m[1] + 0.5 * Fy) / rho, u2 = (m[2] + 0.5 * Fz) / rho;
         const double uu = u0 * u0 + u1 * u1 + u2 * u2;
         const double uF = u0 * Fx + u1 * Fy + u2 * Fz;
@@ -587,8 +398,8 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
             const int cx = kCx[j], cy = kCy[j], cz = kCz[j];
             const double w = wq(j);
             const double L = double(Ls[j][threadIdx.x]);
-            *(LT *)((char *)(lam0 + (size_t)j * n) + oL) =
-                LT((1.0 - om) * L + a + (b0 * (cx - u0) + b1 * (cy - u1) + b2 * (cz - u2)) * ir);
+            *(P *)((char *)(lam0 + (size_t)j * n) + oP) =
+                P((1.0 - om) * L + a + (b0 * (cx - u0) + b1 * (cy - u1) + b2 * (cz - u2)) * ir);
             const double cu = cx * u0 + cy * u1 + cz * u2;
             const double cF = cx * Fx + cy * Fy + cz * Fz;
             const double deq = w * dr + w * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
@@ -606,59 +417,18 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
             fb0 += ub0 * h;
             fb1 += ub1 * h;
             fb2 += ub2 * h;
-            if (clear_ub) {  // this thread was its last reader: zero for the next step's spread
-                ub[id] = 0.0;
-                ub[n + id] = 0.0;
-                ub[2 * n + id] = 0.0;
-            }
+            // this thread was its last reader: zero for the next step's spread
+            ub[id] = 0.0;
+            ub[n + id] = 0.0;
+            ub[2 * n + id] = 0.0;
         }
         Fb[id] = fb0;
         Fb[n + id] = fb1;
         Fb[2 * n + id] = fb2;
     }
-    if (tslot) {  // this block's running sum over the sweep, in its own slot
-        block_sum<1>(tb);
-        if (threadIdx.x == 0)
-            tslot[blockIdx.x] += tb[0];
-    } else {
-        block_atomic_add<1>(tb, grads + 5);
-    }
-}
-
-// phib_i = sum_x Fb(x) delta(x - q_i) and qb0_i += sum_x (Fb(x) . phi_i)
-// grad_q delta over the fluid nodes (one wavefront per vertex)
-__global__ __launch_bounds__(256) void ka_interp_force(AdjArgs A, const double *__restrict__ q,
-                                                       const double *__restrict__ phi, const double *__restrict__ Fb,
-                                                       double *__restrict__ phib, double *__restrict__ qb0)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = (int)(t >> 6), k = (int)(t & 63);
-    if (v >= A.nv) return;
-    const int nv = A.nv;
-    const long long n = A.g.n;
-    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
-    const double p[3] = {phi[v], phi[nv + v], phi[2 * nv + v]};
-    double pb[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
-    if (finite_pos(qx, qy, qz)) {
-        const Node nd = stencil_node(A, qx, qy, qz, k);
-        if (nd.id >= 0) {
-            const double fb[3] = {Fb[nd.id], Fb[n + nd.id], Fb[2 * n + nd.id]};
-            const double fp = fb[0] * p[0] + fb[1] * p[1] + fb[2] * p[2];
-            for (int c = 0; c < 3; ++c) {
-                pb[c] = fb[c] * nd.w;
-                s[c] = fp * nd.gw[c];
-            }
-        }
-    }
-    for (int c = 0; c < 3; ++c) {
-        pb[c] = wave_sum64(pb[c]);
-        s[c] = wave_sum64(s[c]);
-    }
-    if (k == 0)
-        for (int c = 0; c < 3; ++c) {
-            phib[c * nv + v] = pb[c];
-            qb0[c * nv + v] += s[c];
-        }
+    block_sum<1>(tb);  // this block's running sum over the sweep, in its own slot
+    if (threadIdx.x == 0)
+        tslot[blockIdx.x] += tb[0];
 }
 
 // qb0_i += (d Phi / d q phib)_i (the directional derivative of the nodal
@@ -854,129 +624,9 @@ __global__ __launch_bounds__(256) void ka_interp_force_s(AdjArgs A, const double
         vpart[blockIdx.x] = vd[0];
 }
 
-// F = ub = 0 over [3][n] each (F may be null), acc[0..3] = 0, in one launch
-__global__ __launch_bounds__(256) void ka_zero_fields(double *__restrict__ F, double *__restrict__ ub, long long n3,
-                                                      double *__restrict__ acc)
-{
-    const long long s0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s0 < 4) acc[s0] = 0.0;
-    for (long long i = s0; i < n3; i += (long long)gridDim.x * blockDim.x) {
-        if (F) F[i] = 0.0;
-        ub[i] = 0.0;
-    }
-}
-
-// p[0..n) = 0 and dst[0..n) = src[0..n) as kernels, so that the reverse
-// sweep can be captured in a graph without memset or copy nodes
-__global__ __launch_bounds__(256) void ka_zero(double *__restrict__ p, long long n)
-{
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        p[i] = 0.0;
-}
-
-__global__ __launch_bounds__(256) void ka_copy(double *__restrict__ dst, const double *__restrict__ src, long long n)
-{
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        dst[i] = src[i];
-}
-
 int blocks_for(long long threads) { return (int)((threads + 255) / 256); }
 
-int grid_stride_blocks(long long n)
-{
-    const long long b = (n + 255) / 256;
-    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
-}
-
 }  // namespace
-
-hipError_t adj_zero(double *p, long long n, hipStream_t s)
-{
-    ka_zero<<<grid_stride_blocks(n), 256, 0, s>>>(p, n);
-    return hipGetLastError();
-}
-
-hipError_t adj_copy(double *dst, const double *src, long long n, hipStream_t s)
-{
-    ka_copy<<<grid_stride_blocks(n), 256, 0, s>>>(dst, src, n);
-    return hipGetLastError();
-}
-
-hipError_t adj_zero_fields(double *F, double *ub, long long n3, double *acc, hipStream_t s)
-{
-    ka_zero_fields<<<grid_stride_blocks(n3), 256, 0, s>>>(F, ub, n3, acc);
-    return hipGetLastError();
-}
-
-hipError_t adj_volume(const AdjArgs &A, const double *q, const double *X, const int *faces, const double *dir,
-                      double *acc, hipStream_t s)
-{
-    ka_volume<<<blocks_for(A.nf), 256, 0, s>>>(A, q, X, faces, dir, acc);
-    return hipGetLastError();
-}
-
-hipError_t adj_vertex_forces(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref,
-                             const double *acc, double *phi, double *gV, hipStream_t s)
-{
-    ka_vertex_forces<<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, q, inc4, fref, acc, phi, gV);
-    return hipGetLastError();
-}
-
-hipError_t adj_spread2(const AdjArgs &A, const double *q, const double *phi, const double *qb, double *F, double *ub,
-                       hipStream_t s)
-{
-    ka_spread2<<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, phi, qb, F, ub);
-    return hipGetLastError();
-}
-
-hipError_t adj_moments(const AdjArgs &A, int fp64, const void *f1, const double *F, const double *ub, double *lam,
-                       hipStream_t s)
-{
-    if (fp64)
-        ka_moments_adj<double><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const double *)f1, F, ub, lam);
-    else
-        ka_moments_adj<float><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const float *)f1, F, ub, lam);
-    return hipGetLastError();
-}
-
-hipError_t adj_interp(const AdjArgs &A, int fp64, const double *q, const double *qb1, const void *f1,
-                      const double *F, double *qb0, hipStream_t s)
-{
-    if (fp64)
-        ka_interp_adj<double><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, qb1, (const double *)f1, F, qb0);
-    else
-        ka_interp_adj<float><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, qb1, (const float *)f1, F, qb0);
-    return hipGetLastError();
-}
-
-hipError_t adj_lb(const AdjArgs &A, int fp64, const void *f0, const void *f1, const double *F, double *ub,
-                  const double *lam1, double *lam0, double *Fb, double *grads, hipStream_t s)
-{
-    if (fp64)
-        ka_lb_adj<double><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const double *)f0, (const double *)f1, F, ub, 0,
-                                                              nullptr, lam1,
-                                                              lam0, Fb, grads);
-    else
-        ka_lb_adj<float><<<blocks_for(A.g.n), 256, 0, s>>>(A, (const float *)f0, (const float *)f1, F, ub, 0,
-                                                             nullptr, lam1,
-                                                             lam0, Fb, grads);
-    return hipGetLastError();
-}
-
-hipError_t adj_interp_force(const AdjArgs &A, const double *q, const double *phi, const double *Fb, double *phib,
-                            double *qb0, hipStream_t s)
-{
-    ka_interp_force<<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, q, phi, Fb, phib, qb0);
-    return hipGetLastError();
-}
-
-hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref, const double *phib,
-                         const double *gV, const double *acc, double *qb0, double *grads, hipStream_t s)
-{
-    ka_force_jvp<double><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, q, inc4, fref, phib, gV, acc, acc + 1, 1, qb0,
-                                                                  grads);
-    return hipGetLastError();
-}
 
 template <typename P>
 static hipError_t reverse_kept(const AdjArgs &A, const AdjLevel &L, const AdjWork &w, hipStream_t s)
@@ -988,8 +638,7 @@ static hipError_t reverse_kept(const AdjArgs &A, const AdjLevel &L, const AdjWor
     // every step); grad V . phib goes through per-block partial sums
     ka_spread_interp_u<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, U, w.ub, w.qb0);
     ka_moments_adj_u<P><<<blocks_for(n), 256, 0, s>>>(A, f1, U, w.ub, (P *)w.lam1);
-    ka_lb_adj<P, P, P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, w.ub, 1, w.tpart, (const P *)w.lam1, (P *)w.lam0,
-                                                     w.Fb, w.grads);
+    ka_lb_adj<P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, w.ub, w.tpart, (const P *)w.lam1, (P *)w.lam0, w.Fb);
     const int nvp = blocks_for(64ll * A.nv);
     ka_interp_force_s<P><<<nvp, 256, 0, s>>>(A, L.q, phs, gvs, L.dV, w.Fb, w.phib, w.qb0, w.vpart);
     ka_force_jvp<P><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, L.q, L.inc4, L.fref, w.phib, gvs, L.dV, w.vpart, nvp,

@@ -1589,18 +1589,14 @@ struct AdjState {
     double *lam[2] = {nullptr, nullptr};  // ping-pong adjoints of the populations: [1] is t+1
     double *qb[2] = {nullptr, nullptr};   // and of the positions
     double *lam_buf[2] = {nullptr, nullptr}, *qb_buf[2] = {nullptr, nullptr};  // their allocations
-    double *F = nullptr, *Fb = nullptr, *ub = nullptr;
-    double *phi = nullptr, *gV = nullptr, *phib = nullptr;
-    double *acc = nullptr;             // [4]: V - V0 and grad V . dir, twice
+    double *Fb = nullptr, *ub = nullptr, *phib = nullptr;
     double *grads = nullptr;           // [6]
-    double *tpart = nullptr;           // every level kept: per-block sums of the tau derivative
-    double *vpart = nullptr;           // and per-block shares of grad V . phib
-    hipGraph_t graph = nullptr;        // checkpoint mode: recompute and reverse sweep of one full segment
-    hipGraphExec_t gexec = nullptr;
-    // every level kept: the forward's own fields of each step (element size es)
-    void *Fs = nullptr, *Us = nullptr;    // [n][3][n_nodes] force density (active tiles), u(t+1)
-    void *phs = nullptr, *gvs = nullptr;  // [n][3][nv] phi_S + phi_W, dV/dq
-    double *dVs = nullptr;                // [n] V - V0
+    double *tpart = nullptr;           // per-block sums of the tau derivative
+    double *vpart = nullptr;           // per-block shares of grad V . phib
+    // the forward's own fields of each recorded step (element size es)
+    void *Fs = nullptr, *Us = nullptr;    // [steps][3][n_nodes] force density (active tiles), u(t+1)
+    void *phs = nullptr, *gvs = nullptr;  // [steps][3][nv] phi_S + phi_W, dV/dq
+    double *dVs = nullptr;                // [steps] V - V0
 };
 
 namespace {
@@ -1610,14 +1606,11 @@ void free_adjoint(iblb_ctx *c)
     AdjState *a = c->adj;
     if (!a) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (a->gexec) (void)hipGraphExecDestroy(a->gexec);
-    if (a->graph) (void)hipGraphDestroy(a->graph);
     for (char *p : a->ck) (void)hipFree(p);
-    if (a->store) (void)hipFree(a->store);
-    for (void *p : {a->Fs, a->Us, a->phs, a->gvs, (void *)a->dVs})
+    for (void *p : {a->store, a->Fs, a->Us, a->phs, a->gvs})
         if (p) (void)hipFree(p);
-    for (double *p : {a->qs, a->lam_buf[0], a->lam_buf[1], a->qb_buf[0], a->qb_buf[1], a->F, a->Fb, a->ub, a->phi,
-                      a->gV, a->phib, a->acc, a->grads, a->tpart, a->vpart})
+    for (double *p : {a->qs, a->dVs, a->lam_buf[0], a->lam_buf[1], a->qb_buf[0], a->qb_buf[1], a->Fb, a->ub,
+                      a->phib, a->grads, a->tpart, a->vpart})
         if (p) (void)hipFree(p);
     delete a;
     c->adj = nullptr;
@@ -1678,87 +1671,113 @@ AdjArgs adj_args(const iblb_ctx *c)
 
 void *level(AdjState *a, size_t n, int k) { return (char *)a->store + (size_t)k * 19 * n * a->es; }
 
-// Stores the populations (in the step's arithmetic precision) and positions
-// of the current time t as level k.
-hipError_t store_level(iblb_ctx *c, AdjState *a, long long t, int k)
-{
-    const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
-    hipError_t e = c->prec == IBLB_FP64
-                       ? launch_get_pops(c->prec, c->d, c->g, (int)(t & 1), (double *)level(a, n, k), c->stream)
-                       : launch_get_pops_f32(c->prec, c->d, c->g, (int)(t & 1), (float *)level(a, n, k), c->stream);
-    if (e == hipSuccess) e = adj_copy(a->qs + (size_t)k * 3 * nv, c->d.q, 3 * (long long)nv, c->stream);
-    return e;
-}
-
-// One reverse step: (lam[1], qb[1]) at t+1 -> (lam[0], qb[0]) at t, from the
-// stored levels k (time t) and k + 1.
-hipError_t reverse_step(iblb_ctx *c, AdjState *a, const AdjArgs &A, int k)
-{
-    const hipStream_t s = c->stream;
-    const size_t n = (size_t)c->g.n;
-    const Dev &d = c->d;
-    const int fp64 = a->es == 8;
-    const void *f0 = level(a, n, k), *f1 = level(a, n, k + 1);
-    const double *q = a->qs + (size_t)k * 3 * c->nv;
-    hipError_t e;
-#define ADJ_TRY(x)                    \
-    do {                              \
-        e = (x);                      \
-        if (e != hipSuccess) return e; \
-    } while (0)
-    ADJ_TRY(adj_zero_fields(a->F, a->ub, 3 * (long long)n, a->acc, s));
-    ADJ_TRY(adj_volume(A, q, d.Xref, d.faces, nullptr, a->acc, s));
-    ADJ_TRY(adj_vertex_forces(A, q, d.inc4, d.fref, a->acc, a->phi, a->gV, s));
-    ADJ_TRY(adj_spread2(A, q, a->phi, a->qb[1], a->F, a->ub, s));
-    ADJ_TRY(adj_moments(A, fp64, f1, a->F, a->ub, a->lam[1], s));
-    ADJ_TRY(adj_interp(A, fp64, q, a->qb[1], f1, a->F, a->qb[0], s));
-    ADJ_TRY(adj_lb(A, fp64, f0, f1, a->F, a->ub, a->lam[1], a->lam[0], a->Fb, a->grads, s));
-    ADJ_TRY(adj_interp_force(A, q, a->phi, a->Fb, a->phib, a->qb[0], s));
-    ADJ_TRY(adj_volume(A, q, d.Xref, d.faces, a->phib, a->acc + 2, s));
-    ADJ_TRY(adj_force_jvp(A, q, d.inc4, d.fref, a->phib, a->gV, a->acc + 2, a->qb[0], a->grads, s));
-#undef ADJ_TRY
-    std::swap(a->lam[0], a->lam[1]);
-    std::swap(a->qb[0], a->qb[1]);
-    return hipSuccess;
-}
-
-// Checkpoint mode: the recompute of one segment from its restored checkpoint
-// (time levels t .. t + len) and its reverse sweep, as launches on the
-// context stream (kernels only, so that it can be captured).
-hipError_t enqueue_segment(iblb_ctx *c, AdjState *a, const AdjArgs &A, long long t, int len)
-{
-    hipError_t e;
-    for (int k = 0; k <= len; ++k) {
-        e = store_level(c, a, t, k);
-        if (e == hipSuccess && k < len) {
-            e = enqueue_step(c, (int)(t & 1), false);
-            ++t;
-        }
-        if (e != hipSuccess) return e;
-    }
-    for (int k = len - 1; k >= 0; --k) {
-        e = reverse_step(c, a, A, k);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
+// Device memory for a recording of `levels` time levels (populations,
+// positions) and the fields of the levels - 1 steps between them, and the
+// reverse sweep's working arrays.
 int alloc_sweep(iblb_ctx *c, AdjState *a, size_t levels)
 {
-    const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
-    auto get = [&](double **p, size_t count) { return hipMalloc(p, std::max<size_t>(count, 1) * 8) == hipSuccess; };
-    if (hipMalloc(&a->store, levels * 19 * n * a->es) != hipSuccess) {
-        a->store = nullptr;
+    const size_t n = (size_t)c->g.n, nv = (size_t)c->nv, L = levels - 1, es = a->es;
+    auto getb = [](void **p, size_t bytes) {
+        if (hipMalloc(p, std::max<size_t>(bytes, 1)) == hipSuccess) return true;
+        *p = nullptr;
+        return false;
+    };
+    auto get = [&](double **p, size_t count) { return getb((void **)p, count * 8); };
+    if (!getb(&a->store, levels * 19 * n * es) || !getb(&a->Fs, L * 3 * n * es) || !getb(&a->Us, L * 3 * n * es) ||
+        !getb(&a->phs, L * 3 * nv * es) || !getb(&a->gvs, L * 3 * nv * es) || !get(&a->dVs, L) ||
+        !get(&a->qs, levels * 3 * nv))
         return fail(c, IBLB_E_DEVICE, "no device memory for " + std::to_string(levels) +
-                                          " stored time levels (record with a checkpoint interval instead)");
-    }
-    if (!get(&a->qs, levels * 3 * nv) || !get(&a->lam_buf[0], 19 * n) || !get(&a->lam_buf[1], 19 * n) ||
-        !get(&a->qb_buf[0], 3 * nv) || !get(&a->qb_buf[1], 3 * nv) || !get(&a->F, 3 * n) || !get(&a->Fb, 3 * n) ||
-        !get(&a->ub, 3 * n) || !get(&a->phi, 3 * nv) || !get(&a->gV, 3 * nv) || !get(&a->phib, 3 * nv) ||
-        !get(&a->acc, 4) || !get(&a->grads, 6) || !get(&a->tpart, (size_t)adj_lb_blocks((long long)n)) ||
+                                          " recorded time levels (record with a checkpoint interval instead)");
+    if (!get(&a->lam_buf[0], 19 * n) || !get(&a->lam_buf[1], 19 * n) || !get(&a->qb_buf[0], 3 * nv) ||
+        !get(&a->qb_buf[1], 3 * nv) || !get(&a->Fb, 3 * n) || !get(&a->ub, 3 * n) || !get(&a->phib, 3 * nv) ||
+        !get(&a->grads, 6) || !get(&a->tpart, (size_t)adj_lb_blocks((long long)n)) ||
         !get(&a->vpart, (size_t)adj_vertex_blocks((long long)nv)))
         return fail(c, IBLB_E_DEVICE, "no device memory for the reverse sweep");
     return IBLB_OK;
+}
+
+// Steps the context `len` times from its current time t0, recording time
+// levels 0 .. len (populations in the step's arithmetic precision, positions)
+// and the forward's own fields of each step (launch_record; the level index
+// comes from the device step counter).  With use_graph, full runs of
+// kGraphSteps steps from even times replay one captured graph.
+int record_steps(iblb_ctx *c, AdjState *a, int len, bool use_graph)
+{
+    const uint32_t t0 = (uint32_t)c->t, maxl = (uint32_t)len;
+    const uint32_t maxf = (uint32_t)len - 1u;  // field levels: the steps recorded
+    hipGraphExec_t gx = nullptr;
+    hipGraph_t gr = nullptr;
+    auto record = [&](int p) {
+        return launch_record(c->prec, c->d, c->g, c->m, p, t0, maxl, maxf, a->store, a->qs, a->Fs, a->Us, a->phs,
+                             a->gvs, a->dVs, c->stream);
+    };
+    auto one = [&](int p) {
+        hipError_t e = record(p);
+        return e == hipSuccess ? enqueue_step(c, p, false) : e;
+    };
+    int rc = IBLB_OK, left = len;
+    while (!rc && left > 0) {
+        const int p = (int)(c->t & 1);
+        hipError_t e = hipSuccess;
+        if (p == 0 && left >= kGraphSteps && use_graph && c->use_graph) {
+            if (!gx) {
+                e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+                hipError_t e1 = hipSuccess;
+                for (int k = 0; k < kGraphSteps && e == hipSuccess && e1 == hipSuccess; ++k) e1 = one(k & 1);
+                if (e == hipSuccess) e = hipStreamEndCapture(c->stream, &gr);
+                if (e == hipSuccess) e = e1;
+                if (e == hipSuccess) e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
+            }
+            if (e == hipSuccess) e = hipGraphLaunch(gx, c->stream);
+            c->t += kGraphSteps;
+            left -= kGraphSteps;
+        } else {
+            e = one(p);
+            c->t += 1;
+            left -= 1;
+        }
+        if (e != hipSuccess) rc = hip_fail(c, e, "recording the window");
+    }
+    if (!rc) {
+        hipError_t e = record((int)(c->t & 1));
+        if (e != hipSuccess) rc = hip_fail(c, e, "storing the last level");
+    }
+    if (gx || gr) {
+        if (c->stream) (void)hipStreamSynchronize(c->stream);
+        if (gx) (void)hipGraphExecDestroy(gx);
+        if (gr) (void)hipGraphDestroy(gr);
+    }
+    return rc;
+}
+
+// Reverse steps len - 1 .. 0 over the recorded levels: (lam[1], qb[1]) at
+// the end of the recording to the adjoints at its start.
+hipError_t reverse_steps(iblb_ctx *c, AdjState *a, const AdjArgs &A, int len)
+{
+    const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
+    const size_t fl = 3 * n * a->es, vl = 3 * nv * a->es;
+    for (int k = len - 1; k >= 0; --k) {
+        AdjLevel L;
+        L.f0 = level(a, n, k);
+        L.f1 = level(a, n, k + 1);
+        L.F = (const char *)a->Fs + (size_t)k * fl;
+        L.U = (const char *)a->Us + (size_t)k * fl;
+        L.phs = (const char *)a->phs + (size_t)k * vl;
+        L.gvs = (const char *)a->gvs + (size_t)k * vl;
+        L.dV = a->dVs + k;
+        L.q = a->qs + (size_t)k * 3 * nv;
+        L.Xref = c->d.Xref;
+        L.faces = c->d.faces;
+        L.inc4 = c->d.inc4;
+        L.fref = c->d.fref;
+        const AdjWork W{a->ub,   a->lam[1], a->lam[0], a->Fb,    a->phib,
+                        a->qb[1], a->qb[0], a->grads,  a->tpart, a->vpart};
+        hipError_t e = adj_reverse_kept(A, a->es == 8, L, W, c->stream);
+        if (e != hipSuccess) return e;
+        std::swap(a->lam[0], a->lam[1]);
+        std::swap(a->qb[0], a->qb[1]);
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -1778,61 +1797,13 @@ int iblb_adjoint_record(iblb_ctx *c, int32_t n_steps, int32_t every)
     a->es = c->prec == IBLB_FP64 ? 8 : 4;
     int rc = IBLB_OK;
     if (every == 0) {
-        // every time level kept: the reverse sweep needs no recompute.  Each
-        // step stores the level of its start time (the level index comes
-        // from the device step counter), in replays of one captured graph of
-        // kGraphSteps steps from even times and single launches otherwise.
+        // every time level kept: the reverse sweep needs no recompute
         rc = alloc_sweep(c, a, (size_t)n_steps + 1);
-        if (!rc) {
-            const size_t n = (size_t)c->g.n, nv = (size_t)c->nv, L = (size_t)n_steps;
-            if (hipMalloc(&a->Fs, L * 3 * n * a->es) != hipSuccess || hipMalloc(&a->Us, L * 3 * n * a->es) != hipSuccess ||
-                hipMalloc(&a->phs, L * 3 * nv * a->es) != hipSuccess ||
-                hipMalloc(&a->gvs, L * 3 * nv * a->es) != hipSuccess || hipMalloc(&a->dVs, L * 8) != hipSuccess)
-                rc = fail(c, IBLB_E_DEVICE, "no device memory for the kept fields (record with a checkpoint interval)");
-        }
-        const uint32_t t0 = (uint32_t)a->t0, maxl = (uint32_t)n_steps;
-        const uint32_t maxf = (uint32_t)n_steps - 1u;  // field levels: the steps of the window
-        hipGraphExec_t gx = nullptr;
-        hipGraph_t gr = nullptr;
-        auto record = [&](int p) {
-            return launch_record(c->prec, c->d, c->g, c->m, p, t0, maxl, maxf, a->store, a->qs, a->Fs, a->Us, a->phs,
-                                 a->gvs, a->dVs, c->stream);
-        };
-        auto one = [&](int p) {
-            hipError_t e = record(p);
-            return e == hipSuccess ? enqueue_step(c, p, false) : e;
-        };
-        int left = n_steps;
-        while (!rc && left > 0) {
-            const int p = (int)(c->t & 1);
-            hipError_t e = hipSuccess;
-            if (p == 0 && left >= kGraphSteps && c->use_graph) {
-                if (!gx) {
-                    e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
-                    hipError_t e1 = hipSuccess;
-                    for (int k = 0; k < kGraphSteps && e == hipSuccess && e1 == hipSuccess; ++k) e1 = one(k & 1);
-                    if (e == hipSuccess) e = hipStreamEndCapture(c->stream, &gr);
-                    if (e == hipSuccess) e = e1;
-                    if (e == hipSuccess) e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
-                }
-                if (e == hipSuccess) e = hipGraphLaunch(gx, c->stream);
-                c->t += kGraphSteps;
-                left -= kGraphSteps;
-            } else {
-                e = one(p);
-                c->t += 1;
-                left -= 1;
-            }
-            if (e != hipSuccess) rc = hip_fail(c, e, "recording the window");
-        }
-        if (!rc) {
-            hipError_t e = record((int)(c->t & 1));
-            if (e != hipSuccess) rc = hip_fail(c, e, "storing the last level");
-        }
+        if (!rc) rc = record_steps(c, a, n_steps, true);
         if (c->stream) (void)hipStreamSynchronize(c->stream);
-        if (gx) (void)hipGraphExecDestroy(gx);
-        if (gr) (void)hipGraphDestroy(gr);
     } else {
+        // a device copy of the whole state every `every` steps; the sweep
+        // records each segment again from its checkpoint
         a->snap = checkpoint_bytes(c);
         const int nseg = (n_steps + every - 1) / every;
         for (int k = 0; !rc && k <= nseg; ++k) {
@@ -1865,8 +1836,7 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
         rc = alloc_sweep(c, a, (size_t)a->every + 1);
         if (rc) return rc;
     }
-    // the same buffer roles at the start of every call (a captured segment
-    // graph has them built in)
+    // the same buffer roles at the start of every call
     for (int k = 0; k < 2; ++k) {
         a->lam[k] = a->lam_buf[k];
         a->qb[k] = a->qb_buf[k];
@@ -1878,75 +1848,38 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     HIP_TRY(c, hipMemcpyAsync(a->qb[1], soa.data(), 3 * nv * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemsetAsync(a->lam[1], 0, 19 * n * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(a->grads, 0, 6 * 8, c->stream));
+    // the sweep clears ub itself after this first zeroing; the tau
+    // derivative collects in per-block slots, added up below
+    HIP_TRY(c, hipMemsetAsync(a->ub, 0, 3 * n * 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(a->tpart, 0, (size_t)adj_lb_blocks((long long)n) * 8, c->stream));
     if (a->every == 0) {
-        // the kept-field sweep clears ub itself after this first zeroing; the
-        // tau derivative collects in per-block slots, added up below
-        HIP_TRY(c, hipMemsetAsync(a->ub, 0, 3 * n * 8, c->stream));
-        HIP_TRY(c, hipMemsetAsync(a->tpart, 0, (size_t)adj_lb_blocks((long long)n) * 8, c->stream));
-        const size_t fl = 3 * n * a->es, vl = 3 * nv * a->es;
-        for (int k = a->n - 1; k >= 0; --k) {
-            AdjLevel L;
-            L.f0 = level(a, n, k);
-            L.f1 = level(a, n, k + 1);
-            L.F = (const char *)a->Fs + (size_t)k * fl;
-            L.U = (const char *)a->Us + (size_t)k * fl;
-            L.phs = (const char *)a->phs + (size_t)k * vl;
-            L.gvs = (const char *)a->gvs + (size_t)k * vl;
-            L.dV = a->dVs + k;
-            L.q = a->qs + (size_t)k * 3 * nv;
-            L.Xref = c->d.Xref;
-            L.faces = c->d.faces;
-            L.inc4 = c->d.inc4;
-            L.fref = c->d.fref;
-            const AdjWork W{a->ub,   a->lam[1], a->lam[0], a->Fb,    a->phib,
-                            a->qb[1], a->qb[0], a->acc,    a->grads, a->tpart, a->vpart};
-            HIP_TRY(c, adj_reverse_kept(A, a->es == 8, L, W, c->stream));
-            std::swap(a->lam[0], a->lam[1]);
-            std::swap(a->qb[0], a->qb[1]);
-        }
+        HIP_TRY(c, reverse_steps(c, a, A, a->n));
     } else {
-        // Full segments replay one captured graph: with an even checkpoint
-        // interval every full segment starts at the parity of t0, and the
-        // ping-pong buffers are back in their roles at its end.  A shorter
-        // last segment, or an odd interval, is launched directly.
-        const bool use_graph = (a->every % 2) == 0 && c->use_graph;
+        // Segments from the last: restore its checkpoint, record it again
+        // with every level and field kept, sweep it backwards.
         const int nseg = (a->n + a->every - 1) / a->every;
-        drop_graph(c);
-        for (int sgm = nseg - 1; sgm >= 0; --sgm) {
+        const long long t_end = a->t0 + a->n;
+        for (int sgm = nseg - 1; !rc && sgm >= 0; --sgm) {
             rc = checkpoint(c, a->ck[(size_t)sgm], false);
-            if (rc) return rc;
-            const int len = std::min(a->every, a->n - sgm * a->every);
-            const long long t = a->t0 + (long long)sgm * a->every;
-            if (use_graph && len == a->every) {
-                if (!a->gexec) {
-                    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                    hipError_t e = enqueue_segment(c, a, A, t, len);
-                    hipGraph_t gr = nullptr;
-                    hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
-                    if (e != hipSuccess) {
-                        if (gr) (void)hipGraphDestroy(gr);
-                        return hip_fail(c, e, "reverse sweep capture");
-                    }
-                    HIP_TRY(c, e2);
-                    a->graph = gr;
-                    HIP_TRY(c, hipGraphInstantiate(&a->gexec, a->graph, nullptr, nullptr, 0));
-                }
-                HIP_TRY(c, hipGraphLaunch(a->gexec, c->stream));
-            } else {
-                HIP_TRY(c, enqueue_segment(c, a, A, t, len));
-            }
+            if (rc) break;
+            c->t = a->t0 + (long long)sgm * a->every;
+            rc = record_steps(c, a, std::min(a->every, a->n - sgm * a->every), false);
+            if (rc) break;
+            const hipError_t e = reverse_steps(c, a, A, std::min(a->every, a->n - sgm * a->every));
+            if (e != hipSuccess) rc = hip_fail(c, e, "reverse sweep");
         }
         // back to the end of the window
-        rc = checkpoint(c, a->ck[(size_t)nseg], false);
+        const int rc2 = checkpoint(c, a->ck[(size_t)nseg], false);
+        c->t = t_end;
         if (rc) return rc;
+        if (rc2) return rc2;
     }
     HIP_TRY(c, hipMemcpyAsync(grads, a->grads, 6 * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(soa.data(), a->qb[1], 3 * nv * 8, hipMemcpyDeviceToHost, c->stream));
-    std::vector<double> tp(a->every == 0 ? (size_t)adj_lb_blocks((long long)n) : 0);
-    if (!tp.empty())
-        HIP_TRY(c, hipMemcpyAsync(tp.data(), a->tpart, tp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> tp((size_t)adj_lb_blocks((long long)n));
+    HIP_TRY(c, hipMemcpyAsync(tp.data(), a->tpart, tp.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (double v : tp) grads[5] += v;  // the kept-field sweep's tau derivative, by blocks
+    for (double v : tp) grads[5] += v;  // the tau derivative, by blocks
     if (dJdq0)
         for (size_t i = 0; i < nv; ++i)
             for (int k = 0; k < 3; ++k) dJdq0[3 * i + k] = soa[(size_t)k * nv + i];

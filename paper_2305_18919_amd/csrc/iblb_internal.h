@@ -135,8 +135,8 @@ hipError_t launch_batch(int prec, int which, const DomRec *recs, const uint32_t 
 hipError_t launch_batch_errors(const DomRec *recs, int n, int *err, hipStream_t s);
 // Discrete adjoint of the step (iblb_adjoint.hip), FP64 arithmetic: the
 // constants of one context's step.  Fields are canonical [19][n] / [3][n]
-// arrays (deviations f - w rho0; FP64, or the step's own precision where a
-// kernel says so), vertex arrays SoA [3][nv].
+// arrays (deviations f - w rho0, in the step's own precision), vertex arrays
+// SoA [3][nv].
 struct AdjArgs {
     Grid g;
     int nv, nf, slots;
@@ -145,31 +145,8 @@ struct AdjArgs {
     double alpha[3], kv_over_V0, V0, eps_lo, eps_hi, xi, rc, z_lo, z_hi;
     double origin[3];
 };
-hipError_t adj_zero(double *p, long long n, hipStream_t s);
-hipError_t adj_copy(double *dst, const double *src, long long n, hipStream_t s);
-// F = ub = 0 ([3][n] each) and acc[0..3] = 0
-hipError_t adj_zero_fields(double *F, double *ub, long long n3, double *acc, hipStream_t s);
-// acc[0] += V - V0, acc[1] += grad V . dir (dir may be null)
-hipError_t adj_volume(const AdjArgs &A, const double *q, const double *X, const int *faces, const double *dir,
-                      double *acc, hipStream_t s);
-// nodal forces phi and grad V per vertex (acc[0] = V - V0)
-hipError_t adj_vertex_forces(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref,
-                             const double *acc, double *phi, double *gV, hipStream_t s);
-// F(x) += sum_i delta(x - q_i) phi_i, ub(x) += sum_i delta(x - q_i) qb_i on the fluid nodes
-hipError_t adj_spread2(const AdjArgs &A, const double *q, const double *phi, const double *qb, double *F, double *ub,
-                       hipStream_t s);
-// stored populations f0 = f(t), f1 = f(t+1): double (fp64 != 0) or float
-hipError_t adj_moments(const AdjArgs &A, int fp64, const void *f1, const double *F, const double *ub, double *lam,
-                       hipStream_t s);
-hipError_t adj_interp(const AdjArgs &A, int fp64, const double *q, const double *qb1, const void *f1,
-                      const double *F, double *qb0, hipStream_t s);
-// lam0 and Fb from lam1; grads[5] += the tau derivative of this step
-hipError_t adj_lb(const AdjArgs &A, int fp64, const void *f0, const void *f1, const double *F, double *ub,
-                  const double *lam1, double *lam0, double *Fb, double *grads, hipStream_t s);
-hipError_t adj_interp_force(const AdjArgs &A, const double *q, const double *phi, const double *Fb, double *phib,
-                            double *qb0, hipStream_t s);
-// One reverse step of a window whose every level was kept with its fields
-// (launch_record): the level's arrays, element type
+// One reverse step from a recording (launch_record; every level of the
+// window, or of one checkpoint segment): the level's arrays, element type
 // double (fp64 != 0) or float, and the working arrays of the sweep.
 struct AdjLevel {
     const void *f0, *f1;          // populations of time t and t + 1
@@ -183,7 +160,12 @@ struct AdjLevel {
     const double *fref;
 };
 struct AdjWork {
-    double *ub, *lam1, *lam0, *Fb, *phib, *qb1, *qb0, *acc, *grads;
+    double *ub;     // [3][n] adjoint of u', zero at the step's start (ka_lb_adj clears it)
+    double *lam1, *lam0;      // [19][n] adjoint populations at t + 1 and t (element type of the level)
+    double *Fb;               // [3][n]
+    double *phib, *qb1, *qb0; // [3][nv]
+    double *grads;            // [6]: grads[0..4] accumulate here
+
     double *tpart;  // [adj_lb_blocks(n)] per-block running sums of the tau derivative
     double *vpart;  // [adj_vertex_blocks(nv)] per-block shares of grad V . phib
 };
@@ -192,12 +174,8 @@ struct AdjWork {
 inline int adj_lb_blocks(long long n) { return (int)((n + 255) / 256); }
 inline int adj_vertex_blocks(long long nv) { return (int)((64 * nv + 255) / 256); }
 hipError_t adj_reverse_kept(const AdjArgs &A, int fp64, const AdjLevel &L, const AdjWork &w, hipStream_t s);
-// grads[0..4] += the alpha_1..3, k_V and eps_lo derivatives of this step
-hipError_t adj_force_jvp(const AdjArgs &A, const double *q, const int4 *inc4, const double *fref, const double *phib,
-                         const double *gV, const double *acc, double *qb0, double *grads, hipStream_t s);
 // debug / query kernels
 hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double *out, hipStream_t s);
-hipError_t launch_get_pops_f32(int prec, const Dev &d, const Grid &g, int p, float *out, hipStream_t s);
 // One step of an adjoint recording (device step counter t = ctr[p]): the
 // populations (double for FP64 storage, else float) and positions of time t
 // into level t - t0 (at most maxl) of [level][19][n] and [level][3][nv]; the

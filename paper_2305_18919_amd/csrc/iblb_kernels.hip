@@ -1787,18 +1787,6 @@ hipError_t launch_stamp(const Dev &d, const Grid &g, const MeshArgs &m, int p, h
     return hipGetLastError();
 }
 
-// populations in the arithmetic precision of the step: exact for every
-// storage precision except FP64 (prec 0), which this launcher rejects
-hipError_t launch_get_pops_f32(int prec, const Dev &d, const Grid &g, int p, float *out, hipStream_t s)
-{
-    if (prec == 0)
-        return hipErrorInvalidValue;
-    return with_pop_type(prec, [&](auto tag) {
-        using S = decltype(tag);
-        k_get_pops<S, float><<<lb_grid(g), lb_block(g), 0, s>>>((const S *)d.f, p, out, g);
-    });
-}
-
 hipError_t launch_record(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, uint32_t t0, uint32_t maxl,
                          uint32_t maxf, void *store, double *qs, void *Fs, void *Us, void *phs, void *gvs,
                          double *dVs, hipStream_t s)

@@ -21,6 +21,7 @@ UNIT = {iblb.FP16_DEV: 2.0 ** -11, iblb.BF16_DEV: 2.0 ** -8}
 CASES = {
     "walls_ragged": Domain(30, 22, 19, tau=0.8, u_wall_lo=(0.01, -0.005, 0), u_wall_hi=(-0.02, 0.01, 0)),
     "periodic_ragged": Domain(20, 13, 11, wall_mode=PERIODIC_ALL, tau=1.3, body_force=(1e-5, 0, -2e-5)),
+    "wide_rows_ragged": Domain(140, 9, 10, tau=0.9, u_wall_lo=(0.004, 0.002, 0), u_wall_hi=(-0.003, 0, 0)),
 }
 
 
