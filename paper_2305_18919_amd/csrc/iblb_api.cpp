@@ -1601,17 +1601,15 @@ struct AdjState {
 
 namespace {
 
+void free_sweep(AdjState *a);
+
 void free_adjoint(iblb_ctx *c)
 {
     AdjState *a = c->adj;
     if (!a) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (char *p : a->ck) (void)hipFree(p);
-    for (void *p : {a->store, a->Fs, a->Us, a->phs, a->gvs})
-        if (p) (void)hipFree(p);
-    for (double *p : {a->qs, a->dVs, a->lam_buf[0], a->lam_buf[1], a->qb_buf[0], a->qb_buf[1], a->Fb, a->ub,
-                      a->phib, a->grads, a->tpart, a->vpart})
-        if (p) (void)hipFree(p);
+    free_sweep(a);
     delete a;
     c->adj = nullptr;
 }
@@ -1671,9 +1669,24 @@ AdjArgs adj_args(const iblb_ctx *c)
 
 void *level(AdjState *a, size_t n, int k) { return (char *)a->store + (size_t)k * 19 * n * a->es; }
 
+// Frees the recording buffers and working arrays of the reverse sweep (not
+// the checkpoints).
+void free_sweep(AdjState *a)
+{
+    for (void **p : {&a->store, &a->Fs, &a->Us, &a->phs, &a->gvs}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    for (double **p : {&a->qs, &a->dVs, &a->lam_buf[0], &a->lam_buf[1], &a->qb_buf[0], &a->qb_buf[1], &a->Fb, &a->ub,
+                       &a->phib, &a->grads, &a->tpart, &a->vpart}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+}
+
 // Device memory for a recording of `levels` time levels (populations,
 // positions) and the fields of the levels - 1 steps between them, and the
-// reverse sweep's working arrays.
+// reverse sweep's working arrays; on failure nothing stays allocated.
 int alloc_sweep(iblb_ctx *c, AdjState *a, size_t levels)
 {
     const size_t n = (size_t)c->g.n, nv = (size_t)c->nv, L = levels - 1, es = a->es;
@@ -1685,14 +1698,18 @@ int alloc_sweep(iblb_ctx *c, AdjState *a, size_t levels)
     auto get = [&](double **p, size_t count) { return getb((void **)p, count * 8); };
     if (!getb(&a->store, levels * 19 * n * es) || !getb(&a->Fs, L * 3 * n * es) || !getb(&a->Us, L * 3 * n * es) ||
         !getb(&a->phs, L * 3 * nv * es) || !getb(&a->gvs, L * 3 * nv * es) || !get(&a->dVs, L) ||
-        !get(&a->qs, levels * 3 * nv))
+        !get(&a->qs, levels * 3 * nv)) {
+        free_sweep(a);
         return fail(c, IBLB_E_DEVICE, "no device memory for " + std::to_string(levels) +
                                           " recorded time levels (record with a checkpoint interval instead)");
+    }
     if (!get(&a->lam_buf[0], 19 * n) || !get(&a->lam_buf[1], 19 * n) || !get(&a->qb_buf[0], 3 * nv) ||
         !get(&a->qb_buf[1], 3 * nv) || !get(&a->Fb, 3 * n) || !get(&a->ub, 3 * n) || !get(&a->phib, 3 * nv) ||
         !get(&a->grads, 6) || !get(&a->tpart, (size_t)adj_lb_blocks((long long)n)) ||
-        !get(&a->vpart, (size_t)adj_vertex_blocks((long long)nv)))
+        !get(&a->vpart, (size_t)adj_vertex_blocks((long long)nv))) {
+        free_sweep(a);
         return fail(c, IBLB_E_DEVICE, "no device memory for the reverse sweep");
+    }
     return IBLB_OK;
 }
 
@@ -1832,8 +1849,8 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     int rc = sync_ctx(c);
     if (rc) return rc;
     const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
-    if (!a->lam_buf[0]) {
-        rc = alloc_sweep(c, a, (size_t)a->every + 1);
+    if (!a->lam_buf[0]) {  // checkpoint mode: buffers for one segment, allocated at the first sweep
+        rc = alloc_sweep(c, a, (size_t)std::min(a->every, a->n) + 1);
         if (rc) return rc;
     }
     // the same buffer roles at the start of every call
