@@ -27,8 +27,9 @@
 // along phib, computed with dual numbers.  The forward's own force density,
 // u(t+1) and nodal force parts of each step are read back from the recording
 // (every level of the window, or of one checkpoint segment at a time), so
-// nothing of the forward is recomputed here, and the adjoint lam is stored in
-// the step's own precision (FP32 for an FP32 step).
+// nothing of the forward is recomputed here, and the adjoints lam and ub are
+// stored in the step's own precision (FP32 for an FP32 step); ub accumulates
+// with atomic adds, whose order is not fixed.
 #include "iblb_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -310,7 +311,7 @@ __device__ __forceinline__ T ld32(const T *base, uint32_t byte_off)
 
 template <typename P>
 __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict__ f0, const P *__restrict__ f1,
-                                                 const P *__restrict__ F, double *__restrict__ ub,
+                                                 const P *__restrict__ F, P *__restrict__ ub,
                                                  double *__restrict__ tslot, const P *__restrict__ lam1,
                                                  P *__restrict__ lam0, double *__restrict__ Fb)
 {
@@ -408,7 +409,7 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
         }
         tb[0] = tt;
         double fb0 = g0 + 0.5 * b0 * ir, fb1 = g1 + 0.5 * b1 * ir, fb2 = g2 + 0.5 * b2 * ir;
-        const double ub0 = ub[id], ub1 = ub[n + id], ub2 = ub[2 * n + id];
+        const double ub0 = double(ub[id]), ub1 = double(ub[n + id]), ub2 = double(ub[2 * n + id]);
         if (ub0 != 0.0 || ub1 != 0.0 || ub2 != 0.0) {
             double d1 = 0.0;
 #pragma unroll
@@ -418,9 +419,9 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
             fb1 += ub1 * h;
             fb2 += ub2 * h;
             // this thread was its last reader: zero for the next step's spread
-            ub[id] = 0.0;
-            ub[n + id] = 0.0;
-            ub[2 * n + id] = 0.0;
+            ub[id] = P(0);
+            ub[n + id] = P(0);
+            ub[2 * n + id] = P(0);
         }
         Fb[id] = fb0;
         Fb[n + id] = fb1;
@@ -520,12 +521,12 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
 // lam_j += (c_j - u') . ub / rho1 where ub != 0, u' from U, rho1 from f1
 template <typename P>
 __global__ __launch_bounds__(256) void ka_moments_adj_u(AdjArgs A, const P *__restrict__ f1, const P *__restrict__ U,
-                                                        const double *__restrict__ ub, P *__restrict__ lam)
+                                                        const P *__restrict__ ub, P *__restrict__ lam)
 {
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = A.g.n;
     if (id >= n) return;
-    const double b[3] = {ub[id], ub[n + id], ub[2 * n + id]};
+    const double b[3] = {double(ub[id]), double(ub[n + id]), double(ub[2 * n + id])};
     if (b[0] == 0.0 && b[1] == 0.0 && b[2] == 0.0) return;
     double dr = 0.0;
 #pragma unroll
@@ -544,7 +545,7 @@ __global__ __launch_bounds__(256) void ka_moments_adj_u(AdjArgs A, const P *__re
 template <typename P>
 __global__ __launch_bounds__(256) void ka_spread_interp_u(AdjArgs A, const double *__restrict__ q,
                                                           const double *__restrict__ qb1, const P *__restrict__ U,
-                                                          double *ub, double *__restrict__ qb0)
+                                                          P *ub, double *__restrict__ qb0)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = (int)(t >> 6), k = (int)(t & 63);
@@ -560,7 +561,7 @@ __global__ __launch_bounds__(256) void ka_spread_interp_u(AdjArgs A, const doubl
         if (nd.id >= 0) {
             for (int c = 0; c < 3; ++c) u[c] = double(U[c * n + nd.id]);
             if (nd.w != 0.0)
-                for (int c = 0; c < 3; ++c) atomicAdd(ub + c * n + nd.id, b[c] * nd.w);
+                for (int c = 0; c < 3; ++c) atomicAdd(ub + c * n + nd.id, P(b[c] * nd.w));
         } else {
             for (int c = 0; c < 3; ++c) u[c] = nd.side ? A.uhi[c] : A.ulo[c];
         }
@@ -636,9 +637,10 @@ static hipError_t reverse_kept(const AdjArgs &A, const AdjLevel &L, const AdjWor
     const P *phs = (const P *)L.phs, *gvs = (const P *)L.gvs;
     // ub starts at zero (cleared by the sweep's caller, then by ka_lb_adj of
     // every step); grad V . phib goes through per-block partial sums
-    ka_spread_interp_u<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, U, w.ub, w.qb0);
-    ka_moments_adj_u<P><<<blocks_for(n), 256, 0, s>>>(A, f1, U, w.ub, (P *)w.lam1);
-    ka_lb_adj<P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, w.ub, w.tpart, (const P *)w.lam1, (P *)w.lam0, w.Fb);
+    P *ub = (P *)w.ub;
+    ka_spread_interp_u<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, U, ub, w.qb0);
+    ka_moments_adj_u<P><<<blocks_for(n), 256, 0, s>>>(A, f1, U, ub, (P *)w.lam1);
+    ka_lb_adj<P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, ub, w.tpart, (const P *)w.lam1, (P *)w.lam0, w.Fb);
     const int nvp = blocks_for(64ll * A.nv);
     ka_interp_force_s<P><<<nvp, 256, 0, s>>>(A, L.q, phs, gvs, L.dV, w.Fb, w.phib, w.qb0, w.vpart);
     ka_force_jvp<P><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, L.q, L.inc4, L.fref, w.phib, gvs, L.dV, w.vpart, nvp,
