@@ -298,9 +298,11 @@ int iblb_batch_destroy(iblb_batch *b);
  *  every = 0: every time level and the forward's own fields of each step in
  *    device memory, in the step's arithmetic precision (FP64 for FP64
  *    storage, FP32 otherwise): per step 25 x N values (populations, force
- *    density, velocity), 6 x n_vertices values (nodal force parts, dV/dq) and
- *    3 x n_vertices + 1 doubles (positions, V - V0); the sweep then
- *    recomputes nothing.  Its adjoint populations are stored in the same
+ *    density, velocity), 6 x n_vertices values (nodal force parts, dV/dq),
+ *    3 x n_vertices + 1 doubles (positions, V - V0), and the step's tile
+ *    vertex masks and active-tile list (tiles x (8 ceil(n_vertices / 64) + 4)
+ *    bytes, tiles = ceil(nx/4) ceil(ny/4) ceil(N / (nx ny) / 4)); the sweep
+ *    then recomputes nothing.  Its adjoint populations are stored in the same
  *    precision.
  *  every > 0: a device copy of the whole context state every `every` steps;
  *    the sweep restores each segment's checkpoint, records the segment again

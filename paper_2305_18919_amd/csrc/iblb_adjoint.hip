@@ -11,9 +11,9 @@
 // Given the adjoints lam(t+1) of f(t+1) and qb(t+1) of q(t+1), the kernels
 // below produce lam(t), qb(t) and add this step's share of the parameter
 // derivatives, in the reverse order of the forward operations:
-//   ka_spread_interp_u   ub(x) = sum_i delta(x - q_i) qb_i (the adjoint of u'),
-//                        and qb(t) = qb(t+1) + sum_x (u'(x) . qb) grad_q delta
-//   ka_moments_adj_u     lam(t+1) += d u'/d f(t+1)^T ub
+//   ka_spread_tiles      ub(x) = sum_i delta(x - q_i) qb_i (the adjoint of u'),
+//                        gathered per tile, and lam(t+1) += d u'/d f(t+1)^T ub;
+//                        qb(t) = qb(t+1) + sum_x (u'(x) . qb) grad_q delta
 //   ka_lb_adj            lam(t) from lam(t+1): propagation reversed (a pull),
 //                        then the transposed Jacobian of the collision;
 //                        Fb = d f*/d F^T Lam + ub / (2 rho'), tau derivative
@@ -28,8 +28,7 @@
 // u(t+1) and nodal force parts of each step are read back from the recording
 // (every level of the window, or of one checkpoint segment at a time), so
 // nothing of the forward is recomputed here, and the adjoints lam and ub are
-// stored in the step's own precision (FP32 for an FP32 step); ub accumulates
-// with atomic adds, whose order is not fixed.
+// stored in the step's own precision (FP32 for an FP32 step).
 #include "iblb_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -518,50 +517,36 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
 // the force density F, u(t+1) in U, the nodal force parts and V - V0 of each
 // step come from the forward itself (element type P), so nothing is recomputed
 
-// lam_j += (c_j - u') . ub / rho1 where ub != 0, u' from U, rho1 from f1
-template <typename P>
-__global__ __launch_bounds__(256) void ka_moments_adj_u(AdjArgs A, const P *__restrict__ f1, const P *__restrict__ U,
-                                                        const P *__restrict__ ub, P *__restrict__ lam)
+__device__ __forceinline__ int wave_incl_scan(int c, int lane)
 {
-    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long n = A.g.n;
-    if (id >= n) return;
-    const double b[3] = {double(ub[id]), double(ub[n + id]), double(ub[2 * n + id])};
-    if (b[0] == 0.0 && b[1] == 0.0 && b[2] == 0.0) return;
-    double dr = 0.0;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) dr += double(f1[i * n + id]);
-    const double ir = 1.0 / (A.rho0 + dr);
-    const double ub_u = b[0] * double(U[id]) + b[1] * double(U[n + id]) + b[2] * double(U[2 * n + id]);
-#pragma unroll
-    for (int j = 0; j < 19; ++j)
-        lam[j * n + id] = P(double(lam[j * n + id]) + (kCx[j] * b[0] + kCy[j] * b[1] + kCz[j] * b[2] - ub_u) * ir);
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(c, off, 64);
+        c += lane >= off ? y : 0;
+    }
+    return c;
 }
 
-// One lane per (vertex, stencil node), both adjoints that start from qb1:
-//   ub(x) += sum_i delta(x - q_i) qb1_i over the fluid nodes (the adjoint of u'),
-//   qb0_i = qb1_i + sum_x (u'(x) . qb1_i) grad_q delta(x - q_i), u' from U
-//   (the wall velocity at a wall node).
+// One wavefront per vertex, one lane per stencil node (t = thread index from
+// the first vertex block): qb0_i = qb1_i + sum_x (u'(x) . qb1_i) grad_q
+// delta(x - q_i), u' from U (the wall velocity at a wall node).
 template <typename P>
-__global__ __launch_bounds__(256) void ka_spread_interp_u(AdjArgs A, const double *__restrict__ q,
-                                                          const double *__restrict__ qb1, const P *__restrict__ U,
-                                                          P *ub, double *__restrict__ qb0)
+__device__ __forceinline__ void interp_adj_u(const AdjArgs &A, const double *__restrict__ q,
+                                             const double *__restrict__ qb1, const P *__restrict__ U,
+                                             double *__restrict__ qb0, long long t)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = (int)(t >> 6), k = (int)(t & 63);
-    if (v >= A.nv) return;  // whole wavefronts take the same branch
     const int nv = A.nv;
     const long long n = A.g.n;
+    const int v = (int)(t >> 6), lane = (int)(t & 63);
+    if (v >= nv) return;  // whole wavefronts take the same branch
     const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
     const double b[3] = {qb1[v], qb1[nv + v], qb1[2 * nv + v]};
     double s[3] = {0.0, 0.0, 0.0};
     if (finite_pos(qx, qy, qz)) {
-        const Node nd = stencil_node(A, qx, qy, qz, k);
+        const Node nd = stencil_node(A, qx, qy, qz, lane);
         double u[3];
         if (nd.id >= 0) {
             for (int c = 0; c < 3; ++c) u[c] = double(U[c * n + nd.id]);
-            if (nd.w != 0.0)
-                for (int c = 0; c < 3; ++c) atomicAdd(ub + c * n + nd.id, P(b[c] * nd.w));
         } else {
             for (int c = 0; c < 3; ++c) u[c] = nd.side ? A.uhi[c] : A.ulo[c];
         }
@@ -569,8 +554,158 @@ __global__ __launch_bounds__(256) void ka_spread_interp_u(AdjArgs A, const doubl
         for (int c = 0; c < 3; ++c) s[c] = ubq * nd.gw[c];
     }
     for (int c = 0; c < 3; ++c) s[c] = wave_sum64(s[c]);
-    if (k == 0)
+    if (lane == 0)
         for (int c = 0; c < 3; ++c) qb0[c * nv + v] = b[c] + s[c];
+}
+
+// Tile blocks (lane = node), striding over the forward step's list of active
+// tiles: the adjoint of u' gathered from the vertices whose stencil reaches
+// the tile (the tile's vertex mask as the forward spread it), ub(x) =
+// sum_i delta(x - q_i) qb1_i, written for every node of the tile; then, where
+// ub != 0, the adjoint of u' = (sum c f1 + F/2) / rho1 with respect to f1:
+// lam_j += (c_j - u') . ub / rho1, u' from U.  The list comes out in
+// ascending vertex order and four wavefronts each sum a quarter of it, so the
+// sums have a fixed order (no atomics).  Wavefront 0 fetches its nodes' f1,
+// U and lam when the tile is known, so that those loads overlap the gather.
+// Blocks ntb and after: interp_adj_u, one wavefront per vertex.
+template <typename P>
+__global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *__restrict__ q,
+                                                       const double *__restrict__ qb1, const P *__restrict__ f1,
+                                                       const P *__restrict__ U, const uint64_t *__restrict__ mask,
+                                                       const int *__restrict__ alist, const uint32_t *__restrict__ acnt,
+                                                       int ntb, P *__restrict__ ub, P *__restrict__ lam,
+                                                       double *__restrict__ qb0, int *err)
+{
+    const Grid &g = A.g;
+    const int nv = A.nv;
+    const long long n = g.n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if ((int)blockIdx.x >= ntb) {
+        interp_adj_u<P>(A, q, qb1, U, qb0, (long long)(blockIdx.x - ntb) * blockDim.x + tid);
+        return;
+    }
+    __shared__ int sid[kTileCap];
+    __shared__ P sw[kTileCap * 12];      // per listed vertex: its weights at the tile's 4 x, 4 y, 4 z positions
+    __shared__ double sqb[kTileCap * 3];  // and qb1
+    __shared__ int swt[4];
+    __shared__ double part[3][3][64];
+    const int W = (nv + 63) >> 6, J = (W + 255) >> 8;  // mask words per thread: at most 4 (65536 vertices)
+    // the first tile is read together with the count (clamped into the list;
+    // volatile, so that it is not deferred past the test on the count)
+    int tile = ((const volatile int *)alist)[(int)blockIdx.x < g.nt ? (int)blockIdx.x : 0];
+    const uint32_t na = acnt[0];
+    for (uint32_t ai = blockIdx.x; ai < na; ai += (uint32_t)ntb) {
+        if (ai != blockIdx.x)
+            tile = alist[ai];
+        const uint64_t *mw = mask + (long long)tile * W;
+        // wavefront 0: its node of the tile, and that node's f1, U and lam
+        const int tz = tile / (g.ntx * g.nty);
+        const int rem = tile - tz * g.ntx * g.nty;
+        const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
+        const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+        const int x = tx * 4 + lx, y = ty * 4 + ly, zf = tz * 4 + lz;
+        const bool node = wave == 0 && x < g.nx && y < g.ny && zf < g.nzf;
+        const long long id = ((long long)zf * g.ny + y) * g.nx + x;
+        P fv[19], lv[19], uv[3];
+        if (node) {
+#pragma unroll
+            for (int k = 0; k < 19; ++k) {
+                fv[k] = f1[k * n + id];
+                lv[k] = lam[k * n + id];
+            }
+            for (int k = 0; k < 3; ++k) uv[k] = U[k * n + id];
+        }
+        const int w0 = tid * J;
+        uint64_t wv[4];
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            wv[j] = (j < J && w0 + j < W) ? mw[w0 + j] : 0ull;
+            c += __popcll(wv[j]);
+        }
+        const int incl = wave_incl_scan(c, lane);
+        if (lane == 63)
+            swt[wave] = incl;
+        __syncthreads();
+        const int tot = swt[0] + swt[1] + swt[2] + swt[3];
+        // the list in ascending vertex order
+        int pos = incl - c;
+        for (int w = 0; w < wave; ++w)
+            pos += swt[w];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint64_t word = wv[j];
+            while (word != 0ull) {
+                const int bit = __ffsll((unsigned long long)word) - 1;
+                word &= word - 1ull;
+                if (pos < kTileCap)
+                    sid[pos] = (w0 + j) * 64 + bit;
+                ++pos;
+            }
+        }
+        const int nent = tot < kTileCap ? tot : kTileCap;
+        if (tot > kTileCap && tid == 0)
+            atomicOr(err, kErrOverflow);
+        __syncthreads();
+        const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 4 + g.zoff;  // lattice coordinates of the tile's first node
+        for (int e = tid; e < nent; e += 256) {
+            const int v = sid[e] < nv ? sid[e] : 0;  // (marks name vertices below nv only)
+            const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+            const int bx = (int)floor(qx) - 1, by = (int)floor(qy) - 1, bz = (int)floor(qz) - 1;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                // offset of the tile's node in the vertex's stencil (0..3 inside)
+                const int ox = wrapn(x0 + l - bx, g.nx), oy = wrapn(y0 + l - by, g.ny);
+                const int oz = g.walls ? z0 + l - bz : wrapn(z0 + l - bz, g.nz);
+                sw[e * 12 + l] = P(ox <= 3 ? phi4d(double(bx + ox) - qx) : 0.0);
+                sw[e * 12 + 4 + l] = P(oy <= 3 ? phi4d(double(by + oy) - qy) : 0.0);
+                sw[e * 12 + 8 + l] = P(oz >= 0 && oz <= 3 ? phi4d(double(bz + oz) - qz) : 0.0);
+            }
+            for (int k = 0; k < 3; ++k) sqb[e * 3 + k] = qb1[k * nv + v];
+        }
+        __syncthreads();
+        const int chunk = (nent + 3) >> 2;
+        const int e0 = wave * chunk, e1 = min(nent, e0 + chunk);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            const double w = double(sw[e * 12 + lx]) * double(sw[e * 12 + 4 + ly]) * double(sw[e * 12 + 8 + lz]);
+            s0 += sqb[e * 3] * w;
+            s1 += sqb[e * 3 + 1] * w;
+            s2 += sqb[e * 3 + 2] * w;
+        }
+        if (wave > 0) {
+            part[wave - 1][0][lane] = s0;
+            part[wave - 1][1][lane] = s1;
+            part[wave - 1][2][lane] = s2;
+        }
+        __syncthreads();
+        // wavefront 0 finishes the tile; the others go on to the next, whose
+        // first barrier wavefront 0 reaches only after this
+        if (wave == 0) {
+            for (int w = 0; w < 3; ++w) {
+                s0 += part[w][0][lane];
+                s1 += part[w][1][lane];
+                s2 += part[w][2][lane];
+            }
+            if (node) {
+                const P u0 = P(s0), u1 = P(s1), u2 = P(s2);
+                ub[id] = u0;
+                ub[n + id] = u1;
+                ub[2 * n + id] = u2;
+                const double b[3] = {double(u0), double(u1), double(u2)};
+                if (b[0] != 0.0 || b[1] != 0.0 || b[2] != 0.0) {
+                    double dr = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 19; ++k) dr += double(fv[k]);
+                    const double ir = 1.0 / (A.rho0 + dr);
+                    const double ub_u = b[0] * double(uv[0]) + b[1] * double(uv[1]) + b[2] * double(uv[2]);
+#pragma unroll
+                    for (int j = 0; j < 19; ++j)
+                        lam[j * n + id] = P(double(lv[j]) + (kCx[j] * b[0] + kCy[j] * b[1] + kCz[j] * b[2] - ub_u) * ir);
+                }
+            }
+        }
+    }
 }
 
 // phib_i = sum_x Fb delta and qb0_i += sum_x (Fb . phi_i) grad_q delta, with
@@ -638,8 +773,11 @@ static hipError_t reverse_kept(const AdjArgs &A, const AdjLevel &L, const AdjWor
     // ub starts at zero (cleared by the sweep's caller, then by ka_lb_adj of
     // every step); grad V . phib goes through per-block partial sums
     P *ub = (P *)w.ub;
-    ka_spread_interp_u<P><<<blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, U, ub, w.qb0);
-    ka_moments_adj_u<P><<<blocks_for(n), 256, 0, s>>>(A, f1, U, ub, (P *)w.lam1);
+    // tile blocks for the active-tile count expected at set-up, with a
+    // quarter in reserve; they stride over the list if it grows beyond that
+    const int ntb = A.tile_blocks;
+    ka_spread_tiles<P><<<ntb + blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, f1, U, L.mask, L.alist, L.acnt,
+                                                                       ntb, ub, (P *)w.lam1, w.qb0, w.err);
     ka_lb_adj<P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, ub, w.tpart, (const P *)w.lam1, (P *)w.lam0, w.Fb);
     const int nvp = blocks_for(64ll * A.nv);
     ka_interp_force_s<P><<<nvp, 256, 0, s>>>(A, L.q, phs, gvs, L.dV, w.Fb, w.phib, w.qb0, w.vpart);

@@ -1593,6 +1593,9 @@ struct AdjState {
     double *grads = nullptr;           // [6]
     double *tpart = nullptr;           // per-block sums of the tau derivative
     double *vpart = nullptr;           // per-block shares of grad V . phib
+    uint64_t *mask_s = nullptr;           // [levels][tiles][nwords] tile vertex masks of the positions
+    int *alist_s = nullptr;               // [steps][tiles] active tiles of each step
+    uint32_t *acnt_s = nullptr;           // [steps] and their count
     // the forward's own fields of each recorded step (element size es)
     void *Fs = nullptr, *Us = nullptr;    // [steps][3][n_nodes] force density (active tiles), u(t+1)
     void *phs = nullptr, *gvs = nullptr;  // [steps][3][nv] phi_S + phi_W, dV/dq
@@ -1664,6 +1667,8 @@ AdjArgs adj_args(const iblb_ctx *c)
     A.rc = c->m.rc;
     A.z_lo = c->m.z_lo;
     A.z_hi = c->m.z_hi;
+    const int hint = std::max(1, c->m.tiles_hint);
+    A.tile_blocks = std::min(c->g.nt, hint + hint / 4 + 16);
     return A;
 }
 
@@ -1673,7 +1678,8 @@ void *level(AdjState *a, size_t n, int k) { return (char *)a->store + (size_t)k 
 // the checkpoints).
 void free_sweep(AdjState *a)
 {
-    for (void **p : {&a->store, &a->Fs, &a->Us, &a->phs, &a->gvs}) {
+    for (void **p : {&a->store, &a->Fs, &a->Us, &a->phs, &a->gvs, (void **)&a->mask_s, (void **)&a->alist_s,
+                     (void **)&a->acnt_s}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -1698,7 +1704,9 @@ int alloc_sweep(iblb_ctx *c, AdjState *a, size_t levels)
     auto get = [&](double **p, size_t count) { return getb((void **)p, count * 8); };
     if (!getb(&a->store, levels * 19 * n * es) || !getb(&a->Fs, L * 3 * n * es) || !getb(&a->Us, L * 3 * n * es) ||
         !getb(&a->phs, L * 3 * nv * es) || !getb(&a->gvs, L * 3 * nv * es) || !get(&a->dVs, L) ||
-        !get(&a->qs, levels * 3 * nv)) {
+        !get(&a->qs, levels * 3 * nv) ||
+        !getb((void **)&a->mask_s, levels * (size_t)c->g.nt * (size_t)c->m.nwords * 8) ||
+        !getb((void **)&a->alist_s, L * (size_t)c->g.nt * 4) || !getb((void **)&a->acnt_s, L * 4)) {
         free_sweep(a);
         return fail(c, IBLB_E_DEVICE, "no device memory for " + std::to_string(levels) +
                                           " recorded time levels (record with a checkpoint interval instead)");
@@ -1726,7 +1734,7 @@ int record_steps(iblb_ctx *c, AdjState *a, int len, bool use_graph)
     hipGraph_t gr = nullptr;
     auto record = [&](int p) {
         return launch_record(c->prec, c->d, c->g, c->m, p, t0, maxl, maxf, a->store, a->qs, a->Fs, a->Us, a->phs,
-                             a->gvs, a->dVs, c->stream);
+                             a->gvs, a->dVs, a->mask_s, a->alist_s, a->acnt_s, c->stream);
     };
     auto one = [&](int p) {
         hipError_t e = record(p);
@@ -1783,12 +1791,16 @@ hipError_t reverse_steps(iblb_ctx *c, AdjState *a, const AdjArgs &A, int len)
         L.gvs = (const char *)a->gvs + (size_t)k * vl;
         L.dV = a->dVs + k;
         L.q = a->qs + (size_t)k * 3 * nv;
+        const size_t nw = (size_t)c->g.nt * (size_t)c->m.nwords;
+        L.mask = a->mask_s + (size_t)k * nw;
+        L.alist = a->alist_s + (size_t)k * c->g.nt;
+        L.acnt = a->acnt_s + k;
         L.Xref = c->d.Xref;
         L.faces = c->d.faces;
         L.inc4 = c->d.inc4;
         L.fref = c->d.fref;
         const AdjWork W{a->ub,   a->lam[1], a->lam[0], a->Fb,    a->phib,
-                        a->qb[1], a->qb[0], a->grads,  a->tpart, a->vpart};
+                        a->qb[1], a->qb[0], a->grads,  a->tpart, a->vpart, c->d.err};
         hipError_t e = adj_reverse_kept(A, a->es == 8, L, W, c->stream);
         if (e != hipSuccess) return e;
         std::swap(a->lam[0], a->lam[1]);

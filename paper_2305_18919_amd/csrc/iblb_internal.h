@@ -144,6 +144,7 @@ struct AdjArgs {
     double body[3], ulo[3], uhi[3];
     double alpha[3], kv_over_V0, V0, eps_lo, eps_hi, xi, rc, z_lo, z_hi;
     double origin[3];
+    int tile_blocks;            // blocks of the reverse spread over the active tiles (launch sizing)
 };
 // One reverse step from a recording (launch_record; every level of the
 // window, or of one checkpoint segment): the level's arrays, element type
@@ -154,6 +155,9 @@ struct AdjLevel {
     const void *phs, *gvs;        // phi_S + phi_W and dV/dq of step t
     const double *dV;             // V - V0 of step t
     const double *q;              // positions of time t
+    const uint64_t *mask;         // tile vertex masks of these positions, [tiles][ceil(nv / 64)]
+    const int *alist;             // active tiles of step t and their count
+    const uint32_t *acnt;
     const double *Xref;
     const int *faces;
     const int4 *inc4;
@@ -168,6 +172,7 @@ struct AdjWork {
 
     double *tpart;  // [adj_lb_blocks(n)] per-block running sums of the tau derivative
     double *vpart;  // [adj_vertex_blocks(nv)] per-block shares of grad V . phib
+    int *err;         // the context's error bits (a tile list overflow)
 };
 // Blocks of the LB adjoint over n nodes and of the 64-lanes-per-vertex
 // kernels over nv vertices (256 threads per block): the sizes of tpart, vpart.
@@ -182,10 +187,11 @@ hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double 
 // fields of the step just taken into level t - 1 - t0 (at most maxf): force
 // density on its active tiles (zero elsewhere) and u into [level][3][n], the
 // nodal force parts phi_S + phi_W and dV/dq into [level][3][nv], V - V0 into
-// [level].
+// [level]; the tiles' vertex masks of time t into [level][tiles][nwords], the
+// step's active tile list and count into [level][tiles] and [level].
 hipError_t launch_record(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, uint32_t t0, uint32_t maxl,
                          uint32_t maxf, void *store, double *qs, void *Fs, void *Us, void *phs, void *gvs,
-                         double *dVs, hipStream_t s);
+                         double *dVs, uint64_t *mask_s, int *alist_s, uint32_t *acnt_s, hipStream_t s);
 
 hipError_t launch_set_pops(int prec, const Dev &d, const Grid &g, int p, const double *in, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Dev &d, const LBArgs &a, int p, double *rho, double *u, hipStream_t s);

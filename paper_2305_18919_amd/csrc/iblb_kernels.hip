@@ -1333,7 +1333,9 @@ __global__ __launch_bounds__(256) void k_get_pops(const S *__restrict__ f, int p
 // (so that a captured graph of several steps records a new level at every
 // step):
 //  - level t - t0 (at most maxl) of the time levels: the populations of time
-//    t in canonical order, converted to O, and the positions;
+//    t in canonical order, converted to O, the positions, and the tiles'
+//    vertex masks of these positions (set by the previous move, not yet read
+//    by this step's spreading);
 //  - level t - 1 - t0 (at most maxf; the wrapped -1 before the window's
 //    first step is skipped) of the fields of the step just taken: its force
 //    density on its active tiles (stamp == t) and zero elsewhere, u(t) as it
@@ -1349,7 +1351,10 @@ __global__ __launch_bounds__(256) void k_record(const S *__restrict__ f, const O
                                                 const O *__restrict__ phiSW, const O *__restrict__ gV,
                                                 const double *__restrict__ partials, int nparts, int nv,
                                                 O *__restrict__ phs, O *__restrict__ gvs, double *__restrict__ dVs,
-                                                Grid g)
+                                                const uint64_t *__restrict__ mask, const int *__restrict__ alist,
+                                                const uint32_t *__restrict__ acnt, int nwords,
+                                                uint64_t *__restrict__ mask_s, int *__restrict__ alist_s,
+                                                uint32_t *__restrict__ acnt_s, Grid g)
 {
     using T = typename Pop<S>::C;
     const uint32_t t = ctr[p];
@@ -1387,13 +1392,20 @@ __global__ __launch_bounds__(256) void k_record(const S *__restrict__ f, const O
             gvs[(size_t)levf * 3 * nv + i] = gV[i];
         }
     }
+    const long long nw = (long long)g.nt * nwords;
+    if (rec && i < nw)
+        mask_s[(size_t)lev * (size_t)nw + i] = mask[i];
+    if (recf && i < g.nt)
+        alist_s[(size_t)levf * g.nt + i] = alist[i];
     if (recf && blockIdx.x == 0 && threadIdx.x < 64) {
         double sum = 0.0;
         for (int k = threadIdx.x; k < nparts; k += 64)
             sum += partials[k];
         sum = wave_sum<double>(sum);
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
             dVs[levf] = sum;
+            acnt_s[levf] = acnt[0];
+        }
     }
 }
 
@@ -1789,16 +1801,19 @@ hipError_t launch_stamp(const Dev &d, const Grid &g, const MeshArgs &m, int p, h
 
 hipError_t launch_record(int prec, const Dev &d, const Grid &g, const MeshArgs &m, int p, uint32_t t0, uint32_t maxl,
                          uint32_t maxf, void *store, double *qs, void *Fs, void *Us, void *phs, void *gvs,
-                         double *dVs, hipStream_t s)
+                         double *dVs, uint64_t *mask_s, int *alist_s, uint32_t *acnt_s, hipStream_t s)
 {
-    const long long work = g.n > 3ll * m.nv ? g.n : 3ll * m.nv;
+    long long work = g.n > 3ll * m.nv ? g.n : 3ll * m.nv;
+    if ((long long)g.nt * m.nwords > work)
+        work = (long long)g.nt * m.nwords;
     const int blocks = (int)((work + 255) / 256);
     return with_pop_type(prec, [&](auto tag) {
         using S = decltype(tag);
         using O = typename Pop<S>::C;
         k_record<S, O><<<blocks, 256, 0, s>>>((const S *)d.f, (const O *)d.F, (const O *)d.U, d.stamp, d.ctr, p, t0,
                                              maxl, maxf, (O *)store, qs, (O *)Fs, (O *)Us, d.q, (const O *)d.phiSW,
-                                             (const O *)d.gV, d.partials, m.nparts, m.nv, (O *)phs, (O *)gvs, dVs, g);
+                                             (const O *)d.gV, d.partials, m.nparts, m.nv, (O *)phs, (O *)gvs, dVs,
+                                             d.mask, d.alist, d.acnt, m.nwords, mask_s, alist_s, acnt_s, g);
     });
 }
 
