@@ -306,8 +306,11 @@ int iblb_batch_destroy(iblb_batch *b);
  *    precision.
  *  every > 0: a device copy of the whole context state every `every` steps;
  *    the sweep restores each segment's checkpoint, records the segment again
- *    as above (every + 1 levels and every steps of fields in device memory)
- *    and walks it backwards.
+ *    as above and walks it backwards.  It holds two such recordings (2 x
+ *    (every + 1) levels and 2 x every steps of fields in device memory): the
+ *    segment before is recorded on the context's stream while the segment
+ *    after it is swept on a second stream the library owns, ordered with
+ *    events; iblb_adjoint_backward returns once both are done.
  * Replaces any earlier recording.  The context is left at t0 + n.  Errors:
  * IBLB_E_INVAL (null context, n < 1, every < 0), IBLB_E_STATE (no mesh),
  * IBLB_E_DEVICE (the recording does not fit in device memory, or a HIP

@@ -307,6 +307,12 @@ __device__ __forceinline__ T ld32(const T *base, uint32_t byte_off)
 {
     return *(const T *)((const char *)base + byte_off);
 }
+// the same for a recorded level, read once by the sweep
+template <typename T>
+__device__ __forceinline__ T ld32_once(const T *base, uint32_t byte_off)
+{
+    return __builtin_nontemporal_load((const T *)((const char *)base + byte_off));
+}
 
 template <typename P>
 __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict__ f0, const P *__restrict__ f1,
@@ -339,7 +345,7 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
         P fv[19];
         P lt[19];
 #pragma unroll
-        for (int i = 0; i < 19; ++i) fv[i] = ld32(f0 + (size_t)i * n, oP);
+        for (int i = 0; i < 19; ++i) fv[i] = ld32_once(f0 + (size_t)i * n, oP);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             const bool wall = (kCz[i] < 0 && wlo) || (kCz[i] > 0 && whi);
@@ -358,8 +364,8 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
 #pragma unroll
         for (int i = 0; i < 19; ++i) Ls[i][threadIdx.x] = lt[i];
         const double rho = A.rho0 + dr;
-        const double Fx = double(ld32(F, oP)) + A.body[0], Fy = double(ld32(F + n, oP)) + A.body[1],
-                     Fz = double(ld32(F + 2 * n, oP)) + A.body[2];
+        const double Fx = double(ld32_once(F, oP)) + A.body[0], Fy = double(ld32_once(F + n, oP)) + A.body[1],
+                     Fz = double(ld32_once(F + 2 * n, oP)) + A.body[2];
         const double u0 = (m[0] + 0.5 * Fx) / rho, u1 = (m[1] + 0.5 * Fy) / rho, u2 = (m[2] + 0.5 * Fz) / rho;
         const double uu = u0 * u0 + u1 * u1 + u2 * u2;
         const double uF = u0 * Fx + u1 * Fy + u2 * Fz;

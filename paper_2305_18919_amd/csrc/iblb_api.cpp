@@ -1578,14 +1578,29 @@ int iblb_batch_destroy(iblb_batch *b)
 // ---------------------------------------------------------------------------
 // Adjoint: a recorded window of steps and its reverse sweep
 // ---------------------------------------------------------------------------
+// Time levels of a recorded window (or of one checkpoint segment) and the
+// forward's own fields of the steps between them.
+struct Recording {
+    void *store = nullptr;                // [levels][19][n] populations (element size es)
+    double *qs = nullptr;                 // [levels][3][nv] positions
+    uint64_t *mask_s = nullptr;           // [levels][tiles][nwords] tile vertex masks of the positions
+    int *alist_s = nullptr;               // [steps][tiles] active tiles of each step
+    uint32_t *acnt_s = nullptr;           // [steps] and their count
+    void *Fs = nullptr, *Us = nullptr;    // [steps][3][n_nodes] force density (active tiles), u(t+1)
+    void *phs = nullptr, *gvs = nullptr;  // [steps][3][nv] phi_S + phi_W, dV/dq
+    double *dVs = nullptr;                // [steps] V - V0
+};
+
 struct AdjState {
     long long t0 = 0;                  // time at the start of the recorded window
     int n = 0, every = 0;              // steps recorded; steps per checkpoint, 0 = every level kept
     std::vector<char *> ck;            // checkpoint mode: device states at t0, t0 + every, ..., t0 + n
     size_t snap = 0;                   // bytes of one checkpoint
     size_t es = 8;                     // bytes per stored population: the step's arithmetic precision
-    void *store = nullptr;             // [levels][19][n] populations of the stored time levels
-    double *qs = nullptr;              // [levels][3][nv] positions of the stored time levels
+    Recording rec[2];                  // every level of the window; or two segments, one being
+                                       // recorded while the sweep reads the other
+    hipStream_t rs = nullptr;          // checkpoint mode: the reverse sweep's stream
+    hipEvent_t recorded[2] = {nullptr, nullptr}, swept[2] = {nullptr, nullptr};  // per recording
     double *lam[2] = {nullptr, nullptr};  // ping-pong adjoints of the populations: [1] is t+1
     double *qb[2] = {nullptr, nullptr};   // and of the positions
     double *lam_buf[2] = {nullptr, nullptr}, *qb_buf[2] = {nullptr, nullptr};  // their allocations
@@ -1593,13 +1608,6 @@ struct AdjState {
     double *grads = nullptr;           // [6]
     double *tpart = nullptr;           // per-block sums of the tau derivative
     double *vpart = nullptr;           // per-block shares of grad V . phib
-    uint64_t *mask_s = nullptr;           // [levels][tiles][nwords] tile vertex masks of the positions
-    int *alist_s = nullptr;               // [steps][tiles] active tiles of each step
-    uint32_t *acnt_s = nullptr;           // [steps] and their count
-    // the forward's own fields of each recorded step (element size es)
-    void *Fs = nullptr, *Us = nullptr;    // [steps][3][n_nodes] force density (active tiles), u(t+1)
-    void *phs = nullptr, *gvs = nullptr;  // [steps][3][nv] phi_S + phi_W, dV/dq
-    double *dVs = nullptr;                // [steps] V - V0
 };
 
 namespace {
@@ -1611,8 +1619,14 @@ void free_adjoint(iblb_ctx *c)
     AdjState *a = c->adj;
     if (!a) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (a->rs) (void)hipStreamSynchronize(a->rs);
     for (char *p : a->ck) (void)hipFree(p);
     free_sweep(a);
+    for (int k = 0; k < 2; ++k) {
+        if (a->recorded[k]) (void)hipEventDestroy(a->recorded[k]);
+        if (a->swept[k]) (void)hipEventDestroy(a->swept[k]);
+    }
+    if (a->rs) (void)hipStreamDestroy(a->rs);
     delete a;
     c->adj = nullptr;
 }
@@ -1672,28 +1686,32 @@ AdjArgs adj_args(const iblb_ctx *c)
     return A;
 }
 
-void *level(AdjState *a, size_t n, int k) { return (char *)a->store + (size_t)k * 19 * n * a->es; }
+void *level(const AdjState *a, const Recording &r, size_t n, int k)
+{
+    return (char *)r.store + (size_t)k * 19 * n * a->es;
+}
 
 // Frees the recording buffers and working arrays of the reverse sweep (not
 // the checkpoints).
 void free_sweep(AdjState *a)
 {
-    for (void **p : {&a->store, &a->Fs, &a->Us, &a->phs, &a->gvs, (void **)&a->mask_s, (void **)&a->alist_s,
-                     (void **)&a->acnt_s}) {
-        if (*p) (void)hipFree(*p);
-        *p = nullptr;
-    }
-    for (double **p : {&a->qs, &a->dVs, &a->lam_buf[0], &a->lam_buf[1], &a->qb_buf[0], &a->qb_buf[1], &a->Fb, &a->ub,
+    for (Recording &r : a->rec)
+        for (void **p : {&r.store, &r.Fs, &r.Us, &r.phs, &r.gvs, (void **)&r.mask_s, (void **)&r.alist_s,
+                         (void **)&r.acnt_s, (void **)&r.qs, (void **)&r.dVs}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+    for (double **p : {&a->lam_buf[0], &a->lam_buf[1], &a->qb_buf[0], &a->qb_buf[1], &a->Fb, &a->ub,
                        &a->phib, &a->grads, &a->tpart, &a->vpart}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
 }
 
-// Device memory for a recording of `levels` time levels (populations,
+// Device memory for `nrec` recordings of `levels` time levels (populations,
 // positions) and the fields of the levels - 1 steps between them, and the
 // reverse sweep's working arrays; on failure nothing stays allocated.
-int alloc_sweep(iblb_ctx *c, AdjState *a, size_t levels)
+int alloc_sweep(iblb_ctx *c, AdjState *a, size_t levels, int nrec)
 {
     const size_t n = (size_t)c->g.n, nv = (size_t)c->nv, L = levels - 1, es = a->es;
     auto getb = [](void **p, size_t bytes) {
@@ -1702,14 +1720,17 @@ int alloc_sweep(iblb_ctx *c, AdjState *a, size_t levels)
         return false;
     };
     auto get = [&](double **p, size_t count) { return getb((void **)p, count * 8); };
-    if (!getb(&a->store, levels * 19 * n * es) || !getb(&a->Fs, L * 3 * n * es) || !getb(&a->Us, L * 3 * n * es) ||
-        !getb(&a->phs, L * 3 * nv * es) || !getb(&a->gvs, L * 3 * nv * es) || !get(&a->dVs, L) ||
-        !get(&a->qs, levels * 3 * nv) ||
-        !getb((void **)&a->mask_s, levels * (size_t)c->g.nt * (size_t)c->m.nwords * 8) ||
-        !getb((void **)&a->alist_s, L * (size_t)c->g.nt * 4) || !getb((void **)&a->acnt_s, L * 4)) {
-        free_sweep(a);
-        return fail(c, IBLB_E_DEVICE, "no device memory for " + std::to_string(levels) +
-                                          " recorded time levels (record with a checkpoint interval instead)");
+    for (int k = 0; k < nrec; ++k) {
+        Recording &r = a->rec[k];
+        if (!getb(&r.store, levels * 19 * n * es) || !getb(&r.Fs, L * 3 * n * es) || !getb(&r.Us, L * 3 * n * es) ||
+            !getb(&r.phs, L * 3 * nv * es) || !getb(&r.gvs, L * 3 * nv * es) || !get(&r.dVs, L) ||
+            !get(&r.qs, levels * 3 * nv) ||
+            !getb((void **)&r.mask_s, levels * (size_t)c->g.nt * (size_t)c->m.nwords * 8) ||
+            !getb((void **)&r.alist_s, L * (size_t)c->g.nt * 4) || !getb((void **)&r.acnt_s, L * 4)) {
+            free_sweep(a);
+            return fail(c, IBLB_E_DEVICE, "no device memory for " + std::to_string(levels) +
+                                              " recorded time levels (record with a checkpoint interval instead)");
+        }
     }
     if (!get(&a->lam_buf[0], 19 * n) || !get(&a->lam_buf[1], 19 * n) || !get(&a->qb_buf[0], 3 * nv) ||
         !get(&a->qb_buf[1], 3 * nv) || !get(&a->Fb, 3 * n) || !get(&a->ub, 3 * n) || !get(&a->phib, 3 * nv) ||
@@ -1726,15 +1747,15 @@ int alloc_sweep(iblb_ctx *c, AdjState *a, size_t levels)
 // and the forward's own fields of each step (launch_record; the level index
 // comes from the device step counter).  With use_graph, full runs of
 // kGraphSteps steps from even times replay one captured graph.
-int record_steps(iblb_ctx *c, AdjState *a, int len, bool use_graph)
+int record_steps(iblb_ctx *c, AdjState *a, Recording &r, int len, bool use_graph)
 {
     const uint32_t t0 = (uint32_t)c->t, maxl = (uint32_t)len;
     const uint32_t maxf = (uint32_t)len - 1u;  // field levels: the steps recorded
     hipGraphExec_t gx = nullptr;
     hipGraph_t gr = nullptr;
     auto record = [&](int p) {
-        return launch_record(c->prec, c->d, c->g, c->m, p, t0, maxl, maxf, a->store, a->qs, a->Fs, a->Us, a->phs,
-                             a->gvs, a->dVs, a->mask_s, a->alist_s, a->acnt_s, c->stream);
+        return launch_record(c->prec, c->d, c->g, c->m, p, t0, maxl, maxf, r.store, r.qs, r.Fs, r.Us, r.phs, r.gvs,
+                             r.dVs, r.mask_s, r.alist_s, r.acnt_s, c->stream);
     };
     auto one = [&](int p) {
         hipError_t e = record(p);
@@ -1775,38 +1796,106 @@ int record_steps(iblb_ctx *c, AdjState *a, int len, bool use_graph)
     return rc;
 }
 
-// Reverse steps len - 1 .. 0 over the recorded levels: (lam[1], qb[1]) at
-// the end of the recording to the adjoints at its start.
-hipError_t reverse_steps(iblb_ctx *c, AdjState *a, const AdjArgs &A, int len)
+// One reverse step, at level k of a recording, on stream s: (lam[1], qb[1])
+// of time k + 1 to (lam[0], qb[0]) of time k, then the two swap roles.
+hipError_t reverse_step(iblb_ctx *c, AdjState *a, const Recording &r, const AdjArgs &A, int k, hipStream_t s)
 {
     const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
     const size_t fl = 3 * n * a->es, vl = 3 * nv * a->es;
-    for (int k = len - 1; k >= 0; --k) {
-        AdjLevel L;
-        L.f0 = level(a, n, k);
-        L.f1 = level(a, n, k + 1);
-        L.F = (const char *)a->Fs + (size_t)k * fl;
-        L.U = (const char *)a->Us + (size_t)k * fl;
-        L.phs = (const char *)a->phs + (size_t)k * vl;
-        L.gvs = (const char *)a->gvs + (size_t)k * vl;
-        L.dV = a->dVs + k;
-        L.q = a->qs + (size_t)k * 3 * nv;
-        const size_t nw = (size_t)c->g.nt * (size_t)c->m.nwords;
-        L.mask = a->mask_s + (size_t)k * nw;
-        L.alist = a->alist_s + (size_t)k * c->g.nt;
-        L.acnt = a->acnt_s + k;
-        L.Xref = c->d.Xref;
-        L.faces = c->d.faces;
-        L.inc4 = c->d.inc4;
-        L.fref = c->d.fref;
-        const AdjWork W{a->ub,   a->lam[1], a->lam[0], a->Fb,    a->phib,
-                        a->qb[1], a->qb[0], a->grads,  a->tpart, a->vpart, c->d.err};
-        hipError_t e = adj_reverse_kept(A, a->es == 8, L, W, c->stream);
-        if (e != hipSuccess) return e;
-        std::swap(a->lam[0], a->lam[1]);
-        std::swap(a->qb[0], a->qb[1]);
+    AdjLevel L;
+    L.f0 = level(a, r, n, k);
+    L.f1 = level(a, r, n, k + 1);
+    L.F = (const char *)r.Fs + (size_t)k * fl;
+    L.U = (const char *)r.Us + (size_t)k * fl;
+    L.phs = (const char *)r.phs + (size_t)k * vl;
+    L.gvs = (const char *)r.gvs + (size_t)k * vl;
+    L.dV = r.dVs + k;
+    L.q = r.qs + (size_t)k * 3 * nv;
+    const size_t nw = (size_t)c->g.nt * (size_t)c->m.nwords;
+    L.mask = r.mask_s + (size_t)k * nw;
+    L.alist = r.alist_s + (size_t)k * c->g.nt;
+    L.acnt = r.acnt_s + k;
+    L.Xref = c->d.Xref;
+    L.faces = c->d.faces;
+    L.inc4 = c->d.inc4;
+    L.fref = c->d.fref;
+    const AdjWork W{a->ub,    a->lam[1], a->lam[0], a->Fb,    a->phib,
+                    a->qb[1], a->qb[0],  a->grads,  a->tpart, a->vpart, c->d.err};
+    const hipError_t e = adj_reverse_kept(A, a->es == 8, L, W, s);
+    std::swap(a->lam[0], a->lam[1]);
+    std::swap(a->qb[0], a->qb[1]);
+    return e;
+}
+
+// Checkpoint mode: segments from the last.  Each is recorded again from its
+// checkpoint on the context's stream (which owns the state) into one of two
+// recordings, while the reverse sweep of the segment after it runs from the
+// other recording on a stream of its own; the launches of the two alternate
+// step by step.  Events order each recording before its sweep, and each
+// sweep before the recording that reuses its buffers.  Both streams are
+// latency-bound at these sizes, so they share the device.
+int sweep_segments(iblb_ctx *c, AdjState *a, const AdjArgs &A)
+{
+    const int every = a->every, nseg = (a->n + every - 1) / every;
+    auto seg_len = [&](int sgm) { return std::min(every, a->n - sgm * every); };
+    if (!a->rs) {
+        if (hipStreamCreateWithFlags(&a->rs, hipStreamNonBlocking) != hipSuccess) {
+            a->rs = nullptr;
+            return fail(c, IBLB_E_DEVICE, "cannot create the reverse sweep's stream");
+        }
+        for (int k = 0; k < 2; ++k)
+            if (hipEventCreateWithFlags(&a->recorded[k], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&a->swept[k], hipEventDisableTiming) != hipSuccess)
+                return fail(c, IBLB_E_DEVICE, "cannot create the reverse sweep's events");
     }
-    return hipSuccess;
+    int rc = checkpoint(c, a->ck[(size_t)nseg - 1], false);
+    if (rc) return rc;
+    c->t = a->t0 + (long long)(nseg - 1) * every;
+    rc = record_steps(c, a, a->rec[0], seg_len(nseg - 1), false);
+    if (rc) return rc;
+    HIP_TRY(c, hipEventRecord(a->recorded[0], c->stream));
+    for (int sgm = nseg - 1; sgm >= 0; --sgm) {
+        const int b = (nseg - 1 - sgm) & 1;  // this segment's recording; the one before it takes 1 - b
+        const int lv = seg_len(sgm), lr = sgm > 0 ? seg_len(sgm - 1) : 0;
+        HIP_TRY(c, hipStreamWaitEvent(a->rs, a->recorded[b], 0));
+        Recording &next = a->rec[1 - b];
+        uint32_t t0 = 0;
+        if (lr) {
+            if (sgm + 1 < nseg)  // rec[1 - b] was read by the sweep of segment sgm + 1
+                HIP_TRY(c, hipStreamWaitEvent(c->stream, a->swept[1 - b], 0));
+            rc = checkpoint(c, a->ck[(size_t)sgm - 1], false);
+            if (rc) return rc;
+            c->t = a->t0 + (long long)(sgm - 1) * every;
+            t0 = (uint32_t)c->t;
+        }
+        auto record = [&](int p) {
+            return launch_record(c->prec, c->d, c->g, c->m, p, t0, (uint32_t)lr, (uint32_t)lr - 1u, next.store,
+                                 next.qs, next.Fs, next.Us, next.phs, next.gvs, next.dVs, next.mask_s, next.alist_s,
+                                 next.acnt_s, c->stream);
+        };
+        for (int j = 0; j < std::max(lr, lv); ++j) {
+            if (j < lr) {
+                const int p = (int)(c->t & 1);
+                hipError_t e = record(p);
+                if (e == hipSuccess) e = enqueue_step(c, p, false);
+                if (e != hipSuccess) return hip_fail(c, e, "recording a segment");
+                c->t += 1;
+            }
+            if (j < lv) {
+                const hipError_t e = reverse_step(c, a, a->rec[b], A, lv - 1 - j, a->rs);
+                if (e != hipSuccess) return hip_fail(c, e, "reverse sweep");
+            }
+        }
+        if (lr) {
+            const hipError_t e = record((int)(c->t & 1));
+            if (e != hipSuccess) return hip_fail(c, e, "storing the last level");
+            HIP_TRY(c, hipEventRecord(a->recorded[1 - b], c->stream));
+        }
+        HIP_TRY(c, hipEventRecord(a->swept[b], a->rs));
+    }
+    // the results are read on the context's stream, after the last sweep
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, a->swept[(nseg - 1) & 1], 0));
+    return IBLB_OK;
 }
 
 }  // namespace
@@ -1827,8 +1916,8 @@ int iblb_adjoint_record(iblb_ctx *c, int32_t n_steps, int32_t every)
     int rc = IBLB_OK;
     if (every == 0) {
         // every time level kept: the reverse sweep needs no recompute
-        rc = alloc_sweep(c, a, (size_t)n_steps + 1);
-        if (!rc) rc = record_steps(c, a, n_steps, true);
+        rc = alloc_sweep(c, a, (size_t)n_steps + 1, 1);
+        if (!rc) rc = record_steps(c, a, a->rec[0], n_steps, true);
         if (c->stream) (void)hipStreamSynchronize(c->stream);
     } else {
         // a device copy of the whole state every `every` steps; the sweep
@@ -1861,8 +1950,8 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     int rc = sync_ctx(c);
     if (rc) return rc;
     const size_t n = (size_t)c->g.n, nv = (size_t)c->nv;
-    if (!a->lam_buf[0]) {  // checkpoint mode: buffers for one segment, allocated at the first sweep
-        rc = alloc_sweep(c, a, (size_t)std::min(a->every, a->n) + 1);
+    if (!a->lam_buf[0]) {  // checkpoint mode: buffers for two segments, allocated at the first sweep
+        rc = alloc_sweep(c, a, (size_t)std::min(a->every, a->n) + 1, a->n > a->every ? 2 : 1);
         if (rc) return rc;
     }
     // the same buffer roles at the start of every call
@@ -1882,24 +1971,14 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     HIP_TRY(c, hipMemsetAsync(a->ub, 0, 3 * n * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(a->tpart, 0, (size_t)adj_lb_blocks((long long)n) * 8, c->stream));
     if (a->every == 0) {
-        HIP_TRY(c, reverse_steps(c, a, A, a->n));
+        for (int k = a->n - 1; k >= 0; --k) HIP_TRY(c, reverse_step(c, a, a->rec[0], A, k, c->stream));
     } else {
-        // Segments from the last: restore its checkpoint, record it again
-        // with every level and field kept, sweep it backwards.
-        const int nseg = (a->n + a->every - 1) / a->every;
-        const long long t_end = a->t0 + a->n;
-        for (int sgm = nseg - 1; !rc && sgm >= 0; --sgm) {
-            rc = checkpoint(c, a->ck[(size_t)sgm], false);
-            if (rc) break;
-            c->t = a->t0 + (long long)sgm * a->every;
-            rc = record_steps(c, a, std::min(a->every, a->n - sgm * a->every), false);
-            if (rc) break;
-            const hipError_t e = reverse_steps(c, a, A, std::min(a->every, a->n - sgm * a->every));
-            if (e != hipSuccess) rc = hip_fail(c, e, "reverse sweep");
-        }
+        rc = sweep_segments(c, a, A);
+        if (rc && a->rs) (void)hipStreamSynchronize(a->rs);
         // back to the end of the window
+        const int nseg = (a->n + a->every - 1) / a->every;
         const int rc2 = checkpoint(c, a->ck[(size_t)nseg], false);
-        c->t = t_end;
+        c->t = a->t0 + a->n;
         if (rc) return rc;
         if (rc2) return rc2;
     }

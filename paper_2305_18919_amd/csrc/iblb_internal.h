@@ -185,7 +185,7 @@ hipError_t launch_get_pops(int prec, const Dev &d, const Grid &g, int p, double 
 // populations (double for FP64 storage, else float) and positions of time t
 // into level t - t0 (at most maxl) of [level][19][n] and [level][3][nv]; the
 // fields of the step just taken into level t - 1 - t0 (at most maxf): force
-// density on its active tiles (zero elsewhere) and u into [level][3][n], the
+// density on its active tiles (zero elsewhere) and u (on those tiles only) into [level][3][n], the
 // nodal force parts phi_S + phi_W and dV/dq into [level][3][nv], V - V0 into
 // [level]; the tiles' vertex masks of time t into [level][tiles][nwords], the
 // step's active tile list and count into [level][tiles] and [level].

@@ -1339,8 +1339,9 @@ __global__ __launch_bounds__(256) void k_get_pops(const S *__restrict__ f, int p
 //  - level t - 1 - t0 (at most maxf; the wrapped -1 before the window's
 //    first step is skipped) of the fields of the step just taken: its force
 //    density on its active tiles (stamp == t) and zero elsewhere, u(t) as it
-//    left it in U (valid on the active tiles, the only nodes the adjoint
-//    reads), the nodal force parts phi_S + phi_W and dV/dq, and V - V0.
+//    left it in U, on the active tiles (the only nodes where it is valid
+//    and the adjoint reads it; the rest of the level is not written), the
+//    nodal force parts phi_S + phi_W and dV/dq, and V - V0.
 // O is the step's arithmetic type (double for FP64 storage, else float).
 template <typename S, typename O>
 __global__ __launch_bounds__(256) void k_record(const S *__restrict__ f, const O *__restrict__ F,
@@ -1363,7 +1364,12 @@ __global__ __launch_bounds__(256) void k_record(const S *__restrict__ f, const O
     const long long n = g.n;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
-        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), zf = (int)(i / ((long long)g.nx * g.ny));
+        // n < 2^31: 32-bit index arithmetic
+        const uint32_t ui = (uint32_t)i, row = ui / (uint32_t)g.nx, zr = row / (uint32_t)g.ny;
+        const int x = (int)(ui - row * (uint32_t)g.nx), y = (int)(row - zr * (uint32_t)g.ny), zf = (int)zr;
+        // the levels are written once here and read once, in reverse order,
+        // by the sweep: non-temporal stores keep them from displacing the
+        // step's own arrays in the caches
         if (rec) {
             T d[19];
             if (p)
@@ -1372,15 +1378,17 @@ __global__ __launch_bounds__(256) void k_record(const S *__restrict__ f, const O
                 load_pops<S, false>(f, g, x, y, zf, d);
             O *out = store + (size_t)lev * 19 * (size_t)n;
             for (int k = 0; k < 19; ++k)
-                out[k * n + i] = O(d[k]);
+                __builtin_nontemporal_store(O(d[k]), &out[(size_t)k * n + i]);
         }
         if (recf) {
+            // U is valid, and read by the sweep, on the step's active tiles only
             const bool on = stamp[tile_of(g, x, y, zf)] == t;
             O *Fo = Fs + (size_t)levf * 3 * (size_t)n;
             O *Uo = Us + (size_t)levf * 3 * (size_t)n;
             for (int c = 0; c < 3; ++c) {
-                Fo[c * n + i] = on ? F[c * n + i] : O(0);
-                Uo[c * n + i] = U[c * n + i];
+                __builtin_nontemporal_store(on ? F[(size_t)c * n + i] : O(0), &Fo[(size_t)c * n + i]);
+                if (on)
+                    __builtin_nontemporal_store(U[(size_t)c * n + i], &Uo[(size_t)c * n + i]);
             }
         }
     }
