@@ -323,7 +323,6 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
     const Grid &g = A.g;
     const long long n = g.n;
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    __shared__ P Ls[19][256];
     double tb[1] = {0.0};
     if (id < n) {
         // node coordinates and the row/plane offsets of its neighbours (no
@@ -340,8 +339,7 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
         const uint32_t oP = uid * (uint32_t)sizeof(P);
         // the node's populations and Lam_i, the adjoint of post-collision
         // population i at x, gathered before any is used (all loads in
-        // flight together); the populations stay in registers, Lam goes to
-        // this thread's LDS slots, which the two passes below read
+        // flight together)
         P fv[19];
         P lt[19];
 #pragma unroll
@@ -357,12 +355,10 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
         for (int i = 0; i < 19; ++i) {
             const double d = double(fv[i]);
             dr += d;
-            m[0] += kCx[i] * d;
-            m[1] += kCy[i] * d;
-            m[2] += kCz[i] * d;
+            if (kCx[i] != 0) m[0] += kCx[i] > 0 ? d : -d;
+            if (kCy[i] != 0) m[1] += kCy[i] > 0 ? d : -d;
+            if (kCz[i] != 0) m[2] += kCz[i] > 0 ? d : -d;
         }
-#pragma unroll
-        for (int i = 0; i < 19; ++i) Ls[i][threadIdx.x] = lt[i];
         const double rho = A.rho0 + dr;
         const double Fx = double(ld32_once(F, oP)) + A.body[0], Fy = double(ld32_once(F + n, oP)) + A.body[1],
                      Fz = double(ld32_once(F + 2 * n, oP)) + A.body[2];
@@ -370,47 +366,73 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
         const double uu = u0 * u0 + u1 * u1 + u2 * u2;
         const double uF = u0 * Fx + u1 * Fy + u2 * Fz;
         const double om = A.omega, guo = 1.0 - 0.5 * om;
-        double a = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0, tt = 0.0;
-        // first pass: the density, velocity and force adjoints (unrolled by
-        // two only, to keep the registers of a few directions live at a
-        // time); wall links also add their moving-wall term to the density
-        // adjoint
-#pragma unroll 2
+        // Every sum over i of Lam_i times a polynomial of degree <= 2 in c_i
+        // (the transposed Jacobians of f^eq and of the Guo source) is a
+        // combination of the moments of w_i Lam_i: M0, M1_a = sum w Lam c_a,
+        // M2_ab = sum w Lam c_a c_b.  Lf = sum Lam_i f_i for the tau
+        // derivative; aw collects the moving-wall terms of the wall links.
+        double M0 = 0.0, M1[3] = {0.0, 0.0, 0.0}, Mxx = 0.0, Myy = 0.0, Mzz = 0.0, Mxy = 0.0, Mxz = 0.0,
+               Myz = 0.0, Lf = 0.0, aw = 0.0;
+#pragma unroll
         for (int i = 0; i < 19; ++i) {
-            const int cx = cCx[i], cy = cCy[i], cz = cCz[i];
-            const double w = wq(i);
-            const double L = double(Ls[i][threadIdx.x]);
-            if ((cz < 0 && wlo) || (cz > 0 && whi)) {
-                const double uwx = cz < 0 ? A.ulo[0] : A.uhi[0], uwy = cz < 0 ? A.ulo[1] : A.uhi[1];
-                a += -6.0 * w * (cx * uwx + cy * uwy) * L;  // wall velocities are tangential
+            const double L = double(lt[i]);
+            const double wl = wq(i) * L;
+            Lf += L * double(fv[i]);
+            M0 += wl;
+            if (kCx[i] != 0) {
+                M1[0] += kCx[i] > 0 ? wl : -wl;
+                Mxx += wl;
             }
-            const double cu = cx * u0 + cy * u1 + cz * u2;
-            const double cF = cx * Fx + cy * Fy + cz * Fz;
-            const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
-            // f*_i = d_i - om (d_i - deq_i) + guo s_i
-            a += L * om * w * (1.0 + poly);
-            const double Lr = L * om * w * rho, Lg = L * guo * w;
-            b0 += Lr * (3.0 * cx + 9.0 * cu * cx - 3.0 * u0) + Lg * (-3.0 * Fx + 9.0 * cF * cx);
-            b1 += Lr * (3.0 * cy + 9.0 * cu * cy - 3.0 * u1) + Lg * (-3.0 * Fy + 9.0 * cF * cy);
-            b2 += Lr * (3.0 * cz + 9.0 * cu * cz - 3.0 * u2) + Lg * (-3.0 * Fz + 9.0 * cF * cz);
-            g0 += Lg * (3.0 * (cx - u0) + 9.0 * cu * cx);
-            g1 += Lg * (3.0 * (cy - u1) + 9.0 * cu * cy);
-            g2 += Lg * (3.0 * (cz - u2) + 9.0 * cu * cz);
+            if (kCy[i] != 0) {
+                M1[1] += kCy[i] > 0 ? wl : -wl;
+                Myy += wl;
+            }
+            if (kCz[i] != 0) {
+                M1[2] += kCz[i] > 0 ? wl : -wl;
+                Mzz += wl;
+            }
+            if (kCx[i] * kCy[i] != 0) Mxy += kCx[i] * kCy[i] > 0 ? wl : -wl;
+            if (kCx[i] * kCz[i] != 0) Mxz += kCx[i] * kCz[i] > 0 ? wl : -wl;
+            if (kCy[i] * kCz[i] != 0) Myz += kCy[i] * kCz[i] > 0 ? wl : -wl;
+            if ((kCz[i] < 0 && wlo) || (kCz[i] > 0 && whi)) {
+                // wall velocities are tangential
+                const double uwx = kCz[i] < 0 ? A.ulo[0] : A.uhi[0], uwy = kCz[i] < 0 ? A.ulo[1] : A.uhi[1];
+                aw += -6.0 * wl * (kCx[i] * uwx + kCy[i] * uwy);
+            }
         }
-        // second pass: lam(t) and the tau derivative
+        const double M2u0 = Mxx * u0 + Mxy * u1 + Mxz * u2, M2u1 = Mxy * u0 + Myy * u1 + Myz * u2,
+                     M2u2 = Mxz * u0 + Myz * u1 + Mzz * u2;
+        const double M2F0 = Mxx * Fx + Mxy * Fy + Mxz * Fz, M2F1 = Mxy * Fx + Myy * Fy + Myz * Fz,
+                     M2F2 = Mxz * Fx + Myz * Fy + Mzz * Fz;
+        const double uM1 = u0 * M1[0] + u1 * M1[1] + u2 * M1[2];
+        const double uM2u = u0 * M2u0 + u1 * M2u1 + u2 * M2u2;
+        const double FM1 = Fx * M1[0] + Fy * M1[1] + Fz * M1[2];
+        const double FM2u = Fx * M2u0 + Fy * M2u1 + Fz * M2u2;
+        // f*_i = d_i - om (d_i - deq_i) + guo s_i: the density adjoint a, the
+        // velocity adjoint b and the force adjoint g
+        const double a = aw + om * (M0 + 3.0 * uM1 + 4.5 * uM2u - 1.5 * uu * M0);
+        const double orho = om * rho;
+        const double b0 = orho * (3.0 * M1[0] + 9.0 * M2u0 - 3.0 * u0 * M0) + guo * (-3.0 * Fx * M0 + 9.0 * M2F0);
+        const double b1 = orho * (3.0 * M1[1] + 9.0 * M2u1 - 3.0 * u1 * M0) + guo * (-3.0 * Fy * M0 + 9.0 * M2F1);
+        const double b2 = orho * (3.0 * M1[2] + 9.0 * M2u2 - 3.0 * u2 * M0) + guo * (-3.0 * Fz * M0 + 9.0 * M2F2);
+        const double g0 = guo * (3.0 * (M1[0] - u0 * M0) + 9.0 * M2u0);
+        const double g1 = guo * (3.0 * (M1[1] - u1 * M0) + 9.0 * M2u1);
+        const double g2 = guo * (3.0 * (M1[2] - u2 * M0) + 9.0 * M2u2);
+        // tau derivative: sum_j Lam_j om^2 (f_j - deq_j + s_j / 2)
+        const double Ldeq = dr * M0 + rho * (3.0 * uM1 + 4.5 * uM2u - 1.5 * uu * M0);
+        const double Lsrc = 3.0 * FM1 - 3.0 * uF * M0 + 9.0 * FM2u;
+        const double tt = om * om * (Lf - Ldeq + 0.5 * Lsrc);
+        // lam(t)_j = (1 - om) Lam_j + a + b . (c_j - u) / rho
         const double ir = 1.0 / rho;
+        const double bi0 = b0 * ir, bi1 = b1 * ir, bi2 = b2 * ir;
+        const double a0 = a - (bi0 * u0 + bi1 * u1 + bi2 * u2);
 #pragma unroll
         for (int j = 0; j < 19; ++j) {
-            const int cx = kCx[j], cy = kCy[j], cz = kCz[j];
-            const double w = wq(j);
-            const double L = double(Ls[j][threadIdx.x]);
-            *(P *)((char *)(lam0 + (size_t)j * n) + oP) =
-                P((1.0 - om) * L + a + (b0 * (cx - u0) + b1 * (cy - u1) + b2 * (cz - u2)) * ir);
-            const double cu = cx * u0 + cy * u1 + cz * u2;
-            const double cF = cx * Fx + cy * Fy + cz * Fz;
-            const double deq = w * dr + w * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-            const double si = w * (3.0 * (cF - uF) + 9.0 * cF * cu);
-            tt += L * om * om * ((double(fv[j]) - deq) + 0.5 * si);
+            double v = (1.0 - om) * double(lt[j]) + a0;
+            if (kCx[j] != 0) v += kCx[j] > 0 ? bi0 : -bi0;
+            if (kCy[j] != 0) v += kCy[j] > 0 ? bi1 : -bi1;
+            if (kCz[j] != 0) v += kCz[j] > 0 ? bi2 : -bi2;
+            *(P *)((char *)(lam0 + (size_t)j * n) + oP) = P(v);
         }
         tb[0] = tt;
         double fb0 = g0 + 0.5 * b0 * ir, fb1 = g1 + 0.5 * b1 * ir, fb2 = g2 + 0.5 * b2 * ir;
