@@ -12,13 +12,13 @@
 // below produce lam(t), qb(t) and add this step's share of the parameter
 // derivatives, in the reverse order of the forward operations:
 //   ka_spread_tiles      ub(x) = sum_i delta(x - q_i) qb_i (the adjoint of u'),
-//                        gathered per tile, and lam(t+1) += d u'/d f(t+1)^T ub;
-//                        qb(t) = qb(t+1) + sum_x (u'(x) . qb) grad_q delta
+//                        gathered per tile, and lam(t+1) += d u'/d f(t+1)^T ub
 //   ka_lb_adj            lam(t) from lam(t+1): propagation reversed (a pull),
 //                        then the transposed Jacobian of the collision;
 //                        Fb = d f*/d F^T Lam + ub / (2 rho'), tau derivative
-//   ka_interp_force_s    phib_i = sum_x Fb delta, qb += sum_x (Fb . phi_i) grad_q
-//                        delta, and the shares of Vdot = grad V . phib
+//   ka_interp_adj        phib_i = sum_x Fb delta, qb(t) = qb(t+1) + sum_x
+//                        (Fb . phi_i + u'(x) . qb(t+1)) grad_q delta, and the
+//                        shares of Vdot = grad V . phib
 //   ka_force_jvp         qb += (d Phi / d q)^T phib and the alpha, k_V, eps
 //                        derivatives.
 // Every nodal force is minus the gradient of an energy (W_S, k_V (V - V0)^2 /
@@ -36,12 +36,7 @@
 namespace iblb {
 namespace {
 
-// the same tables in constant memory, for loops that index them with a
-// uniform counter
-__constant__ int cCx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-__constant__ int cCy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-__constant__ int cCz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-
+// D3Q19 velocities
 constexpr int kCx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 constexpr int kCy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int kCz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
@@ -555,37 +550,6 @@ __device__ __forceinline__ int wave_incl_scan(int c, int lane)
     return c;
 }
 
-// One wavefront per vertex, one lane per stencil node (t = thread index from
-// the first vertex block): qb0_i = qb1_i + sum_x (u'(x) . qb1_i) grad_q
-// delta(x - q_i), u' from U (the wall velocity at a wall node).
-template <typename P>
-__device__ __forceinline__ void interp_adj_u(const AdjArgs &A, const double *__restrict__ q,
-                                             const double *__restrict__ qb1, const P *__restrict__ U,
-                                             double *__restrict__ qb0, long long t)
-{
-    const int nv = A.nv;
-    const long long n = A.g.n;
-    const int v = (int)(t >> 6), lane = (int)(t & 63);
-    if (v >= nv) return;  // whole wavefronts take the same branch
-    const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
-    const double b[3] = {qb1[v], qb1[nv + v], qb1[2 * nv + v]};
-    double s[3] = {0.0, 0.0, 0.0};
-    if (finite_pos(qx, qy, qz)) {
-        const Node nd = stencil_node(A, qx, qy, qz, lane);
-        double u[3];
-        if (nd.id >= 0) {
-            for (int c = 0; c < 3; ++c) u[c] = double(U[c * n + nd.id]);
-        } else {
-            for (int c = 0; c < 3; ++c) u[c] = nd.side ? A.uhi[c] : A.ulo[c];
-        }
-        const double ubq = u[0] * b[0] + u[1] * b[1] + u[2] * b[2];
-        for (int c = 0; c < 3; ++c) s[c] = ubq * nd.gw[c];
-    }
-    for (int c = 0; c < 3; ++c) s[c] = wave_sum64(s[c]);
-    if (lane == 0)
-        for (int c = 0; c < 3; ++c) qb0[c * nv + v] = b[c] + s[c];
-}
-
 // Tile blocks (lane = node), striding over the forward step's list of active
 // tiles: the adjoint of u' gathered from the vertices whose stencil reaches
 // the tile (the tile's vertex mask as the forward spread it), ub(x) =
@@ -595,23 +559,17 @@ __device__ __forceinline__ void interp_adj_u(const AdjArgs &A, const double *__r
 // ascending vertex order and four wavefronts each sum a quarter of it, so the
 // sums have a fixed order (no atomics).  Wavefront 0 fetches its nodes' f1,
 // U and lam when the tile is known, so that those loads overlap the gather.
-// Blocks ntb and after: interp_adj_u, one wavefront per vertex.
 template <typename P>
 __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *__restrict__ q,
                                                        const double *__restrict__ qb1, const P *__restrict__ f1,
                                                        const P *__restrict__ U, const uint64_t *__restrict__ mask,
                                                        const int *__restrict__ alist, const uint32_t *__restrict__ acnt,
-                                                       int ntb, P *__restrict__ ub, P *__restrict__ lam,
-                                                       double *__restrict__ qb0, int *err)
+                                                       int ntb, P *__restrict__ ub, P *__restrict__ lam, int *err)
 {
     const Grid &g = A.g;
     const int nv = A.nv;
     const long long n = g.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if ((int)blockIdx.x >= ntb) {
-        interp_adj_u<P>(A, q, qb1, U, qb0, (long long)(blockIdx.x - ntb) * blockDim.x + tid);
-        return;
-    }
     __shared__ int sid[kTileCap];
     __shared__ P sw[kTileCap * 12];      // per listed vertex: its weights at the tile's 4 x, 4 y, 4 z positions
     __shared__ double sqb[kTileCap * 3];  // and qb1
@@ -736,15 +694,22 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
     }
 }
 
-// phib_i = sum_x Fb delta and qb0_i += sum_x (Fb . phi_i) grad_q delta, with
-// phi_i = (phi_S + phi_W)_i - k_V (V - V0) / V0 (dV/dq)_i from the kept parts;
-// vpart[block] = this block's share of grad V . phib
+// The adjoints of both interpolations, one wavefront per vertex, one lane
+// per stencil node, sharing the stencil weights:
+//  - of the force spreading: phib_i = sum_x Fb delta(x - q_i), and
+//    sum_x (Fb . phi_i) grad_q delta, with phi_i = (phi_S + phi_W)_i -
+//    k_V (V - V0) / V0 (dV/dq)_i from the kept parts;
+//  - of the velocity interpolation of the move: sum_x (u'(x) . qb1_i)
+//    grad_q delta, u' from U (the wall velocity at a wall node);
+// qb0_i = qb1_i + both sums (the force Jacobian's share is added after), and
+// vpart[block] = this block's share of grad V . phib.
 template <typename P>
-__global__ __launch_bounds__(256) void ka_interp_force_s(AdjArgs A, const double *__restrict__ q,
-                                                         const P *__restrict__ phs, const P *__restrict__ gvs,
-                                                         const double *__restrict__ dV, const double *__restrict__ Fb,
-                                                         double *__restrict__ phib, double *__restrict__ qb0,
-                                                         double *__restrict__ vpart)
+__global__ __launch_bounds__(256) void ka_interp_adj(AdjArgs A, const double *__restrict__ q,
+                                                     const double *__restrict__ qb1, const P *__restrict__ U,
+                                                     const P *__restrict__ phs, const P *__restrict__ gvs,
+                                                     const double *__restrict__ dV, const double *__restrict__ Fb,
+                                                     double *__restrict__ phib, double *__restrict__ qb0,
+                                                     double *__restrict__ vpart)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = (int)(t >> 6), k = (int)(t & 63);
@@ -754,6 +719,7 @@ __global__ __launch_bounds__(256) void ka_interp_force_s(AdjArgs A, const double
     if (v < nv) {  // whole wavefronts take the same branch
         const double kf = A.kv_over_V0 * dV[0];
         const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
+        const double b[3] = {qb1[v], qb1[nv + v], qb1[2 * nv + v]};
         double p[3], gv[3];
         for (int c = 0; c < 3; ++c) {
             gv[c] = double(gvs[c * nv + v]);
@@ -762,14 +728,18 @@ __global__ __launch_bounds__(256) void ka_interp_force_s(AdjArgs A, const double
         double pb[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
         if (finite_pos(qx, qy, qz)) {
             const Node nd = stencil_node(A, qx, qy, qz, k);
+            double u[3];
+            double sw = 0.0;  // the weight of grad_q delta at this node
             if (nd.id >= 0) {
                 const double fb[3] = {Fb[nd.id], Fb[n + nd.id], Fb[2 * n + nd.id]};
-                const double fp = fb[0] * p[0] + fb[1] * p[1] + fb[2] * p[2];
-                for (int c = 0; c < 3; ++c) {
-                    pb[c] = fb[c] * nd.w;
-                    s[c] = fp * nd.gw[c];
-                }
+                for (int c = 0; c < 3; ++c) u[c] = double(U[c * n + nd.id]);
+                sw = fb[0] * p[0] + fb[1] * p[1] + fb[2] * p[2];
+                for (int c = 0; c < 3; ++c) pb[c] = fb[c] * nd.w;
+            } else {
+                for (int c = 0; c < 3; ++c) u[c] = nd.side ? A.uhi[c] : A.ulo[c];
             }
+            sw += u[0] * b[0] + u[1] * b[1] + u[2] * b[2];
+            for (int c = 0; c < 3; ++c) s[c] = sw * nd.gw[c];
         }
         for (int c = 0; c < 3; ++c) {
             pb[c] = wave_sum64(pb[c]);
@@ -778,7 +748,7 @@ __global__ __launch_bounds__(256) void ka_interp_force_s(AdjArgs A, const double
         if (k == 0) {
             for (int c = 0; c < 3; ++c) {
                 phib[c * nv + v] = pb[c];
-                qb0[c * nv + v] += s[c];
+                qb0[c * nv + v] = b[c] + s[c];
             }
             vd[0] = gv[0] * pb[0] + gv[1] * pb[1] + gv[2] * pb[2];
         }
@@ -804,11 +774,11 @@ static hipError_t reverse_kept(const AdjArgs &A, const AdjLevel &L, const AdjWor
     // tile blocks for the active-tile count expected at set-up, with a
     // quarter in reserve; they stride over the list if it grows beyond that
     const int ntb = A.tile_blocks;
-    ka_spread_tiles<P><<<ntb + blocks_for(64ll * A.nv), 256, 0, s>>>(A, L.q, w.qb1, f1, U, L.mask, L.alist, L.acnt,
-                                                                       ntb, ub, (P *)w.lam1, w.qb0, w.err);
+    ka_spread_tiles<P><<<ntb, 256, 0, s>>>(A, L.q, w.qb1, f1, U, L.mask, L.alist, L.acnt, ntb, ub, (P *)w.lam1,
+                                           w.err);
     ka_lb_adj<P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, ub, w.tpart, (const P *)w.lam1, (P *)w.lam0, w.Fb);
     const int nvp = blocks_for(64ll * A.nv);
-    ka_interp_force_s<P><<<nvp, 256, 0, s>>>(A, L.q, phs, gvs, L.dV, w.Fb, w.phib, w.qb0, w.vpart);
+    ka_interp_adj<P><<<nvp, 256, 0, s>>>(A, L.q, w.qb1, U, phs, gvs, L.dV, w.Fb, w.phib, w.qb0, w.vpart);
     ka_force_jvp<P><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, L.q, L.inc4, L.fref, w.phib, gvs, L.dV, w.vpart, nvp,
                                                           w.qb0, w.grads);
     return hipGetLastError();
