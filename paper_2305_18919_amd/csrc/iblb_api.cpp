@@ -1838,16 +1838,17 @@ int sweep_segments(iblb_ctx *c, AdjState *a, const AdjArgs &A)
 {
     const int every = a->every, nseg = (a->n + every - 1) / every;
     auto seg_len = [&](int sgm) { return std::min(every, a->n - sgm * every); };
-    if (!a->rs) {
-        if (hipStreamCreateWithFlags(&a->rs, hipStreamNonBlocking) != hipSuccess) {
-            a->rs = nullptr;
-            return fail(c, IBLB_E_DEVICE, "cannot create the reverse sweep's stream");
-        }
-        for (int k = 0; k < 2; ++k)
-            if (hipEventCreateWithFlags(&a->recorded[k], hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&a->swept[k], hipEventDisableTiming) != hipSuccess)
-                return fail(c, IBLB_E_DEVICE, "cannot create the reverse sweep's events");
+    // the stream and events, created at the first sweep (each one that is
+    // still missing, should an earlier attempt have failed part-way)
+    if (!a->rs && hipStreamCreateWithFlags(&a->rs, hipStreamNonBlocking) != hipSuccess) {
+        a->rs = nullptr;
+        return fail(c, IBLB_E_DEVICE, "cannot create the reverse sweep's stream");
     }
+    for (hipEvent_t *ev : {&a->recorded[0], &a->recorded[1], &a->swept[0], &a->swept[1]})
+        if (!*ev && hipEventCreateWithFlags(ev, hipEventDisableTiming) != hipSuccess) {
+            *ev = nullptr;
+            return fail(c, IBLB_E_DEVICE, "cannot create the reverse sweep's events");
+        }
     int rc = checkpoint(c, a->ck[(size_t)nseg - 1], false);
     if (rc) return rc;
     c->t = a->t0 + (long long)(nseg - 1) * every;

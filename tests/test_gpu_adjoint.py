@@ -87,6 +87,27 @@ def test_checkpoint_segments_match_every_level_kept(prec):
     assert np.abs(dq8 - dq0).max() <= 1e-12 * np.abs(dq0).max()
 
 
+def test_checkpoint_sweeps_repeat_on_one_recording():
+    """Two sweeps of one checkpointed recording, one per observable: the
+    second reuses the sweep's stream, events and the two segment recordings
+    of the first, and both give the gradients of recordings made for them
+    alone."""
+    announce("adjoint checkpoint sweeps repeated")
+    d, m = make(**BASE)
+    with iblb.Simulation(d, m, precision=iblb.FP32_DEV) as s:
+        s.adjoint_record(STEPS, 8)
+        _, _, dh, dr2 = iblb.sphere_fit_grad(s.vertices(), 0, 0.5, 2.0)
+        gh, qh = s.adjoint_backward(dh)
+        gr, qr = s.adjoint_backward(dr2)
+        assert s.t == STEPS
+    for which, g, dq in (("h", gh, qh), ("r2", gr, qr)):
+        _, g1, dq1 = gpu_gradients(iblb.FP32_DEV, which, 8)
+        dabar = sum(mk * g[k] for k, mk in enumerate(MODEL))
+        g = np.array([dabar, g[3], g[4], g[5]])
+        assert np.abs(g - g1).max() <= 1e-12 * np.abs(g1).max(), (which, g, g1)
+        assert np.abs(dq - dq1).max() <= 1e-12 * np.abs(dq1).max()
+
+
 def test_autograd_function_combines_both_observables():
     d, m = make(**BASE)
     p = torch.tensor([BASE["abar"], BASE["kv"], BASE["eps"], BASE["tau"]], dtype=torch.float64, requires_grad=True)
