@@ -557,8 +557,10 @@ __device__ __forceinline__ int wave_incl_scan(int c, int lane)
 // ub != 0, the adjoint of u' = (sum c f1 + F/2) / rho1 with respect to f1:
 // lam_j += (c_j - u') . ub / rho1, u' from U.  The list comes out in
 // ascending vertex order and four wavefronts each sum a quarter of it, so the
-// sums have a fixed order (no atomics).  Wavefront 0 fetches its nodes' f1,
-// U and lam when the tile is known, so that those loads overlap the gather.
+// sums have a fixed order (no atomics).  The listed vertices' positions and
+// qb1 are loaded in one round and their 12 one-dimensional weights each are
+// evaluated by 12 threads; wavefront 0 fetches its nodes' f1, U and lam while
+// the sums run.
 template <typename P>
 __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *__restrict__ q,
                                                        const double *__restrict__ qb1, const P *__restrict__ f1,
@@ -573,6 +575,7 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
     __shared__ int sid[kTileCap];
     __shared__ P sw[kTileCap * 12];      // per listed vertex: its weights at the tile's 4 x, 4 y, 4 z positions
     __shared__ double sqb[kTileCap * 3];  // and qb1
+    __shared__ double sq[kTileCap * 3];   // and q
     __shared__ int swt[4];
     __shared__ double part[3][3][64];
     const int W = (nv + 63) >> 6, J = (W + 255) >> 8;  // mask words per thread: at most 4 (65536 vertices)
@@ -592,15 +595,6 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
         const int x = tx * 4 + lx, y = ty * 4 + ly, zf = tz * 4 + lz;
         const bool node = wave == 0 && x < g.nx && y < g.ny && zf < g.nzf;
         const long long id = ((long long)zf * g.ny + y) * g.nx + x;
-        P fv[19], lv[19], uv[3];
-        if (node) {
-#pragma unroll
-            for (int k = 0; k < 19; ++k) {
-                fv[k] = f1[k * n + id];
-                lv[k] = lam[k * n + id];
-            }
-            for (int k = 0; k < 3; ++k) uv[k] = U[k * n + id];
-        }
         const int w0 = tid * J;
         uint64_t wv[4];
         int c = 0;
@@ -634,22 +628,50 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
             atomicOr(err, kErrOverflow);
         __syncthreads();
         const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 4 + g.zoff;  // lattice coordinates of the tile's first node
+        // the listed vertices' positions and qb1, all loads in flight together
         for (int e = tid; e < nent; e += 256) {
             const int v = sid[e] < nv ? sid[e] : 0;  // (marks name vertices below nv only)
-            const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
-            const int bx = (int)floor(qx) - 1, by = (int)floor(qy) - 1, bz = (int)floor(qz) - 1;
+            double a[6];
 #pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                // offset of the tile's node in the vertex's stencil (0..3 inside)
-                const int ox = wrapn(x0 + l - bx, g.nx), oy = wrapn(y0 + l - by, g.ny);
-                const int oz = g.walls ? z0 + l - bz : wrapn(z0 + l - bz, g.nz);
-                sw[e * 12 + l] = P(ox <= 3 ? phi4d(double(bx + ox) - qx) : 0.0);
-                sw[e * 12 + 4 + l] = P(oy <= 3 ? phi4d(double(by + oy) - qy) : 0.0);
-                sw[e * 12 + 8 + l] = P(oz >= 0 && oz <= 3 ? phi4d(double(bz + oz) - qz) : 0.0);
+            for (int k = 0; k < 3; ++k) {
+                a[k] = q[k * nv + v];
+                a[3 + k] = qb1[k * nv + v];
             }
-            for (int k = 0; k < 3; ++k) sqb[e * 3 + k] = qb1[k * nv + v];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                sq[e * 3 + k] = a[k];
+                sqb[e * 3 + k] = a[3 + k];
+            }
         }
         __syncthreads();
+        // their 1D weights at the tile's 4 x, 4 y and 4 z positions, one per
+        // thread (12 per vertex), so that the evaluations run side by side
+        for (int it = tid; it < nent * 12; it += 256) {
+            const int e = it / 12, r = it - e * 12, ax = r >> 2, l = r & 3;
+            const double qa = sq[e * 3 + ax];
+            const int b = (int)floor(qa) - 1;
+            // offset of the tile's node in the vertex's stencil (0..3 inside)
+            int o;
+            if (ax == 0)
+                o = wrapn(x0 + l - b, g.nx);
+            else if (ax == 1)
+                o = wrapn(y0 + l - b, g.ny);
+            else
+                o = g.walls ? z0 + l - b : wrapn(z0 + l - b, g.nz);
+            sw[it] = P(o >= 0 && o <= 3 ? phi4d(double(b + o) - qa) : 0.0);
+        }
+        __syncthreads();
+        // wavefront 0 fetches its node's f1, U and lam now: the loads overlap
+        // the sums below, which read LDS only
+        P fv[19], lv[19], uv[3];
+        if (node) {
+#pragma unroll
+            for (int k = 0; k < 19; ++k) {
+                fv[k] = f1[k * n + id];
+                lv[k] = lam[k * n + id];
+            }
+            for (int k = 0; k < 3; ++k) uv[k] = U[k * n + id];
+        }
         const int chunk = (nent + 3) >> 2;
         const int e0 = wave * chunk, e1 = min(nent, e0 + chunk);
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
