@@ -900,8 +900,7 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
     for (uint32_t ai = (uint32_t)blk; ai < na; ai += nsp) {
         const uint32_t an = ai + nsp;
         const int next = alist[an < na ? an : ai];
-        // this lane's node; wavefront 0 fetches its populations now, next to
-        // the tile's mask words
+        // this lane's node (wavefront 0 updates it once the force is known)
         const int tz = tile / (g.ntx * g.nty);
         const int rem = tile - tz * g.ntx * g.nty;
         const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
@@ -915,13 +914,6 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 wv[j] = (j < J && w0 + j < W) ? mw[w0 + j] : 0ull;
-        }
-        if (wave == 0 && node) {
-            T d[19];
-            load_pops<S, P == 1>(f, g, x, y, zf, d);
-#pragma unroll
-            for (int i = 0; i < 19; ++i)
-                spop[i][lane] = d[i];
         }
         // set bits (low 20 bits) and nonzero words (above) of this thread's words
         int c = 0;
@@ -982,13 +974,24 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
             }
         }
         __syncthreads();
-        // stage each listed vertex's local weights and total force
+        // stage each listed vertex's local weights and total force.
+        // Wavefront 0 fetches its node's populations first, so that they
+        // arrive with the staged vertices' loads: fetched earlier, they would
+        // be waited for at the first barrier (loads complete in order)
         {
+            T d[19];
+            if (wave == 0 && node)
+                load_pops<S, P == 1>(f, g, x, y, zf, d);
             const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 4 + g.zoff;
             const T kf = skfac;
             for (int e = tid; e < nent; e += 256) {
                 const Staged<T> st = stage_load<T>(sid[e], base, wts, phiSW, gV, nv, err, g, x0, y0, z0);
                 stage_store<T>(st, e, kf, sw, sph);
+            }
+            if (wave == 0 && node) {
+#pragma unroll
+                for (int i = 0; i < 19; ++i)
+                    spop[i][lane] = d[i];
             }
         }
         __syncthreads();
