@@ -469,20 +469,20 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int v = t >> 3, lane = t & 7;
-    // Vdot = grad V . phib, the sum of nvp partial sums
-    __shared__ double s_vdot;
-    {
-        double vs[1] = {0.0};
-        for (int k = threadIdx.x; k < nvp; k += 256) vs[0] += vparts[k];
-        block_sum<1>(vs);
-        if (threadIdx.x == 0) s_vdot = vs[0];
-        __syncthreads();
-    }
+    const int nv = A.nv, nf = A.nf;
+    // the vertex's own phib, dV/dq and qb0 so far, read by lane 0 at the
+    // end: loaded first, so that they arrive with the face data
+    double pbv[3] = {0.0, 0.0, 0.0}, gvv[3] = {0.0, 0.0, 0.0}, qbv[3] = {0.0, 0.0, 0.0};
+    if (v < nv && lane == 0)
+        for (int k = 0; k < 3; ++k) {
+            pbv[k] = phib[k * nv + v];
+            gvv[k] = double(gV[k * nv + v]);
+            qbv[k] = qb0[k * nv + v];
+        }
     double pg[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (v < A.nv) {  // whole groups of 8 take the same branch
-        const int nv = A.nv, nf = A.nf;
+    double jv[3] = {0.0, 0.0, 0.0}, dgv[3] = {0.0, 0.0, 0.0}, dS[3][3] = {{0}}, ljz = 0.0;
+    if (v < nv) {  // whole groups of 8 take the same branch
         const double w1 = 0.5 * A.alpha[2];
-        double jv[3] = {0.0, 0.0, 0.0}, dgv[3] = {0.0, 0.0, 0.0}, dS[3][3] = {{0}}, ljz = 0.0;
         for (int s = lane; s < A.slots; s += 8) {
             const int4 e = inc4[(long long)v * A.slots + s];
             if (e.w < 0) continue;
@@ -521,12 +521,23 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
             for (int m = 0; m < 3; ++m) dS[m][k] = group8_sum(dS[m][k]);
         }
         ljz = group8_sum(ljz);
+    }
+    // Vdot = grad V . phib, the sum of nvp partial sums (after the face work,
+    // which does not need it)
+    __shared__ double s_vdot;
+    {
+        double vs[1] = {0.0};
+        for (int k = threadIdx.x; k < nvp; k += 256) vs[0] += vparts[k];
+        block_sum<1>(vs);
+        if (threadIdx.x == 0) s_vdot = vs[0];
+        __syncthreads();
+    }
+    if (v < nv) {
         if (lane == 0) {
             const double dV = dVp[0], Vdot = s_vdot;
-            const double pbv[3] = {phib[v], phib[nv + v], phib[2 * nv + v]};
             for (int k = 0; k < 3; ++k) {
-                const double gvk = double(gV[k * nv + v]);
-                qb0[k * nv + v] += jv[k] - A.kv_over_V0 * (Vdot * gvk + dV * dgv[k]);
+                const double gvk = gvv[k];
+                qb0[k * nv + v] = qbv[k] + (jv[k] - A.kv_over_V0 * (Vdot * gvk + dV * dgv[k]));
                 for (int m = 0; m < 3; ++m) pg[m] += pbv[k] * dS[m][k];
                 pg[3] += pbv[k] * (-dV / A.V0) * gvk;
             }
