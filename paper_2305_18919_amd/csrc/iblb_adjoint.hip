@@ -12,7 +12,8 @@
 // below produce lam(t), qb(t) and add this step's share of the parameter
 // derivatives, in the reverse order of the forward operations:
 //   ka_spread_tiles      ub(x) = sum_i delta(x - q_i) qb_i (the adjoint of u'),
-//                        gathered per tile, and lam(t+1) += d u'/d f(t+1)^T ub
+//                        gathered per tile, and lam(t+1) += d u'/d f(t+1)^T ub;
+//                        keeps ub / (2 rho') for the next kernel
 //   ka_lb_adj            lam(t) from lam(t+1): propagation reversed (a pull),
 //                        then the transposed Jacobian of the collision;
 //                        Fb = d f*/d F^T Lam + ub / (2 rho'), tau derivative
@@ -288,11 +289,11 @@ __device__ __forceinline__ void block_sum(double (&v)[K])
 //   lam0_j = (1 - 1/tau) Lam_j + a + b . (c_j - u) / rho,
 //   a = sum_i Lam_i d f*_i / d rho |u,   b = sum_i Lam_i d f*_i / d u,
 //   Fb = sum_i Lam_i d S_i / d F + b / (2 rho) + ub / (2 rho1)  (the last term
-//        the force share of the interpolated velocity's adjoint),
+//        the force share of the interpolated velocity's adjoint, which the
+//        spread adjoint leaves in ub already divided by 2 rho1),
 //   d/dtau: sum_i Lam_i [(f_i - f^eq_i) + s_i / 2] / tau^2  with S_i = (1 - 1/(2 tau)) s_i.
-// Lam is gathered once into LDS and read by two passes; the populations stay
-// in registers.  ub is zeroed where it was read (this kernel is its last
-// reader in the step).  The tau derivative goes to tslot[block], a running
+// Lam, the populations, F and ub are all loaded before any is used.  ub is
+// zeroed where it was read (this kernel is its last reader in the step).  The tau derivative goes to tslot[block], a running
 // sum per block that the caller adds up at the end of the sweep.  P is the
 // element type of the kept populations, force density and of lam.
 // element at a 32-bit byte offset from a base pointer (a uniform base and
@@ -310,7 +311,7 @@ __device__ __forceinline__ T ld32_once(const T *base, uint32_t byte_off)
 }
 
 template <typename P>
-__global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict__ f0, const P *__restrict__ f1,
+__global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict__ f0,
                                                  const P *__restrict__ F, P *__restrict__ ub,
                                                  double *__restrict__ tslot, const P *__restrict__ lam1,
                                                  P *__restrict__ lam0, double *__restrict__ Fb)
@@ -337,6 +338,7 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
         // flight together)
         P fv[19];
         P lt[19];
+        const P ubv[3] = {ld32(ub, oP), ld32(ub + n, oP), ld32(ub + 2 * n, oP)};
 #pragma unroll
         for (int i = 0; i < 19; ++i) fv[i] = ld32_once(f0 + (size_t)i * n, oP);
 #pragma unroll
@@ -431,15 +433,12 @@ __global__ __launch_bounds__(256) void ka_lb_adj(AdjArgs A, const P *__restrict_
         }
         tb[0] = tt;
         double fb0 = g0 + 0.5 * b0 * ir, fb1 = g1 + 0.5 * b1 * ir, fb2 = g2 + 0.5 * b2 * ir;
-        const double ub0 = double(ub[id]), ub1 = double(ub[n + id]), ub2 = double(ub[2 * n + id]);
+        const double ub0 = double(ubv[0]), ub1 = double(ubv[1]), ub2 = double(ubv[2]);
         if (ub0 != 0.0 || ub1 != 0.0 || ub2 != 0.0) {
-            double d1 = 0.0;
-#pragma unroll
-            for (int i = 0; i < 19; ++i) d1 += double(ld32(f1 + (size_t)i * n, oP));
-            const double h = 0.5 / (A.rho0 + d1);
-            fb0 += ub0 * h;
-            fb1 += ub1 * h;
-            fb2 += ub2 * h;
+            // ub / (2 rho1), as the spread adjoint left it
+            fb0 += ub0;
+            fb1 += ub1;
+            fb2 += ub2;
             // this thread was its last reader: zero for the next step's spread
             ub[id] = P(0);
             ub[n + id] = P(0);
@@ -566,7 +565,8 @@ __device__ __forceinline__ int wave_incl_scan(int c, int lane)
 // the tile (the tile's vertex mask as the forward spread it), ub(x) =
 // sum_i delta(x - q_i) qb1_i, written for every node of the tile; then, where
 // ub != 0, the adjoint of u' = (sum c f1 + F/2) / rho1 with respect to f1:
-// lam_j += (c_j - u') . ub / rho1, u' from U.  The list comes out in
+// lam_j += (c_j - u') . ub / rho1, u' from U; ub / (2 rho1), its force share,
+// is what stays in ub for the LB adjoint.  The list comes out in
 // ascending vertex order and four wavefronts each sum a quarter of it, so the
 // sums have a fixed order (no atomics).  The listed vertices' positions and
 // qb1 are loaded in one round and their 12 one-dimensional weights each are
@@ -707,21 +707,24 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
                 s2 += part[w][2][lane];
             }
             if (node) {
-                const P u0 = P(s0), u1 = P(s1), u2 = P(s2);
-                ub[id] = u0;
-                ub[n + id] = u1;
-                ub[2 * n + id] = u2;
-                const double b[3] = {double(u0), double(u1), double(u2)};
+                const double b[3] = {double(P(s0)), double(P(s1)), double(P(s2))};
+                // the force share of u' = (sum c f1 + F/2) / rho1 needs
+                // ub / (2 rho1): kept in ub for the LB adjoint
+                double h = 0.0;
                 if (b[0] != 0.0 || b[1] != 0.0 || b[2] != 0.0) {
                     double dr = 0.0;
 #pragma unroll
                     for (int k = 0; k < 19; ++k) dr += double(fv[k]);
                     const double ir = 1.0 / (A.rho0 + dr);
+                    h = 0.5 * ir;
                     const double ub_u = b[0] * double(uv[0]) + b[1] * double(uv[1]) + b[2] * double(uv[2]);
 #pragma unroll
                     for (int j = 0; j < 19; ++j)
                         lam[j * n + id] = P(double(lv[j]) + (kCx[j] * b[0] + kCy[j] * b[1] + kCz[j] * b[2] - ub_u) * ir);
                 }
+                ub[id] = P(b[0] * h);
+                ub[n + id] = P(b[1] * h);
+                ub[2 * n + id] = P(b[2] * h);
             }
         }
     }
@@ -809,7 +812,7 @@ static hipError_t reverse_kept(const AdjArgs &A, const AdjLevel &L, const AdjWor
     const int ntb = A.tile_blocks;
     ka_spread_tiles<P><<<ntb, 256, 0, s>>>(A, L.q, w.qb1, f1, U, L.mask, L.alist, L.acnt, ntb, ub, (P *)w.lam1,
                                            w.err);
-    ka_lb_adj<P><<<blocks_for(n), 256, 0, s>>>(A, f0, f1, F, ub, w.tpart, (const P *)w.lam1, (P *)w.lam0, w.Fb);
+    ka_lb_adj<P><<<blocks_for(n), 256, 0, s>>>(A, f0, F, ub, w.tpart, (const P *)w.lam1, (P *)w.lam0, w.Fb);
     const int nvp = blocks_for(64ll * A.nv);
     ka_interp_adj<P><<<nvp, 256, 0, s>>>(A, L.q, w.qb1, U, phs, gvs, L.dV, w.Fb, w.phib, w.qb0, w.vpart);
     ka_force_jvp<P><<<blocks_for(8ll * A.nv), 256, 0, s>>>(A, L.q, L.inc4, L.fref, w.phib, gvs, L.dV, w.vpart, nvp,

@@ -164,7 +164,7 @@ struct AdjLevel {
     const double *fref;
 };
 struct AdjWork {
-    double *ub;     // [3][n] adjoint of u' (element type of the level), zero at the step's start (ka_lb_adj clears it)
+    double *ub;     // [3][n] adjoint of u' over 2 rho(t+1) (element type of the level), zero at the step's start (ka_lb_adj clears it)
     double *lam1, *lam0;      // [19][n] adjoint populations at t + 1 and t (element type of the level)
     double *Fb;               // [3][n]
     double *phib, *qb1, *qb0; // [3][nv]
