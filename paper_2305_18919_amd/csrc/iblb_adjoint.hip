@@ -753,28 +753,33 @@ __global__ __launch_bounds__(256) void ka_interp_adj(AdjArgs A, const double *__
     const long long n = A.g.n;
     double vd[1] = {0.0};
     if (v < nv) {  // whole wavefronts take the same branch
-        const double kf = A.kv_over_V0 * dV[0];
+        // every load of the vertex's own data first; each is waited for only
+        // where it is used
         const double qx = q[v], qy = q[nv + v], qz = q[2 * nv + v];
         const double b[3] = {qb1[v], qb1[nv + v], qb1[2 * nv + v]};
-        double p[3], gv[3];
-        for (int c = 0; c < 3; ++c) {
-            gv[c] = double(gvs[c * nv + v]);
-            p[c] = double(phs[c * nv + v]) - kf * gv[c];
-        }
+        const P gvr[3] = {gvs[v], gvs[nv + v], gvs[2 * nv + v]};
+        const P phr[3] = {phs[v], phs[nv + v], phs[2 * nv + v]};
+        const double dVv = dV[0];
         double pb[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
         if (finite_pos(qx, qy, qz)) {
             const Node nd = stencil_node(A, qx, qy, qz, k);
-            double u[3];
-            double sw = 0.0;  // the weight of grad_q delta at this node
+            double sw;  // the weight of grad_q delta at this node
             if (nd.id >= 0) {
                 const double fb[3] = {Fb[nd.id], Fb[n + nd.id], Fb[2 * n + nd.id]};
-                for (int c = 0; c < 3; ++c) u[c] = double(U[c * n + nd.id]);
-                sw = fb[0] * p[0] + fb[1] * p[1] + fb[2] * p[2];
-                for (int c = 0; c < 3; ++c) pb[c] = fb[c] * nd.w;
+                const double u[3] = {double(U[nd.id]), double(U[n + nd.id]), double(U[2 * n + nd.id])};
+                const double kf = A.kv_over_V0 * dVv;
+                sw = u[0] * b[0] + u[1] * b[1] + u[2] * b[2];
+                for (int c = 0; c < 3; ++c) {
+                    sw += fb[c] * (double(phr[c]) - kf * double(gvr[c]));
+                    pb[c] = fb[c] * nd.w;
+                }
             } else {
-                for (int c = 0; c < 3; ++c) u[c] = nd.side ? A.uhi[c] : A.ulo[c];
+                // beyond a wall u' is the wall velocity: its products with
+                // qb1 are uniform values, so no lane indexes the arguments
+                const double blo = A.ulo[0] * b[0] + A.ulo[1] * b[1] + A.ulo[2] * b[2];
+                const double bhi = A.uhi[0] * b[0] + A.uhi[1] * b[1] + A.uhi[2] * b[2];
+                sw = nd.side ? bhi : blo;
             }
-            sw += u[0] * b[0] + u[1] * b[1] + u[2] * b[2];
             for (int c = 0; c < 3; ++c) s[c] = sw * nd.gw[c];
         }
         for (int c = 0; c < 3; ++c) {
@@ -786,7 +791,7 @@ __global__ __launch_bounds__(256) void ka_interp_adj(AdjArgs A, const double *__
                 phib[c * nv + v] = pb[c];
                 qb0[c * nv + v] = b[c] + s[c];
             }
-            vd[0] = gv[0] * pb[0] + gv[1] * pb[1] + gv[2] * pb[2];
+            vd[0] = double(gvr[0]) * pb[0] + double(gvr[1]) * pb[1] + double(gvr[2]) * pb[2];
         }
     }
     block_sum<1>(vd);  // grad V . phib = sum_i (dV/dq)_i . phib_i, by blocks
