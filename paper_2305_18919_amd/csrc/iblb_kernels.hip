@@ -359,13 +359,18 @@ __global__ __launch_bounds__(1024) void k_lb(S *__restrict__ f, const typename P
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int zf = blockIdx.z;
-    const uint32_t t = ctr[ODD ? 1 : 0];
-    if (act == nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 &&
-        threadIdx.y == 0)
-        ctr[ODD ? 0 : 1] = t + 1u;
+    if (act == nullptr) {
+        // only the thread that advances the counter reads it: the other
+        // wavefronts go straight to their populations
+        if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 && threadIdx.y == 0)
+            ctr[ODD ? 0 : 1] = ctr[ODD ? 1 : 0] + 1u;
+    } else {
+        if (x >= a.g.nx || y >= a.g.ny)
+            return;
+        if (act[tile_of(a.g, x, y, zf)] == act_stamp(ctr[ODD ? 1 : 0]))
+            return;
+    }
     if (x >= a.g.nx || y >= a.g.ny)
-        return;
-    if (act != nullptr && act[tile_of(a.g, x, y, zf)] == act_stamp(t))
         return;
     lb_node<S, ODD>(f, Fext, err, a, x, y, zf, T(0), T(0), T(0));
 }
