@@ -138,9 +138,10 @@ __device__ __forceinline__ void volume_corner(const T *a, const T *b, const T *c
         U[k] = u[k] + (-o[k]);
         Wv[k] = w[k] + (-o[k]);
     }
-    g[0] = (U[1] * Wv[2] - U[2] * Wv[1]) / 6.0;
-    g[1] = (U[2] * Wv[0] - U[0] * Wv[2]) / 6.0;
-    g[2] = (U[0] * Wv[1] - U[1] * Wv[0]) / 6.0;
+    constexpr double sixth = 1.0 / 6.0;
+    g[0] = (U[1] * Wv[2] - U[2] * Wv[1]) * sixth;
+    g[1] = (U[2] * Wv[0] - U[0] * Wv[2]) * sixth;
+    g[2] = (U[0] * Wv[1] - U[1] * Wv[0]) * sixth;
 }
 
 // LJ force magnitude per unit eps along the wall normal at distance d
@@ -157,10 +158,13 @@ __device__ __forceinline__ Dual lj_unit(double xi, double rc, Dual d)
 {
     if (!(d.v < rc)) return mk(0.0);
     const Dual dd = d.v < 0.5 * xi ? mk(0.5 * xi) : d;
-    const Dual r = xi / dd;
+    // one reciprocal for both quotients: r = xi / dd and the result / dd
+    const double id = 1.0 / dd.v;
+    const Dual r = Dual{xi * id, -xi * dd.d * id * id};
     const Dual r2 = r * r;
     const Dual r6 = r2 * r2 * r2;
-    return 48.0 * (r6 * r6 - 0.5 * r6) / dd;
+    const Dual g = 48.0 * (r6 * r6 - 0.5 * r6);
+    return Dual{g.v * id, (g.d - g.v * id * dd.d) * id};
 }
 
 // ---------------------------------------------------------------- 4-point stencil
@@ -495,10 +499,13 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
             }
             for (int k = 0; k < 5; ++k) fr[k] = fref[k * nf + j];
             const FaceParts<Dual> p = face_parts<Dual>(a, b, c, fr, corner);
-            const Dual w2 = (mk(0.5 * (A.alpha[0] - A.alpha[2])) + 0.25 * (A.alpha[0] + A.alpha[1]) * p.lnJ) / p.J;
+            // w2 = num / J, with one reciprocal of J for it and its derivatives
+            const Dual num = mk(0.5 * (A.alpha[0] - A.alpha[2])) + 0.25 * (A.alpha[0] + A.alpha[1]) * p.lnJ;
+            const double iJ = 1.0 / p.J.v;
+            const Dual w2 = Dual{num.v * iJ, (num.d - num.v * iJ * p.J.d) * iJ};
             // derivatives of w2 with respect to alpha_1..3 (w1 = alpha3/2)
-            const double lnJ = p.lnJ.v, J = p.J.v;
-            const double dw2[3] = {(0.5 + 0.25 * lnJ) / J, 0.25 * lnJ / J, -0.5 / J};
+            const double lnJ = p.lnJ.v;
+            const double dw2[3] = {(0.5 + 0.25 * lnJ) * iJ, 0.25 * lnJ * iJ, -0.5 * iJ};
             Dual gc[3];
             volume_corner<Dual>(a, b, c, A.origin, corner, gc);
             for (int k = 0; k < 3; ++k) {
@@ -507,11 +514,12 @@ __global__ __launch_bounds__(256) void ka_force_jvp(AdjArgs A, const double *__r
                 for (int m = 0; m < 3; ++m) dS[m][k] += dw2[m] * p.Fadj[k].v + (m == 2 ? 0.5 * p.FG[k].v : 0.0);
             }
             if (A.g.walls) {
-                const Dual cz = (a[2] + b[2] + c[2]) / 3.0;
+                constexpr double third = 1.0 / 3.0;
+                const Dual cz = (a[2] + b[2] + c[2]) * third;
                 const Dual flo = lj_unit(A.xi, A.rc, cz + (-A.z_lo));
                 const Dual fhi = lj_unit(A.xi, A.rc, (-1.0) * cz + A.z_hi);
-                jv[2] += (A.eps_lo * flo.d - A.eps_hi * fhi.d) / 3.0;
-                ljz += flo.v / 3.0;
+                jv[2] += (A.eps_lo * flo.d - A.eps_hi * fhi.d) * third;
+                ljz += flo.v * third;
             }
         }
         for (int k = 0; k < 3; ++k) {
