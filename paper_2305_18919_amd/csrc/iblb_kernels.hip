@@ -1366,37 +1366,50 @@ __global__ __launch_bounds__(256) void k_record(const S *__restrict__ f, const O
                                                 uint32_t *__restrict__ acnt_s, Grid g)
 {
     using T = typename Pop<S>::C;
-    const uint32_t t = ctr[p];
-    const uint32_t lev = t - t0, levf = t - 1u - t0;
-    const bool rec = lev <= maxl, recf = levf <= maxf;
     const long long n = g.n;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // the node's populations, fields and stamp are loaded before the step
+    // counter is known (they are the live state, whatever the level), so
+    // that the wavefront waits for one round of loads; the counter decides
+    // only which stores happen
+    T d[19];
+    O Fv[3], Uv[3];
+    uint32_t st = 0;
     if (i < n) {
         // n < 2^31: 32-bit index arithmetic
         const uint32_t ui = (uint32_t)i, row = ui / (uint32_t)g.nx, zr = row / (uint32_t)g.ny;
         const int x = (int)(ui - row * (uint32_t)g.nx), y = (int)(row - zr * (uint32_t)g.ny), zf = (int)zr;
+        if (p)
+            load_pops<S, true>(f, g, x, y, zf, d);
+        else
+            load_pops<S, false>(f, g, x, y, zf, d);
+        st = stamp[tile_of(g, x, y, zf)];
+        for (int c = 0; c < 3; ++c) {
+            Fv[c] = F[(size_t)c * n + i];
+            Uv[c] = U[(size_t)c * n + i];
+        }
+    }
+    const uint32_t t = ctr[p];
+    const uint32_t lev = t - t0, levf = t - 1u - t0;
+    const bool rec = lev <= maxl, recf = levf <= maxf;
+    if (i < n) {
         // the levels are written once here and read once, in reverse order,
         // by the sweep: non-temporal stores keep them from displacing the
         // step's own arrays in the caches
         if (rec) {
-            T d[19];
-            if (p)
-                load_pops<S, true>(f, g, x, y, zf, d);
-            else
-                load_pops<S, false>(f, g, x, y, zf, d);
             O *out = store + (size_t)lev * 19 * (size_t)n;
             for (int k = 0; k < 19; ++k)
                 __builtin_nontemporal_store(O(d[k]), &out[(size_t)k * n + i]);
         }
         if (recf) {
             // U is valid, and read by the sweep, on the step's active tiles only
-            const bool on = stamp[tile_of(g, x, y, zf)] == t;
+            const bool on = st == t;
             O *Fo = Fs + (size_t)levf * 3 * (size_t)n;
             O *Uo = Us + (size_t)levf * 3 * (size_t)n;
             for (int c = 0; c < 3; ++c) {
-                __builtin_nontemporal_store(on ? F[(size_t)c * n + i] : O(0), &Fo[(size_t)c * n + i]);
+                __builtin_nontemporal_store(on ? Fv[c] : O(0), &Fo[(size_t)c * n + i]);
                 if (on)
-                    __builtin_nontemporal_store(U[(size_t)c * n + i], &Uo[(size_t)c * n + i]);
+                    __builtin_nontemporal_store(Uv[c], &Uo[(size_t)c * n + i]);
             }
         }
     }
