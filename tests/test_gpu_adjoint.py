@@ -71,7 +71,7 @@ def test_fp32_forward_adjoint_matches_reference():
     assert np.abs(dq0 - dqr).max() <= 1e-4 * np.abs(dqr).max()
 
 
-@pytest.mark.parametrize("prec", [iblb.FP32_DEV, iblb.BF16_DEV])
+@pytest.mark.parametrize("prec", [iblb.FP32_DEV, iblb.FP16_DEV, iblb.BF16_DEV])
 def test_checkpoint_segments_match_every_level_kept(prec):
     """Checkpoints every 8 steps (two full segments and a shorter one, each
     recorded again from its checkpoint) give the gradients of the window
@@ -85,6 +85,27 @@ def test_checkpoint_segments_match_every_level_kept(prec):
     announce(f"  max rel diff {np.abs(g8 - g0).max() / np.abs(g0).max():.2e}")
     assert np.abs(g8 - g0).max() <= 1e-12 * np.abs(g0).max(), (g8, g0)
     assert np.abs(dq8 - dq0).max() <= 1e-12 * np.abs(dq0).max()
+
+
+@pytest.mark.parametrize("prec", [iblb.FP16_DEV, iblb.BF16_DEV])
+def test_16bit_forward_adjoint_matches_reference(prec):
+    """16-bit population storage: the adjoint linearises around the 16-bit
+    forward's own trajectory, which departs from the FP64 one by the storage
+    rounding (FP16 keeps 11 significant bits of the scaled deviation, BF16 8),
+    so the gradients agree with the FP64 reference to that rounding only.
+    Measured: FP16 5.2e-5 (the tau derivative, the most sensitive) and 1.9e-7
+    in dJ/dq0; BF16 2.5e-4 and 1.9e-6.  The bounds leave a factor of about 4,
+    and BF16 keeps 8 times FP16's rounding."""
+    announce(f"adjoint 16-bit h prec={prec}")
+    J, g, dq0 = gpu_gradients(prec, "h", 0)
+    d, m = make(**BASE)
+    Jr, gr, dqr = gradients(d, m, MODEL, BASE["abar"], BASE["kv"], BASE["eps"], BASE["tau"], STEPS, "h")
+    rel = np.abs(g - gr) / np.abs(gr)
+    dq_rel = np.abs(dq0 - dqr).max() / np.abs(dqr).max()
+    announce(f"  rel {rel} dq {dq_rel:.2e}")
+    tol, dq_tol = (2e-4, 1e-6) if prec == iblb.FP16_DEV else (1e-3, 1e-5)
+    assert (rel <= tol).all(), rel
+    assert dq_rel <= dq_tol, dq_rel
 
 
 def test_checkpoint_sweeps_repeat_on_one_recording():
