@@ -1702,8 +1702,10 @@ hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, h
 // sheared capsule shares 0 / 0.2 / 0.35 / 0.5 / 0.6 / 0.7 / 0.8 gave 29.1 /
 // 28.6 / 28.6 / 28.5 / 28.7 / 29.8 / 29.8; shares 0.45 / 0.6 / 0.75 gave
 // 28.8 / 28.2 / 28.9 there and 82.4 / 81.5 / 83.8 on the 128x128x96 wetting
-// droplet.
-constexpr double kLbShareWithForces = 0.6;
+// droplet.  With the spreading's population fetch next to its staged loads,
+// 0.4 / 0.5 / 0.6 / 0.7 gave 28.01 / 28.00 / 28.42 / 29.40 at 64^3 and
+// 77.3 / 77.4 / 77.3 / 79.0 on the wetting droplet.
+constexpr double kLbShareWithForces = 0.5;
 
 int lb_blocks_with_forces(const Grid &g)
 {
