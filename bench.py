@@ -1,26 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark of one full IB-LB step on one MI355X.
 
-Workload (default): the 64^3 shear case -- walls moving at -+0.01, a rigidly
-coated capsule alpha = abar(1,1,1) at Ca = 0.05 meshed as a level-4 icosphere
-(2562 vertices, 5120 faces, R = 10), FP32 deviation populations with FP64
-positions and volume reductions.  Synthetic seeded inputs, no datasets.
+Workload (default, ``--workload wetting128``): the 128x128x96 wetting droplet
+-- no-slip walls at z = 0 and 95, a softly coated droplet alpha = abar(1,0,1),
+abar = 1e-4, meshed as a level-5 icosphere (10242 vertices, 20480 faces, R =
+24), a wetting lower wall (eps/abar = 1, r_cut = 2) -- with FP32 deviation
+populations and FP64 positions and volume reductions.  Synthetic seeded
+inputs, no datasets.
 
-Timed region: K steps replayed from captured hipGraphs, inputs resident in
-HBM, bracketed by torch.cuda.synchronize().  value = fluid nodes x steps /
-seconds / 1e6 (MLUPS) for the whole step (forces, spreading, LB, moments,
-interpolation and move).
+Timed region: W untimed warm-up steps, then exactly K steps replayed from
+hipGraphs captured before the warm-up (16-step graphs, one-step graphs for the
+remainder, either start parity), inputs resident in HBM.  hipEvents on the
+library's stream bracket the K steps, inside torch.cuda.synchronize() on both
+sides.  value = fluid nodes x K / event seconds / 1e6 (MLUPS) for the whole
+step (forces, spreading, LB, moments, interpolation and move).
 
-roofline: the LB kernel k_lb, the step's bandwidth-bound work, timed in a
-pass of the same domain without a mesh (so that it updates every fluid node):
-hipEvents on the library's stream around a run of graph-replayed launches,
-achieved = fluid nodes x 38 population accesses x bytes per population /
-average launch time; traffic = HBM bytes per launch from the committed
-copy-calibrated FETCH_SIZE/WRITE_SIZE counter runs, while the kernel source is
-the one they were taken on (else null).  A further pass times every kernel of the coupled step
-with hipEvents around each launch ("kernels"; these include the per-launch
-event overhead).  The FP64 CPU oracle is timed on a bounded sample of the same
-workload.
+roofline: the whole step as one unit of work.  achieved = the step's
+algorithmic bytes (the LB's 38 population accesses per fluid node plus the
+interface terms on the shell nodes, faces and vertices) / the event-timed step;
+peak = 8 TB/s HBM.  traffic = HBM bytes per step from committed
+FETCH_SIZE/WRITE_SIZE counter runs over the four dispatches of a step
+(copy-calibrated), while the kernel source is the one they were taken on, else
+null.  "dispatches" breaks the step into its four dispatches, timed one by one
+with hipEvents in a separate pass of plain launches, each with its own share of
+the algorithmic bytes.  Secondary figures: the LB kernel alone on the same
+lattice without a mesh ("lb_only"), the 256^3 probe beyond the Infinity Cache
+("probe256"), and a plain device copy ("device_copy").  "adjoint": the
+adjoint/forward time ratio of the differentiation workload (64x64x48, 2000
+steps, checkpoints every 100) with the largest relative error of its gradients
+against central finite differences.  The FP64 CPU oracle is timed on a bounded
+sample of the same workload on all host cores and on one.
 
 --pass lb / --pass copy run only the LB-only pass, or a plain device copy of
 --copy-mib MiB, for hardware-counter runs.  --study precision runs the
@@ -36,7 +45,9 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
+import subprocess
 import sys
 import time
 
@@ -45,6 +56,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + % HBM roofline per IB-LB step; adjoint/forward time ratio at stated accuracy"
 HBM_PEAK_GBS = 8000.0
+DISPATCHES = ("forces", "spread", "moments", "move")
 
 
 def workload(name: str):
@@ -56,13 +68,20 @@ def workload(name: str):
     if name == "wetting128":
         return I.c3_wetting(1.0), 1
     if name == "probe256":
-        w = I.c3_wetting(1.0)
-        w.domain = I.Domain(256, 256, 256)
-        w.mesh.vertices = w.mesh.vertices + [64.0, 64.0, 0.0]
-        w.mesh.ref_vertices = w.mesh.ref_vertices + [64.0, 64.0, 0.0]
-        w.name = "probe256_f32"
-        return w, 1
+        return probe256(), 1
     raise SystemExit(f"unknown workload {name}")
+
+
+def probe256():
+    """The wetting droplet of the 128x128x96 case in a 256^3 lattice: 1.26 GB of
+    FP32 populations, far beyond the 256 MB Infinity Cache."""
+    from paper_2305_18919_amd import inputs as I
+    w = I.c3_wetting(1.0)
+    w.domain = I.Domain(256, 256, 256)
+    w.mesh.vertices = w.mesh.vertices + [64.0, 64.0, 0.0]
+    w.mesh.ref_vertices = w.mesh.ref_vertices + [64.0, 64.0, 0.0]
+    w.name = "probe256_f32"
+    return w
 
 
 POP_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
@@ -74,61 +93,257 @@ def lb_bytes_per_node(precision: int) -> int:
     return 38 * POP_BYTES[precision]
 
 
-def cpu_baseline(w, budget_s: float):
-    """The FP64 oracle on this host, on a bounded number of steps of the same workload."""
-    from oracle import oracle as O
-    sim = O.OracleSim(w.domain, w.mesh)
-    sim.step(2)  # warm-up
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        sim.step(5)
-        steps += 5
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    return {"value": round(w.domain.n_fluid * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{w.name}: {steps} FP64 oracle steps after 2 warm-up steps ({dt:.1f} s)"}
+# ----------------------------------------------------------------- host bookkeeping
+
+def step_geometry(dom, q, split: dict) -> dict:
+    """Node counts behind the algorithmic bytes of one step at positions q.
+
+    shell: fluid nodes inside some vertex's 4^3 stencil; active: nodes of the
+    4^3 tiles those stencils reach (the spreading dispatch updates them).  Per
+    dispatch, the LB nodes it updates: the LB blocks of the other nodes (block
+    width and forces share of the library's split) go first to the forces
+    dispatch, the rest to the spreading dispatch."""
+    import numpy as np
+    nx, ny, nzf = dom.nx, dom.ny, dom.nz_fluid
+    walls = dom.wall_mode == 0
+    b = np.floor(q).astype(np.int64) - 1
+    k = np.arange(4)
+    xs = (b[:, 0, None] + k) % nx
+    ys = (b[:, 1, None] + k) % ny
+    zs = b[:, 2, None] + k - (1 if walls else 0)
+    if not walls:
+        zs = zs % nzf
+    X = np.broadcast_to(xs[:, None, None, :], (len(q), 4, 4, 4))
+    Y = np.broadcast_to(ys[:, None, :, None], (len(q), 4, 4, 4))
+    Z = np.broadcast_to(zs[:, :, None, None], (len(q), 4, 4, 4))
+    ok = (Z >= 0) & (Z < nzf)
+    shell = np.zeros((nzf, ny, nx), dtype=bool)
+    shell[Z[ok], Y[ok], X[ok]] = True
+    ntz, nty, ntx = (nzf + 3) // 4, (ny + 3) // 4, (nx + 3) // 4
+    tiles = np.zeros((ntz, nty, ntx), dtype=bool)
+    tiles[Z[ok] >> 2, Y[ok] >> 2, X[ok] >> 2] = True
+    act = tiles[(np.arange(nzf) >> 2)[:, None, None], (np.arange(ny) >> 2)[None, :, None],
+                (np.arange(nx) >> 2)[None, None, :]]
+    bxw = split["block_x"]
+    byw = 256 // bxw
+    nbx, nby = (nx + bxw - 1) // bxw, (ny + byw - 1) // byw
+    pad = ((0, 0), (0, nby * byw - ny), (0, nbx * bxw - nx))
+    other = (~np.pad(act, pad, constant_values=True)).reshape(nzf, nby, byw, nbx, bxw).sum(axis=(2, 4)).reshape(-1)
+    nb = other.size
+    e0 = int(split["share_forces"] * nb + 0.5)
+    n_act = int(act.sum())
+    lb = {"forces": int(other[:e0].sum()), "spread": int(other[e0:].sum()) + n_act, "moments": 0, "move": 0}
+    assert sum(lb.values()) == dom.n_fluid, (lb, dom.n_fluid)
+    return {"shell_nodes": int(shell.sum()), "active_nodes": n_act, "lb_nodes": lb, "lb_blocks": nb}
 
 
-def lb_traffic(workload_name: str, prec: int):
-    """HBM bytes per k_lb launch from the committed FETCH_SIZE/WRITE_SIZE runs
-    (copy-calibrated), or None when they were taken on another kernel source
-    or another workload."""
+def algorithmic_bytes(dom, mesh, prec: int, geo: dict) -> dict:
+    """Bytes the method must move in one step, per dispatch: every fluid node's
+    19 populations read and written once (38 s_pop), the shell nodes' force
+    density written and read (6 s_F), their populations read again and u(t+1)
+    written and read for the interpolation (19 s_pop + 8 s_F), the faces'
+    indices, reference data and corner force and volume terms (12 + 40 s_F),
+    and the vertices' FP64 positions, nodal forces and incidence (104 + 6 s_F +
+    48 B).  s_pop: bytes per stored population; s_F: bytes per value of the
+    step's arithmetic type."""
+    sp, sf = POP_BYTES[prec], (8 if prec == 0 else 4)
+    ns, nf, nv = geo["shell_nodes"], mesh.n_faces, mesh.n_vertices
+    lb = {k: v * 38 * sp for k, v in geo["lb_nodes"].items()}
+    ib = {
+        "forces": nf * (12 + 4 * sf + 36 * sf) + nv * (48 + 8) + 6 * nv * 8,
+        "spread": ns * 6 * sf + nv * 6 * sf,
+        "moments": ns * (19 * sp + 4 * sf),
+        "move": ns * 4 * sf + nv * 48,
+    }
+    per = {k: lb[k] + ib[k] for k in DISPATCHES}
+    return {"total": sum(per.values()), "lb": sum(lb.values()), "ib": sum(ib.values()), "per_dispatch": per}
+
+
+# ----------------------------------------------------------------- GPU timing
+
+def event_time(stream, fn):
+    """Milliseconds between hipEvents recorded on `stream` around fn()."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def step_traffic(workload_name: str, prec: int):
+    """HBM bytes per step (the four dispatches) from the committed
+    FETCH_SIZE/WRITE_SIZE runs (copy-calibrated), or None when they were
+    taken on another kernel source or another workload."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_lb_shear64_f32_counters.json")
-    if workload_name != "shear64_capsule_f32" or prec != 1 or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", "step_wetting128_f32_counters.json")
+    if workload_name != "wetting128_f32" or prec != 1 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
     src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
         return None
-    return int(rec["traffic_bytes_per_launch"])
+    return int(rec["traffic_bytes_per_step"])
 
 
-def lb_roofline(dom, prec: int, launches: int, traffic=None):
+def lb_roofline(dom, prec: int, launches: int):
     """k_lb over every fluid node of the domain (no mesh), graph-replayed;
     hipEvents on the library stream around `launches` consecutive launches."""
-    import torch
     from paper_2305_18919_amd import iblb
     launches = max(16, launches // 16 * 16)
     with iblb.Simulation(dom, None, precision=prec, graph=True) as sim:
         sim.step(64)
         sim.sync()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(sim.stream)
-        sim.step(launches)
-        e1.record(sim.stream)
-        e1.synchronize()
+        ms = event_time(sim.stream, lambda: sim.step(launches))
         sim.sync()
-        us = e0.elapsed_time(e1) * 1e3 / launches
+    us = ms * 1e3 / launches
     alg = dom.n_fluid * lb_bytes_per_node(prec)
     achieved = alg / (us * 1e-6) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_lb (every fluid node, no mesh)", "alg_bytes_per_launch": alg,
-            "launches": launches, "avg_us": round(us, 3)}
+    return {"kernel": "k_lb (every fluid node, no mesh)", "fluid_nodes": dom.n_fluid, "alg_bytes_per_launch": alg,
+            "launches": launches, "avg_us": round(us, 3), "achieved_GBs": round(achieved, 1),
+            "frac": round(achieved / HBM_PEAK_GBS, 4)}
+
+
+def coupled_rate(w, prec: int, steps: int, warmup: int):
+    """Graph-replayed coupled steps of workload w: (us per step, MLUPS)."""
+    from paper_2305_18919_amd import iblb
+    with iblb.Simulation(w.domain, w.mesh, precision=prec, graph=True) as sim:
+        sim.step(warmup)
+        sim.sync()
+        ms = event_time(sim.stream, lambda: sim.step(steps))
+        sim.sync()
+    us = ms * 1e3 / steps
+    return us, w.domain.n_fluid / us
+
+
+def device_copy(mib: int, reps: int = 20):
+    """A plain device-to-device copy (torch copy_): read + write bytes / time."""
+    import torch
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ms = event_time(s, lambda: [dst.copy_(src) for _ in range(reps)])
+    del src, dst
+    return {"mib": mib, "GBs_read_plus_write": round(2 * n * reps / (ms * 1e-3) / 1e9, 1)}
+
+
+def adjoint_summary(steps: int = 2000, every: int = 100):
+    """The differentiation workload (64x64x48 wetting droplet, FP32 forward,
+    `steps` steps): forward time, recorded forward with checkpoints every
+    `every` steps plus the reverse sweep of one observable, their ratio, and the
+    adjoint gradients of the height h and squared contact radius r2 against
+    central finite differences of FP64 runs, at the configured relative step
+    1e-4 and at 1e-5."""
+    import numpy as np
+    from paper_2305_18919_amd import iblb
+    from paper_2305_18919_amd import inputs as I
+    w = I.differentiation_case()
+    model = w.notes["model"]
+    base = dict(abar=w.notes["abar"], kv=w.notes["kv"], eps=w.notes["eps"], tau=w.notes["tau"])
+    with iblb.Simulation(w.domain, w.mesh, precision=1, graph=True) as s:
+        s.step(64)
+        s.sync()
+    with iblb.Simulation(w.domain, w.mesh, precision=1, graph=True) as s:
+        s.sync()
+        t_fwd = event_time(s.stream, lambda: s.step(w.steps)) * 1e-3
+    with iblb.Simulation(w.domain, w.mesh, precision=1, graph=True) as s:
+        s.sync()
+        t0 = time.perf_counter()
+        s.adjoint_record(w.steps, every)
+        s.sync()
+        t_rec = time.perf_counter() - t0
+        h, r2, dh, dr2 = iblb.sphere_fit_grad(s.vertices(), 0, w.domain.z_lo, w.mesh.r_cut_wall)
+        t0 = time.perf_counter()
+        gh, _ = s.adjoint_backward(dh)
+        t_bwd = time.perf_counter() - t0
+        gr, _ = s.adjoint_backward(dr2)
+    ad = {"h": [sum(m * gh[k] for k, m in enumerate(model)), gh[3], gh[4], gh[5]],
+          "r2": [sum(m * gr[k] for k, m in enumerate(model)), gr[3], gr[4], gr[5]]}
+
+    def observe(pp):
+        wc = I.differentiation_case(pp["abar"], pp["kv"], pp["eps"] / pp["abar"], pp["tau"])
+        with iblb.Simulation(wc.domain, wc.mesh, precision=0, graph=True) as sm:
+            sm.step(wc.steps)
+            hh, rr, _, _ = iblb.sphere_fit_grad(sm.vertices(), 0, wc.domain.z_lo, wc.mesh.r_cut_wall)
+        return hh, rr
+
+    names = ("abar", "kv", "eps", "tau")
+    errs = {}
+    for hrel in (1e-4, 1e-5):
+        rel = {"h": [], "r2": []}
+        for j, name in enumerate(names):
+            hs = base[name] * hrel
+            pp, pm = dict(base), dict(base)
+            pp[name] += hs
+            pm[name] -= hs
+            a, b = observe(pp), observe(pm)
+            for key, idx in (("h", 0), ("r2", 1)):
+                fd = (a[idx] - b[idx]) / (2 * hs)
+                rel[key].append(float(abs(ad[key][j] - fd) / max(abs(fd), 1e-300)))
+        errs[hrel] = rel
+    best = {k: [min(errs[1e-4][k][j], errs[1e-5][k][j]) for j in range(4)] for k in ("h", "r2")}
+    return {
+        "workload": w.name, "steps": w.steps, "checkpoint_every": every,
+        "forward_s": round(t_fwd, 5), "record_s": round(t_rec, 5), "backward_s": round(t_bwd, 5),
+        "adjoint_over_forward": round((t_rec + t_bwd) / t_fwd, 3),
+        "params": ["abar", "k_V", "eps", "tau"],
+        "fd_rel_error_h1e-4": errs[1e-4], "fd_rel_error_h1e-5": errs[1e-5],
+        "max_fd_rel_error_h1e-4": max(max(v) for v in errs[1e-4].values()),
+        "max_fd_rel_error_best_step": max(max(v) for v in best.values()),
+        "h": h, "r2": r2, "grad": {k: [float(x) for x in v] for k, v in ad.items()},
+    }
+
+
+# ----------------------------------------------------------------- CPU oracle
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(name: str, budget_s: float):
+    """Child process: the FP64 oracle on a bounded number of steps of workload
+    `name`, at the thread count of OMP_NUM_THREADS; prints one JSON line."""
+    from oracle import oracle as O
+    w, _ = workload(name)
+    sim = O.OracleSim(w.domain, w.mesh)
+    sim.step(1)  # warm-up
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        sim.step(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    print(json.dumps({"mlups": w.domain.n_fluid * steps / dt / 1e6, "steps": steps, "seconds": dt}), flush=True)
+
+
+def cpu_baseline(name: str, wname: str, budget_s: float):
+    """The FP64 oracle on this host's cores and on one core, each in a child
+    process that never touches the GPU."""
+    nproc = len(os.sched_getaffinity(0))
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or nproc
+    legs = {}
+    for threads in (cores, 1):
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+        out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", name, "--cpu-seconds",
+                              str(budget_s)], env=env, capture_output=True, text=True, check=True)
+        legs[threads] = json.loads(out.stdout.strip().splitlines()[-1])
+    a, one = legs[cores], legs[1]
+    return {"value": round(a["mlups"], 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{wname}: {a['steps']} FP64 oracle steps after 1 warm-up step ({a['seconds']:.1f} s) on "
+                      f"{cores} threads; {one['steps']} steps ({one['seconds']:.1f} s) on 1 thread",
+            "value_1core": round(one["mlups"], 3), "nproc": nproc, "cpu_model": cpu_model()}
 
 
 def precision_study(steps: int):
@@ -527,14 +742,17 @@ def copy_pass(mib: int, reps: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="shear64")
-    ap.add_argument("--timed-steps", type=int, default=500, help="steps of the per-kernel hipEvent pass")
-    ap.add_argument("--lb-launches", type=int, default=1600, help="launches of the LB-only roofline pass")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="wetting128")
+    ap.add_argument("--timed-steps", type=int, default=200, help="steps of the per-dispatch hipEvent pass")
+    ap.add_argument("--lb-launches", type=int, default=800, help="launches of the LB-only pass")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--pass", dest="only", choices=["lb", "copy"], default=None)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the timed step and its roofline (no secondary figures, adjoint or oracle)")
+    ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--pass", dest="only", choices=["lb", "copy", "step"], default=None)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--study", choices=["precision", "precision64", "shear", "batch", "adjoint", "wetting",
                                         "spreading"], default=None,
@@ -545,35 +763,28 @@ def main():
                          "spreading: contact radius against time (Eq. tanner_law)")
     ap.add_argument("--study-steps", type=int, default=50000)
     ap.add_argument("--precision", choices=sorted(PRECISIONS), default=None,
-                    help="population storage (default: the workload's, FP32 for shear64)")
+                    help="population storage (default: the workload's, FP32 for the benchmark workloads)")
     args = ap.parse_args()
+    if args.cpu_leg is not None:
+        cpu_leg(args.cpu_leg, args.cpu_seconds)
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the library has no multi-GPU path"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the library has no multi-GPU path "
+                                   "(the sharding design is described with the kernels)"}))
         raise SystemExit(2)
 
     import torch
     from paper_2305_18919_amd import iblb
 
-    if args.study == "precision":
-        precision_study(args.study_steps)
-        return
-    if args.study == "shear":
-        shear_study(args.study_steps)
-        return
-    if args.study == "batch":
-        batch_study(args.study_steps, args.warmup)
-        return
-    if args.study == "adjoint":
-        adjoint_study(100)
-        return
-    if args.study == "wetting":
-        wetting_study(args.study_steps)
-        return
-    if args.study == "precision64":
-        precision64_study(args.study_steps)
-        return
-    if args.study == "spreading":
-        spreading_study(args.study_steps)
+    studies = {"precision": lambda: precision_study(args.study_steps),
+               "shear": lambda: shear_study(args.study_steps),
+               "batch": lambda: batch_study(args.study_steps, args.warmup),
+               "adjoint": lambda: adjoint_study(100),
+               "wetting": lambda: wetting_study(args.study_steps),
+               "precision64": lambda: precision64_study(args.study_steps),
+               "spreading": lambda: spreading_study(args.study_steps)}
+    if args.study is not None:
+        studies[args.study]()
         return
     w, prec = workload(args.workload)
     if args.precision is not None:
@@ -585,48 +796,83 @@ def main():
         copy_pass(args.copy_mib, 10)
         return
     if args.only == "lb":
-        print(json.dumps({"pass": "lb", "workload": w.name, "roofline": lb_roofline(dom, prec, args.lb_launches)}),
+        print(json.dumps({"pass": "lb", "workload": w.name, "lb_only": lb_roofline(dom, prec, args.lb_launches)}),
               flush=True)
         return
 
+    # the timed step: graphs captured at construction, W warm-up steps, then
+    # exactly K steps between hipEvents on the library stream
     sim = iblb.Simulation(dom, mesh, precision=prec, graph=True)
+    split = sim.lb_split()
     sim.step(args.warmup)
     sim.sync()
+    q0 = sim.vertices()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(args.steps)
+    ms = event_time(sim.stream, lambda: sim.step(args.steps))
     sim.sync()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt * 1e3 / args.steps
-    mlups = dom.n_fluid * args.steps / dt / 1e6
+    wall = time.perf_counter() - t0
+    ms_per_step = ms / args.steps
+    mlups = dom.n_fluid * args.steps / (ms * 1e-3) / 1e6
+    print(f"[bench] {w.name}: {ms_per_step * 1e3:.2f} us/step, {mlups:.1f} MLUPS", file=sys.stderr, flush=True)
 
-    # per-kernel hipEvent pass on the library stream
-    sim.set_timing(True)
-    sim.reset_timing()
-    sim.step(args.timed_steps)
-    sim.sync()
-    kernels = {}
-    for name in ("forces", "spread", "lb", "move"):
-        ms, n = sim.kernel_time(name)
-        if n:
-            kernels[name] = {"avg_us": round(ms * 1e3 / n, 3), "launches": n}
-    sim.set_timing(False)
-    kernels["active_tile_nodes"] = sim.active_nodes()
+    geo = step_geometry(dom, q0, split)
+    alg = algorithmic_bytes(dom, mesh, prec, geo)
+    achieved = alg["total"] / (ms_per_step * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": step_traffic(w.name, prec),
+                "kernel": "whole step (forces, spread, moments, move dispatches)",
+                "alg_bytes_per_step": alg["total"], "alg_bytes_lb": alg["lb"], "alg_bytes_ib": alg["ib"],
+                "avg_us": round(ms_per_step * 1e3, 3)}
+
+    # per-dispatch pass: the same four dispatches launched one by one, each
+    # bracketed by hipEvents
+    dispatches = {}
+    if args.only != "step":
+        sim.set_timing(True)
+        sim.reset_timing()
+        sim.step(args.timed_steps)
+        sim.sync()
+        for name in DISPATCHES:
+            tms, n = sim.kernel_time(name)
+            if n:
+                us = tms * 1e3 / n
+                b = alg["per_dispatch"][name]
+                dispatches[name] = {"avg_us": round(us, 3), "launches": n, "alg_bytes": b,
+                                    "lb_nodes": geo["lb_nodes"][name],
+                                    "achieved_GBs": round(b / (us * 1e-6) / 1e9, 1)}
+        sim.set_timing(False)
+        if dispatches:
+            dom_name = max(dispatches, key=lambda k: dispatches[k]["avg_us"])
+            roofline["dominant_dispatch"] = dom_name
+    active_nodes = sim.active_nodes()
     sim.close()
 
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 6), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
         "config": {"workload": w.name, "grid": [dom.nx, dom.ny, dom.nz], "fluid_nodes": dom.n_fluid,
                    "vertices": mesh.n_vertices, "faces": mesh.n_faces, "tau": dom.tau,
-                   "alpha": list(mesh.alpha), "positions": "f64", "launch": "hipGraph, 16 steps per replay"},
-        "roofline": lb_roofline(dom, prec, args.lb_launches, lb_traffic(w.name, prec)),
-        "kernels": kernels,
+                   "alpha": list(mesh.alpha), "positions": "f64",
+                   "launch": "hipGraphs of 16 and 1 steps captured before the warm-up", "lb_split": split},
+        "roofline": roofline,
+        "wall_ms_per_step": round(wall * 1e3 / args.steps, 6),
+        "dispatches": dispatches,
+        "geometry": dict({k: v for k, v in geo.items() if k != "lb_nodes"}, active_tile_nodes_device=active_nodes,
+                         lb_nodes=geo["lb_nodes"]),
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    if not args.no_extra and args.only != "step":
+        out["lb_only"] = lb_roofline(dom, prec, args.lb_launches)
+        pw = probe256()
+        out["probe256"] = {"lb_only": lb_roofline(pw.domain, 1, 64)}
+        us, ml = coupled_rate(pw, 1, 64, 16)
+        out["probe256"]["coupled_step"] = {"avg_us": round(us, 3), "mlups": round(ml, 1)}
+        out["device_copy"] = [device_copy(128), device_copy(1024)]
+        out["adjoint"] = adjoint_summary()
+    if not args.no_cpu and args.only != "step":
+        out["cpu_baseline"] = cpu_baseline(args.workload, w.name, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -188,16 +188,27 @@ int iblb_debug_get_nodal_forces(iblb_ctx *ctx, int32_t mesh_id, double *phi);
 int iblb_save_state(iblb_ctx *ctx, void *host_buf, size_t *bytes);
 int iblb_load_state(iblb_ctx *ctx, const void *host_buf, size_t bytes);
 
-/* Execution controls.  graph != 0: iblb_step replays a captured hipGraph
- * (default); 0: plain launches.  timing != 0: plain launches bracketed by
- * hipEvents per kernel on the context stream, accumulated until read. */
+/* Execution controls.  graph != 0: iblb_step replays captured hipGraphs
+ * (default) of 16 steps and of one step, for either parity of the start
+ * time; iblb_set_graph(ctx, 1) captures them at once (they are captured on
+ * first use otherwise), so that no later call of iblb_step captures.  0:
+ * plain launches.  timing != 0: plain launches of the same dispatches, each
+ * bracketed by hipEvents on the context stream, accumulated until read.
+ * Capture errors return IBLB_E_DEVICE. */
 int iblb_set_graph(iblb_ctx *ctx, int32_t graph);
 int iblb_set_timing(iblb_ctx *ctx, int32_t timing);
-/* Per-kernel accumulated event time.  names: "forces" (interface forces and
- * the list of active tiles), "spread" (spreading and the LB of the active
- * tiles), "lb" (LB of the other nodes), "move" (u(t+1) on the active tiles,
- * interpolation and move).  Returns total milliseconds and launch count;
- * resets nothing. */
+/* Launch shape of the LB of the nodes outside the active tiles (for
+ * accounting): blocks of block_x x (256 / block_x) nodes of one z layer,
+ * numbered x fastest, the first share_forces of them run by the forces
+ * dispatch and the rest by the spreading dispatch.  Either output may be
+ * NULL. */
+int iblb_get_lb_split(const iblb_ctx *ctx, int32_t *block_x, double *share_forces);
+/* Per-dispatch accumulated event time.  names: "forces" (interface forces,
+ * the list of active tiles, and their share of the LB outside the active
+ * tiles), "spread" (spreading, the LB of the active tiles, and the rest of
+ * that LB), "moments" (u(t+1) on the active tiles), "move" (interpolation
+ * and move), "lb" (the step without a mesh).  Returns total milliseconds and
+ * launch count; resets nothing. */
 int iblb_kernel_time(iblb_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 int iblb_reset_timing(iblb_ctx *ctx);
 

@@ -22,10 +22,10 @@ using namespace iblb;
 namespace {
 
 constexpr char kMagic[8] = {'I', 'B', 'L', 'B', 'S', 'T', '0', '1'};
-constexpr int kNumKernels = 4;
+constexpr int kNumKernels = 5;
 constexpr int kGraphSteps = 16;  // steps per captured graph (even)
-const char *const kKernelNames[kNumKernels] = {"forces", "spread", "lb", "move"};
-enum { K_FORCES = 0, K_SPREAD = 1, K_LB = 2, K_MOVE = 3 };
+const char *const kKernelNames[kNumKernels] = {"forces", "spread", "moments", "move", "lb"};
+enum { K_FORCES = 0, K_SPREAD = 1, K_MOMENTS = 2, K_MOVE = 3, K_LB = 4 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -98,7 +98,7 @@ Layout make_layout(const Grid &g, size_t ps, size_t ts, int nv, int nf, int slot
     L.partials = take((size_t)nparts * 8);
     L.mask = take((size_t)g.nt * ((nv + 63) / 64) * 8);
     L.act = take((size_t)(g.nt + 4095) / 4096 * 4096);
-    L.acnt = take(4);
+    L.acnt = take(2 * 4);
     L.alist = take((size_t)g.nt * 4);
     L.mesh_end = o;
     return L;
@@ -130,13 +130,14 @@ struct iblb_ctx {
     double V0 = 0.0;
     long long t = 0;
     bool use_graph = true;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    // captured steps: [start parity][0: kGraphSteps steps, 1: one step]
+    hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     bool timing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<hipEvent_t> pool;
-    double ktime[kNumKernels] = {0, 0, 0, 0};
-    long long kcount[kNumKernels] = {0, 0, 0, 0};
+    double ktime[kNumKernels] = {0, 0, 0, 0, 0};
+    long long kcount[kNumKernels] = {0, 0, 0, 0, 0};
     void *fext_alloc = nullptr;
     void *mesh_alloc = nullptr;
     struct AdjState *adj = nullptr;  // recorded window of the adjoint, if any
@@ -242,10 +243,13 @@ void lb_args(iblb_ctx *c)
 
 void drop_graph(iblb_ctx *c)
 {
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->gexec = nullptr;
-    c->graph = nullptr;
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k < 2; ++k) {
+            if (c->gexec[p][k]) (void)hipGraphExecDestroy(c->gexec[p][k]);
+            if (c->graph[p][k]) (void)hipGraphDestroy(c->graph[p][k]);
+            c->gexec[p][k] = nullptr;
+            c->graph[p][k] = nullptr;
+        }
 }
 
 hipEvent_t get_event(iblb_ctx *c)
@@ -264,35 +268,26 @@ hipError_t launch_kernel(iblb_ctx *c, int which, int p, hipStream_t st)
 {
     const Dev &d = c->d;
     switch (which) {
-    case K_FORCES: return launch_forces(c->prec, d, c->lb, c->m, p, 0, st);
-    case K_SPREAD: return launch_spread(c->prec, d, c->lb, c->m, p, 0, st);
-    case K_LB: return launch_lb(c->prec, d, c->lb, p, c->has_mesh ? 1 : 0, st);
-    default: return launch_move(c->prec, d, c->lb, c->m, p, st);
+    case K_FORCES: return launch_forces(c->prec, d, c->lb, c->m, p, 1, st);
+    case K_SPREAD: return launch_spread(c->prec, d, c->lb, c->m, p, 1, st);
+    case K_MOMENTS: return launch_moments(c->prec, d, c->lb, c->m, p, st);
+    case K_MOVE: return launch_move(c->prec, d, c->lb, c->m, p, st);
+    default: return launch_lb(c->prec, d, c->lb, p, 0, st);
     }
 }
 
-// One step of parity p.  With a mesh: the interface forces and the list of
-// active tiles, then one dispatch that spreads onto the active tiles (force +
-// their LB), then the moments of the active tiles and the move.  The LB of
-// all other nodes runs in the first two dispatches, split between them.  Timed steps launch the bulk LB as a kernel of
-// its own so that each duration can be read.
+// One step of parity p.  With a mesh, four dispatches: the interface forces
+// and the list of active tiles; the spreading onto the active tiles (force +
+// their LB); the moments of the active tiles; the interpolation and move.
+// The LB of all other nodes runs in the first two, split between them.
+// Without a mesh, the LB alone.  Timed steps bracket each dispatch with
+// hipEvents (the same launches otherwise).
 hipError_t enqueue_step(iblb_ctx *c, int p, bool timed)
 {
-    if (c->has_mesh && !timed) {
-        hipError_t e = launch_forces(c->prec, c->d, c->lb, c->m, p, 1, c->stream);
-        if (e == hipSuccess) e = launch_spread(c->prec, c->d, c->lb, c->m, p, 1, c->stream);
-        if (e == hipSuccess) e = launch_kernel(c, K_MOVE, p, c->stream);
-        return e;
-    }
-    int seq[4], ns = 0;
-    if (c->has_mesh) {
-        seq[ns++] = K_FORCES;
-        seq[ns++] = K_SPREAD;
-        seq[ns++] = K_LB;
-        seq[ns++] = K_MOVE;
-    } else {
-        seq[ns++] = K_LB;
-    }
+    static const int with_mesh[4] = {K_FORCES, K_SPREAD, K_MOMENTS, K_MOVE};
+    static const int no_mesh[1] = {K_LB};
+    const int *seq = c->has_mesh ? with_mesh : no_mesh;
+    const int ns = c->has_mesh ? 4 : 1;
     for (int k = 0; k < ns; ++k) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (timed) {
@@ -308,6 +303,39 @@ hipError_t enqueue_step(iblb_ctx *c, int p, bool timed)
         }
     }
     return hipSuccess;
+}
+
+// Captures the graph of kGraphSteps steps (which = 0) or of one step
+// (which = 1) from a time of parity p, if not yet captured: every kernel
+// reads the step from the device counter, so a graph replays at any later
+// time of the same parity.
+int capture_steps(iblb_ctx *c, int p, int which)
+{
+    if (c->gexec[p][which]) return IBLB_OK;
+    const int steps = which == 0 ? kGraphSteps : 1;
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < steps && e == hipSuccess; ++k) e = enqueue_step(c, (p + k) & 1, false);
+    hipGraph_t gr = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
+    if (e != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return hip_fail(c, e, "step capture");
+    }
+    if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+    c->graph[p][which] = gr;
+    HIP_TRY(c, hipGraphInstantiate(&c->gexec[p][which], gr, nullptr, nullptr, 0));
+    return IBLB_OK;
+}
+
+int capture_all(iblb_ctx *c)
+{
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k < 2; ++k) {
+            int rc = capture_steps(c, p, k);
+            if (rc) return rc;
+        }
+    return IBLB_OK;
 }
 
 int collect_timing(iblb_ctx *c)
@@ -398,7 +426,7 @@ int rebuild_lists(iblb_ctx *c)
     if (rc) return rc;
     HIP_TRY(c, hipMemsetAsync(c->d.mask, 0, (size_t)c->g.nt * c->m.nwords * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d.act, 0, (size_t)(c->g.nt + 4095) / 4096 * 4096, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->d.acnt, 0, 4, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d.acnt, 0, 2 * 4, c->stream));
     HIP_TRY(c, launch_stamp(c->d, c->g, c->m, (int)(c->t & 1), c->stream));
     return IBLB_OK;
 }
@@ -629,30 +657,19 @@ int iblb_add_mesh(iblb_ctx *c, const iblb_mesh_desc *mesh, int32_t *mesh_id)
 int iblb_step(iblb_ctx *c, int32_t n_steps)
 {
     if (!c || n_steps < 0) return IBLB_E_INVAL;
-    // A captured graph holds kGraphSteps steps starting at an even time;
-    // the rest (short counts, odd start, timing) is launched directly.
+    // Captured graphs of kGraphSteps steps, then of one step, from the
+    // current parity; launched directly when graphs are off or when timing.
     int left = n_steps;
     while (left > 0) {
         const int p = (int)(c->t & 1);
-        if (!c->timing && c->use_graph && p == 0 && left >= kGraphSteps) {
-            if (!c->gexec) {
-                HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                hipError_t e = hipSuccess;
-                for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
-                    e = enqueue_step(c, k & 1, false);
-                hipGraph_t gr = nullptr;
-                hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
-                if (e != hipSuccess) {
-                    if (gr) (void)hipGraphDestroy(gr);
-                    return hip_fail(c, e, "step capture");
-                }
-                if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
-                c->graph = gr;
-                HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
-            }
-            HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
-            c->t += kGraphSteps;
-            left -= kGraphSteps;
+        if (!c->timing && c->use_graph) {
+            const int which = left >= kGraphSteps ? 0 : 1;
+            int rc = capture_steps(c, p, which);
+            if (rc) return rc;
+            HIP_TRY(c, hipGraphLaunch(c->gexec[p][which], c->stream));
+            const int k = which == 0 ? kGraphSteps : 1;
+            c->t += k;
+            left -= k;
         } else {
             hipError_t e = enqueue_step(c, p, c->timing);
             if (e != hipSuccess) return hip_fail(c, e, "step launch");
@@ -976,7 +993,18 @@ int iblb_set_graph(iblb_ctx *c, int32_t graph)
 {
     if (!c) return IBLB_E_INVAL;
     c->use_graph = graph != 0;
-    if (!c->use_graph) drop_graph(c);
+    if (!c->use_graph) {
+        drop_graph(c);
+        return IBLB_OK;
+    }
+    return capture_all(c);
+}
+
+int iblb_get_lb_split(const iblb_ctx *c, int32_t *block_x, double *share_forces)
+{
+    if (!c) return IBLB_E_INVAL;
+    if (block_x) *block_x = lb_block_width(c->g);
+    if (share_forces) *share_forces = lb_share_with_forces();
     return IBLB_OK;
 }
 
@@ -1007,8 +1035,11 @@ int iblb_active_nodes(iblb_ctx *c, int64_t *n)
     *n = 0;
     if (!c->has_mesh) return IBLB_OK;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->t == 0) return IBLB_OK;
+    // the count of the last completed step t - 1 (its move cleared the other
+    // parity's counter for the next step)
     uint32_t na = 0;
-    HIP_TRY(c, hipMemcpy(&na, c->d.acnt, 4, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(&na, c->d.acnt + ((c->t - 1) & 1), 4, hipMemcpyDeviceToHost));
     if (na > (uint32_t)c->g.nt) return fail(c, IBLB_E_STATE, "active tile count out of range");
     std::vector<int> tiles(na);
     if (na) HIP_TRY(c, hipMemcpy(tiles.data(), c->d.alist, (size_t)na * 4, hipMemcpyDeviceToHost));
@@ -1176,21 +1207,23 @@ int build_tables(iblb_batch *b)
         const int hint = std::max(1, c->m.tiles_hint);
         const long long want = hint_sum > 0 ? std::llround(budget * hint / (double)hint_sum) : 1;
         r.nsp = (int)std::max(1ll, std::min(want, (long long)c->g.nt));
-        const int mw = (hint + hint / 4 + 3) / 4 + 1, mcap = (c->g.nt + 3) / 4;
-        r.mblocks = std::max(1, std::min(mw, mcap));
-        if ((long long)c->m.nparts + 1 + nlb[(size_t)k] >= (1ll << 24) ||
+        r.mblocks = std::max(1, moments_blocks(c->g, c->m));
+        if ((long long)c->m.nparts + scan_block_count(c->g) + nlb[(size_t)k] >= (1ll << 24) ||
             (long long)r.nsp + nlb[(size_t)k] >= (1ll << 24))
             return bfail(b, IBLB_E_INVAL, "member " + std::to_string(k) + " has too many blocks for a batch");
     }
     auto entry = [](int k, int blk) { return (uint32_t)k | ((uint32_t)blk << 8); };
     auto on = [&](int k) { return b->status[(size_t)k] == IBLB_OK; };
     for (int k = 0; k < n; ++k)
-        if (on(k))
-            for (int j = 0; j <= recs[(size_t)k].m.nparts; ++j) tab[B_FORCES].push_back(entry(k, j));
+        if (on(k)) {
+            const int nf = recs[(size_t)k].m.nparts + scan_block_count(recs[(size_t)k].a.g);
+            for (int j = 0; j < nf; ++j) tab[B_FORCES].push_back(entry(k, j));
+        }
     for (int k = 0; k < n; ++k)
-        if (on(k))
-            for (int j = 0; j < recs[(size_t)k].lb0; ++j)
-                tab[B_FORCES].push_back(entry(k, recs[(size_t)k].m.nparts + 1 + j));
+        if (on(k)) {
+            const int nf = recs[(size_t)k].m.nparts + scan_block_count(recs[(size_t)k].a.g);
+            for (int j = 0; j < recs[(size_t)k].lb0; ++j) tab[B_FORCES].push_back(entry(k, nf + j));
+        }
     for (int k = 0; k < n; ++k)
         if (on(k))
             for (int j = 0; j < recs[(size_t)k].nsp; ++j) tab[B_SPREAD].push_back(entry(k, j));

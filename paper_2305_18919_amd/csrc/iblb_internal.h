@@ -81,8 +81,9 @@ struct Dev {
                           // move, read and cleared by the next step's spreading)
     uint8_t *act;         // [nt, padded to 4096] act_stamp(t) of the step t at which the tile is
                           // active (written by the previous move; 0 = never)
-    uint32_t *acnt;       // [1] active tiles of the step
-    int *alist;           // [nt] active tile indices of the step (scan order)
+    uint32_t *acnt;       // [2] acnt[t & 1]: active tiles of step t (cleared by the move of step
+                          // t - 1, counted up by the scan blocks of step t)
+    int *alist;           // [nt] active tile indices of the step (in the order the scan found them)
     double *scratch;      // small FP64 scratch for queries (64 doubles)
     int num_cus;          // compute units of the device (launch sizing)
 };
@@ -119,9 +120,19 @@ hipError_t launch_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs
 // active tiles
 hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, int with_lb,
                          hipStream_t s);
-// moments of the active tiles, then interpolation, move, and the next step's
-// act stamps and vertex masks
+// u(t+1) on the nodes of the active tiles
+hipError_t launch_moments(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);
+// interpolation, move, and the next step's act stamps and vertex masks
 hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s);
+// the LB blocks of the nodes outside the active tiles: width (nodes along x;
+// 256 / width rows of one z layer) and the share run by the forces dispatch
+// (the spreading dispatch runs the rest)
+int lb_block_width(const Grid &g);
+double lb_share_with_forces();
+// blocks of the moments dispatch (launch sizing)
+int moments_blocks(const Grid &g, const MeshArgs &m);
+// blocks that list the active tiles in the forces dispatch
+inline int scan_block_count(const Grid &g) { return (g.nt + 4095) / 4096; }
 // act stamps and vertex masks of the current step from the stored positions
 // (masks and stamps cleared beforehand)
 hipError_t launch_stamp(const Dev &d, const Grid &g, const MeshArgs &m, int p, hipStream_t s);

@@ -465,70 +465,68 @@ __device__ __forceinline__ int stencil_tile(const Grid &g, const StencilRuns &r,
     return tile_of(g, x, y, zf);
 }
 
-// Inclusive sum over the 64 lanes of a wavefront, in lane order.
-__device__ __forceinline__ int wave_incl_scan(int c, int lane)
+// Inclusive sum over the 64 lanes of a wavefront, in lane order, with DPP
+// lane moves: shifts by 1, 2, 4 and 8 lanes within each row of 16, then the
+// last lane of row 0 added to row 1 and of row 2 to row 3 (row_bcast:15), and
+// the last lane of row 1 to rows 2 and 3 (row_bcast:31).  A lane whose source
+// lies outside its row, or whose row the mask leaves out, adds 0.
+__device__ __forceinline__ int wave_incl_scan(int c)
 {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(c, off, 64);
-        c += lane >= off ? y : 0;
-    }
+    c += __builtin_amdgcn_update_dpp(0, c, 0x111, 0xf, 0xf, false);  // row_shr:1
+    c += __builtin_amdgcn_update_dpp(0, c, 0x112, 0xf, 0xf, false);  // row_shr:2
+    c += __builtin_amdgcn_update_dpp(0, c, 0x114, 0xf, 0xf, false);  // row_shr:4
+    c += __builtin_amdgcn_update_dpp(0, c, 0x118, 0xf, 0xf, false);  // row_shr:8
+    c += __builtin_amdgcn_update_dpp(0, c, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    c += __builtin_amdgcn_update_dpp(0, c, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
     return c;
 }
 
 // The step's active tiles, those stamped act[tile] == act_stamp(t) by the
-// previous move, compacted into alist in ascending tile order by one
-// 256-thread block.  The byte stamps are read in chunks of 4096 tiles, 16
-// per thread (one 16-byte load each; the array is padded to whole chunks),
-// the loads of up to eight chunks issued before any is used; each chunk is
-// then a block-wide prefix sum of the per-thread counts.
+// previous move, compacted into alist: one 256-thread block per chunk of 4096
+// tiles, 16 per thread (one 16-byte load each; the array is padded to whole
+// chunks).  A block-wide prefix sum of the per-thread counts orders the
+// chunk's tiles, and one atomic add on the step's counter (cleared by the
+// previous move) reserves their place in the list.  Chunks therefore land in
+// the order their blocks finish; every consumer of the list treats its tiles
+// independently, so nothing computed depends on that order.
 constexpr int kScanChunk = 4096;
 
-__device__ __forceinline__ void scan_block(const uint8_t *__restrict__ act, uint32_t *acnt, int *alist, uint32_t t,
-                                           const Grid &g)
+__device__ __forceinline__ int scan_blocks(const Grid &g) { return (g.nt + kScanChunk - 1) / kScanChunk; }
+
+__device__ __forceinline__ void scan_block(int chunk, const uint8_t *__restrict__ act, uint32_t *acnt, int *alist,
+                                           uint32_t t)
 {
     __shared__ int swt[4];
+    __shared__ uint32_t sbase;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nch = (g.nt + kScanChunk - 1) / kScanChunk;
     const uint32_t st = act_stamp(t);
-    const uint4 *a4 = reinterpret_cast<const uint4 *>(act);
-    int base = 0;
-    for (int c0 = 0; c0 < nch; c0 += 8) {
-        uint4 v[8];
+    const uint4 v = reinterpret_cast<const uint4 *>(act)[chunk * (kScanChunk / 16) + tid];
+    // bit b: the b-th of this thread's 16 tiles carries the stamp
+    uint32_t msk = 0u;
+    const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            v[j] = c0 + j < nch ? a4[(c0 + j) * (kScanChunk / 16) + tid] : make_uint4(0u, 0u, 0u, 0u);
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (c0 + j >= nch)
-                break;
-            // bit b: the b-th of this thread's 16 tiles carries the stamp
-            uint32_t m = 0u;
-            const uint32_t w4[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    m |= ((w4[q] >> (8 * b)) & 0xffu) == st ? 1u << (4 * q + b) : 0u;
-            const int c = __popc(m);
-            const int incl = wave_incl_scan(c, lane);
-            if (lane == 63)
-                swt[wave] = incl;
-            __syncthreads();
-            int o = base + incl - c;
-            for (int w = 0; w < wave; ++w)
-                o += swt[w];
-            base += swt[0] + swt[1] + swt[2] + swt[3];
-            const int k0 = (c0 + j) * kScanChunk + tid * 16;
-            while (m != 0u) {
-                alist[o++] = k0 + __builtin_ctz(m);
-                m &= m - 1u;
-            }
-            __syncthreads();
-        }
+        for (int b = 0; b < 4; ++b)
+            msk |= ((w4[q] >> (8 * b)) & 0xffu) == st ? 1u << (4 * q + b) : 0u;
+    const int c = __popc(msk);
+    const int incl = wave_incl_scan(c);
+    if (lane == 63)
+        swt[wave] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        const int tot = swt[0] + swt[1] + swt[2] + swt[3];
+        sbase = tot ? atomicAdd(acnt, (uint32_t)tot) : 0u;
     }
-    if (tid == 0)
-        *acnt = (uint32_t)base;
+    __syncthreads();
+    int o = (int)sbase + incl - c;
+    for (int w = 0; w < wave; ++w)
+        o += swt[w];
+    const int k0 = chunk * kScanChunk + tid * 16;
+    while (msk != 0u) {
+        alist[o++] = k0 + __builtin_ctz(msk);
+        msk &= msk - 1u;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -704,10 +702,10 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
         partials[blk] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-// Blocks [0, nparts) compute the interface forces, block nparts lists the
-// step's active tiles, and the blocks after it (if any) run the first LB
-// blocks of the nodes outside the active tiles (the spreading dispatch runs
-// the rest).
+// Blocks [0, nparts) compute the interface forces, the next scan_blocks
+// blocks list the step's active tiles, and the blocks after them (if any) run
+// the first LB blocks of the nodes outside the active tiles (the spreading
+// dispatch runs the rest).
 template <typename S, int P, typename T = typename Pop<S>::C>
 __device__ __forceinline__ void forces_dispatch(int blk, const double *__restrict__ q,
                                                 const double *__restrict__ Xref, const int4 *__restrict__ inc4,
@@ -719,12 +717,13 @@ __device__ __forceinline__ void forces_dispatch(int blk, const double *__restric
                                                 const T *__restrict__ Fext, int *err, const LBArgs &a,
                                                 const MeshArgs &m, int bxw, int nbx, int nby)
 {
+    const int nscan = scan_blocks(a.g);
     if (blk < m.nparts)
         forces_block<T>(blk, q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, err, a.g, m);
-    else if (blk == m.nparts)
-        scan_block(act, acnt, alist, ctr[P], a.g);
+    else if (blk < m.nparts + nscan)
+        scan_block(blk - m.nparts, act, acnt + P, alist, ctr[P]);
     else
-        bulk_lb_block<S, P == 1>(blk - m.nparts - 1, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
+        bulk_lb_block<S, P == 1>(blk - m.nparts - nscan, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
 }
 
 template <typename S, int P, typename T = typename Pop<S>::C>
@@ -897,7 +896,7 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
     // the count of active tiles and the block's first tile are read together
     // (block index < nsp <= tile count, so the slot exists); the volatile
     // read keeps the compiler from deferring it past the test on the count
-    const uint32_t na = acnt[0];
+    const uint32_t na = acnt[P];
     int tile = ((const volatile int *)alist)[(uint32_t)blk];
     const uint32_t t = ctr[P];
     const int w0 = tid * J;
@@ -930,7 +929,7 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
             if (lane == 0)
                 skfac = kfac;
         }
-        const int incl = wave_incl_scan(c, lane);
+        const int incl = wave_incl_scan(c);
         if (lane == 63)
             swt[wave] = incl;
         __syncthreads();
@@ -1079,7 +1078,7 @@ __device__ __forceinline__ void moments_dispatch(int blk, int nblk, const S *__r
 {
     const Grid &g = a.g;
     const int lane = threadIdx.x & 63;
-    const uint32_t na = acnt[0];
+    const uint32_t na = acnt[P];
     const uint32_t first = (uint32_t)blk * 4 + (threadIdx.x >> 6);
     // the first tile is read together with the count (clamped into the list;
     // volatile, so that it is not deferred past the test on the count)
@@ -1191,18 +1190,23 @@ __device__ __forceinline__ T group_sum(T v)
     return v;
 }
 
+// The first thread also advances the step counter and clears the next step's
+// active-tile counter acnt[1 - P] (no kernel of this step reads it).
 template <typename T, int P, int VPW>
 __device__ __forceinline__ void move_dispatch(int blk, double *__restrict__ q, const T *__restrict__ U,
-                                              const uint32_t *__restrict__ stamp, uint32_t *ctr, uint8_t *act,
-                                              uint64_t *mask, int *err, const LBArgs &a, const MeshArgs &m)
+                                              const uint32_t *__restrict__ stamp, uint32_t *ctr, uint32_t *acnt,
+                                              uint8_t *act, uint64_t *mask, int *err, const LBArgs &a,
+                                              const MeshArgs &m)
 {
     const Grid &g = a.g;
     constexpr int L = 64 / VPW;  // lanes per vertex
     const int sl = threadIdx.x & (L - 1);
     const int v = (blk * 256 + (int)threadIdx.x) / L;
     const uint32_t t = ctr[P];
-    if (blk == 0 && threadIdx.x == 0)
+    if (blk == 0 && threadIdx.x == 0) {
         ctr[1 - P] = t + 1u;
+        acnt[1 - P] = 0u;
+    }
     if (v >= m.nv)
         return;
     const int nv = m.nv;
@@ -1238,10 +1242,10 @@ __device__ __forceinline__ void move_dispatch(int blk, double *__restrict__ q, c
 
 template <typename T, int P, int VPW>
 __global__ __launch_bounds__(256) void k_move(double *__restrict__ q, const T *__restrict__ U,
-                                              const uint32_t *__restrict__ stamp, uint32_t *ctr, uint8_t *act,
-                                              uint64_t *mask, int *err, LBArgs a, MeshArgs m)
+                                              const uint32_t *__restrict__ stamp, uint32_t *ctr, uint32_t *acnt,
+                                              uint8_t *act, uint64_t *mask, int *err, LBArgs a, MeshArgs m)
 {
-    move_dispatch<T, P, VPW>((int)blockIdx.x, q, U, stamp, ctr, act, mask, err, a, m);
+    move_dispatch<T, P, VPW>((int)blockIdx.x, q, U, stamp, ctr, acnt, act, mask, err, a, m);
 }
 
 // marks of the current step t = ctr[p] from the stored positions (after a
@@ -1305,7 +1309,8 @@ __global__ __launch_bounds__(256) void kb_move(const DomRec *__restrict__ R, con
     const uint32_t e = tab[blockIdx.x];
     const DomRec &r = R[e & 0xffu];
     const Dev &d = r.d;
-    move_dispatch<T, P, VPW>((int)(e >> 8), d.q, (const T *)d.U, d.stamp, d.ctr, d.act, d.mask, d.err, r.a, r.m);
+    move_dispatch<T, P, VPW>((int)(e >> 8), d.q, (const T *)d.U, d.stamp, d.ctr, d.acnt, d.act, d.mask, d.err, r.a,
+                             r.m);
 }
 
 __global__ __launch_bounds__(256) void kb_errors(const DomRec *__restrict__ R, int n, int *__restrict__ err)
@@ -1433,7 +1438,7 @@ __global__ __launch_bounds__(256) void k_record(const S *__restrict__ f, const O
         sum = wave_sum<double>(sum);
         if (threadIdx.x == 0) {
             dVs[levf] = sum;
-            acnt_s[levf] = acnt[0];
+            acnt_s[levf] = acnt[1 - p];
         }
     }
 }
@@ -1707,6 +1712,9 @@ hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, h
 // 77.3 / 77.4 / 77.3 / 79.0 on the wetting droplet.
 constexpr double kLbShareWithForces = 0.5;
 
+int lb_block_width(const Grid &g) { return (int)lb_block(g).x; }
+double lb_share_with_forces() { return kLbShareWithForces; }
+
 int lb_blocks_with_forces(const Grid &g)
 {
     const dim3 gr = lb_grid(g);
@@ -1719,7 +1727,7 @@ static void forces_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int 
 {
     using T = typename Pop<S>::C;
     const dim3 bl = lb_block(a.g), gr = lb_grid(a.g);
-    k_forces<S, P><<<m.nparts + 1 + nlb, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.fref, (T *)d.phiSW, (T *)d.gV, d.base,
+    k_forces<S, P><<<m.nparts + (a.g.nt + kScanChunk - 1) / kScanChunk + nlb, 256, 0, s>>>(d.q, d.Xref, d.inc4, d.fref, (T *)d.phiSW, (T *)d.gV, d.base,
                                                        (T *)d.wts, d.partials, d.act, d.acnt, d.alist, d.ctr,
                                                        (S *)d.f, (const T *)d.Fext, d.err, a, m, (int)bl.x,
                                                        (int)gr.x, (int)gr.y);
@@ -1761,26 +1769,44 @@ hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs
     });
 }
 
+// four active tiles per block (one per wavefront), for the active-tile count
+// expected at set-up with a quarter in reserve; the blocks stride over the
+// list if it grows beyond that
+int moments_blocks(const Grid &g, const MeshArgs &m)
+{
+    const int want = (m.tiles_hint + m.tiles_hint / 4 + 3) / 4 + 1;
+    const int cap = (g.nt + 3) / 4;
+    return want < cap ? want : cap;
+}
+
+template <typename S, int P>
+static void moments_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s)
+{
+    using T = typename Pop<S>::C;
+    k_moments<S, P><<<moments_blocks(a.g, m), 256, 0, s>>>((const S *)d.f, (const T *)d.F, (const T *)d.Fext,
+                                                           d.acnt, d.alist, (T *)d.U, a);
+}
+
+hipError_t launch_moments(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)
+{
+    return with_pop_type(prec, [&](auto tag) {
+        using S = decltype(tag);
+        p ? moments_launch<S, 1>(d, a, m, s) : moments_launch<S, 0>(d, a, m, s);
+    });
+}
+
 template <typename S, int P>
 static void move_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, hipStream_t s)
 {
     using T = typename Pop<S>::C;
-    // four active tiles per block (one per wavefront), for the active-tile
-    // count expected at set-up with a quarter in reserve; the blocks stride
-    // over the list if it grows beyond that
-    const int want = (m.tiles_hint + m.tiles_hint / 4 + 3) / 4 + 1;
-    const int cap = (a.g.nt + 3) / 4;
-    const int mblocks = want < cap ? want : cap;
-    k_moments<S, P><<<mblocks, 256, 0, s>>>((const S *)d.f, (const T *)d.F, (const T *)d.Fext, d.acnt, d.alist,
-                                            (T *)d.U, a);
     // one vertex per wavefront while the GPU holds all of them at once (about
     // 32 wavefronts per CU at this kernel's register count), else two
     if (m.nv <= 32 * d.num_cus)
-        k_move<T, P, 1><<<(m.nv + 3) / 4, 256, 0, s>>>(d.q, (const T *)d.U, d.stamp, d.ctr, d.act, d.mask, d.err,
-                                                        a, m);
+        k_move<T, P, 1><<<(m.nv + 3) / 4, 256, 0, s>>>(d.q, (const T *)d.U, d.stamp, d.ctr, d.acnt, d.act, d.mask,
+                                                        d.err, a, m);
     else
-        k_move<T, P, 2><<<(m.nv + 7) / 8, 256, 0, s>>>(d.q, (const T *)d.U, d.stamp, d.ctr, d.act, d.mask, d.err,
-                                                        a, m);
+        k_move<T, P, 2><<<(m.nv + 7) / 8, 256, 0, s>>>(d.q, (const T *)d.U, d.stamp, d.ctr, d.acnt, d.act, d.mask,
+                                                        d.err, a, m);
 }
 
 hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, hipStream_t s)

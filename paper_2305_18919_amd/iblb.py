@@ -113,6 +113,7 @@ def lib():
             "iblb_load_state": [_vp, _vp, C.c_size_t],
             "iblb_set_graph": [_vp, C.c_int32],
             "iblb_set_timing": [_vp, C.c_int32],
+            "iblb_get_lb_split": [_vp, _ip, _dp],
             "iblb_kernel_time": [_vp, C.c_char_p, _dp, C.POINTER(C.c_int64)],
             "iblb_reset_timing": [_vp],
             "iblb_active_nodes": [_vp, C.POINTER(C.c_int64)],
@@ -266,6 +267,13 @@ class Simulation:
 
     def set_timing(self, on: bool):
         self._check(lib().iblb_set_timing(self.h, int(bool(on))))
+
+    def lb_split(self) -> dict:
+        """Launch shape of the LB outside the active tiles (iblb_get_lb_split)."""
+        bx = C.c_int32()
+        sh = C.c_double()
+        self._check(lib().iblb_get_lb_split(self.h, C.byref(bx), C.byref(sh)))
+        return {"block_x": bx.value, "share_forces": sh.value}
 
     def reset_timing(self):
         self._check(lib().iblb_reset_timing(self.h))
