@@ -10,8 +10,9 @@ query-time observables in numpy:
   shear plane (Eq. taylor_deform) from the central second-moment tensor of the
   enclosed polyhedron, read as an ellipsoid with M = V/5 diag(r^2);
 * equilibrium contact angle from an algebraic least-squares sphere fit of the
-  vertices away from the wall (the paper fits a circle cut by a chord; see the
-  appendix on the resolution test).
+  vertices away from the wall, and the paper's own measurement (appendix on the
+  resolution test): a circle cut by the wall chord, fitted to a slice of the
+  mesh holding about (4 / 3^(1/4)) sqrt(pi N_f) nodes.
 """
 from __future__ import annotations
 
@@ -287,19 +288,61 @@ def shape_dtheta(q, faces):
     return (r1 - r3) / (r1 + r3), th
 
 
-def contact_angle_sphere(q, z_wall: float, exclude: float = 2.0):
-    """Algebraic least-squares sphere through vertices with z - z_wall >= exclude.
+def contact_angle_sphere(q, z_wall: float, exclude: float = 2.0, wall_hi: bool = False):
+    """Algebraic least-squares sphere through the vertices at least `exclude`
+    from the wall plane z = z_wall (the lower wall, or the upper one with
+    wall_hi, the liquid then lying below it).
 
-    Solves |p|^2 = 2 c.p + k for (c, k); R^2 = k + |c|^2.  Returns
+    Solves |p|^2 = 2 c.p + k for (c, k); R^2 = k + |c|^2; the centre's height
+    hc above the wall into the liquid gives theta = arccos(-hc / R).  Returns
     (theta_deg, contact_radius, height, centre, R)."""
     q = np.asarray(q, dtype=np.float64)
-    p = q[q[:, 2] - z_wall >= exclude]
+    dist = (z_wall - q[:, 2]) if wall_hi else (q[:, 2] - z_wall)
+    p = q[dist >= exclude]
     A = np.hstack([2.0 * p, np.ones((p.shape[0], 1))])
     rhs = (p * p).sum(axis=1)
     sol, *_ = np.linalg.lstsq(A, rhs, rcond=None)
     cen, k = sol[:3], sol[3]
     R = np.sqrt(k + cen @ cen)
-    hc = cen[2] - z_wall
+    hc = (z_wall - cen[2]) if wall_hi else (cen[2] - z_wall)
     theta = np.degrees(np.arccos(np.clip(-hc / R, -1.0, 1.0)))
     r = np.sqrt(max(0.0, R * R - hc * hc))
-    return theta, r, cen[2] + R - z_wall, cen, R
+    return theta, r, hc + R, cen, R
+
+
+def slice_count(n_faces: int) -> int:
+    """Nodes in the paper's fitting slice, (4 / 3^(1/4)) sqrt(pi N_f), rounded
+    (appendix on the resolution test).  For a sphere meshed by N_f nearly
+    equilateral triangles this is the number of nodes within two edge lengths
+    of a plane through the centre."""
+    return int(np.floor(4.0 / 3.0 ** 0.25 * np.sqrt(np.pi * n_faces) + 0.5))
+
+
+def contact_angle_slice(q, faces, z_wall: float, exclude: float = 2.0, wall_hi: bool = False, K=None):
+    """The paper's contact angle (appendix on the resolution test): a circle cut
+    by the wall chord fitted to a slice of the mesh.  The slice is the K nodes
+    nearest the plane y = y of the volume centroid (ties to the lower vertex
+    index), K = slice_count(N_f) unless given; they are projected on (x, z),
+    those at least `exclude` from the wall plane kept, and the circle
+    x^2 + z^2 = 2 c.p + k fitted by algebraic least squares.  Returns
+    (theta_deg, contact_radius, height, centre_xz, R) as contact_angle_sphere."""
+    q = np.asarray(q, dtype=np.float64)
+    nv = q.shape[0]
+    K = slice_count(len(faces)) if K is None else int(K)
+    K = max(1, min(nv, K))
+    _, _, xc = volume_area_centroid(q, faces)
+    d = np.abs(q[:, 1] - xc[1])
+    order = np.lexsort((np.arange(nv), d))[:K]
+    p = q[order]
+    dist = (z_wall - p[:, 2]) if wall_hi else (p[:, 2] - z_wall)
+    p = p[dist >= exclude]
+    xz = p[:, [0, 2]]
+    A = np.hstack([2.0 * xz, np.ones((xz.shape[0], 1))])
+    rhs = (xz * xz).sum(axis=1)
+    sol, *_ = np.linalg.lstsq(A, rhs, rcond=None)
+    cen, k = sol[:2], sol[2]
+    R = np.sqrt(k + cen @ cen)
+    hc = (z_wall - cen[1]) if wall_hi else (cen[1] - z_wall)
+    theta = np.degrees(np.arccos(np.clip(-hc / R, -1.0, 1.0)))
+    r = np.sqrt(max(0.0, R * R - hc * hc))
+    return theta, r, hc + R, cen, R
