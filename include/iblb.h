@@ -157,12 +157,19 @@ int iblb_volume(iblb_ctx *ctx, int32_t mesh_id, double *V, double *A);
  * as an ellipsoid (M = V/5 diag(r^2)); centroid = volume centroid. */
 int iblb_shape(iblb_ctx *ctx, int32_t mesh_id, double *D, double *Theta, double centroid[3]);
 
-/* Contact angle against a wall (0: lower, 1: upper), the paper's circle-cut-
- * by-a-chord fit (appendix on the resolution test) done as an algebraic least-
- * squares sphere fit in FP64 of the vertices at least 2 lattice units away from
- * that wall plane (method 0, the only one supported).  Returns the angle in
- * degrees measured inside the liquid, the contact radius and the height of the
- * fitted cap above the wall plane. */
+/* Contact angle against a wall (0: lower, 1: upper), FP64, from vertices at
+ * least 2 lattice units away from that wall plane.
+ *   method 1: the paper's measurement (appendix on the resolution test), a
+ *     circle cut by the wall chord fitted by algebraic least squares in the
+ *     (x, z) plane to a slice of the mesh: the K = round((4 / 3^(1/4))
+ *     sqrt(pi N_f)) vertices nearest the plane y = y of the volume centroid,
+ *     ties to the lower vertex index (K capped at the vertex count).
+ *   method 0: an algebraic least-squares sphere fit of all those vertices
+ *     (the three-dimensional form of the same cap).
+ * Returns the angle in degrees measured inside the liquid, the contact radius
+ * and the height of the fitted cap above the wall plane.  IBLB_E_INVAL for
+ * another wall or method, IBLB_E_STATE without walls or with too few vertices
+ * (4 for the sphere, 3 for the circle) away from the wall. */
 int iblb_contact_angle(iblb_ctx *ctx, int32_t mesh_id, int32_t wall, int32_t method,
                        double *theta_deg, double *contact_radius, double *height);
 

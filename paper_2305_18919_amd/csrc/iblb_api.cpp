@@ -765,51 +765,83 @@ int iblb_shape(iblb_ctx *c, int32_t mesh_id, double *D, double *Theta, double ce
     return rc;
 }
 
+// Solves the n x n (n <= 4) symmetric normal equations N s = r of an algebraic
+// least-squares fit, N given as its packed upper triangle (row by row), by
+// Gaussian elimination with partial pivoting.  False when N is singular.
+static bool solve_normal(int n, const double *packed, const double *r, double *s)
+{
+    double N[4][5];
+    int k = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i; j < n; ++j) {
+            N[i][j] = packed[k];
+            N[j][i] = packed[k];
+            ++k;
+        }
+    for (int i = 0; i < n; ++i) N[i][n] = r[i];
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int row = col + 1; row < n; ++row)
+            if (std::fabs(N[row][col]) > std::fabs(N[piv][col])) piv = row;
+        if (!(std::fabs(N[piv][col]) > 0.0)) return false;
+        for (int cc = 0; cc <= n; ++cc) std::swap(N[col][cc], N[piv][cc]);
+        for (int row = col + 1; row < n; ++row) {
+            const double fct = N[row][col] / N[col][col];
+            for (int cc = col; cc <= n; ++cc) N[row][cc] -= fct * N[col][cc];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double acc = N[i][n];
+        for (int j = i + 1; j < n; ++j) acc -= N[i][j] * s[j];
+        s[i] = acc / N[i][i];
+    }
+    return true;
+}
+
+// Nodes of the paper's fitting slice, (4 / 3^(1/4)) sqrt(pi N_f) rounded
+// (appendix on the resolution test), at most the vertex count.
+static int slice_count(int nf, int nv)
+{
+    const int K = (int)std::floor(4.0 / std::pow(3.0, 0.25) * std::sqrt(M_PI * nf) + 0.5);
+    return std::max(1, std::min(nv, K));
+}
+
 int iblb_contact_angle(iblb_ctx *c, int32_t mesh_id, int32_t wall, int32_t method, double *theta_deg,
                        double *contact_radius, double *height)
 {
     int rc = mesh_ok(c, mesh_id);
     if (rc) return rc;
     if (wall != 0 && wall != 1) return fail(c, IBLB_E_INVAL, "wall must be 0 (lower) or 1 (upper)");
-    if (method != 0) return fail(c, IBLB_E_INVAL, "only method 0 (sphere fit) is supported");
+    if (method != 0 && method != 1) return fail(c, IBLB_E_INVAL, "method must be 0 (sphere) or 1 (slice circle)");
     if (!c->g.walls) return fail(c, IBLB_E_STATE, "no walls in a periodic domain");
     rc = sync_ctx(c);
     const double zw = wall ? c->dom.nz - 1.5 : 0.5;
     const double shift[3] = {c->m.origin[0], c->m.origin[1], zw};
-    double mom[15];
-    HIP_TRY(c, launch_sphere_moments(c->d, c->m, wall, zw, 2.0, shift, c->d.scratch, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(mom, c->d.scratch, 15 * 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (mom[14] < 4.0) return fail(c, IBLB_E_STATE, "fewer than 4 vertices away from the wall");
-    // normal equations N s = r, N symmetric 4x4 from the packed upper triangle
-    double N[4][5];
-    int k = 0;
-    for (int i = 0; i < 4; ++i)
-        for (int j = i; j < 4; ++j) {
-            N[i][j] = mom[k];
-            N[j][i] = mom[k];
-            ++k;
-        }
-    for (int i = 0; i < 4; ++i) N[i][4] = mom[10 + i];
-    for (int col = 0; col < 4; ++col) {  // Gaussian elimination, partial pivoting
-        int piv = col;
-        for (int r = col + 1; r < 4; ++r)
-            if (std::fabs(N[r][col]) > std::fabs(N[piv][col])) piv = r;
-        if (!(std::fabs(N[piv][col]) > 0.0)) return fail(c, IBLB_E_STATE, "singular sphere fit");
-        for (int cc = 0; cc < 5; ++cc) std::swap(N[col][cc], N[piv][cc]);
-        for (int r = col + 1; r < 4; ++r) {
-            const double fct = N[r][col] / N[col][col];
-            for (int cc = col; cc < 5; ++cc) N[r][cc] -= fct * N[col][cc];
-        }
+    double R, hc;
+    if (method == 0) {
+        double mom[15], s[4];
+        HIP_TRY(c, launch_sphere_moments(c->d, c->m, wall, zw, 2.0, shift, c->d.scratch, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(mom, c->d.scratch, 15 * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (mom[14] < 4.0) return fail(c, IBLB_E_STATE, "fewer than 4 vertices away from the wall");
+        if (!solve_normal(4, mom, mom + 10, s)) return fail(c, IBLB_E_STATE, "singular sphere fit");
+        R = std::sqrt(s[3] + s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        hc = wall ? -s[2] : s[2];  // centre height above the wall plane (into the fluid)
+    } else {
+        // mesh moments (for the centroid plane) into scratch[0..10], the slice's
+        // normal equations into scratch[16..25]
+        double mom[10], s[3];
+        const double sh2[2] = {shift[0], zw};
+        HIP_TRY(c, launch_mesh_moments(c->d, c->m, c->d.scratch, c->stream));
+        HIP_TRY(c, launch_slice_moments(c->d, c->m, c->d.scratch, slice_count(c->m.nf, c->m.nv), wall, zw, 2.0,
+                                        sh2, c->d.scratch + 16, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(mom, c->d.scratch + 16, 10 * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (mom[9] < 3.0) return fail(c, IBLB_E_STATE, "fewer than 3 slice vertices away from the wall");
+        if (!solve_normal(3, mom, mom + 6, s)) return fail(c, IBLB_E_STATE, "singular circle fit");
+        R = std::sqrt(s[2] + s[0] * s[0] + s[1] * s[1]);
+        hc = wall ? -s[1] : s[1];
     }
-    double s[4];
-    for (int i = 3; i >= 0; --i) {
-        double acc = N[i][4];
-        for (int j = i + 1; j < 4; ++j) acc -= N[i][j] * s[j];
-        s[i] = acc / N[i][i];
-    }
-    const double R = std::sqrt(s[3] + s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-    const double hc = wall ? -s[2] : s[2];  // centre height above the wall plane (into the fluid)
     const double cth = std::max(-1.0, std::min(1.0, -hc / R));
     if (theta_deg) *theta_deg = std::acos(cth) * 180.0 / M_PI;
     if (contact_radius) *contact_radius = std::sqrt(std::max(0.0, R * R - hc * hc));

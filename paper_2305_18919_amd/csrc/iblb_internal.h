@@ -211,5 +211,9 @@ hipError_t launch_nodal_forces(int prec, const Dev &d, const MeshArgs &m, double
 hipError_t launch_mesh_moments(const Dev &d, const MeshArgs &m, double *out, hipStream_t s);
 hipError_t launch_sphere_moments(const Dev &d, const MeshArgs &m, int wall_hi, double z_wall, double excl,
                                  const double *shift, double *out, hipStream_t s);
+// circle fit on the mesh slice of the K vertices nearest the centroid plane;
+// mom = the output of launch_mesh_moments (device), shift = (x, z)
+hipError_t launch_slice_moments(const Dev &d, const MeshArgs &m, const double *mom, int K, int wall_hi,
+                                double z_wall, double excl, const double *shift, double *out, hipStream_t s);
 
 }  // namespace iblb

@@ -1639,6 +1639,95 @@ __global__ __launch_bounds__(1024) void k_sphere_moments(const double *__restric
     block_reduce_store<15>(acc, out);
 }
 
+// The paper's contact-angle measurement (appendix on the resolution test): a
+// circle cut by the wall chord fitted to a slice of the mesh.  The slice is the
+// K vertices nearest the plane, normal to y, through the volume centroid (ties
+// to the lower vertex index).  One block: a radix select over the 64-bit
+// patterns of |y - y_c| (non-negative doubles order as their bit patterns)
+// finds the K-th key T; the vertices below T and the lowest-indexed ones equal
+// to T make the slice.  Those at least excl from the wall plane add to the
+// normal equations of x^2 + z^2 = 2 c.p + k in the (x, z) plane, p shifted by
+// (sx, sz): packed upper triangle (6), right side (3), count.  mom holds the
+// mesh moments of k_mesh_moments (V at 0, the volume y moment about m.origin
+// at 3).
+__global__ __launch_bounds__(1024) void k_slice_moments(const double *__restrict__ q, const double *__restrict__ mom,
+                                                        double *__restrict__ out, MeshArgs m, int K, int wall_hi,
+                                                        double z_wall, double excl, double sx, double sz)
+{
+    __shared__ unsigned hist[256];
+    __shared__ unsigned wave_ties[16];
+    __shared__ unsigned long long s_prefix;
+    __shared__ unsigned s_need;
+    const int nv = m.nv, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double yc = m.origin[1] + mom[3] / mom[0];
+    auto key_of = [&](int v) { return (unsigned long long)__double_as_longlong(fabs(q[nv + v] - yc)); };
+
+    unsigned long long prefix = 0, mask = 0;
+    unsigned need = (unsigned)K;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        if (tid < 256)
+            hist[tid] = 0;
+        __syncthreads();
+        for (int v = tid; v < nv; v += blockDim.x) {
+            const unsigned long long key = key_of(v);
+            if ((key & mask) == prefix)
+                atomicAdd(&hist[(key >> shift) & 255], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            unsigned cum = 0;
+            int b = 0;
+            for (; b < 255 && cum + hist[b] < need; ++b)
+                cum += hist[b];
+            s_prefix = prefix | ((unsigned long long)b << shift);
+            s_need = need - cum;
+        }
+        __syncthreads();
+        prefix = s_prefix;
+        need = s_need;
+        mask |= 255ull << shift;
+    }
+
+    // prefix is T; `need` vertices with key T belong to the slice, in index order
+    double acc[10];
+    for (int k = 0; k < 10; ++k)
+        acc[k] = 0.0;
+    unsigned base = 0;
+    for (int c0 = 0; c0 < nv; c0 += blockDim.x) {
+        const int v = c0 + tid;
+        const unsigned long long key = v < nv ? key_of(v) : ~0ull;
+        const bool tie = v < nv && key == prefix;
+        const unsigned long long bal = __ballot(tie);
+        if (lane == 0)
+            wave_ties[wv] = (unsigned)__popcll(bal);
+        __syncthreads();
+        unsigned rank = base + (unsigned)__popcll(bal & ((1ull << lane) - 1ull)), total = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            rank += w < wv ? wave_ties[w] : 0u;
+            total += wave_ties[w];
+        }
+        __syncthreads();
+        base += total;
+        if (v < nv && (key < prefix || (tie && rank < need))) {
+            const double zq = q[2 * nv + v];
+            const double dist = wall_hi ? z_wall - zq : zq - z_wall;
+            if (dist >= excl) {
+                const double px = q[v] - sx, pz = zq - sz;
+                const double r[3] = {2.0 * px, 2.0 * pz, 1.0};
+                const double b = px * px + pz * pz;
+                int k = 0;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = i; j < 3; ++j)
+                        acc[k++] += r[i] * r[j];
+                for (int i = 0; i < 3; ++i)
+                    acc[6 + i] += r[i] * b;
+                acc[9] += 1.0;
+            }
+        }
+    }
+    block_reduce_store<10>(acc, out);
+}
+
 dim3 lb_block(const Grid &g)
 {
     const int bx = g.nx >= 64 ? 64 : (g.nx >= 32 ? 32 : 16);
@@ -1934,6 +2023,13 @@ hipError_t launch_sphere_moments(const Dev &d, const MeshArgs &m, int wall_hi, d
                                  const double *shift, double *out, hipStream_t s)
 {
     k_sphere_moments<<<1, 1024, 0, s>>>(d.q, out, m, wall_hi, z_wall, excl, shift[0], shift[1], shift[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_moments(const Dev &d, const MeshArgs &m, const double *mom, int K, int wall_hi,
+                                double z_wall, double excl, const double *shift, double *out, hipStream_t s)
+{
+    k_slice_moments<<<1, 1024, 0, s>>>(d.q, mom, out, m, K, wall_hi, z_wall, excl, shift[0], shift[1]);
     return hipGetLastError();
 }
 

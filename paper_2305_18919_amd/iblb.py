@@ -353,9 +353,11 @@ class Simulation:
         self._check(lib().iblb_shape(self.h, 0, C.byref(D), C.byref(th), _p(cen)))
         return D.value, th.value, cen
 
-    def contact_angle(self, wall: int = 0):
+    def contact_angle(self, wall: int = 0, method: int = 0):
+        """(theta_deg, contact_radius, height): method 0 sphere fit, 1 the
+        slice circle fit."""
         th, r, h = C.c_double(), C.c_double(), C.c_double()
-        self._check(lib().iblb_contact_angle(self.h, 0, wall, 0, C.byref(th), C.byref(r), C.byref(h)))
+        self._check(lib().iblb_contact_angle(self.h, 0, wall, method, C.byref(th), C.byref(r), C.byref(h)))
         return th.value, r.value, h.value
 
     # -- adjoint
