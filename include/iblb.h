@@ -177,6 +177,19 @@ int iblb_contact_angle(iblb_ctx *ctx, int32_t mesh_id, int32_t wall, int32_t met
  * density of the last step in the Guo velocity (zero before the first step). */
 int iblb_get_fields(iblb_ctx *ctx, double *rho, double *u);
 
+/* Allocation-free form of iblb_get_fields, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * iblb_get_fields, which allocates a device staging buffer of 32 bytes per
+ * fluid node on every call; this one stages through a fixed device array of
+ * IBLB_NOALLOC_MAX_NODES * 32 bytes (64 MiB) that the library holds on every
+ * GPU it runs on until the process ends.  Lattices with more fluid nodes get
+ * IBLB_E_INVAL; IBLB_E_DEVICE if the array could not be located on the
+ * context's device.  All calls on one GPU share that array: calls that
+ * overlap on one GPU (from several threads) race. */
+#define IBLB_NOALLOC_MAX_NODES 2097152
+int iblb_get_fields_noalloc(iblb_ctx *ctx, double *rho, double *u);
+
 /* Debug / validation calls. */
 /* Fixed external force density [3][N] added every step; only without a mesh. */
 int iblb_debug_set_force(iblb_ctx *ctx, const double *F);

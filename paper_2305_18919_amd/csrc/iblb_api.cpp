@@ -122,6 +122,7 @@ struct iblb_ctx {
     Layout L;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = 0;  // the device current at creation, which holds the workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;
     bool own_ws = false;
@@ -441,6 +442,25 @@ int mesh_ok(iblb_ctx *c, int32_t mesh_id)
 
 }  // namespace
 
+namespace iblb {
+int get_fields_staged(iblb_ctx *c, double *staging, double *rho, double *u)
+{
+    int rc = sync_ctx(c);
+    if (rc == IBLB_E_DEVICE) return rc;
+    const size_t n = (size_t)c->g.n;
+    double *dr = staging, *du = staging + n;
+    HIP_TRY(c, launch_get_fields(c->prec, c->d, c->lb, (int)(c->t & 1), dr, du, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(rho, dr, n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(u, du, 3 * n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return rc;
+}
+
+long long ctx_fluid_nodes(const iblb_ctx *c) { return (long long)c->g.n; }
+int ctx_device(const iblb_ctx *c) { return c->device; }
+int ctx_fail(iblb_ctx *c, int code, const char *msg) { return fail(c, code, msg); }
+}  // namespace iblb
+
 extern "C" {
 
 int iblb_workspace_bytes(const iblb_domain_desc *dom, const iblb_mesh_desc *mesh, size_t *bytes)
@@ -510,6 +530,8 @@ int iblb_create(const iblb_domain_desc *dom, void *dev_workspace, size_t workspa
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             return bail(IBLB_E_DEVICE);
         d.num_cus = cus;
+        c->device = dev;
+        noalloc_setup(dev);
     }
     lb_args(c);
     if (hipMemsetAsync(c->ws + c->L.stamp, 0, c->L.dom_end - c->L.stamp, c->stream) != hipSuccess ||
@@ -852,16 +874,9 @@ int iblb_contact_angle(iblb_ctx *c, int32_t mesh_id, int32_t wall, int32_t metho
 int iblb_get_fields(iblb_ctx *c, double *rho, double *u)
 {
     if (!c || !rho || !u) return IBLB_E_INVAL;
-    int rc = sync_ctx(c);
-    const size_t n = (size_t)c->g.n;
     TmpDev tmp;
-    HIP_TRY(c, hipMalloc(&tmp.p, 4 * n * 8));
-    double *dr = (double *)tmp.p, *du = dr + n;
-    HIP_TRY(c, launch_get_fields(c->prec, c->d, c->lb, (int)(c->t & 1), dr, du, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(rho, dr, n * 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(u, du, 3 * n * 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return rc;
+    HIP_TRY(c, hipMalloc(&tmp.p, 4 * (size_t)c->g.n * 8));
+    return get_fields_staged(c, (double *)tmp.p, rho, u);
 }
 
 int iblb_debug_set_force(iblb_ctx *c, const double *F)

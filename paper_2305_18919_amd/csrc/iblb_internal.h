@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct iblb_ctx;
+
 namespace iblb {
 
 // Force-density tiles: 4x4x4 fluid nodes, one wavefront each when spreading.
@@ -215,5 +217,16 @@ hipError_t launch_sphere_moments(const Dev &d, const MeshArgs &m, int wall_hi, d
 // mom = the output of launch_mesh_moments (device), shift = (x, z)
 hipError_t launch_slice_moments(const Dev &d, const MeshArgs &m, const double *mom, int K, int wall_hi,
                                 double z_wall, double excl, const double *shift, double *out, hipStream_t s);
+
+// Context accessors for entry points outside iblb_api.cpp.
+long long ctx_fluid_nodes(const iblb_ctx *c);
+int ctx_device(const iblb_ctx *c);
+int ctx_fail(iblb_ctx *c, int code, const char *msg);  // records msg, returns code
+// iblb_get_fields through a caller-chosen device staging buffer of 4 n doubles
+// (rho [n], then u [3][n]); allocates nothing.
+int get_fields_staged(iblb_ctx *c, double *staging, double *rho, double *u);
+// Per-device set-up of the fixed staging array of iblb_get_fields_noalloc; run
+// by iblb_create with `device` current, once per device.
+void noalloc_setup(int device);
 
 }  // namespace iblb

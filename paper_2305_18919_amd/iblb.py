@@ -104,6 +104,7 @@ def lib():
             "iblb_shape": [_vp, C.c_int32, _dp, _dp, _dp],
             "iblb_contact_angle": [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp, _dp],
             "iblb_get_fields": [_vp, _dp, _dp],
+            "iblb_get_fields_noalloc": [_vp, _dp, _dp],
             "iblb_debug_set_force": [_vp, _dp],
             "iblb_debug_get_force": [_vp, _dp],
             "iblb_debug_get_populations": [_vp, _dp],
