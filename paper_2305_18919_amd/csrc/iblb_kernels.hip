@@ -846,6 +846,13 @@ __device__ __forceinline__ void stage_store(const Staged<T> &s, int e, T kf, T *
         sph[e * 4 + c] = s.ph[c] - kf * s.gv[c];
 }
 
+// Entries of a tile's vertex list staged in LDS per pass of the spreading.
+constexpr int kStageChunk = 128;
+// Spreading blocks per CU the register budget aims at: three with FP32
+// arithmetic; FP64 needs the whole register file of one.
+template <typename S>
+constexpr int kSpreadOccupancy = sizeof(typename Pop<S>::C) == 8 ? 1 : 3;
+
 // Blocks [0, nsp) spread: one 256-thread block (four wavefronts) per active
 // tile, striding over the list.  Blocks from nsp on (if any) run the LB of the
 // nodes outside the active tiles: it is bandwidth-bound, the spreading is
@@ -855,14 +862,16 @@ __device__ __forceinline__ void stage_store(const Staged<T> &s, int e, T kf, T *
 // Spreading: the tile's vertex
 // mask (bit v set when vertex v's stencil reaches the tile) is read whole,
 // thread k taking the k-th contiguous run of words; a block-wide prefix sum of
-// the words' bit counts gives every word the list position of its first set
-// bit; the nonzero words go to LDS in order and the wavefronts expand them,
-// one lane per bit, so the listed vertices come out in ascending index order.  All four wavefronts
-// stage the listed vertices in LDS; wavefront w sums the w-th contiguous
-// quarter of the ordered list for the 64 nodes of the tile (one per lane), and
-// the four partial sums are added in wavefront order, so every node's sum has
-// a fixed order.  Wavefront 0 finishes with the LB update of the tile's nodes,
-// whose populations it fetched at the start.
+// the words' bit counts gives every thread the list position of its first set
+// bit, and each thread writes the list entries of its own set bits, so the
+// listed vertices come out in ascending index order.  The list is staged in
+// LDS in passes of kStageChunk entries (one pass for all but the most crowded
+// tiles), which keeps the block's LDS small;
+// wavefront w sums the w-th contiguous quarter of each pass for the 64 nodes
+// of the tile (one per lane), and the four partial sums are added in
+// wavefront order, so every node's sum has a fixed order.  Wavefront 0
+// finishes with the LB update of the tile's nodes, whose populations it
+// fetched with the first pass.
 template <typename S, int P, typename T = typename Pop<S>::C>
 __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
@@ -879,20 +888,16 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
         bulk_lb_block<S, P == 1>(lb0 + blk - nsp, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
         return;
     }
-    __shared__ int sid[kTileCap];
-    __shared__ __align__(16) T sw[kTileCap * 12];
-    __shared__ __align__(16) T sph[kTileCap * 4];
+    __shared__ int sid[kStageChunk];
+    __shared__ __align__(16) T sw[kStageChunk * 12];
+    __shared__ __align__(16) T sph[kStageChunk * 4];
     __shared__ T part[3][3][64];
-    __shared__ T spop[19][64];        // wavefront 0's prefetched populations
-    __shared__ uint64_t swd[kTileCap];  // the nonzero mask words, in order,
-    __shared__ int swo[kTileCap];       // the list position of each one's first bit,
-    __shared__ int swi[kTileCap];       // and its word index
+    __shared__ T spop[19][64];  // wavefront 0's prefetched populations
     __shared__ int swt[4];
     __shared__ T skfac;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nv = m.nv, W = m.nwords;
     const int J = (W + 255) >> 8;  // words per thread, at most 4
-    const uint64_t below = (1ull << lane) - 1ull;
     // the count of active tiles and the block's first tile are read together
     // (block index < nsp <= tile count, so the slot exists); the volatile
     // read keeps the compiler from deferring it past the test on the count
@@ -919,11 +924,11 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
             for (int j = 0; j < 4; ++j)
                 wv[j] = (j < J && w0 + j < W) ? mw[w0 + j] : 0ull;
         }
-        // set bits (low 20 bits) and nonzero words (above) of this thread's words
+        // set bits of this thread's words
         int c = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            c += __popcll(wv[j]) + (wv[j] != 0ull ? 1 << 20 : 0);
+            c += __popcll(wv[j]);
         if (wave == 1 && ai == (uint32_t)blk) {
             const T kfac = T(volume_factor(partials, m, lane));
             if (lane == 0)
@@ -938,60 +943,69 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             wn[j] = (an < na && j < J && w0 + j < W) ? mask[(long long)next * W + w0 + j] : 0ull;
-        const int tot = swt[0] + swt[1] + swt[2] + swt[3];
-        int nent = tot & 0xfffff;
-        const int nnz = tot >> 20;
+        int nent = swt[0] + swt[1] + swt[2] + swt[3];
         if (nent > kTileCap) {
             if (tid == 0)
                 atomicOr(err, kErrOverflow);
             nent = kTileCap;
         }
-        // the nonzero words in order; a word at position >= kTileCap has all its
-        // bits at list positions >= kTileCap and is dropped with them
-        {
-            int pre = incl - c;
-            for (int w = 0; w < wave; ++w)
-                pre += swt[w];
-            int o = pre & 0xfffff, k = pre >> 20;
+        // list position of this thread's first set bit: the list is in thread
+        // order, and within a thread in word and bit order
+        int pre = incl - c;
+        for (int w = 0; w < wave; ++w)
+            pre += swt[w];
+        const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 4 + g.zoff;
+        const T kf = skfac;
+        T Fx = T(0), Fy = T(0), Fz = T(0);
+        // The ordered list in passes of kStageChunk entries: every thread
+        // writes the entries of its own words' set bits that fall in the pass,
+        // the vertices of the pass are staged (local weights and total force),
+        // and wavefront w sums the w-th contiguous quarter of the pass.
+        auto expand = [&](int c0, int cn) {
+            int o = pre;
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (wv[j] != 0ull) {
-                    if (k < kTileCap) {
-                        swd[k] = wv[j];
-                        swo[k] = o;
-                        swi[k] = w0 + j;
+            for (int j = 0; j < 4; ++j) {
+                uint64_t word = wv[j];
+                const int nb = __popcll(word);
+                if (o < c0 + cn && o + nb > c0) {
+                    for (int p = o; word != 0ull && p < c0 + cn; ++p) {
+                        if (p >= c0)
+                            sid[p - c0] = (w0 + j) * 64 + __builtin_ctzll(word);
+                        word &= word - 1ull;
                     }
-                    ++k;
-                    o += __popcll(wv[j]);
                 }
-        }
-        __syncthreads();
-        // expand the nonzero words, one lane per bit
-        const int nw = nnz < kTileCap ? nnz : kTileCap;
-#pragma unroll 4
-        for (int k = wave; k < nw; k += 4) {
-            const uint64_t word = swd[k];
-            if ((word >> lane) & 1ull) {
-                const int pos = swo[k] + __popcll(word & below);
-                if (pos < kTileCap)
-                    sid[pos] = swi[k] * 64 + lane;
+                o += nb;
             }
-        }
+        };
+        static_assert(kStageChunk <= 256, "one staged entry per thread and pass");
+        auto stage = [&](int cn) {
+            if (tid < cn) {
+                const Staged<T> st = stage_load<T>(sid[tid], base, wts, phiSW, gV, nv, err, g, x0, y0, z0);
+                stage_store<T>(st, tid, kf, sw, sph);
+            }
+        };
+        auto accumulate = [&](int cn) {
+            const int q4 = (cn + 3) >> 2;
+            const int e0 = wave * q4, e1 = min(cn, e0 + q4);
+#pragma unroll 8
+            for (int e = e0; e < e1; ++e) {
+                const T w = sw[e * 12 + lx] * sw[e * 12 + 4 + ly] * sw[e * 12 + 8 + lz];
+                Fx += sph[e * 4 + 0] * w;
+                Fy += sph[e * 4 + 1] * w;
+                Fz += sph[e * 4 + 2] * w;
+            }
+        };
+        // the first pass: wavefront 0 fetches its node's populations with the
+        // staged loads (fetched earlier, they would be waited for at the
+        // barrier: loads complete in order)
+        const int cn0 = min(kStageChunk, nent);
+        expand(0, cn0);
         __syncthreads();
-        // stage each listed vertex's local weights and total force.
-        // Wavefront 0 fetches its node's populations first, so that they
-        // arrive with the staged vertices' loads: fetched earlier, they would
-        // be waited for at the first barrier (loads complete in order)
         {
             T d[19];
             if (wave == 0 && node)
                 load_pops<S, P == 1>(f, g, x, y, zf, d);
-            const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 4 + g.zoff;
-            const T kf = skfac;
-            for (int e = tid; e < nent; e += 256) {
-                const Staged<T> st = stage_load<T>(sid[e], base, wts, phiSW, gV, nv, err, g, x0, y0, z0);
-                stage_store<T>(st, e, kf, sw, sph);
-            }
+            stage(cn0);
             if (wave == 0 && node) {
 #pragma unroll
                 for (int i = 0; i < 19; ++i)
@@ -999,16 +1013,16 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
             }
         }
         __syncthreads();
-        // this wavefront's quarter of the ordered list
-        const int chunk = (nent + 3) >> 2;
-        const int e0 = wave * chunk, e1 = min(nent, e0 + chunk);
-        T Fx = T(0), Fy = T(0), Fz = T(0);
-#pragma unroll 8
-        for (int e = e0; e < e1; ++e) {
-            const T w = sw[e * 12 + lx] * sw[e * 12 + 4 + ly] * sw[e * 12 + 8 + lz];
-            Fx += sph[e * 4 + 0] * w;
-            Fy += sph[e * 4 + 1] * w;
-            Fz += sph[e * 4 + 2] * w;
+        accumulate(cn0);
+        // further passes (tiles listing more than kStageChunk vertices)
+        for (int c0 = kStageChunk; c0 < nent; c0 += kStageChunk) {
+            const int cn = min(kStageChunk, nent - c0);
+            __syncthreads();  // the previous pass is done with sid, sw and sph
+            expand(c0, cn);
+            __syncthreads();
+            stage(cn);
+            __syncthreads();
+            accumulate(cn);
         }
         if (wave > 0) {
             part[wave - 1][0][lane] = Fx;
@@ -1053,7 +1067,7 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
 }
 
 template <typename S, int P, typename T = typename Pop<S>::C>
-__global__ __launch_bounds__(256, 3) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
+__global__ __launch_bounds__(256, kSpreadOccupancy<S>) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
                                                 const double *__restrict__ partials, const uint32_t *__restrict__ ctr,
                                                 uint64_t *__restrict__ mask, const uint32_t *__restrict__ acnt,
@@ -1283,7 +1297,7 @@ __global__ __launch_bounds__(256) void kb_forces(const DomRec *__restrict__ R, c
 }
 
 template <typename S, int P, typename T = typename Pop<S>::C>
-__global__ __launch_bounds__(256, 3) void kb_spread(const DomRec *__restrict__ R, const uint32_t *__restrict__ tab)
+__global__ __launch_bounds__(256, kSpreadOccupancy<S>) void kb_spread(const DomRec *__restrict__ R, const uint32_t *__restrict__ tab)
 {
     const uint32_t e = tab[blockIdx.x];
     const DomRec &r = R[e & 0xffu];
@@ -1832,6 +1846,21 @@ hipError_t launch_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs
     });
 }
 
+// Spreading blocks one CU holds at once (limited by registers and LDS).
+template <typename S, int P>
+static int spread_blocks_per_cu()
+{
+    using T = typename Pop<S>::C;
+    static int n = 0;
+    if (n == 0) {
+        int k = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, k_spread<S, P, T>, 256, 0) != hipSuccess || k < 1)
+            k = 1;
+        n = k;
+    }
+    return n;
+}
+
 template <typename S, int P>
 static void spread_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int nsp, int with_lb, hipStream_t s)
 {
@@ -1848,12 +1877,12 @@ static void spread_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int 
 hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, int with_lb,
                          hipStream_t s)
 {
-    // spreading blocks: as many as the CUs hold at once (register-limited: 2
-    // per CU with FP32 arithmetic, 1 with FP64), striding over the active tiles
-    const int fit = d.num_cus * (prec == 0 ? 1 : 2);
-    const int nsp = a.g.nt < fit ? a.g.nt : fit;
+    // spreading blocks: as many as the CUs hold at once, striding over the
+    // active tiles
     return with_pop_type(prec, [&](auto tag) {
         using S = decltype(tag);
+        const int fit = d.num_cus * (p ? spread_blocks_per_cu<S, 1>() : spread_blocks_per_cu<S, 0>());
+        const int nsp = a.g.nt < fit ? a.g.nt : fit;
         p ? spread_launch<S, 1>(d, a, m, nsp, with_lb, s) : spread_launch<S, 0>(d, a, m, nsp, with_lb, s);
     });
 }
