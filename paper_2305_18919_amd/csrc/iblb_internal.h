@@ -34,6 +34,7 @@ struct Grid {
     long long n;          // fluid nodes
     int ntx, nty, ntz;    // tiles over fluid nodes
     int nt;
+    long long pp;         // population pitch: population i of node k is f[i * pp + k]
 };
 
 struct LBArgs {
@@ -61,7 +62,8 @@ struct MeshArgs {
 
 // Device buffers of one context (typed as void* where the precision varies).
 struct Dev {
-    void *f;              // [19][n] populations (deviation; FP16/BF16: deviation / w_i, scaled), AA layout
+    void *f;              // [19][pp] populations (deviation; FP16/BF16: deviation / w_i, scaled), AA
+                          // layout; entries n..pp-1 of each population are padding
     void *F;              // [3][n] IB force density of the step stamped in `stamp`
     void *Fext;           // [3][n] or null
     uint32_t *stamp;      // [nt] step+1 for which F of the tile is valid

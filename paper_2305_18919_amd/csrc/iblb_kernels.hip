@@ -232,7 +232,7 @@ __device__ __forceinline__ void load_pops(const S *__restrict__ f, const Grid &g
                                           typename Pop<S>::C *d)
 {
     const uint32_t me = (uint32_t)nidx(g, x, y, zf);
-    const uint32_t n = (uint32_t)g.n;
+    const uint32_t n = (uint32_t)g.pp;
     if (!SWAPPED) {
 #pragma unroll
         for (int i = 0; i < 19; ++i)
@@ -307,7 +307,7 @@ __device__ __forceinline__ void lb_collide(S *__restrict__ f, const T *__restric
             const T cuw = T(cx(i)) * T(uw[0]) + T(cy(i)) * T(uw[1]) + T(cz(i)) * T(uw[2]);
             post -= T(6) * w * rho * cuw;
         }
-        const uint32_t n32 = (uint32_t)n, me32 = (uint32_t)me;
+        const uint32_t n32 = (uint32_t)g.pp, me32 = (uint32_t)me;
         if (!ODD || !fluid)
             store_through(pop_at(f, opp(i) * n32 + me32), Pop<S>::put(post, i));
         else
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(256) void k_init(S *__restrict__ f, LBArgs a, int c
     for (int i = 0; i < 19; ++i) {
         const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
         const double w = wgt<double>(i);
-        f[i * g.n + me] = Pop<S>::put(T(w * a.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu)), i);
+        f[i * g.pp + me] = Pop<S>::put(T(w * a.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu)), i);
     }
 }
 
@@ -1475,13 +1475,13 @@ __global__ __launch_bounds__(256) void k_set_pops(S *__restrict__ f, int p, cons
             long long src;
             const bool ok = shifted(g, b, x, y, zf, i, -1, src);
             if (ok)
-                f[opp(i) * n + src] = Pop<S>::put(T(in[i * n + me]), i);
+                f[opp(i) * g.pp + src] = Pop<S>::put(T(in[i * n + me]), i);
             else
-                f[i * n + me] = Pop<S>::put(T(in[i * n + me]), i);
+                f[i * g.pp + me] = Pop<S>::put(T(in[i * n + me]), i);
         }
     } else {
         for (int i = 0; i < 19; ++i)
-            f[i * n + me] = Pop<S>::put(T(in[i * n + me]), i);
+            f[i * g.pp + me] = Pop<S>::put(T(in[i * n + me]), i);
     }
 }
 
