@@ -1705,6 +1705,8 @@ struct AdjState {
     double *grads = nullptr;           // [6]
     double *tpart = nullptr;           // per-block sums of the tau derivative
     double *vpart = nullptr;           // per-block shares of grad V . phib
+    double *serr = nullptr;            // the reverse sweep's error bits (one int): apart from the
+                                       // context's, which the checkpoint restores overwrite
 };
 
 namespace {
@@ -1799,7 +1801,7 @@ void free_sweep(AdjState *a)
             *p = nullptr;
         }
     for (double **p : {&a->lam_buf[0], &a->lam_buf[1], &a->qb_buf[0], &a->qb_buf[1], &a->Fb, &a->ub,
-                       &a->phib, &a->grads, &a->tpart, &a->vpart}) {
+                       &a->phib, &a->grads, &a->tpart, &a->vpart, &a->serr}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -1832,7 +1834,7 @@ int alloc_sweep(iblb_ctx *c, AdjState *a, size_t levels, int nrec)
     if (!get(&a->lam_buf[0], 19 * n) || !get(&a->lam_buf[1], 19 * n) || !get(&a->qb_buf[0], 3 * nv) ||
         !get(&a->qb_buf[1], 3 * nv) || !get(&a->Fb, 3 * n) || !get(&a->ub, 3 * n) || !get(&a->phib, 3 * nv) ||
         !get(&a->grads, 6) || !get(&a->tpart, (size_t)adj_lb_blocks((long long)n)) ||
-        !get(&a->vpart, (size_t)adj_vertex_blocks((long long)nv))) {
+        !get(&a->vpart, (size_t)adj_vertex_blocks((long long)nv)) || !get(&a->serr, 1)) {
         free_sweep(a);
         return fail(c, IBLB_E_DEVICE, "no device memory for the reverse sweep");
     }
@@ -1917,7 +1919,7 @@ hipError_t reverse_step(iblb_ctx *c, AdjState *a, const Recording &r, const AdjA
     L.inc4 = c->d.inc4;
     L.fref = c->d.fref;
     const AdjWork W{a->ub,    a->lam[1], a->lam[0], a->Fb,    a->phib,
-                    a->qb[1], a->qb[0],  a->grads,  a->tpart, a->vpart, c->d.err};
+                    a->qb[1], a->qb[0],  a->grads,  a->tpart, a->vpart, (int *)a->serr};
     const hipError_t e = adj_reverse_kept(A, a->es == 8, L, W, s);
     std::swap(a->lam[0], a->lam[1]);
     std::swap(a->qb[0], a->qb[1]);
@@ -2068,6 +2070,7 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     // derivative collects in per-block slots, added up below
     HIP_TRY(c, hipMemsetAsync(a->ub, 0, 3 * n * 8, c->stream));
     HIP_TRY(c, hipMemsetAsync(a->tpart, 0, (size_t)adj_lb_blocks((long long)n) * 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(a->serr, 0, 8, c->stream));
     if (a->every == 0) {
         for (int k = a->n - 1; k >= 0; --k) HIP_TRY(c, reverse_step(c, a, a->rec[0], A, k, c->stream));
     } else {
@@ -2084,7 +2087,15 @@ int iblb_adjoint_backward(iblb_ctx *c, const double *dJdq, double *grads, double
     HIP_TRY(c, hipMemcpyAsync(soa.data(), a->qb[1], 3 * nv * 8, hipMemcpyDeviceToHost, c->stream));
     std::vector<double> tp((size_t)adj_lb_blocks((long long)n));
     HIP_TRY(c, hipMemcpyAsync(tp.data(), a->tpart, tp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    int serr = 0;
+    HIP_TRY(c, hipMemcpyAsync(&serr, a->serr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (serr) {  // the sweep's errors join the context's
+        int e = 0;
+        HIP_TRY(c, hipMemcpy(&e, c->d.err, sizeof(int), hipMemcpyDeviceToHost));
+        e |= serr;
+        HIP_TRY(c, hipMemcpy(c->d.err, &e, sizeof(int), hipMemcpyHostToDevice));
+    }
     for (double v : tp) grads[5] += v;  // the tau derivative, by blocks
     if (dJdq0)
         for (size_t i = 0; i < nv; ++i)

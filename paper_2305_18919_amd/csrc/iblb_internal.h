@@ -187,7 +187,8 @@ struct AdjWork {
 
     double *tpart;  // [adj_lb_blocks(n)] per-block running sums of the tau derivative
     double *vpart;  // [adj_vertex_blocks(nv)] per-block shares of grad V . phib
-    int *err;         // the context's error bits (a tile list overflow)
+    int *err;         // the sweep's error bits (a tile list overflow), added to the context's
+                      // once the sweep is done
 };
 // Blocks of the LB adjoint over n nodes and of the 64-lanes-per-vertex
 // kernels over nv vertices (256 threads per block): the sizes of tpart, vpart.

@@ -54,11 +54,12 @@ class IBLBError(RuntimeError):
 _lib = None
 
 
-def _hip_runtimes() -> set:
-    """Paths of HIP runtime libraries mapped into this process."""
+def _hip_runtimes(maps: str = "/proc/self/maps") -> set:
+    """Paths of HIP runtime libraries mapped into this process (read from its
+    memory map, /proc/self/maps unless another file in that format is given)."""
     found = set()
     try:
-        with open("/proc/self/maps") as fh:
+        with open(maps) as fh:
             for line in fh:
                 path = line.split()[-1] if line.strip() else ""
                 if "libamdhip64.so" in path:

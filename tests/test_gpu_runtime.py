@@ -1,5 +1,7 @@
 """Execution modes, determinism, checkpoints, queries and error paths of the
 C ABI on the GPU."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -169,3 +171,27 @@ def test_active_nodes_are_the_stencil_tiles(case):
             g.step(1)
             n = g.active_nodes()
             assert 0 < n < dom.n_fluid and n == _stencil_tile_nodes(q, dom)
+
+
+def test_tile_list_overflow_is_reported():
+    """More than 512 vertices whose stencils reach one tile (a level-4
+    icosphere of radius 1, 2562 vertices, inside one 4^3 neighbourhood): the
+    spreading keeps the first 512 of the tile's list, raises the overflow bit
+    and the step reports IBLB_E_UNSTABLE naming it; nothing is written out of
+    bounds, so the fields stay finite."""
+    d = Domain(32, 32, 32, wall_mode=iblb.PERIODIC_ALL)
+    m = sphere_mesh(4, 1.0, (16.3, 16.2, 16.1), (1e-3, 0.0, 0.0))
+    assert m.n_vertices > 512
+    announce("tile list overflow")
+    with iblb.Simulation(d, m, precision=iblb.FP32_DEV) as g:
+        g.step(1)
+        with pytest.raises(iblb.IBLBError) as e:
+            g.sync()
+        assert e.value.code == iblb.IBLB_E_UNSTABLE
+        assert "tile list overflow" in str(e.value)
+        # the error stays raised; the fields are still copied out
+        rho, u = np.zeros(g.shape), np.zeros((3,) + g.shape)
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = iblb.lib().iblb_get_fields(g.h, rho.ctypes.data_as(dp), u.ctypes.data_as(dp))
+        assert rc == iblb.IBLB_E_UNSTABLE
+        assert np.isfinite(rho).all() and np.isfinite(u).all()
