@@ -12,7 +12,9 @@ query-time observables in numpy:
 * equilibrium contact angle from an algebraic least-squares sphere fit of the
   vertices away from the wall, and the paper's own measurement (appendix on the
   resolution test): a circle cut by the wall chord, fitted to a slice of the
-  mesh holding about (4 / 3^(1/4)) sqrt(pi N_f) nodes.
+  mesh holding about (4 / 3^(1/4)) sqrt(pi N_f) nodes;
+* the small-deformation theory of a particle in shear the paper compares its
+  shear runs with (Eqs. evJK, L_M, deformation_J), integrated in time.
 """
 from __future__ import annotations
 
@@ -346,3 +348,65 @@ def contact_angle_slice(q, faces, z_wall: float, exclude: float = 2.0, wall_hi: 
     theta = np.degrees(np.arccos(np.clip(-hc / R, -1.0, 1.0)))
     r = np.sqrt(max(0.0, R * R - hc * hc))
     return theta, r, hc + R, cen, R
+
+
+def shear_deformation_ode(a, t_end: float, n_steps: int, lam: float = 1.0, n_samples: int = 0):
+    """Small-deformation dynamics of a particle in simple shear (Interface
+    model section, Eqs. evJK and L_M), integrated by the classical fourth-order
+    Runge-Kutta method from a sphere at rest (J = K = 0).
+
+    Units: time in 1 / gammadot, lengths in the radius R; a = (a1, a2, a3) =
+    alpha_k / (mu R gammadot), i.e. alpha_k / (alpha Ca) with Ca = mu R
+    gammadot / alpha.  The shear flow is u = (z, 0, 0) (flow along x,
+    gradient along z): velocity gradient G_ij = du_i/dx_j, E = (G + G^T) / 2,
+    Omega = (G - G^T) / 2, and the Jaumann derivative D A / Dt = dA/dt -
+    (Omega A - A Omega).  J here is the deformation itself (the paper's J
+    times Ca), so Eq. deformation_J reads D = (J_xx^2 + J_xz^2)^(1/2); the
+    inclination is that of the principal axis of J's x-z block, measured from
+    x toward z.  Returns a dict with t, D and Theta at n_samples + 1 equally
+    spaced times (start and end included; the end alone if n_samples = 0) and
+    the final J and K."""
+    a1, a2, a3 = (float(v) for v in a)
+    G = np.zeros((3, 3))
+    G[0, 2] = 1.0
+    E = 0.5 * (G + G.T)
+    W = 0.5 * (G - G.T)
+    c_lam = 2.0 * lam + 3.0
+    c_m = 19.0 * lam + 16.0
+
+    def rates(J, K):
+        L = 4.0 * (a2 + a3) * J - (6.0 * a2 + 10.0 * a3) * K
+        M = -4.0 * (a1 + 2.0 * a2 + 2.0 * a3) * J + (12.0 * a2 + 16.0 * a3) * K
+        DK = 5.0 * E / c_lam + L / c_lam + M * (6.0 * lam + 4.0) / (c_lam * c_m)
+        DJ_K = 2.0 * M / c_m
+        # dA/dt = D A / Dt + (Omega A - A Omega), for K and for J = (J - K) + K
+        dK = DK + W @ K - K @ W
+        dJ = DJ_K + DK + W @ J - J @ W
+        return dJ, dK
+
+    def observe(J):
+        return np.hypot(J[0, 0], J[0, 2]), 0.5 * np.arctan2(2.0 * J[0, 2], J[0, 0] - J[2, 2])
+
+    dt = t_end / n_steps
+    every = n_steps // n_samples if n_samples else n_steps
+    J = np.zeros((3, 3))
+    K = np.zeros((3, 3))
+    ts, Ds, Ths = [], [], []
+    if n_samples:
+        ts.append(0.0)
+        Ds.append(0.0)
+        Ths.append(0.0)
+    for s in range(1, n_steps + 1):
+        k1 = rates(J, K)
+        k2 = rates(J + 0.5 * dt * k1[0], K + 0.5 * dt * k1[1])
+        k3 = rates(J + 0.5 * dt * k2[0], K + 0.5 * dt * k2[1])
+        k4 = rates(J + dt * k3[0], K + dt * k3[1])
+        J = J + dt / 6.0 * (k1[0] + 2.0 * k2[0] + 2.0 * k3[0] + k4[0])
+        K = K + dt / 6.0 * (k1[1] + 2.0 * k2[1] + 2.0 * k3[1] + k4[1])
+        if s % every == 0 or s == n_steps:
+            D, th = observe(J)
+            if not ts or ts[-1] < s * dt:
+                ts.append(s * dt)
+                Ds.append(D)
+                Ths.append(th)
+    return {"t": np.array(ts), "D": np.array(Ds), "Theta": np.array(Ths), "J": J, "K": K}
