@@ -382,15 +382,16 @@ def precision_study(steps: int):
 def shear_study(steps: int):
     """Steady deformation D and inclination Theta of a sheared particle at
     Ca = 0.01, 0.05, 0.1, 0.2 on the 64^3 shear domain (walls at -+0.01, R =
-    10, level-4 icosphere, Couette start), FP32 storage: a coated capsule
-    abar(1,1,1) against the small-deformation steady D of Eq. deformation
-    (35/48 Ca for equal alphas), and a pure droplet abar(1,0,0) against Eq.
+    10, level-4 icosphere, Couette start), FP32 storage: the four particles of
+    Table 1 with a strain modulus (rigidly and softly coated droplets,
+    non-pre-stressed and pure elastic capsules) against the small-deformation
+    steady D of Eq. deformation, and a pure droplet abar(1,0,0) against Eq.
     deformation_droplet (35/32 Ca at viscosity ratio 1) and Eq.
     inclination_angle (pi/4 - 35/32 Ca).  D and Theta come from the second
-    moments of the polyhedron, sampled 20 times per run.  The capsule's
-    last 4 samples are averaged.  The droplet runs an eighth of the steps and
-    is averaged over gammadot t in [0.5, 1]: its relaxation time at
-    viscosity ratio 1 is about 2.2 Ca / gammadot, while a mesh with tension
+    moments of the polyhedron, sampled 20 times per run; the last 4 samples
+    are averaged.  The droplet runs an eighth of the steps and is averaged
+    over gammadot t in [0.5, 1]: its relaxation time at viscosity ratio 1 is
+    about 2.2 Ca / gammadot, while a mesh with tension
     only (no alpha_2, alpha_3) has no resistance against the tangential drift
     of its vertices that tank-treading accumulates, and its shape creeps
     away from the plateau after about one shear time."""
@@ -398,7 +399,10 @@ def shear_study(steps: int):
     from paper_2305_18919_amd import iblb
     from paper_2305_18919_amd import inputs as I
     out = {"study": "shear deformation vs small-Ca theory", "workload": "shear64", "steps": steps, "cases": []}
-    for kind, shape, nsteps in (("capsule abar(1,1,1)", (1.0, 1.0, 1.0), steps),
+    for kind, shape, nsteps in (("rigidly coated droplet abar(1,1,1)", (1.0, 1.0, 1.0), steps),
+                                ("softly coated droplet abar(1,0,1)", (1.0, 0.0, 1.0), steps),
+                                ("non-pre-stressed capsule abar(0,1,1)", (0.0, 1.0, 1.0), steps),
+                                ("pure elastic capsule abar(0,0,1)", (0.0, 0.0, 1.0), steps),
                                 ("droplet abar(1,0,0)", (1.0, 0.0, 0.0), steps // 8)):
         for ca in (0.01, 0.05, 0.1, 0.2):
             w = I.c2_shear(ca)
@@ -421,7 +425,7 @@ def shear_study(steps: int):
                 out["cases"].append(case)
                 print(json.dumps(case), flush=True)
                 continue
-            if shape[1] > 0:
+            if shape[2] > 0:
                 window = trace[-4:]
             else:
                 window = [r for r in trace if 0.5 <= gdot * r[0] <= 1.0]
@@ -429,9 +433,12 @@ def shear_study(steps: int):
             D = sum(d for _, d, _ in window) / len(window)
             th = sum(t for _, _, t in window) / len(window)
             case.update({"D": D, "Theta": th, "D_trace": [round(d, 5) for _, d, _ in trace]})
-            if shape[1] > 0:
+            if shape[2] > 0:
+                # Eq. deformation with the moduli in units of abar and Ca = mu R
+                # gammadot / abar (the printed alpha_1 factor cancels, which
+                # also covers the non-pre-stressed particles)
                 a1, a2, a3 = shape
-                k = 5 * a1 * (3 * a2 + 4 * a3) / (4 * (3 * a1 * a2 + 5 * a1 * a3 + 2 * a2 * a3 + 2 * a3 * a3))
+                k = 5 * (3 * a2 + 4 * a3) / (4 * (3 * a1 * a2 + 5 * a1 * a3 + 2 * a2 * a3 + 2 * a3 * a3))
                 case["D_theory"] = k * ca
             else:
                 case["D_theory"] = 35.0 / 32.0 * ca
