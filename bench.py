@@ -449,21 +449,44 @@ def shear_study(steps: int):
     print(json.dumps(out), flush=True)
 
 
-def batch_study(steps: int, warmup: int):
+def sync_study(rounds: int = 2000):
+    """What ordering two whole-GPU phases costs: a kernel boundary (graph-
+    replayed launches) against a grid-wide barrier in one cooperative kernel,
+    for 256 to 2048 blocks of 256 threads (iblb_probe_phase_sync)."""
+    from paper_2305_18919_amd import iblb
+    out = {"study": "phase ordering: kernel boundary vs grid-wide barrier", "rounds": rounds, "cases": []}
+    for blocks in (256, 512, 1024, 2048):
+        try:
+            b, g = iblb.probe_phase_sync(blocks, rounds)
+            out["cases"].append({"blocks": blocks, "boundary_us": round(b, 3), "barrier_us": round(g, 3)})
+        except iblb.IBLBError as e:
+            out["cases"].append({"blocks": blocks, "error": str(e)})
+        print(json.dumps(out["cases"][-1]), flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def batch_study(steps: int, warmup: int, chunk: int = 500):
     """The 48-domain parameter sweep (cubic edges 32-80, one droplet each)
     stepped as one batch -- each step kernel launched once for all domains,
     launch shape from the library's autotuner -- against the same domains
-    stepped one context after another.  MLUPS count the fluid nodes of the
-    domains still stepped (members frozen by an instability before the timed
-    steps are left out of both rates).  step_roofline: LB bytes of those
-    domains per step (38 FP32 population accesses per node) over the batch's
-    time per step, against 8 TB/s."""
+    stepped one context after another.
+
+    The timed steps run in chunks of `chunk` with a check of every member's
+    error word before each chunk: a member that turned unstable is frozen
+    there (its garbage state can spread its vertices over the whole domain and
+    make every tile active, costing the batch far more than its own share),
+    so at most one chunk of its garbage is timed.  MLUPS count the fluid
+    nodes of the members stepped in each chunk.  The one-at-a-time leg steps
+    the members that stayed stable through the whole batch leg, each replaying
+    its own graphs, for the same number of steps.  step_roofline: LB bytes of
+    the stable members per step (38 FP32 population accesses per node) over
+    the batch's time per step of those members, against 8 TB/s."""
     import torch
     from paper_2305_18919_amd import iblb
     from paper_2305_18919_amd import inputs as I
     ws = I.batch_sweep()
     sims = [iblb.Simulation(w.domain, w.mesh, precision=1, graph=True) for w in ws]
-    out = {"study": "batched sweep", "domains": len(ws), "steps": steps, "warmup": warmup}
+    out = {"study": "batched sweep", "domains": len(ws), "steps": steps, "warmup": warmup, "check_every": chunk}
     with iblb.Batch(sims) as b:
         t0 = time.perf_counter()
         out["tune_ms_per_step"] = round(b.tune(32), 5)
@@ -471,31 +494,36 @@ def batch_study(steps: int, warmup: int):
         out["config"] = b.config
         b.step(warmup)
         status = b.check()
-        live = [k for k, st in enumerate(status) if st == iblb.IBLB_OK]
-        nodes = sum(ws[k].domain.n_fluid for k in live)
-        b.sync()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b.step(steps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        after = b.check()
-    ms = dt * 1e3 / steps
+        frozen_before = [k for k, st in enumerate(status) if st != iblb.IBLB_OK]
+        dt, node_steps, done, frozen_during = 0.0, 0, 0, []
+        while done < steps:
+            n = min(chunk, steps - done)
+            live = [k for k, st in enumerate(status) if st == iblb.IBLB_OK]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.step(n)
+            torch.cuda.synchronize()
+            dt += time.perf_counter() - t0
+            node_steps += n * sum(ws[k].domain.n_fluid for k in live)
+            done += n
+            status = b.check()
+            frozen_during += [ws[k].name + f" (by step {warmup + done})" for k in live if status[k] != iblb.IBLB_OK]
+    stable = [k for k, st in enumerate(status) if st == iblb.IBLB_OK]
+    nodes = sum(ws[k].domain.n_fluid for k in stable)
+    mlups = node_steps / dt / 1e6
+    ms = nodes / (mlups * 1e6) * 1e3  # batch time per step of the stable members
     out.update({
-        "frozen_before_timing": [ws[k].name for k, st in enumerate(status) if st != iblb.IBLB_OK],
-        "frozen_during_timing": [ws[k].name for k in live if after[k] != iblb.IBLB_OK],
-        "fluid_nodes": nodes, "vertices": sum(ws[k].mesh.n_vertices for k in live),
-        "batch": {"ms_per_step": round(ms, 5), "mlups": round(nodes * steps / dt / 1e6, 1)},
+        "frozen_before_timing": [ws[k].name for k in frozen_before],
+        "frozen_during_timing": frozen_during,
+        "stable_members": len(stable), "fluid_nodes": nodes, "vertices": sum(ws[k].mesh.n_vertices for k in stable),
+        "batch": {"ms_per_step": round(ms, 5), "mlups": round(mlups, 1)},
     })
     alg = nodes * lb_bytes_per_node(1)
     out["step_roofline"] = {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                             "alg_bytes_per_step": alg}
-    # the same domains stepped one context at a time (each replaying its own
-    # graphs); a member that turns unstable still costs its launches in both
-    # legs, so the device is synchronised without reading its error word
     seq = 0.0
-    for k in live:
+    for k in stable:
         s = sims[k]
         s.step(32)
         torch.cuda.synchronize()
@@ -503,8 +531,9 @@ def batch_study(steps: int, warmup: int):
         s.step(steps)
         torch.cuda.synchronize()
         seq += time.perf_counter() - t0
-    out["one_at_a_time"] = {"ms_per_step": round(seq * 1e3 / steps, 5), "mlups": round(nodes * steps / seq / 1e6, 1)}
-    out["speedup"] = round(seq / dt, 2)
+    seq_mlups = nodes * steps / seq / 1e6
+    out["one_at_a_time"] = {"ms_per_step": round(seq * 1e3 / steps, 5), "mlups": round(seq_mlups, 1)}
+    out["speedup"] = round(mlups / seq_mlups, 2)
     for s in sims:
         s.close()
     print(json.dumps(out), flush=True)
@@ -762,12 +791,13 @@ def main():
     ap.add_argument("--pass", dest="only", choices=["lb", "copy", "step"], default=None)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--study", choices=["precision", "precision64", "shear", "batch", "adjoint", "wetting",
-                                        "spreading"], default=None,
+                                        "spreading", "sync"], default=None,
                     help="precision: contact angle of the 128x128x96 wetting droplet per population storage; "
                          "precision64: the same on the 64x64x48 wetting case, near equilibrium; "
                          "shear: steady D and Theta against the small-Ca theory; "
                          "wetting: equilibrium contact angle against eps/abar for the five models; "
-                         "spreading: contact radius against time (Eq. tanner_law)")
+                         "spreading: contact radius against time (Eq. tanner_law); "
+                         "sync: kernel boundary against grid-wide barrier")
     ap.add_argument("--study-steps", type=int, default=50000)
     ap.add_argument("--precision", choices=sorted(PRECISIONS), default=None,
                     help="population storage (default: the workload's, FP32 for the benchmark workloads)")
@@ -789,7 +819,8 @@ def main():
                "adjoint": lambda: adjoint_study(100),
                "wetting": lambda: wetting_study(args.study_steps),
                "precision64": lambda: precision64_study(args.study_steps),
-               "spreading": lambda: spreading_study(args.study_steps)}
+               "spreading": lambda: spreading_study(args.study_steps),
+               "sync": lambda: sync_study()}
     if args.study is not None:
         studies[args.study]()
         return

@@ -190,6 +190,19 @@ int iblb_get_fields(iblb_ctx *ctx, double *rho, double *u);
 #define IBLB_NOALLOC_MAX_NODES 2097152
 int iblb_get_fields_noalloc(iblb_ctx *ctx, double *rho, double *u);
 
+/* The cost of ordering two phases of a step across the whole GPU, two ways:
+ * `rounds` back-to-back launches of a kernel of `blocks` 256-thread blocks,
+ * replayed from a captured graph (kernel boundaries), against one
+ * cooperative kernel of `blocks` blocks passing `rounds` grid-wide barriers
+ * (an atomic arrival count and generation).  Each block writes one word per
+ * phase in both.  Outputs: microseconds per boundary and per barrier, the
+ * median of 5 repetitions.  This is the measurement behind the batched
+ * step's dispatch-per-phase design.  Allocates its own stream and buffer.
+ * IBLB_E_INVAL for rounds outside [1, 100000], or blocks beyond what the GPU
+ * holds at once; IBLB_E_UNSTABLE if a barrier wait gave up (the kernel ends
+ * in any case); IBLB_E_DEVICE for runtime errors. */
+int iblb_probe_phase_sync(int32_t blocks, int32_t rounds, double *boundary_us, double *barrier_us);
+
 /* Debug / validation calls. */
 /* Fixed external force density [3][N] added every step; only without a mesh. */
 int iblb_debug_set_force(iblb_ctx *ctx, const double *F);
@@ -289,7 +302,9 @@ typedef struct {
 int iblb_batch_create(iblb_ctx *const *members, int32_t n, void *hip_stream, iblb_batch **out);
 /* n_steps steps of every member that is not frozen (asynchronous; replays a
  * captured hipGraph of 16 steps from even times).  Each member's step count
- * advances by n_steps. */
+ * advances by n_steps.  A member whose device error bits are set stops at
+ * once: its blocks return without work until iblb_batch_check freezes it, so
+ * the garbage state of an unstable member costs the others nothing. */
 int iblb_batch_step(iblb_batch *b, int32_t n_steps);
 int iblb_batch_sync(iblb_batch *b);
 /* Synchronises, reads every member's device error bits and freezes each

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libiblb.so")
 SOURCES = [os.path.join(HERE, "csrc", "iblb_kernels.hip"), os.path.join(HERE, "csrc", "iblb_adjoint.hip"),
-           os.path.join(HERE, "csrc", "iblb_noalloc.hip"), os.path.join(HERE, "csrc", "iblb_api.cpp")]
+           os.path.join(HERE, "csrc", "iblb_noalloc.hip"), os.path.join(HERE, "csrc", "iblb_probe.hip"),
+           os.path.join(HERE, "csrc", "iblb_api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1291,6 +1291,8 @@ __global__ __launch_bounds__(256) void kb_forces(const DomRec *__restrict__ R, c
     const uint32_t e = tab[blockIdx.x];
     const DomRec &r = R[e & 0xffu];
     const Dev &d = r.d;
+    if (*d.err != 0)
+        return;  // the member turned unstable: its blocks stop until the check freezes it
     forces_dispatch<S, P, T>((int)(e >> 8), d.q, d.Xref, d.inc4, d.fref, (T *)d.phiSW, (T *)d.gV, d.base,
                              (T *)d.wts, d.partials, d.act, d.acnt, d.alist, d.ctr, (S *)d.f, (const T *)d.Fext,
                              d.err, r.a, r.m, r.bxw, r.nbx, r.nby);
@@ -1302,6 +1304,8 @@ __global__ __launch_bounds__(256, kSpreadOccupancy<S>) void kb_spread(const DomR
     const uint32_t e = tab[blockIdx.x];
     const DomRec &r = R[e & 0xffu];
     const Dev &d = r.d;
+    if (*d.err != 0)
+        return;  // the member turned unstable: its blocks stop until the check freezes it
     spread_dispatch<S, P, T>((int)(e >> 8), d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV,
                              d.partials, d.ctr, d.mask, d.acnt, d.alist, (T *)d.F, d.stamp, (S *)d.f,
                              (const T *)d.Fext, d.err, r.a, r.m, d.act, r.nsp, r.lb0, r.bxw, r.nbx, r.nby);
@@ -1313,6 +1317,8 @@ __global__ __launch_bounds__(256) void kb_moments(const DomRec *__restrict__ R, 
     const uint32_t e = tab[blockIdx.x];
     const DomRec &r = R[e & 0xffu];
     const Dev &d = r.d;
+    if (*d.err != 0)
+        return;  // the member turned unstable: its blocks stop until the check freezes it
     moments_dispatch<S, P, T>((int)(e >> 8), r.mblocks, (const S *)d.f, (const T *)d.F, (const T *)d.Fext, d.acnt,
                               d.alist, (T *)d.U, r.a);
 }
@@ -1323,6 +1329,8 @@ __global__ __launch_bounds__(256) void kb_move(const DomRec *__restrict__ R, con
     const uint32_t e = tab[blockIdx.x];
     const DomRec &r = R[e & 0xffu];
     const Dev &d = r.d;
+    if (*d.err != 0)
+        return;  // the member turned unstable: its blocks stop until the check freezes it
     move_dispatch<T, P, VPW>((int)(e >> 8), d.q, (const T *)d.U, d.stamp, d.ctr, d.acnt, d.act, d.mask, d.err, r.a,
                              r.m);
 }

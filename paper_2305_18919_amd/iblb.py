@@ -106,6 +106,7 @@ def lib():
             "iblb_contact_angle": [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp, _dp],
             "iblb_get_fields": [_vp, _dp, _dp],
             "iblb_get_fields_noalloc": [_vp, _dp, _dp],
+            "iblb_probe_phase_sync": [C.c_int32, C.c_int32, _dp, _dp],
             "iblb_debug_set_force": [_vp, _dp],
             "iblb_debug_get_force": [_vp, _dp],
             "iblb_debug_get_populations": [_vp, _dp],
@@ -505,3 +506,13 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+def probe_phase_sync(blocks: int, rounds: int = 1000):
+    """Microseconds per kernel boundary and per grid-wide barrier between two
+    phases of `blocks` blocks (iblb_probe_phase_sync)."""
+    b, g = C.c_double(), C.c_double()
+    rc = lib().iblb_probe_phase_sync(int(blocks), int(rounds), C.byref(b), C.byref(g))
+    if rc != IBLB_OK:
+        raise IBLBError(rc, "iblb_probe_phase_sync failed")
+    return b.value, g.value

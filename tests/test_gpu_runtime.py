@@ -195,3 +195,17 @@ def test_tile_list_overflow_is_reported():
         rc = iblb.lib().iblb_get_fields(g.h, rho.ctypes.data_as(dp), u.ctypes.data_as(dp))
         assert rc == iblb.IBLB_E_UNSTABLE
         assert np.isfinite(rho).all() and np.isfinite(u).all()
+
+
+def test_phase_sync_probe():
+    """Both orderings run and pass every phase (the probe checks that the
+    barrier's generation count reached the number of rounds); sizes it
+    cannot hold at once are refused."""
+    for blocks in (256, 1024):
+        announce(f"phase sync probe blocks={blocks}")
+        b, g = iblb.probe_phase_sync(blocks, 200)
+        announce(f"  boundary {b:.3f} us, barrier {g:.3f} us")
+        assert 0.0 < b < 1e3 and 0.0 < g < 1e3
+    x, y = ctypes.c_double(), ctypes.c_double()
+    assert iblb.lib().iblb_probe_phase_sync(1 << 24, 10, ctypes.byref(x), ctypes.byref(y)) == iblb.IBLB_E_INVAL
+    assert iblb.lib().iblb_probe_phase_sync(256, 0, ctypes.byref(x), ctypes.byref(y)) == iblb.IBLB_E_INVAL
