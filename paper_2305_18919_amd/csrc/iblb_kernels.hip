@@ -328,16 +328,18 @@ __device__ __forceinline__ void lb_node(S *__restrict__ f, const T *__restrict__
 // LB of one node of the LB tiling (blocks of bxw x (256 / bxw) nodes in one
 // z layer, numbered x fastest), unless its tile is active at step t (those
 // nodes are updated by the spreading, with their force).
-template <typename S, bool ODD, typename T = typename Pop<S>::C>
+// A block of NT < 256 threads runs part `sub` of the 256-node LB block b (its
+// consecutive rows NT / bxw at a time).
+template <typename S, bool ODD, int NT = 256, typename T = typename Pop<S>::C>
 __device__ __forceinline__ void bulk_lb_block(int b, S *__restrict__ f, const T *__restrict__ Fext,
                                               const uint8_t *__restrict__ act, uint32_t t, int *err, const LBArgs &a,
-                                              int bxw, int nbx, int nby)
+                                              int bxw, int nbx, int nby, int sub = 0)
 {
     const int zf = b / (nbx * nby);
     const int rem = b - zf * nbx * nby;
     const int byi = rem / nbx, bxi = rem - byi * nbx;
     const int x = bxi * bxw + (int)(threadIdx.x % (unsigned)bxw);
-    const int y = byi * (256 / bxw) + (int)(threadIdx.x / (unsigned)bxw);
+    const int y = byi * (256 / bxw) + sub * (NT / bxw) + (int)(threadIdx.x / (unsigned)bxw);
     if (x >= a.g.nx || y >= a.g.ny)
         return;
     if (act[tile_of(a.g, x, y, zf)] == act_stamp(t))
@@ -850,8 +852,11 @@ __device__ __forceinline__ void stage_store(const Staged<T> &s, int e, T kf, T *
 constexpr int kStageChunk = 128;
 // Spreading blocks per CU the register budget aims at: three with FP32
 // arithmetic; FP64 needs the whole register file of one.
+// Wavefronts per SIMD the spreading's register budget aims at (the second
+// launch bound): three with FP32 arithmetic; FP64 needs the whole register
+// file of one.
 template <typename S>
-constexpr int kSpreadOccupancy = sizeof(typename Pop<S>::C) == 8 ? 1 : 3;
+constexpr int kSpreadWaves = sizeof(typename Pop<S>::C) == 8 ? 1 : 3;
 
 // Blocks [0, nsp) spread: one 256-thread block (four wavefronts) per active
 // tile, striding over the list.  Blocks from nsp on (if any) run the LB of the
@@ -872,7 +877,7 @@ constexpr int kSpreadOccupancy = sizeof(typename Pop<S>::C) == 8 ? 1 : 3;
 // wavefront order, so every node's sum has a fixed order.  Wavefront 0
 // finishes with the LB update of the tile's nodes, whose populations it
 // fetched with the first pass.
-template <typename S, int P, typename T = typename Pop<S>::C>
+template <typename S, int P, int NW, typename T = typename Pop<S>::C>
 __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
                                                 const double *__restrict__ partials, const uint32_t *__restrict__ ctr,
@@ -883,21 +888,25 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
                                                 const uint8_t *__restrict__ act, int nsp, int lb0, int bxw, int nbx,
                                                 int nby)
 {
+    constexpr int NT = 64 * NW;  // threads per block
+    constexpr int NSUB = 256 / NT;
+    static_assert(NW == 2 || NW == 4, "two or four wavefronts per block");
     const Grid &g = a.g;
     if (blk >= nsp) {
-        bulk_lb_block<S, P == 1>(lb0 + blk - nsp, f, Fext, act, ctr[P], err, a, bxw, nbx, nby);
+        const int j = blk - nsp;
+        bulk_lb_block<S, P == 1, NT>(lb0 + j / NSUB, f, Fext, act, ctr[P], err, a, bxw, nbx, nby, j % NSUB);
         return;
     }
     __shared__ int sid[kStageChunk];
     __shared__ __align__(16) T sw[kStageChunk * 12];
     __shared__ __align__(16) T sph[kStageChunk * 4];
-    __shared__ T part[3][3][64];
+    __shared__ T part[NW - 1][3][64];
     __shared__ T spop[19][64];  // wavefront 0's prefetched populations
-    __shared__ int swt[4];
+    __shared__ int swt[NW];
     __shared__ T skfac;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nv = m.nv, W = m.nwords;
-    const int J = (W + 255) >> 8;  // words per thread, at most 4
+    const int J = (W + NT - 1) / NT;  // words per thread, at most 4 (the launch keeps W <= 4 NT)
     // the count of active tiles and the block's first tile are read together
     // (block index < nsp <= tile count, so the slot exists); the volatile
     // read keeps the compiler from deferring it past the test on the count
@@ -943,7 +952,10 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             wn[j] = (an < na && j < J && w0 + j < W) ? mask[(long long)next * W + w0 + j] : 0ull;
-        int nent = swt[0] + swt[1] + swt[2] + swt[3];
+        int nent = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            nent += swt[w];
         if (nent > kTileCap) {
             if (tid == 0)
                 atomicOr(err, kErrOverflow);
@@ -977,7 +989,7 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
                 o += nb;
             }
         };
-        static_assert(kStageChunk <= 256, "one staged entry per thread and pass");
+        static_assert(kStageChunk <= NT, "one staged entry per thread and pass");
         auto stage = [&](int cn) {
             if (tid < cn) {
                 const Staged<T> st = stage_load<T>(sid[tid], base, wts, phiSW, gV, nv, err, g, x0, y0, z0);
@@ -985,8 +997,8 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
             }
         };
         auto accumulate = [&](int cn) {
-            const int q4 = (cn + 3) >> 2;
-            const int e0 = wave * q4, e1 = min(cn, e0 + q4);
+            const int qw = (cn + NW - 1) / NW;
+            const int e0 = wave * qw, e1 = min(cn, e0 + qw);
 #pragma unroll 8
             for (int e = e0; e < e1; ++e) {
                 const T w = sw[e * 12 + lx] * sw[e * 12 + 4 + ly] * sw[e * 12 + 8 + lz];
@@ -1039,7 +1051,7 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
         // LDS is not written again before every wavefront has passed the next
         // iteration's first barrier, which wavefront 0 reaches only after this
         if (wave == 0) {
-            for (int w = 0; w < 3; ++w) {
+            for (int w = 0; w < NW - 1; ++w) {
                 Fx += part[w][0][lane];
                 Fy += part[w][1][lane];
                 Fz += part[w][2][lane];
@@ -1066,8 +1078,8 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
     }
 }
 
-template <typename S, int P, typename T = typename Pop<S>::C>
-__global__ __launch_bounds__(256, kSpreadOccupancy<S>) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
+template <typename S, int P, int NW, typename T = typename Pop<S>::C>
+__global__ __launch_bounds__(64 * NW, kSpreadWaves<S>) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
                                                 const double *__restrict__ partials, const uint32_t *__restrict__ ctr,
                                                 uint64_t *__restrict__ mask, const uint32_t *__restrict__ acnt,
@@ -1077,8 +1089,8 @@ __global__ __launch_bounds__(256, kSpreadOccupancy<S>) void k_spread(const Base 
                                                 const uint8_t *__restrict__ act, int nsp, int lb0, int bxw, int nbx,
                                                 int nby)
 {
-    spread_dispatch<S, P, T>((int)blockIdx.x, base, wts, phiSW, gV, partials, ctr, mask, acnt, alist, F, stamp, f,
-                             Fext, err, a, m, act, nsp, lb0, bxw, nbx, nby);
+    spread_dispatch<S, P, NW, T>((int)blockIdx.x, base, wts, phiSW, gV, partials, ctr, mask, acnt, alist, F, stamp,
+                                 f, Fext, err, a, m, act, nsp, lb0, bxw, nbx, nby);
 }
 
 // u(t+1) = (sum c f(t+1) + F(t)/2) / rho(t+1) once per node of the active
@@ -1299,14 +1311,14 @@ __global__ __launch_bounds__(256) void kb_forces(const DomRec *__restrict__ R, c
 }
 
 template <typename S, int P, typename T = typename Pop<S>::C>
-__global__ __launch_bounds__(256, kSpreadOccupancy<S>) void kb_spread(const DomRec *__restrict__ R, const uint32_t *__restrict__ tab)
+__global__ __launch_bounds__(256, kSpreadWaves<S>) void kb_spread(const DomRec *__restrict__ R, const uint32_t *__restrict__ tab)
 {
     const uint32_t e = tab[blockIdx.x];
     const DomRec &r = R[e & 0xffu];
     const Dev &d = r.d;
     if (*d.err != 0)
         return;  // the member turned unstable: its blocks stop until the check freezes it
-    spread_dispatch<S, P, T>((int)(e >> 8), d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV,
+    spread_dispatch<S, P, 4, T>((int)(e >> 8), d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV,
                              d.partials, d.ctr, d.mask, d.acnt, d.alist, (T *)d.F, d.stamp, (S *)d.f,
                              (const T *)d.Fext, d.err, r.a, r.m, d.act, r.nsp, r.lb0, r.bxw, r.nbx, r.nby);
 }
@@ -1854,44 +1866,55 @@ hipError_t launch_forces(int prec, const Dev &d, const LBArgs &a, const MeshArgs
     });
 }
 
-// Spreading blocks one CU holds at once (limited by registers and LDS).
-template <typename S, int P>
+// Spreading blocks of NW wavefronts one CU holds at once (limited by
+// registers and LDS).
+template <typename S, int P, int NW>
 static int spread_blocks_per_cu()
 {
     using T = typename Pop<S>::C;
     static int n = 0;
     if (n == 0) {
         int k = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, k_spread<S, P, T>, 256, 0) != hipSuccess || k < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, k_spread<S, P, NW, T>, 64 * NW, 0) != hipSuccess ||
+            k < 1)
             k = 1;
         n = k;
     }
     return n;
 }
 
-template <typename S, int P>
-static void spread_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int nsp, int with_lb, hipStream_t s)
+// The spreading dispatch with blocks of NW wavefronts: as many spreading
+// blocks as the CUs hold at once, striding over the active tiles (one each
+// while the list is no longer than that), then the LB blocks from lb0 on,
+// each 256-node LB block split over 4 / NW blocks.
+template <typename S, int P, int NW>
+static void spread_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int with_lb, hipStream_t s)
 {
     using T = typename Pop<S>::C;
     const dim3 bl = lb_block(a.g), gr = lb_grid(a.g);
+    const int fit = d.num_cus * spread_blocks_per_cu<S, P, NW>();
+    const int nsp = a.g.nt < fit ? a.g.nt : fit;
     const int lb0 = lb_blocks_with_forces(a.g);
-    const int nlb = with_lb ? (int)(gr.x * gr.y * gr.z) - lb0 : 0;
-    k_spread<S, P><<<nsp + nlb, 256, 0, s>>>(d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV,
-                                             d.partials, d.ctr, d.mask, d.acnt, d.alist, (T *)d.F, d.stamp,
-                                             (S *)d.f, (const T *)d.Fext, d.err, a, m, d.act, nsp, lb0, (int)bl.x,
-                                             (int)gr.x, (int)gr.y);
+    const int nlb = with_lb ? ((int)(gr.x * gr.y * gr.z) - lb0) * (4 / NW) : 0;
+    k_spread<S, P, NW><<<nsp + nlb, 64 * NW, 0, s>>>(d.base, (const T *)d.wts, (const T *)d.phiSW,
+                                                     (const T *)d.gV, d.partials, d.ctr, d.mask, d.acnt, d.alist,
+                                                     (T *)d.F, d.stamp, (S *)d.f, (const T *)d.Fext, d.err, a, m,
+                                                     d.act, nsp, lb0, (int)bl.x, (int)gr.x, (int)gr.y);
 }
 
 hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, int with_lb,
                          hipStream_t s)
 {
-    // spreading blocks: as many as the CUs hold at once, striding over the
-    // active tiles
+    // two-wavefront blocks (twice as many resident, so that each active tile
+    // of a large mesh gets a block of its own) while a tile's vertex mask fits
+    // four words per thread of them; four-wavefront blocks beyond that
+    const bool two = m.nwords <= 4 * 128;
     return with_pop_type(prec, [&](auto tag) {
         using S = decltype(tag);
-        const int fit = d.num_cus * (p ? spread_blocks_per_cu<S, 1>() : spread_blocks_per_cu<S, 0>());
-        const int nsp = a.g.nt < fit ? a.g.nt : fit;
-        p ? spread_launch<S, 1>(d, a, m, nsp, with_lb, s) : spread_launch<S, 0>(d, a, m, nsp, with_lb, s);
+        if (two)
+            p ? spread_launch<S, 1, 2>(d, a, m, with_lb, s) : spread_launch<S, 0, 2>(d, a, m, with_lb, s);
+        else
+            p ? spread_launch<S, 1, 4>(d, a, m, with_lb, s) : spread_launch<S, 0, 4>(d, a, m, with_lb, s);
     });
 }
 
