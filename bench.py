@@ -95,15 +95,20 @@ def lb_bytes_per_node(precision: int) -> int:
 
 # ----------------------------------------------------------------- host bookkeeping
 
-def step_geometry(dom, q, split: dict) -> dict:
+def step_geometry(dom, q, split: dict, tile=None) -> dict:
     """Node counts behind the algorithmic bytes of one step at positions q.
 
     shell: fluid nodes inside some vertex's 4^3 stencil; active: nodes of the
-    4^3 tiles those stencils reach (the spreading dispatch updates them).  Per
+    tiles (extents `tile`, the library's by default) those stencils reach (the
+    spreading dispatch updates them).  Per
     dispatch, the LB nodes it updates: the LB blocks of the other nodes (block
     width and forces share of the library's split) go first to the forces
     dispatch, the rest to the spreading dispatch."""
     import numpy as np
+    if tile is None:
+        from paper_2305_18919_amd import iblb
+        tile = iblb.tile_shape()
+    tx, ty, tz = tile
     nx, ny, nzf = dom.nx, dom.ny, dom.nz_fluid
     walls = dom.wall_mode == 0
     b = np.floor(q).astype(np.int64) - 1
@@ -119,11 +124,11 @@ def step_geometry(dom, q, split: dict) -> dict:
     ok = (Z >= 0) & (Z < nzf)
     shell = np.zeros((nzf, ny, nx), dtype=bool)
     shell[Z[ok], Y[ok], X[ok]] = True
-    ntz, nty, ntx = (nzf + 3) // 4, (ny + 3) // 4, (nx + 3) // 4
+    ntz, nty, ntx = -(-nzf // tz), -(-ny // ty), -(-nx // tx)
     tiles = np.zeros((ntz, nty, ntx), dtype=bool)
-    tiles[Z[ok] >> 2, Y[ok] >> 2, X[ok] >> 2] = True
-    act = tiles[(np.arange(nzf) >> 2)[:, None, None], (np.arange(ny) >> 2)[None, :, None],
-                (np.arange(nx) >> 2)[None, None, :]]
+    tiles[Z[ok] // tz, Y[ok] // ty, X[ok] // tx] = True
+    act = tiles[(np.arange(nzf) // tz)[:, None, None], (np.arange(ny) // ty)[None, :, None],
+                (np.arange(nx) // tx)[None, None, :]]
     bxw = split["block_x"]
     byw = 256 // bxw
     nbx, nby = (nx + bxw - 1) // bxw, (ny + byw - 1) // byw

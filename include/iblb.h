@@ -123,8 +123,9 @@ int iblb_create(const iblb_domain_desc *dom, void *dev_workspace, size_t workspa
  * evaluated face by face, expanded exactly in the displacements from
  * ref_vertices.  *mesh_id = 0.  Fails with IBLB_E_STATE if a mesh exists or a
  * debug force field is set, IBLB_E_INVAL above 65536 vertices (the spreading
- * keeps one bit per vertex for every 4x4x4 tile of the lattice:
- * tiles x ceil(n_vertices / 64) x 8 bytes of device memory). */
+ * keeps one bit per vertex for every tile of the lattice, see
+ * iblb_tile_shape: tiles x ceil(n_vertices / 64) x 8 bytes of device
+ * memory). */
 int iblb_add_mesh(iblb_ctx *ctx, const iblb_mesh_desc *mesh, int32_t *mesh_id);
 
 /* Enqueue n_steps full IB-LB steps on the context stream; returns without
@@ -245,11 +246,18 @@ int iblb_get_lb_split(const iblb_ctx *ctx, int32_t *block_x, double *share_force
 int iblb_kernel_time(iblb_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 int iblb_reset_timing(iblb_ctx *ctx);
 
-/* Fluid nodes in the active tiles of the last completed step, the 4x4x4
- * tiles reached by some vertex stencil (their LB runs with the spreading, the
- * "lb" kernel updates the rest); 0 without a mesh or before the first step.
- * Synchronises. */
+/* Fluid nodes in the active tiles of the last completed step, the tiles
+ * reached by some vertex's 4^3 stencil (Eq. ibm-interpolation_stencil; their LB
+ * runs with the spreading, the "lb" kernel updates the rest); 0 without a mesh
+ * or before the first step.  Synchronises. */
 int iblb_active_nodes(iblb_ctx *ctx, int64_t *n);
+
+/* Extents in fluid nodes along x, y and z of the tiles the lattice is cut
+ * into for the spreading (product 64, one wavefront's lanes; tile (i, j, k)
+ * holds the nodes x in [i tx, (i + 1) tx), y and z likewise, z counted in
+ * fluid layers; tiles at the lattice's far faces are partial).  Any pointer
+ * may be null; never fails. */
+void iblb_tile_shape(int32_t *tx, int32_t *ty, int32_t *tz);
 
 const char *iblb_last_error(const iblb_ctx *ctx);
 int iblb_destroy(iblb_ctx *ctx);
@@ -347,7 +355,8 @@ int iblb_batch_destroy(iblb_batch *b);
  *    density, velocity), 6 x n_vertices values (nodal force parts, dV/dq),
  *    3 x n_vertices + 1 doubles (positions, V - V0), and the step's tile
  *    vertex masks and active-tile list (tiles x (8 ceil(n_vertices / 64) + 4)
- *    bytes, tiles = ceil(nx/4) ceil(ny/4) ceil(N / (nx ny) / 4)); the sweep
+ *    bytes, tiles = ceil(nx/tx) ceil(ny/ty) ceil(N / (nx ny) / tz) with the
+ *    extents of iblb_tile_shape); the sweep
  *    then recomputes nothing.  Its adjoint populations are stored in the same
  *    precision.
  *  every > 0: a device copy of the whole context state every `every` steps;

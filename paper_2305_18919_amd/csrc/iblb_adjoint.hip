@@ -592,7 +592,7 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
     const long long n = g.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     __shared__ int sid[kTileCap];
-    __shared__ P sw[kTileCap * 12];      // per listed vertex: its weights at the tile's 4 x, 4 y, 4 z positions
+    __shared__ P sw[kTileCap * kTileW];  // per listed vertex: its weights at the tile's x, y and z coordinates
     __shared__ double sqb[kTileCap * 3];  // and qb1
     __shared__ double sq[kTileCap * 3];   // and q
     __shared__ int swt[4];
@@ -610,8 +610,8 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
         const int tz = tile / (g.ntx * g.nty);
         const int rem = tile - tz * g.ntx * g.nty;
         const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
-        const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
-        const int x = tx * 4 + lx, y = ty * 4 + ly, zf = tz * 4 + lz;
+        const int lx = lane & (kTileX - 1), ly = (lane >> kTileLX) & (kTileY - 1), lz = lane >> (kTileLX + kTileLY);
+        const int x = (tx << kTileLX) + lx, y = (ty << kTileLY) + ly, zf = (tz << kTileLZ) + lz;
         const bool node = wave == 0 && x < g.nx && y < g.ny && zf < g.nzf;
         const long long id = ((long long)zf * g.ny + y) * g.nx + x;
         const int w0 = tid * J;
@@ -646,7 +646,8 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
         if (tot > kTileCap && tid == 0)
             atomicOr(err, kErrOverflow);
         __syncthreads();
-        const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 4 + g.zoff;  // lattice coordinates of the tile's first node
+        // lattice coordinates of the tile's first node
+        const int x0 = tx << kTileLX, y0 = ty << kTileLY, z0 = (tz << kTileLZ) + g.zoff;
         // the listed vertices' positions and qb1, all loads in flight together
         for (int e = tid; e < nent; e += 256) {
             const int v = sid[e] < nv ? sid[e] : 0;  // (marks name vertices below nv only)
@@ -663,10 +664,12 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
             }
         }
         __syncthreads();
-        // their 1D weights at the tile's 4 x, 4 y and 4 z positions, one per
-        // thread (12 per vertex), so that the evaluations run side by side
-        for (int it = tid; it < nent * 12; it += 256) {
-            const int e = it / 12, r = it - e * 12, ax = r >> 2, l = r & 3;
+        // their 1D weights at the tile's x, y and z coordinates, one per
+        // thread (kTileW per vertex), so that the evaluations run side by side
+        for (int it = tid; it < nent * kTileW; it += 256) {
+            const int e = it / kTileW, r = it - e * kTileW;
+            const int ax = r < kTileX ? 0 : (r < kTileX + kTileY ? 1 : 2);
+            const int l = r - (ax == 0 ? 0 : (ax == 1 ? kTileX : kTileX + kTileY));
             const double qa = sq[e * 3 + ax];
             const int b = (int)floor(qa) - 1;
             // offset of the tile's node in the vertex's stencil (0..3 inside)
@@ -695,7 +698,8 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
         const int e0 = wave * chunk, e1 = min(nent, e0 + chunk);
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int e = e0; e < e1; ++e) {
-            const double w = double(sw[e * 12 + lx]) * double(sw[e * 12 + 4 + ly]) * double(sw[e * 12 + 8 + lz]);
+            const double w = double(sw[e * kTileW + lx]) * double(sw[e * kTileW + kTileX + ly]) *
+                             double(sw[e * kTileW + kTileX + kTileY + lz]);
             s0 += sqb[e * 3] * w;
             s1 += sqb[e * 3 + 1] * w;
             s2 += sqb[e * 3 + 2] * w;

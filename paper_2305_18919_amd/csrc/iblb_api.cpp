@@ -61,9 +61,9 @@ Grid make_grid(const iblb_domain_desc &d)
     g.zoff = g.walls;
     g.nzf = g.walls ? d.nz - 2 : d.nz;
     g.n = (long long)g.nx * g.ny * g.nzf;
-    g.ntx = (g.nx + 3) / 4;
-    g.nty = (g.ny + 3) / 4;
-    g.ntz = (g.nzf + 3) / 4;
+    g.ntx = (g.nx + kTileX - 1) >> kTileLX;
+    g.nty = (g.ny + kTileY - 1) >> kTileLY;
+    g.ntz = (g.nzf + kTileZ - 1) >> kTileLZ;
     g.nt = g.ntx * g.nty * g.ntz;
     g.pp = population_pitch(g.n, pop_bytes(d.precision));
     return g;
@@ -427,7 +427,7 @@ int count_active_tiles(iblb_ctx *c, int *out)
             } else {
                 zf = wrap(zf, g.nz);
             }
-            on[((size_t)(zf >> 2) * g.nty + (y >> 2)) * g.ntx + (x >> 2)] = 1;
+            on[((size_t)(zf >> kTileLZ) * g.nty + (y >> kTileLY)) * g.ntx + (x >> kTileLX)] = 1;
         }
     }
     int n = 0;
@@ -1093,6 +1093,13 @@ int iblb_kernel_time(iblb_ctx *c, const char *name, double *total_ms, int64_t *l
     return fail(c, IBLB_E_INVAL, std::string("unknown kernel name ") + name);
 }
 
+void iblb_tile_shape(int32_t *tx, int32_t *ty, int32_t *tz)
+{
+    if (tx) *tx = kTileX;
+    if (ty) *ty = kTileY;
+    if (tz) *tz = kTileZ;
+}
+
 int iblb_active_nodes(iblb_ctx *c, int64_t *n)
 {
     if (!c || !n) return IBLB_E_INVAL;
@@ -1113,7 +1120,8 @@ int iblb_active_nodes(iblb_ctx *c, int64_t *n)
         if (tile < 0 || tile >= g.nt) return fail(c, IBLB_E_STATE, "active tile index out of range");
         const int tz = tile / (g.ntx * g.nty), rem = tile % (g.ntx * g.nty);
         const int ty = rem / g.ntx, tx = rem % g.ntx;
-        total += (int64_t)std::min(4, g.nx - 4 * tx) * std::min(4, g.ny - 4 * ty) * std::min(4, g.nzf - 4 * tz);
+        total += (int64_t)std::min(kTileX, g.nx - kTileX * tx) * std::min(kTileY, g.ny - kTileY * ty) *
+                 std::min(kTileZ, g.nzf - kTileZ * tz);
     }
     *n = total;
     return IBLB_OK;

@@ -9,8 +9,17 @@ struct iblb_ctx;
 
 namespace iblb {
 
-// Force-density tiles: 4x4x4 fluid nodes, one wavefront each when spreading.
-constexpr int kTile = 4;
+// Force-density tiles: kTileX x kTileY x kTileZ fluid nodes (x fastest), the
+// 64 lanes of one wavefront; the extents are powers of two, given as log2.
+// An x-row of a tile is 8 consecutive nodes, 32 bytes of an FP32 population
+// array: the spreading and moments gather the populations of the active tiles
+// row by row, and rows of 4 nodes used a quarter of each 64-byte fetch.
+constexpr int kTileLX = 3, kTileLY = 1, kTileLZ = 2;
+constexpr int kTileX = 1 << kTileLX, kTileY = 1 << kTileLY, kTileZ = 1 << kTileLZ;
+// one-dimensional stencil weights staged per listed vertex: one per tile coordinate
+constexpr int kTileW = kTileX + kTileY + kTileZ;
+static_assert(kTileX * kTileY * kTileZ == 64, "a tile is one wavefront");
+static_assert(kTileX >= 1 && kTileY >= 1 && kTileZ >= 1, "tile extents");
 // Maximum vertices whose stencil reaches one tile.
 constexpr int kTileCap = 512;
 // Maximum mesh vertices: the per-tile vertex masks hold nv bits in at most

@@ -113,7 +113,7 @@ __device__ __forceinline__ long long nidx(const Grid &g, int x, int y, int zf)
 
 __device__ __forceinline__ int tile_of(const Grid &g, int x, int y, int zf)
 {
-    return ((zf >> 2) * g.nty + (y >> 2)) * g.ntx + (x >> 2);
+    return ((zf >> kTileLZ) * g.nty + (y >> kTileLY)) * g.ntx + (x >> kTileLX);
 }
 
 // 4-point stencil phi4, Eq. ibm-interpolation_stencil.
@@ -409,17 +409,18 @@ __global__ __launch_bounds__(256) void k_init(S *__restrict__ f, LBArgs a, int c
 // wrapped if periodic, clipped to the fluid layers between walls).  Along an
 // axis the stencil's nodes form runs of consecutive nodes in one tile; a run
 // opens at offset k when node k is in the fluid and node k - 1 is not, or lies
-// in another tile.  With at least 8 nodes per axis a run never reopens a tile
-// already visited, so the run openings name each touched tile once: bit k of
-// the mask is set when offset k opens a run (at most three per axis).
+// in another tile: bit k of the mask is set when offset k opens a run (at
+// most three per axis).  The openings name every touched tile; a periodic axis
+// whose last tile is partial can name one twice, which the marks (a stamp and
+// an OR) absorb.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned runs_wrapped(int b, int n)
+__device__ __forceinline__ unsigned runs_wrapped(int b, int n, int sh)
 {
     unsigned mask = 1u;
-    int prev = wrapi(b, n) >> 2;
+    int prev = wrapi(b, n) >> sh;
 #pragma unroll
     for (int k = 1; k < 4; ++k) {
-        const int tl = wrapi(b + k, n) >> 2;
+        const int tl = wrapi(b + k, n) >> sh;
         mask |= tl != prev ? 1u << k : 0u;
         prev = tl;
     }
@@ -427,7 +428,7 @@ __device__ __forceinline__ unsigned runs_wrapped(int b, int n)
 }
 
 // b = first stencil layer counted in fluid layers (may be outside [0, nzf))
-__device__ __forceinline__ unsigned runs_clipped(int b, int nzf)
+__device__ __forceinline__ unsigned runs_clipped(int b, int nzf, int sh)
 {
     unsigned mask = 0u;
     int prev = -1;
@@ -435,7 +436,7 @@ __device__ __forceinline__ unsigned runs_clipped(int b, int nzf)
     for (int k = 0; k < 4; ++k) {
         const int zf = b + k;
         const bool in = zf >= 0 && zf < nzf;
-        const int tl = in ? zf >> 2 : -1;
+        const int tl = in ? zf >> sh : -1;
         mask |= (in && tl != prev) ? 1u << k : 0u;
         prev = tl;
     }
@@ -453,9 +454,9 @@ __device__ __forceinline__ StencilRuns stencil_runs(const Grid &g, double qx, do
     r.bx = (int)floor(qx) - 1;
     r.by = (int)floor(qy) - 1;
     r.bz = (int)floor(qz) - 1;
-    r.mx = runs_wrapped(r.bx, g.nx);
-    r.my = runs_wrapped(r.by, g.ny);
-    r.mz = g.walls ? runs_clipped(r.bz - g.zoff, g.nzf) : runs_wrapped(r.bz, g.nz);
+    r.mx = runs_wrapped(r.bx, g.nx, kTileLX);
+    r.my = runs_wrapped(r.by, g.ny, kTileLY);
+    r.mz = g.walls ? runs_clipped(r.bz - g.zoff, g.nzf, kTileLZ) : runs_wrapped(r.bz, g.nz, kTileLZ);
     return r;
 }
 
@@ -766,22 +767,23 @@ __device__ __forceinline__ double volume_factor(const double *__restrict__ parti
 // Spreading, one 256-thread block per active tile (gather form, no FP atomics)
 // ---------------------------------------------------------------------------
 // A listed vertex as the gather needs it: its phi4 weight at each of the
-// tile's four local coordinates per axis (zero where the stencil misses that
-// coordinate), and phi_S + phi_W and dV/dq.
+// tile's local coordinates per axis (kTileX, then kTileY, then kTileZ of
+// them; zero where the stencil misses that coordinate), and phi_S + phi_W and
+// dV/dq.
 template <typename T>
 struct Staged {
-    T w[12];
+    T w[kTileW];
     T ph[3], gv[3];
 };
 
-// Weights of one axis at the tile's local coordinates origin + 0..3: the
+// Weights of one axis at the tile's TW local coordinates origin + 0..TW-1: the
 // stencil of corner b covers node b + k, k = 0..3 (wrapped with period n when
 // n > 0).
-template <typename T>
+template <int TW, typename T>
 __device__ __forceinline__ void local_weights(const T *sw, int b, int origin, int n, T *out)
 {
 #pragma unroll
-    for (int l = 0; l < 4; ++l) {
+    for (int l = 0; l < TW; ++l) {
         int k = origin + l - b;
         if (n > 0 && k < 0)
             k += n;
@@ -826,57 +828,118 @@ __device__ __forceinline__ Staged<T> stage_load(int v, const Base *__restrict__ 
         s.ph[c] = phiSW[c * nv + u];
         s.gv[c] = gV[c * nv + u];
     }
-    local_weights<T>(w, bs.x, x0, g.nx, s.w);
-    local_weights<T>(w + 4, bs.y, y0, g.ny, s.w + 4);
-    local_weights<T>(w + 8, bs.z, z0, g.walls ? 0 : g.nz, s.w + 8);
+    local_weights<kTileX>(w, bs.x, x0, g.nx, s.w);
+    local_weights<kTileY>(w + 4, bs.y, y0, g.ny, s.w + kTileX);
+    local_weights<kTileZ>(w + 8, bs.z, z0, g.walls ? 0 : g.nz, s.w + kTileX + kTileY);
     if (!ok || !bs.ok) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k)
+        for (int k = 0; k < kTileW; ++k)
             s.w[k] = T(0);
     }
     return s;
 }
 
-template <typename T>
-__device__ __forceinline__ void stage_store(const Staged<T> &s, int e, T kf, T *sw, T *sph)
-{
-#pragma unroll
-    for (int k = 0; k < 12; ++k)
-        sw[e * 12 + k] = s.w[k];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-        sph[e * 4 + c] = s.ph[c] - kf * s.gv[c];
-}
-
 // Entries of a tile's vertex list staged in LDS per pass of the spreading.
 constexpr int kStageChunk = 128;
-// Spreading blocks per CU the register budget aims at: three with FP32
-// arithmetic; FP64 needs the whole register file of one.
+// Staged entries are summed in groups of four: one 4-wide LDS read per axis
+// gives the group's weights at the lane's local coordinate.
+constexpr int kGroup = 4;
+
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+    T v[4];
+};
+
+// A staged entry e: sw[r][e] is its phi4 weight at tile coordinate r (x
+// coordinates first, then y, then z, as in Staged); sph[e] its
+// phi_S + phi_W - k dV/dq.
+template <typename T>
+__device__ __forceinline__ void stage_store(const Staged<T> &s, int e, T kf, T (*sw)[kStageChunk], T (*sph)[4])
+{
+#pragma unroll
+    for (int r = 0; r < kTileW; ++r)
+        sw[r][e] = s.w[r];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        sph[e][c] = s.ph[c] - kf * s.gv[c];
+    sph[e][3] = T(0);
+}
+
+// A padding entry: zero weight and a finite (zero) force.
+template <typename T>
+__device__ __forceinline__ void stage_zero(int e, T (*sw)[kStageChunk], T (*sph)[4])
+{
+#pragma unroll
+    for (int r = 0; r < kTileW; ++r)
+        sw[r][e] = T(0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        sph[e][c] = T(0);
+}
+
+// Index of the r-th set bit (counted from 0, r < popcount(x)) of x, by halving.
+__host__ __device__ __forceinline__ int select_bit(uint64_t x, int r)
+{
+    int pos = 0;
+    uint32_t v = (uint32_t)x;
+    int c = __builtin_popcount(v);
+    if (r >= c) {
+        r -= c;
+        pos = 32;
+        v = (uint32_t)(x >> 32);
+    }
+    c = __builtin_popcount(v & 0xffffu);
+    if (r >= c) {
+        r -= c;
+        pos += 16;
+        v >>= 16;
+    }
+    c = __builtin_popcount(v & 0xffu);
+    if (r >= c) {
+        r -= c;
+        pos += 8;
+        v >>= 8;
+    }
+    c = __builtin_popcount(v & 0xfu);
+    if (r >= c) {
+        r -= c;
+        pos += 4;
+        v >>= 4;
+    }
+    c = __builtin_popcount(v & 0x3u);
+    if (r >= c) {
+        r -= c;
+        pos += 2;
+        v >>= 2;
+    }
+    return pos + (r >= (int)(v & 1u) ? 1 : 0);
+}
+
 // Wavefronts per SIMD the spreading's register budget aims at (the second
 // launch bound): three with FP32 arithmetic; FP64 needs the whole register
 // file of one.
 template <typename S>
 constexpr int kSpreadWaves = sizeof(typename Pop<S>::C) == 8 ? 1 : 3;
 
-// Blocks [0, nsp) spread: one 256-thread block (four wavefronts) per active
-// tile, striding over the list.  Blocks from nsp on (if any) run the LB of the
+// Blocks [0, nsp) spread: one block of NW wavefronts per active tile,
+// striding over the list.  Blocks from nsp on (if any) run the LB of the
 // nodes outside the active tiles: it is bandwidth-bound, the spreading is
 // latency-bound, and the two touch disjoint nodes (in the AA pattern each node
 // reads and writes only its own 19 slots), so they share the dispatch.
 //
-// Spreading: the tile's vertex
-// mask (bit v set when vertex v's stencil reaches the tile) is read whole,
-// thread k taking the k-th contiguous run of words; a block-wide prefix sum of
-// the words' bit counts gives every thread the list position of its first set
-// bit, and each thread writes the list entries of its own set bits, so the
-// listed vertices come out in ascending index order.  The list is staged in
-// LDS in passes of kStageChunk entries (one pass for all but the most crowded
-// tiles), which keeps the block's LDS small;
-// wavefront w sums the w-th contiguous quarter of each pass for the 64 nodes
-// of the tile (one per lane), and the four partial sums are added in
-// wavefront order, so every node's sum has a fixed order.  Wavefront 0
-// finishes with the LB update of the tile's nodes, whose populations it
-// fetched with the first pass.
+// Spreading: the tile's vertex mask (bit v set when vertex v's stencil
+// reaches the tile) is read whole, thread k taking the k-th contiguous run of
+// words, and copied to LDS with each thread's first list position (a prefix
+// sum of the words' bit counts), so the list is in ascending vertex order.
+// List entry e is then found by the thread that stages it: a binary search
+// over the positions names the thread holding it and a halving search its
+// bit, with no serial walk over the bits.  The list is staged in LDS in passes
+// of kStageChunk entries (one pass for all but the most crowded tiles);
+// wavefront w sums the w-th contiguous part of each pass's groups of four
+// entries for the 64 nodes of the tile (one per lane), and the partial sums are
+// added in wavefront order, so every node's sum has a fixed order.  Wavefront
+// 0 fetches its node's populations as soon as the tile is known and finishes
+// with the LB update of the tile's nodes.
 template <typename S, int P, int NW, typename T = typename Pop<S>::C>
 __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
@@ -891,15 +954,17 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
     constexpr int NT = 64 * NW;  // threads per block
     constexpr int NSUB = 256 / NT;
     static_assert(NW == 2 || NW == 4, "two or four wavefronts per block");
+    static_assert(kStageChunk <= NT && kStageChunk % kGroup == 0, "one staged entry per thread and pass");
     const Grid &g = a.g;
     if (blk >= nsp) {
         const int j = blk - nsp;
         bulk_lb_block<S, P == 1, NT>(lb0 + j / NSUB, f, Fext, act, ctr[P], err, a, bxw, nbx, nby, j % NSUB);
         return;
     }
-    __shared__ int sid[kStageChunk];
-    __shared__ __align__(16) T sw[kStageChunk * 12];
-    __shared__ __align__(16) T sph[kStageChunk * 4];
+    __shared__ uint64_t swd[4 * NT];  // the tile's mask words
+    __shared__ int spre[NT];          // each thread's first list position within its wavefront
+    __shared__ __align__(32) T sw[kTileW][kStageChunk];
+    __shared__ __align__(32) T sph[kStageChunk][4];
     __shared__ T part[NW - 1][3][64];
     __shared__ T spop[19][64];  // wavefront 0's prefetched populations
     __shared__ int swt[NW];
@@ -922,8 +987,9 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
         const int tz = tile / (g.ntx * g.nty);
         const int rem = tile - tz * g.ntx * g.nty;
         const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
-        const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
-        const int x = tx * 4 + lx, y = ty * 4 + ly, zf = tz * 4 + lz;
+        const int lx = lane & (kTileX - 1), ly = (lane >> kTileLX) & (kTileY - 1), lz = lane >> (kTileLX + kTileLY);
+        const int x0 = tx << kTileLX, y0 = ty << kTileLY, zt = tz << kTileLZ;
+        const int x = x0 + lx, y = y0 + ly, zf = zt + lz;
         const bool node = x < g.nx && y < g.ny && zf < g.nzf;
         uint64_t *mw = mask + (long long)tile * W;
         if (ai == (uint32_t)blk) {
@@ -933,6 +999,11 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
             for (int j = 0; j < 4; ++j)
                 wv[j] = (j < J && w0 + j < W) ? mw[w0 + j] : 0ull;
         }
+        // the node's populations, issued after the mask words (loads return
+        // in order, so waiting for the words does not wait for these)
+        T d[19];
+        if (wave == 0 && node)
+            load_pops<S, P == 1>(f, g, x, y, zf, d);
         // set bits of this thread's words
         int c = 0;
 #pragma unroll
@@ -946,93 +1017,109 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
         const int incl = wave_incl_scan(c);
         if (lane == 63)
             swt[wave] = incl;
+        spre[tid] = incl - c;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < J)
+                swd[w0 + j] = wv[j];
         __syncthreads();
         // the next tile's words (its index has arrived by now)
         uint64_t wn[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             wn[j] = (an < na && j < J && w0 + j < W) ? mask[(long long)next * W + w0 + j] : 0ull;
+        int sb[NW];  // list position of each wavefront's first entry
         int nent = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w)
+        for (int w = 0; w < NW; ++w) {
+            sb[w] = nent;
             nent += swt[w];
+        }
         if (nent > kTileCap) {
             if (tid == 0)
                 atomicOr(err, kErrOverflow);
             nent = kTileCap;
         }
-        // list position of this thread's first set bit: the list is in thread
-        // order, and within a thread in word and bit order
-        int pre = incl - c;
-        for (int w = 0; w < wave; ++w)
-            pre += swt[w];
-        const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 4 + g.zoff;
+        const int z0 = zt + g.zoff;
         const T kf = skfac;
         T Fx = T(0), Fy = T(0), Fz = T(0);
-        // The ordered list in passes of kStageChunk entries: every thread
-        // writes the entries of its own words' set bits that fall in the pass,
-        // the vertices of the pass are staged (local weights and total force),
-        // and wavefront w sums the w-th contiguous quarter of the pass.
-        auto expand = [&](int c0, int cn) {
-            int o = pre;
+        // Entry e of the list: the thread k holding it is the last one whose
+        // first position is <= e; the entry is the r-th set bit of its words.
+        auto entry = [&](int e) {
+            int k = 0;
+#pragma unroll
+            for (int step = NT / 2; step > 0; step >>= 1) {
+                const int kk = k + step;
+                int pk = spre[kk];
+#pragma unroll
+                for (int w = 1; w < NW; ++w)
+                    pk += kk >= 64 * w ? sb[w] - sb[w - 1] : 0;
+                if (pk <= e)
+                    k = kk;
+            }
+            int r = e - spre[k];
+#pragma unroll
+            for (int w = 1; w < NW; ++w)
+                r -= k >= 64 * w ? sb[w] - sb[w - 1] : 0;
+            int v = -1;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                uint64_t word = wv[j];
-                const int nb = __popcll(word);
-                if (o < c0 + cn && o + nb > c0) {
-                    for (int p = o; word != 0ull && p < c0 + cn; ++p) {
-                        if (p >= c0)
-                            sid[p - c0] = (w0 + j) * 64 + __builtin_ctzll(word);
-                        word &= word - 1ull;
-                    }
+                if (j < J && v < 0) {
+                    const uint64_t word = swd[k * J + j];
+                    const int cnt = __popcll(word);
+                    if (r < cnt)
+                        v = (k * J + j) * 64 + select_bit(word, r);
+                    else
+                        r -= cnt;
                 }
-                o += nb;
             }
+            return v;
         };
-        static_assert(kStageChunk <= NT, "one staged entry per thread and pass");
-        auto stage = [&](int cn) {
+        // pass [c0, c0 + cn), padded with zero entries to whole groups
+        auto stage = [&](int c0, int cn) {
+            const int cp = (cn + kGroup - 1) / kGroup * kGroup;
             if (tid < cn) {
-                const Staged<T> st = stage_load<T>(sid[tid], base, wts, phiSW, gV, nv, err, g, x0, y0, z0);
+                const Staged<T> st = stage_load<T>(entry(c0 + tid), base, wts, phiSW, gV, nv, err, g, x0, y0, z0);
                 stage_store<T>(st, tid, kf, sw, sph);
+            } else if (tid < cp) {
+                stage_zero<T>(tid, sw, sph);
             }
         };
         auto accumulate = [&](int cn) {
-            const int qw = (cn + NW - 1) / NW;
-            const int e0 = wave * qw, e1 = min(cn, e0 + qw);
-#pragma unroll 8
-            for (int e = e0; e < e1; ++e) {
-                const T w = sw[e * 12 + lx] * sw[e * 12 + 4 + ly] * sw[e * 12 + 8 + lz];
-                Fx += sph[e * 4 + 0] * w;
-                Fy += sph[e * 4 + 1] * w;
-                Fz += sph[e * 4 + 2] * w;
+            const int ng = (cn + kGroup - 1) / kGroup;
+            const int gq = (ng + NW - 1) / NW;
+            const int g0 = wave * gq, g1 = min(ng, g0 + gq);
+#pragma unroll 2
+            for (int gi = g0; gi < g1; ++gi) {
+                const int e = gi * kGroup;
+                const Quad<T> wx = *reinterpret_cast<const Quad<T> *>(&sw[lx][e]);
+                const Quad<T> wy = *reinterpret_cast<const Quad<T> *>(&sw[kTileX + ly][e]);
+                const Quad<T> wz = *reinterpret_cast<const Quad<T> *>(&sw[kTileX + kTileY + lz][e]);
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j) {
+                    const Quad<T> ph = *reinterpret_cast<const Quad<T> *>(&sph[e + j][0]);
+                    const T w = wx.v[j] * wy.v[j] * wz.v[j];
+                    Fx += ph.v[0] * w;
+                    Fy += ph.v[1] * w;
+                    Fz += ph.v[2] * w;
+                }
             }
         };
-        // the first pass: wavefront 0 fetches its node's populations with the
-        // staged loads (fetched earlier, they would be waited for at the
-        // barrier: loads complete in order)
+        // the first pass; wavefront 0 parks its populations in LDS with it
         const int cn0 = min(kStageChunk, nent);
-        expand(0, cn0);
-        __syncthreads();
-        {
-            T d[19];
-            if (wave == 0 && node)
-                load_pops<S, P == 1>(f, g, x, y, zf, d);
-            stage(cn0);
-            if (wave == 0 && node) {
+        stage(0, cn0);
+        if (wave == 0 && node) {
 #pragma unroll
-                for (int i = 0; i < 19; ++i)
-                    spop[i][lane] = d[i];
-            }
+            for (int i = 0; i < 19; ++i)
+                spop[i][lane] = d[i];
         }
         __syncthreads();
         accumulate(cn0);
         // further passes (tiles listing more than kStageChunk vertices)
         for (int c0 = kStageChunk; c0 < nent; c0 += kStageChunk) {
             const int cn = min(kStageChunk, nent - c0);
-            __syncthreads();  // the previous pass is done with sid, sw and sph
-            expand(c0, cn);
-            __syncthreads();
-            stage(cn);
+            __syncthreads();  // the previous pass is done with sw and sph
+            stage(c0, cn);
             __syncthreads();
             accumulate(cn);
         }
@@ -1062,11 +1149,11 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
                 F[g.n + me] = Fy;
                 F[2 * g.n + me] = Fz;
                 // the LB update of this active node, with its force in hand
-                T d[19];
+                T dd[19];
 #pragma unroll
                 for (int i = 0; i < 19; ++i)
-                    d[i] = spop[i][lane];
-                lb_collide<S, P == 1>(f, Fext, err, a, x, y, zf, d, Fx, Fy, Fz);
+                    dd[i] = spop[i][lane];
+                lb_collide<S, P == 1>(f, Fext, err, a, x, y, zf, dd, Fx, Fy, Fz);
             }
             if (lane == 0)
                 stamp[tile] = t + 1u;
@@ -1115,7 +1202,8 @@ __device__ __forceinline__ void moments_dispatch(int blk, int nblk, const S *__r
         const int tz = tile / (g.ntx * g.nty);
         const int rem = tile - tz * g.ntx * g.nty;
         const int ty = rem / g.ntx, tx = rem - ty * g.ntx;
-        const int x = tx * 4 + (lane & 3), y = ty * 4 + ((lane >> 2) & 3), zf = tz * 4 + (lane >> 4);
+        const int x = (tx << kTileLX) + (lane & (kTileX - 1)), y = (ty << kTileLY) + ((lane >> kTileLX) & (kTileY - 1)),
+                  zf = (tz << kTileLZ) + (lane >> (kTileLX + kTileLY));
         tile = next;
         if (x >= g.nx || y >= g.ny || zf >= g.nzf)
             continue;

@@ -120,6 +120,7 @@ def lib():
             "iblb_kernel_time": [_vp, C.c_char_p, _dp, C.POINTER(C.c_int64)],
             "iblb_reset_timing": [_vp],
             "iblb_active_nodes": [_vp, C.POINTER(C.c_int64)],
+            "iblb_tile_shape": [_ip, _ip, _ip],
             "iblb_destroy": [_vp],
             "iblb_batch_create": [C.POINTER(_vp), C.c_int32, _vp, pp],
             "iblb_batch_step": [_vp, C.c_int32],
@@ -138,6 +139,7 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = C.c_int
+        L.iblb_tile_shape.restype = None
         L.iblb_last_error.argtypes = [_vp]
         L.iblb_last_error.restype = C.c_char_p
         L.iblb_batch_last_error.argtypes = [_vp]
@@ -146,6 +148,13 @@ def lib():
         L.iblb_batch_member_error.restype = C.c_char_p
         _lib = L
     return _lib
+
+
+def tile_shape() -> tuple:
+    """Extents (x, y, z) in fluid nodes of the tiles the spreading works on."""
+    t = [C.c_int32() for _ in range(3)]
+    lib().iblb_tile_shape(*[C.byref(v) for v in t])
+    return tuple(v.value for v in t)
 
 
 def _p(a: np.ndarray):

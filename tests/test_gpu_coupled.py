@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 
 def ragged_case():
-    """Sizes that are not multiples of the 4^3 tiles; the mesh straddles the x seam
+    """Sizes that are not multiples of the tile extents; the mesh straddles the x seam
     and feels the lower wall through the LJ force."""
     d = Domain(26, 21, 18, tau=0.9, u_wall_lo=(0.002, 0, 0), u_wall_hi=(-0.003, 0.001, 0))
     m = sphere_mesh(2, 4.5, (1.3, 10.2, 0.5 + 4.5 + 0.6), (2e-3, 1e-3, 1e-3), amplitude=0.02, seed=5,

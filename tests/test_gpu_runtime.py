@@ -134,8 +134,9 @@ def test_graph_with_odd_starts_and_counts(prec):
 
 
 def _stencil_tile_nodes(q, dom):
-    """Fluid nodes of the 4x4x4 tiles reached by the 4^3 stencils of the
+    """Fluid nodes of the library's tiles reached by the 4^3 stencils of the
     vertices at q (x, y periodic; z periodic or clipped to the fluid layers)."""
+    TX, TY, TZ = iblb.tile_shape()
     walls = dom.wall_mode == iblb.WALLS_Z
     zoff, nzf = (1, dom.nz - 2) if walls else (0, dom.nz)
     tiles = set()
@@ -147,8 +148,9 @@ def _stencil_tile_nodes(q, dom):
             z = b[2] + (k >> 4)
             zf = z - zoff if walls else z % dom.nz
             if 0 <= zf < nzf:
-                tiles.add((x // 4, y // 4, zf // 4))
-    return sum(min(4, dom.nx - 4 * tx) * min(4, dom.ny - 4 * ty) * min(4, nzf - 4 * tz) for tx, ty, tz in tiles)
+                tiles.add((x // TX, y // TY, zf // TZ))
+    return sum(min(TX, dom.nx - TX * tx) * min(TY, dom.ny - TY * ty) * min(TZ, nzf - TZ * tz)
+               for tx, ty, tz in tiles)
 
 
 @pytest.mark.parametrize("case", ["walls_ragged", "periodic_ragged"])
