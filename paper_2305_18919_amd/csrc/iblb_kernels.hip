@@ -999,21 +999,28 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
             for (int j = 0; j < 4; ++j)
                 wv[j] = (j < J && w0 + j < W) ? mw[w0 + j] : 0ull;
         }
-        // the node's populations, issued after the mask words (loads return
-        // in order, so waiting for the words does not wait for these)
-        T d[19];
-        if (wave == 0 && node)
-            load_pops<S, P == 1>(f, g, x, y, zf, d);
-        // set bits of this thread's words
-        int c = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            c += __popcll(wv[j]);
+        // wavefront 1 sums the volume partials (their loads overlap those of
+        // the words)
         if (wave == 1 && ai == (uint32_t)blk) {
             const T kfac = T(volume_factor(partials, m, lane));
             if (lane == 0)
                 skfac = kfac;
         }
+        // set bits of this thread's words
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            c += __popcll(wv[j]);
+        // wavefront 0 fetches its node's populations now, once the words are
+        // in: issued earlier, they would be waited for with the words (a wait
+        // after a branch holding loads covers every load issued before it).
+        // The test on an opaque copy of c (never negative) keeps the loads
+        // behind the count.
+        T d[19];
+        int ck = c;
+        asm volatile("" : "+v"(ck));
+        if (wave == 0 && node && ck >= 0)
+            load_pops<S, P == 1>(f, g, x, y, zf, d);
         const int incl = wave_incl_scan(c);
         if (lane == 63)
             swt[wave] = incl;
