@@ -173,43 +173,49 @@ __device__ __forceinline__ T wave_sum(T v)
 // swapped = (t odd): f_i(x) is at slot (opp(i), x - c_i), or at (i, x) when
 // x - c_i is not a fluid node.
 // ---------------------------------------------------------------------------
+// A node's index and the index offsets (modulo 2^32, periodic wrap applied)
+// to its neighbours one step up and down each axis: a shifted node's index is
+// then two or three 32-bit adds (node indices stay below 2^32).
 struct Nbr {
-    int xp, xm, yp, ym, zp, zm;
+    uint32_t me;
+    uint32_t xp, xm, yp, ym, zp, zm;
     bool zp_ok, zm_ok;
 };
 
 __device__ __forceinline__ Nbr neighbours(const Grid &g, int x, int y, int zf)
 {
     Nbr b;
-    b.xp = (x + 1 == g.nx) ? 0 : x + 1;
-    b.xm = (x == 0) ? g.nx - 1 : x - 1;
-    b.yp = (y + 1 == g.ny) ? 0 : y + 1;
-    b.ym = (y == 0) ? g.ny - 1 : y - 1;
-    b.zp = zf + 1;
-    b.zm = zf - 1;
+    const uint32_t nx = (uint32_t)g.nx, sxy = nx * (uint32_t)g.ny;
+    b.me = (uint32_t)nidx(g, x, y, zf);
+    b.xp = (x + 1 == g.nx) ? 1u - nx : 1u;
+    b.xm = (x == 0) ? nx - 1u : 0u - 1u;
+    b.yp = (y + 1 == g.ny) ? nx - sxy : nx;
+    b.ym = (y == 0) ? sxy - nx : 0u - nx;
+    b.zp = sxy;
+    b.zm = 0u - sxy;
     if (g.walls) {
-        b.zp_ok = b.zp < g.nzf;
-        b.zm_ok = b.zm >= 0;
+        b.zp_ok = zf + 1 < g.nzf;
+        b.zm_ok = zf - 1 >= 0;
     } else {
         b.zp_ok = b.zm_ok = true;
-        if (b.zp == g.nzf) b.zp = 0;
-        if (b.zm < 0) b.zm = g.nzf - 1;
+        const uint32_t all = sxy * (uint32_t)g.nzf;
+        if (zf + 1 == g.nzf) b.zp = sxy - all;
+        if (zf == 0) b.zm = all - sxy;
     }
     return b;
 }
 
 // node x + s*c_i (s = +1 destination, -1 source); returns false if not fluid
-__device__ __forceinline__ bool shifted(const Grid &g, const Nbr &b, int x, int y, int zf, int i, int s,
-                                        long long &out)
+__device__ __forceinline__ bool shifted(const Nbr &b, int i, int s, uint32_t &out)
 {
     const int ddx = s * cx(i), ddy = s * cy(i), ddz = s * cz(i);
-    const int xx = ddx == 0 ? x : (ddx > 0 ? b.xp : b.xm);
-    const int yy = ddy == 0 ? y : (ddy > 0 ? b.yp : b.ym);
+    uint32_t o = b.me;
+    if (ddx != 0) o += ddx > 0 ? b.xp : b.xm;
+    if (ddy != 0) o += ddy > 0 ? b.yp : b.ym;
     bool ok = true;
-    int zz = zf;
-    if (ddz > 0) { zz = b.zp; ok = b.zp_ok; }
-    if (ddz < 0) { zz = b.zm; ok = b.zm_ok; }
-    out = nidx(g, xx, yy, zz);
+    if (ddz > 0) { o += b.zp; ok = b.zp_ok; }
+    if (ddz < 0) { o += b.zm; ok = b.zm_ok; }
+    out = o;
     return ok;
 }
 
@@ -241,9 +247,9 @@ __device__ __forceinline__ void load_pops(const S *__restrict__ f, const Grid &g
         const Nbr b = neighbours(g, x, y, zf);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            long long src;
-            const bool ok = shifted(g, b, x, y, zf, i, -1, src);
-            d[i] = Pop<S>::get(*pop_at(f, ok ? opp(i) * n + (uint32_t)src : i * n + me), i);
+            uint32_t src;
+            const bool ok = shifted(b, i, -1, src);
+            d[i] = Pop<S>::get(*pop_at(f, ok ? opp(i) * n + src : i * n + me), i);
         }
     }
 }
@@ -299,8 +305,8 @@ __device__ __forceinline__ void lb_collide(S *__restrict__ f, const T *__restric
         const T cF = T(cx(i)) * Fx + T(cy(i)) * Fy + T(cz(i)) * Fz;
         const T guo_i = w * guo * (T(3) * cmuF + T(9) * cF * cu);
         T post = d[i] - (d[i] - deq) * tinv + guo_i;
-        long long dst;
-        const bool fluid = shifted(g, b, x, y, zf, i, +1, dst);
+        uint32_t dst;
+        const bool fluid = shifted(b, i, +1, dst);
         if (!fluid) {
             // half-way bounce-back off a (moving) wall: -2 w rho (c.u_w)/c_s^2
             const double *uw = cz(i) < 0 ? a.ulo : a.uhi;
@@ -311,7 +317,7 @@ __device__ __forceinline__ void lb_collide(S *__restrict__ f, const T *__restric
         if (!ODD || !fluid)
             store_through(pop_at(f, opp(i) * n32 + me32), Pop<S>::put(post, i));
         else
-            store_through(pop_at(f, i * n32 + (uint32_t)dst), Pop<S>::put(post, i));
+            store_through(pop_at(f, i * n32 + dst), Pop<S>::put(post, i));
     }
 }
 
@@ -1587,8 +1593,8 @@ __global__ __launch_bounds__(256) void k_set_pops(S *__restrict__ f, int p, cons
         const Nbr b = neighbours(g, x, y, zf);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            long long src;
-            const bool ok = shifted(g, b, x, y, zf, i, -1, src);
+            uint32_t src;
+            const bool ok = shifted(b, i, -1, src);
             if (ok)
                 f[opp(i) * g.pp + src] = Pop<S>::put(T(in[i * n + me]), i);
             else
