@@ -107,7 +107,7 @@ Layout make_layout(const Grid &g, size_t ps, size_t ts, int nv, int nf, int slot
     L.faces = take((size_t)3 * nf * 4);
     L.fref = take((size_t)5 * nf * 8);
     L.inc4 = take((size_t)nv * slots * 16);
-    L.U = take(nv ? (size_t)3 * g.n * ts : 0);
+    L.U = take(nv ? (size_t)4 * g.n * ts : 0);
     L.phiSW = take((size_t)3 * nv * ts);
     L.gV = take((size_t)3 * nv * ts);
     L.base = take((size_t)nv * sizeof(Base));

@@ -84,7 +84,7 @@ struct Dev {
     int *faces;           // [3][nf]
     double *fref;         // [5][nf]: Ginv11, Ginv12, Ginv22, A0, 1/detG
     int4 *inc4;           // [nv][slots]: (a, b, c, face*4 + corner), faces ascending; unused slots w = -1
-    void *U;              // [3][n] u(t+1) on the nodes of the active tiles
+    void *U;              // [n][4] u(t+1) (x, y, z, unused) on the nodes of the active tiles
     void *phiSW;          // [3][nv] elastic + wall force
     void *gV;             // [3][nv] dV/dq
     Base *base;           // [nv]

@@ -100,6 +100,12 @@ struct Pop<__bf16> {
 // cost of a little extra work.
 __host__ __device__ __forceinline__ uint8_t act_stamp(uint32_t t) { return (uint8_t)(t % 255u + 1u); }
 
+// Four values loaded or stored as one vector (16 bytes in FP32).
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+    T v[4];
+};
+
 __device__ __forceinline__ int wrapi(int a, int n)
 {
     int r = a % n;
@@ -851,11 +857,6 @@ constexpr int kStageChunk = 128;
 // gives the group's weights at the lane's local coordinate.
 constexpr int kGroup = 4;
 
-template <typename T>
-struct alignas(4 * sizeof(T)) Quad {
-    T v[4];
-};
-
 // A staged entry e: sw[r][e] is its phi4 weight at tile coordinate r (x
 // coordinates first, then y, then z, as in Staged); sph[e] its
 // phi_S + phi_W - k dV/dq.
@@ -1238,9 +1239,12 @@ __device__ __forceinline__ void moments_dispatch(int blk, int nblk, const S *__r
             if (cz(i) != 0) mz += T(cz(i)) * d[i];
         }
         const T rho = T(a.rho0) + drho;
-        U[me] = (mx + T(0.5) * Fx) / rho;
-        U[g.n + me] = (my + T(0.5) * Fy) / rho;
-        U[2 * g.n + me] = (mz + T(0.5) * Fz) / rho;
+        Quad<T> u;
+        u.v[0] = (mx + T(0.5) * Fx) / rho;
+        u.v[1] = (my + T(0.5) * Fy) / rho;
+        u.v[2] = (mz + T(0.5) * Fz) / rho;
+        u.v[3] = T(0);
+        reinterpret_cast<Quad<T> *>(U)[me] = u;
     }
 }
 
@@ -1296,11 +1300,11 @@ __device__ __forceinline__ void stencil_velocity(const T *__restrict__ U, const 
         const long long me = nidx(g, x, y, zf);
         // every fluid stencil node lies in an active tile of this step; U is
         // read unconditionally and used if the tile carries this step's stamp
-        const T u0 = U[me], u1 = U[g.n + me], u2 = U[2 * g.n + me];
+        const Quad<T> u = reinterpret_cast<const Quad<T> *>(U)[me];
         const bool fresh = stamp[tile_of(g, x, y, zf)] == t + 1u;
-        ux = fresh ? u0 : T(0);
-        uy = fresh ? u1 : T(0);
-        uz = fresh ? u2 : T(0);
+        ux = fresh ? u.v[0] : T(0);
+        uy = fresh ? u.v[1] : T(0);
+        uz = fresh ? u.v[2] : T(0);
     }
     sx += ux * w;
     sy += uy * w;
@@ -1526,7 +1530,7 @@ __global__ __launch_bounds__(256) void k_record(const S *__restrict__ f, const O
         st = stamp[tile_of(g, x, y, zf)];
         for (int c = 0; c < 3; ++c) {
             Fv[c] = F[(size_t)c * n + i];
-            Uv[c] = U[(size_t)c * n + i];
+            Uv[c] = U[(size_t)4 * i + c];
         }
     }
     const uint32_t t = ctr[p];
