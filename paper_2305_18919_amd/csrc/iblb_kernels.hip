@@ -1179,6 +1179,15 @@ __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict_
     }
 }
 
+// Role of block b of the spreading dispatch: its first `pre` blocks run LB
+// blocks (those from nsp on), the next nsp spread, the rest run the remaining
+// LB blocks.  LB blocks dispatched ahead of the spreading keep the memory
+// system busy while the spreading's first dependent loads are in flight.
+__device__ __forceinline__ int spread_role(int b, int nsp, int pre)
+{
+    return b < pre ? nsp + b : (b < pre + nsp ? b - pre : b);
+}
+
 template <typename S, int P, int NW, typename T = typename Pop<S>::C>
 __global__ __launch_bounds__(64 * NW, kSpreadWaves<S>) void k_spread(const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
@@ -1188,9 +1197,9 @@ __global__ __launch_bounds__(64 * NW, kSpreadWaves<S>) void k_spread(const Base 
                                                 uint32_t *__restrict__ stamp, S *__restrict__ f,
                                                 const T *__restrict__ Fext, int *err, LBArgs a, MeshArgs m,
                                                 const uint8_t *__restrict__ act, int nsp, int lb0, int bxw, int nbx,
-                                                int nby)
+                                                int nby, int pre)
 {
-    spread_dispatch<S, P, NW, T>((int)blockIdx.x, base, wts, phiSW, gV, partials, ctr, mask, acnt, alist, F, stamp,
+    spread_dispatch<S, P, NW, T>(spread_role((int)blockIdx.x, nsp, pre), base, wts, phiSW, gV, partials, ctr, mask, acnt, alist, F, stamp,
                                  f, Fext, err, a, m, act, nsp, lb0, bxw, nbx, nby);
 }
 
@@ -1939,6 +1948,11 @@ hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, h
 // 0.4 / 0.5 / 0.6 / 0.7 gave 28.01 / 28.00 / 28.42 / 29.40 at 64^3 and
 // 77.3 / 77.4 / 77.3 / 79.0 on the wetting droplet.
 constexpr double kLbShareWithForces = 0.5;
+// Share of the spreading dispatch's LB blocks dispatched ahead of its
+// spreading blocks.  Measured on the 128x128x96 droplet (FP32, us per step):
+// 0 / 0.25 / 0.375 / 0.5 / 0.625 / 0.75 / 1 gave 69.3 / 68.2 / 67.4 / 67.6 /
+// 67.1 / 67.4 / 69.8.
+constexpr double kLbAheadOfSpread = 0.625;
 
 int lb_block_width(const Grid &g) { return (int)lb_block(g).x; }
 double lb_share_with_forces() { return kLbShareWithForces; }
@@ -2001,10 +2015,11 @@ static void spread_launch(const Dev &d, const LBArgs &a, const MeshArgs &m, int 
     const int nsp = a.g.nt < fit ? a.g.nt : fit;
     const int lb0 = lb_blocks_with_forces(a.g);
     const int nlb = with_lb ? ((int)(gr.x * gr.y * gr.z) - lb0) * (4 / NW) : 0;
+    const int pre = (int)(kLbAheadOfSpread * nlb);
     k_spread<S, P, NW><<<nsp + nlb, 64 * NW, 0, s>>>(d.base, (const T *)d.wts, (const T *)d.phiSW,
                                                      (const T *)d.gV, d.partials, d.ctr, d.mask, d.acnt, d.alist,
                                                      (T *)d.F, d.stamp, (S *)d.f, (const T *)d.Fext, d.err, a, m,
-                                                     d.act, nsp, lb0, (int)bl.x, (int)gr.x, (int)gr.y);
+                                                     d.act, nsp, lb0, (int)bl.x, (int)gr.x, (int)gr.y, pre);
 }
 
 hipError_t launch_spread(int prec, const Dev &d, const LBArgs &a, const MeshArgs &m, int p, int with_lb,
