@@ -106,8 +106,12 @@ struct alignas(4 * sizeof(T)) Quad {
     T v[4];
 };
 
+// a modulo n in [0, n); the common case, a already in range, skips the
+// integer division
 __device__ __forceinline__ int wrapi(int a, int n)
 {
+    if ((unsigned)a < (unsigned)n)
+        return a;
     int r = a % n;
     return r < 0 ? r + n : r;
 }
