@@ -574,12 +574,14 @@ __device__ __forceinline__ int wave_incl_scan(int c, int lane)
 // sum_i delta(x - q_i) qb1_i, written for every node of the tile; then, where
 // ub != 0, the adjoint of u' = (sum c f1 + F/2) / rho1 with respect to f1:
 // lam_j += (c_j - u') . ub / rho1, u' from U; ub / (2 rho1), its force share,
-// is what stays in ub for the LB adjoint.  The list comes out in
-// ascending vertex order and four wavefronts each sum a quarter of it, so the
-// sums have a fixed order (no atomics).  The listed vertices' positions and
-// qb1 are loaded in one round and their 12 one-dimensional weights each are
-// evaluated by 12 threads; wavefront 0 fetches its nodes' f1, U and lam while
-// the sums run.
+// is what stays in ub for the LB adjoint.  The list is in ascending vertex
+// order (entry e found by a binary search over the threads' first list
+// positions, as in the forward spreading) and four wavefronts each sum a
+// quarter of it, so the sums have a fixed order (no atomics).  The listed
+// vertices' positions and qb1 are loaded in one round and their
+// one-dimensional weights at the tile's coordinates (kTileW per vertex) are
+// evaluated one per thread; wavefront 0 fetches its nodes' f1, U and lam
+// while the sums run.
 template <typename P>
 __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *__restrict__ q,
                                                        const double *__restrict__ qb1, const P *__restrict__ f1,
@@ -591,7 +593,8 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
     const int nv = A.nv;
     const long long n = g.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    __shared__ int sid[kTileCap];
+    __shared__ uint64_t swd[4 * 256];  // the tile's mask words
+    __shared__ int spre[256];          // each thread's first list position within its wavefront
     __shared__ P sw[kTileCap * kTileW];  // per listed vertex: its weights at the tile's x, y and z coordinates
     __shared__ double sqb[kTileCap * 3];  // and qb1
     __shared__ double sq[kTileCap * 3];   // and q
@@ -625,32 +628,50 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
         const int incl = wave_incl_scan(c, lane);
         if (lane == 63)
             swt[wave] = incl;
-        __syncthreads();
-        const int tot = swt[0] + swt[1] + swt[2] + swt[3];
-        // the list in ascending vertex order
-        int pos = incl - c;
-        for (int w = 0; w < wave; ++w)
-            pos += swt[w];
+        spre[tid] = incl - c;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            uint64_t word = wv[j];
-            while (word != 0ull) {
-                const int bit = __ffsll((unsigned long long)word) - 1;
-                word &= word - 1ull;
-                if (pos < kTileCap)
-                    sid[pos] = (w0 + j) * 64 + bit;
-                ++pos;
-            }
-        }
+        for (int j = 0; j < 4; ++j)
+            if (j < J)
+                swd[w0 + j] = wv[j];
+        __syncthreads();
+        // list position of each wavefront's first entry
+        const int sb1 = swt[0], sb2 = sb1 + swt[1], sb3 = sb2 + swt[2];
+        const int tot = sb3 + swt[3];
         const int nent = tot < kTileCap ? tot : kTileCap;
         if (tot > kTileCap && tid == 0)
             atomicOr(err, kErrOverflow);
-        __syncthreads();
+        // entry e of the list (ascending vertex order): the thread k holding it
+        // is the last one whose first position is <= e (binary search), the
+        // entry the r-th set bit of its words
+        auto entry = [&](int e) {
+            auto first = [&](int k) {
+                return spre[k] + (k >= 192 ? sb3 : (k >= 128 ? sb2 : (k >= 64 ? sb1 : 0)));
+            };
+            int k = 0;
+#pragma unroll
+            for (int step = 128; step > 0; step >>= 1)
+                if (first(k + step) <= e)
+                    k += step;
+            int r = e - first(k), v = -1;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j < J && v < 0) {
+                    const uint64_t word = swd[k * J + j];
+                    const int cnt = __popcll(word);
+                    if (r < cnt)
+                        v = (k * J + j) * 64 + select_bit(word, r);
+                    else
+                        r -= cnt;
+                }
+            }
+            return v;
+        };
         // lattice coordinates of the tile's first node
         const int x0 = tx << kTileLX, y0 = ty << kTileLY, z0 = (tz << kTileLZ) + g.zoff;
         // the listed vertices' positions and qb1, all loads in flight together
         for (int e = tid; e < nent; e += 256) {
-            const int v = sid[e] < nv ? sid[e] : 0;  // (marks name vertices below nv only)
+            const int ve = entry(e);
+            const int v = (unsigned)ve < (unsigned)nv ? ve : 0;  // (marks name vertices below nv only)
             double a[6];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {

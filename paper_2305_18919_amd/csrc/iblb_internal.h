@@ -32,6 +32,44 @@ constexpr int kErrDensity = 4;     // a node density became non-finite or left (
 constexpr int kErrMach = 8;        // |u| above 0.3 somewhere
 constexpr int kErrList = 16;       // a tile list held an invalid vertex index
 
+// Index of the r-th set bit (counted from 0, r < popcount(x)) of x, by halving.
+__host__ __device__ inline int select_bit(uint64_t x, int r)
+{
+    int pos = 0;
+    uint32_t v = (uint32_t)x;
+    int c = __builtin_popcount(v);
+    if (r >= c) {
+        r -= c;
+        pos = 32;
+        v = (uint32_t)(x >> 32);
+    }
+    c = __builtin_popcount(v & 0xffffu);
+    if (r >= c) {
+        r -= c;
+        pos += 16;
+        v >>= 16;
+    }
+    c = __builtin_popcount(v & 0xffu);
+    if (r >= c) {
+        r -= c;
+        pos += 8;
+        v >>= 8;
+    }
+    c = __builtin_popcount(v & 0xfu);
+    if (r >= c) {
+        r -= c;
+        pos += 4;
+        v >>= 4;
+    }
+    c = __builtin_popcount(v & 0x3u);
+    if (r >= c) {
+        r -= c;
+        pos += 2;
+        v >>= 2;
+    }
+    return pos + (r >= (int)(v & 1u) ? 1 : 0);
+}
+
 struct alignas(16) Base {
     int x, y, z, ok;  // stencil corner floor(q)-1 (x, y wrapped; z absolute, wrapped if periodic); ok = 1 if finite
 };

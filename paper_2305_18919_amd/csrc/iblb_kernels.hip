@@ -888,43 +888,6 @@ __device__ __forceinline__ void stage_zero(int e, T (*sw)[kStageChunk], T (*sph)
         sph[e][c] = T(0);
 }
 
-// Index of the r-th set bit (counted from 0, r < popcount(x)) of x, by halving.
-__host__ __device__ __forceinline__ int select_bit(uint64_t x, int r)
-{
-    int pos = 0;
-    uint32_t v = (uint32_t)x;
-    int c = __builtin_popcount(v);
-    if (r >= c) {
-        r -= c;
-        pos = 32;
-        v = (uint32_t)(x >> 32);
-    }
-    c = __builtin_popcount(v & 0xffffu);
-    if (r >= c) {
-        r -= c;
-        pos += 16;
-        v >>= 16;
-    }
-    c = __builtin_popcount(v & 0xffu);
-    if (r >= c) {
-        r -= c;
-        pos += 8;
-        v >>= 8;
-    }
-    c = __builtin_popcount(v & 0xfu);
-    if (r >= c) {
-        r -= c;
-        pos += 4;
-        v >>= 4;
-    }
-    c = __builtin_popcount(v & 0x3u);
-    if (r >= c) {
-        r -= c;
-        pos += 2;
-        v >>= 2;
-    }
-    return pos + (r >= (int)(v & 1u) ? 1 : 0);
-}
 
 // Wavefronts per SIMD the spreading's register budget aims at (the second
 // launch bound): three with FP32 arithmetic; FP64 needs the whole register
