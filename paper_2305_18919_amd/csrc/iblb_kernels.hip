@@ -57,6 +57,18 @@ __device__ __forceinline__ constexpr int cz(int i)
     return t[i];
 }
 __device__ __forceinline__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+// The ten populations that move along x (c_x != 0): their indices, and the
+// place of population i among them.
+__device__ __forceinline__ constexpr int xpop(int k)
+{
+    constexpr int t[10] = {1, 2, 7, 8, 9, 10, 11, 12, 13, 14};
+    return t[k];
+}
+__device__ __forceinline__ constexpr int xslot(int i)
+{
+    constexpr int t[19] = {-1, 0, 1, -1, -1, -1, -1, 2, 3, 4, 5, 6, 7, 8, 9, -1, -1, -1, -1};
+    return t[i];
+}
 template <typename T>
 __device__ __forceinline__ constexpr T wgt(int i)
 {
@@ -267,12 +279,88 @@ __device__ __forceinline__ void load_pops(const S *__restrict__ f, const Grid &g
 // ---------------------------------------------------------------------------
 // LB: AA-pattern stream + collide
 // ---------------------------------------------------------------------------
+// Value v of the lane CTRL names (a DPP wave shift or rotation by one lane).
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+    } else {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+        return __builtin_bit_cast(T, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    }
+}
+
+// Odd-step stores of the ten populations that move along x, for LB rows held
+// whole by consecutive lanes: RW = 1, a row is one wavefront (64 nodes);
+// RW = 2, a row is two consecutive wavefronts (128 nodes).  Node x's value
+// belongs at x + c_x; each lane instead stores, at its own x (in the
+// destination row), the value of node x - c_x, taken from the neighbouring
+// lane by a wave shift (across the two halves of a row through LDS, and
+// around the row's periodic seam).  Each wavefront then writes whole lines
+// instead of lines offset by one node.  xv, xa, xf: per population the value,
+// the aligned slot and whether the destination row is fluid (the same for the
+// whole row); own: the node is this thread's to update.  Every lane of the
+// block must get here.
+template <typename S, int RW, typename T>
+__device__ __forceinline__ void aligned_x_stores(S *__restrict__ f, const T *xv, const uint32_t *xa, const bool *xf,
+                                                 bool own)
+{
+    constexpr int BACK = RW == 1 ? 0x13c : 0x138;  // lane k takes lane k - 1 (wave_ror:1 / wave_shr:1)
+    constexpr int FWD = RW == 1 ? 0x134 : 0x130;   // lane k takes lane k + 1 (wave_rol:1 / wave_shl:1)
+    // the block's linear thread index (k_lb runs two-dimensional blocks)
+    const int tid = (int)(threadIdx.y * blockDim.x + threadIdx.x);
+    const int lane = tid & 63, wave = tid >> 6;
+    const int ow = own ? 1 : 0;
+    T vs[10];
+    int os[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        if (cx(xpop(k)) > 0) {
+            vs[k] = dpp_move<BACK>(xv[k]);
+            os[k] = dpp_move<BACK>(ow);
+        } else {
+            vs[k] = dpp_move<FWD>(xv[k]);
+            os[k] = dpp_move<FWD>(ow);
+        }
+    }
+    if constexpr (RW == 2) {
+        // the value leaving one half of the row enters the other half (the
+        // second half's last node wraps to the first half's first)
+        __shared__ T ev[16][10];
+        __shared__ int eo[16][10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            if (lane == (cx(xpop(k)) > 0 ? 63 : 0)) {
+                ev[wave][k] = xv[k];
+                eo[wave][k] = ow;
+            }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            if (lane == (cx(xpop(k)) > 0 ? 0 : 63)) {
+                vs[k] = ev[wave ^ 1][k];
+                os[k] = eo[wave ^ 1][k];
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k)
+        if (xf[k] && os[k])
+            store_through(pop_at(f, xa[k]), Pop<S>::put(vs[k], xpop(k)));
+}
+
 // Collision of node (x, y, zf) whose populations d (canonical order, time t)
 // are in hand, with the immersed-boundary force density (fx, fy, fz) of this
 // step (body force and external field are added here), and the AA write-back.
-template <typename S, bool ODD, typename T = typename Pop<S>::C>
+// RW > 0: whole LB rows per lane group, odd steps store the x-moving
+// populations aligned (aligned_x_stores); write == false: the node is not
+// this thread's, nothing is stored or flagged (its lanes still take part).
+template <typename S, bool ODD, int RW = 0, typename T = typename Pop<S>::C>
 __device__ __forceinline__ void lb_collide(S *__restrict__ f, const T *__restrict__ Fext, int *err,
-                                           const LBArgs &a, int x, int y, int zf, const T *d, T fx, T fy, T fz)
+                                           const LBArgs &a, int x, int y, int zf, const T *d, T fx, T fy, T fz,
+                                           bool write = true)
 {
     const Grid &g = a.g;
     const long long n = g.n;
@@ -300,12 +388,16 @@ __device__ __forceinline__ void lb_collide(S *__restrict__ f, const T *__restric
     const T uy = (my + T(0.5) * Fy) / rho;
     const T uz = (mz + T(0.5) * Fz) / rho;
     const T uu = ux * ux + uy * uy + uz * uz;
-    if (!(fabs(drho) < T(0.5)))
+    if (write && !(fabs(drho) < T(0.5)))
         atomicOr(err, kErrDensity);
-    if (uu > T(0.09))
+    if (write && uu > T(0.09))
         atomicOr(err, kErrMach);
 
     const T tinv = T(a.tau_inv), guo = T(a.guo);
+    constexpr bool AL = ODD && RW > 0;
+    T xv[10] = {};
+    uint32_t xa[10] = {};
+    bool xf[10] = {};
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
         const T w = wgt<T>(i);
@@ -324,11 +416,20 @@ __device__ __forceinline__ void lb_collide(S *__restrict__ f, const T *__restric
             post -= T(6) * w * rho * cuw;
         }
         const uint32_t n32 = (uint32_t)g.pp, me32 = (uint32_t)me;
-        if (!ODD || !fluid)
-            store_through(pop_at(f, opp(i) * n32 + me32), Pop<S>::put(post, i));
-        else
-            store_through(pop_at(f, i * n32 + dst), Pop<S>::put(post, i));
+        if (AL && cx(i) != 0)
+            xf[xslot(i)] = fluid;
+        if (AL && cx(i) != 0 && fluid) {
+            xv[xslot(i)] = post;
+            xa[xslot(i)] = i * n32 + dst - (cx(i) > 0 ? b.xp : b.xm);
+        } else if (write) {
+            if (!ODD || !fluid)
+                store_through(pop_at(f, opp(i) * n32 + me32), Pop<S>::put(post, i));
+            else
+                store_through(pop_at(f, i * n32 + dst), Pop<S>::put(post, i));
+        }
     }
+    if constexpr (AL)
+        aligned_x_stores<S, RW>(f, xv, xa, xf, write);
 }
 
 // LB update of node (x, y, zf): load its populations, collide, write back.
@@ -369,7 +470,10 @@ __device__ __forceinline__ void bulk_lb_block(int b, S *__restrict__ f, const T 
 // force and spreading kernels, which update the active tiles themselves.
 // In the AA pattern each node reads and writes only its own 19 slots, so the
 // two node sets never touch the same memory.
-template <typename S, bool ODD>
+// RW > 0 (the block's rows are the lattice's whole rows of 64 or 128 nodes):
+// odd steps store the x-moving populations aligned; every lane takes part,
+// rows beyond the lattice on copies of its last row that store nothing.
+template <typename S, bool ODD, int RW>
 __global__ __launch_bounds__(1024) void k_lb(S *__restrict__ f, const typename Pop<S>::C *__restrict__ Fext,
                                             const uint8_t *__restrict__ act, uint32_t *ctr, int *err, LBArgs a)
 {
@@ -377,6 +481,20 @@ __global__ __launch_bounds__(1024) void k_lb(S *__restrict__ f, const typename P
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int zf = blockIdx.z;
+    if constexpr (ODD && RW > 0) {
+        const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+        if (act == nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid == 0)
+            ctr[0] = ctr[1] + 1u;
+        const bool in = y < a.g.ny;
+        const int yc = in ? y : a.g.ny - 1;
+        bool own = in;
+        if (act != nullptr)
+            own = own && act[tile_of(a.g, x, yc, zf)] != act_stamp(ctr[1]);
+        T d[19];
+        load_pops<S, ODD>(f, a.g, x, yc, zf, d);
+        lb_collide<S, ODD, RW>(f, Fext, err, a, x, yc, zf, d, T(0), T(0), T(0), own);
+        return;
+    }
     if (act == nullptr) {
         // only the thread that advances the counter reads it: the other
         // wavefronts go straight to their populations
@@ -1897,9 +2015,20 @@ template <typename S, bool ODD>
 static void lb_launch(const Dev &d, const LBArgs &a, bool bulk, hipStream_t s)
 {
     using T = typename Pop<S>::C;
-    const int bx = a.g.nx >= 128 ? 128 : (int)lb_block(a.g).x, by = 1024 / bx;
+    const int bx = a.g.nx >= 128 ? 128 : (int)lb_block(a.g).x;
+    // whole rows of 128 or 64 nodes per block: aligned odd-step x stores;
+    // rows of 128 in blocks of two rows, so that the exchange between a row's
+    // halves waits for four wavefronts, not sixteen
+    const int rw = a.g.nx == bx ? (bx == 128 ? 2 : (bx == 64 ? 1 : 0)) : 0;
+    const int by = rw == 2 ? 2 : 1024 / bx;
     const dim3 blk(bx, by, 1), grd((a.g.nx + bx - 1) / bx, (a.g.ny + by - 1) / by, a.g.nzf);
-    k_lb<S, ODD><<<grd, blk, 0, s>>>((S *)d.f, (const T *)d.Fext, bulk ? d.act : nullptr, d.ctr, d.err, a);
+    const uint8_t *ac = bulk ? d.act : nullptr;
+    if (rw == 2)
+        k_lb<S, ODD, 2><<<grd, blk, 0, s>>>((S *)d.f, (const T *)d.Fext, ac, d.ctr, d.err, a);
+    else if (rw == 1)
+        k_lb<S, ODD, 1><<<grd, blk, 0, s>>>((S *)d.f, (const T *)d.Fext, ac, d.ctr, d.err, a);
+    else
+        k_lb<S, ODD, 0><<<grd, blk, 0, s>>>((S *)d.f, (const T *)d.Fext, ac, d.ctr, d.err, a);
 }
 
 hipError_t launch_lb(int prec, const Dev &d, const LBArgs &a, int p, int bulk, hipStream_t s)

@@ -22,6 +22,7 @@ CASES = {
     "walls_ragged": Domain(30, 22, 19, tau=0.8, u_wall_lo=(0.01, -0.005, 0), u_wall_hi=(-0.02, 0.01, 0)),
     "periodic_ragged": Domain(20, 13, 11, wall_mode=PERIODIC_ALL, tau=1.3, body_force=(1e-5, 0, -2e-5)),
     "wide_rows_ragged": Domain(140, 9, 10, tau=0.9, u_wall_lo=(0.004, 0.002, 0), u_wall_hi=(-0.003, 0, 0)),
+    "rows128_walls": Domain(128, 11, 9, tau=0.85, u_wall_lo=(0.006, -0.002, 0), u_wall_hi=(-0.004, 0.003, 0)),
 }
 
 
@@ -47,9 +48,10 @@ def test_lb_one_step_within_one_rounding(prec, name):
 
 @pytest.mark.parametrize("prec", [iblb.FP16_DEV, iblb.BF16_DEV])
 @pytest.mark.parametrize("nsteps", [2, 7])
-def test_lb_error_grows_at_most_one_rounding_per_step(prec, nsteps):
-    d = CASES["walls_ragged"]
-    announce(f"lb 16-bit prec={prec} {nsteps} steps")
+@pytest.mark.parametrize("name", ["walls_ragged", "rows128_walls"])
+def test_lb_error_grows_at_most_one_rounding_per_step(prec, nsteps, name):
+    d = CASES[name]
+    announce(f"lb 16-bit prec={prec} {name} {nsteps} steps")
     F = random_force_field((d.nz_fluid, d.ny, d.nx), 2e-4, seed=8)
     o = O.OracleSim(d)
     o.set_force(F)

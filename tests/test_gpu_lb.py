@@ -19,6 +19,12 @@ CASES = {
     # rows of 128 nodes or more run in 128-wide blocks: one full block and a
     # ragged one of 12 nodes per row
     "wide_rows_ragged": Domain(140, 9, 10, tau=0.9, u_wall_lo=(0.004, 0.002, 0), u_wall_hi=(-0.003, 0, 0)),
+    # rows of exactly 128 or 64 nodes are held whole by one block (two or
+    # one wavefronts): odd steps store the x-moving populations aligned,
+    # taking each value from the neighbouring lane; ny leaves the last block
+    # of rows partly outside the lattice
+    "rows128_walls": Domain(128, 11, 9, tau=0.85, u_wall_lo=(0.006, -0.002, 0), u_wall_hi=(-0.004, 0.003, 0)),
+    "rows64_periodic": Domain(64, 19, 9, wall_mode=PERIODIC_ALL, tau=1.1, body_force=(2e-5, -1e-5, 1e-5)),
 }
 
 
