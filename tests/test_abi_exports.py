@@ -44,3 +44,38 @@ def test_workspace_bytes_validates_domain_without_gpu():
             iblb.workspace_bytes(bad, iblb.FP64)
     with pytest.raises(iblb.IBLBError):
         iblb.workspace_bytes(w.domain, 5)
+
+
+def test_tile_shape_is_one_wavefront_of_power_of_two_extents():
+    from paper_2305_18919_amd import iblb
+    tx, ty, tz = iblb.tile_shape()
+    assert tx * ty * tz == 64
+    assert all(e >= 1 and (e & (e - 1)) == 0 for e in (tx, ty, tz))
+
+
+def test_step_geometry_counts_the_stencil_tiles_by_brute_force():
+    """bench.step_geometry's active nodes (the tiles reached by some vertex's
+    4^3 stencil, in the library's tile shape) against a direct count over the
+    stencil nodes, on a small droplet next to a wall and across the x seam."""
+    import numpy as np
+    import bench
+    from paper_2305_18919_amd import iblb
+    from paper_2305_18919_amd.inputs import Domain, sphere_mesh
+    dom = Domain(37, 26, 20, tau=0.9)
+    mesh = sphere_mesh(2, 5.0, (1.2, 12.3, 0.5 + 5.0 + 0.4), (1e-3, 1e-3, 1e-3), amplitude=0.03, seed=2)
+    q = np.asarray(mesh.vertices)
+    TX, TY, TZ = iblb.tile_shape()
+    nzf = dom.nz - 2
+    tiles = set()
+    for p in q:
+        b = np.floor(p).astype(int) - 1
+        for k in range(64):
+            x = (b[0] + (k & 3)) % dom.nx
+            y = (b[1] + ((k >> 2) & 3)) % dom.ny
+            zf = b[2] + (k >> 4) - 1
+            if 0 <= zf < nzf:
+                tiles.add((x // TX, y // TY, zf // TZ))
+    want = sum(min(TX, dom.nx - TX * a) * min(TY, dom.ny - TY * c) * min(TZ, nzf - TZ * e) for a, c, e in tiles)
+    geo = bench.step_geometry(dom, q, {"block_x": 32, "share_forces": 0.5})
+    assert geo["active_nodes"] == want
+    assert sum(geo["lb_nodes"].values()) == dom.n_fluid
