@@ -8,13 +8,14 @@
 //             nodal_force_V), wall force (Eq. LJ_interaction), FP64 block
 //             partials of V - V0, and the vertex's phi4 stencil weights; one
 //             more block compacts the step's active tiles
-//   k_spread  one block per active 4x4x4 tile: gathers phi_i w_i(x) of the
+//   k_spread  one block per active tile (kTileX x kTileY x kTileZ nodes, one
+//             lane each): gathers phi_i w_i(x) of the
 //             vertices whose stencil reaches the tile, in ascending vertex order
 //             (Eq. ibm-governing_eq2), no floating-point atomics, then the LB
 //             update of the tile's nodes with that force; further blocks of the
 //             same dispatch run the LB of every other fluid node (Eqs. LBeq, feq)
 //   k_moments u(t+1) on the nodes of the active tiles, with F(t)/2
-//   k_move    one wavefront per vertex, one lane per stencil node:
+//   k_move    one or two vertices per wavefront, one lane per stencil node:
 //             interpolation (Eq. ibm-governing_eq1), Euler update (Eq.
 //             ibm_update_pos), the stamps and vertex masks of the tiles the
 //             vertex reaches at t + 1, and the device step counter.
@@ -28,7 +29,7 @@
 // launch.
 //
 // Data layout (all structure-of-arrays, x fastest):
-//   populations f[19][N] (N fluid nodes), deviations f_i - w_i rho0, in place
+//   populations f[19][pp] (N fluid nodes, row pitch pp >= N), deviations f_i - w_i rho0, in place
 //   with the AA pattern: at even times slot (i, x) holds f_i(x); at odd times
 //   slot (opp(i), x - c_i) holds f_i(x) (slot (i, x) when x - c_i is solid).
 //   force density F[3][N], valid on a tile when stamp[tile] == step + 1.
@@ -898,7 +899,7 @@ __device__ __forceinline__ double volume_factor(const double *__restrict__ parti
 }
 
 // ---------------------------------------------------------------------------
-// Spreading, one 256-thread block per active tile (gather form, no FP atomics)
+// Spreading, one block per active tile (gather form, no FP atomics)
 // ---------------------------------------------------------------------------
 // A listed vertex as the gather needs it: its phi4 weight at each of the
 // tile's local coordinates per axis (kTileX, then kTileY, then kTileZ of
@@ -1030,8 +1031,10 @@ constexpr int kSpreadWaves = sizeof(typename Pop<S>::C) == 8 ? 1 : 3;
 // wavefront w sums the w-th contiguous part of each pass's groups of four
 // entries for the 64 nodes of the tile (one per lane), and the partial sums are
 // added in wavefront order, so every node's sum has a fixed order.  Wavefront
-// 0 fetches its node's populations as soon as the tile is known and finishes
-// with the LB update of the tile's nodes.
+// 0 fetches its node's populations once it has counted its mask words (so
+// that waiting for the words does not wait for them) and finishes with the
+// LB update of the tile's nodes.  Block indices map to these roles through
+// spread_role (part of the LB blocks come first).
 template <typename S, int P, int NW, typename T = typename Pop<S>::C>
 __device__ __forceinline__ void spread_dispatch(int blk, const Base *__restrict__ base, const T *__restrict__ wts,
                                                 const T *__restrict__ phiSW, const T *__restrict__ gV,
