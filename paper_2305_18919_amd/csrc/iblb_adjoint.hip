@@ -577,11 +577,18 @@ __device__ __forceinline__ int wave_incl_scan(int c, int lane)
 // is what stays in ub for the LB adjoint.  The list is in ascending vertex
 // order (entry e found by a binary search over the threads' first list
 // positions, as in the forward spreading) and four wavefronts each sum a
-// quarter of it, so the sums have a fixed order (no atomics).  The listed
+// quarter of its groups of four entries (one 4-wide LDS read per axis and
+// group), so the sums have a fixed order (no atomics).  The listed
 // vertices' positions and qb1 are loaded in one round and their
 // one-dimensional weights at the tile's coordinates (kTileW per vertex) are
 // evaluated one per thread; wavefront 0 fetches its nodes' f1, U and lam
 // while the sums run.
+// Four values read from LDS as one vector.
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad4 {
+    T v[4];
+};
+
 template <typename P>
 __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *__restrict__ q,
                                                        const double *__restrict__ qb1, const P *__restrict__ f1,
@@ -595,7 +602,10 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     __shared__ uint64_t swd[4 * 256];  // the tile's mask words
     __shared__ int spre[256];          // each thread's first list position within its wavefront
-    __shared__ P sw[kTileCap * kTileW];  // per listed vertex: its weights at the tile's x, y and z coordinates
+    // per listed vertex e its weight at tile coordinate r (x coordinates, then
+    // y, then z) in sw[r][e], so that one 4-wide read per axis gives four
+    // entries' weights
+    __shared__ __align__(32) P sw[kTileW][kTileCap];
     __shared__ double sqb[kTileCap * 3];  // and qb1
     __shared__ double sq[kTileCap * 3];   // and q
     __shared__ int swt[4];
@@ -701,8 +711,14 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
                 o = wrapn(y0 + l - b, g.ny);
             else
                 o = g.walls ? z0 + l - b : wrapn(z0 + l - b, g.nz);
-            sw[it] = P(o >= 0 && o <= 3 ? phi4d(double(b + o) - qa) : 0.0);
+            sw[r][e] = P(o >= 0 && o <= 3 ? phi4d(double(b + o) - qa) : 0.0);
         }
+        // the list padded to whole groups of four with zero entries
+        const int npad = (nent + 3) & ~3;
+        for (int it = tid; it < (npad - nent) * kTileW; it += 256)
+            sw[it % kTileW][nent + it / kTileW] = P(0);
+        for (int it = tid; it < (npad - nent) * 3; it += 256)
+            sqb[nent * 3 + it] = 0.0;
         __syncthreads();
         // wavefront 0 fetches its node's f1, U and lam now: the loads overlap
         // the sums below, which read LDS only
@@ -715,15 +731,22 @@ __global__ __launch_bounds__(256) void ka_spread_tiles(AdjArgs A, const double *
             }
             for (int k = 0; k < 3; ++k) uv[k] = U[k * n + id];
         }
-        const int chunk = (nent + 3) >> 2;
-        const int e0 = wave * chunk, e1 = min(nent, e0 + chunk);
+        // wavefront w sums the w-th contiguous quarter of the groups of four
+        const int ng = npad >> 2, gq = (ng + 3) >> 2;
+        const int g0 = wave * gq, g1 = min(ng, g0 + gq);
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            const double w = double(sw[e * kTileW + lx]) * double(sw[e * kTileW + kTileX + ly]) *
-                             double(sw[e * kTileW + kTileX + kTileY + lz]);
-            s0 += sqb[e * 3] * w;
-            s1 += sqb[e * 3 + 1] * w;
-            s2 += sqb[e * 3 + 2] * w;
+        for (int gi = g0; gi < g1; ++gi) {
+            const int e = gi * 4;
+            const Quad4<P> wx = *reinterpret_cast<const Quad4<P> *>(&sw[lx][e]);
+            const Quad4<P> wy = *reinterpret_cast<const Quad4<P> *>(&sw[kTileX + ly][e]);
+            const Quad4<P> wz = *reinterpret_cast<const Quad4<P> *>(&sw[kTileX + kTileY + lz][e]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double w = double(wx.v[j]) * double(wy.v[j]) * double(wz.v[j]);
+                s0 += sqb[(e + j) * 3] * w;
+                s1 += sqb[(e + j) * 3 + 1] * w;
+                s2 += sqb[(e + j) * 3 + 2] * w;
+            }
         }
         if (wave > 0) {
             part[wave - 1][0][lane] = s0;
