@@ -53,6 +53,30 @@ def test_ragged_fp64(nsteps):
         compare(g, o, 4.5, 1e-13, 1e-12, f"ragged {nsteps}")
 
 
+@pytest.mark.parametrize("prec", [iblb.FP64, iblb.FP32_DEV])
+def test_dense_mesh_lists_staged_in_several_passes(prec):
+    """A level-4 icosphere (2562 vertices) of radius 6 in a periodic 32^3
+    lattice: 49 tiles list more than 128 vertices (up to 423), so the
+    spreading stages their lists in two to four passes of 128 entries, each
+    entry found by its binary search.  Forces, force density and positions
+    against the oracle after 3 steps."""
+    d = Domain(32, 32, 32, wall_mode=PERIODIC_ALL)
+    m = sphere_mesh(4, 6.0, (16.3, 16.2, 16.1), (1e-3, 0.0, 1e-3), amplitude=0.02, seed=9)
+    announce(f"dense mesh prec={prec}")
+    o = O.OracleSim(d, m)
+    o.step(3)
+    with iblb.Simulation(d, m, precision=prec) as g:
+        g.step(3)
+        g.sync()
+        if prec == iblb.FP64:
+            assert rel(g.nodal_forces(), o.nodal_forces()) < 1e-12
+            assert rel(g.force(), o.force()) < 1e-12
+            compare(g, o, 6.0, 1e-13, 1e-12, "dense fp64")
+        else:
+            assert rel(g.force(), o.force()) < 1e-5
+            compare(g, o, 6.0, 1e-7, 1e-5, "dense fp32")
+
+
 def test_droplet32_fp64_500_steps():
     w = c1_droplet()
     announce("droplet32 fp64 500 steps")
