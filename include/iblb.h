@@ -294,8 +294,10 @@ typedef struct {
                                      layer: 16, 32 or 64 (capped per member by its nx); 0 = the
                                      single-context rule (64 if nx >= 64, 32 if nx >= 32, else 16) */
     int32_t spread_blocks_per_cu; /* spreading blocks of the whole batch per compute unit, 1..8,
-                                     shared out in proportion to the members' active tiles;
-                                     0 = 2 (1 with FP64) */
+                                     shared out in proportion to the members' active tiles; the
+                                     blocks are two wavefronts (four while a stepped member has
+                                     more than 32768 vertices); 0 = eight wavefronts per compute
+                                     unit (four with FP64) */
     int32_t vertices_per_wave;    /* interpolation and move: 1 or 2 vertices per 64-lane wavefront;
                                      0 = 1 while the batch has at most 32 vertices per compute unit */
     int32_t reserved;             /* 0 */
@@ -327,7 +329,8 @@ int iblb_batch_set_config(iblb_batch *b, iblb_batch_config const *cfg);
 /* Autotuner: times trial_steps (rounded up to a multiple of 16) graph-replayed
  * steps of the batch for each launch shape visited by two passes of
  * coordinate descent over lb_block_x {16, 32, 64}, lb_share_forces {0.3,
- * 0.45, 0.6, 0.75}, spread_blocks_per_cu {1, 2, 3} and vertices_per_wave
+ * 0.45, 0.6, 0.75, 0.9}, spread_blocks_per_cu {2, 4, 6} ({1, 2, 3} with
+ * four-wavefront spreading blocks) and vertices_per_wave
  * {1, 2}, keeps the fastest and writes its time per step (ms).  The members'
  * device state is copied aside first and restored afterwards (needs that much
  * free device memory), so the trial steps leave no trace. */

@@ -1202,6 +1202,7 @@ struct iblb_batch {
     int off[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
     BatchCfg cfg;
     int vpw_used = 1;
+    int nw_used = 4;                // wavefronts per spreading block
     bool dirty = true;              // tables to rebuild before the next launch
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -1233,10 +1234,21 @@ void bdrop_graph(iblb_batch *b)
 // the single-context LB block width for a lattice of width nx
 int lb_width_rule(int nx) { return nx >= 64 ? 64 : (nx >= 32 ? 32 : 16); }
 
+// Wavefronts per spreading block of a batch: two while every stepped member's
+// vertex mask fits four words per thread of them (at most 32768 vertices),
+// else four, as for a single context.
+int spread_nw(const iblb_batch *b)
+{
+    for (size_t k = 0; k < b->mem.size(); ++k)
+        if (b->status[k] == IBLB_OK && b->mem[k]->m.nwords > 4 * 128) return 4;
+    return 2;
+}
+
 BatchCfg resolved(const iblb_batch *b)
 {
     BatchCfg c = b->cfg;
-    if (c.spread_per_cu == 0) c.spread_per_cu = b->prec == IBLB_FP64 ? 1 : 2;
+    // default: eight spreading wavefronts per CU (four with FP64)
+    if (c.spread_per_cu == 0) c.spread_per_cu = (b->prec == IBLB_FP64 ? 4 : 8) / spread_nw(b);
     if (c.vpw == 0) {
         long long nv = 0;
         for (size_t k = 0; k < b->mem.size(); ++k)
@@ -1255,6 +1267,7 @@ int build_tables(iblb_batch *b)
     // launches already queued read the current records and tables
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     const BatchCfg cfg = resolved(b);
+    const int nw = spread_nw(b), nsub = 4 / nw;
     const int n = (int)b->mem.size();
     std::vector<DomRec> recs((size_t)n);
     std::vector<uint32_t> tab[4];
@@ -1281,7 +1294,7 @@ int build_tables(iblb_batch *b)
         r.nsp = (int)std::max(1ll, std::min(want, (long long)c->g.nt));
         r.mblocks = std::max(1, moments_blocks(c->g, c->m));
         if ((long long)c->m.nparts + scan_block_count(c->g) + nlb[(size_t)k] >= (1ll << 24) ||
-            (long long)r.nsp + nlb[(size_t)k] >= (1ll << 24))
+            (long long)r.nsp + (long long)nsub * nlb[(size_t)k] >= (1ll << 24))
             return bfail(b, IBLB_E_INVAL, "member " + std::to_string(k) + " has too many blocks for a batch");
     }
     auto entry = [](int k, int blk) { return (uint32_t)k | ((uint32_t)blk << 8); };
@@ -1301,7 +1314,7 @@ int build_tables(iblb_batch *b)
             for (int j = 0; j < recs[(size_t)k].nsp; ++j) tab[B_SPREAD].push_back(entry(k, j));
     for (int k = 0; k < n; ++k)
         if (on(k))
-            for (int j = 0; j < nlb[(size_t)k] - recs[(size_t)k].lb0; ++j)
+            for (int j = 0; j < nsub * (nlb[(size_t)k] - recs[(size_t)k].lb0); ++j)
                 tab[B_SPREAD].push_back(entry(k, recs[(size_t)k].nsp + j));
     for (int k = 0; k < n; ++k)
         if (on(k))
@@ -1333,6 +1346,7 @@ int build_tables(iblb_batch *b)
     if (total) BHIP_TRY(b, hipMemcpyAsync(b->tabs, all.data(), total * 4, hipMemcpyHostToDevice, b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     b->vpw_used = cfg.vpw;
+    b->nw_used = nw;
     b->dirty = false;
     return IBLB_OK;
 }
@@ -1340,7 +1354,8 @@ int build_tables(iblb_batch *b)
 hipError_t batch_enqueue(iblb_batch *b, int p)
 {
     for (int w = 0; w < 4; ++w) {
-        hipError_t e = launch_batch(b->prec, w, b->recs, b->tabs + b->off[w], b->cnt[w], p, b->vpw_used, b->stream);
+        hipError_t e = launch_batch(b->prec, w, b->recs, b->tabs + b->off[w], b->cnt[w], p, b->vpw_used, b->nw_used,
+                                    b->stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1620,9 +1635,11 @@ int iblb_batch_tune(iblb_batch *b, int32_t trial_steps, double *best_ms_per_step
             if (dim == 0)
                 for (int v : {16, 32, 64}) { c.lb_bx = v; cands.push_back(c); }
             if (dim == 1)
-                for (double v : {0.3, 0.45, 0.6, 0.75}) { c.lb_share = v; cands.push_back(c); }
+                for (double v : {0.3, 0.45, 0.6, 0.75, 0.9}) { c.lb_share = v; cands.push_back(c); }
+            // spreading wavefronts per CU: 4, 8, 12 (the most the register
+            // budget holds at once with FP32)
             if (dim == 2)
-                for (int v : {1, 2, 3}) { c.spread_per_cu = v; cands.push_back(c); }
+                for (int v : {4, 8, 12}) { c.spread_per_cu = v / spread_nw(b); cands.push_back(c); }
             if (dim == 3)
                 for (int v : {1, 2}) { c.vpw = v; cands.push_back(c); }
             const BatchCfg cur = best;

@@ -190,9 +190,10 @@ hipError_t launch_stamp(const Dev &d, const Grid &g, const MeshArgs &m, int p, h
 // One batched dispatch `which` over `nblocks` blocks: entry k of `tab` is block
 // k's domain (low 8 bits) and its block index within the single-domain
 // dispatch of that domain (upper 24 bits).  vpw: vertices per wavefront of the
-// move (1 or 2).
+// move (1 or 2); spread_nw: wavefronts per block of the spreading dispatch (2
+// or 4; its LB blocks of 256 nodes then span 4 / spread_nw table entries).
 hipError_t launch_batch(int prec, int which, const DomRec *recs, const uint32_t *tab, int nblocks, int p, int vpw,
-                        hipStream_t s);
+                        int spread_nw, hipStream_t s);
 // err[k] = *recs[k].d.err for k < n
 hipError_t launch_batch_errors(const DomRec *recs, int n, int *err, hipStream_t s);
 // Discrete adjoint of the step (iblb_adjoint.hip), FP64 arithmetic: the

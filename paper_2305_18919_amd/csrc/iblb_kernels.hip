@@ -1512,15 +1512,16 @@ __global__ __launch_bounds__(256) void kb_forces(const DomRec *__restrict__ R, c
                              d.err, r.a, r.m, r.bxw, r.nbx, r.nby);
 }
 
-template <typename S, int P, typename T = typename Pop<S>::C>
-__global__ __launch_bounds__(256, kSpreadWaves<S>) void kb_spread(const DomRec *__restrict__ R, const uint32_t *__restrict__ tab)
+template <typename S, int P, int NW, typename T = typename Pop<S>::C>
+__global__ __launch_bounds__(64 * NW, kSpreadWaves<S>) void kb_spread(const DomRec *__restrict__ R,
+                                                                     const uint32_t *__restrict__ tab)
 {
     const uint32_t e = tab[blockIdx.x];
     const DomRec &r = R[e & 0xffu];
     const Dev &d = r.d;
     if (*d.err != 0)
         return;  // the member turned unstable: its blocks stop until the check freezes it
-    spread_dispatch<S, P, 4, T>((int)(e >> 8), d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV,
+    spread_dispatch<S, P, NW, T>((int)(e >> 8), d.base, (const T *)d.wts, (const T *)d.phiSW, (const T *)d.gV,
                              d.partials, d.ctr, d.mask, d.acnt, d.alist, (T *)d.F, d.stamp, (S *)d.f,
                              (const T *)d.Fext, d.err, r.a, r.m, d.act, r.nsp, r.lb0, r.bxw, r.nbx, r.nby);
 }
@@ -2191,12 +2192,17 @@ hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &
 }
 
 template <typename S, int P>
-static void batch_launch(int which, const DomRec *R, const uint32_t *tab, int nb, int vpw, hipStream_t s)
+static void batch_launch(int which, const DomRec *R, const uint32_t *tab, int nb, int vpw, int nw, hipStream_t s)
 {
     using T = typename Pop<S>::C;
     switch (which) {
     case B_FORCES: kb_forces<S, P><<<nb, 256, 0, s>>>(R, tab); break;
-    case B_SPREAD: kb_spread<S, P><<<nb, 256, 0, s>>>(R, tab); break;
+    case B_SPREAD:
+        if (nw == 2)
+            kb_spread<S, P, 2><<<nb, 128, 0, s>>>(R, tab);
+        else
+            kb_spread<S, P, 4><<<nb, 256, 0, s>>>(R, tab);
+        break;
     case B_MOMENTS: kb_moments<S, P><<<nb, 256, 0, s>>>(R, tab); break;
     default:
         if (vpw == 2)
@@ -2207,13 +2213,14 @@ static void batch_launch(int which, const DomRec *R, const uint32_t *tab, int nb
 }
 
 hipError_t launch_batch(int prec, int which, const DomRec *recs, const uint32_t *tab, int nblocks, int p, int vpw,
-                        hipStream_t s)
+                        int spread_nw, hipStream_t s)
 {
     if (nblocks <= 0)
         return hipSuccess;
     return with_pop_type(prec, [&](auto tag) {
         using S = decltype(tag);
-        p ? batch_launch<S, 1>(which, recs, tab, nblocks, vpw, s) : batch_launch<S, 0>(which, recs, tab, nblocks, vpw, s);
+        p ? batch_launch<S, 1>(which, recs, tab, nblocks, vpw, spread_nw, s)
+          : batch_launch<S, 0>(which, recs, tab, nblocks, vpw, spread_nw, s);
     });
 }
 

@@ -159,8 +159,8 @@ def test_tune_leaves_no_trace():
             cfg = b.config
             announce(f"  tuned {cfg} at {ms:.4f} ms/step")
             assert ms > 0
-            assert cfg["lb_block_x"] in (16, 32, 64) and cfg["spread_blocks_per_cu"] in (1, 2, 3)
-            assert cfg["vertices_per_wave"] in (1, 2) and cfg["lb_share_forces"] in (0.3, 0.45, 0.6, 0.75)
+            assert cfg["lb_block_x"] in (16, 32, 64) and cfg["spread_blocks_per_cu"] in (2, 4, 6)
+            assert cfg["vertices_per_wave"] in (1, 2) and cfg["lb_share_forces"] in (0.3, 0.45, 0.6, 0.75, 0.9)
             for s, (q, f) in zip(sims, before):
                 assert s.t == 8
                 assert np.array_equal(s.vertices(), q) and np.array_equal(s.populations(), f)
