@@ -77,6 +77,41 @@ def test_dense_mesh_lists_staged_in_several_passes(prec):
             compare(g, o, 6.0, 1e-7, 1e-5, "dense fp32")
 
 
+ROWS128 = {
+    "walls": dict(tau=0.8, u_wall_lo=(0.004, -0.001, 0), u_wall_hi=(-0.003, 0.002, 0)),
+    "periodic": dict(wall_mode=PERIODIC_ALL),
+}
+
+
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("prec", [iblb.FP32_DEV, iblb.FP16_DEV])
+@pytest.mark.parametrize("case", sorted(ROWS128))
+def test_rows128_odd_steps_against_oracle(case, prec, graph):
+    """A lattice of 128-node rows (odd ny: the last LB block of each layer has
+    one row), so that the LB blocks of the forces and spreading dispatches
+    span whole rows; the droplet straddles the periodic x seam, so active
+    tiles sit at both ends of rows.  Populations, positions and velocities
+    against the oracle after 7 steps (4 odd)."""
+    d = Domain(128, 13, 12, **ROWS128[case])
+    zc = 6.0 if case == "periodic" else 0.5 + 4.0 + 0.7
+    m = sphere_mesh(2, 4.0, (1.4, 6.3, zc), (1e-3, 2e-3, 1e-3), amplitude=0.02, seed=7,
+                    **({} if case == "periodic" else dict(eps_lo=2e-3, r_cut=2.0)))
+    announce(f"rows128 {case} prec={prec} graph={graph}")
+    o = O.OracleSim(d, m)
+    o.step(7)
+    with iblb.Simulation(d, m, precision=prec, graph=graph) as g:
+        g.step(7)
+        g.sync()
+        ef = rel(g.populations(), o.populations())
+        announce(f"  |df|/|f|={ef:.3e}")
+        if prec == iblb.FP32_DEV:
+            assert ef < 1e-6
+            compare(g, o, 4.0, 1e-7, 1e-5, f"rows128 {case} fp32")
+        else:
+            assert ef < 5e-3
+            compare(g, o, 4.0, 1e-4, 5e-3, f"rows128 {case} fp16")
+
+
 def test_droplet32_fp64_500_steps():
     w = c1_droplet()
     announce("droplet32 fp64 500 steps")
