@@ -75,6 +75,18 @@ __device__ __forceinline__ constexpr T wgt(int i)
 {
     return i == 0 ? T(1.0 / 3.0) : (i <= 6 ? T(1.0 / 18.0) : T(1.0 / 36.0));
 }
+// c_i . (x, y, z) with only the nonzero components of c_i (a product with a
+// zero component is not folded away in IEEE arithmetic).
+template <typename T>
+__device__ __forceinline__ T cdot(int i, T x, T y, T z)
+{
+    T r = T(0);
+    bool any = false;
+    if (cx(i) != 0) { r = cx(i) > 0 ? x : -x; any = true; }
+    if (cy(i) != 0) { const T t = cy(i) > 0 ? y : -y; r = any ? r + t : t; any = true; }
+    if (cz(i) != 0) { const T t = cz(i) > 0 ? z : -z; r = any ? r + t : t; any = true; }
+    return r;
+}
 // The collision pairs population i (odd) with i + 1: opposite velocities,
 // equal weights.
 __device__ constexpr bool pairs_opposite()
@@ -456,8 +468,8 @@ __device__ __forceinline__ void lb_collide(S *__restrict__ f, const T *__restric
 #pragma unroll
     for (int i = 1; i < 19; i += 2) {
         const T w = wgt<T>(i);
-        const T cu = T(cx(i)) * ux + T(cy(i)) * uy + T(cz(i)) * uz;
-        const T cF = T(cx(i)) * Fx + T(cy(i)) * Fy + T(cz(i)) * Fz;
+        const T cu = cdot<T>(i, ux, uy, uz);
+        const T cF = cdot<T>(i, Fx, Fy, Fz);
         const T wr = w * rho, wg = w * guo;
         const T qe = w * drho + wr * (T(4.5) * cu * cu - T(1.5) * uu), qo = T(3) * wr * cu;
         const T se = wg * (T(9) * cF * cu - T(3) * uF), so = (T(3) * wg) * cF;
