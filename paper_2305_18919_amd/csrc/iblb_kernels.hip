@@ -888,6 +888,16 @@ __device__ __forceinline__ void forces_block(int blk, const double *__restrict__
         partials[blk] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// Block b of n renumbered so that the blocks the hardware dispatches to one
+// XCD (b mod 8, round-robin) take a contiguous range: the force blocks of one
+// XCD then read neighbouring vertices, whose positions share its L2.  A
+// permutation of [0, n), so results do not change.
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    const int q = n / 8, r = n % 8, x = b % 8, k = b / 8;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // Blocks [0, nparts) compute the interface forces, the next scan_blocks
 // blocks list the step's active tiles, and the blocks after them (if any) run
 // the first LB blocks of the nodes outside the active tiles (the spreading
@@ -905,7 +915,7 @@ __device__ __forceinline__ void forces_dispatch(int blk, const double *__restric
 {
     const int nscan = scan_blocks(a.g);
     if (blk < m.nparts)
-        forces_block<T>(blk, q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, err, a.g, m);
+        forces_block<T>(xcd_block(blk, m.nparts), q, Xref, inc4, fref, phiSW, gVout, base, wts, partials, err, a.g, m);
     else if (blk < m.nparts + nscan)
         scan_block(blk - m.nparts, act, acnt + P, alist, ctr[P]);
     else
