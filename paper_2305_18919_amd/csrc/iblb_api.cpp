@@ -1292,7 +1292,7 @@ int build_tables(iblb_batch *b)
         const int hint = std::max(1, c->m.tiles_hint);
         const long long want = hint_sum > 0 ? std::llround(budget * hint / (double)hint_sum) : 1;
         r.nsp = (int)std::max(1ll, std::min(want, (long long)c->g.nt));
-        r.mblocks = std::max(1, moments_blocks(c->g, c->m));
+        r.mblocks = std::max(1, moments_blocks(c->g, c->m, 4));
         if ((long long)c->m.nparts + scan_block_count(c->g) + nlb[(size_t)k] >= (1ll << 24) ||
             (long long)r.nsp + (long long)nsub * nlb[(size_t)k] >= (1ll << 24))
             return bfail(b, IBLB_E_INVAL, "member " + std::to_string(k) + " has too many blocks for a batch");

@@ -180,8 +180,8 @@ hipError_t launch_move(int prec, const Dev &d, const LBArgs &a, const MeshArgs &
 // (the spreading dispatch runs the rest)
 int lb_block_width(const Grid &g);
 double lb_share_with_forces();
-// blocks of the moments dispatch (launch sizing)
-int moments_blocks(const Grid &g, const MeshArgs &m);
+// blocks of the moments dispatch of `waves` wavefronts each (launch sizing)
+int moments_blocks(const Grid &g, const MeshArgs &m, int waves);
 // blocks that list the active tiles in the forces dispatch
 inline int scan_block_count(const Grid &g) { return (g.nt + 4095) / 4096; }
 // act stamps and vertex masks of the current step from the stored positions
