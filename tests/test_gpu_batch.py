@@ -105,6 +105,27 @@ def test_batch_agrees_with_members_stepped_alone(prec, tol):
         assert eq <= tol and ef <= tol
 
 
+def test_four_wave_spreading_blocks_agree_with_members_alone():
+    """A member of more than 32768 vertices (level-6 icosphere, 40962
+    vertices: 641 mask words per tile, beyond four words per thread of a
+    two-wavefront block) makes the batch's spreading run four-wavefront
+    blocks; it and a small member agree with the same contexts stepped
+    alone, at the FP32 tolerance of the two-wavefront batches."""
+    specs = [
+        (Domain(60, 60, 60, wall_mode=1),
+         sphere_mesh(6, 27.0, (30.3, 29.6, 30.1), (1e-3, 0.0, 1e-3), amplitude=0.005, seed=3)),
+        members()[1],
+    ]
+    announce("batch with four-wavefront spreading blocks vs alone")
+    ref = alone(specs, iblb.FP32_DEV, (7, 9))
+    got = batched(specs, iblb.FP32_DEV, (7, 9), vertices_per_wave=1)
+    for (d, m), (q, f), (qr, fr) in zip(specs, got, ref):
+        R = float(np.linalg.norm(m.ref_vertices - m.ref_vertices.mean(0), axis=1).max())
+        eq, ef = np.abs(q - qr).max() / R, rel(f, fr)
+        announce(f"  {d.nx}x{d.ny}x{d.nz} nv={m.n_vertices}: |dq|/R={eq:.2e} |df|/|f|={ef:.2e}")
+        assert eq <= 2e-6 and ef <= 2e-6
+
+
 def test_batch_fp64_matches_oracle():
     specs = members()
     announce("batch fp64 vs oracle, 12 steps")
