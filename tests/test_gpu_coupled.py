@@ -77,6 +77,29 @@ def test_dense_mesh_lists_staged_in_several_passes(prec):
             compare(g, o, 6.0, 1e-7, 1e-5, "dense fp32")
 
 
+@pytest.mark.parametrize("prec", [iblb.FP64, iblb.FP32_DEV])
+def test_mask_beyond_four_words_per_thread(prec):
+    """A level-6 icosphere (40962 vertices, 641 mask words per tile) of
+    radius 27 in a periodic 60^3 lattice: beyond four words per thread of a
+    two-wavefront block, so the spreading runs four-wavefront blocks.
+    Forces, force density and positions against the oracle after 3 steps."""
+    d = Domain(60, 60, 60, wall_mode=PERIODIC_ALL)
+    m = sphere_mesh(6, 27.0, (30.3, 29.6, 30.1), (1e-3, 0.0, 1e-3), amplitude=0.005, seed=3)
+    announce(f"level-6 mesh prec={prec}")
+    o = O.OracleSim(d, m)
+    o.step(3)
+    with iblb.Simulation(d, m, precision=prec) as g:
+        g.step(3)
+        g.sync()
+        if prec == iblb.FP64:
+            assert rel(g.nodal_forces(), o.nodal_forces()) < 1e-12
+            assert rel(g.force(), o.force()) < 1e-12
+            compare(g, o, 27.0, 1e-13, 1e-12, "level-6 fp64")
+        else:
+            assert rel(g.force(), o.force()) < 1e-5
+            compare(g, o, 27.0, 1e-7, 1e-5, "level-6 fp32")
+
+
 ROWS128 = {
     "walls": dict(tau=0.8, u_wall_lo=(0.004, -0.001, 0), u_wall_hi=(-0.003, 0.002, 0)),
     "periodic": dict(wall_mode=PERIODIC_ALL),
