@@ -46,6 +46,23 @@ def test_workspace_bytes_validates_domain_without_gpu():
         iblb.workspace_bytes(w.domain, 5)
 
 
+def test_workspace_bytes_enforces_the_lattice_size_limits():
+    """The populations must fit in 4 GiB (19 x nodes x bytes per population,
+    32-bit byte offsets) and the lattice hold at most 2^31 nodes."""
+    from paper_2305_18919_amd import iblb
+    from paper_2305_18919_amd.inputs import Domain
+    under = Domain(512, 512, 200)   # 52.4 M nodes: 3.98 GB of FP32 populations
+    over = Domain(512, 512, 240)    # 62.9 M nodes: 4.78 GB in FP32, 2.39 GB in FP16
+    assert iblb.workspace_bytes(under, iblb.FP32_DEV) >= under.n_fluid * 19 * 4
+    with pytest.raises(iblb.IBLBError):
+        iblb.workspace_bytes(over, iblb.FP32_DEV)
+    with pytest.raises(iblb.IBLBError):
+        iblb.workspace_bytes(under, iblb.FP64)
+    assert iblb.workspace_bytes(over, iblb.FP16_DEV) >= over.n_fluid * 19 * 2
+    with pytest.raises(iblb.IBLBError):
+        iblb.workspace_bytes(Domain(2048, 2048, 600), iblb.BF16_DEV)  # beyond 2^31 nodes
+
+
 def test_tile_shape_is_one_wavefront_of_power_of_two_extents():
     from paper_2305_18919_amd import iblb
     tx, ty, tz = iblb.tile_shape()

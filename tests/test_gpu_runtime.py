@@ -83,6 +83,12 @@ def test_mesh_validation_errors():
         with pytest.raises(iblb.IBLBError) as e:
             g.add_mesh(bad)
         assert e.value.code == iblb.IBLB_E_INVAL
+        huge = sphere_mesh(1, 3.0, (8.0, 8.0, 8.0), (1e-3, 0, 0))
+        huge.vertices = np.full((65537, 3), 8.0)  # one vertex beyond the limit of 65536
+        huge.ref_vertices = huge.vertices.copy()
+        with pytest.raises(iblb.IBLBError) as e:
+            g.add_mesh(huge)
+        assert e.value.code == iblb.IBLB_E_INVAL
         g.add_mesh(m)
         with pytest.raises(iblb.IBLBError) as e:
             g.add_mesh(m)
